@@ -1,0 +1,192 @@
+/*
+ * sigkernel.h -- C ABI of the MI355X (gfx950) signature-kernel library.
+ *
+ * Computes signature kernels k(x, y) = <S(x), S(y)> of piecewise-linear paths
+ * by solving the Goursat problem d^2k/dsdt = <x'(s), y'(t)> k, k(0,.) =
+ * k(.,0) = 1 (Theorem "sigpdetheorem" of Cass, Piatti, Pei, "Numerical
+ * Schemes for Signature Kernels") cell by cell on the grid of the two paths,
+ * with one of the paper's three schemes:
+ *
+ *   SK_FD           first-order explicit finite differences on the
+ *                   lambda-order dyadic refinement of the grid (Section 2,
+ *                   Definition "Dyadic finite differences approximation
+ *                   scheme"); `order` = lambda.
+ *   SK_POLY_APPROX  polynomial approximation scheme of order N (Section 3.2,
+ *                   Definition "Polynomial approximation numerical scheme");
+ *                   `order` = N.
+ *   SK_POLY_INTERP  polynomial interpolation scheme of order N at the N+1
+ *                   Chebyshev extrema (Section 3.3, Definition "Polynomial
+ *                   interpolation numerical scheme"); `order` = N.
+ *
+ * Paths are given by their points only: the time partition drops out of all
+ * schemes once each cell is normalised to the unit square, so only the cell
+ * constants c_ij = <x_{i+1} - x_i, y_{j+1} - y_j> enter.  A path with one
+ * point (no segment) has kernel 1 with every other path.
+ *
+ * Conventions of every call:
+ *   - Pointers are device pointers unless stated otherwise; all arrays are
+ *     dense, row-major, in the element type given by `dtype` (SK_F32: float,
+ *     SK_F64: double).
+ *   - Calls are asynchronous and ordered on `stream`, except that
+ *     sigkernel_pairs / sigkernel_backward(SK_OP_PAIRS) synchronise `stream`
+ *     once per chunk to upload per-pair descriptors.
+ *   - No call allocates device memory: the caller passes a workspace `ws` of
+ *     `ws_bytes` bytes (size it with sigkernel_*_workspace).  A smaller
+ *     workspace is accepted as long as it holds one pair: work is then done
+ *     in chunks of pairs.  The workspace must not be used concurrently by
+ *     another call.
+ *   - The caller owns all buffers.  The library keeps only immutable,
+ *     c-independent coefficient tables (host side, built on first use).
+ *   - Return value: SK_OK (0) on success, a negative SK_E* code on error (see
+ *     sigkernel_error_string and sigkernel_last_error for a description).
+ *     Errors in argument checking are reported before any device work is
+ *     queued; no C++ exception crosses this interface.
+ *
+ * Exponent output: kernels of long or large paths exceed the floating-point
+ * range.  When K_exp (k_exp) is non-null the value is K * 2^K_exp with K a
+ * mantissa in [0.5, 1) in magnitude (or 0); when it is null the value is
+ * written directly (and may overflow to inf).
+ */
+#ifndef SIGKERNEL_H
+#define SIGKERNEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SK_OK 0
+#define SK_EINVAL (-1)        /* bad shape, null pointer, order out of range   */
+#define SK_EWORKSPACE (-2)    /* workspace smaller than one pair needs          */
+#define SK_EUNSUPPORTED (-3)  /* valid request this build does not implement    */
+#define SK_EHIP (-4)          /* HIP runtime error (detail in sigkernel_last_error) */
+
+/* schemes */
+#define SK_FD 0
+#define SK_POLY_APPROX 1
+#define SK_POLY_INTERP 2
+
+/* element / arithmetic type of paths, outputs and the cell sweep */
+#define SK_F64 0
+#define SK_F32 1
+
+/* execution algorithm */
+#define SK_ALGO_BATCHED 0 /* all pairs of a chunk in one wavefront launch   */
+#define SK_ALGO_PLAIN 1   /* one launch per pair, one workgroup sweeping the
+                             anti-diagonals (FP64, forward only)             */
+
+/* backward operations */
+#define SK_OP_GRAM 0
+#define SK_OP_PAIRS 1
+
+/* compiled limits */
+#define SK_MIN_POLY_ORDER 2
+#define SK_MAX_POLY_ORDER 8
+#define SK_MAX_DYADIC_ORDER 8
+#define SK_MAX_BACKWARD_DIM 64
+
+typedef struct sk_params {
+    int32_t scheme; /* SK_FD, SK_POLY_APPROX or SK_POLY_INTERP                      */
+    int32_t order;  /* N in [SK_MIN_POLY_ORDER, SK_MAX_POLY_ORDER] for the polynomial
+                       schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD          */
+    int32_t dtype;  /* SK_F32 or SK_F64                                              */
+    int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
+} sk_params;
+
+/*
+ * Workspace sizes (bytes) for processing all pairs in one chunk (capped at a
+ * few GiB, beyond which work is chunked).  Host-only, no device access.
+ * Returns 0 on invalid arguments (see sigkernel_last_error).
+ * `backward` != 0 sizes the workspace of sigkernel_backward.
+ */
+size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                                const sk_params* p, int32_t backward);
+/* x_off, y_off: HOST arrays of npairs + 1 point offsets (see sigkernel_pairs). */
+size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int64_t npairs,
+                                 int64_t d, const sk_params* p, int32_t backward);
+
+/*
+ * Gram matrix K[a * ny + b] = k(X[a], Y[b]) (paper: the kernel evaluations
+ * of Section 1 computed by the chosen scheme; endpoint as in the scheme's
+ * definition, the average of the top and right edges of the last cell for
+ * the polynomial schemes).
+ *   X: nx paths of lx_pts points in R^d, shape (nx, lx_pts, d).
+ *   Y: ny paths of ly_pts points, shape (ny, ly_pts, d).
+ *   K: nx * ny outputs; K_exp: nx * ny int32 exponents or NULL.
+ */
+int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                   int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Independent pairs of uneven lengths: k[i] = k(x_i, y_i).
+ *   Xcat: all x paths concatenated, shape (x_off[npairs], d); path x_i is
+ *   rows [x_off[i], x_off[i+1]).  Likewise Ycat, y_off.  x_off and y_off are
+ *   HOST arrays (npairs + 1 entries, non-decreasing, first entry 0); every
+ *   path must have at least one point.
+ *   k: npairs outputs; k_exp: npairs int32 exponents or NULL.
+ */
+int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, const int64_t* y_off,
+                    int64_t npairs, int64_t d, const sk_params* p, void* k, int32_t* k_exp,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Reverse-mode derivative of a forward call (polynomial schemes, batched
+ * algorithm): the exact gradient of the computed scheme (discrete adjoint of
+ * the cell recursion), for the loss L = sum_i gK[i] * K[i] with K[i] the
+ * forward outputs.
+ *   op == SK_OP_GRAM : X, nx, lx_pts, Y, ny, ly_pts as in sigkernel_gram;
+ *                      x_off, y_off ignored; gK has nx * ny entries;
+ *                      gX (nx, lx_pts, d) and gY (ny, ly_pts, d) are
+ *                      overwritten with dL/dX and dL/dY.
+ *   op == SK_OP_PAIRS: X, Y are Xcat, Ycat; x_off, y_off HOST offsets; nx is
+ *                      npairs (ny, lx_pts, ly_pts ignored); gK has npairs
+ *                      entries; gX, gY have the shapes of Xcat, Ycat.
+ *   gK_exp: optional int32 exponents, seed gK * 2^gK_exp (so that the loss
+ *   can be taken through log K when K itself overflows); NULL means 0.
+ *   When X and Y are the same tensor the caller sums gX and gY.
+ */
+int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t nx, int64_t lx_pts,
+                       const void* Y, const int64_t* y_off, int64_t ny, int64_t ly_pts, int64_t d,
+                       const sk_params* p, const void* gK, const int32_t* gK_exp, void* gX,
+                       void* gY, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The increment Gram matrices of a Gram call: C[((a * ny + b) * lx + i) * ly + j]
+ * = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> with lx = lx_pts - 1,
+ * ly = ly_pts - 1 (the constants C_ij of the schemes with unit time steps),
+ * computed by the same MFMA kernel that feeds the sweeps.  Needs the forward
+ * workspace of the same call with scheme SK_POLY_APPROX.
+ */
+int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                             int64_t ly_pts, int64_t d, int32_t dtype, void* C, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Kernel timing for measurement (diagnostics).  While enabled, every kernel
+ * launch of the library is bracketed by two HIP events recorded on its
+ * stream.  sigkernel_profile_enable(on) clears the records and switches
+ * collection on or off.  sigkernel_profile_read(name, &ms, &n) waits for the
+ * recorded events of kernels called `name` ("gram", "sweep", "sweep_ckpt",
+ * "adjoint", "contract", "reduce", "fd_sweep", "plain") and returns their
+ * summed elapsed time in milliseconds and the launch count.  Host memory
+ * for the records grows with the number of launches until the next enable.
+ */
+int sigkernel_profile_enable(int32_t on);
+int sigkernel_profile_read(const char* name, double* total_ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* sigkernel_error_string(int status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* sigkernel_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIGKERNEL_H */

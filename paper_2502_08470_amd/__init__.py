@@ -1,0 +1,9 @@
+"""MI355X (gfx950) signature-kernel solvers: finite-difference, polynomial
+approximation and polynomial interpolation schemes for the Goursat PDE of
+the signature kernel, batched over path pairs, forward and adjoint."""
+from .api import (SigKernelGram, cell_constants, gram, gram_backward, mmd2, pairs,
+                  pairs_backward, sig_gram)
+from ._lib import SigKernelError
+
+__all__ = ["gram", "pairs", "gram_backward", "pairs_backward", "cell_constants",
+           "SigKernelGram", "sig_gram", "mmd2", "SigKernelError"]

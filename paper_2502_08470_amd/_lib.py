@@ -1,0 +1,105 @@
+"""ctypes binding of ``libsigkernel.so`` (argument marshalling only).
+
+The library is loaded from this package's directory; there is no fallback:
+if it is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsigkernel.so")
+
+SK_OK, SK_EINVAL, SK_EWORKSPACE, SK_EUNSUPPORTED, SK_EHIP = 0, -1, -2, -3, -4
+SK_FD, SK_POLY_APPROX, SK_POLY_INTERP = 0, 1, 2
+SK_F64, SK_F32 = 0, 1
+SK_ALGO_BATCHED, SK_ALGO_PLAIN = 0, 1
+SK_OP_GRAM, SK_OP_PAIRS = 0, 1
+
+EXPORTS = (
+    "sigkernel_gram_workspace",
+    "sigkernel_pairs_workspace",
+    "sigkernel_gram",
+    "sigkernel_pairs",
+    "sigkernel_backward",
+    "sigkernel_cell_constants",
+    "sigkernel_error_string",
+    "sigkernel_last_error",
+    "sigkernel_profile_enable",
+    "sigkernel_profile_read",
+)
+
+
+class SkParams(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32)]
+
+
+class SigKernelError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"sigkernel status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load (once) and return the library with its prototypes set."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2502_08470_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    pp = ctypes.POINTER(SkParams)
+    L.sigkernel_gram_workspace.argtypes = [i64, i64, i64, i64, i64, pp, i32]
+    L.sigkernel_gram_workspace.restype = sz
+    L.sigkernel_pairs_workspace.argtypes = [i64p, i64p, i64, i64, pp, i32]
+    L.sigkernel_pairs_workspace.restype = sz
+    L.sigkernel_gram.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp, sz, vp]
+    L.sigkernel_gram.restype = ctypes.c_int
+    L.sigkernel_pairs.argtypes = [vp, i64p, vp, i64p, i64, i64, pp, vp, vp, vp, sz, vp]
+    L.sigkernel_pairs.restype = ctypes.c_int
+    L.sigkernel_backward.argtypes = [i32, vp, i64p, i64, i64, vp, i64p, i64, i64, i64, pp,
+                                     vp, vp, vp, vp, vp, sz, vp]
+    L.sigkernel_backward.restype = ctypes.c_int
+    L.sigkernel_cell_constants.argtypes = [vp, i64, i64, vp, i64, i64, i64, i32, vp, vp, sz, vp]
+    L.sigkernel_cell_constants.restype = ctypes.c_int
+    L.sigkernel_error_string.argtypes = [ctypes.c_int]
+    L.sigkernel_error_string.restype = ctypes.c_char_p
+    L.sigkernel_last_error.argtypes = []
+    L.sigkernel_last_error.restype = ctypes.c_char_p
+    L.sigkernel_profile_enable.argtypes = [i32]
+    L.sigkernel_profile_enable.restype = ctypes.c_int
+    L.sigkernel_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]
+    L.sigkernel_profile_read.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != SK_OK:
+        L = lib()
+        detail = L.sigkernel_last_error().decode() or L.sigkernel_error_string(status).decode()
+        raise SigKernelError(status, detail)
+
+
+def last_error() -> str:
+    return lib().sigkernel_last_error().decode()
+
+
+def profile_enable(on: bool) -> None:
+    check(lib().sigkernel_profile_enable(1 if on else 0))
+
+
+def profile_read(name: str):
+    """(total milliseconds, launches) of the kernel ``name`` since enable."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    check(lib().sigkernel_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,221 @@
+"""PyTorch binding of the signature-kernel library.
+
+PyTorch provides device memory and the current HIP stream; every step of
+the computation runs in the library's HIP kernels.  Tensors must live on a
+GPU ("cuda" device in PyTorch-ROCm) and be float32 or float64.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple, Union
+
+import torch
+
+from . import _lib as L
+
+_SCHEMES = {"fd": L.SK_FD, "approx": L.SK_POLY_APPROX, "interp": L.SK_POLY_INTERP}
+_ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN}
+
+
+def _params(dtype: torch.dtype, scheme: str, order: int, algo: str) -> L.SkParams:
+    if dtype == torch.float32:
+        dt = L.SK_F32
+    elif dtype == torch.float64:
+        dt = L.SK_F64
+    else:
+        raise TypeError(f"unsupported dtype {dtype}")
+    if scheme not in _SCHEMES:
+        raise ValueError(f"scheme must be one of {sorted(_SCHEMES)}")
+    if algo not in _ALGOS:
+        raise ValueError(f"algo must be one of {sorted(_ALGOS)}")
+    return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo])
+
+
+def _dev(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensors must be on a GPU device")
+    return t.contiguous()
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _i64arr(seq) -> ctypes.Array:
+    a = (ctypes.c_int64 * len(seq))(*[int(v) for v in seq])
+    return a
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    if nbytes == 0:
+        raise L.SigKernelError(L.SK_EINVAL, L.last_error())
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
+         algo: str = "batched", return_exp: bool = False):
+    """K[a, b] = k(X[a], Y[b]) for paths X (nx, lx_pts, d), Y (ny, ly_pts, d).
+
+    With ``return_exp`` returns (mantissa, exponent) with value
+    mantissa * 2**exponent (exponent int32)."""
+    X, Y = _dev(X), _dev(Y)
+    if X.dim() != 3 or Y.dim() != 3 or X.shape[2] != Y.shape[2] or X.dtype != Y.dtype:
+        raise ValueError("X and Y must be (n, points, d) with the same d and dtype")
+    p = _params(X.dtype, scheme, order, algo)
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    lib = L.lib()
+    K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
+    Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
+    if nx * ny == 0:
+        return (K, Ke) if return_exp else K
+    nb = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 0)
+    ws = _workspace(nb, X.device)
+    L.check(lib.sigkernel_gram(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p), _ptr(K),
+                               _ptr(Ke), _ptr(ws), nb, _stream(X)))
+    return (K, Ke) if return_exp else K
+
+
+def _concat(paths: Union[Sequence[torch.Tensor], Tuple[torch.Tensor, Sequence[int]]]):
+    if isinstance(paths, tuple) and len(paths) == 2 and torch.is_tensor(paths[0]):
+        cat, off = paths
+        off = [int(v) for v in off]
+        return _dev(cat), off
+    lens = [int(p.shape[0]) for p in paths]
+    off = [0]
+    for n in lens:
+        off.append(off[-1] + n)
+    return _dev(torch.cat(list(paths), dim=0)), off
+
+
+def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
+          return_exp: bool = False):
+    """k[i] = k(xs[i], ys[i]) for lists of (points_i, d) tensors of uneven
+    lengths, or (concatenated points, offsets) tuples."""
+    Xc, xo = _concat(xs)
+    Yc, yo = _concat(ys)
+    if len(xo) != len(yo):
+        raise ValueError("xs and ys must hold the same number of paths")
+    npairs = len(xo) - 1
+    d = Xc.shape[1]
+    p = _params(Xc.dtype, scheme, order, algo)
+    lib = L.lib()
+    k = torch.empty(npairs, dtype=Xc.dtype, device=Xc.device)
+    ke = torch.empty(npairs, dtype=torch.int32, device=Xc.device) if return_exp else None
+    if npairs == 0:
+        return (k, ke) if return_exp else k
+    xa, ya = _i64arr(xo), _i64arr(yo)
+    nb = lib.sigkernel_pairs_workspace(xa, ya, npairs, d, ctypes.byref(p), 0)
+    ws = _workspace(nb, Xc.device)
+    L.check(lib.sigkernel_pairs(_ptr(Xc), xa, _ptr(Yc), ya, npairs, d, ctypes.byref(p), _ptr(k),
+                                _ptr(ke), _ptr(ws), nb, _stream(Xc)))
+    return (k, ke) if return_exp else k
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
+                  order: int = 4, gK_exp: Optional[torch.Tensor] = None):
+    """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order)."""
+    X, Y = _dev(X), _dev(Y)
+    gK = _dev(gK.to(X.dtype))
+    p = _params(X.dtype, scheme, order, "batched")
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    if gK.shape != (nx, ny):
+        raise ValueError("gK must have shape (nx, ny)")
+    lib = L.lib()
+    gX = torch.empty_like(X)
+    gY = torch.empty_like(Y)
+    if nx * ny == 0:
+        return gX.zero_(), gY.zero_()
+    ge = _dev(gK_exp.to(torch.int32)) if gK_exp is not None else None
+    nb = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 1)
+    ws = _workspace(nb, X.device)
+    L.check(lib.sigkernel_backward(L.SK_OP_GRAM, _ptr(X), None, nx, lxp, _ptr(Y), None, ny, lyp,
+                                   d, ctypes.byref(p), _ptr(gK), _ptr(ge), _ptr(gX), _ptr(gY),
+                                   _ptr(ws), nb, _stream(X)))
+    return gX, gY
+
+
+def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int = 4,
+                   gk_exp: Optional[torch.Tensor] = None):
+    """Gradients of sum(gk * pairs(xs, ys)) with respect to the concatenated
+    points; returns (gXcat, gYcat, x_offsets, y_offsets)."""
+    Xc, xo = _concat(xs)
+    Yc, yo = _concat(ys)
+    npairs = len(xo) - 1
+    d = Xc.shape[1]
+    p = _params(Xc.dtype, scheme, order, "batched")
+    lib = L.lib()
+    gk = _dev(gk.to(Xc.dtype))
+    gX = torch.empty_like(Xc)
+    gY = torch.empty_like(Yc)
+    xa, ya = _i64arr(xo), _i64arr(yo)
+    ge = _dev(gk_exp.to(torch.int32)) if gk_exp is not None else None
+    nb = lib.sigkernel_pairs_workspace(xa, ya, npairs, d, ctypes.byref(p), 1)
+    ws = _workspace(nb, Xc.device)
+    L.check(lib.sigkernel_backward(L.SK_OP_PAIRS, _ptr(Xc), xa, npairs, 0, _ptr(Yc), ya, 0, 0, d,
+                                   ctypes.byref(p), _ptr(gk), _ptr(ge), _ptr(gX), _ptr(gY),
+                                   _ptr(ws), nb, _stream(Xc)))
+    return gX, gY, xo, yo
+
+
+def cell_constants(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+    """C[a, b, i, j] = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> from the
+    library's MFMA increment-Gram kernel."""
+    X, Y = _dev(X), _dev(Y)
+    p = _params(X.dtype, "approx", 2, "batched")
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    lib = L.lib()
+    C = torch.empty((nx, ny, lxp - 1, lyp - 1), dtype=X.dtype, device=X.device)
+    nb = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 0)
+    ws = _workspace(nb, X.device)
+    L.check(lib.sigkernel_cell_constants(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, p.dtype, _ptr(C),
+                                         _ptr(ws), nb, _stream(X)))
+    return C
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+class SigKernelGram(torch.autograd.Function):
+    """Differentiable Gram matrix; the backward runs the library's adjoint
+    sweep (exact gradient of the computed scheme)."""
+
+    @staticmethod
+    def forward(ctx, X, Y, scheme="approx", order=4):
+        ctx.save_for_backward(X, Y)
+        ctx.scheme, ctx.order = scheme, order
+        return gram(X, Y, scheme, order)
+
+    @staticmethod
+    def backward(ctx, gK):
+        X, Y = ctx.saved_tensors
+        gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order)
+        return gX, gY, None, None
+
+
+def sig_gram(X, Y, scheme: str = "approx", order: int = 4) -> torch.Tensor:
+    return SigKernelGram.apply(X, Y, scheme, order)
+
+
+def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4) -> torch.Tensor:
+    """Unbiased (U-statistic) squared MMD between path sets X and Y, with the
+    within-sample diagonals excluded; differentiable in X and Y."""
+    n, m = X.shape[0], Y.shape[0]
+    Kxx = sig_gram(X, X, scheme, order)
+    Kyy = sig_gram(Y, Y, scheme, order)
+    Kxy = sig_gram(X, Y, scheme, order)
+    sxx = (Kxx.sum() - torch.diagonal(Kxx).sum()) / (n * (n - 1))
+    syy = (Kyy.sum() - torch.diagonal(Kyy).sum()) / (m * (m - 1))
+    return sxx + syy - 2.0 * Kxy.mean()

@@ -1,0 +1,856 @@
+// C ABI of the signature-kernel library: argument checking, coefficient
+// tables, workspace planning and chunked dispatch of the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sigkernel.h"
+#include "sk_launch.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(SK_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SK_TRY_HIP(expr, where)               \
+    do {                                      \
+        hipError_t e__ = (expr);              \
+        if (e__ != hipSuccess) return hip_fail(e__, where); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// optional per-kernel timing with HIP events recorded on the launch stream
+// ---------------------------------------------------------------------------
+struct ProfRec {
+    const char* name;
+    hipEvent_t start, stop;
+};
+std::atomic<bool> g_prof{false};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_recs;
+
+struct ProfScope {
+    const char* name;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+        if (!g_prof.load(std::memory_order_relaxed)) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEventRecord(b, st);
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        g_prof_recs.push_back({name, a, b});
+    }
+};
+
+#define SK_LAUNCH(name, st, expr, where)      \
+    do {                                      \
+        ProfScope ps__(name, st);             \
+        SK_TRY_HIP(expr, where);              \
+    } while (0)
+
+constexpr int64_t kAlign = 256;
+constexpr size_t kDefaultCap = (size_t)16 << 30;  // bytes of one default chunk
+
+inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// interpolation tables (c-independent, built in FP64 on the host)
+// ---------------------------------------------------------------------------
+// Interpolation of u^r at the Chebyshev extrema of [0, 1]: the degree-N
+// interpolant's monomial coefficients R[n][r], from a partial-pivoting LU
+// solve of the Vandermonde system.  Scaled to the factorial basis:
+// Rs[n][r] = R[n][r] n! / r!.
+struct InterpTableF64 {
+    double rs[SK_NMAX + 1][SK_TMAX];
+    double rmax[SK_TMAX];
+};
+
+double fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+void lu_solve_inplace(std::vector<double> a, int M, std::vector<double>& b) {
+    std::vector<int> piv(M);
+    for (int k = 0; k < M; ++k) {
+        int p = k;
+        for (int i = k + 1; i < M; ++i)
+            if (std::fabs(a[i * M + k]) > std::fabs(a[p * M + k])) p = i;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < M; ++j) std::swap(a[k * M + j], a[p * M + j]);
+        for (int i = k + 1; i < M; ++i) {
+            a[i * M + k] /= a[k * M + k];
+            for (int j = k + 1; j < M; ++j) a[i * M + j] -= a[i * M + k] * a[k * M + j];
+        }
+    }
+    for (int k = 0; k < M; ++k) std::swap(b[k], b[piv[k]]);
+    for (int i = 1; i < M; ++i)
+        for (int j = 0; j < i; ++j) b[i] -= a[i * M + j] * b[j];
+    for (int i = M - 1; i >= 0; --i) {
+        for (int j = i + 1; j < M; ++j) b[i] -= a[i * M + j] * b[j];
+        b[i] /= a[i * M + i];
+    }
+}
+
+InterpTableF64 build_interp_table(int N) {
+    const int M = N + 1;
+    std::vector<double> u(M), V(M * M);
+    for (int m = 0; m <= N; ++m) u[m] = 0.5 * std::cos(M_PI * m / N) + 0.5;
+    for (int m = 0; m <= N; ++m)
+        for (int n = 0; n <= N; ++n) V[m * M + n] = std::pow(u[m], n);
+    InterpTableF64 t;
+    std::memset(&t, 0, sizeof(t));
+    for (int k = 0; k < SK_TMAX; ++k) {
+        const int r = N + 1 + k;
+        std::vector<double> b(M);
+        for (int m = 0; m <= N; ++m) b[m] = std::pow(u[m], r);
+        lu_solve_inplace(V, M, b);
+        for (int n = 0; n <= N; ++n) {
+            t.rs[n][k] = b[n] * fact(n) / fact(r);
+            t.rmax[k] = std::max(t.rmax[k], std::fabs(t.rs[n][k]));
+        }
+    }
+    return t;
+}
+
+template <typename R>
+const SkTab<R>& interp_table(int N) {
+    static std::once_flag once[SK_NMAX + 1];
+    static SkTab<R> tabs[SK_NMAX + 1];
+    std::call_once(once[N], [N]() {
+        InterpTableF64 t = build_interp_table(N);
+        SkTab<R>& o = tabs[N];
+        std::memset(&o, 0, sizeof(o));
+        for (int n = 0; n <= N; ++n)
+            for (int k = 0; k < SK_TMAX; ++k) o.rs[n][k] = (R)t.rs[n][k];
+        for (int k = 0; k < SK_TMAX; ++k) o.rmax[k] = (R)t.rmax[k];
+    });
+    return tabs[N];
+}
+
+template <typename R>
+SkTab<R> table_for(const sk_params& p) {
+    if (p.scheme == SK_POLY_INTERP) return interp_table<R>(p.order);
+    SkTab<R> t;
+    std::memset(&t, 0, sizeof(t));
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+int check_params(const sk_params* p, bool backward) {
+    if (!p) return fail(SK_EINVAL, "params is NULL");
+    if (p->dtype != SK_F32 && p->dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", p->dtype);
+    if (p->algo != SK_ALGO_BATCHED && p->algo != SK_ALGO_PLAIN)
+        return fail(SK_EINVAL, "algo %d", p->algo);
+    if (p->scheme == SK_FD) {
+        if (p->order < 0) return fail(SK_EINVAL, "dyadic order %d < 0", p->order);
+        if (p->order > SK_MAX_DYADIC_ORDER)
+            return fail(SK_EUNSUPPORTED, "dyadic order %d > %d", p->order, SK_MAX_DYADIC_ORDER);
+        if (backward) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
+    } else if (p->scheme == SK_POLY_APPROX || p->scheme == SK_POLY_INTERP) {
+        if (p->order < SK_MIN_POLY_ORDER)
+            return fail(SK_EINVAL, "polynomial order %d < %d", p->order, SK_MIN_POLY_ORDER);
+        if (p->order > SK_MAX_POLY_ORDER)
+            return fail(SK_EUNSUPPORTED, "polynomial order %d > %d", p->order, SK_MAX_POLY_ORDER);
+    } else {
+        return fail(SK_EINVAL, "scheme %d", p->scheme);
+    }
+    if (p->algo == SK_ALGO_PLAIN) {
+        if (p->dtype != SK_F64) return fail(SK_EUNSUPPORTED, "the plain algorithm is FP64 only");
+        if (backward) return fail(SK_EUNSUPPORTED, "the plain algorithm is forward only");
+    }
+    return SK_OK;
+}
+
+int check_dims(int64_t d, bool backward) {
+    if (d < 1) return fail(SK_EINVAL, "d = %lld < 1", (long long)d);
+    if (backward && d > SK_MAX_BACKWARD_DIM)
+        return fail(SK_EUNSUPPORTED, "backward needs d <= %d", SK_MAX_BACKWARD_DIM);
+    return SK_OK;
+}
+
+int check_len(int64_t pts, int lam, const char* what) {
+    if (pts < 1) return fail(SK_EINVAL, "%s has %lld points (need >= 1)", what, (long long)pts);
+    if (((pts - 1) << lam) > (int64_t)1 << 24)
+        return fail(SK_EUNSUPPORTED, "%s: %lld segments (refined) exceed 2^24", what,
+                    (long long)((pts - 1) << lam));
+    return SK_OK;
+}
+
+int check_offsets(const int64_t* off, int64_t npairs, int lam, const char* what) {
+    if (!off) return fail(SK_EINVAL, "%s offsets are NULL", what);
+    if (off[0] != 0) return fail(SK_EINVAL, "%s offsets must start at 0", what);
+    for (int64_t i = 0; i < npairs; ++i) {
+        int64_t n = off[i + 1] - off[i];
+        int rc = check_len(n, lam, what);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
+size_t esize(const sk_params& p) { return p.dtype == SK_F32 ? 4 : 8; }
+int lam_of(const sk_params& p) { return p.scheme == SK_FD ? p.order : 0; }
+int ckpt_stride(const sk_params& p) {
+    return p.dtype == SK_F32 ? SkCkptStride<float>::value : SkCkptStride<double>::value;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout of one chunk
+// ---------------------------------------------------------------------------
+struct Layout {
+    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, total;
+};
+
+// Region sizes for P pairs with total per-array element counts `z` (sum over
+// the chunk's pairs).
+Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, bool list) {
+    Layout L;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.cskew = take(z.c * (int64_t)es);
+    L.gskew = backward ? take(z.c * (int64_t)es) : off;
+    L.ck = backward ? take(z.ck * (int64_t)es) : off;
+    L.ce = backward ? take(z.ce * 4) : off;
+    L.qb = backward ? take(z.qb * (int64_t)es) : off;
+    L.qe = backward ? take(z.qe * 4) : off;
+    L.dxp = backward ? take(z.dx * (int64_t)es) : off;
+    L.dyp = backward ? take(z.dy * (int64_t)es) : off;
+    L.kbuf = backward ? take(P * (int64_t)es) : off;
+    L.kexp = backward ? take(P * 4) : off;
+    L.desc = list ? take(P * (int64_t)sizeof(SkPairDesc)) : off;
+    L.total = off;
+    return L;
+}
+
+SkPairSizes scale(const SkPairSizes& z, int64_t P) {
+    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P};
+    return o;
+}
+
+SkPairSizes add(const SkPairSizes& a, const SkPairSizes& b) {
+    SkPairSizes o = {a.c + b.c, a.ck + b.ck, a.ce + b.ce, a.qb + b.qb,
+                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy};
+    return o;
+}
+
+// Gram: largest chunk of uniform pairs that fits in `bytes`.
+int64_t gram_chunk(const SkPairSizes& per, int64_t npairs, size_t es, bool backward,
+                   size_t bytes) {
+    if (npairs <= 0) return 0;
+    int64_t one = layout_for(per, 1, es, backward, false).total;
+    if ((size_t)one > bytes) return 0;
+    int64_t P = std::min<int64_t>(npairs, (int64_t)(bytes / (size_t)std::max<int64_t>(1, one)) + 1);
+    while (P > 1 && (size_t)layout_for(scale(per, P), P, es, backward, false).total > bytes) {
+        int64_t per_b = layout_for(scale(per, P), P, es, backward, false).total / P + 1;
+        int64_t guess = (int64_t)(bytes / (size_t)per_b);
+        P = std::max<int64_t>(1, std::min(P - 1, guess));
+    }
+    return P;
+}
+
+hipError_t lds_limit(size_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int v = 0;
+    e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    *out = (size_t)v;
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+template <typename R>
+int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, const SkPairSrc& src,
+                      int64_t P, int max_nsteps_pad, int max_ly, char* ws, const Layout& L,
+                      R* K, int32_t* Kexp, hipStream_t st) {
+    const bool interp = p.scheme == SK_POLY_INTERP;
+    const int lam = lam_of(p);
+    R* cskew = reinterpret_cast<R*>(ws + L.cskew);
+    GramArgs<R> ga;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = lam;
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
+    SK_LAUNCH("gram", st, SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st), "increment Gram");
+    if (p.scheme == SK_FD) {
+        FdArgs<R> fa;
+        fa.src = src; fa.lam = lam; fa.cskew = cskew; fa.K = K; fa.Kexp = Kexp;
+        SK_LAUNCH("fd_sweep", st, SkLaunch<R>::sweep_fd(fa, P, max_ly << lam, st), "finite-difference sweep");
+    } else {
+        SweepArgs<R> sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
+        sa.K = K; sa.Kexp = Kexp;
+        SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, max_ly, st), "sweep");
+    }
+    return SK_OK;
+}
+
+template <typename R>
+int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
+    size_t lim = 0;
+    SK_TRY_HIP(lds_limit(&lim), "device query");
+    size_t need = p.scheme == SK_FD ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
+                                    : SkLaunch<R>::sweep_lds(p.order, (int)max_ly);
+    need = std::max(need, SkLaunch<R>::gram_lds((int)((d + 3) / 4 * 4)));
+    if (need > lim)
+        return fail(SK_EUNSUPPORTED, "paths too long for one workgroup's LDS (%zu > %zu bytes)",
+                    need, lim);
+    return SK_OK;
+}
+
+template <typename R>
+int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                 int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+                 hipStream_t st) {
+    const int64_t npairs = nx * ny;
+    if (npairs == 0) return SK_OK;
+    const int lam = lam_of(p);
+    const int64_t lx = lxp - 1, ly = lyp - 1;
+    if (p.algo == SK_ALGO_PLAIN) {
+        const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
+        if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
+        PlainArgs<R> pa;
+        std::memset(&pa, 0, sizeof(pa));
+        pa.d = d; pa.lx = (int)lx; pa.ly = (int)ly; pa.lam = lam;
+        pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
+        pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
+        for (int64_t a = 0; a < nx; ++a)
+            for (int64_t b = 0; b < ny; ++b) {
+                pa.x = X + a * lxp * d; pa.y = Y + b * lyp * d; pa.k_idx = a * ny + b;
+                if (lx == 0 || ly == 0) {
+                    SK_TRY_HIP(SkLaunch<R>::fill(K + pa.k_idx, 1, (R)1, st), "fill");
+                    if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + pa.k_idx), 1, st), "fill");
+                    continue;
+                }
+                if (p.scheme == SK_FD)
+                    SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
+                else
+                    SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+                              "plain polynomial sweep");
+            }
+        return SK_OK;
+    }
+    int rc = check_lds<R>(p, ly, d);
+    if (rc) return rc;
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false);
+    const int64_t P = gram_chunk(per, npairs, sizeof(R), false, wsb);
+    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    const Layout L = layout_for(scale(per, P), P, sizeof(R), false, false);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    for (int64_t first = 0; first < npairs; first += P) {
+        const int64_t cnt = std::min(P, npairs - first);
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
+        src.desc = nullptr;
+        rc = run_chunk_forward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)ly, (char*)ws, L, K,
+                                  Kexp, st);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
+// List mode planning: greedy chunks by bytes.
+struct ListChunk {
+    int64_t first, count;
+    SkPairSizes tot;
+    int max_nsteps_pad, max_ly;
+    int64_t max_pts;
+};
+
+int plan_pairs(const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
+               const sk_params& p, bool backward, size_t wsb, std::vector<ListChunk>& out,
+               size_t* need_all) {
+    const int lam = lam_of(p);
+    const size_t es = esize(p);
+    ListChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0};
+    size_t max_one = 0;
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int lx = (int)(xo[i + 1] - xo[i] - 1), ly = (int)(yo[i + 1] - yo[i] - 1);
+        const SkPairSizes z = sk_pair_sizes(lx, ly, lam, p.order, ckpt_stride(p), d, backward);
+        const SkGeom g = sk_make_geom(lx << lam, ly << lam);
+        ListChunk nxt = cur;
+        nxt.count += 1;
+        nxt.tot = add(cur.tot, z);
+        nxt.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
+        nxt.max_ly = std::max(cur.max_ly, ly);
+        nxt.max_pts = std::max<int64_t>(cur.max_pts, std::max(lx, ly) + 1);
+        const size_t bytes = (size_t)layout_for(nxt.tot, nxt.count, es, backward, true).total;
+        max_one = std::max(max_one, (size_t)layout_for(z, 1, es, backward, true).total);
+        if (bytes > wsb && cur.count > 0) {
+            out.push_back(cur);
+            cur = {i, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0};
+            --i;
+            continue;
+        }
+        cur = nxt;
+    }
+    if (cur.count > 0) out.push_back(cur);
+    if (need_all) *need_all = max_one;
+    return SK_OK;
+}
+
+std::vector<SkPairDesc> make_desc(const int64_t* xo, const int64_t* yo, const ListChunk& c,
+                                  const sk_params& p, int64_t d, bool backward) {
+    std::vector<SkPairDesc> v(c.count);
+    SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
+    const int lam = lam_of(p);
+    for (int64_t k = 0; k < c.count; ++k) {
+        const int64_t i = c.first + k;
+        SkPairDesc& q = v[k];
+        q.x_off = xo[i];
+        q.y_off = yo[i];
+        q.lx = (int32_t)(xo[i + 1] - xo[i] - 1);
+        q.ly = (int32_t)(yo[i + 1] - yo[i] - 1);
+        q.k_idx = i;
+        q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
+        q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
+        run = add(run, sk_pair_sizes(q.lx, q.ly, lam, p.order, ckpt_stride(p), d, backward));
+    }
+    return v;
+}
+
+template <typename R>
+int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
+                  int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+                  hipStream_t st) {
+    if (npairs == 0) return SK_OK;
+    const int lam = lam_of(p);
+    if (p.algo == SK_ALGO_PLAIN) {
+        PlainArgs<R> pa;
+        std::memset(&pa, 0, sizeof(pa));
+        pa.d = d; pa.lam = lam; pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
+        pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
+        for (int64_t i = 0; i < npairs; ++i) {
+            const int64_t lx = xo[i + 1] - xo[i] - 1, ly = yo[i + 1] - yo[i] - 1;
+            const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
+            if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
+            pa.x = Xc + xo[i] * d; pa.y = Yc + yo[i] * d; pa.lx = (int)lx; pa.ly = (int)ly;
+            pa.k_idx = i;
+            if (lx == 0 || ly == 0) {
+                SK_TRY_HIP(SkLaunch<R>::fill(K + i, 1, (R)1, st), "fill");
+                if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + i), 1, st), "fill");
+                continue;
+            }
+            if (p.scheme == SK_FD)
+                SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
+            else
+                SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+                          "plain polynomial sweep");
+        }
+        return SK_OK;
+    }
+    std::vector<ListChunk> chunks;
+    size_t need_one = 0;
+    plan_pairs(xo, yo, npairs, d, p, false, wsb, chunks, &need_one);
+    if (need_one > wsb) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    int max_ly = 0;
+    for (auto& c : chunks) max_ly = std::max(max_ly, c.max_ly);
+    int rc = check_lds<R>(p, max_ly, d);
+    if (rc) return rc;
+    for (const ListChunk& c : chunks) {
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), false, true);
+        std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, false);
+        SkPairDesc* ddesc = reinterpret_cast<SkPairDesc*>((char*)ws + L.desc);
+        SK_TRY_HIP(hipMemcpyAsync(ddesc, desc.data(), desc.size() * sizeof(SkPairDesc),
+                                  hipMemcpyHostToDevice, st), "descriptor upload");
+        SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.desc = ddesc;
+        rc = run_chunk_forward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_ly,
+                                  (char*)ws, L, K, Kexp, st);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+template <typename R>
+int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
+                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly,
+                       int max_strips, char* ws, const Layout& L, const R* gK,
+                       const int32_t* gKexp, hipStream_t st) {
+    const bool interp = p.scheme == SK_POLY_INTERP;
+    R* cskew = reinterpret_cast<R*>(ws + L.cskew);
+    GramArgs<R> ga;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = 0;
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
+    SK_LAUNCH("gram", st, SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st), "increment Gram");
+    // forward with checkpoints; its kernel values go to the chunk's scratch
+    // slots (Gram mode: k_idx - first; list mode: descriptors carry local k_idx)
+    SweepArgs<R> sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
+    R* kbuf = reinterpret_cast<R*>(ws + L.kbuf);
+    int32_t* kexp = reinterpret_cast<int32_t*>(ws + L.kexp);
+    const int64_t kbase = src.desc ? 0 : src.first;
+    sa.K = kbuf - kbase;
+    sa.Kexp = kexp - kbase;
+    sa.ck = reinterpret_cast<R*>(ws + L.ck);
+    sa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
+    sa.qb = reinterpret_cast<R*>(ws + L.qb);
+    sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
+    SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, max_ly, st), "checkpoint sweep");
+    AdjArgs<R> aa;
+    std::memset(&aa, 0, sizeof(aa));
+    aa.src = src; aa.cskew = cskew; aa.tab = sa.tab; aa.gK = gK; aa.gKexp = gKexp;
+    aa.ck = sa.ck; aa.ce = sa.ce; aa.qb = sa.qb; aa.qe = sa.qe;
+    aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
+    SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, max_ly, st), "adjoint sweep");
+    ContractArgs<R> ca;
+    ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = aa.gskew;
+    ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
+    ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
+    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (2 * d * (int64_t)sizeof(R))));
+    SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
+    return SK_OK;
+}
+
+template <typename R>
+int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                  int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX, R* gY,
+                  void* ws, size_t wsb, hipStream_t st) {
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+    const int64_t npairs = nx * ny;
+    const int64_t lx = lxp - 1, ly = lyp - 1;
+    if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
+    int rc = check_lds<R>(p, ly, d);
+    if (rc) return rc;
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true);
+    const int64_t P = gram_chunk(per, npairs, sizeof(R), true, wsb);
+    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    const Layout L = layout_for(scale(per, P), P, sizeof(R), true, false);
+    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    for (int64_t first = 0; first < npairs; first += P) {
+        const int64_t cnt = std::min(P, npairs - first);
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
+        rc = run_chunk_backward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)ly, g.nstrips,
+                                   (char*)ws, L, gK, gKexp, st);
+        if (rc) return rc;
+        ReduceGramArgs<R> ra;
+        ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
+        ra.first = first; ra.count = cnt; ra.dx_stride = per.dx; ra.dy_stride = per.dy;
+        ra.nstrips = g.nstrips;
+        ra.dxp = reinterpret_cast<const R*>((char*)ws + L.dxp);
+        ra.dyp = reinterpret_cast<const R*>((char*)ws + L.dyp);
+        ra.gX = gX; ra.gY = gY;
+        SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
+    }
+    return SK_OK;
+}
+
+template <typename R>
+int pairs_backward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
+                   int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX, R* gY,
+                   void* ws, size_t wsb, hipStream_t st) {
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, xo[npairs] * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, yo[npairs] * d, (R)0, st), "fill");
+    if (npairs == 0) return SK_OK;
+    std::vector<ListChunk> chunks;
+    size_t need_one = 0;
+    plan_pairs(xo, yo, npairs, d, p, true, wsb, chunks, &need_one);
+    if (need_one > wsb) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    int max_ly = 0;
+    for (auto& c : chunks) max_ly = std::max(max_ly, c.max_ly);
+    int rc = check_lds<R>(p, max_ly, d);
+    if (rc) return rc;
+    for (const ListChunk& c : chunks) {
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, true);
+        std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, true);
+        // the checkpoint pass writes kernel values by k_idx: route them to the
+        // chunk's scratch slots
+        for (int64_t k = 0; k < c.count; ++k) desc[k].k_idx = k;
+        SkPairDesc* ddesc = reinterpret_cast<SkPairDesc*>((char*)ws + L.desc);
+        SK_TRY_HIP(hipMemcpyAsync(ddesc, desc.data(), desc.size() * sizeof(SkPairDesc),
+                                  hipMemcpyHostToDevice, st), "descriptor upload");
+        SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.desc = ddesc;
+        int max_strips = 0;
+        for (const auto& q : desc) max_strips = std::max(max_strips, sk_make_geom(q.lx, q.ly).nstrips);
+        rc = run_chunk_backward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_ly,
+                                   max_strips, (char*)ws, L, gK + c.first,
+                                   gKexp ? gKexp + c.first : nullptr, st);
+        if (rc) return rc;
+        ReducePairsArgs<R> ra;
+        ra.desc = ddesc; ra.count = c.count; ra.d = d; ra.max_pts = c.max_pts;
+        ra.dxp = reinterpret_cast<const R*>((char*)ws + L.dxp);
+        ra.dyp = reinterpret_cast<const R*>((char*)ws + L.dyp);
+        ra.gX = gX; ra.gY = gY;
+        SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_pairs(ra, st), "gradient reduction");
+    }
+    return SK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported C ABI
+// ===========================================================================
+extern "C" {
+
+const char* sigkernel_error_string(int status) {
+    switch (status) {
+        case SK_OK: return "success";
+        case SK_EINVAL: return "invalid argument";
+        case SK_EWORKSPACE: return "workspace too small";
+        case SK_EUNSUPPORTED: return "unsupported by this build";
+        case SK_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* sigkernel_last_error(void) { return g_last_error.c_str(); }
+
+int sigkernel_profile_enable(int32_t on) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (ProfRec& r : g_prof_recs) {
+        hipEventSynchronize(r.stop);
+        hipEventDestroy(r.start);
+        hipEventDestroy(r.stop);
+    }
+    g_prof_recs.clear();
+    g_prof.store(on != 0);
+    return SK_OK;
+}
+
+int sigkernel_profile_read(const char* name, double* total_ms, int64_t* launches) {
+    g_last_error.clear();
+    if (!name || !total_ms || !launches) return fail(SK_EINVAL, "NULL pointer");
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    double tot = 0.0;
+    int64_t n = 0;
+    for (ProfRec& r : g_prof_recs) {
+        if (std::strcmp(r.name, name) != 0) continue;
+        SK_TRY_HIP(hipEventSynchronize(r.stop), "event synchronize");
+        float ms = 0.f;
+        SK_TRY_HIP(hipEventElapsedTime(&ms, r.start, r.stop), "event elapsed time");
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return SK_OK;
+}
+
+size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                                const sk_params* p, int32_t backward) {
+    g_last_error.clear();
+    if (check_params(p, backward != 0) || check_dims(d, backward != 0) ||
+        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y"))
+        return 0;
+    if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
+    const int lam = lam_of(*p);
+    if (p->algo == SK_ALGO_PLAIN) {
+        int64_t lx = lx_pts - 1, ly = ly_pts - 1;
+        return (size_t)std::max<int64_t>(256, std::max<int64_t>((lx + ly) * (p->order + 1),
+                                                               3 * ((lx << lam) + 1)) * 8);
+    }
+    const SkPairSizes per = sk_pair_sizes((int)(lx_pts - 1), (int)(ly_pts - 1), lam, p->order,
+                                          ckpt_stride(*p), d, backward != 0);
+    const int64_t npairs = std::max<int64_t>(1, nx * ny);
+    int64_t P = gram_chunk(per, npairs, esize(*p), backward != 0, kDefaultCap);
+    if (P <= 0) P = 1;
+    return std::max<size_t>(256, (size_t)layout_for(scale(per, P), P, esize(*p), backward != 0, false).total);
+}
+
+size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int64_t npairs,
+                                 int64_t d, const sk_params* p, int32_t backward) {
+    g_last_error.clear();
+    if (check_params(p, backward != 0) || check_dims(d, backward != 0)) return 0;
+    if (npairs < 0) { fail(SK_EINVAL, "negative npairs"); return 0; }
+    if (check_offsets(x_off, npairs, lam_of(*p), "x") || check_offsets(y_off, npairs, lam_of(*p), "y"))
+        return 0;
+    const int lam = lam_of(*p);
+    if (p->algo == SK_ALGO_PLAIN) {
+        int64_t need = 256;
+        for (int64_t i = 0; i < npairs; ++i) {
+            int64_t lx = x_off[i + 1] - x_off[i] - 1, ly = y_off[i + 1] - y_off[i] - 1;
+            need = std::max(need, std::max<int64_t>((lx + ly) * (p->order + 1), 3 * ((lx << lam) + 1)) * 8);
+        }
+        return (size_t)need;
+    }
+    std::vector<ListChunk> chunks;
+    size_t need_one = 0;
+    plan_pairs(x_off, y_off, npairs, d, *p, backward != 0, kDefaultCap, chunks, &need_one);
+    size_t best = need_one;
+    for (const ListChunk& c : chunks)
+        best = std::max(best, (size_t)layout_for(c.tot, c.count, esize(*p), backward != 0, true).total);
+    return std::max<size_t>(best, 256);
+}
+
+int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                   int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                   void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, false);
+    if (!rc) rc = check_dims(d, false);
+    if (rc) return rc;
+    if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
+    if ((rc = check_len(lx_pts, lam_of(*p), "x")) || (rc = check_len(ly_pts, lam_of(*p), "y")))
+        return rc;
+    if (nx * ny == 0) return SK_OK;
+    if (!X || !Y || !K || !ws) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (p->dtype == SK_F32)
+            return gram_forward<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts, d,
+                                       *p, (float*)K, K_exp, ws, ws_bytes, stream);
+        return gram_forward<double>((const double*)X, nx, lx_pts, (const double*)Y, ny, ly_pts, d,
+                                    *p, (double*)K, K_exp, ws, ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, const int64_t* y_off,
+                    int64_t npairs, int64_t d, const sk_params* p, void* k, int32_t* k_exp,
+                    void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, false);
+    if (!rc) rc = check_dims(d, false);
+    if (rc) return rc;
+    if (npairs < 0) return fail(SK_EINVAL, "negative npairs");
+    if (npairs == 0) return SK_OK;
+    if ((rc = check_offsets(x_off, npairs, lam_of(*p), "x")) ||
+        (rc = check_offsets(y_off, npairs, lam_of(*p), "y")))
+        return rc;
+    if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (p->dtype == SK_F32)
+            return pairs_forward<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
+                                        npairs, d, *p, (float*)k, k_exp, ws, ws_bytes, stream);
+        return pairs_forward<double>((const double*)Xcat, x_off, (const double*)Ycat, y_off,
+                                     npairs, d, *p, (double*)k, k_exp, ws, ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t nx, int64_t lx_pts,
+                       const void* Y, const int64_t* y_off, int64_t ny, int64_t ly_pts, int64_t d,
+                       const sk_params* p, const void* gK, const int32_t* gK_exp, void* gX,
+                       void* gY, void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, true);
+    if (!rc) rc = check_dims(d, true);
+    if (rc) return rc;
+    if (p->scheme == SK_FD) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
+    if (op != SK_OP_GRAM && op != SK_OP_PAIRS) return fail(SK_EINVAL, "op %d", op);
+    if (nx < 0 || (op == SK_OP_GRAM && ny < 0)) return fail(SK_EINVAL, "negative batch");
+    if (op == SK_OP_GRAM) {
+        if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    } else {
+        if ((rc = check_offsets(x_off, nx, 0, "x")) || (rc = check_offsets(y_off, nx, 0, "y")))
+            return rc;
+    }
+    if (!X || !Y || !gK || !gX || !gY || !ws) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (op == SK_OP_GRAM) {
+            if (p->dtype == SK_F32)
+                return gram_backward<float>((const float*)X, nx, lx_pts, (const float*)Y, ny,
+                                            ly_pts, d, *p, (const float*)gK, gK_exp, (float*)gX,
+                                            (float*)gY, ws, ws_bytes, stream);
+            return gram_backward<double>((const double*)X, nx, lx_pts, (const double*)Y, ny,
+                                         ly_pts, d, *p, (const double*)gK, gK_exp, (double*)gX,
+                                         (double*)gY, ws, ws_bytes, stream);
+        }
+        if (p->dtype == SK_F32)
+            return pairs_backward<float>((const float*)X, x_off, (const float*)Y, y_off, nx, d, *p,
+                                         (const float*)gK, gK_exp, (float*)gX, (float*)gY, ws,
+                                         ws_bytes, stream);
+        return pairs_backward<double>((const double*)X, x_off, (const double*)Y, y_off, nx, d, *p,
+                                      (const double*)gK, gK_exp, (double*)gX, (double*)gY, ws,
+                                      ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                             int64_t ly_pts, int64_t d, int32_t dtype, void* C, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    sk_params p = {SK_POLY_APPROX, SK_MIN_POLY_ORDER, dtype, SK_ALGO_BATCHED};
+    int rc = check_params(&p, false);
+    if (!rc) rc = check_dims(d, false);
+    if (rc) return rc;
+    if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
+    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    const int64_t npairs = nx * ny, lx = lx_pts - 1, ly = ly_pts - 1;
+    if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
+    if (!X || !Y || !C || !ws) return fail(SK_EINVAL, "NULL pointer");
+    const size_t es = esize(p);
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, false);
+    const int64_t P = gram_chunk(per, npairs, es, false, ws_bytes);
+    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
+    const Layout L = layout_for(scale(per, P), P, es, false, false);
+    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    for (int64_t first = 0; first < npairs; first += P) {
+        const int64_t cnt = std::min(P, npairs - first);
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.ny = ny; src.lx_pts = lx_pts; src.ly_pts = ly_pts; src.stride = per; src.first = first;
+        if (dtype == SK_F32) {
+            GramArgs<float> ga;
+            ga.X = (const float*)X; ga.Y = (const float*)Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4);
+            ga.lam = 0; ga.src = src; ga.cskew = (float*)((char*)ws + L.cskew); ga.maxc = nullptr;
+            SK_TRY_HIP(SkLaunch<float>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
+            SK_TRY_HIP(SkLaunch<float>::unskew(src, ga.cskew, (float*)C, first, cnt, lx * ly, stream), "unskew");
+        } else {
+            GramArgs<double> ga;
+            ga.X = (const double*)X; ga.Y = (const double*)Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4);
+            ga.lam = 0; ga.src = src; ga.cskew = (double*)((char*)ws + L.cskew); ga.maxc = nullptr;
+            SK_TRY_HIP(SkLaunch<double>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
+            SK_TRY_HIP(SkLaunch<double>::unskew(src, ga.cskew, (double*)C, first, cnt, lx * ly, stream), "unskew");
+        }
+    }
+    return SK_OK;
+}
+
+}  // extern "C"

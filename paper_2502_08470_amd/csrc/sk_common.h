@@ -1,0 +1,124 @@
+// Shared host/device definitions of the signature-kernel GPU library.
+//
+// Grid of one path pair: cells (i, j), 0 <= i < lx (segments of x),
+// 0 <= j < ly (segments of y); cell constant c_ij = <dx_i, dy_j> (the PDE
+// constant on the normalised unit cell; the time partition drops out once
+// edge coefficients are expressed in the cell's local variables).
+//
+// Wavefront mapping (one 64-lane wave per pair): lane r owns the x-segments
+// i = 64 s + r of strips s = 0, 1, ...; at step tau it processes the cell with
+// linear index L = tau - r, strip s = L / Tp, column j = L % Tp.  Tp is the
+// strip period max(ly, W), W = min(lx, 64), which guarantees that the last
+// lane of strip s-1 has produced the left edge of (64 s, j) before lane 0 of
+// strip s needs it.  Lanes run strips back to back, so all lanes stay busy
+// except during the first and last 63 steps of the whole pair.
+//
+// The "skewed" layout stores any per-cell quantity (cell constants c, or
+// dL/dc in the backward pass) as rows tau of 64 lane slots: element
+// [tau][r] is the value of the cell that lane r processes at step tau, zero
+// where that lane is idle.  The sweep then reads one contiguous 64-element row
+// per step.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIP__
+#define __host__
+#define __device__
+#endif
+
+#define SK_LANES 64
+
+struct SkGeom {
+    int32_t lx, ly;      // segments (after dyadic refinement for the FD scheme)
+    int32_t nstrips;     // ceil(lx / 64)
+    int32_t Tp;          // strip period max(ly, min(lx, 64))
+    int32_t nsteps;      // steps until the last cell (lx-1, ly-1) is done
+    int32_t nsteps_pad;  // nsteps rounded up to a multiple of 64
+};
+
+__host__ __device__ inline SkGeom sk_make_geom(int32_t lx, int32_t ly) {
+    SkGeom g;
+    g.lx = lx;
+    g.ly = ly;
+    if (lx <= 0 || ly <= 0) {
+        g.nstrips = 0; g.Tp = 0; g.nsteps = 0; g.nsteps_pad = 0;
+        return g;
+    }
+    int32_t W = lx < SK_LANES ? lx : SK_LANES;
+    g.nstrips = (lx + SK_LANES - 1) / SK_LANES;
+    g.Tp = ly > W ? ly : W;
+    int32_t rlast = (lx - 1) - (g.nstrips - 1) * SK_LANES;
+    g.nsteps = (g.nstrips - 1) * g.Tp + (ly - 1) + rlast + 1;
+    g.nsteps_pad = (g.nsteps + 63) / 64 * 64;
+    return g;
+}
+
+// Per-pair description.  Gram calls derive it from the pair index; list
+// (ragged) calls read it from a device array.
+struct SkPairDesc {
+    int64_t x_off;    // offset of the first point of x, in points
+    int64_t y_off;    // offset of the first point of y, in points
+    int32_t lx, ly;   // segments of x and y (unrefined)
+    int64_t k_idx;    // output index of the pair
+    // element offsets of the pair's blocks in the chunk's workspace arrays
+    int64_t c_off;    // skewed cell constants / skewed dL/dc
+    int64_t ck_off;   // lane checkpoints (backward only)
+    int64_t ce_off;   // checkpoint exponents (int32 elements)
+    int64_t qb_off;   // strip-boundary edge vectors (backward only)
+    int64_t qe_off;   // strip-boundary exponents (int32 elements)
+    int64_t dx_off;   // per-pair dL/d(dx) partials
+    int64_t dy_off;   // per-pair, per-strip dL/d(dy) partials
+};
+
+// Per-pair workspace strides, all derived from the pair's geometry.
+struct SkPairSizes {
+    int64_t c, ck, ce, qb, qe, dx, dy;
+};
+
+__host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int32_t lam,
+                                                     int32_t N, int32_t S, int64_t d,
+                                                     bool backward) {
+    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0};
+    SkGeom g = sk_make_geom(lx << lam, ly << lam);
+    z.c = (int64_t)g.nsteps_pad * SK_LANES;
+    if (backward && g.nsteps > 0) {
+        int64_t nck = (g.nsteps + S - 1) / S;
+        z.ck = nck * 2 * (N + 1) * SK_LANES;
+        z.ce = nck;
+        z.qb = (int64_t)g.nstrips * g.ly * (N + 1);
+        z.qe = (int64_t)g.nstrips * g.ly;
+        z.dx = (int64_t)lx * d;
+        z.dy = (int64_t)g.nstrips * ly * d;
+    }
+    return z;
+}
+
+struct SkPairSrc {
+    // Gram mode (desc == nullptr): pair p = a * ny + b, uniform strides.
+    int64_t ny;
+    int64_t lx_pts, ly_pts;
+    SkPairSizes stride;
+    int64_t first;          // global index of the chunk's first pair
+    // List mode
+    const SkPairDesc* desc; // device array indexed by chunk-local pair
+};
+
+__host__ __device__ inline SkPairDesc sk_pair(const SkPairSrc& s, int64_t local) {
+    if (s.desc) return s.desc[local];
+    SkPairDesc d;
+    int64_t p = s.first + local;
+    int64_t a = p / s.ny, b = p % s.ny;
+    d.x_off = a * s.lx_pts;
+    d.y_off = b * s.ly_pts;
+    d.lx = (int32_t)(s.lx_pts - 1);
+    d.ly = (int32_t)(s.ly_pts - 1);
+    d.k_idx = p;
+    d.c_off = local * s.stride.c;
+    d.ck_off = local * s.stride.ck;
+    d.ce_off = local * s.stride.ce;
+    d.qb_off = local * s.stride.qb;
+    d.qe_off = local * s.stride.qe;
+    d.dx_off = local * s.stride.dx;
+    d.dy_off = local * s.stride.dy;
+    return d;
+}

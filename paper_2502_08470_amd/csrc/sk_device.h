@@ -1,0 +1,320 @@
+// Device-side building blocks: cross-lane moves, wave reductions and the
+// one-cell maps of the polynomial schemes.
+//
+// Edge coefficients are kept in the factorial-scaled basis P'_n = n! P_n,
+// where P_n are the coefficients of an edge in its cell's local variable
+// u in [0, 1].  In that basis the untruncated one-step map of Proposition
+// "approxsolution" (eqs. powerseries1/2, normalised cell, constant c) reads
+//
+//   A^P_r = sum_{k<=min(r,N)} w_{r-k} P'_k + c^r sum_{k=1}^{N} Q'_k / (r+k)!,
+//   A^Q_r = sum_{k<=min(r,N)} w_{r-k} Q'_k + c^r sum_{k=1}^{N} P'_k / (r+k)!,
+//
+// with w_m = c^m / m! (a Toeplitz part and a Hankel part).  The
+// approximation scheme keeps rows r <= N (the truncation pi_N).  The
+// interpolation scheme keeps rows up to N + T and folds rows N+1..N+T back
+// with a fixed matrix: since the interpolation operator at the Chebyshev
+// extrema reproduces polynomials of degree <= N, interpolating the exact edge
+// sum_r A_r u^r equals A_{<=N} + sum_{r>N} A_r Omega^N(u^r), and in the scaled
+// basis Omega^N(u^r) contributes Rs[n][r] = R[n][r] n!/r!.  Rs is independent
+// of c and built once on the host in FP64.  The number of tail rows T is
+// chosen adaptively per wavefront step (see below) so that the dropped rows
+// are below the working precision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SK_NMAX 12   // largest compiled polynomial order
+#define SK_TMAX 6    // longest interpolation tail (table size)
+
+// Longest interpolation tail compiled per working precision: FP32 reaches
+// its precision with fewer rows than FP64 at the same |c|.
+template <typename R> struct SkTailMax;
+template <> struct SkTailMax<float> { static constexpr int value = 4; };
+template <> struct SkTailMax<double> { static constexpr int value = 6; };
+
+// Kernel-argument tables of the interpolation scheme.
+template <typename R>
+struct SkTab {
+    R rs[SK_NMAX + 1][SK_TMAX];  // scaled projection of tail row N+1+t onto row n
+    R rmax[SK_TMAX];             // max_n |rs[n][t]|
+};
+
+// ---------------------------------------------------------------------------
+// compile-time constants
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double sk_inv_fact(int m) {
+    double f = 1.0;
+    for (int i = 2; i <= m; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+
+template <typename R>
+__device__ __forceinline__ R ifact(int m) { return (R)sk_inv_fact(m); }
+
+// ---------------------------------------------------------------------------
+// cross-lane moves (DPP across the whole 64-lane wave) and reductions
+// ---------------------------------------------------------------------------
+// lane r receives the value of lane r-1 (lane 0 receives 0)
+__device__ __forceinline__ float lane_from_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_from_prev(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x138, 0xf, 0xf, true);
+    o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x138, 0xf, 0xf, true);
+    return *reinterpret_cast<double*>(&o);
+}
+// lane r receives the value of lane r+1 (lane 63 receives 0)
+__device__ __forceinline__ float lane_from_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_from_next(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x130, 0xf, 0xf, true);
+    o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x130, 0xf, 0xf, true);
+    return *reinterpret_cast<double*>(&o);
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_max(R v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        R u = __shfl_xor(v, o, 64);
+        v = v > u ? v : u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float sk_ldexp(float v, int e) { return ldexpf(v, e); }
+__device__ __forceinline__ double sk_ldexp(double v, int e) { return ldexp(v, e); }
+__device__ __forceinline__ float sk_abs(float v) { return fabsf(v); }
+__device__ __forceinline__ double sk_abs(double v) { return fabs(v); }
+__device__ __forceinline__ int sk_frexp_exp(float v) { int e; frexpf(v, &e); return e; }
+__device__ __forceinline__ int sk_frexp_exp(double v) { int e; frexp(v, &e); return e; }
+__device__ __forceinline__ bool sk_finite(float v) { return isfinite(v); }
+__device__ __forceinline__ bool sk_finite(double v) { return isfinite(v); }
+
+// Rescale band: the wave exponent changes only when the largest live
+// magnitude leaves [2^-band, 2^band].
+template <typename R> struct SkBand;
+template <> struct SkBand<float> { static constexpr int value = 32; };
+template <> struct SkBand<double> { static constexpr int value = 256; };
+
+// Wave-uniform exponent update from the largest live magnitude `m`
+// (already reduced over the wave).  Returns the shift to apply (0 = none).
+template <typename R>
+__device__ __forceinline__ int sk_rescale_shift(R m) {
+    if (!(m > (R)0) || !sk_finite(m)) return 0;
+    int e = sk_frexp_exp(m);
+    constexpr int band = SkBand<R>::value;
+    return (e > band || e < -band) ? e : 0;
+}
+
+// ---------------------------------------------------------------------------
+// adaptive tail of the interpolation scheme
+// ---------------------------------------------------------------------------
+// Tail rows r = N+1, N+2, ... are added while any active lane of the wave
+// still needs them (a wave-uniform decision).  After row r a lane is done
+// when (i) its projected contribution is below the working precision
+// relative to the edge scale, 2 |A_r| max_n |Rs[n][r]| <= eps (|A_0^P| +
+// |A_0^Q|), and (ii) the rows not yet computed shrink at least geometrically
+// with ratio 1/2, which holds once |c| <= (r - N + 1) / 2 (each further row
+// multiplies the dominant Toeplitz term by c / (r + 1 - k), k <= N).  Under
+// (i) and (ii) all dropped rows together stay below eps relative.
+template <typename R> struct SkEps;
+template <> struct SkEps<float> { static constexpr double value = 1.0 / (1 << 26); };
+template <> struct SkEps<double> { static constexpr double value = 1.0 / (double)(1ull << 55); };
+
+__device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) != 0; }
+
+// ---------------------------------------------------------------------------
+// forward cell map
+// ---------------------------------------------------------------------------
+// (P, Q): bottom and left edges in the scaled basis; returns top (Po) and
+// right (Qo).  TMAX = 0: approximation scheme.  TMAX > 0: interpolation
+// scheme with the adaptive tail above; `active` lanes take part in the
+// tail decision (idle lanes may hold stale values).
+template <typename R, int N, int TMAX>
+__device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], R c,
+                                            bool active, const SkTab<R>& tab, R (&Po)[N + 1],
+                                            R (&Qo)[N + 1]) {
+    constexpr int M = N + TMAX;
+    R w[M + 1], cp[M + 1];
+    w[0] = (R)1;
+    cp[0] = (R)1;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        cp[m] = cp[m - 1] * c;
+        w[m] = w[m - 1] * (c * (R)(1.0 / m));
+    }
+#pragma unroll
+    for (int r = 0; r <= N; ++r) {
+        R tp = (R)0, tq = (R)0;
+#pragma unroll
+        for (int k = r; k >= 0; --k) {
+            tp = fma(w[r - k], P[k], tp);
+            tq = fma(w[r - k], Q[k], tq);
+        }
+        R hq = (R)0, hp = (R)0;
+#pragma unroll
+        for (int k = N; k >= 1; --k) {
+            hq = fma(Q[k], ifact<R>(r + k), hq);
+            hp = fma(P[k], ifact<R>(r + k), hp);
+        }
+        Po[r] = fma(cp[r], hq, tp);
+        Qo[r] = fma(cp[r], hp, tq);
+    }
+    if (TMAX > 0) {
+        const R scale = (R)SkEps<R>::value * (sk_abs(Po[0]) + sk_abs(Qo[0]));
+        const R ac = sk_abs(c);
+        R ap[N + 1], aq[N + 1];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            ap[n] = Po[n];
+            aq[n] = Qo[n];
+        }
+#pragma unroll
+        for (int t = 0; t < TMAX; ++t) {
+            const int r = N + 1 + t;
+            R tp = (R)0, tq = (R)0;
+#pragma unroll
+            for (int k = N; k >= 0; --k) {
+                tp = fma(w[r - k], P[k], tp);
+                tq = fma(w[r - k], Q[k], tq);
+            }
+            R hq = (R)0, hp = (R)0;
+#pragma unroll
+            for (int k = N; k >= 1; --k) {
+                hq = fma(Q[k], ifact<R>(r + k), hq);
+                hp = fma(P[k], ifact<R>(r + k), hp);
+            }
+            const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = fma(tab.rs[n][t], arp, ap[n]);
+                aq[n] = fma(tab.rs[n][t], arq, aq[n]);
+            }
+            const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
+            const bool more = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
+            if (!sk_wave_any(more)) break;
+        }
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            Po[n] = ap[n];
+            Qo[n] = aq[n];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint cell map
+// ---------------------------------------------------------------------------
+// Given the cell's inputs (P, Q), constant c and the adjoints a = dL/dPo,
+// b = dL/dQo, returns the adjoints of the inputs (aP = dL/dP, aQ = dL/dQ) and
+// g = dL/dc.  The forward map is linear in (P, Q), so its transpose does not
+// need the inputs; g does: dA^P_r/dc = sum_{k<=min(r-1,N)} w_{r-1-k} P'_k
+// + r c^{r-1} sum_k Q'_k/(r+k)!.
+template <typename R, int N, int TMAX>
+__device__ __forceinline__ void sk_cell_adj(const R (&P)[N + 1], const R (&Q)[N + 1], R c,
+                                            bool active, const SkTab<R>& tab, const R (&a)[N + 1],
+                                            const R (&b)[N + 1], R (&aP)[N + 1],
+                                            R (&aQ)[N + 1], R& g) {
+    constexpr int M = N + TMAX;
+    R w[M + 1], cp[M + 1];
+    w[0] = (R)1;
+    cp[0] = (R)1;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) {
+        cp[m] = cp[m - 1] * c;
+        w[m] = w[m - 1] * (c * (R)(1.0 / m));
+    }
+    // adjoints of the untruncated rows: rows <= N directly, tail rows through
+    // the transposed projection
+    R ea[M + 1], eb[M + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) {
+        ea[n] = a[n];
+        eb[n] = b[n];
+    }
+#pragma unroll
+    for (int t = 0; t < TMAX; ++t) {
+        R sa = (R)0, sb = (R)0;
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            sa = fma(tab.rs[n][t], a[n], sa);
+            sb = fma(tab.rs[n][t], b[n], sb);
+        }
+        ea[N + 1 + t] = sa;
+        eb[N + 1 + t] = sb;
+    }
+    // forward rows (recomputed) give dL/dc and, for the interpolation
+    // scheme, the same tail length as the forward map
+    R gacc = (R)0;
+    R tp_prev = (R)0, tq_prev = (R)0;
+    R scale = (R)0;
+    const R ac = sk_abs(c);
+    int T = 0;
+#pragma unroll
+    for (int r = 0; r <= M; ++r) {
+        R tp = (R)0, tq = (R)0;
+#pragma unroll
+        for (int k = (r < N ? r : N); k >= 0; --k) {
+            tp = fma(w[r - k], P[k], tp);
+            tq = fma(w[r - k], Q[k], tq);
+        }
+        R hq = (R)0, hp = (R)0;
+#pragma unroll
+        for (int k = N; k >= 1; --k) {
+            hq = fma(Q[k], ifact<R>(r + k), hq);
+            hp = fma(P[k], ifact<R>(r + k), hp);
+        }
+        if (r >= 1) {
+            // dA^P_r/dc = (Toeplitz row r-1) + r c^{r-1} H_r(Q)
+            const R rc = (R)r * cp[r - 1];
+            gacc = fma(ea[r], fma(rc, hq, tp_prev), gacc);
+            gacc = fma(eb[r], fma(rc, hp, tq_prev), gacc);
+        }
+        tp_prev = tp;
+        tq_prev = tq;
+        if (r == 0) scale = (R)SkEps<R>::value * (sk_abs(fma(cp[0], hq, tp)) + sk_abs(fma(cp[0], hp, tq)));
+        if (r > N) {
+            T = r - N;
+            const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+            const R tail = (R)2 * tab.rmax[r - N - 1] * (sk_abs(arp) + sk_abs(arq));
+            const bool more = active && (!(tail <= scale) || ac > (R)(0.5 * (r - N + 1)));
+            if (!sk_wave_any(more)) break;
+        }
+    }
+    g = gacc;
+    // transposed map over rows 0..N+T
+    R cb[M + 1], ca[M + 1];
+#pragma unroll
+    for (int r = 0; r <= M; ++r) {
+        ca[r] = cp[r] * ea[r];
+        cb[r] = cp[r] * eb[r];
+    }
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+        R sp = (R)0, sq = (R)0;
+#pragma unroll
+        for (int r = M; r >= k; --r) {
+            if (r <= N + T) {
+                sp = fma(w[r - k], ea[r], sp);
+                sq = fma(w[r - k], eb[r], sq);
+            }
+        }
+        if (k >= 1) {
+#pragma unroll
+            for (int r = M; r >= 0; --r) {
+                if (r <= N + T) {
+                    sp = fma(cb[r], ifact<R>(r + k), sp);
+                    sq = fma(ca[r], ifact<R>(r + k), sq);
+                }
+            }
+        }
+        aP[k] = sp;
+        aQ[k] = sq;
+    }
+}

@@ -1,0 +1,3 @@
+// FP64 instantiation of the batched kernels and their launchers.
+#include "sk_launch_impl.h"
+template struct SkLaunch<double>;

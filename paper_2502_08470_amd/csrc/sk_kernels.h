@@ -1,0 +1,862 @@
+// Kernel templates of the batched signature-kernel path (instantiated per
+// real type in sk_inst_*.hip).  See sk_common.h for the wavefront mapping
+// and the skewed layout, sk_device.h for the cell maps.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sk_common.h"
+#include "sk_device.h"
+
+typedef float sk_f4 __attribute__((ext_vector_type(4)));
+typedef double sk_d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// (a) increment Gram: skewed cell constants by MFMA
+// ---------------------------------------------------------------------------
+template <typename R>
+struct GramArgs {
+    const R* X;
+    const R* Y;
+    int64_t d;
+    int32_t dpad;       // d rounded up to a multiple of 4
+    int32_t lam;        // dyadic refinement (finite differences), 0 otherwise
+    SkPairSrc src;
+    R* cskew;           // chunk buffer of skewed constants
+    unsigned* maxc;     // per chunk-local pair: bits of max |c| (nullable)
+};
+
+template <typename R> struct SkMfma;
+// 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator element v of lane l holds D[row(l, v)][l % 16].  The FP32 and
+// FP64 instructions place the four output rows of a lane differently.
+template <> struct SkMfma<float> {
+    typedef sk_f4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct SkMfma<double> {
+    typedef sk_d4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// One workgroup (4 waves) writes skewed rows [64 b, 64 b + 64) of one pair.
+// For every strip s that owns one of those cells it stages the 64 x-rows of
+// the strip and the 128 y-columns the rows can touch, multiplies them with
+// 16x16x4 MFMAs (K = d) into an LDS tile, 64 columns at a time, and gathers
+// each skewed element from the tile.  Rows are written once, whole,
+// coalesced.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t local = blockIdx.y;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    const int b = blockIdx.x;
+    if (64 * b >= g.nsteps_pad) return;
+    const int dp = a.dpad;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* Xs = reinterpret_cast<R*>(sk_smem);          // [64][dp]
+    R* Ys = Xs + 64 * dp;                            // [128][dp]
+    R* Tt = Ys + 128 * dp;                           // [64][65]
+    const R* X = a.X + pd.x_off * a.d;
+    const R* Y = a.Y + pd.y_off * a.d;
+    const R rscale = (R)1 / (R)(1 << a.lam);
+
+    R val[16];
+    int Le[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        val[q] = (R)0;
+        int e = tid + 256 * q;
+        Le[q] = 64 * b + (e >> 6) - (e & 63);
+    }
+    const int Lmin = 64 * b - 63, Lmax = 64 * b + 63;
+    int s_lo = Lmin < 0 ? 0 : Lmin / g.Tp;
+    int s_hi = Lmax / g.Tp;
+    if (s_hi > g.nstrips - 1) s_hi = g.nstrips - 1;
+    typedef typename SkMfma<R>::acc_t acc_t;
+    for (int s = s_lo; s <= s_hi; ++s) {
+        const int jb = Lmin - s * g.Tp;  // column of tile entry 0
+        __syncthreads();
+        // stage increments (refined: segment increment / 2^lam)
+        for (int e = tid; e < 64 * dp; e += 256) {
+            int rr = e / dp, k = e - rr * dp;
+            int ir = s * 64 + rr;
+            R v = (R)0;
+            if (ir < g.lx && k < a.d) {
+                int i = ir >> a.lam;
+                v = (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale;
+            }
+            Xs[e] = v;
+        }
+        for (int e = tid; e < 128 * dp; e += 256) {
+            int cc = e / dp, k = e - cc * dp;
+            int jr = jb + cc;
+            R v = (R)0;
+            if (jr >= 0 && jr < g.ly && k < a.d) {
+                int j = jr >> a.lam;
+                v = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
+            }
+            Ys[e] = v;
+        }
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();
+            // wave w: rows 16w..16w+15 against columns 64h..64h+63
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                acc_t acc = {0, 0, 0, 0};
+                const int col0 = 64 * h + 16 * ni;
+                for (int kk = 0; kk < dp; kk += 4) {
+                    R av = Xs[(16 * wave + (lane & 15)) * dp + kk + (lane >> 4)];
+                    R bv = Ys[(col0 + (lane & 15)) * dp + kk + (lane >> 4)];
+                    acc = SkMfma<R>::mma(av, bv, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 65 + 16 * ni + (lane & 15)] = acc[v];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int L = Le[q];
+                const int r = (tid + 256 * q) & 63;
+                const int col = L - Lmin - 64 * h;
+                if (L >= 0 && col >= 0 && col < 64) {
+                    int ss = L / g.Tp, j = L - ss * g.Tp;
+                    if (ss == s && j < g.ly && s * 64 + r < g.lx) val[q] = Tt[r * 65 + col];
+                }
+            }
+        }
+    }
+    R* out = a.cskew + pd.c_off + (int64_t)64 * 64 * b;
+    R mx = (R)0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        out[tid + 256 * q] = val[q];
+        R av = sk_abs(val[q]);
+        mx = av > mx ? av : mx;
+    }
+    if (a.maxc) {
+        mx = wave_max(mx);
+        if (lane == 0) atomicMax(a.maxc + local, __float_as_uint((float)mx));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (b) forward wavefront sweep of the polynomial schemes
+// ---------------------------------------------------------------------------
+template <typename R>
+struct SweepArgs {
+    SkPairSrc src;
+    const R* cskew;
+    SkTab<R> tab;
+    R* K;                  // kernel values (mantissas if Kexp)
+    int32_t* Kexp;         // nullable
+    // checkpoint outputs (backward recompute)
+    R* ck;
+    int32_t* ce;
+    R* qb;
+    int32_t* qe;
+};
+
+template <typename R>
+__device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, R v, int E) {
+    if (Kexp) {
+        int e = (v == (R)0 || !sk_finite(v)) ? 0 : sk_frexp_exp(v);
+        K[idx] = sk_ldexp(v, -e);
+        Kexp[idx] = E + e;
+    } else {
+        K[idx] = sk_ldexp(v, E);
+    }
+}
+
+template <typename R, int N, int TMAX, bool CKPT, int S>
+__global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
+    const int r = threadIdx.x;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    if (g.nsteps == 0) {
+        if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* qlds = reinterpret_cast<R*>(sk_smem);
+    int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N + 1));
+    const R* cs = a.cskew + pd.c_off;
+
+    R P[N + 1], Qs[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) {
+        P[n] = (R)0;
+        Qs[n] = (R)0;
+    }
+    int E = 0;
+    int L = -r, s = 0, j = 0;
+    bool live = false;
+    const int nst8 = (g.nsteps + 7) & ~7;
+    R cb[8], cn[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cb[u] = cs[u * 64 + r];
+    for (int t0 = 0; t0 < nst8; t0 += 8) {
+        if (t0 + 8 < g.nsteps_pad) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cn[u] = cs[(int64_t)(t0 + 8 + u) * 64 + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int tau = t0 + u;
+            R Qin[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+            const int i = s * 64 + r;
+            live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
+            if (live) {
+                const R one = sk_ldexp((R)1, -E);
+                if (j == 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) P[n] = n == 0 ? one : (R)0;
+                }
+                if (r == 0) {
+                    if (s == 0) {
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? one : (R)0;
+                    } else {
+                        const int sh = qtag[j] - E;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) Qin[n] = sk_ldexp(qlds[j * (N + 1) + n], sh);
+                    }
+                }
+            }
+            if (CKPT && (tau % S) == 0 && tau < g.nsteps) {
+                R* ck = a.ck + pd.ck_off + (int64_t)(tau / S) * 2 * (N + 1) * 64;
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    ck[n * 64 + r] = P[n];
+                    ck[(N + 1 + n) * 64 + r] = Qin[n];
+                }
+                if (r == 0) a.ce[pd.ce_off + tau / S] = E;
+            }
+            R Po[N + 1], Qo[N + 1];
+            sk_cell_fwd<R, N, TMAX>(P, Qin, cb[u], live, a.tab, Po, Qo);
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                P[n] = Po[n];
+                Qs[n] = Qo[n];
+            }
+            if (live) {
+                if (r == 63 && s + 1 < g.nstrips) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) qlds[j * (N + 1) + n] = Qo[n];
+                    qtag[j] = E;
+                    if (CKPT) {
+                        const int64_t o = (int64_t)(s + 1) * g.ly + j;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
+                        a.qe[pd.qe_off + o] = E;
+                    }
+                }
+                if (i == g.lx - 1 && j == g.ly - 1) {
+                    R kv = (R)0;
+#pragma unroll
+                    for (int n = N; n >= 0; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
+                    sk_write_k(a.K, a.Kexp, pd.k_idx, (R)0.5 * kv, E);
+                }
+            }
+            if (L >= 0) {
+                if (++j == g.Tp) {
+                    j = 0;
+                    ++s;
+                }
+            }
+            ++L;
+        }
+        // exponent tracking: wave-uniform power-of-two rescale of live state
+        R m = (R)0;
+        if (live) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                R ap = sk_abs(P[n]), aq = sk_abs(Qs[n]);
+                m = ap > m ? ap : m;
+                m = aq > m ? aq : m;
+            }
+        }
+        const int sh = sk_rescale_shift<R>(wave_max(m));
+        if (sh != 0) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                P[n] = sk_ldexp(P[n], -sh);
+                Qs[n] = sk_ldexp(Qs[n], -sh);
+            }
+            E += sh;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cb[u] = cn[u];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (d) adjoint sweep: reversed wavefront with segment recompute
+// ---------------------------------------------------------------------------
+template <typename R>
+struct AdjArgs {
+    SkPairSrc src;
+    const R* cskew;
+    SkTab<R> tab;
+    const R* gK;           // dL/dK per output index
+    const int32_t* gKexp;  // nullable: seed = gK * 2^gKexp
+    const R* ck;
+    const int32_t* ce;
+    const R* qb;
+    const int32_t* qe;
+    R* gskew;              // out: skewed dL/dc
+};
+
+template <typename R, int N, int TMAX, int S>
+__global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
+    const int r = threadIdx.x;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    if (g.nsteps == 0) return;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* llds = reinterpret_cast<R*>(sk_smem);
+    int* ltag = reinterpret_cast<int*>(llds + (size_t)g.ly * (N + 1));
+    const R* cs = a.cskew + pd.c_off;
+    R* gs = a.gskew + pd.c_off;
+    const R gk = a.gK[pd.k_idx];
+    const int gexp = a.gKexp ? a.gKexp[pd.k_idx] : 0;
+    int El = gexp;
+
+    R lp[N + 1], lqs[N + 1];
+#pragma unroll
+    for (int n = 0; n <= N; ++n) {
+        lp[n] = (R)0;
+        lqs[n] = (R)0;
+    }
+    const int nck = (g.nsteps + S - 1) / S;
+    for (int kk = nck - 1; kk >= 0; --kk) {
+        const int tau0 = kk * S;
+        R cseg[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
+        // ---- recompute the segment's cell inputs from the checkpoint
+        R Pst[S][N + 1], Qst[S][N + 1];
+        bool lv[S];
+        int sst[S], jst[S];
+        const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
+        const int E = a.ce[pd.ce_off + kk];
+        R P[N + 1], Qs[N + 1];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            P[n] = ck[n * 64 + r];
+            Qs[n] = ck[(N + 1 + n) * 64 + r];
+        }
+        int L = tau0 - r, s = 0, j = 0;
+        if (L >= 0) {
+            s = L / g.Tp;
+            j = L - s * g.Tp;
+        }
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int i = s * 64 + r;
+            const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
+            R Qin[N + 1];
+            if (u == 0) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
+            } else {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                if (live) {
+                    const R one = sk_ldexp((R)1, -E);
+                    if (j == 0) {
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) P[n] = n == 0 ? one : (R)0;
+                    }
+                    if (r == 0) {
+                        if (s == 0) {
+#pragma unroll
+                            for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? one : (R)0;
+                        } else {
+                            const int64_t o = (int64_t)s * g.ly + j;
+                            const int sh = a.qe[pd.qe_off + o] - E;
+#pragma unroll
+                            for (int n = 0; n <= N; ++n)
+                                Qin[n] = sk_ldexp(a.qb[pd.qb_off + o * (N + 1) + n], sh);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                Pst[u][n] = P[n];
+                Qst[u][n] = Qin[n];
+            }
+            lv[u] = live;
+            sst[u] = s;
+            jst[u] = j;
+            if (u < S - 1) {
+                R Po[N + 1], Qo[N + 1];
+                sk_cell_fwd<R, N, TMAX>(P, Qin, cseg[u], live, a.tab, Po, Qo);
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    P[n] = Po[n];
+                    Qs[n] = Qo[n];
+                }
+            }
+            if (L >= 0) {
+                if (++j == g.Tp) {
+                    j = 0;
+                    ++s;
+                }
+            }
+            ++L;
+        }
+        // ---- adjoint steps in reverse
+#pragma unroll
+        for (int u = S - 1; u >= 0; --u) {
+            const int tau = tau0 + u;
+            const bool live = lv[u];
+            const int ss = sst[u], jj = jst[u], i = ss * 64 + r;
+            R lq_recv[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
+            R ap[N + 1], aq[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = (R)0;
+                aq[n] = (R)0;
+            }
+            if (live) {
+                const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
+                if (last_col || last_row) {
+                    // endpoint seed: L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
+                    const R sd = (last_col && last_row) ? sk_ldexp((R)0.5 * gk, gexp - El) : (R)0;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        if (last_col) ap[n] = sd * ifact<R>(n);
+                        if (last_row) aq[n] = sd * ifact<R>(n);
+                    }
+                }
+                if (!last_col) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) ap[n] = lp[n];
+                }
+                if (!last_row) {
+                    if (r == 63) {
+                        const int sh = ltag[jj] - El;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) aq[n] = sk_ldexp(llds[jj * (N + 1) + n], sh);
+                    } else {
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) aq[n] = lq_recv[n];
+                    }
+                }
+            }
+            R gv;
+            sk_cell_adj<R, N, TMAX>(Pst[u], Qst[u], cseg[u], live, a.tab, ap, aq, lp, lqs, gv);
+            if (live && r == 0 && ss > 0) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
+                ltag[jj] = El;
+            }
+            gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, El + E) : (R)0;
+            if ((tau & 7) == 0) {
+                R m = (R)0;
+                if (live) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
+                        m = x1 > m ? x1 : m;
+                        m = x2 > m ? x2 : m;
+                    }
+                }
+                const int sh = sk_rescale_shift<R>(wave_max(m));
+                if (sh != 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        lp[n] = sk_ldexp(lp[n], -sh);
+                        lqs[n] = sk_ldexp(lqs[n], -sh);
+                    }
+                    El += sh;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (e) gradient contraction: dL/dc -> dL/d(dx), dL/d(dy) per pair
+// ---------------------------------------------------------------------------
+template <typename R>
+struct ContractArgs {
+    const R* X;
+    const R* Y;
+    int64_t d;
+    SkPairSrc src;
+    const R* gskew;
+    R* dxp;   // [pair][lx][d]
+    R* dyp;   // [pair][strip][ly][d]
+    int32_t jchunk;  // columns per LDS pass
+};
+
+// One wave per (pair, strip): lane r accumulates dL/d(dx_i) for its row
+// i = 64 s + r in registers; dL/d(dy_j) is accumulated in LDS (lanes touch
+// distinct columns within a step) and written per strip.  The y increments
+// of the current column chunk are staged in LDS next to it.
+template <typename R, int DMAX>
+__global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
+    const int r = threadIdx.x;
+    const int s = blockIdx.x;
+    const int64_t local = blockIdx.y;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    if (g.nsteps == 0 || s >= g.nstrips) return;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    const int64_t d = a.d;
+    const int jc = a.jchunk;
+    R* dyl = reinterpret_cast<R*>(sk_smem);  // [jc][d] accumulators
+    R* ycl = dyl + (int64_t)jc * d;            // [jc][d] y increments
+    const R* X = a.X + pd.x_off * d;
+    const R* Y = a.Y + pd.y_off * d;
+    const R* gsk = a.gskew + pd.c_off;
+    const int i = s * 64 + r;
+    const bool rowok = i < g.lx;
+    R xi[DMAX], acc[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        xi[k] = (R)0;
+        acc[k] = (R)0;
+        if (k < d && rowok) xi[k] = X[(int64_t)(i + 1) * d + k] - X[(int64_t)i * d + k];
+    }
+    for (int j0 = 0; j0 < g.ly; j0 += jc) {
+        const int j1 = (j0 + jc < g.ly) ? j0 + jc : g.ly;
+        for (int e = r; e < (j1 - j0) * d; e += 64) {
+            dyl[e] = (R)0;
+            const int64_t j = j0 + e / d, k = e % d;
+            ycl[e] = Y[(j + 1) * d + k] - Y[j * d + k];
+        }
+        __syncthreads();
+        int tend = s * g.Tp + j1 - 1 + 63;
+        if (tend > g.nsteps - 1) tend = g.nsteps - 1;
+        for (int tau = s * g.Tp + j0; tau <= tend; ++tau) {
+            const int j = tau - r - s * g.Tp;
+            const R gv = gsk[(int64_t)tau * 64 + r];
+            if (rowok && j >= j0 && j < j1) {
+                const int jl = (j - j0) * (int)d;
+#pragma unroll
+                for (int k = 0; k < DMAX; ++k) {
+                    if (k < d) {
+                        acc[k] = fma(gv, ycl[jl + k], acc[k]);
+                        dyl[jl + k] = fma(gv, xi[k], dyl[jl + k]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j0) * d;
+        for (int e = r; e < (j1 - j0) * d; e += 64) dyo[e] = dyl[e];
+        __syncthreads();
+    }
+    if (rowok) {
+#pragma unroll
+        for (int k = 0; k < DMAX; ++k)
+            if (k < d) a.dxp[pd.dx_off + (int64_t)i * d + k] = acc[k];
+    }
+}
+
+// gX[a][t][k] += sum over chunk pairs (a, b) of (dx[t-1][k] - dx[t][k]);
+// gY likewise over (a, b) and strips.  Gram mode.
+template <typename R>
+struct ReduceGramArgs {
+    int64_t nx, ny, lx_pts, ly_pts, d;
+    int64_t first, count;   // chunk pairs [first, first + count)
+    int64_t dx_stride, dy_stride, nstrips;
+    const R* dxp;
+    const R* dyp;
+    R* gX;
+    R* gY;
+};
+
+template <typename R>
+__global__ void k_reduce_gram_x(const ReduceGramArgs<R> a) {
+    const int64_t lx = a.lx_pts - 1, d = a.d;
+    const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
+    const int64_t per = a.lx_pts * d;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (a_hi - a_lo + 1) * per) return;
+    const int64_t ai = a_lo + e / per, rem = e % per, t = rem / d, k = rem % d;
+    int64_t p0 = ai * a.ny, p1 = p0 + a.ny;
+    if (p0 < a.first) p0 = a.first;
+    if (p1 > a.first + a.count) p1 = a.first + a.count;
+    R sum = (R)0;
+    for (int64_t p = p0; p < p1; ++p) {
+        const R* dx = a.dxp + (p - a.first) * a.dx_stride;
+        R v = (R)0;
+        if (t > 0) v += dx[(t - 1) * d + k];
+        if (t < lx) v -= dx[t * d + k];
+        sum += v;
+    }
+    a.gX[ai * per + t * d + k] += sum;
+}
+
+template <typename R>
+__global__ void k_reduce_gram_y(const ReduceGramArgs<R> a) {
+    const int64_t ly = a.ly_pts - 1, d = a.d;
+    const int64_t per = a.ly_pts * d;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.ny * per) return;
+    const int64_t bi = e / per, rem = e % per, t = rem / d, k = rem % d;
+    const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
+    R sum = (R)0;
+    for (int64_t ai = a_lo; ai <= a_hi; ++ai) {
+        const int64_t p = ai * a.ny + bi;
+        if (p < a.first || p >= a.first + a.count) continue;
+        const R* dy = a.dyp + (p - a.first) * a.dy_stride;
+        for (int64_t s = 0; s < a.nstrips; ++s) {
+            const R* dys = dy + s * ly * d;
+            R v = (R)0;
+            if (t > 0) v += dys[(t - 1) * d + k];
+            if (t < ly) v -= dys[t * d + k];
+            sum += v;
+        }
+    }
+    a.gY[bi * per + t * d + k] += sum;
+}
+
+// List mode: every pair owns its own x and y points.
+template <typename R>
+struct ReducePairsArgs {
+    const SkPairDesc* desc;
+    int64_t count, d, max_pts;
+    const R* dxp;
+    const R* dyp;
+    R* gX;
+    R* gY;
+};
+
+template <typename R>
+__global__ void k_reduce_pairs(const ReducePairsArgs<R> a) {
+    const int64_t local = blockIdx.y;
+    const SkPairDesc pd = a.desc[local];
+    const int64_t d = a.d;
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         e < a.max_pts * d; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / d, k = e % d;
+        if (t <= pd.lx) {
+            R v = (R)0;
+            if (pd.lx > 0 && pd.ly > 0) {
+                const R* dx = a.dxp + pd.dx_off;
+                if (t > 0) v += dx[(t - 1) * d + k];
+                if (t < pd.lx) v -= dx[t * d + k];
+            }
+            a.gX[(pd.x_off + t) * d + k] = v;
+        }
+        if (t <= pd.ly) {
+            R v = (R)0;
+            if (pd.lx > 0 && pd.ly > 0) {
+                for (int s = 0; s < g.nstrips; ++s) {
+                    const R* dy = a.dyp + pd.dy_off + (int64_t)s * pd.ly * d;
+                    if (t > 0) v += dy[(t - 1) * d + k];
+                    if (t < pd.ly) v -= dy[t * d + k];
+                }
+            }
+            a.gY[(pd.y_off + t) * d + k] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finite-difference baseline: batched wavefront over the refined grid
+// ---------------------------------------------------------------------------
+template <typename R>
+struct FdArgs {
+    SkPairSrc src;
+    int32_t lam;
+    const R* cskew;   // skewed refined constants c / 4^lam
+    R* K;
+    int32_t* Kexp;
+};
+
+// Lane r owns refined row i and keeps k(s_{i+1}, t_j); it receives
+// k(s_i, t_{j+1}) from lane r-1 and remembers the value received one step
+// earlier, k(s_i, t_j).
+template <typename R>
+__global__ __launch_bounds__(64) void k_sweep_fd(const FdArgs<R> a) {
+    const int r = threadIdx.x;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0) {
+        if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* blds = reinterpret_cast<R*>(sk_smem);  // k(s_{64 s}, t_{j+1}) from strip s-1
+    const R* cs = a.cskew + pd.c_off;
+    R kown = (R)1, bprev = (R)1, out = (R)1;
+    int L = -r, s = 0, j = 0;
+    for (int tau = 0; tau < g.nsteps; ++tau) {
+        R b = lane_from_prev(out);
+        const int i = s * 64 + r;
+        const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
+        const R c = cs[(int64_t)tau * 64 + r];
+        if (live) {
+            R kij;
+            if (j == 0) {
+                kown = (R)1;
+                kij = (R)1;
+            } else {
+                kij = bprev;
+            }
+            if (r == 0) {
+                b = (s == 0) ? (R)1 : blds[j];
+                kij = (s == 0 || j == 0) ? (R)1 : blds[j - 1];
+            }
+            out = kown + b - kij + (R)0.5 * c * (kown + b);
+            kown = out;
+            bprev = b;
+            if (r == 63 && s + 1 < g.nstrips) blds[j] = out;
+            if (i == g.lx - 1 && j == g.ly - 1) sk_write_k(a.K, a.Kexp, pd.k_idx, out, 0);
+        }
+        if (L >= 0) {
+            if (++j == g.Tp) {
+                j = 0;
+                ++s;
+            }
+        }
+        ++L;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// plain single-pair kernels (one pair per launch, anti-diagonal parallel,
+// cell constants computed on the fly, state in workspace memory)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PlainArgs {
+    const R* x;        // points of x
+    const R* y;
+    int64_t d;
+    int32_t lx, ly;    // segments
+    int32_t lam;
+    R* pst;            // polynomial: [lx][N+1] bottom edges, [ly][N+1] left edges
+    R* diag;           // finite differences: 3 rotating node diagonals of length lx*2^lam + 1
+    SkTab<R> tab;
+    R* K;
+    int32_t* Kexp;
+    int64_t k_idx;
+};
+
+template <typename R>
+__device__ __forceinline__ R sk_dot_inc(const R* x, const R* y, int64_t d, int i, int j) {
+    R acc = (R)0;
+    for (int64_t k = 0; k < d; ++k)
+        acc = fma(x[(int64_t)(i + 1) * d + k] - x[(int64_t)i * d + k],
+                  y[(int64_t)(j + 1) * d + k] - y[(int64_t)j * d + k], acc);
+    return acc;
+}
+
+template <typename R, int N, int TMAX>
+__global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
+    const int lx = a.lx, ly = a.ly;
+    R* pe = a.pst;                         // p^{i, j}
+    R* qe = a.pst + (int64_t)lx * (N + 1); // q^{i, j}
+    for (int e = threadIdx.x; e < (lx + ly) * (N + 1); e += blockDim.x)
+        a.pst[e] = (e % (N + 1)) == 0 ? (R)1 : (R)0;
+    __syncthreads();
+    for (int dg = 0; dg <= lx + ly - 2; ++dg) {
+        int i_lo = dg - (ly - 1);
+        if (i_lo < 0) i_lo = 0;
+        const int i_hi = dg < lx - 1 ? dg : lx - 1;
+        for (int i = i_lo + threadIdx.x; i <= i_hi; i += blockDim.x) {
+            const int j = dg - i;
+            const R c = sk_dot_inc(a.x, a.y, a.d, i, j);
+            R P[N + 1], Q[N + 1], Po[N + 1], Qo[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                P[n] = pe[i * (N + 1) + n];
+                Q[n] = qe[j * (N + 1) + n];
+            }
+            sk_cell_fwd<R, N, TMAX>(P, Q, c, true, a.tab, Po, Qo);
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                pe[i * (N + 1) + n] = Po[n];
+                qe[j * (N + 1) + n] = Qo[n];
+            }
+            if (i == lx - 1 && j == ly - 1) {
+                R kv = (R)0;
+#pragma unroll
+                for (int n = N; n >= 0; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
+                sk_write_k(a.K, a.Kexp, a.k_idx, (R)0.5 * kv, 0);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_plain_fd(const PlainArgs<R> a) {
+    const int m = a.lx << a.lam, n = a.ly << a.lam;
+    const R sc = (R)1 / (R)((int64_t)1 << (2 * a.lam));
+    // node (x, y) lies on node diagonal x + y; three rotating diagonals indexed by x
+    R* D[3] = {a.diag, a.diag + (m + 1), a.diag + 2 * (m + 1)};
+    for (int e = threadIdx.x; e < 3 * (m + 1); e += blockDim.x) a.diag[e] = (R)1;
+    __syncthreads();
+    for (int dg = 0; dg <= m + n - 2; ++dg) {
+        R* d0 = D[dg % 3];        // nodes on diagonal dg
+        R* d1 = D[(dg + 1) % 3];  // dg + 1
+        R* d2 = D[(dg + 2) % 3];  // dg + 2 (written)
+        int i_lo = dg - (n - 1);
+        if (i_lo < 0) i_lo = 0;
+        const int i_hi = dg < m - 1 ? dg : m - 1;
+        for (int i = i_lo + threadIdx.x; i <= i_hi; i += blockDim.x) {
+            const int j = dg - i;
+            const R c = sk_dot_inc(a.x, a.y, a.d, i >> a.lam, j >> a.lam) * sc;
+            const R k00 = d0[i], k10 = d1[i + 1], k01 = d1[i];
+            const R k11 = k10 + k01 - k00 + (R)0.5 * c * (k10 + k01);
+            d2[i + 1] = k11;
+            if (i == m - 1 && j == n - 1) sk_write_k(a.K, a.Kexp, a.k_idx, k11, 0);
+        }
+        // boundary nodes (0, dg + 2) and (dg + 2, 0) stay 1
+        if (threadIdx.x == 0) d2[0] = (R)1;
+        if (threadIdx.x == 0 && dg + 2 <= m) d2[dg + 2] = (R)1;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: skewed constants back to row-major C[p][i][j]
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_unskew(SkPairSrc src, const R* cskew, R* C, int64_t first) {
+    const int64_t local = blockIdx.y;
+    const SkPairDesc pd = sk_pair(src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    const int64_t n = (int64_t)pd.lx * pd.ly;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / pd.ly), j = (int)(e % pd.ly);
+        const int s = i / 64, r = i % 64;
+        const int64_t tau = (int64_t)s * g.Tp + j + r;
+        C[(first + local) * n + e] = cskew[pd.c_off + tau * 64 + r];
+    }
+}

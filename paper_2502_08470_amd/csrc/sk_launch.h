@@ -1,0 +1,43 @@
+// Host-side launchers of the batched kernels (defined per real type in
+// sk_inst_f32.hip / sk_inst_f64.hip).  Argument structs live in sk_kernels.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sk_kernels.h"
+
+// orders with compiled polynomial kernels
+#define SK_MIN_ORDER 2
+#define SK_MAX_ORDER 8
+#define SK_MAX_DYADIC 8
+#define SK_MAX_DIM 64
+// checkpoint stride of the adjoint's forward recompute
+template <typename R> struct SkCkptStride;
+template <> struct SkCkptStride<float> { static constexpr int value = 4; };
+template <> struct SkCkptStride<double> { static constexpr int value = 2; };
+
+template <typename R>
+struct SkLaunch {
+    static hipError_t fill(R* p, int64_t n, R v, hipStream_t st);
+    static hipError_t fill_u32(unsigned* p, int64_t n, hipStream_t st);
+    static hipError_t gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs, hipStream_t st);
+    static hipError_t sweep(const SweepArgs<R>& a, int N, bool interp, bool ckpt, int64_t npairs,
+                            int max_ly, hipStream_t st);
+    static hipError_t adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs, int max_ly,
+                              hipStream_t st);
+    static hipError_t contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
+                               hipStream_t st);
+    static hipError_t reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st);
+    static hipError_t reduce_pairs(const ReducePairsArgs<R>& a, hipStream_t st);
+    static hipError_t sweep_fd(const FdArgs<R>& a, int64_t npairs, int max_ly_refined,
+                               hipStream_t st);
+    static hipError_t plain_poly(const PlainArgs<R>& a, int N, bool interp, hipStream_t st);
+    static hipError_t plain_fd(const PlainArgs<R>& a, hipStream_t st);
+    static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
+                             int64_t npairs, int64_t cells, hipStream_t st);
+    // LDS bytes needed per workgroup by the sweep / adjoint for a given column count
+    static size_t sweep_lds(int N, int ly) { return (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4; }
+    static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 65) * sizeof(R); }
+};
+
+extern template struct SkLaunch<float>;
+extern template struct SkLaunch<double>;

@@ -1,0 +1,206 @@
+// Definitions of SkLaunch<R> (included once per real type).
+#pragma once
+#include "sk_launch.h"
+
+#define SK_CHECK_LAUNCH() \
+    do {                  \
+        hipError_t e_ = hipGetLastError(); \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+template <typename R>
+hipError_t SkLaunch<R>::fill(R* p, int64_t n, R v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::fill_u32(unsigned* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3((unsigned)blocks), dim3(256), 0, st, p, n, 0u);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs,
+                             hipStream_t st) {
+    if (npairs <= 0 || ntau_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_skew<R>, dim3(ntau_blocks, (unsigned)npairs), dim3(256),
+                       gram_lds(a.dpad), st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R, int N, int TMAX>
+static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int max_ly,
+                             hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    size_t lds = SkLaunch<R>::sweep_lds(N, max_ly);
+    if (ckpt)
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, true, S>), dim3((unsigned)npairs), dim3(64), lds,
+                           st, a);
+    else
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, false, S>), dim3((unsigned)npairs), dim3(64), lds,
+                           st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R, int N>
+static hipError_t sk_sweep_t(const SweepArgs<R>& a, bool interp, bool ckpt, int64_t npairs,
+                             int max_ly, hipStream_t st) {
+    return interp ? sk_sweep_n<R, N, SkTailMax<R>::value>(a, ckpt, npairs, max_ly, st)
+                  : sk_sweep_n<R, N, 0>(a, ckpt, npairs, max_ly, st);
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::sweep(const SweepArgs<R>& a, int N, bool interp, bool ckpt,
+                              int64_t npairs, int max_ly, hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    switch (N) {
+        case 2: return sk_sweep_t<R, 2>(a, interp, ckpt, npairs, max_ly, st);
+        case 3: return sk_sweep_t<R, 3>(a, interp, ckpt, npairs, max_ly, st);
+        case 4: return sk_sweep_t<R, 4>(a, interp, ckpt, npairs, max_ly, st);
+        case 5: return sk_sweep_t<R, 5>(a, interp, ckpt, npairs, max_ly, st);
+        case 6: return sk_sweep_t<R, 6>(a, interp, ckpt, npairs, max_ly, st);
+        case 7: return sk_sweep_t<R, 7>(a, interp, ckpt, npairs, max_ly, st);
+        case 8: return sk_sweep_t<R, 8>(a, interp, ckpt, npairs, max_ly, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int N, int TMAX>
+static hipError_t sk_adj_n(const AdjArgs<R>& a, int64_t npairs, int max_ly, hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    size_t lds = SkLaunch<R>::sweep_lds(N, max_ly);
+    hipLaunchKernelGGL((k_adjoint<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R, int N>
+static hipError_t sk_adj_t(const AdjArgs<R>& a, bool interp, int64_t npairs, int max_ly,
+                           hipStream_t st) {
+    return interp ? sk_adj_n<R, N, SkTailMax<R>::value>(a, npairs, max_ly, st)
+                  : sk_adj_n<R, N, 0>(a, npairs, max_ly, st);
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs,
+                                int max_ly, hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    switch (N) {
+        case 2: return sk_adj_t<R, 2>(a, interp, npairs, max_ly, st);
+        case 3: return sk_adj_t<R, 3>(a, interp, npairs, max_ly, st);
+        case 4: return sk_adj_t<R, 4>(a, interp, npairs, max_ly, st);
+        case 5: return sk_adj_t<R, 5>(a, interp, npairs, max_ly, st);
+        case 6: return sk_adj_t<R, 6>(a, interp, npairs, max_ly, st);
+        case 7: return sk_adj_t<R, 7>(a, interp, npairs, max_ly, st);
+        case 8: return sk_adj_t<R, 8>(a, interp, npairs, max_ly, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
+                                 hipStream_t st) {
+    if (npairs <= 0 || max_strips <= 0) return hipSuccess;
+    size_t lds = (size_t)2 * a.jchunk * a.d * sizeof(R);
+    dim3 grid(max_strips, (unsigned)npairs);
+    if (a.d <= 4)
+        hipLaunchKernelGGL((k_contract<R, 4>), grid, dim3(64), lds, st, a);
+    else if (a.d <= 8)
+        hipLaunchKernelGGL((k_contract<R, 8>), grid, dim3(64), lds, st, a);
+    else if (a.d <= 16)
+        hipLaunchKernelGGL((k_contract<R, 16>), grid, dim3(64), lds, st, a);
+    else if (a.d <= 32)
+        hipLaunchKernelGGL((k_contract<R, 32>), grid, dim3(64), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_contract<R, 64>), grid, dim3(64), lds, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
+    int64_t nx_e = (a_hi - a_lo + 1) * a.lx_pts * a.d;
+    int64_t ny_e = a.ny * a.ly_pts * a.d;
+    hipLaunchKernelGGL(k_reduce_gram_x<R>, dim3((unsigned)((nx_e + 255) / 256)), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_reduce_gram_y<R>, dim3((unsigned)((ny_e + 255) / 256)), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::reduce_pairs(const ReducePairsArgs<R>& a, hipStream_t st) {
+    if (a.count <= 0) return hipSuccess;
+    int64_t e = a.max_pts * a.d;
+    int64_t bx = (e + 255) / 256;
+    if (bx > 64) bx = 64;
+    hipLaunchKernelGGL(k_reduce_pairs<R>, dim3((unsigned)bx, (unsigned)a.count), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::sweep_fd(const FdArgs<R>& a, int64_t npairs, int max_ly_refined,
+                                 hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sweep_fd<R>, dim3((unsigned)npairs), dim3(64),
+                       (size_t)max_ly_refined * sizeof(R), st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R, int N>
+static hipError_t sk_plain_n(const PlainArgs<R>& a, bool interp, hipStream_t st) {
+    if (interp)
+        hipLaunchKernelGGL((k_plain_poly<R, N, SkTailMax<R>::value>), dim3(1), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_plain_poly<R, N, 0>), dim3(1), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::plain_poly(const PlainArgs<R>& a, int N, bool interp, hipStream_t st) {
+    switch (N) {
+        case 2: return sk_plain_n<R, 2>(a, interp, st);
+        case 3: return sk_plain_n<R, 3>(a, interp, st);
+        case 4: return sk_plain_n<R, 4>(a, interp, st);
+        case 5: return sk_plain_n<R, 5>(a, interp, st);
+        case 6: return sk_plain_n<R, 6>(a, interp, st);
+        case 7: return sk_plain_n<R, 7>(a, interp, st);
+        case 8: return sk_plain_n<R, 8>(a, interp, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::plain_fd(const PlainArgs<R>& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_plain_fd<R>, dim3(1), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
+                               int64_t npairs, int64_t cells, hipStream_t st) {
+    if (npairs <= 0 || cells <= 0) return hipSuccess;
+    int64_t bx = (cells + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(k_unskew<R>, dim3((unsigned)bx, (unsigned)npairs), dim3(256), 0, st, src,
+                       cskew, C, first);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}

@@ -1,0 +1,157 @@
+"""GPU backward parity: the adjoint sweep against oracle gradients.
+
+* Tiny FP64 inputs: complex-step derivatives of the numpy oracle (exact to
+  rounding): 1e-10 relative in the max norm.
+* Larger FP64 / FP32 inputs: central finite differences of the C oracle
+  (h = 1e-4, FP64) on sampled coordinates; FP64 path within 1e-6 relative
+  (the FD truncation error is O(h^2)), FP32 path within 1e-5 relative (the
+  gradient target of the FP32 path).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import bm_paths, log_banner, oracle_gram
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2502_08470_amd as P
+    from paper_2502_08470_amd import _lib
+    _lib.lib()
+    return P
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 4), ("interp", 4), ("approx", 2)])
+def test_tiny_gradient_matches_complex_step(sk, scheme, order):
+    from oracle import derivatives as D
+    from oracle import schemes as S
+    log_banner(f"tiny gradient {scheme} {order}")
+    rng = np.random.default_rng(3)
+    X = bm_paths(rng, 2, 5, 2, 0.5)
+    Y = bm_paths(rng, 3, 4, 2, 0.5)
+    gK = rng.normal(size=(2, 3))
+    fn = S.approx_scheme if scheme == "approx" else S.interp_scheme
+    gXo = np.zeros_like(X)
+    gYo = np.zeros_like(Y)
+    for a in range(2):
+        for b in range(3):
+            gXo[a] += gK[a, b] * D.complex_step_grad(fn, X[a], Y[b], wrt="x", N=order)
+            gYo[b] += gK[a, b] * D.complex_step_grad(fn, X[a], Y[b], wrt="y", N=order)
+    gX, gY = sk.gram_backward(dev(X, torch.float64), dev(Y, torch.float64),
+                              dev(gK, torch.float64), scheme, order)
+    np.testing.assert_allclose(gX.cpu().numpy(), gXo, rtol=0, atol=1e-10 * np.abs(gXo).max())
+    np.testing.assert_allclose(gY.cpu().numpy(), gYo, rtol=0, atol=1e-10 * np.abs(gYo).max())
+
+
+def fd_gram_grad(X, Y, gK, scheme, order, idx, which, h=1e-4):
+    """Central difference of sum(gK * K) in one coordinate of X or Y."""
+    def loss(Xv, Yv):
+        m, e = oracle_gram(Xv, Yv, scheme, order)
+        return float(np.sum(gK * np.ldexp(m, e)))
+    P = (X if which == "x" else Y).copy()
+    P[idx] += h
+    lp = loss(P, Y) if which == "x" else loss(X, P)
+    P[idx] -= 2 * h
+    lm = loss(P, Y) if which == "x" else loss(X, P)
+    return (lp - lm) / (2 * h)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-6), (torch.float32, 1e-5)])
+@pytest.mark.parametrize("scheme,order", [("approx", 6), ("interp", 5)])
+def test_multi_strip_gradient_matches_finite_differences(sk, dtype, tol, scheme, order):
+    log_banner(f"multi-strip gradient {dtype} {scheme} {order}")
+    rng = np.random.default_rng(21)
+    X = bm_paths(rng, 2, 140, 3, 0.4 / np.sqrt(140))
+    Y = bm_paths(rng, 2, 75, 3, 0.4 / np.sqrt(75))
+    if dtype == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+        Y = Y.astype(np.float32).astype(np.float64)
+    gK = rng.normal(size=(2, 2))
+    gX, gY = sk.gram_backward(dev(X, dtype), dev(Y, dtype), dev(gK, dtype), scheme, order)
+    gX, gY = gX.cpu().double().numpy(), gY.cpu().double().numpy()
+    picks = [("x", (0, 0, 0)), ("x", (1, 63, 1)), ("x", (0, 64, 2)), ("x", (1, 140, 0)),
+             ("y", (0, 0, 1)), ("y", (1, 37, 2)), ("y", (0, 75, 0)), ("x", (1, 100, 1))]
+    scale = max(np.abs(gX).max(), np.abs(gY).max())
+    for which, idx in picks:
+        fd = fd_gram_grad(X, Y, gK, scheme, order, idx, which)
+        got = gX[idx] if which == "x" else gY[idx]
+        assert abs(got - fd) <= tol * scale, (which, idx, got, fd)
+
+
+def test_gradient_seed_exponent(sk):
+    rng = np.random.default_rng(4)
+    X = dev(bm_paths(rng, 2, 70, 3, 0.05), torch.float64)
+    Y = dev(bm_paths(rng, 2, 80, 3, 0.05), torch.float64)
+    gK = dev(rng.normal(size=(2, 2)), torch.float64)
+    ge = torch.tensor([[3, -2], [0, 5]], dtype=torch.int32, device="cuda")
+    gX1, gY1 = sk.gram_backward(X, Y, gK * torch.pow(2.0, ge.double()), "approx", 4)
+    gX2, gY2 = sk.gram_backward(X, Y, gK, "approx", 4, gK_exp=ge)
+    torch.testing.assert_close(gX1, gX2, rtol=1e-13, atol=0)
+    torch.testing.assert_close(gY1, gY2, rtol=1e-13, atol=0)
+
+
+def test_pairs_gradient_matches_finite_differences(sk):
+    from oracle import c_oracle as C
+    log_banner("pairs gradient")
+    rng = np.random.default_rng(8)
+    lens_x, lens_y = [70, 3, 130], [66, 90, 2]
+    xs = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0] for n in lens_x]
+    ys = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0] for n in lens_y]
+    gk = rng.normal(size=3)
+    gXc, gYc, xo, yo = sk.pairs_backward([dev(a, torch.float64) for a in xs],
+                                         [dev(b, torch.float64) for b in ys],
+                                         dev(gk, torch.float64), "approx", 5)
+    gXc = gXc.cpu().numpy()
+    for p, t, k in [(0, 0, 0), (0, 69, 2), (2, 64, 1), (1, 1, 0)]:
+        def loss(v):
+            xs2 = list(xs)
+            xs2[p] = v
+            m, e = C.pairs(xs2, ys, C.APPROX, 5)
+            return float(np.sum(gk * np.ldexp(m, e)))
+        h = 1e-4
+        v = xs[p].copy()
+        v[t, k] += h
+        lp = loss(v)
+        v[t, k] -= 2 * h
+        lm = loss(v)
+        fd = (lp - lm) / (2 * h)
+        assert abs(gXc[xo[p] + t, k] - fd) <= 1e-6 * max(1.0, abs(fd)), (p, t, k)
+
+
+def test_autograd_and_mmd_fp32(sk):
+    log_banner("autograd mmd fp32")
+    import workloads as W
+    X, Y = W.mmd_sets(0, n=3, steps=256)
+    Xt = dev(X, torch.float32).requires_grad_(True)
+    Yt = dev(Y, torch.float32).requires_grad_(True)
+    val = sk.mmd2(Xt, Yt, "approx", 8)
+    val.backward()
+    gX = Xt.grad.cpu().double().numpy()
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+
+    def mmd(Xv, Yv):
+        from oracle import schemes as S
+        kxx = np.ldexp(*oracle_gram(Xv, Xv, "approx", 8))
+        kyy = np.ldexp(*oracle_gram(Yv, Yv, "approx", 8))
+        kxy = np.ldexp(*oracle_gram(Xv, Yv, "approx", 8))
+        return S.mmd2_unbiased(kxx, kyy, kxy)
+    assert float(val) == pytest.approx(mmd(Xd, Yd), rel=1e-4, abs=1e-6)
+    scale = np.abs(gX).max()
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        idx = (int(rng.integers(3)), int(rng.integers(257)), int(rng.integers(5)))
+        h = 1e-4
+        P = Xd.copy()
+        P[idx] += h
+        lp = mmd(P, Yd)
+        P[idx] -= 2 * h
+        lm = mmd(P, Yd)
+        fd = (lp - lm) / (2 * h)
+        assert abs(gX[idx] - fd) <= 1e-5 * scale, (idx, gX[idx], fd)
