@@ -230,12 +230,12 @@ int ckpt_stride(const sk_params& p) {
 // workspace layout of one chunk
 // ---------------------------------------------------------------------------
 struct Layout {
-    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, total;
+    int64_t cskew, gskew, ck, ce, qb, qe, ck0, qb0, dxp, dyp, kbuf, kexp, desc, total;
 };
 
 // Region sizes for P pairs with total per-array element counts `z` (sum over
 // the chunk's pairs).
-Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, bool list) {
+Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, bool list, int N) {
     Layout L;
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -249,6 +249,8 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     L.ce = backward ? take(z.ce * 4) : off;
     L.qb = backward ? take(z.qb * (int64_t)es) : off;
     L.qe = backward ? take(z.qe * 4) : off;
+    L.ck0 = backward ? take(z.ck / (N + 1) * 8) : off;  // FP64 corner coefficients
+    L.qb0 = backward ? take(z.qe * 8) : off;
     L.dxp = backward ? take(z.dx * (int64_t)es) : off;
     L.dyp = backward ? take(z.dy * (int64_t)es) : off;
     L.kbuf = backward ? take(P * (int64_t)es) : off;
@@ -271,13 +273,13 @@ SkPairSizes add(const SkPairSizes& a, const SkPairSizes& b) {
 
 // Gram: largest chunk of uniform pairs that fits in `bytes`.
 int64_t gram_chunk(const SkPairSizes& per, int64_t npairs, size_t es, bool backward,
-                   size_t bytes) {
+                   size_t bytes, int N) {
     if (npairs <= 0) return 0;
-    int64_t one = layout_for(per, 1, es, backward, false).total;
+    int64_t one = layout_for(per, 1, es, backward, false, N).total;
     if ((size_t)one > bytes) return 0;
     int64_t P = std::min<int64_t>(npairs, (int64_t)(bytes / (size_t)std::max<int64_t>(1, one)) + 1);
-    while (P > 1 && (size_t)layout_for(scale(per, P), P, es, backward, false).total > bytes) {
-        int64_t per_b = layout_for(scale(per, P), P, es, backward, false).total / P + 1;
+    while (P > 1 && (size_t)layout_for(scale(per, P), P, es, backward, false, N).total > bytes) {
+        int64_t per_b = layout_for(scale(per, P), P, es, backward, false, N).total / P + 1;
         int64_t guess = (int64_t)(bytes / (size_t)per_b);
         P = std::max<int64_t>(1, std::min(P - 1, guess));
     }
@@ -368,12 +370,12 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
             }
         return SK_OK;
     }
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false);
+    const int64_t P = gram_chunk(per, npairs, sizeof(R), false, wsb, p.order);
+    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
     int rc = check_lds<R>(p, ly, d);
     if (rc) return rc;
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false);
-    const int64_t P = gram_chunk(per, npairs, sizeof(R), false, wsb);
-    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
-    const Layout L = layout_for(scale(per, P), P, sizeof(R), false, false);
+    const Layout L = layout_for(scale(per, P), P, sizeof(R), false, false, p.order);
     const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
     for (int64_t first = 0; first < npairs; first += P) {
         const int64_t cnt = std::min(P, npairs - first);
@@ -413,8 +415,8 @@ int plan_pairs(const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
         nxt.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
         nxt.max_ly = std::max(cur.max_ly, ly);
         nxt.max_pts = std::max<int64_t>(cur.max_pts, std::max(lx, ly) + 1);
-        const size_t bytes = (size_t)layout_for(nxt.tot, nxt.count, es, backward, true).total;
-        max_one = std::max(max_one, (size_t)layout_for(z, 1, es, backward, true).total);
+        const size_t bytes = (size_t)layout_for(nxt.tot, nxt.count, es, backward, true, p.order).total;
+        max_one = std::max(max_one, (size_t)layout_for(z, 1, es, backward, true, p.order).total);
         if (bytes > wsb && cur.count > 0) {
             out.push_back(cur);
             cur = {i, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0};
@@ -487,7 +489,7 @@ int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo
     int rc = check_lds<R>(p, max_ly, d);
     if (rc) return rc;
     for (const ListChunk& c : chunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), false, true);
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), false, true, p.order);
         std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, false);
         SkPairDesc* ddesc = reinterpret_cast<SkPairDesc*>((char*)ws + L.desc);
         SK_TRY_HIP(hipMemcpyAsync(ddesc, desc.data(), desc.size() * sizeof(SkPairDesc),
@@ -531,18 +533,21 @@ int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     sa.qb = reinterpret_cast<R*>(ws + L.qb);
     sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
+    sa.ck0 = reinterpret_cast<double*>(ws + L.ck0);
+    sa.qb0 = reinterpret_cast<double*>(ws + L.qb0);
     SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, max_ly, st), "checkpoint sweep");
     AdjArgs<R> aa;
     std::memset(&aa, 0, sizeof(aa));
     aa.src = src; aa.cskew = cskew; aa.tab = sa.tab; aa.gK = gK; aa.gKexp = gKexp;
-    aa.ck = sa.ck; aa.ce = sa.ce; aa.qb = sa.qb; aa.qe = sa.qe;
+    aa.ck = sa.ck; aa.ce = sa.ce; aa.qb = sa.qb; aa.qe = sa.qe; aa.ck0 = sa.ck0; aa.qb0 = sa.qb0;
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, max_ly, st), "adjoint sweep");
     ContractArgs<R> ca;
     ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = aa.gskew;
     ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
     ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
-    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (2 * d * (int64_t)sizeof(R))));
+    const int64_t dmax = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64;
+    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (dmax * (int64_t)sizeof(R))));
     SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
     return SK_OK;
 }
@@ -551,17 +556,21 @@ template <typename R>
 int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
                   int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX, R* gY,
                   void* ws, size_t wsb, hipStream_t st) {
-    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
-    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
     const int64_t npairs = nx * ny;
     const int64_t lx = lxp - 1, ly = lyp - 1;
-    if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
+    if (npairs == 0 || lx == 0 || ly == 0) {
+        SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+        SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+        return SK_OK;
+    }
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true);
+    const int64_t P = gram_chunk(per, npairs, sizeof(R), true, wsb, p.order);
+    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
     int rc = check_lds<R>(p, ly, d);
     if (rc) return rc;
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true);
-    const int64_t P = gram_chunk(per, npairs, sizeof(R), true, wsb);
-    if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
-    const Layout L = layout_for(scale(per, P), P, sizeof(R), true, false);
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+    const Layout L = layout_for(scale(per, P), P, sizeof(R), true, false, p.order);
     const SkGeom g = sk_make_geom((int)lx, (int)ly);
     for (int64_t first = 0; first < npairs; first += P) {
         const int64_t cnt = std::min(P, npairs - first);
@@ -587,8 +596,6 @@ template <typename R>
 int pairs_backward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
                    int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX, R* gY,
                    void* ws, size_t wsb, hipStream_t st) {
-    SK_TRY_HIP(SkLaunch<R>::fill(gX, xo[npairs] * d, (R)0, st), "fill");
-    SK_TRY_HIP(SkLaunch<R>::fill(gY, yo[npairs] * d, (R)0, st), "fill");
     if (npairs == 0) return SK_OK;
     std::vector<ListChunk> chunks;
     size_t need_one = 0;
@@ -598,8 +605,10 @@ int pairs_backward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* y
     for (auto& c : chunks) max_ly = std::max(max_ly, c.max_ly);
     int rc = check_lds<R>(p, max_ly, d);
     if (rc) return rc;
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, xo[npairs] * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, yo[npairs] * d, (R)0, st), "fill");
     for (const ListChunk& c : chunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, true);
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, true, p.order);
         std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, true);
         // the checkpoint pass writes kernel values by k_idx: route them to the
         // chunk's scratch slots
@@ -695,9 +704,9 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
     const SkPairSizes per = sk_pair_sizes((int)(lx_pts - 1), (int)(ly_pts - 1), lam, p->order,
                                           ckpt_stride(*p), d, backward != 0);
     const int64_t npairs = std::max<int64_t>(1, nx * ny);
-    int64_t P = gram_chunk(per, npairs, esize(*p), backward != 0, kDefaultCap);
+    int64_t P = gram_chunk(per, npairs, esize(*p), backward != 0, kDefaultCap, p->order);
     if (P <= 0) P = 1;
-    return std::max<size_t>(256, (size_t)layout_for(scale(per, P), P, esize(*p), backward != 0, false).total);
+    return std::max<size_t>(256, (size_t)layout_for(scale(per, P), P, esize(*p), backward != 0, false, p->order).total);
 }
 
 size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int64_t npairs,
@@ -721,7 +730,7 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     plan_pairs(x_off, y_off, npairs, d, *p, backward != 0, kDefaultCap, chunks, &need_one);
     size_t best = need_one;
     for (const ListChunk& c : chunks)
-        best = std::max(best, (size_t)layout_for(c.tot, c.count, esize(*p), backward != 0, true).total);
+        best = std::max(best, (size_t)layout_for(c.tot, c.count, esize(*p), backward != 0, true, p->order).total);
     return std::max<size_t>(best, 256);
 }
 
@@ -827,9 +836,9 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
     if (!X || !Y || !C || !ws) return fail(SK_EINVAL, "NULL pointer");
     const size_t es = esize(p);
     const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, false);
-    const int64_t P = gram_chunk(per, npairs, es, false, ws_bytes);
+    const int64_t P = gram_chunk(per, npairs, es, false, ws_bytes, p.order);
     if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
-    const Layout L = layout_for(scale(per, P), P, es, false, false);
+    const Layout L = layout_for(scale(per, P), P, es, false, false, p.order);
     const SkGeom g = sk_make_geom((int)lx, (int)ly);
     for (int64_t first = 0; first < npairs; first += P) {
         const int64_t cnt = std::min(P, npairs - first);

@@ -2,6 +2,10 @@
 // one-cell maps of the polynomial schemes.
 //
 // Edge coefficients are kept in the factorial-scaled basis P'_n = n! P_n,
+// in the working precision R, except the constant coefficient P'_0 (the
+// kernel value at the cell corner), which is carried and updated in FP64 as
+// well: its update adds O(c) corrections to an O(1) value every cell, the
+// dominant source of rounding error in an FP32 sweep.
 // where P_n are the coefficients of an edge in its cell's local variable
 // u in [0, 1].  In that basis the untruncated one-step map of Proposition
 // "approxsolution" (eqs. powerseries1/2, normalised cell, constant c) reads
@@ -137,9 +141,10 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // scheme with the adaptive tail above; `active` lanes take part in the
 // tail decision (idle lanes may hold stale values).
 template <typename R, int N, int TMAX>
-__device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], R c,
-                                            bool active, const SkTab<R>& tab, R (&Po)[N + 1],
-                                            R (&Qo)[N + 1]) {
+__device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
+                                            double Q0, R c, bool active, const SkTab<R>& tab,
+                                            R (&Po)[N + 1], R (&Qo)[N + 1], double& Po0,
+                                            double& Qo0) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
@@ -149,8 +154,20 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         cp[m] = cp[m - 1] * c;
         w[m] = w[m - 1] * (c * (R)(1.0 / m));
     }
+    // row 0 carries the kernel value at the corner: P'_0 + sum_{k>=1} Q'_k/k!
+    // (and symmetrically); the corner coefficient is accumulated in FP64
+    {
+        R hq = (R)0, hp = (R)0;
 #pragma unroll
-    for (int r = 0; r <= N; ++r) {
+        for (int k = N; k >= 1; --k) {
+            hq = fma(Q[k], ifact<R>(k), hq);
+            hp = fma(P[k], ifact<R>(k), hp);
+        }
+        Po0 = P0 + (double)hq;
+        Qo0 = Q0 + (double)hp;
+    }
+#pragma unroll
+    for (int r = 1; r <= N; ++r) {
         R tp = (R)0, tq = (R)0;
 #pragma unroll
         for (int k = r; k >= 0; --k) {
@@ -167,14 +184,9 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         Qo[r] = fma(cp[r], hp, tq);
     }
     if (TMAX > 0) {
-        const R scale = (R)SkEps<R>::value * (sk_abs(Po[0]) + sk_abs(Qo[0]));
+        const R scale = (R)SkEps<R>::value * (R)(fabs(Po0) + fabs(Qo0));
         const R ac = sk_abs(c);
-        R ap[N + 1], aq[N + 1];
-#pragma unroll
-        for (int n = 0; n <= N; ++n) {
-            ap[n] = Po[n];
-            aq[n] = Qo[n];
-        }
+        R t0p = (R)0, t0q = (R)0;  // tail contributions to row 0
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
             const int r = N + 1 + t;
@@ -191,21 +203,22 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 hp = fma(P[k], ifact<R>(r + k), hp);
             }
             const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+            t0p = fma(tab.rs[0][t], arp, t0p);
+            t0q = fma(tab.rs[0][t], arq, t0q);
 #pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                ap[n] = fma(tab.rs[n][t], arp, ap[n]);
-                aq[n] = fma(tab.rs[n][t], arq, aq[n]);
+            for (int n = 1; n <= N; ++n) {
+                Po[n] = fma(tab.rs[n][t], arp, Po[n]);
+                Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
             const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
             const bool more = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
             if (!sk_wave_any(more)) break;
         }
-#pragma unroll
-        for (int n = 0; n <= N; ++n) {
-            Po[n] = ap[n];
-            Qo[n] = aq[n];
-        }
+        Po0 += (double)t0p;
+        Qo0 += (double)t0q;
     }
+    Po[0] = (R)Po0;
+    Qo[0] = (R)Qo0;
 }
 
 // ---------------------------------------------------------------------------

@@ -173,16 +173,18 @@ struct SweepArgs {
     int32_t* ce;
     R* qb;
     int32_t* qe;
+    double* ck0;   // FP64 corner coefficients of the checkpoints
+    double* qb0;   // FP64 corner coefficients of the strip-boundary edges
 };
 
 template <typename R>
-__device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, R v, int E) {
+__device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, double v, int E) {
     if (Kexp) {
-        int e = (v == (R)0 || !sk_finite(v)) ? 0 : sk_frexp_exp(v);
-        K[idx] = sk_ldexp(v, -e);
+        int e = (v == 0.0 || !isfinite(v)) ? 0 : sk_frexp_exp(v);
+        K[idx] = (R)ldexp(v, -e);
         Kexp[idx] = E + e;
     } else {
-        K[idx] = sk_ldexp(v, E);
+        K[idx] = (R)ldexp(v, E);
     }
 }
 
@@ -196,12 +198,15 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
         if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
         return;
     }
+    // LDS: FP64 corners, then edge coefficients, then exponent tags
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    R* qlds = reinterpret_cast<R*>(sk_smem);
+    double* qlds0 = reinterpret_cast<double*>(sk_smem);
+    R* qlds = reinterpret_cast<R*>(qlds0 + g.ly);
     int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N + 1));
     const R* cs = a.cskew + pd.c_off;
 
     R P[N + 1], Qs[N + 1];
+    double P0 = 0.0, Qs0 = 0.0;
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
         P[n] = (R)0;
@@ -224,59 +229,75 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             const int tau = t0 + u;
             R Qin[N + 1];
 #pragma unroll
-            for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+            for (int n = 1; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+            double Qin0 = lane_from_prev(Qs0);
             const int i = s * 64 + r;
             live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             if (live) {
-                const R one = sk_ldexp((R)1, -E);
+                const double one = ldexp(1.0, -E);
                 if (j == 0) {
+                    P0 = one;
 #pragma unroll
-                    for (int n = 0; n <= N; ++n) P[n] = n == 0 ? one : (R)0;
+                    for (int n = 1; n <= N; ++n) P[n] = (R)0;
                 }
                 if (r == 0) {
                     if (s == 0) {
+                        Qin0 = one;
 #pragma unroll
-                        for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? one : (R)0;
+                        for (int n = 1; n <= N; ++n) Qin[n] = (R)0;
                     } else {
                         const int sh = qtag[j] - E;
+                        Qin0 = ldexp(qlds0[j], sh);
 #pragma unroll
-                        for (int n = 0; n <= N; ++n) Qin[n] = sk_ldexp(qlds[j * (N + 1) + n], sh);
+                        for (int n = 1; n <= N; ++n) Qin[n] = sk_ldexp(qlds[j * (N + 1) + n], sh);
                     }
                 }
             }
+            P[0] = (R)P0;
+            Qin[0] = (R)Qin0;
             if (CKPT && (tau % S) == 0 && tau < g.nsteps) {
-                R* ck = a.ck + pd.ck_off + (int64_t)(tau / S) * 2 * (N + 1) * 64;
+                const int64_t kk = tau / S;
+                R* ck = a.ck + pd.ck_off + kk * 2 * (N + 1) * 64;
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
                     ck[n * 64 + r] = P[n];
                     ck[(N + 1 + n) * 64 + r] = Qin[n];
                 }
-                if (r == 0) a.ce[pd.ce_off + tau / S] = E;
+                double* ck0 = a.ck0 + pd.ck_off / (N + 1) + kk * 2 * 64;
+                ck0[r] = P0;
+                ck0[64 + r] = Qin0;
+                if (r == 0) a.ce[pd.ce_off + kk] = E;
             }
             R Po[N + 1], Qo[N + 1];
-            sk_cell_fwd<R, N, TMAX>(P, Qin, cb[u], live, a.tab, Po, Qo);
+            double Po0, Qo0;
+            sk_cell_fwd<R, N, TMAX>(P, Qin, P0, Qin0, cb[u], live, a.tab, Po, Qo, Po0, Qo0);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
                 Qs[n] = Qo[n];
             }
+            P0 = Po0;
+            Qs0 = Qo0;
             if (live) {
                 if (r == 63 && s + 1 < g.nstrips) {
+                    qlds0[j] = Qo0;
 #pragma unroll
-                    for (int n = 0; n <= N; ++n) qlds[j * (N + 1) + n] = Qo[n];
+                    for (int n = 1; n <= N; ++n) qlds[j * (N + 1) + n] = Qo[n];
                     qtag[j] = E;
                     if (CKPT) {
                         const int64_t o = (int64_t)(s + 1) * g.ly + j;
 #pragma unroll
                         for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
+                        a.qb0[pd.qe_off + o] = Qo0;
                         a.qe[pd.qe_off + o] = E;
                     }
                 }
                 if (i == g.lx - 1 && j == g.ly - 1) {
-                    R kv = (R)0;
+                    R kr = (R)0;
 #pragma unroll
-                    for (int n = N; n >= 0; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
-                    sk_write_k(a.K, a.Kexp, pd.k_idx, (R)0.5 * kv, E);
+                    for (int n = N; n >= 1; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
+                    const double kv = 0.5 * (Po0 + Qo0 + (double)kr);
+                    sk_write_k(a.K, a.Kexp, pd.k_idx, kv, E);
                 }
             }
             if (L >= 0) {
@@ -290,8 +311,9 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
         // exponent tracking: wave-uniform power-of-two rescale of live state
         R m = (R)0;
         if (live) {
+            m = (R)fmax(fabs(P0), fabs(Qs0));
 #pragma unroll
-            for (int n = 0; n <= N; ++n) {
+            for (int n = 1; n <= N; ++n) {
                 R ap = sk_abs(P[n]), aq = sk_abs(Qs[n]);
                 m = ap > m ? ap : m;
                 m = aq > m ? aq : m;
@@ -304,6 +326,8 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                 P[n] = sk_ldexp(P[n], -sh);
                 Qs[n] = sk_ldexp(Qs[n], -sh);
             }
+            P0 = ldexp(P0, -sh);
+            Qs0 = ldexp(Qs0, -sh);
             E += sh;
         }
 #pragma unroll
@@ -325,6 +349,8 @@ struct AdjArgs {
     const int32_t* ce;
     const R* qb;
     const int32_t* qe;
+    const double* ck0;
+    const double* qb0;
     R* gskew;              // out: skewed dL/dc
 };
 
@@ -361,6 +387,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
         bool lv[S];
         int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
+        const double* ck0 = a.ck0 + pd.ck_off / (N + 1) + (int64_t)kk * 2 * 64;
         const int E = a.ce[pd.ce_off + kk];
         R P[N + 1], Qs[N + 1];
 #pragma unroll
@@ -368,6 +395,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
             P[n] = ck[n * 64 + r];
             Qs[n] = ck[(N + 1 + n) * 64 + r];
         }
+        double P0 = ck0[r], Qs0 = ck0[64 + r];
         int L = tau0 - r, s = 0, j = 0;
         if (L >= 0) {
             s = L / g.Tp;
@@ -378,31 +406,39 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
             const int i = s * 64 + r;
             const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             R Qin[N + 1];
+            double Qin0;
             if (u == 0) {
 #pragma unroll
                 for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
+                Qin0 = Qs0;
             } else {
 #pragma unroll
-                for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                for (int n = 1; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                Qin0 = lane_from_prev(Qs0);
                 if (live) {
-                    const R one = sk_ldexp((R)1, -E);
+                    const double one = ldexp(1.0, -E);
                     if (j == 0) {
+                        P0 = one;
 #pragma unroll
-                        for (int n = 0; n <= N; ++n) P[n] = n == 0 ? one : (R)0;
+                        for (int n = 1; n <= N; ++n) P[n] = (R)0;
                     }
                     if (r == 0) {
                         if (s == 0) {
+                            Qin0 = one;
 #pragma unroll
-                            for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? one : (R)0;
+                            for (int n = 1; n <= N; ++n) Qin[n] = (R)0;
                         } else {
                             const int64_t o = (int64_t)s * g.ly + j;
                             const int sh = a.qe[pd.qe_off + o] - E;
+                            Qin0 = ldexp(a.qb0[pd.qe_off + o], sh);
 #pragma unroll
-                            for (int n = 0; n <= N; ++n)
+                            for (int n = 1; n <= N; ++n)
                                 Qin[n] = sk_ldexp(a.qb[pd.qb_off + o * (N + 1) + n], sh);
                         }
                     }
                 }
+                P[0] = (R)P0;
+                Qin[0] = (R)Qin0;
             }
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
@@ -414,12 +450,15 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
             jst[u] = j;
             if (u < S - 1) {
                 R Po[N + 1], Qo[N + 1];
-                sk_cell_fwd<R, N, TMAX>(P, Qin, cseg[u], live, a.tab, Po, Qo);
+                double Po0, Qo0;
+                sk_cell_fwd<R, N, TMAX>(P, Qin, P0, Qin0, cseg[u], live, a.tab, Po, Qo, Po0, Qo0);
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
                     P[n] = Po[n];
                     Qs[n] = Qo[n];
                 }
+                P0 = Po0;
+                Qs0 = Qo0;
             }
             if (L >= 0) {
                 if (++j == g.Tp) {
@@ -518,9 +557,12 @@ struct ContractArgs {
 };
 
 // One wave per (pair, strip): lane r accumulates dL/d(dx_i) for its row
-// i = 64 s + r in registers; dL/d(dy_j) is accumulated in LDS (lanes touch
-// distinct columns within a step) and written per strip.  The y increments
-// of the current column chunk are staged in LDS next to it.
+// i = 64 s + r in registers.  dL/d(dy_j) for the strip is a sum down the
+// column j, whose cells lanes r = 0..63 visit at consecutive steps; the
+// partial sum therefore travels with the wavefront (lane r-1 -> lane r, one
+// DPP move per step) and the strip's last row writes it out.  The y
+// increments of a column chunk are staged in LDS; rows of dL/dc are
+// prefetched eight steps ahead.
 template <typename R, int DMAX>
 __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const int r = threadIdx.x;
@@ -532,53 +574,79 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     extern __shared__ __align__(16) unsigned char sk_smem[];
     const int64_t d = a.d;
     const int jc = a.jchunk;
-    R* dyl = reinterpret_cast<R*>(sk_smem);  // [jc][d] accumulators
-    R* ycl = dyl + (int64_t)jc * d;            // [jc][d] y increments
+    R* ycl = reinterpret_cast<R*>(sk_smem);  // [jc][DMAX] y increments of the chunk
     const R* X = a.X + pd.x_off * d;
     const R* Y = a.Y + pd.y_off * d;
     const R* gsk = a.gskew + pd.c_off;
     const int i = s * 64 + r;
     const bool rowok = i < g.lx;
-    R xi[DMAX], acc[DMAX];
+    const int last_r = (g.lx - 1 - s * 64) < 63 ? (g.lx - 1 - s * 64) : 63;
+    R xi[DMAX], accx[DMAX];
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
         xi[k] = (R)0;
-        acc[k] = (R)0;
+        accx[k] = (R)0;
         if (k < d && rowok) xi[k] = X[(int64_t)(i + 1) * d + k] - X[(int64_t)i * d + k];
     }
     for (int j0 = 0; j0 < g.ly; j0 += jc) {
         const int j1 = (j0 + jc < g.ly) ? j0 + jc : g.ly;
-        for (int e = r; e < (j1 - j0) * d; e += 64) {
-            dyl[e] = (R)0;
-            const int64_t j = j0 + e / d, k = e % d;
-            ycl[e] = Y[(j + 1) * d + k] - Y[j * d + k];
+        __syncthreads();
+        for (int e = r; e < (j1 - j0) * DMAX; e += 64) {
+            const int jj = e / DMAX, k = e % DMAX;
+            const int64_t j = j0 + jj;
+            ycl[e] = k < d ? Y[(j + 1) * d + k] - Y[j * d + k] : (R)0;
         }
         __syncthreads();
+        R accy[DMAX];
+#pragma unroll
+        for (int k = 0; k < DMAX; ++k) accy[k] = (R)0;
+        const int tbeg = s * g.Tp + j0;
         int tend = s * g.Tp + j1 - 1 + 63;
         if (tend > g.nsteps - 1) tend = g.nsteps - 1;
-        for (int tau = s * g.Tp + j0; tau <= tend; ++tau) {
-            const int j = tau - r - s * g.Tp;
-            const R gv = gsk[(int64_t)tau * 64 + r];
-            if (rowok && j >= j0 && j < j1) {
-                const int jl = (j - j0) * (int)d;
+        R gb[8], gn[8];
 #pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    if (k < d) {
-                        acc[k] = fma(gv, ycl[jl + k], acc[k]);
-                        dyl[jl + k] = fma(gv, xi[k], dyl[jl + k]);
+        for (int u = 0; u < 8; ++u) gb[u] = tbeg + u <= tend ? gsk[(int64_t)(tbeg + u) * 64 + r] : (R)0;
+        for (int t0 = tbeg; t0 <= tend; t0 += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int tau = t0 + 8 + u;
+                gn[u] = tau <= tend ? gsk[(int64_t)tau * 64 + r] : (R)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int tau = t0 + u;
+                const int j = tau - r - s * g.Tp;
+#pragma unroll
+                for (int k = 0; k < DMAX; ++k) accy[k] = lane_from_prev(accy[k]);
+                if (r == 0) {
+#pragma unroll
+                    for (int k = 0; k < DMAX; ++k) accy[k] = (R)0;
+                }
+                const bool ok = rowok && j >= j0 && j < j1 && tau <= tend;
+                if (ok) {
+                    const R gv = gb[u];
+                    const R* yj = ycl + (j - j0) * DMAX;
+#pragma unroll
+                    for (int k = 0; k < DMAX; ++k) {
+                        accx[k] = fma(gv, yj[k], accx[k]);
+                        accy[k] = fma(gv, xi[k], accy[k]);
+                    }
+                    if (r == last_r) {
+                        R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j) * d;
+#pragma unroll
+                        for (int k = 0; k < DMAX; ++k)
+                            if (k < d) dyo[k] = accy[k];
                     }
                 }
             }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gb[u] = gn[u];
         }
-        __syncthreads();
-        R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j0) * d;
-        for (int e = r; e < (j1 - j0) * d; e += 64) dyo[e] = dyl[e];
-        __syncthreads();
     }
     if (rowok) {
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
-            if (k < d) a.dxp[pd.dx_off + (int64_t)i * d + k] = acc[k];
+            if (k < d) a.dxp[pd.dx_off + (int64_t)i * d + k] = accx[k];
     }
 }
 
@@ -796,7 +864,9 @@ __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
                 P[n] = pe[i * (N + 1) + n];
                 Q[n] = qe[j * (N + 1) + n];
             }
-            sk_cell_fwd<R, N, TMAX>(P, Q, c, true, a.tab, Po, Qo);
+            double Po0, Qo0;
+            sk_cell_fwd<R, N, TMAX>(P, Q, (double)P[0], (double)Q[0], c, true, a.tab, Po, Qo, Po0,
+                                    Qo0);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 pe[i * (N + 1) + n] = Po[n];
@@ -805,8 +875,8 @@ __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
             if (i == lx - 1 && j == ly - 1) {
                 R kv = (R)0;
 #pragma unroll
-                for (int n = N; n >= 0; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
-                sk_write_k(a.K, a.Kexp, a.k_idx, (R)0.5 * kv, 0);
+                for (int n = N; n >= 1; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
+                sk_write_k(a.K, a.Kexp, a.k_idx, 0.5 * (Po0 + Qo0 + (double)kv), 0);
             }
         }
         __syncthreads();

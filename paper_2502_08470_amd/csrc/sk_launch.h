@@ -35,7 +35,9 @@ struct SkLaunch {
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
     // LDS bytes needed per workgroup by the sweep / adjoint for a given column count
-    static size_t sweep_lds(int N, int ly) { return (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4; }
+    static size_t sweep_lds(int N, int ly) {
+        return (size_t)ly * 8 + (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4;
+    }
     static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 65) * sizeof(R); }
 };
 

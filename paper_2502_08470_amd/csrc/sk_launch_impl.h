@@ -112,18 +112,18 @@ template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    size_t lds = (size_t)2 * a.jchunk * a.d * sizeof(R);
     dim3 grid(max_strips, (unsigned)npairs);
+    const size_t jc = (size_t)a.jchunk;
     if (a.d <= 4)
-        hipLaunchKernelGGL((k_contract<R, 4>), grid, dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_contract<R, 4>), grid, dim3(64), jc * 4 * sizeof(R), st, a);
     else if (a.d <= 8)
-        hipLaunchKernelGGL((k_contract<R, 8>), grid, dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_contract<R, 8>), grid, dim3(64), jc * 8 * sizeof(R), st, a);
     else if (a.d <= 16)
-        hipLaunchKernelGGL((k_contract<R, 16>), grid, dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_contract<R, 16>), grid, dim3(64), jc * 16 * sizeof(R), st, a);
     else if (a.d <= 32)
-        hipLaunchKernelGGL((k_contract<R, 32>), grid, dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_contract<R, 32>), grid, dim3(64), jc * 32 * sizeof(R), st, a);
     else
-        hipLaunchKernelGGL((k_contract<R, 64>), grid, dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_contract<R, 64>), grid, dim3(64), jc * 64 * sizeof(R), st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }

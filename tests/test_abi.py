@@ -1,0 +1,120 @@
+"""The C-ABI library: exports and host-side argument checking (no GPU).
+
+Every call here fails in host-side validation before any device work, so it
+runs on a machine without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2502_08470_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "sigkernel.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sigkernel_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def P(scheme=1, order=4, dtype=1, algo=0):
+    return ctypes.byref(L.SkParams(scheme, order, dtype, algo))
+
+
+def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
+    vp = ctypes.c_void_p
+    return L.lib().sigkernel_gram(vp(X), nx, lxp, vp(Y), ny, lyp, d, p, vp(K), None, vp(ws), wsb,
+                                  None)
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(p=P(order=1)), L.SK_EINVAL),
+    (dict(p=P(order=9)), L.SK_EUNSUPPORTED),
+    (dict(p=P(scheme=0, order=9)), L.SK_EUNSUPPORTED),
+    (dict(p=P(scheme=0, order=-1)), L.SK_EINVAL),
+    (dict(p=P(scheme=7)), L.SK_EINVAL),
+    (dict(p=P(dtype=3)), L.SK_EINVAL),
+    (dict(p=P(algo=5)), L.SK_EINVAL),
+    (dict(p=P(algo=1, dtype=1)), L.SK_EUNSUPPORTED),
+    (dict(p=P(), d=0), L.SK_EINVAL),
+    (dict(p=P(), lxp=0), L.SK_EINVAL),
+    (dict(p=P(), nx=-1), L.SK_EINVAL),
+    (dict(p=P(), X=0), L.SK_EINVAL),
+    (dict(p=P(), K=0), L.SK_EINVAL),
+    (dict(p=P(), ws=0), L.SK_EINVAL),
+    (dict(p=P(), wsb=16), L.SK_EWORKSPACE),
+    (dict(p=None), L.SK_EINVAL),
+])
+def test_gram_argument_errors(args, code):
+    assert gram(**args) == code
+    assert L.last_error() != ""
+
+
+def test_empty_batch_is_ok_without_device_work():
+    assert gram(P(), nx=0) == L.SK_OK
+
+
+def test_backward_rejections():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    def bwd(p, op=0, d=3):
+        return lib.sigkernel_backward(op, vp(1), None, 2, 10, vp(1), None, 2, 10, d, p, vp(1),
+                                      None, vp(1), vp(1), vp(1), 1 << 30, None)
+    assert bwd(P(scheme=0, order=0)) == L.SK_EUNSUPPORTED
+    assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
+    assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
+    assert bwd(P(), op=4) == L.SK_EINVAL
+
+
+def test_pairs_offset_validation():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    off = lambda v: (ctypes.c_int64 * len(v))(*v)
+    ok = off([0, 5, 9])
+    bad0 = off([1, 5, 9])
+    empty = off([0, 0, 9])
+    def pr(xo, yo):
+        return lib.sigkernel_pairs(vp(1), xo, vp(1), yo, 2, 3, P(), vp(1), None, vp(1), 1 << 30, None)
+    assert pr(bad0, ok) == L.SK_EINVAL
+    assert pr(ok, empty) == L.SK_EINVAL
+    assert lib.sigkernel_pairs_workspace(ok, ok, 2, 3, P(), 0) > 0
+    assert lib.sigkernel_pairs_workspace(ok, bad0, 2, 3, P(), 0) == 0
+
+
+def test_workspace_sizes():
+    lib = L.lib()
+    f = lambda nx, b: lib.sigkernel_gram_workspace(nx, 257, nx, 257, 8, P(order=6), b)
+    assert 0 < f(1, 0) < f(4, 0) < f(16, 0)
+    assert f(16, 1) > f(16, 0)
+    assert lib.sigkernel_gram_workspace(4, 1, 4, 1, 8, P(), 0) >= 256
+    assert lib.sigkernel_gram_workspace(4, 10, 4, 10, 8, P(order=1), 0) == 0
+
+
+def test_error_strings():
+    lib = L.lib()
+    for code in (0, -1, -2, -3, -4):
+        assert lib.sigkernel_error_string(code).decode()
+    assert lib.sigkernel_error_string(17).decode() == "unknown status"
+
+
+def test_product_path_has_no_oracle_dependency():
+    # the package must not import the oracle
+    import paper_2502_08470_amd
+    pkg = os.path.dirname(paper_2502_08470_amd.__file__)
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(root, f)).read()
+                assert "from oracle" not in src and "import oracle" not in src, f
