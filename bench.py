@@ -106,11 +106,15 @@ def main(argv=None) -> int:
                       "gram": 2.0 * DIM, "contract": 4.0 * DIM}
     dom = max((k for k in flops_per_cell if ktimes[k][1] > 0), key=lambda k: ktimes[k][0])
     dom_ms, dom_n = ktimes[dom]
-    achieved = flops_per_cell[dom] * cells * dom_n / (dom_ms * 1e-3)
+    # every step runs each kernel over all cells once (possibly in several
+    # launches of part of the pairs): FLOPs per launch = cells * steps / launches
+    cells_per_launch = cells * args.steps / dom_n
+    achieved = flops_per_cell[dom] * cells_per_launch / (dom_ms / dom_n * 1e-3)
     roofline = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VALU, "traffic": None,
                 "flops_per_cell": flops_per_cell[dom], "launch_ms": dom_ms / dom_n,
+                "launches_per_step": dom_n / args.steps,
                 "kernel_ms_per_step": {k: ktimes[k][0] / args.steps for k in kernels}}
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,

@@ -33,7 +33,7 @@
 // Longest interpolation tail compiled per working precision: FP32 reaches
 // its precision with fewer rows than FP64 at the same |c|.
 template <typename R> struct SkTailMax;
-template <> struct SkTailMax<float> { static constexpr int value = 4; };
+template <> struct SkTailMax<float> { static constexpr int value = 3; };
 template <> struct SkTailMax<double> { static constexpr int value = 6; };
 
 // Kernel-argument tables of the interpolation scheme.
@@ -140,11 +140,17 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // right (Qo).  TMAX = 0: approximation scheme.  TMAX > 0: interpolation
 // scheme with the adaptive tail above; `active` lanes take part in the
 // tail decision (idle lanes may hold stale values).
-template <typename R, int N, int TMAX>
+// WD: also return the c-derivatives of the untruncated rows,
+//   D^P_r = dA^P_r/dc = (Toeplitz row r-1 of P) + r c^{r-1} (Hankel row r of Q),
+// for r = 1..N+T in DP[r-1] (zero beyond the rows kept), and the number of
+// tail rows kept T (wave-uniform).  These are all the adjoint needs from the
+// forward: its transposed map does not depend on the edges.
+template <typename R, int N, int TMAX, bool WD = false>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
                                             double Q0, R c, bool active, const SkTab<R>& tab,
                                             R (&Po)[N + 1], R (&Qo)[N + 1], double& Po0,
-                                            double& Qo0) {
+                                            double& Qo0, R* DP = nullptr, R* DQ = nullptr,
+                                            int* Tkept = nullptr) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
@@ -153,6 +159,14 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
     for (int m = 1; m <= M; ++m) {
         cp[m] = cp[m - 1] * c;
         w[m] = w[m - 1] * (c * (R)(1.0 / m));
+    }
+    if (WD) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            DP[r] = (R)0;
+            DQ[r] = (R)0;
+        }
+        *Tkept = 0;
     }
     // row 0 carries the kernel value at the corner: P'_0 + sum_{k>=1} Q'_k/k!
     // (and symmetrically); the corner coefficient is accumulated in FP64
@@ -166,6 +180,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         Po0 = P0 + (double)hq;
         Qo0 = Q0 + (double)hp;
     }
+    R tpp = P[0], tqp = Q[0];  // Toeplitz row r-1
 #pragma unroll
     for (int r = 1; r <= N; ++r) {
         R tp = (R)0, tq = (R)0;
@@ -182,6 +197,13 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         }
         Po[r] = fma(cp[r], hq, tp);
         Qo[r] = fma(cp[r], hp, tq);
+        if (WD) {
+            const R rc = (R)r * cp[r - 1];
+            DP[r - 1] = fma(rc, hq, tpp);
+            DQ[r - 1] = fma(rc, hp, tqp);
+            tpp = tp;
+            tqp = tq;
+        }
     }
     if (TMAX > 0) {
         const R scale = (R)SkEps<R>::value * (R)(fabs(Po0) + fabs(Qo0));
@@ -203,6 +225,14 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 hp = fma(P[k], ifact<R>(r + k), hp);
             }
             const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+            if (WD) {
+                const R rc = (R)r * cp[r - 1];
+                DP[r - 1] = fma(rc, hq, tpp);
+                DQ[r - 1] = fma(rc, hp, tqp);
+                tpp = tp;
+                tqp = tq;
+                *Tkept = t + 1;
+            }
             t0p = fma(tab.rs[0][t], arp, t0p);
             t0q = fma(tab.rs[0][t], arq, t0q);
 #pragma unroll
@@ -224,16 +254,18 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
 // ---------------------------------------------------------------------------
 // adjoint cell map
 // ---------------------------------------------------------------------------
-// Given the cell's inputs (P, Q), constant c and the adjoints a = dL/dPo,
-// b = dL/dQo, returns the adjoints of the inputs (aP = dL/dP, aQ = dL/dQ) and
-// g = dL/dc.  The forward map is linear in (P, Q), so its transpose does not
-// need the inputs; g does: dA^P_r/dc = sum_{k<=min(r-1,N)} w_{r-1-k} P'_k
-// + r c^{r-1} sum_k Q'_k/(r+k)!.
+// Given the adjoints a = dL/dPo, b = dL/dQo of a cell's outputs, returns the
+// adjoints of its inputs (aP = dL/dP, aQ = dL/dQ) and g = dL/dc.  The map is
+// linear in (P, Q), so its transpose needs only c and the number of tail rows
+// T the forward kept; g needs the row derivatives D^P, D^Q recorded by the
+// forward (sk_cell_fwd with WD).  Rows are visited once, in outer-product
+// order, so no per-row arrays stay live:
+//   aP_k += w_{r-k} ea_r (k <= min(r, N)),  aP_k += c^r eb_r / (r+k)! (k >= 1),
+// with ea_r = a_r for r <= N and ea_r = sum_n Rs[n][r] a_n for tail rows.
 template <typename R, int N, int TMAX>
-__device__ __forceinline__ void sk_cell_adj(const R (&P)[N + 1], const R (&Q)[N + 1], R c,
-                                            bool active, const SkTab<R>& tab, const R (&a)[N + 1],
-                                            const R (&b)[N + 1], R (&aP)[N + 1],
-                                            R (&aQ)[N + 1], R& g) {
+__device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, const R (&a)[N + 1],
+                                            const R (&b)[N + 1], const R* DP, const R* DQ,
+                                            R (&aP)[N + 1], R (&aQ)[N + 1], R& g) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
@@ -243,91 +275,43 @@ __device__ __forceinline__ void sk_cell_adj(const R (&P)[N + 1], const R (&Q)[N 
         cp[m] = cp[m - 1] * c;
         w[m] = w[m - 1] * (c * (R)(1.0 / m));
     }
-    // adjoints of the untruncated rows: rows <= N directly, tail rows through
-    // the transposed projection
-    R ea[M + 1], eb[M + 1];
 #pragma unroll
-    for (int n = 0; n <= N; ++n) {
-        ea[n] = a[n];
-        eb[n] = b[n];
+    for (int k = 0; k <= N; ++k) {
+        aP[k] = (R)0;
+        aQ[k] = (R)0;
     }
-#pragma unroll
-    for (int t = 0; t < TMAX; ++t) {
-        R sa = (R)0, sb = (R)0;
-#pragma unroll
-        for (int n = 0; n <= N; ++n) {
-            sa = fma(tab.rs[n][t], a[n], sa);
-            sb = fma(tab.rs[n][t], b[n], sb);
-        }
-        ea[N + 1 + t] = sa;
-        eb[N + 1 + t] = sb;
-    }
-    // forward rows (recomputed) give dL/dc and, for the interpolation
-    // scheme, the same tail length as the forward map
     R gacc = (R)0;
-    R tp_prev = (R)0, tq_prev = (R)0;
-    R scale = (R)0;
-    const R ac = sk_abs(c);
-    int T = 0;
 #pragma unroll
     for (int r = 0; r <= M; ++r) {
-        R tp = (R)0, tq = (R)0;
+        if (r > N && r - N > T) break;  // wave-uniform
+        R ea, eb;
+        if (r <= N) {
+            ea = a[r];
+            eb = b[r];
+        } else {
+            ea = (R)0;
+            eb = (R)0;
 #pragma unroll
-        for (int k = (r < N ? r : N); k >= 0; --k) {
-            tp = fma(w[r - k], P[k], tp);
-            tq = fma(w[r - k], Q[k], tq);
-        }
-        R hq = (R)0, hp = (R)0;
-#pragma unroll
-        for (int k = N; k >= 1; --k) {
-            hq = fma(Q[k], ifact<R>(r + k), hq);
-            hp = fma(P[k], ifact<R>(r + k), hp);
+            for (int n = 0; n <= N; ++n) {
+                ea = fma(tab.rs[n][r - N - 1], a[n], ea);
+                eb = fma(tab.rs[n][r - N - 1], b[n], eb);
+            }
         }
         if (r >= 1) {
-            // dA^P_r/dc = (Toeplitz row r-1) + r c^{r-1} H_r(Q)
-            const R rc = (R)r * cp[r - 1];
-            gacc = fma(ea[r], fma(rc, hq, tp_prev), gacc);
-            gacc = fma(eb[r], fma(rc, hp, tq_prev), gacc);
+            gacc = fma(ea, DP[r - 1], gacc);
+            gacc = fma(eb, DQ[r - 1], gacc);
         }
-        tp_prev = tp;
-        tq_prev = tq;
-        if (r == 0) scale = (R)SkEps<R>::value * (sk_abs(fma(cp[0], hq, tp)) + sk_abs(fma(cp[0], hp, tq)));
-        if (r > N) {
-            T = r - N;
-            const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
-            const R tail = (R)2 * tab.rmax[r - N - 1] * (sk_abs(arp) + sk_abs(arq));
-            const bool more = active && (!(tail <= scale) || ac > (R)(0.5 * (r - N + 1)));
-            if (!sk_wave_any(more)) break;
+#pragma unroll
+        for (int k = (r < N ? r : N); k >= 0; --k) {
+            aP[k] = fma(w[r - k], ea, aP[k]);
+            aQ[k] = fma(w[r - k], eb, aQ[k]);
+        }
+        const R cb = cp[r] * eb, ca = cp[r] * ea;
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            aP[k] = fma(cb, ifact<R>(r + k), aP[k]);
+            aQ[k] = fma(ca, ifact<R>(r + k), aQ[k]);
         }
     }
     g = gacc;
-    // transposed map over rows 0..N+T
-    R cb[M + 1], ca[M + 1];
-#pragma unroll
-    for (int r = 0; r <= M; ++r) {
-        ca[r] = cp[r] * ea[r];
-        cb[r] = cp[r] * eb[r];
-    }
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-        R sp = (R)0, sq = (R)0;
-#pragma unroll
-        for (int r = M; r >= k; --r) {
-            if (r <= N + T) {
-                sp = fma(w[r - k], ea[r], sp);
-                sq = fma(w[r - k], eb[r], sq);
-            }
-        }
-        if (k >= 1) {
-#pragma unroll
-            for (int r = M; r >= 0; --r) {
-                if (r <= N + T) {
-                    sp = fma(cb[r], ifact<R>(r + k), sp);
-                    sq = fma(ca[r], ifact<R>(r + k), sq);
-                }
-            }
-        }
-        aP[k] = sp;
-        aQ[k] = sq;
-    }
 }

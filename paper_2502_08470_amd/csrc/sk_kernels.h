@@ -355,7 +355,7 @@ struct AdjArgs {
 };
 
 template <typename R, int N, int TMAX, int S>
-__global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
+__device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const int r = threadIdx.x;
     const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
@@ -382,8 +382,11 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
         R cseg[S];
 #pragma unroll
         for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
-        // ---- recompute the segment's cell inputs from the checkpoint
-        R Pst[S][N + 1], Qst[S][N + 1];
+        // ---- replay the segment's forward from the checkpoint, recording
+        // each cell's row derivatives and kept tail length
+        constexpr int M = N + TMAX;
+        R Dp[S][M], Dq[S][M];
+        int Tst[S];
         bool lv[S];
         int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
@@ -440,26 +443,20 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
                 P[0] = (R)P0;
                 Qin[0] = (R)Qin0;
             }
-#pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                Pst[u][n] = P[n];
-                Qst[u][n] = Qin[n];
-            }
             lv[u] = live;
             sst[u] = s;
             jst[u] = j;
-            if (u < S - 1) {
-                R Po[N + 1], Qo[N + 1];
-                double Po0, Qo0;
-                sk_cell_fwd<R, N, TMAX>(P, Qin, P0, Qin0, cseg[u], live, a.tab, Po, Qo, Po0, Qo0);
+            R Po[N + 1], Qo[N + 1];
+            double Po0, Qo0;
+            sk_cell_fwd<R, N, TMAX, true>(P, Qin, P0, Qin0, cseg[u], live, a.tab, Po, Qo, Po0, Qo0,
+                                          Dp[u], Dq[u], &Tst[u]);
 #pragma unroll
-                for (int n = 0; n <= N; ++n) {
-                    P[n] = Po[n];
-                    Qs[n] = Qo[n];
-                }
-                P0 = Po0;
-                Qs0 = Qo0;
+            for (int n = 0; n <= N; ++n) {
+                P[n] = Po[n];
+                Qs[n] = Qo[n];
             }
+            P0 = Po0;
+            Qs0 = Qo0;
             if (L >= 0) {
                 if (++j == g.Tp) {
                     j = 0;
@@ -510,7 +507,7 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
                 }
             }
             R gv;
-            sk_cell_adj<R, N, TMAX>(Pst[u], Qst[u], cseg[u], live, a.tab, ap, aq, lp, lqs, gv);
+            sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
             if (live && r == 0 && ss > 0) {
 #pragma unroll
                 for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
@@ -539,6 +536,25 @@ __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
             }
         }
     }
+}
+
+// Two entry points of the same body: where the register footprint allows it,
+// the compiler is asked to fit two waves per SIMD (the adjoint is latency
+// bound at one); elsewhere forcing it would spill to scratch.
+template <typename R, int N, int TMAX>
+constexpr bool sk_adj_two_waves() {
+    return sizeof(R) == 4 ? (TMAX == 0 || N <= 6) : (TMAX == 0 && N <= 6);
+}
+
+template <typename R, int N, int TMAX, int S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_adjoint_w2(const AdjArgs<R> a) {
+    sk_adjoint_body<R, N, TMAX, S>(a);
+}
+
+template <typename R, int N, int TMAX, int S>
+__global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
+    sk_adjoint_body<R, N, TMAX, S>(a);
 }
 
 // ---------------------------------------------------------------------------

@@ -80,7 +80,10 @@ template <typename R, int N, int TMAX>
 static hipError_t sk_adj_n(const AdjArgs<R>& a, int64_t npairs, int max_ly, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
     size_t lds = SkLaunch<R>::sweep_lds(N, max_ly);
-    hipLaunchKernelGGL((k_adjoint<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
+    if constexpr (sk_adj_two_waves<R, N, TMAX>())
+        hipLaunchKernelGGL((k_adjoint_w2<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
