@@ -3,8 +3,9 @@
 One step = forward Gram + backward (adjoint) of a 128 x 128 Gram matrix of
 paths in R^8 with 256 Brownian steps (std 0.5/sqrt(256) per coordinate),
 polynomial interpolation scheme of order 6, FP32 cell sweep and FP32 MFMA
-increment Gram; loss L = sum(K) (gK = 1).  Inputs are resident on the GPU
-before timing.  Reported:
+increment Gram; loss L = sum(K), differentiated with torch.autograd through
+the library's SigKernelGram (gradients with respect to both path sets).
+Inputs are resident on the GPU before timing.  Reported:
 
 * value: PDE cell updates per second of the whole fwd+bwd step (cells
   counted once per step: 128 * 128 * 256 * 256).
@@ -69,14 +70,15 @@ def main(argv=None) -> int:
     _lib.lib()
     dev = torch.device("cuda:0")
     X, Y = W.batched_interp_gram(0, n=N_PATHS, steps=STEPS, d=DIM)
-    Xt = torch.tensor(X, device=dev)
-    Yt = torch.tensor(Y, device=dev)
-    gK = torch.ones((N_PATHS, N_PATHS), dtype=torch.float32, device=dev)
+    Xt = torch.tensor(X, device=dev).requires_grad_(True)
+    Yt = torch.tensor(Y, device=dev).requires_grad_(True)
 
     def step():
-        K = sk.gram(Xt, Yt, SCHEME, ORDER)
-        gX, gY = sk.gram_backward(Xt, Yt, gK, SCHEME, ORDER)
-        return K, gX, gY
+        Xt.grad = None
+        Yt.grad = None
+        K = sk.sig_gram(Xt, Yt, SCHEME, ORDER)
+        K.sum().backward()
+        return K.detach(), Xt.grad, Yt.grad
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -151,8 +153,8 @@ def main(argv=None) -> int:
                                "seconds": c1 - c0}
     if not args.no_plain:
         npl = 16
-        Xd = Xt[:1].double()
-        Yd = Yt[:npl].double()
+        Xd = Xt.detach()[:1].double()
+        Yd = Yt.detach()[:npl].double()
         sk.gram(Xd, Yd, SCHEME, ORDER, algo="plain")
         torch.cuda.synchronize()
         p0 = time.perf_counter()

@@ -157,6 +157,31 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
                        void* gY, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Forward and backward of a Gram call with the backward's state kept in
+ * between (trading memory for the recomputation sigkernel_backward does).
+ * sigkernel_gram_save computes K (and K_exp) like sigkernel_gram with the
+ * polynomial scheme `p` and additionally leaves in `state` the skewed cell
+ * constants, the wavefront checkpoints and the strip-boundary edges of every
+ * pair; `state` must hold sigkernel_gram_state_size bytes (one region for
+ * all pairs, no chunking; the caller owns it).
+ * sigkernel_gram_backward_saved then computes gX, gY exactly as
+ * sigkernel_backward(SK_OP_GRAM, ...) would, for the same X, Y and params,
+ * from that state (which it also uses as scratch).  Calling it with a state
+ * not produced by sigkernel_gram_save for the same arguments gives undefined
+ * results.  Errors as for sigkernel_backward; SK_EWORKSPACE when the state
+ * is too small.
+ */
+size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                                 const sk_params* p);
+int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                        int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                        void* state, size_t state_bytes, hipStream_t stream);
+int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, const void* Y,
+                                  int64_t ny, int64_t ly_pts, int64_t d, const sk_params* p,
+                                  const void* gK, const int32_t* gK_exp, void* gX, void* gY,
+                                  void* state, size_t state_bytes, hipStream_t stream);
+
+/*
  * The increment Gram matrices of a Gram call: C[((a * ny + b) * lx + i) * ly + j]
  * = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> with lx = lx_pts - 1,
  * ly = ly_pts - 1 (the constants C_ij of the schemes with unit time steps),

@@ -24,6 +24,9 @@ EXPORTS = (
     "sigkernel_pairs",
     "sigkernel_backward",
     "sigkernel_cell_constants",
+    "sigkernel_gram_state_size",
+    "sigkernel_gram_save",
+    "sigkernel_gram_backward_saved",
     "sigkernel_error_string",
     "sigkernel_last_error",
     "sigkernel_profile_enable",
@@ -69,6 +72,13 @@ def lib():
     L.sigkernel_backward.restype = ctypes.c_int
     L.sigkernel_cell_constants.argtypes = [vp, i64, i64, vp, i64, i64, i64, i32, vp, vp, sz, vp]
     L.sigkernel_cell_constants.restype = ctypes.c_int
+    L.sigkernel_gram_state_size.argtypes = [i64, i64, i64, i64, i64, pp]
+    L.sigkernel_gram_state_size.restype = sz
+    L.sigkernel_gram_save.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp, sz, vp]
+    L.sigkernel_gram_save.restype = ctypes.c_int
+    L.sigkernel_gram_backward_saved.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp,
+                                                vp, vp, sz, vp]
+    L.sigkernel_gram_backward_saved.restype = ctypes.c_int
     L.sigkernel_error_string.argtypes = [ctypes.c_int]
     L.sigkernel_error_string.restype = ctypes.c_char_p
     L.sigkernel_last_error.argtypes = []

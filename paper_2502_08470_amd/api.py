@@ -185,23 +185,91 @@ def cell_constants(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
     return C
 
 
+def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
+                    order: int = 4) -> int:
+    """Bytes of the backward state kept by gram_save for these shapes."""
+    p = _params(X.dtype, scheme, order, "batched")
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    nb = L.lib().sigkernel_gram_state_size(nx, lxp, ny, lyp, d, ctypes.byref(p))
+    if nb == 0:
+        raise L.SigKernelError(L.SK_EINVAL, L.last_error())
+    return int(nb)
+
+
+def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
+              return_exp: bool = False):
+    """Gram matrix plus the state its backward needs: returns (K, state) or
+    (K, K_exp, state).  Pass the state to gram_backward_saved."""
+    X, Y = _dev(X), _dev(Y)
+    p = _params(X.dtype, scheme, order, "batched")
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
+    Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
+    state = _workspace(gram_state_size(X, Y, scheme, order), X.device)
+    L.check(L.lib().sigkernel_gram_save(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
+                                        _ptr(K), _ptr(Ke), _ptr(state), state.numel(),
+                                        _stream(X)))
+    return (K, Ke, state) if return_exp else (K, state)
+
+
+def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
+                        state: torch.Tensor, scheme: str = "approx", order: int = 4,
+                        gK_exp: Optional[torch.Tensor] = None):
+    """Same result as gram_backward, from the state left by gram_save(X, Y)."""
+    X, Y = _dev(X), _dev(Y)
+    gK = _dev(gK.to(X.dtype))
+    p = _params(X.dtype, scheme, order, "batched")
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    gX = torch.empty_like(X)
+    gY = torch.empty_like(Y)
+    ge = _dev(gK_exp.to(torch.int32)) if gK_exp is not None else None
+    L.check(L.lib().sigkernel_gram_backward_saved(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d,
+                                                  ctypes.byref(p), _ptr(gK), _ptr(ge), _ptr(gX),
+                                                  _ptr(gY), _ptr(state), state.numel(),
+                                                  _stream(X)))
+    return gX, gY
+
+
 # ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
+def _state_budget(device) -> int:
+    """Largest backward state kept between forward and backward: half the
+    free device memory, capped by SK_STATE_BUDGET_GB (default 96)."""
+    import os
+    free, _ = torch.cuda.mem_get_info(device)
+    cap = float(os.environ.get("SK_STATE_BUDGET_GB", "96")) * (1 << 30)
+    return int(min(0.5 * free, cap))
+
+
 class SigKernelGram(torch.autograd.Function):
     """Differentiable Gram matrix; the backward runs the library's adjoint
-    sweep (exact gradient of the computed scheme)."""
+    sweep (exact gradient of the computed scheme).  When the backward state
+    fits the memory budget the forward keeps it (gram_save) and the backward
+    starts from it; otherwise the backward recomputes it in chunks."""
 
     @staticmethod
     def forward(ctx, X, Y, scheme="approx", order=4):
         ctx.save_for_backward(X, Y)
         ctx.scheme, ctx.order = scheme, order
+        ctx.state = None
+        if scheme != "fd" and (X.requires_grad or Y.requires_grad):
+            if gram_state_size(X, Y, scheme, order) <= _state_budget(X.device):
+                K, ctx.state = gram_save(X, Y, scheme, order)
+                return K
         return gram(X, Y, scheme, order)
 
     @staticmethod
     def backward(ctx, gK):
         X, Y = ctx.saved_tensors
-        gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order)
+        if ctx.state is not None:
+            gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order)
+            ctx.state = None
+        else:
+            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order)
         return gX, gY, None, None
 
 

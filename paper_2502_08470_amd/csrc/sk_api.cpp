@@ -508,27 +508,24 @@ int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
+// Backward, first half: increment Gram and the forward sweep that stores
+// lane checkpoints and strip-boundary edges.  Kernel values go to K (indexed
+// by k_idx - kbase).
 template <typename R>
-int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
-                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly,
-                       int max_strips, char* ws, const Layout& L, const R* gK,
-                       const int32_t* gKexp, hipStream_t st) {
+int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
+                      const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly, char* ws,
+                      const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = 0;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
     SK_LAUNCH("gram", st, SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st), "increment Gram");
-    // forward with checkpoints; its kernel values go to the chunk's scratch
-    // slots (Gram mode: k_idx - first; list mode: descriptors carry local k_idx)
     SweepArgs<R> sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
-    R* kbuf = reinterpret_cast<R*>(ws + L.kbuf);
-    int32_t* kexp = reinterpret_cast<int32_t*>(ws + L.kexp);
-    const int64_t kbase = src.desc ? 0 : src.first;
-    sa.K = kbuf - kbase;
-    sa.Kexp = kexp - kbase;
+    sa.K = K;
+    sa.Kexp = Kexp;
     sa.ck = reinterpret_cast<R*>(ws + L.ck);
     sa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     sa.qb = reinterpret_cast<R*>(ws + L.qb);
@@ -536,10 +533,26 @@ int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.ck0 = reinterpret_cast<double*>(ws + L.ck0);
     sa.qb0 = reinterpret_cast<double*>(ws + L.qb0);
     SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, max_ly, st), "checkpoint sweep");
+    return SK_OK;
+}
+
+// Backward, second half: adjoint sweep and gradient contraction from the
+// state left by run_chunk_prepare.
+template <typename R>
+int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
+                      const SkPairSrc& src, int64_t P, int max_ly, int max_strips, char* ws,
+                      const Layout& L, const R* gK, const int32_t* gKexp, hipStream_t st) {
+    const bool interp = p.scheme == SK_POLY_INTERP;
     AdjArgs<R> aa;
     std::memset(&aa, 0, sizeof(aa));
-    aa.src = src; aa.cskew = cskew; aa.tab = sa.tab; aa.gK = gK; aa.gKexp = gKexp;
-    aa.ck = sa.ck; aa.ce = sa.ce; aa.qb = sa.qb; aa.qe = sa.qe; aa.ck0 = sa.ck0; aa.qb0 = sa.qb0;
+    aa.src = src; aa.cskew = reinterpret_cast<const R*>(ws + L.cskew); aa.tab = table_for<R>(p);
+    aa.gK = gK; aa.gKexp = gKexp;
+    aa.ck = reinterpret_cast<const R*>(ws + L.ck);
+    aa.ce = reinterpret_cast<const int32_t*>(ws + L.ce);
+    aa.qb = reinterpret_cast<const R*>(ws + L.qb);
+    aa.qe = reinterpret_cast<const int32_t*>(ws + L.qe);
+    aa.ck0 = reinterpret_cast<const double*>(ws + L.ck0);
+    aa.qb0 = reinterpret_cast<const double*>(ws + L.qb0);
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, max_ly, st), "adjoint sweep");
     ContractArgs<R> ca;
@@ -549,6 +562,90 @@ int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
     const int64_t dmax = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64;
     ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (dmax * (int64_t)sizeof(R))));
     SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
+    return SK_OK;
+}
+
+template <typename R>
+int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
+                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly,
+                       int max_strips, char* ws, const Layout& L, const R* gK,
+                       const int32_t* gKexp, hipStream_t st) {
+    // the checkpoint pass's kernel values go to the chunk's scratch slots
+    // (Gram mode: k_idx - first; list mode: descriptors carry local k_idx)
+    const int64_t kbase = src.desc ? 0 : src.first;
+    R* kbuf = reinterpret_cast<R*>(ws + L.kbuf) - kbase;
+    int32_t* kexp = reinterpret_cast<int32_t*>(ws + L.kexp) - kbase;
+    int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_ly, ws, L, kbuf, kexp, st);
+    if (rc) return rc;
+    return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, max_strips, ws, L, gK, gKexp, st);
+}
+
+// Forward that keeps the whole backward state of a Gram call in `state`
+// (one chunk holding every pair), and the backward that starts from it.
+template <typename R>
+int gram_state_layout(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
+                      const sk_params& p, SkPairSizes* per, Layout* L) {
+    const int64_t npairs = nx * ny;
+    *per = sk_pair_sizes((int)(lxp - 1), (int)(lyp - 1), 0, p.order, ckpt_stride(p), d, true);
+    *L = layout_for(scale(*per, npairs), npairs, sizeof(R), true, false, p.order);
+    return SK_OK;
+}
+
+template <typename R>
+int gram_save(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp, int64_t d,
+              const sk_params& p, R* K, int32_t* Kexp, void* state, size_t bytes, hipStream_t st) {
+    const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
+    if (npairs == 0) return SK_OK;
+    SkPairSizes per;
+    Layout L;
+    gram_state_layout<R>(nx, lxp, ny, lyp, d, p, &per, &L);
+    if ((size_t)L.total > bytes)
+        return fail(SK_EWORKSPACE, "state needs %lld bytes, got %zu", (long long)L.total, bytes);
+    if (lx == 0 || ly == 0) {
+        SK_TRY_HIP(SkLaunch<R>::fill(K, npairs, (R)1, st), "fill");
+        if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp), npairs, st), "fill");
+        return SK_OK;
+    }
+    int rc = check_lds<R>(p, ly, d);
+    if (rc) return rc;
+    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
+    return run_chunk_prepare<R>(p, X, Y, d, src, npairs, g.nsteps_pad, (int)ly, (char*)state, L,
+                                K, Kexp, st);
+}
+
+template <typename R>
+int gram_backward_saved(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                        int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX,
+                        R* gY, void* state, size_t bytes, hipStream_t st) {
+    const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
+    SkPairSizes per;
+    Layout L;
+    gram_state_layout<R>(nx, lxp, ny, lyp, d, p, &per, &L);
+    if ((size_t)L.total > bytes)
+        return fail(SK_EWORKSPACE, "state needs %lld bytes, got %zu", (long long)L.total, bytes);
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+    if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
+    int rc = check_lds<R>(p, ly, d);
+    if (rc) return rc;
+    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
+    rc = run_chunk_adjoint<R>(p, X, Y, d, src, npairs, (int)ly, g.nstrips, (char*)state, L, gK,
+                              gKexp, st);
+    if (rc) return rc;
+    ReduceGramArgs<R> ra;
+    ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
+    ra.first = 0; ra.count = npairs; ra.dx_stride = per.dx; ra.dy_stride = per.dy;
+    ra.nstrips = g.nstrips;
+    ra.dxp = reinterpret_cast<const R*>((char*)state + L.dxp);
+    ra.dyp = reinterpret_cast<const R*>((char*)state + L.dyp);
+    ra.gX = gX; ra.gY = gY;
+    SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
     return SK_OK;
 }
 
@@ -816,6 +913,66 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
         return pairs_backward<double>((const double*)X, x_off, (const double*)Y, y_off, nx, d, *p,
                                       (const double*)gK, gK_exp, (double*)gX, (double*)gY, ws,
                                       ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                                 const sk_params* p) {
+    g_last_error.clear();
+    if (check_params(p, true) || check_dims(d, true) || check_len(lx_pts, 0, "x") ||
+        check_len(ly_pts, 0, "y"))
+        return 0;
+    if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
+    SkPairSizes per;
+    Layout L;
+    if (p->dtype == SK_F32) gram_state_layout<float>(nx, lx_pts, ny, ly_pts, d, *p, &per, &L);
+    else gram_state_layout<double>(nx, lx_pts, ny, ly_pts, d, *p, &per, &L);
+    return std::max<size_t>(256, (size_t)L.total);
+}
+
+int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                        int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                        void* state, size_t state_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, true);
+    if (!rc) rc = check_dims(d, true);
+    if (rc) return rc;
+    if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
+    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if (nx * ny == 0) return SK_OK;
+    if (!X || !Y || !K || !state) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (p->dtype == SK_F32)
+            return gram_save<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts, d, *p,
+                                    (float*)K, K_exp, state, state_bytes, stream);
+        return gram_save<double>((const double*)X, nx, lx_pts, (const double*)Y, ny, ly_pts, d, *p,
+                                 (double*)K, K_exp, state, state_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, const void* Y,
+                                  int64_t ny, int64_t ly_pts, int64_t d, const sk_params* p,
+                                  const void* gK, const int32_t* gK_exp, void* gX, void* gY,
+                                  void* state, size_t state_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, true);
+    if (!rc) rc = check_dims(d, true);
+    if (rc) return rc;
+    if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
+    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if (!X || !Y || !gK || !gX || !gY || !state) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (p->dtype == SK_F32)
+            return gram_backward_saved<float>((const float*)X, nx, lx_pts, (const float*)Y, ny,
+                                              ly_pts, d, *p, (const float*)gK, gK_exp, (float*)gX,
+                                              (float*)gY, state, state_bytes, stream);
+        return gram_backward_saved<double>((const double*)X, nx, lx_pts, (const double*)Y, ny,
+                                           ly_pts, d, *p, (const double*)gK, gK_exp, (double*)gX,
+                                           (double*)gY, state, state_bytes, stream);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
     }

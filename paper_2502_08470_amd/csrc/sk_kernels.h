@@ -64,10 +64,10 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int64_t local = blockIdx.y;
+    const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
-    const int b = blockIdx.x;
+    const int b = blockIdx.y;
     if (64 * b >= g.nsteps_pad) return;
     const int dp = a.dpad;
     extern __shared__ __align__(16) unsigned char sk_smem[];
@@ -582,8 +582,8 @@ struct ContractArgs {
 template <typename R, int DMAX>
 __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const int r = threadIdx.x;
-    const int s = blockIdx.x;
-    const int64_t local = blockIdx.y;
+    const int s = blockIdx.y;
+    const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
     if (g.nsteps == 0 || s >= g.nstrips) return;
@@ -738,12 +738,12 @@ struct ReducePairsArgs {
 
 template <typename R>
 __global__ void k_reduce_pairs(const ReducePairsArgs<R> a) {
-    const int64_t local = blockIdx.y;
+    const int64_t local = blockIdx.x;
     const SkPairDesc pd = a.desc[local];
     const int64_t d = a.d;
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-         e < a.max_pts * d; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+         e < a.max_pts * d; e += (int64_t)gridDim.y * blockDim.x) {
         const int64_t t = e / d, k = e % d;
         if (t <= pd.lx) {
             R v = (R)0;
@@ -934,12 +934,12 @@ __global__ __launch_bounds__(256) void k_plain_fd(const PlainArgs<R> a) {
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void k_unskew(SkPairSrc src, const R* cskew, R* C, int64_t first) {
-    const int64_t local = blockIdx.y;
+    const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(src, local);
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
     const int64_t n = (int64_t)pd.lx * pd.ly;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.y * blockDim.x) {
         const int i = (int)(e / pd.ly), j = (int)(e % pd.ly);
         const int s = i / 64, r = i % 64;
         const int64_t tau = (int64_t)s * g.Tp + j + r;

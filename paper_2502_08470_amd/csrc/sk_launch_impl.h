@@ -32,7 +32,7 @@ template <typename R>
 hipError_t SkLaunch<R>::gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs,
                              hipStream_t st) {
     if (npairs <= 0 || ntau_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram_skew<R>, dim3(ntau_blocks, (unsigned)npairs), dim3(256),
+    hipLaunchKernelGGL(k_gram_skew<R>, dim3((unsigned)npairs, ntau_blocks), dim3(256),
                        gram_lds(a.dpad), st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
@@ -115,7 +115,7 @@ template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    dim3 grid(max_strips, (unsigned)npairs);
+    dim3 grid((unsigned)npairs, max_strips);
     const size_t jc = (size_t)a.jchunk;
     if (a.d <= 4)
         hipLaunchKernelGGL((k_contract<R, 4>), grid, dim3(64), jc * 4 * sizeof(R), st, a);
@@ -150,7 +150,7 @@ hipError_t SkLaunch<R>::reduce_pairs(const ReducePairsArgs<R>& a, hipStream_t st
     int64_t e = a.max_pts * a.d;
     int64_t bx = (e + 255) / 256;
     if (bx > 64) bx = 64;
-    hipLaunchKernelGGL(k_reduce_pairs<R>, dim3((unsigned)bx, (unsigned)a.count), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_pairs<R>, dim3((unsigned)a.count, (unsigned)bx), dim3(256), 0, st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -202,7 +202,7 @@ hipError_t SkLaunch<R>::unskew(const SkPairSrc& src, const R* cskew, R* C, int64
     if (npairs <= 0 || cells <= 0) return hipSuccess;
     int64_t bx = (cells + 255) / 256;
     if (bx > 1024) bx = 1024;
-    hipLaunchKernelGGL(k_unskew<R>, dim3((unsigned)bx, (unsigned)npairs), dim3(256), 0, st, src,
+    hipLaunchKernelGGL(k_unskew<R>, dim3((unsigned)npairs, (unsigned)bx), dim3(256), 0, st, src,
                        cskew, C, first);
     SK_CHECK_LAUNCH();
     return hipSuccess;

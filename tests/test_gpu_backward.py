@@ -155,3 +155,29 @@ def test_autograd_and_mmd_fp32(sk):
         lm = mmd(P, Yd)
         fd = (lp - lm) / (2 * h)
         assert abs(gX[idx] - fd) <= 1e-5 * scale, (idx, gX[idx], fd)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_saved_state_backward_matches_recompute(sk, dtype):
+    log_banner(f"saved-state backward {dtype}")
+    rng = np.random.default_rng(31)
+    X = dev(bm_paths(rng, 3, 130, 4, 0.05), dtype)
+    Y = dev(bm_paths(rng, 2, 70, 4, 0.05), dtype)
+    gK = dev(rng.normal(size=(3, 2)), dtype)
+    for scheme in ("approx", "interp"):
+        K1, state = sk.gram_save(X, Y, scheme, 5)
+        K0 = sk.gram(X, Y, scheme, 5)
+        torch.testing.assert_close(K1, K0, rtol=1e-14 if dtype == torch.float64 else 1e-6, atol=0)
+        gX1, gY1 = sk.gram_backward_saved(X, Y, gK, state, scheme, 5)
+        gX0, gY0 = sk.gram_backward(X, Y, gK, scheme, 5)
+        tol = 1e-12 if dtype == torch.float64 else 1e-6
+        torch.testing.assert_close(gX1, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
+        torch.testing.assert_close(gY1, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
+    # autograd uses the saved path when the state fits
+    Xg = X.clone().requires_grad_(True)
+    Yg = Y.clone().requires_grad_(True)
+    (sk.sig_gram(Xg, Yg, "approx", 5) * gK).sum().backward()
+    gX0, gY0 = sk.gram_backward(X, Y, gK, "approx", 5)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    torch.testing.assert_close(Xg.grad, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
+    torch.testing.assert_close(Yg.grad, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
