@@ -56,6 +56,9 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, copy MIB MiB device to device once (a plain copy "
+                         "kernel of known size, to scale HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -95,6 +98,13 @@ def main(argv=None) -> int:
     t1 = time.perf_counter()
     ktimes = {k: _lib.profile_read(k) for k in kernels}
     _lib.profile_enable(False)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     cells = float(N_PATHS * N_PATHS * STEPS * STEPS)
     value = cells / (ms_per_step * 1e-3)

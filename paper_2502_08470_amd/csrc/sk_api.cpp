@@ -249,8 +249,8 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     L.ce = backward ? take(z.ce * 4) : off;
     L.qb = backward ? take(z.qb * (int64_t)es) : off;
     L.qe = backward ? take(z.qe * 4) : off;
-    L.ck0 = backward ? take(z.ck / (N + 1) * 8) : off;  // FP64 corner coefficients
-    L.qb0 = backward ? take(z.qe * 8) : off;
+    L.ck0 = backward ? take(z.ck / (N + 1) * 2 * 8) : off;  // FP64 coefficients 0, 1
+    L.qb0 = backward ? take(z.qe * 2 * 8) : off;
     L.dxp = backward ? take(z.dx * (int64_t)es) : off;
     L.dyp = backward ? take(z.dy * (int64_t)es) : off;
     L.kbuf = backward ? take(P * (int64_t)es) : off;

@@ -84,7 +84,7 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
     if (backward && g.nsteps > 0) {
         int64_t nck = (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;
-        z.ce = nck;
+        z.ce = nck * SK_LANES;  // per-lane exponents
         z.qb = (int64_t)g.nstrips * g.ly * (N + 1);
         z.qe = (int64_t)g.nstrips * g.ly;
         z.dx = (int64_t)lx * d;

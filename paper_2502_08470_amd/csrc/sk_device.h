@@ -2,10 +2,11 @@
 // one-cell maps of the polynomial schemes.
 //
 // Edge coefficients are kept in the factorial-scaled basis P'_n = n! P_n,
-// in the working precision R, except the constant coefficient P'_0 (the
-// kernel value at the cell corner), which is carried and updated in FP64 as
-// well: its update adds O(c) corrections to an O(1) value every cell, the
-// dominant source of rounding error in an FP32 sweep.
+// in the working precision R, except coefficients 0 and 1 (the kernel value
+// at the cell corner and the slope along the edge), which are carried and
+// updated in FP64 as well: their updates add small corrections to large,
+// long-lived values every cell, the dominant source of rounding error in an
+// FP32 sweep.
 // where P_n are the coefficients of an edge in its cell's local variable
 // u in [0, 1].  In that basis the untruncated one-step map of Proposition
 // "approxsolution" (eqs. powerseries1/2, normalised cell, constant c) reads
@@ -81,6 +82,13 @@ __device__ __forceinline__ double lane_from_next(double v) {
     return *reinterpret_cast<double*>(&o);
 }
 
+__device__ __forceinline__ int lane_from_prev(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int lane_from_next(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
+}
+
 template <typename R>
 __device__ __forceinline__ R wave_max(R v) {
 #pragma unroll
@@ -106,8 +114,8 @@ template <typename R> struct SkBand;
 template <> struct SkBand<float> { static constexpr int value = 32; };
 template <> struct SkBand<double> { static constexpr int value = 256; };
 
-// Wave-uniform exponent update from the largest live magnitude `m`
-// (already reduced over the wave).  Returns the shift to apply (0 = none).
+// Exponent update from the largest magnitude `m` of a lane's state.
+// Returns the shift to apply (0 = none).
 template <typename R>
 __device__ __forceinline__ int sk_rescale_shift(R m) {
     if (!(m > (R)0) || !sk_finite(m)) return 0;
@@ -140,6 +148,11 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // right (Qo).  TMAX = 0: approximation scheme.  TMAX > 0: interpolation
 // scheme with the adaptive tail above; `active` lanes take part in the
 // tail decision (idle lanes may hold stale values).
+// Edge coefficients 0 and 1 (the value at the corner and the slope) are
+// carried in FP64 by the caller (P0, P1, Q0, Q1) and updated here in FP64;
+// P[0], P[1], Q[0], Q[1] must hold their rounded copies, used by the rows
+// n >= 2, which are computed in R.  Outputs likewise: Po0, Po1, Qo0, Qo1 in
+// FP64, Po[0..1], Qo[0..1] their rounded copies.
 // WD: also return the c-derivatives of the untruncated rows,
 //   D^P_r = dA^P_r/dc = (Toeplitz row r-1 of P) + r c^{r-1} (Hankel row r of Q),
 // for r = 1..N+T in DP[r-1] (zero beyond the rows kept), and the number of
@@ -147,9 +160,10 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // forward: its transposed map does not depend on the edges.
 template <typename R, int N, int TMAX, bool WD = false>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
-                                            double Q0, R c, bool active, const SkTab<R>& tab,
-                                            R (&Po)[N + 1], R (&Qo)[N + 1], double& Po0,
-                                            double& Qo0, R* DP = nullptr, R* DQ = nullptr,
+                                            double P1, double Q0, double Q1, R c, bool active,
+                                            const SkTab<R>& tab, R (&Po)[N + 1], R (&Qo)[N + 1],
+                                            double& Po0, double& Po1, double& Qo0, double& Qo1,
+                                            R* DP = nullptr, R* DQ = nullptr,
                                             int* Tkept = nullptr) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
@@ -168,21 +182,36 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         }
         *Tkept = 0;
     }
-    // row 0 carries the kernel value at the corner: P'_0 + sum_{k>=1} Q'_k/k!
-    // (and symmetrically); the corner coefficient is accumulated in FP64
+    // rows 0 and 1 in FP64:
+    //   A_0 = P'_0 + sum_{k>=1} Q'_k/k!,  A_1 = P'_1 + c (P'_0 + sum_{k>=1} Q'_k/(k+1)!)
+    double HQ1, HP1;
     {
-        R hq = (R)0, hp = (R)0;
+        R hq0 = (R)0, hp0 = (R)0, hq1 = (R)0, hp1 = (R)0;
 #pragma unroll
-        for (int k = N; k >= 1; --k) {
-            hq = fma(Q[k], ifact<R>(k), hq);
-            hp = fma(P[k], ifact<R>(k), hp);
+        for (int k = N; k >= 2; --k) {
+            hq0 = fma(Q[k], ifact<R>(k), hq0);
+            hp0 = fma(P[k], ifact<R>(k), hp0);
+            hq1 = fma(Q[k], ifact<R>(k + 1), hq1);
+            hp1 = fma(P[k], ifact<R>(k + 1), hp1);
         }
-        Po0 = P0 + (double)hq;
-        Qo0 = Q0 + (double)hp;
+        const double cd = (double)c;
+        HQ1 = (double)hq1 + 0.5 * Q1;
+        HP1 = (double)hp1 + 0.5 * P1;
+        Po0 = P0 + ((double)hq0 + Q1);
+        Qo0 = Q0 + ((double)hp0 + P1);
+        Po1 = fma(cd, P0 + HQ1, P1);
+        Qo1 = fma(cd, Q0 + HP1, Q1);
     }
-    R tpp = P[0], tqp = Q[0];  // Toeplitz row r-1
+    R tpp = P[0], tqp = Q[0];  // Toeplitz row r-1 (for D)
+    if (WD) {
+        // D_1 = (Toeplitz row 0) + 1 * c^0 * H_1
+        DP[0] = P[0] + (R)HQ1;
+        DQ[0] = Q[0] + (R)HP1;
+        tpp = fma(c, P[0], P[1]);
+        tqp = fma(c, Q[0], Q[1]);
+    }
 #pragma unroll
-    for (int r = 1; r <= N; ++r) {
+    for (int r = 2; r <= N; ++r) {
         R tp = (R)0, tq = (R)0;
 #pragma unroll
         for (int k = r; k >= 0; --k) {
@@ -208,7 +237,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
     if (TMAX > 0) {
         const R scale = (R)SkEps<R>::value * (R)(fabs(Po0) + fabs(Qo0));
         const R ac = sk_abs(c);
-        R t0p = (R)0, t0q = (R)0;  // tail contributions to row 0
+        R t0p = (R)0, t0q = (R)0, t1p = (R)0, t1q = (R)0;  // tail into rows 0, 1
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
             const int r = N + 1 + t;
@@ -235,8 +264,10 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
             }
             t0p = fma(tab.rs[0][t], arp, t0p);
             t0q = fma(tab.rs[0][t], arq, t0q);
+            t1p = fma(tab.rs[1][t], arp, t1p);
+            t1q = fma(tab.rs[1][t], arq, t1q);
 #pragma unroll
-            for (int n = 1; n <= N; ++n) {
+            for (int n = 2; n <= N; ++n) {
                 Po[n] = fma(tab.rs[n][t], arp, Po[n]);
                 Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
@@ -246,9 +277,13 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         }
         Po0 += (double)t0p;
         Qo0 += (double)t0q;
+        Po1 += (double)t1p;
+        Qo1 += (double)t1q;
     }
     Po[0] = (R)Po0;
     Qo[0] = (R)Qo0;
+    Po[1] = (R)Po1;
+    Qo[1] = (R)Qo1;
 }
 
 // ---------------------------------------------------------------------------

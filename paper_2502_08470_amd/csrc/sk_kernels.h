@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     extern __shared__ __align__(16) unsigned char sk_smem[];
     R* Xs = reinterpret_cast<R*>(sk_smem);          // [64][dp]
     R* Ys = Xs + 64 * dp;                            // [128][dp]
-    R* Tt = Ys + 128 * dp;                           // [64][65]
+    R* Tt = Ys + 128 * dp;                           // [64][66]: diagonal reads conflict-free
     const R* X = a.X + pd.x_off * a.d;
     const R* Y = a.Y + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 65 + 16 * ni + (lane & 15)] = acc[v];
+                    Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];
             }
             __syncthreads();
 #pragma unroll
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
                 const int col = L - Lmin - 64 * h;
                 if (L >= 0 && col >= 0 && col < 64) {
                     int ss = L / g.Tp, j = L - ss * g.Tp;
-                    if (ss == s && j < g.ly && s * 64 + r < g.lx) val[q] = Tt[r * 65 + col];
+                    if (ss == s && j < g.ly && s * 64 + r < g.lx) val[q] = Tt[r * 66 + col];
                 }
             }
         }
@@ -188,6 +188,14 @@ __device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, dou
     }
 }
 
+// Magnitude bookkeeping: every lane carries its own power-of-two exponent E
+// (the edges it holds are mantissa * 2^E).  Lanes of one wave sit at very
+// different places of the grid, whose kernel values can differ by far more
+// than the floating-point range, so the exponent travels with the edge that
+// moves to the next lane and the receiving lane aligns both inputs of its cell
+// to the larger exponent (the smaller input loses only bits below the
+// working precision of the larger one).  Every 8 steps each lane rescales its
+// own state back into [2^-band, 2^band].
 template <typename R, int N, int TMAX, bool CKPT, int S>
 __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     const int r = threadIdx.x;
@@ -198,21 +206,22 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
         if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
         return;
     }
-    // LDS: FP64 corners, then edge coefficients, then exponent tags
+    // LDS ring of strip-boundary edges: FP64 corners, coefficients 1..N,
+    // exponent tags
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    double* qlds0 = reinterpret_cast<double*>(sk_smem);
-    R* qlds = reinterpret_cast<R*>(qlds0 + g.ly);
-    int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N + 1));
+    double* qlds0 = reinterpret_cast<double*>(sk_smem);          // [ly][2]
+    R* qlds = reinterpret_cast<R*>(qlds0 + 2 * (size_t)g.ly);     // [ly][N-1]
+    int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N - 1));
     const R* cs = a.cskew + pd.c_off;
 
     R P[N + 1], Qs[N + 1];
-    double P0 = 0.0, Qs0 = 0.0;
+    double P0 = 0.0, P1 = 0.0, Qs0 = 0.0, Qs1 = 0.0;
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
         P[n] = (R)0;
         Qs[n] = (R)0;
     }
-    int E = 0;
+    int E = 0, Es = 0;
     int L = -r, s = 0, j = 0;
     bool live = false;
     const int nst8 = (g.nsteps + 7) & ~7;
@@ -229,32 +238,51 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             const int tau = t0 + u;
             R Qin[N + 1];
 #pragma unroll
-            for (int n = 1; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
-            double Qin0 = lane_from_prev(Qs0);
+            for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+            double Qin0 = lane_from_prev(Qs0), Qin1 = lane_from_prev(Qs1);
+            int Ein = lane_from_prev(Es);
             const int i = s * 64 + r;
             live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             if (live) {
-                const double one = ldexp(1.0, -E);
                 if (j == 0) {
-                    P0 = one;
+                    P0 = 1.0;
+                    P1 = 0.0;
 #pragma unroll
-                    for (int n = 1; n <= N; ++n) P[n] = (R)0;
+                    for (int n = 2; n <= N; ++n) P[n] = (R)0;
+                    E = 0;
                 }
                 if (r == 0) {
                     if (s == 0) {
-                        Qin0 = one;
+                        Qin0 = 1.0;
+                        Qin1 = 0.0;
 #pragma unroll
-                        for (int n = 1; n <= N; ++n) Qin[n] = (R)0;
+                        for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
+                        Ein = 0;
                     } else {
-                        const int sh = qtag[j] - E;
-                        Qin0 = ldexp(qlds0[j], sh);
+                        Qin0 = qlds0[2 * j];
+                        Qin1 = qlds0[2 * j + 1];
 #pragma unroll
-                        for (int n = 1; n <= N; ++n) Qin[n] = sk_ldexp(qlds[j * (N + 1) + n], sh);
+                        for (int n = 2; n <= N; ++n) Qin[n] = qlds[j * (N - 1) + n - 2];
+                        Ein = qtag[j];
                     }
                 }
+                const int Ec = E > Ein ? E : Ein;
+                const int dp = E - Ec, dq = Ein - Ec;
+                P0 = ldexp(P0, dp);
+                P1 = ldexp(P1, dp);
+                Qin0 = ldexp(Qin0, dq);
+                Qin1 = ldexp(Qin1, dq);
+#pragma unroll
+                for (int n = 2; n <= N; ++n) {
+                    P[n] = sk_ldexp(P[n], dp);
+                    Qin[n] = sk_ldexp(Qin[n], dq);
+                }
+                E = Ec;
             }
             P[0] = (R)P0;
+            P[1] = (R)P1;
             Qin[0] = (R)Qin0;
+            Qin[1] = (R)Qin1;
             if (CKPT && (tau % S) == 0 && tau < g.nsteps) {
                 const int64_t kk = tau / S;
                 R* ck = a.ck + pd.ck_off + kk * 2 * (N + 1) * 64;
@@ -263,40 +291,48 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                     ck[n * 64 + r] = P[n];
                     ck[(N + 1 + n) * 64 + r] = Qin[n];
                 }
-                double* ck0 = a.ck0 + pd.ck_off / (N + 1) + kk * 2 * 64;
+                double* ck0 = a.ck0 + pd.ck_off / (N + 1) * 2 + kk * 4 * 64;
                 ck0[r] = P0;
-                ck0[64 + r] = Qin0;
-                if (r == 0) a.ce[pd.ce_off + kk] = E;
+                ck0[64 + r] = P1;
+                ck0[128 + r] = Qin0;
+                ck0[192 + r] = Qin1;
+                a.ce[pd.ce_off + kk * 64 + r] = E;
             }
             R Po[N + 1], Qo[N + 1];
-            double Po0, Qo0;
-            sk_cell_fwd<R, N, TMAX>(P, Qin, P0, Qin0, cb[u], live, a.tab, Po, Qo, Po0, Qo0);
+            double Po0, Po1, Qo0, Qo1;
+            sk_cell_fwd<R, N, TMAX>(P, Qin, P0, P1, Qin0, Qin1, cb[u], live, a.tab, Po, Qo, Po0,
+                                    Po1, Qo0, Qo1);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
                 Qs[n] = Qo[n];
             }
             P0 = Po0;
+            P1 = Po1;
             Qs0 = Qo0;
+            Qs1 = Qo1;
+            Es = E;
             if (live) {
                 if (r == 63 && s + 1 < g.nstrips) {
-                    qlds0[j] = Qo0;
+                    qlds0[2 * j] = Qo0;
+                    qlds0[2 * j + 1] = Qo1;
 #pragma unroll
-                    for (int n = 1; n <= N; ++n) qlds[j * (N + 1) + n] = Qo[n];
+                    for (int n = 2; n <= N; ++n) qlds[j * (N - 1) + n - 2] = Qo[n];
                     qtag[j] = E;
                     if (CKPT) {
                         const int64_t o = (int64_t)(s + 1) * g.ly + j;
 #pragma unroll
                         for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
-                        a.qb0[pd.qe_off + o] = Qo0;
+                        a.qb0[(pd.qe_off + o) * 2] = Qo0;
+                        a.qb0[(pd.qe_off + o) * 2 + 1] = Qo1;
                         a.qe[pd.qe_off + o] = E;
                     }
                 }
                 if (i == g.lx - 1 && j == g.ly - 1) {
                     R kr = (R)0;
 #pragma unroll
-                    for (int n = N; n >= 1; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
-                    const double kv = 0.5 * (Po0 + Qo0 + (double)kr);
+                    for (int n = N; n >= 2; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
+                    const double kv = 0.5 * (Po0 + Qo0 + Po1 + Qo1 + (double)kr);
                     sk_write_k(a.K, a.Kexp, pd.k_idx, kv, E);
                 }
             }
@@ -308,27 +344,29 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             }
             ++L;
         }
-        // exponent tracking: wave-uniform power-of-two rescale of live state
-        R m = (R)0;
+        // per-lane rescale of the live state
         if (live) {
-            m = (R)fmax(fabs(P0), fabs(Qs0));
+            R m = (R)fmax(fmax(fabs(P0), fabs(Qs0)), fmax(fabs(P1), fabs(Qs1)));
 #pragma unroll
-            for (int n = 1; n <= N; ++n) {
+            for (int n = 2; n <= N; ++n) {
                 R ap = sk_abs(P[n]), aq = sk_abs(Qs[n]);
                 m = ap > m ? ap : m;
                 m = aq > m ? aq : m;
             }
-        }
-        const int sh = sk_rescale_shift<R>(wave_max(m));
-        if (sh != 0) {
+            const int sh = sk_rescale_shift<R>(m);
+            if (sh != 0) {
 #pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                P[n] = sk_ldexp(P[n], -sh);
-                Qs[n] = sk_ldexp(Qs[n], -sh);
+                for (int n = 0; n <= N; ++n) {
+                    P[n] = sk_ldexp(P[n], -sh);
+                    Qs[n] = sk_ldexp(Qs[n], -sh);
+                }
+                P0 = ldexp(P0, -sh);
+                P1 = ldexp(P1, -sh);
+                Qs0 = ldexp(Qs0, -sh);
+                Qs1 = ldexp(Qs1, -sh);
+                E += sh;
+                Es = E;
             }
-            P0 = ldexp(P0, -sh);
-            Qs0 = ldexp(Qs0, -sh);
-            E += sh;
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) cb[u] = cn[u];
@@ -354,6 +392,10 @@ struct AdjArgs {
     R* gskew;              // out: skewed dL/dc
 };
 
+// Exponent of an adjoint vector that is zero by construction: below any
+// real exponent, so alignment to the larger exponent ignores it.
+#define SK_ZERO_EXP (-(1 << 29))
+
 template <typename R, int N, int TMAX, int S>
 __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const int r = threadIdx.x;
@@ -368,14 +410,15 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     R* gs = a.gskew + pd.c_off;
     const R gk = a.gK[pd.k_idx];
     const int gexp = a.gKexp ? a.gKexp[pd.k_idx] : 0;
-    int El = gexp;
 
+    // adjoint state: lp (own, exponent El), lqs (sent to lane r-1, exponent Els)
     R lp[N + 1], lqs[N + 1];
 #pragma unroll
     for (int n = 0; n <= N; ++n) {
         lp[n] = (R)0;
         lqs[n] = (R)0;
     }
+    int El = SK_ZERO_EXP, Els = SK_ZERO_EXP;
     const int nck = (g.nsteps + S - 1) / S;
     for (int kk = nck - 1; kk >= 0; --kk) {
         const int tau0 = kk * S;
@@ -383,22 +426,23 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
 #pragma unroll
         for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
         // ---- replay the segment's forward from the checkpoint, recording
-        // each cell's row derivatives and kept tail length
+        // each cell's row derivatives, kept tail length and exponent
         constexpr int M = N + TMAX;
         R Dp[S][M], Dq[S][M];
-        int Tst[S];
+        int Tst[S], Est[S];
         bool lv[S];
         int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
-        const double* ck0 = a.ck0 + pd.ck_off / (N + 1) + (int64_t)kk * 2 * 64;
-        const int E = a.ce[pd.ce_off + kk];
+        const double* ck0 = a.ck0 + pd.ck_off / (N + 1) * 2 + (int64_t)kk * 4 * 64;
+        int E = a.ce[pd.ce_off + (int64_t)kk * 64 + r];
         R P[N + 1], Qs[N + 1];
 #pragma unroll
         for (int n = 0; n <= N; ++n) {
             P[n] = ck[n * 64 + r];
             Qs[n] = ck[(N + 1 + n) * 64 + r];
         }
-        double P0 = ck0[r], Qs0 = ck0[64 + r];
+        double P0 = ck0[r], P1 = ck0[64 + r], Qs0 = ck0[128 + r], Qs1 = ck0[192 + r];
+        int Es = E;
         int L = tau0 - r, s = 0, j = 0;
         if (L >= 0) {
             s = L / g.Tp;
@@ -409,54 +453,78 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             const int i = s * 64 + r;
             const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             R Qin[N + 1];
-            double Qin0;
+            double Qin0, Qin1;
             if (u == 0) {
 #pragma unroll
                 for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
                 Qin0 = Qs0;
+                Qin1 = Qs1;
             } else {
 #pragma unroll
-                for (int n = 1; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
                 Qin0 = lane_from_prev(Qs0);
+                Qin1 = lane_from_prev(Qs1);
+                int Ein = lane_from_prev(Es);
                 if (live) {
-                    const double one = ldexp(1.0, -E);
                     if (j == 0) {
-                        P0 = one;
+                        P0 = 1.0;
+                        P1 = 0.0;
 #pragma unroll
-                        for (int n = 1; n <= N; ++n) P[n] = (R)0;
+                        for (int n = 2; n <= N; ++n) P[n] = (R)0;
+                        E = 0;
                     }
                     if (r == 0) {
                         if (s == 0) {
-                            Qin0 = one;
+                            Qin0 = 1.0;
+                            Qin1 = 0.0;
 #pragma unroll
-                            for (int n = 1; n <= N; ++n) Qin[n] = (R)0;
+                            for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
+                            Ein = 0;
                         } else {
                             const int64_t o = (int64_t)s * g.ly + j;
-                            const int sh = a.qe[pd.qe_off + o] - E;
-                            Qin0 = ldexp(a.qb0[pd.qe_off + o], sh);
+                            Qin0 = a.qb0[(pd.qe_off + o) * 2];
+                            Qin1 = a.qb0[(pd.qe_off + o) * 2 + 1];
 #pragma unroll
-                            for (int n = 1; n <= N; ++n)
-                                Qin[n] = sk_ldexp(a.qb[pd.qb_off + o * (N + 1) + n], sh);
+                            for (int n = 2; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                            Ein = a.qe[pd.qe_off + o];
                         }
                     }
+                    const int Ec = E > Ein ? E : Ein;
+                    const int dp = E - Ec, dq = Ein - Ec;
+                    P0 = ldexp(P0, dp);
+                    P1 = ldexp(P1, dp);
+                    Qin0 = ldexp(Qin0, dq);
+                    Qin1 = ldexp(Qin1, dq);
+#pragma unroll
+                    for (int n = 2; n <= N; ++n) {
+                        P[n] = sk_ldexp(P[n], dp);
+                        Qin[n] = sk_ldexp(Qin[n], dq);
+                    }
+                    E = Ec;
                 }
                 P[0] = (R)P0;
+                P[1] = (R)P1;
                 Qin[0] = (R)Qin0;
+                Qin[1] = (R)Qin1;
             }
             lv[u] = live;
             sst[u] = s;
             jst[u] = j;
+            Est[u] = E;
             R Po[N + 1], Qo[N + 1];
-            double Po0, Qo0;
-            sk_cell_fwd<R, N, TMAX, true>(P, Qin, P0, Qin0, cseg[u], live, a.tab, Po, Qo, Po0, Qo0,
-                                          Dp[u], Dq[u], &Tst[u]);
+            double Po0, Po1, Qo0, Qo1;
+            sk_cell_fwd<R, N, TMAX, true>(P, Qin, P0, P1, Qin0, Qin1, cseg[u], live, a.tab, Po, Qo,
+                                          Po0, Po1, Qo0, Qo1, Dp[u], Dq[u], &Tst[u]);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
                 Qs[n] = Qo[n];
             }
             P0 = Po0;
+            P1 = Po1;
             Qs0 = Qo0;
+            Qs1 = Qo1;
+            Es = E;
             if (L >= 0) {
                 if (++j == g.Tp) {
                     j = 0;
@@ -474,7 +542,9 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             R lq_recv[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
+            const int El_recv = lane_from_next(Els);
             R ap[N + 1], aq[N + 1];
+            int ea = SK_ZERO_EXP, eb = SK_ZERO_EXP;
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 ap[n] = (R)0;
@@ -482,49 +552,58 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             }
             if (live) {
                 const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
-                if (last_col || last_row) {
+                if (last_col && last_row) {
                     // endpoint seed: L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
-                    const R sd = (last_col && last_row) ? sk_ldexp((R)0.5 * gk, gexp - El) : (R)0;
 #pragma unroll
                     for (int n = 0; n <= N; ++n) {
-                        if (last_col) ap[n] = sd * ifact<R>(n);
-                        if (last_row) aq[n] = sd * ifact<R>(n);
+                        ap[n] = (R)0.5 * gk * ifact<R>(n);
+                        aq[n] = ap[n];
                     }
+                    ea = gexp;
+                    eb = gexp;
                 }
                 if (!last_col) {
 #pragma unroll
                     for (int n = 0; n <= N; ++n) ap[n] = lp[n];
+                    ea = El;
                 }
                 if (!last_row) {
                     if (r == 63) {
-                        const int sh = ltag[jj] - El;
 #pragma unroll
-                        for (int n = 0; n <= N; ++n) aq[n] = sk_ldexp(llds[jj * (N + 1) + n], sh);
+                        for (int n = 0; n <= N; ++n) aq[n] = llds[jj * (N + 1) + n];
+                        eb = ltag[jj];
                     } else {
 #pragma unroll
                         for (int n = 0; n <= N; ++n) aq[n] = lq_recv[n];
+                        eb = El_recv;
                     }
                 }
+            }
+            const int Ec = ea > eb ? ea : eb;
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = sk_ldexp(ap[n], ea - Ec);
+                aq[n] = sk_ldexp(aq[n], eb - Ec);
             }
             R gv;
             sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
+            El = Ec;
+            Els = Ec;
             if (live && r == 0 && ss > 0) {
 #pragma unroll
                 for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
-                ltag[jj] = El;
+                ltag[jj] = Ec;
             }
-            gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, El + E) : (R)0;
-            if ((tau & 7) == 0) {
+            gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, Ec + Est[u]) : (R)0;
+            if ((tau & 7) == 0 && live) {
                 R m = (R)0;
-                if (live) {
 #pragma unroll
-                    for (int n = 0; n <= N; ++n) {
-                        R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
-                        m = x1 > m ? x1 : m;
-                        m = x2 > m ? x2 : m;
-                    }
+                for (int n = 0; n <= N; ++n) {
+                    R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
+                    m = x1 > m ? x1 : m;
+                    m = x2 > m ? x2 : m;
                 }
-                const int sh = sk_rescale_shift<R>(wave_max(m));
+                const int sh = sk_rescale_shift<R>(m);
                 if (sh != 0) {
 #pragma unroll
                     for (int n = 0; n <= N; ++n) {
@@ -532,6 +611,7 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                         lqs[n] = sk_ldexp(lqs[n], -sh);
                     }
                     El += sh;
+                    Els = El;
                 }
             }
         }
@@ -880,9 +960,9 @@ __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
                 P[n] = pe[i * (N + 1) + n];
                 Q[n] = qe[j * (N + 1) + n];
             }
-            double Po0, Qo0;
-            sk_cell_fwd<R, N, TMAX>(P, Q, (double)P[0], (double)Q[0], c, true, a.tab, Po, Qo, Po0,
-                                    Qo0);
+            double Po0, Po1, Qo0, Qo1;
+            sk_cell_fwd<R, N, TMAX>(P, Q, (double)P[0], (double)P[1], (double)Q[0], (double)Q[1], c,
+                                    true, a.tab, Po, Qo, Po0, Po1, Qo0, Qo1);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 pe[i * (N + 1) + n] = Po[n];
@@ -891,8 +971,8 @@ __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
             if (i == lx - 1 && j == ly - 1) {
                 R kv = (R)0;
 #pragma unroll
-                for (int n = N; n >= 1; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
-                sk_write_k(a.K, a.Kexp, a.k_idx, 0.5 * (Po0 + Qo0 + (double)kv), 0);
+                for (int n = N; n >= 2; --n) kv = fma(Po[n] + Qo[n], ifact<R>(n), kv);
+                sk_write_k(a.K, a.Kexp, a.k_idx, 0.5 * (Po0 + Qo0 + Po1 + Qo1 + (double)kv), 0);
             }
         }
         __syncthreads();

@@ -35,10 +35,14 @@ struct SkLaunch {
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
     // LDS bytes needed per workgroup by the sweep / adjoint for a given column count
+    // forward: 2 FP64 coefficients + N-1 coefficients + tag per column;
+    // adjoint: N+1 coefficients + tag per column
     static size_t sweep_lds(int N, int ly) {
-        return (size_t)ly * 8 + (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4;
+        const size_t f = (size_t)ly * 16 + (size_t)ly * (N - 1) * sizeof(R) + (size_t)ly * 4;
+        const size_t b = (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4;
+        return f > b ? f : b;
     }
-    static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 65) * sizeof(R); }
+    static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
 };
 
 extern template struct SkLaunch<float>;

@@ -1,0 +1,139 @@
+"""GPU parity at the full sizes of the benchmark configurations, in the
+launch configuration the benchmark uses, checked on sampled outputs the FP64
+oracle computes one by one.
+
+* 128x128 Gram (R^8, 256 steps, interpolation N=6, FP32) through autograd:
+  MAPE <= 1e-6 on a sampled 8x8 block; dL/dX (L = sum K) on sampled
+  coordinates within 1e-5 relative of central differences of the oracle.
+* 4096 uneven oscillatory pairs (R^16, 32..2048 points, approximation N=8):
+  FP64 path on sampled pairs within 1e-8 relative (these short oscillatory
+  pairs amplify rounding; the FP64 oracle itself is only good to about
+  1e-10 on the worst of them).
+* MMD^2 sets (2 x 64 paths in R^5, 512 steps, approximation N=8, FP32):
+  sampled Kxy entries (MAPE <= 1e-6) and dMMD^2/dX on sampled coordinates
+  within 1e-5 relative of central differences of the oracle.
+* 1024x1024 Gram (R^32, 1024 steps, unit-variance cell constants,
+  approximation N=8, FP32 with exponents): sampled pairs within 1e-3
+  relative (kernels near 10^350; FP32 rounding amplified by the problem's
+  conditioning, about 2e-5 at this size).
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_common import log_banner, rel_err, rel_err_exp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2502_08470_amd as P
+    from paper_2502_08470_amd import _lib
+    _lib.lib()
+    return P
+
+
+def test_batched_interp_gram_full_size(sk):
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("full 128x128 interpolation Gram")
+    X, Y = W.batched_interp_gram(0)
+    Xt = torch.tensor(X, device="cuda").requires_grad_(True)
+    Yt = torch.tensor(Y, device="cuda").requires_grad_(True)
+    K = sk.sig_gram(Xt, Yt, "interp", 6)
+    K.sum().backward()
+    rng = np.random.default_rng(0)
+    ia = np.sort(rng.choice(128, 8, replace=False))
+    ib = np.sort(rng.choice(128, 8, replace=False))
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    m, e = C.gram(Xd[ia], Yd[ib], C.INTERP, 6)
+    err = rel_err(K.detach().cpu().numpy()[np.ix_(ia, ib)], np.ldexp(m, e))
+    assert err.mean() <= 1e-6, err.mean()
+    gX = Xt.grad.cpu().double().numpy()
+    scale = np.abs(gX).max()
+    h = 1e-4
+    for a, t, k in [(int(ia[0]), 0, 3), (int(ia[3]), 128, 0), (int(ia[7]), 256, 7)]:
+        P = Xd[a:a + 1].copy()
+        P[0, t, k] += h
+        lp = np.ldexp(*C.gram(P, Yd, C.INTERP, 6)).sum()
+        P[0, t, k] -= 2 * h
+        lm = np.ldexp(*C.gram(P, Yd, C.INTERP, 6)).sum()
+        fd = (lp - lm) / (2 * h)
+        assert abs(gX[a, t, k] - fd) <= 1e-5 * scale, (a, t, k, gX[a, t, k], fd)
+
+
+def test_uneven_pairs_full_size(sk):
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("full 4096 uneven pairs")
+    xs, ys = W.uneven_pairs(0)
+    xs64 = [a.astype(np.float64) for a in xs]
+    ys64 = [b.astype(np.float64) for b in ys]
+    k64, e64 = sk.pairs([torch.tensor(a, device="cuda") for a in xs64],
+                        [torch.tensor(b, device="cuda") for b in ys64], "approx", 8,
+                        return_exp=True)
+    k32, e32 = sk.pairs([torch.tensor(a, device="cuda") for a in xs],
+                        [torch.tensor(b, device="cuda") for b in ys], "approx", 8,
+                        return_exp=True)
+    assert torch.isfinite(k32).all()
+    rng = np.random.default_rng(1)
+    pick = rng.choice(4096, 12, replace=False)
+    m, e = C.pairs([xs64[i] for i in pick], [ys64[i] for i in pick], C.APPROX, 8)
+    err = rel_err_exp(k64.cpu().numpy()[pick], e64.cpu().numpy()[pick], m, e)
+    assert err.max() < 1e-8, err
+
+
+def test_mmd_sets_full_size(sk):
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("full MMD sets")
+    X, Y = W.mmd_sets(0)
+    Xt = torch.tensor(X, device="cuda").requires_grad_(True)
+    Yt = torch.tensor(Y, device="cuda").requires_grad_(True)
+    val = sk.mmd2(Xt, Yt, "approx", 8)
+    val.backward()
+    gX = Xt.grad.cpu().double().numpy()
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    Kxy = sk.gram(Xt.detach(), Yt.detach(), "approx", 8).cpu().numpy()
+    rng = np.random.default_rng(2)
+    ia, ib = rng.choice(64, 4, replace=False), rng.choice(64, 4, replace=False)
+    m, e = C.gram(Xd[ia], Yd[ib], C.APPROX, 8)
+    err = rel_err(Kxy[np.ix_(ia, ib)], np.ldexp(m, e))
+    assert err.mean() <= 1e-6, err
+    # dMMD^2/dX[a]: only row/column a of Kxx and row a of Kxy depend on X[a]
+    n = 64
+    scale = np.abs(gX).max()
+    h = 1e-4
+    for a, t, k in [(int(ia[0]), 100, 2), (int(ia[1]), 511, 4)]:
+        def part(Pa):
+            kx = np.ldexp(*C.gram(Pa[None], Xd, C.APPROX, 8))[0]
+            kx[a] = 0.0  # diagonal excluded by the U-statistic
+            ky = np.ldexp(*C.gram(Pa[None], Yd, C.APPROX, 8))[0]
+            return 2.0 * kx.sum() / (n * (n - 1)) - 2.0 * ky.sum() / (n * n)
+        P = Xd[a].copy()
+        P[t, k] += h
+        lp = part(P)
+        P[t, k] -= 2 * h
+        lm = part(P)
+        fd = (lp - lm) / (2 * h)
+        assert abs(gX[a, t, k] - fd) <= 1e-5 * scale, (a, t, k, gX[a, t, k], fd)
+    assert np.isfinite(float(val))
+
+
+def test_large_gram_full_size_sampled(sk):
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("full 1024x1024 Gram, d=32")
+    X, Y = W.large_gram(0)
+    Xt = torch.tensor(X, device="cuda")
+    Yt = torch.tensor(Y, device="cuda")
+    K, Ke = sk.gram(Xt, Yt, "approx", 8, return_exp=True)
+    K, Ke = K.cpu().numpy(), Ke.cpu().numpy()
+    assert np.isfinite(K).all()
+    rng = np.random.default_rng(3)
+    ia, ib = rng.choice(1024, 2, replace=False), rng.choice(1024, 2, replace=False)
+    m, e = C.gram(X[ia].astype(np.float64), Y[ib].astype(np.float64), C.APPROX, 8)
+    err = rel_err_exp(K[np.ix_(ia, ib)], Ke[np.ix_(ia, ib)], m, e)
+    assert (e + np.log2(np.abs(m))).min() > 500  # far beyond FP32 and FP64 ranges
+    assert err.max() < 1e-3, err
