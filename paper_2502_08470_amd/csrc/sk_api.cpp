@@ -230,7 +230,7 @@ int ckpt_stride(const sk_params& p) {
 // workspace layout of one chunk
 // ---------------------------------------------------------------------------
 struct Layout {
-    int64_t cskew, gskew, ck, ce, qb, qe, ck0, qb0, dxp, dyp, kbuf, kexp, desc, total;
+    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, total;
 };
 
 // Region sizes for P pairs with total per-array element counts `z` (sum over
@@ -249,8 +249,6 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     L.ce = backward ? take(z.ce * 4) : off;
     L.qb = backward ? take(z.qb * (int64_t)es) : off;
     L.qe = backward ? take(z.qe * 4) : off;
-    L.ck0 = backward ? take(z.ck / (N + 1) * 2 * 8) : off;  // FP64 coefficients 0, 1
-    L.qb0 = backward ? take(z.qe * 2 * 8) : off;
     L.dxp = backward ? take(z.dx * (int64_t)es) : off;
     L.dyp = backward ? take(z.dy * (int64_t)es) : off;
     L.kbuf = backward ? take(P * (int64_t)es) : off;
@@ -530,8 +528,6 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     sa.qb = reinterpret_cast<R*>(ws + L.qb);
     sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
-    sa.ck0 = reinterpret_cast<double*>(ws + L.ck0);
-    sa.qb0 = reinterpret_cast<double*>(ws + L.qb0);
     SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, max_ly, st), "checkpoint sweep");
     return SK_OK;
 }
@@ -551,8 +547,6 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.ce = reinterpret_cast<const int32_t*>(ws + L.ce);
     aa.qb = reinterpret_cast<const R*>(ws + L.qb);
     aa.qe = reinterpret_cast<const int32_t*>(ws + L.qe);
-    aa.ck0 = reinterpret_cast<const double*>(ws + L.ck0);
-    aa.qb0 = reinterpret_cast<const double*>(ws + L.qb0);
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, max_ly, st), "adjoint sweep");
     ContractArgs<R> ca;

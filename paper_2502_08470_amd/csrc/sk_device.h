@@ -158,7 +158,10 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // for r = 1..N+T in DP[r-1] (zero beyond the rows kept), and the number of
 // tail rows kept T (wave-uniform).  These are all the adjoint needs from the
 // forward: its transposed map does not depend on the edges.
-template <typename R, int N, int TMAX, bool WD = false>
+// HI = false: every row in R (the FP64 arguments are ignored and the FP64
+// outputs are the R results widened); used where FP32 accuracy of the state
+// is enough, e.g. the adjoint's short replays.
+template <typename R, int N, int TMAX, bool WD = false, bool HI = true>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
                                             double P1, double Q0, double Q1, R c, bool active,
                                             const SkTab<R>& tab, R (&Po)[N + 1], R (&Qo)[N + 1],
@@ -182,10 +185,10 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         }
         *Tkept = 0;
     }
-    // rows 0 and 1 in FP64:
+    // rows 0 and 1 (in FP64 when HI):
     //   A_0 = P'_0 + sum_{k>=1} Q'_k/k!,  A_1 = P'_1 + c (P'_0 + sum_{k>=1} Q'_k/(k+1)!)
     double HQ1, HP1;
-    {
+    if (HI) {
         R hq0 = (R)0, hp0 = (R)0, hq1 = (R)0, hp1 = (R)0;
 #pragma unroll
         for (int k = N; k >= 2; --k) {
@@ -201,6 +204,21 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         Qo0 = Q0 + ((double)hp0 + P1);
         Po1 = fma(cd, P0 + HQ1, P1);
         Qo1 = fma(cd, Q0 + HP1, Q1);
+    } else {
+        R hq0 = (R)0, hp0 = (R)0, hq1 = (R)0, hp1 = (R)0;
+#pragma unroll
+        for (int k = N; k >= 1; --k) {
+            hq0 = fma(Q[k], ifact<R>(k), hq0);
+            hp0 = fma(P[k], ifact<R>(k), hp0);
+            hq1 = fma(Q[k], ifact<R>(k + 1), hq1);
+            hp1 = fma(P[k], ifact<R>(k + 1), hp1);
+        }
+        HQ1 = (double)hq1;
+        HP1 = (double)hp1;
+        Po0 = (double)(P[0] + hq0);
+        Qo0 = (double)(Q[0] + hp0);
+        Po1 = (double)fma(c, P[0] + hq1, P[1]);
+        Qo1 = (double)fma(c, Q[0] + hp1, Q[1]);
     }
     R tpp = P[0], tqp = Q[0];  // Toeplitz row r-1 (for D)
     if (WD) {

@@ -173,8 +173,6 @@ struct SweepArgs {
     int32_t* ce;
     R* qb;
     int32_t* qe;
-    double* ck0;   // FP64 corner coefficients of the checkpoints
-    double* qb0;   // FP64 corner coefficients of the strip-boundary edges
 };
 
 template <typename R>
@@ -291,11 +289,6 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                     ck[n * 64 + r] = P[n];
                     ck[(N + 1 + n) * 64 + r] = Qin[n];
                 }
-                double* ck0 = a.ck0 + pd.ck_off / (N + 1) * 2 + kk * 4 * 64;
-                ck0[r] = P0;
-                ck0[64 + r] = P1;
-                ck0[128 + r] = Qin0;
-                ck0[192 + r] = Qin1;
                 a.ce[pd.ce_off + kk * 64 + r] = E;
             }
             R Po[N + 1], Qo[N + 1];
@@ -323,8 +316,6 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                         const int64_t o = (int64_t)(s + 1) * g.ly + j;
 #pragma unroll
                         for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
-                        a.qb0[(pd.qe_off + o) * 2] = Qo0;
-                        a.qb0[(pd.qe_off + o) * 2 + 1] = Qo1;
                         a.qe[pd.qe_off + o] = E;
                     }
                 }
@@ -387,8 +378,6 @@ struct AdjArgs {
     const int32_t* ce;
     const R* qb;
     const int32_t* qe;
-    const double* ck0;
-    const double* qb0;
     R* gskew;              // out: skewed dL/dc
 };
 
@@ -433,7 +422,6 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
         bool lv[S];
         int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
-        const double* ck0 = a.ck0 + pd.ck_off / (N + 1) * 2 + (int64_t)kk * 4 * 64;
         int E = a.ce[pd.ce_off + (int64_t)kk * 64 + r];
         R P[N + 1], Qs[N + 1];
 #pragma unroll
@@ -441,7 +429,6 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             P[n] = ck[n * 64 + r];
             Qs[n] = ck[(N + 1 + n) * 64 + r];
         }
-        double P0 = ck0[r], P1 = ck0[64 + r], Qs0 = ck0[128 + r], Qs1 = ck0[192 + r];
         int Es = E;
         int L = tau0 - r, s = 0, j = 0;
         if (L >= 0) {
@@ -453,59 +440,40 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             const int i = s * 64 + r;
             const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             R Qin[N + 1];
-            double Qin0, Qin1;
             if (u == 0) {
 #pragma unroll
                 for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
-                Qin0 = Qs0;
-                Qin1 = Qs1;
             } else {
 #pragma unroll
-                for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
-                Qin0 = lane_from_prev(Qs0);
-                Qin1 = lane_from_prev(Qs1);
+                for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
                 int Ein = lane_from_prev(Es);
                 if (live) {
                     if (j == 0) {
-                        P0 = 1.0;
-                        P1 = 0.0;
 #pragma unroll
-                        for (int n = 2; n <= N; ++n) P[n] = (R)0;
+                        for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
                         E = 0;
                     }
                     if (r == 0) {
                         if (s == 0) {
-                            Qin0 = 1.0;
-                            Qin1 = 0.0;
 #pragma unroll
-                            for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
+                            for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
                             Ein = 0;
                         } else {
                             const int64_t o = (int64_t)s * g.ly + j;
-                            Qin0 = a.qb0[(pd.qe_off + o) * 2];
-                            Qin1 = a.qb0[(pd.qe_off + o) * 2 + 1];
 #pragma unroll
-                            for (int n = 2; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                            for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
                             Ein = a.qe[pd.qe_off + o];
                         }
                     }
                     const int Ec = E > Ein ? E : Ein;
                     const int dp = E - Ec, dq = Ein - Ec;
-                    P0 = ldexp(P0, dp);
-                    P1 = ldexp(P1, dp);
-                    Qin0 = ldexp(Qin0, dq);
-                    Qin1 = ldexp(Qin1, dq);
 #pragma unroll
-                    for (int n = 2; n <= N; ++n) {
+                    for (int n = 0; n <= N; ++n) {
                         P[n] = sk_ldexp(P[n], dp);
                         Qin[n] = sk_ldexp(Qin[n], dq);
                     }
                     E = Ec;
                 }
-                P[0] = (R)P0;
-                P[1] = (R)P1;
-                Qin[0] = (R)Qin0;
-                Qin[1] = (R)Qin1;
             }
             lv[u] = live;
             sst[u] = s;
@@ -513,17 +481,13 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             Est[u] = E;
             R Po[N + 1], Qo[N + 1];
             double Po0, Po1, Qo0, Qo1;
-            sk_cell_fwd<R, N, TMAX, true>(P, Qin, P0, P1, Qin0, Qin1, cseg[u], live, a.tab, Po, Qo,
-                                          Po0, Po1, Qo0, Qo1, Dp[u], Dq[u], &Tst[u]);
+            sk_cell_fwd<R, N, TMAX, true, false>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live, a.tab,
+                                                 Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u], Dq[u], &Tst[u]);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
                 Qs[n] = Qo[n];
             }
-            P0 = Po0;
-            P1 = Po1;
-            Qs0 = Qo0;
-            Qs1 = Qo1;
             Es = E;
             if (L >= 0) {
                 if (++j == g.Tp) {
