@@ -13,15 +13,23 @@ Inputs are resident on the GPU before timing.  Reported:
 * mape: mean |K_gpu / K_oracle - 1| on the 16 x 16 block X[0:16] x Y[0:16]
   against the FP64 oracle.
 * roofline: dominant kernel, algorithmic FLOPs / its HIP-event time.
-* cpu_baseline: the FP64 C oracle on that 16 x 16 block, host cores.
+* cpu_baseline: the FP64 C oracle on the 48 x 64 block X[0:48] x Y[0:64]
+  (about 10-20 s on 16 host cores), all host threads OMP_NUM_THREADS allows.
+* roofline.traffic: HBM bytes per launch of the dominant kernel from the
+  committed counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by the
+  same counters read for a plain 1 GiB device copy), reported only when the
+  kernel sources hash to the value recorded with the counters, else null.
 * plain_fp64: the plain single-pair FP64 kernel (one launch per pair,
   forward only) on a sample of pairs of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +46,88 @@ PEAK_FP32_VALU = 157.3e12  # MI355X published FP32 vector peak (FLOP/s)
 PEAK_FP64_VALU = 78.6e12
 SCHEME, ORDER = "interp", 6
 N_PATHS, STEPS, DIM = 128, 256, 8
+CPU_BLOCK = (48, 64)
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_interp_gram_128x128.json")
+CALIBRATE_MIB = 1024
+# bench kernel label -> prefix of the kernel symbol
+KERNEL_SYMBOL = {"gram": "k_gram_skew<", "sweep": "k_sweep<", "sweep_ckpt": "k_sweep<",
+                 "adjoint": "k_adjoint", "contract": "k_contract<", "reduce": "k_reduce"}
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP/C++ sources of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2502_08470_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
+    """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs of
+    `bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain --calibrate-copy 1024`.
+    Each counter is scaled by bytes / counter-KiB of the largest device copy
+    dispatch (the 1 GiB calibration copy: 1 GiB read, 1 GiB written)."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, ctr):
+        d = defaultdict(list)
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == ctr:
+                    d[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return d
+    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    cal = float(CALIBRATE_MIB << 20)
+    copy_f = max(v for k, vs in f.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in w.items() if "copyBuffer" in k for v in vs)
+    fscale, wscale = cal / copy_f, cal / copy_w  # bytes per counter unit
+    kernels = {}
+    for k in sorted(set(f) & set(w)):
+        if not k.startswith("void k_"):
+            continue
+        fb = sum(f[k]) / len(f[k]) * fscale
+        wb = sum(w[k]) / len(w[k]) * wscale
+        kernels[k] = {"dispatches": len(f[k]), "fetch_bytes": fb, "write_bytes": wb,
+                      "bytes": fb + wb}
+    out = {"source_hash": kernel_source_hash(),
+           "calibration": {"copy_bytes": cal, "fetch_counter": copy_f, "write_counter": copy_w,
+                           "fetch_bytes_per_unit": fscale, "write_bytes_per_unit": wscale},
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -f csv -- "
+                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
+                        f"--calibrate-copy {CALIBRATE_MIB}",
+                        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -f csv -- "
+                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
+                        f"--calibrate-copy {CALIBRATE_MIB}",
+                        "python3 bench.py --pmc-summary gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+                        "gpurun_out/pmc_write/write_counter_collection.csv " + os.path.relpath(out_json, ROOT)],
+           "kernels": kernels}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    return 0
+
+
+def traffic_for(label: str, kernel_name_hint: str | None = None):
+    """HBM bytes per launch of the kernel `label` from the committed counter
+    summary, or None when absent or taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            summ = json.load(fh)
+    except OSError:
+        return None
+    if summ.get("source_hash") != kernel_source_hash():
+        return None
+    pre = KERNEL_SYMBOL[label]
+    hits = [v for k, v in summ["kernels"].items()
+            if k.startswith("void " + pre) and (label != "sweep_ckpt" or ", true," in k)
+            and (label != "sweep" or ", false," in k)]
+    if len(hits) != 1:
+        return None
+    return hits[0]
 
 
 def fwd_cell_flops(N: int, T: int) -> float:
@@ -59,7 +149,11 @@ def main(argv=None) -> int:
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB device to device once (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="summarise two rocprofv3 --pmc runs into HBM bytes per dispatch")
     args = ap.parse_args(argv)
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -122,9 +216,12 @@ def main(argv=None) -> int:
     # launches of part of the pairs): FLOPs per launch = cells * steps / launches
     cells_per_launch = cells * args.steps / dom_n
     achieved = flops_per_cell[dom] * cells_per_launch / (dom_ms / dom_n * 1e-3)
+    tr = traffic_for(dom)
     roofline = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                "frac": achieved / PEAK_FP32_VALU,
+                "traffic": None if tr is None else tr["bytes"],
+                "traffic_unit": "bytes per launch (HBM fetch + write)",
                 "flops_per_cell": flops_per_cell[dom], "launch_ms": dom_ms / dom_n,
                 "launches_per_step": dom_n / args.steps,
                 "kernel_ms_per_step": {k: ktimes[k][0] / args.steps for k in kernels}}
@@ -139,27 +236,30 @@ def main(argv=None) -> int:
                       "pairs": N_PATHS * N_PATHS, "cells_per_pair": STEPS * STEPS},
            "gram_entries_per_s": entries, "roofline": roofline}
 
-    # accuracy and CPU oracle on the 16 x 16 block
+    # accuracy on the 16 x 16 block (and the larger CPU sample), CPU oracle
     from oracle import c_oracle as C
-    Xb = X[:16].astype(np.float64)
-    Yb = Y[:16].astype(np.float64)
     threads = C.default_threads()
-    print(f"[bench] oracle 16x16 block on {threads} threads", file=sys.stderr, flush=True)
+    bx, by = (16, 16) if args.no_cpu_baseline else CPU_BLOCK
+    Xb = X[:bx].astype(np.float64)
+    Yb = Y[:by].astype(np.float64)
+    print(f"[bench] oracle {bx}x{by} block on {threads} threads", file=sys.stderr, flush=True)
     c0 = time.perf_counter()
     m, e = C.gram(Xb, Yb, C.INTERP, ORDER, threads=threads)
     c1 = time.perf_counter()
     ref = np.ldexp(m, e)
-    Kb = K[:16, :16].double().cpu().numpy()
+    Kb = K[:bx, :by].double().cpu().numpy()
     ape = np.abs(Kb / ref - 1.0)
-    out["mape"] = float(ape.mean())
-    out["max_ape"] = float(ape.max())
+    out["mape"] = float(ape[:16, :16].mean())
+    out["max_ape"] = float(ape[:16, :16].max())
     if not args.no_cpu_baseline:
-        ocells = 16 * 16 * STEPS * STEPS
+        out["mape_cpu_sample"] = float(ape.mean())
+        out["max_ape_cpu_sample"] = float(ape.max())
+        ocells = bx * by * STEPS * STEPS
         out["cpu_baseline"] = {"value": ocells / (c1 - c0), "unit": "cell-updates/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": "16x16 block X[0:16] x Y[0:16] of the same workload, "
-                                         "forward only, FP64 C oracle (literal 0F1 at the "
-                                         "Chebyshev extrema + Vandermonde solve)",
+                               "sample": f"{bx}x{by} block X[0:{bx}] x Y[0:{by}] of the same "
+                                         "workload, forward only, FP64 C oracle (literal 0F1 "
+                                         "at the Chebyshev extrema + Vandermonde solve)",
                                "seconds": c1 - c0}
     if not args.no_plain:
         npl = 16
@@ -176,6 +276,7 @@ def main(argv=None) -> int:
                                        "per pair",
                              "max_rel_vs_oracle": float(np.max(np.abs(
                                  Kp.cpu().numpy()[0] / ref[0, :npl] - 1.0)))}
+    out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
     return 0
 
