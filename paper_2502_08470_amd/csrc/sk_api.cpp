@@ -298,17 +298,29 @@ hipError_t lds_limit(size_t* out) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
+// LDS budget under which the increment Gram keeps a whole pair's increments
+// resident (one workgroup per pair); longer pairs use 64-row blocks.
+constexpr size_t kGramPairLds = 64 << 10;
+
+template <typename R>
+hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int max_lx,
+                       int max_ly, hipStream_t st) {
+    if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
+        return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
+    return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
+}
+
 template <typename R>
 int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, const SkPairSrc& src,
-                      int64_t P, int max_nsteps_pad, int max_ly, char* ws, const Layout& L,
-                      R* K, int32_t* Kexp, hipStream_t st) {
+                      int64_t P, int max_nsteps_pad, int max_lx, int max_ly, char* ws,
+                      const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     const int lam = lam_of(p);
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = lam;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
-    SK_LAUNCH("gram", st, SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st), "increment Gram");
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
     if (p.scheme == SK_FD) {
         FdArgs<R> fa;
         fa.src = src; fa.lam = lam; fa.cskew = cskew; fa.K = K; fa.Kexp = Kexp;
@@ -381,8 +393,8 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
         std::memset(&src, 0, sizeof(src));
         src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
         src.desc = nullptr;
-        rc = run_chunk_forward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)ly, (char*)ws, L, K,
-                                  Kexp, st);
+        rc = run_chunk_forward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly, (char*)ws,
+                                  L, K, Kexp, st);
         if (rc) return rc;
     }
     return SK_OK;
@@ -392,7 +404,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
 struct ListChunk {
     int64_t first, count;
     SkPairSizes tot;
-    int max_nsteps_pad, max_ly;
+    int max_nsteps_pad, max_lx, max_ly;
     int64_t max_pts;
 };
 
@@ -401,7 +413,7 @@ int plan_pairs(const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
                size_t* need_all) {
     const int lam = lam_of(p);
     const size_t es = esize(p);
-    ListChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0};
+    ListChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0};
     size_t max_one = 0;
     for (int64_t i = 0; i < npairs; ++i) {
         const int lx = (int)(xo[i + 1] - xo[i] - 1), ly = (int)(yo[i + 1] - yo[i] - 1);
@@ -411,13 +423,14 @@ int plan_pairs(const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
         nxt.count += 1;
         nxt.tot = add(cur.tot, z);
         nxt.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
+        nxt.max_lx = std::max(cur.max_lx, lx);
         nxt.max_ly = std::max(cur.max_ly, ly);
         nxt.max_pts = std::max<int64_t>(cur.max_pts, std::max(lx, ly) + 1);
         const size_t bytes = (size_t)layout_for(nxt.tot, nxt.count, es, backward, true, p.order).total;
         max_one = std::max(max_one, (size_t)layout_for(z, 1, es, backward, true, p.order).total);
         if (bytes > wsb && cur.count > 0) {
             out.push_back(cur);
-            cur = {i, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0};
+            cur = {i, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0};
             --i;
             continue;
         }
@@ -496,8 +509,8 @@ int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
         src.desc = ddesc;
-        rc = run_chunk_forward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_ly,
-                                  (char*)ws, L, K, Kexp, st);
+        rc = run_chunk_forward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                  c.max_ly, (char*)ws, L, K, Kexp, st);
         if (rc) return rc;
     }
     return SK_OK;
@@ -511,14 +524,15 @@ int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo
 // by k_idx - kbase).
 template <typename R>
 int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
-                      const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly, char* ws,
+                      const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx, int max_ly,
+                      char* ws,
                       const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = 0;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
-    SK_LAUNCH("gram", st, SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st), "increment Gram");
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
     SweepArgs<R> sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
@@ -561,15 +575,16 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
 
 template <typename R>
 int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
-                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_ly,
-                       int max_strips, char* ws, const Layout& L, const R* gK,
+                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
+                       int max_ly, int max_strips, char* ws, const Layout& L, const R* gK,
                        const int32_t* gKexp, hipStream_t st) {
     // the checkpoint pass's kernel values go to the chunk's scratch slots
     // (Gram mode: k_idx - first; list mode: descriptors carry local k_idx)
     const int64_t kbase = src.desc ? 0 : src.first;
     R* kbuf = reinterpret_cast<R*>(ws + L.kbuf) - kbase;
     int32_t* kexp = reinterpret_cast<int32_t*>(ws + L.kexp) - kbase;
-    int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_ly, ws, L, kbuf, kexp, st);
+    int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_lx, max_ly, ws, L, kbuf,
+                                  kexp, st);
     if (rc) return rc;
     return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, max_strips, ws, L, gK, gKexp, st);
 }
@@ -606,8 +621,8 @@ int gram_save(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64
     SkPairSrc src;
     std::memset(&src, 0, sizeof(src));
     src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
-    return run_chunk_prepare<R>(p, X, Y, d, src, npairs, g.nsteps_pad, (int)ly, (char*)state, L,
-                                K, Kexp, st);
+    return run_chunk_prepare<R>(p, X, Y, d, src, npairs, g.nsteps_pad, (int)lx, (int)ly,
+                                (char*)state, L, K, Kexp, st);
 }
 
 template <typename R>
@@ -668,8 +683,8 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
         src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
-        rc = run_chunk_backward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)ly, g.nstrips,
-                                   (char*)ws, L, gK, gKexp, st);
+        rc = run_chunk_backward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly,
+                                   g.nstrips, (char*)ws, L, gK, gKexp, st);
         if (rc) return rc;
         ReduceGramArgs<R> ra;
         ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
@@ -713,8 +728,8 @@ int pairs_backward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* y
         src.desc = ddesc;
         int max_strips = 0;
         for (const auto& q : desc) max_strips = std::max(max_strips, sk_make_geom(q.lx, q.ly).nstrips);
-        rc = run_chunk_backward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_ly,
-                                   max_strips, (char*)ws, L, gK + c.first,
+        rc = run_chunk_backward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                   c.max_ly, max_strips, (char*)ws, L, gK + c.first,
                                    gKexp ? gKexp + c.first : nullptr, st);
         if (rc) return rc;
         ReducePairsArgs<R> ra;

@@ -334,9 +334,12 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
         aQ[k] = (R)0;
     }
     R gacc = (R)0;
+    // T is the same in every lane; reading it into a scalar register makes
+    // the early exit a branch instead of masked execution of every tail row
+    const int Tu = __builtin_amdgcn_readfirstlane(T);
 #pragma unroll
     for (int r = 0; r <= M; ++r) {
-        if (r > N && r - N > T) break;  // wave-uniform
+        if (r > N && r - N > Tu) break;
         R ea, eb;
         if (r <= N) {
             ea = a[r];

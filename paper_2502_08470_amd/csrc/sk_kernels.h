@@ -158,6 +158,91 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     }
 }
 
+// Pair-resident variant: one workgroup (4 waves) per pair stages the pair's
+// increments in LDS once ([lx][dp] and [ly][dp], unrefined; refined rows
+// index i >> lam) and then produces all skewed row blocks of the pair in
+// turn, so the global loads of the increments are paid once per pair instead
+// of once per 64-row block.  Used when both increment arrays fit in LDS.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0) return;
+    const int dp = a.dpad;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* Tt = reinterpret_cast<R*>(sk_smem);  // [64][66]
+    R* Xs = Tt + 64 * 66;                    // [lx][dp]
+    R* Ys = Xs + (size_t)pd.lx * dp;         // [ly][dp]
+    const R* X = a.X + pd.x_off * a.d;
+    const R* Y = a.Y + pd.y_off * a.d;
+    const R rscale = (R)1 / (R)(1 << a.lam);
+    for (int e = tid; e < pd.lx * dp; e += 256) {
+        const int i = e / dp, k = e - i * dp;
+        Xs[e] = k < a.d ? (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale : (R)0;
+    }
+    for (int e = tid; e < pd.ly * dp; e += 256) {
+        const int j = e / dp, k = e - j * dp;
+        Ys[e] = k < a.d ? (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale : (R)0;
+    }
+    typedef typename SkMfma<R>::acc_t acc_t;
+    const int nblk = g.nsteps_pad / 64;
+    for (int b = 0; b < nblk; ++b) {
+        R val[16];
+        int Le[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            val[q] = (R)0;
+            const int e = tid + 256 * q;
+            Le[q] = 64 * b + (e >> 6) - (e & 63);
+        }
+        const int Lmin = 64 * b - 63, Lmax = 64 * b + 63;
+        const int s_lo = Lmin < 0 ? 0 : Lmin / g.Tp;
+        int s_hi = Lmax / g.Tp;
+        if (s_hi > g.nstrips - 1) s_hi = g.nstrips - 1;
+        for (int s = s_lo; s <= s_hi; ++s) {
+            const int jb = Lmin - s * g.Tp;
+            const int ir = s * 64 + 16 * wave + (lane & 15);
+            const bool rok = ir < g.lx;
+            const R* xrow = Xs + (size_t)(ir >> a.lam) * dp;
+            for (int h = 0; h < 2; ++h) {
+                __syncthreads();  // staging done / previous tile consumed
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    acc_t acc = {0, 0, 0, 0};
+                    const int jr = jb + 64 * h + 16 * ni + (lane & 15);
+                    const bool cok = jr >= 0 && jr < g.ly;
+                    const R* yrow = Ys + (size_t)(cok ? (jr >> a.lam) : 0) * dp;
+                    for (int kk = 0; kk < dp; kk += 4) {
+                        const R av = rok ? xrow[kk + (lane >> 4)] : (R)0;
+                        const R bv = cok ? yrow[kk + (lane >> 4)] : (R)0;
+                        acc = SkMfma<R>::mma(av, bv, acc);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int L = Le[q];
+                    const int r = (tid + 256 * q) & 63;
+                    const int col = L - Lmin - 64 * h;
+                    if (L >= 0 && col >= 0 && col < 64) {
+                        const int ss = L / g.Tp, j = L - ss * g.Tp;
+                        if (ss == s && j < g.ly && s * 64 + r < g.lx) val[q] = Tt[r * 66 + col];
+                    }
+                }
+            }
+        }
+        R* out = a.cskew + pd.c_off + (int64_t)64 * 64 * b;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) out[tid + 256 * q] = val[q];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // (b) forward wavefront sweep of the polynomial schemes
 // ---------------------------------------------------------------------------
@@ -266,14 +351,16 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                 }
                 const int Ec = E > Ein ? E : Ein;
                 const int dp = E - Ec, dq = Ein - Ec;
-                P0 = ldexp(P0, dp);
-                P1 = ldexp(P1, dp);
-                Qin0 = ldexp(Qin0, dq);
-                Qin1 = ldexp(Qin1, dq);
+                if (sk_wave_any(dp != 0 || dq != 0)) {  // rare: skip in the common case
+                    P0 = ldexp(P0, dp);
+                    P1 = ldexp(P1, dp);
+                    Qin0 = ldexp(Qin0, dq);
+                    Qin1 = ldexp(Qin1, dq);
 #pragma unroll
-                for (int n = 2; n <= N; ++n) {
-                    P[n] = sk_ldexp(P[n], dp);
-                    Qin[n] = sk_ldexp(Qin[n], dq);
+                    for (int n = 2; n <= N; ++n) {
+                        P[n] = sk_ldexp(P[n], dp);
+                        Qin[n] = sk_ldexp(Qin[n], dq);
+                    }
                 }
                 E = Ec;
             }
@@ -467,10 +554,12 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                     }
                     const int Ec = E > Ein ? E : Ein;
                     const int dp = E - Ec, dq = Ein - Ec;
+                    if (sk_wave_any(dp != 0 || dq != 0)) {
 #pragma unroll
-                    for (int n = 0; n <= N; ++n) {
-                        P[n] = sk_ldexp(P[n], dp);
-                        Qin[n] = sk_ldexp(Qin[n], dq);
+                        for (int n = 0; n <= N; ++n) {
+                            P[n] = sk_ldexp(P[n], dp);
+                            Qin[n] = sk_ldexp(Qin[n], dq);
+                        }
                     }
                     E = Ec;
                 }
@@ -544,10 +633,15 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 }
             }
             const int Ec = ea > eb ? ea : eb;
+            // vectors tagged SK_ZERO_EXP are zero: only real exponents below
+            // Ec need a shift, which is rare
+            const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
+            if (sk_wave_any(sa || sb)) {
 #pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                ap[n] = sk_ldexp(ap[n], ea - Ec);
-                aq[n] = sk_ldexp(aq[n], eb - Ec);
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = sk_ldexp(ap[n], ea - Ec);
+                    aq[n] = sk_ldexp(aq[n], eb - Ec);
+                }
             }
             R gv;
             sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);

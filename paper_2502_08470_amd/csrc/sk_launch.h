@@ -20,6 +20,10 @@ struct SkLaunch {
     static hipError_t fill(R* p, int64_t n, R v, hipStream_t st);
     static hipError_t fill_u32(unsigned* p, int64_t n, hipStream_t st);
     static hipError_t gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs, hipStream_t st);
+    // pair-resident Gram (all row blocks of a pair in one workgroup); max_lx, max_ly
+    // are unrefined segment counts
+    static hipError_t gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
+                                hipStream_t st);
     static hipError_t sweep(const SweepArgs<R>& a, int N, bool interp, bool ckpt, int64_t npairs,
                             int max_ly, hipStream_t st);
     static hipError_t adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs, int max_ly,
@@ -43,6 +47,9 @@ struct SkLaunch {
         return f > b ? f : b;
     }
     static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
+    static size_t gram_pair_lds(int dpad, int max_lx, int max_ly) {
+        return ((size_t)64 * 66 + (size_t)(max_lx + max_ly) * dpad) * sizeof(R);
+    }
 };
 
 extern template struct SkLaunch<float>;

@@ -38,6 +38,16 @@ hipError_t SkLaunch<R>::gram(const GramArgs<R>& a, int ntau_blocks, int64_t npai
     return hipSuccess;
 }
 
+template <typename R>
+hipError_t SkLaunch<R>::gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
+                                  hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_pair<R>, dim3((unsigned)npairs), dim3(256),
+                       gram_pair_lds(a.dpad, max_lx, max_ly), st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 template <typename R, int N, int TMAX>
 static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int max_ly,
                              hipStream_t st) {
