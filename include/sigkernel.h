@@ -80,6 +80,17 @@ extern "C" {
 #define SK_ALGO_PLAIN 1   /* one launch per pair, one workgroup sweeping the
                              anti-diagonals (FP64, forward only)             */
 
+/* arithmetic of the increment Gram C_ij = <dx_i, dy_j> (MFMA) */
+#define SK_GRAM_NATIVE 0 /* products in the path dtype (FP32 or FP64 16x16x4 MFMA)      */
+#define SK_GRAM_BF16X3 1 /* SK_F32 only: each increment split into three bf16 parts,
+                            the six leading cross products on bf16 MFMA with FP32
+                            accumulation (error at the FP32 level, 2^-24 |dx||dy|) */
+
+/* flags */
+#define SK_SYMMETRIC 1 /* backward of a Gram call whose Y is the same array as X:
+                          dL/dX sums both contributions and is written to gX
+                          (gY is not used and may be NULL)                       */
+
 /* backward operations */
 #define SK_OP_GRAM 0
 #define SK_OP_PAIRS 1
@@ -96,6 +107,8 @@ typedef struct sk_params {
                        schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD          */
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
     int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
+    int32_t gram;   /* SK_GRAM_NATIVE or SK_GRAM_BF16X3 (batched algorithm)           */
+    int32_t flags;  /* 0 or SK_SYMMETRIC                                              */
 } sk_params;
 
 /*
@@ -149,7 +162,9 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
  *                      entries; gX, gY have the shapes of Xcat, Ycat.
  *   gK_exp: optional int32 exponents, seed gK * 2^gK_exp (so that the loss
  *   can be taken through log K when K itself overflows); NULL means 0.
- *   When X and Y are the same tensor the caller sums gX and gY.
+ *   When X and Y are the same array, SK_SYMMETRIC in p->flags (SK_OP_GRAM,
+ *   nx == ny, lx_pts == ly_pts) sums both contributions into gX; without
+ *   it the caller sums gX and gY.
  */
 int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t nx, int64_t lx_pts,
                        const void* Y, const int64_t* y_off, int64_t ny, int64_t ly_pts, int64_t d,
@@ -185,11 +200,12 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
  * The increment Gram matrices of a Gram call: C[((a * ny + b) * lx + i) * ly + j]
  * = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> with lx = lx_pts - 1,
  * ly = ly_pts - 1 (the constants C_ij of the schemes with unit time steps),
- * computed by the same MFMA kernel that feeds the sweeps.  Needs the forward
+ * computed by the 64-row-block MFMA kernel of the sweeps, in p->dtype with
+ * p->gram arithmetic (p->scheme, p->order are not used).  Needs the forward
  * workspace of the same call with scheme SK_POLY_APPROX.
  */
 int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
-                             int64_t ly_pts, int64_t d, int32_t dtype, void* C, void* ws,
+                             int64_t ly_pts, int64_t d, const sk_params* p, void* C, void* ws,
                              size_t ws_bytes, hipStream_t stream);
 
 /*

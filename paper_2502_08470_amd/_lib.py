@@ -16,6 +16,8 @@ SK_FD, SK_POLY_APPROX, SK_POLY_INTERP = 0, 1, 2
 SK_F64, SK_F32 = 0, 1
 SK_ALGO_BATCHED, SK_ALGO_PLAIN = 0, 1
 SK_OP_GRAM, SK_OP_PAIRS = 0, 1
+SK_GRAM_NATIVE, SK_GRAM_BF16X3 = 0, 1
+SK_SYMMETRIC = 1
 
 EXPORTS = (
     "sigkernel_gram_workspace",
@@ -36,7 +38,8 @@ EXPORTS = (
 
 class SkParams(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32)]
+                ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("gram", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class SigKernelError(RuntimeError):
@@ -70,7 +73,7 @@ def lib():
     L.sigkernel_backward.argtypes = [i32, vp, i64p, i64, i64, vp, i64p, i64, i64, i64, pp,
                                      vp, vp, vp, vp, vp, sz, vp]
     L.sigkernel_backward.restype = ctypes.c_int
-    L.sigkernel_cell_constants.argtypes = [vp, i64, i64, vp, i64, i64, i64, i32, vp, vp, sz, vp]
+    L.sigkernel_cell_constants.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, sz, vp]
     L.sigkernel_cell_constants.restype = ctypes.c_int
     L.sigkernel_gram_state_size.argtypes = [i64, i64, i64, i64, i64, pp]
     L.sigkernel_gram_state_size.restype = sz

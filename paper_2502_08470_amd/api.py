@@ -15,9 +15,11 @@ from . import _lib as L
 
 _SCHEMES = {"fd": L.SK_FD, "approx": L.SK_POLY_APPROX, "interp": L.SK_POLY_INTERP}
 _ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN}
+_GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3}
 
 
-def _params(dtype: torch.dtype, scheme: str, order: int, algo: str) -> L.SkParams:
+def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: str = "native",
+            flags: int = 0) -> L.SkParams:
     if dtype == torch.float32:
         dt = L.SK_F32
     elif dtype == torch.float64:
@@ -28,7 +30,9 @@ def _params(dtype: torch.dtype, scheme: str, order: int, algo: str) -> L.SkParam
         raise ValueError(f"scheme must be one of {sorted(_SCHEMES)}")
     if algo not in _ALGOS:
         raise ValueError(f"algo must be one of {sorted(_ALGOS)}")
-    return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo])
+    if gram_mode not in _GRAMS:
+        raise ValueError(f"gram_mode must be one of {sorted(_GRAMS)}")
+    return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo], _GRAMS[gram_mode], int(flags))
 
 
 def _dev(t: torch.Tensor) -> torch.Tensor:
@@ -60,15 +64,16 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 # forward
 # ---------------------------------------------------------------------------
 def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-         algo: str = "batched", return_exp: bool = False):
+         algo: str = "batched", return_exp: bool = False, gram_mode: str = "native"):
     """K[a, b] = k(X[a], Y[b]) for paths X (nx, lx_pts, d), Y (ny, ly_pts, d).
 
     With ``return_exp`` returns (mantissa, exponent) with value
-    mantissa * 2**exponent (exponent int32)."""
+    mantissa * 2**exponent (exponent int32).  ``gram_mode`` "bf16x3"
+    computes the cell constants of float32 paths by bf16 split MFMAs."""
     X, Y = _dev(X), _dev(Y)
     if X.dim() != 3 or Y.dim() != 3 or X.shape[2] != Y.shape[2] or X.dtype != Y.dtype:
         raise ValueError("X and Y must be (n, points, d) with the same d and dtype")
-    p = _params(X.dtype, scheme, order, algo)
+    p = _params(X.dtype, scheme, order, algo, gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     lib = L.lib()
@@ -96,7 +101,7 @@ def _concat(paths: Union[Sequence[torch.Tensor], Tuple[torch.Tensor, Sequence[in
 
 
 def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
-          return_exp: bool = False):
+          return_exp: bool = False, gram_mode: str = "native"):
     """k[i] = k(xs[i], ys[i]) for lists of (points_i, d) tensors of uneven
     lengths, or (concatenated points, offsets) tuples."""
     Xc, xo = _concat(xs)
@@ -105,7 +110,7 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
         raise ValueError("xs and ys must hold the same number of paths")
     npairs = len(xo) - 1
     d = Xc.shape[1]
-    p = _params(Xc.dtype, scheme, order, algo)
+    p = _params(Xc.dtype, scheme, order, algo, gram_mode)
     lib = L.lib()
     k = torch.empty(npairs, dtype=Xc.dtype, device=Xc.device)
     ke = torch.empty(npairs, dtype=torch.int32, device=Xc.device) if return_exp else None
@@ -123,20 +128,24 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
 # backward
 # ---------------------------------------------------------------------------
 def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
-                  order: int = 4, gK_exp: Optional[torch.Tensor] = None):
-    """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order)."""
+                  order: int = 4, gK_exp: Optional[torch.Tensor] = None,
+                  gram_mode: str = "native", symmetric: bool = False):
+    """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order).
+    ``symmetric`` (Y is X): returns (dL/dX with both contributions, None)."""
     X, Y = _dev(X), _dev(Y)
+    if symmetric:
+        Y = X
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, "batched")
+    p = _params(X.dtype, scheme, order, "batched", gram_mode, L.SK_SYMMETRIC if symmetric else 0)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     if gK.shape != (nx, ny):
         raise ValueError("gK must have shape (nx, ny)")
     lib = L.lib()
     gX = torch.empty_like(X)
-    gY = torch.empty_like(Y)
+    gY = None if symmetric else torch.empty_like(Y)
     if nx * ny == 0:
-        return gX.zero_(), gY.zero_()
+        return gX.zero_(), (None if gY is None else gY.zero_())
     ge = _dev(gK_exp.to(torch.int32)) if gK_exp is not None else None
     nb = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 1)
     ws = _workspace(nb, X.device)
@@ -169,26 +178,26 @@ def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int 
     return gX, gY, xo, yo
 
 
-def cell_constants(X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+def cell_constants(X: torch.Tensor, Y: torch.Tensor, gram_mode: str = "native") -> torch.Tensor:
     """C[a, b, i, j] = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> from the
     library's MFMA increment-Gram kernel."""
     X, Y = _dev(X), _dev(Y)
-    p = _params(X.dtype, "approx", 2, "batched")
+    p = _params(X.dtype, "approx", 2, "batched", gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     lib = L.lib()
     C = torch.empty((nx, ny, lxp - 1, lyp - 1), dtype=X.dtype, device=X.device)
     nb = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 0)
     ws = _workspace(nb, X.device)
-    L.check(lib.sigkernel_cell_constants(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, p.dtype, _ptr(C),
-                                         _ptr(ws), nb, _stream(X)))
+    L.check(lib.sigkernel_cell_constants(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
+                                         _ptr(C), _ptr(ws), nb, _stream(X)))
     return C
 
 
 def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
-                    order: int = 4) -> int:
+                    order: int = 4, gram_mode: str = "native") -> int:
     """Bytes of the backward state kept by gram_save for these shapes."""
-    p = _params(X.dtype, scheme, order, "batched")
+    p = _params(X.dtype, scheme, order, "batched", gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     nb = L.lib().sigkernel_gram_state_size(nx, lxp, ny, lyp, d, ctypes.byref(p))
@@ -198,16 +207,16 @@ def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
 
 
 def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-              return_exp: bool = False):
+              return_exp: bool = False, gram_mode: str = "native"):
     """Gram matrix plus the state its backward needs: returns (K, state) or
     (K, K_exp, state).  Pass the state to gram_backward_saved."""
     X, Y = _dev(X), _dev(Y)
-    p = _params(X.dtype, scheme, order, "batched")
+    p = _params(X.dtype, scheme, order, "batched", gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
     Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
-    state = _workspace(gram_state_size(X, Y, scheme, order), X.device)
+    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode), X.device)
     L.check(L.lib().sigkernel_gram_save(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
                                         _ptr(K), _ptr(Ke), _ptr(state), state.numel(),
                                         _stream(X)))
@@ -216,15 +225,18 @@ def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: i
 
 def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
                         state: torch.Tensor, scheme: str = "approx", order: int = 4,
-                        gK_exp: Optional[torch.Tensor] = None):
+                        gK_exp: Optional[torch.Tensor] = None, gram_mode: str = "native",
+                        symmetric: bool = False):
     """Same result as gram_backward, from the state left by gram_save(X, Y)."""
     X, Y = _dev(X), _dev(Y)
+    if symmetric:
+        Y = X
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, "batched")
+    p = _params(X.dtype, scheme, order, "batched", gram_mode, L.SK_SYMMETRIC if symmetric else 0)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     gX = torch.empty_like(X)
-    gY = torch.empty_like(Y)
+    gY = None if symmetric else torch.empty_like(Y)
     ge = _dev(gK_exp.to(torch.int32)) if gK_exp is not None else None
     L.check(L.lib().sigkernel_gram_backward_saved(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d,
                                                   ctypes.byref(p), _ptr(gK), _ptr(ge), _ptr(gX),
@@ -252,38 +264,43 @@ class SigKernelGram(torch.autograd.Function):
     starts from it; otherwise the backward recomputes it in chunks."""
 
     @staticmethod
-    def forward(ctx, X, Y, scheme="approx", order=4):
+    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native"):
         ctx.save_for_backward(X, Y)
-        ctx.scheme, ctx.order = scheme, order
+        ctx.scheme, ctx.order, ctx.gram_mode = scheme, order, gram_mode
+        # the same tensor on both sides: one gradient with both contributions
+        ctx.symmetric = X is Y
         ctx.state = None
         if scheme != "fd" and (X.requires_grad or Y.requires_grad):
-            if gram_state_size(X, Y, scheme, order) <= _state_budget(X.device):
-                K, ctx.state = gram_save(X, Y, scheme, order)
+            if gram_state_size(X, Y, scheme, order, gram_mode) <= _state_budget(X.device):
+                K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode)
                 return K
-        return gram(X, Y, scheme, order)
+        return gram(X, Y, scheme, order, gram_mode=gram_mode)
 
     @staticmethod
     def backward(ctx, gK):
         X, Y = ctx.saved_tensors
+        kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric)
         if ctx.state is not None:
-            gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order)
+            gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
-            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order)
-        return gX, gY, None, None
+            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, **kw)
+        return gX, gY, None, None, None
 
 
-def sig_gram(X, Y, scheme: str = "approx", order: int = 4) -> torch.Tensor:
-    return SigKernelGram.apply(X, Y, scheme, order)
+def sig_gram(X, Y, scheme: str = "approx", order: int = 4,
+             gram_mode: str = "native") -> torch.Tensor:
+    return SigKernelGram.apply(X, Y, scheme, order, gram_mode)
 
 
-def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4) -> torch.Tensor:
+def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
+         gram_mode: str = "native") -> torch.Tensor:
     """Unbiased (U-statistic) squared MMD between path sets X and Y, with the
     within-sample diagonals excluded; differentiable in X and Y."""
     n, m = X.shape[0], Y.shape[0]
-    Kxx = sig_gram(X, X, scheme, order)
-    Kyy = sig_gram(Y, Y, scheme, order)
-    Kxy = sig_gram(X, Y, scheme, order)
+    Kxx = sig_gram(X, X, scheme, order, gram_mode)
+    Kyy = sig_gram(Y, Y, scheme, order, gram_mode)
+    Kxy = sig_gram(X, Y, scheme, order, gram_mode)
     sxx = (Kxx.sum() - torch.diagonal(Kxx).sum()) / (n * (n - 1))
     syy = (Kyy.sum() - torch.diagonal(Kyy).sum()) / (m * (m - 1))
     return sxx + syy - 2.0 * Kxy.mean()

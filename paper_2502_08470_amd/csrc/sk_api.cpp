@@ -191,7 +191,31 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dtype != SK_F64) return fail(SK_EUNSUPPORTED, "the plain algorithm is FP64 only");
         if (backward) return fail(SK_EUNSUPPORTED, "the plain algorithm is forward only");
     }
+    if (p->gram != SK_GRAM_NATIVE && p->gram != SK_GRAM_BF16X3)
+        return fail(SK_EINVAL, "gram mode %d", p->gram);
+    if (p->gram == SK_GRAM_BF16X3 && p->dtype != SK_F32)
+        return fail(SK_EUNSUPPORTED, "the bf16 split Gram is for SK_F32 paths");
+    if (p->gram == SK_GRAM_BF16X3 && p->algo != SK_ALGO_BATCHED)
+        return fail(SK_EUNSUPPORTED, "the bf16 split Gram is a batched-algorithm mode");
+    if (p->flags & ~SK_SYMMETRIC) return fail(SK_EINVAL, "unknown flags 0x%x", p->flags);
     return SK_OK;
+}
+
+// SK_SYMMETRIC: Y is X, so both gradient contributions go to gX (the
+// reductions accumulate, x part then y part, on the same stream).
+int check_symmetric(const sk_params& p, int32_t op, const void* X, int64_t nx, int64_t lx_pts,
+                    const void* Y, int64_t ny, int64_t ly_pts, void* gX, void** gY) {
+    if (!(p.flags & SK_SYMMETRIC)) return SK_OK;
+    if (op != SK_OP_GRAM) return fail(SK_EINVAL, "SK_SYMMETRIC applies to Gram calls");
+    if (X != Y || nx != ny || lx_pts != ly_pts)
+        return fail(SK_EINVAL, "SK_SYMMETRIC needs Y to be the same array as X");
+    *gY = gX;
+    return SK_OK;
+}
+
+// K padding of the increments for the Gram MFMAs: 4 (16x16x4), 16 (bf16 16x16x16)
+int gram_dpad(const sk_params& p, int64_t d) {
+    return p.gram == SK_GRAM_BF16X3 ? (int)((d + 15) / 16 * 16) : (int)((d + 3) / 4 * 4);
 }
 
 int check_dims(int64_t d, bool backward) {
@@ -318,8 +342,8 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
     const int lam = lam_of(p);
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
-    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = lam;
-    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam;
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
     SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
     if (p.scheme == SK_FD) {
         FdArgs<R> fa;
@@ -341,7 +365,7 @@ int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
     SK_TRY_HIP(lds_limit(&lim), "device query");
     size_t need = p.scheme == SK_FD ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
                                     : SkLaunch<R>::sweep_lds(p.order, (int)max_ly);
-    need = std::max(need, SkLaunch<R>::gram_lds((int)((d + 3) / 4 * 4)));
+    need = std::max(need, SkLaunch<R>::gram_lds(gram_dpad(p, d)));
     if (need > lim)
         return fail(SK_EUNSUPPORTED, "paths too long for one workgroup's LDS (%zu > %zu bytes)",
                     need, lim);
@@ -530,8 +554,8 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
-    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4); ga.lam = 0;
-    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = 0;
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
     SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
     SweepArgs<R> sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -904,6 +928,7 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
         if ((rc = check_offsets(x_off, nx, 0, "x")) || (rc = check_offsets(y_off, nx, 0, "y")))
             return rc;
     }
+    if ((rc = check_symmetric(*p, op, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
         if (op == SK_OP_GRAM) {
@@ -973,6 +998,7 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
     if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if ((rc = check_symmetric(*p, SK_OP_GRAM, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !state) return fail(SK_EINVAL, "NULL pointer");
     try {
         if (p->dtype == SK_F32)
@@ -988,10 +1014,12 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
 }
 
 int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
-                             int64_t ly_pts, int64_t d, int32_t dtype, void* C, void* ws,
+                             int64_t ly_pts, int64_t d, const sk_params* pp, void* C, void* ws,
                              size_t ws_bytes, hipStream_t stream) {
     g_last_error.clear();
-    sk_params p = {SK_POLY_APPROX, SK_MIN_POLY_ORDER, dtype, SK_ALGO_BATCHED};
+    if (!pp) return fail(SK_EINVAL, "params is NULL");
+    const int32_t dtype = pp->dtype;
+    sk_params p = {SK_POLY_APPROX, SK_MIN_POLY_ORDER, dtype, SK_ALGO_BATCHED, pp->gram, 0};
     int rc = check_params(&p, false);
     if (!rc) rc = check_dims(d, false);
     if (rc) return rc;
@@ -1013,14 +1041,16 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
         src.ny = ny; src.lx_pts = lx_pts; src.ly_pts = ly_pts; src.stride = per; src.first = first;
         if (dtype == SK_F32) {
             GramArgs<float> ga;
-            ga.X = (const float*)X; ga.Y = (const float*)Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4);
+            ga.X = (const float*)X; ga.Y = (const float*)Y; ga.d = d; ga.dpad = gram_dpad(p, d);
             ga.lam = 0; ga.src = src; ga.cskew = (float*)((char*)ws + L.cskew); ga.maxc = nullptr;
+            ga.split = p.gram == SK_GRAM_BF16X3;
             SK_TRY_HIP(SkLaunch<float>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
             SK_TRY_HIP(SkLaunch<float>::unskew(src, ga.cskew, (float*)C, first, cnt, lx * ly, stream), "unskew");
         } else {
             GramArgs<double> ga;
-            ga.X = (const double*)X; ga.Y = (const double*)Y; ga.d = d; ga.dpad = (int)((d + 3) / 4 * 4);
+            ga.X = (const double*)X; ga.Y = (const double*)Y; ga.d = d; ga.dpad = gram_dpad(p, d);
             ga.lam = 0; ga.src = src; ga.cskew = (double*)((char*)ws + L.cskew); ga.maxc = nullptr;
+            ga.split = 0;
             SK_TRY_HIP(SkLaunch<double>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
             SK_TRY_HIP(SkLaunch<double>::unskew(src, ga.cskew, (double*)C, first, cnt, lx * ly, stream), "unskew");
         }

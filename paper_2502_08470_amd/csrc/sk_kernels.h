@@ -9,6 +9,7 @@
 
 typedef float sk_f4 __attribute__((ext_vector_type(4)));
 typedef double sk_d4 __attribute__((ext_vector_type(4)));
+typedef short sk_s4 __attribute__((ext_vector_type(4)));  // 4 bf16 bit patterns
 
 // ---------------------------------------------------------------------------
 // small utilities
@@ -33,6 +34,7 @@ struct GramArgs {
     SkPairSrc src;
     R* cskew;           // chunk buffer of skewed constants
     unsigned* maxc;     // per chunk-local pair: bits of max |c| (nullable)
+    int32_t split;      // FP32 only: BF16 3-way split products instead of FP32 MFMA
 };
 
 template <typename R> struct SkMfma;
@@ -54,13 +56,75 @@ template <> struct SkMfma<double> {
     static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
+// BF16 3-way split of an FP32 value: x = hi + mid + lo exactly (each part
+// keeps 8 significant bits of what the previous ones left; the two
+// subtractions are exact), as bf16 bit patterns rounded to nearest even.
+__device__ __forceinline__ unsigned sk_bf16_rne(float v) {
+    const unsigned u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+}
+__device__ __forceinline__ void sk_bf16_split(float x, short& h, short& m, short& l) {
+    const unsigned uh = sk_bf16_rne(x);
+    const float r1 = x - __uint_as_float(uh);
+    const unsigned um = sk_bf16_rne(r1);
+    const float r2 = r1 - __uint_as_float(um);
+    const unsigned ul = sk_bf16_rne(r2);
+    h = (short)(uh >> 16);
+    m = (short)(um >> 16);
+    l = (short)(ul >> 16);
+}
+
+// One 16x16 tile of the increment Gram, D[m][n] = sum_k a_m[k] b_n[k] over
+// k < dp, where this lane's row pointer `arow` is a_(lane%16) and `brow` is
+// b_(lane%16) (rows flagged not ok read as zero).
+//  SPLIT = false: 16x16x4 MFMA in R (lane supplies k = kk + lane/16).
+//  SPLIT = true (FP32 only, dp a multiple of 16): each operand split into
+//   three bf16 parts and the six products hi*hi, hi*mid, mid*hi, mid*mid,
+//   hi*lo, lo*hi accumulated in FP32 by 16x16x16 bf16 MFMAs, smallest
+//   first (lane supplies k = kk + 4 (lane/16) + j, j < 4).  The dropped
+//   products are below 2^-24 of |a||b|, the FP32 level.
+template <typename R, bool SPLIT>
+__device__ __forceinline__ typename SkMfma<R>::acc_t sk_gram_tile(const R* arow, bool aok,
+                                                                  const R* brow, bool bok, int dp,
+                                                                  int lane) {
+    typename SkMfma<R>::acc_t acc = {0, 0, 0, 0};
+    if constexpr (!SPLIT) {
+        for (int kk = 0; kk < dp; kk += 4) {
+            const R av = aok ? arow[kk + (lane >> 4)] : (R)0;
+            const R bv = bok ? brow[kk + (lane >> 4)] : (R)0;
+            acc = SkMfma<R>::mma(av, bv, acc);
+        }
+    } else {
+        static_assert(sizeof(R) == 4, "the split Gram is an FP32 mode");
+        for (int kk = 0; kk < dp; kk += 16) {
+            sk_s4 ah, am, al, bh, bm, bl;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = kk + 4 * (lane >> 4) + j;
+                short h, m, l;
+                sk_bf16_split(aok ? (float)arow[k] : 0.0f, h, m, l);
+                ah[j] = h; am[j] = m; al[j] = l;
+                sk_bf16_split(bok ? (float)brow[k] : 0.0f, h, m, l);
+                bh[j] = h; bm[j] = m; bl[j] = l;
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
 // One workgroup (4 waves) writes skewed rows [64 b, 64 b + 64) of one pair.
 // For every strip s that owns one of those cells it stages the 64 x-rows of
 // the strip and the 128 y-columns the rows can touch, multiplies them with
 // 16x16x4 MFMAs (K = d) into an LDS tile, 64 columns at a time, and gathers
 // each skewed element from the tile.  Rows are written once, whole,
 // coalesced.
-template <typename R>
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -120,13 +184,10 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
             // wave w: rows 16w..16w+15 against columns 64h..64h+63
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni) {
-                acc_t acc = {0, 0, 0, 0};
                 const int col0 = 64 * h + 16 * ni;
-                for (int kk = 0; kk < dp; kk += 4) {
-                    R av = Xs[(16 * wave + (lane & 15)) * dp + kk + (lane >> 4)];
-                    R bv = Ys[(col0 + (lane & 15)) * dp + kk + (lane >> 4)];
-                    acc = SkMfma<R>::mma(av, bv, acc);
-                }
+                const acc_t acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * dp, true,
+                                                         Ys + (col0 + (lane & 15)) * dp, true, dp,
+                                                         lane);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];
@@ -163,7 +224,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
 // index i >> lam) and then produces all skewed row blocks of the pair in
 // turn, so the global loads of the increments are paid once per pair instead
 // of once per 64-row block.  Used when both increment arrays fit in LDS.
-template <typename R>
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -211,15 +272,10 @@ __global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
                 __syncthreads();  // staging done / previous tile consumed
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) {
-                    acc_t acc = {0, 0, 0, 0};
                     const int jr = jb + 64 * h + 16 * ni + (lane & 15);
                     const bool cok = jr >= 0 && jr < g.ly;
                     const R* yrow = Ys + (size_t)(cok ? (jr >> a.lam) : 0) * dp;
-                    for (int kk = 0; kk < dp; kk += 4) {
-                        const R av = rok ? xrow[kk + (lane >> 4)] : (R)0;
-                        const R bv = cok ? yrow[kk + (lane >> 4)] : (R)0;
-                        acc = SkMfma<R>::mma(av, bv, acc);
-                    }
+                    const acc_t acc = sk_gram_tile<R, SPLIT>(xrow, rok, yrow, cok, dp, lane);
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
                         Tt[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];

@@ -32,8 +32,16 @@ template <typename R>
 hipError_t SkLaunch<R>::gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs,
                              hipStream_t st) {
     if (npairs <= 0 || ntau_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram_skew<R>, dim3((unsigned)npairs, ntau_blocks), dim3(256),
-                       gram_lds(a.dpad), st, a);
+    if (a.split) {
+        if constexpr (sizeof(R) == 4)
+            hipLaunchKernelGGL((k_gram_skew<R, true>), dim3((unsigned)npairs, ntau_blocks),
+                               dim3(256), gram_lds(a.dpad), st, a);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_gram_skew<R, false>), dim3((unsigned)npairs, ntau_blocks), dim3(256),
+                           gram_lds(a.dpad), st, a);
+    }
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -42,8 +50,15 @@ template <typename R>
 hipError_t SkLaunch<R>::gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
                                   hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram_pair<R>, dim3((unsigned)npairs), dim3(256),
-                       gram_pair_lds(a.dpad, max_lx, max_ly), st, a);
+    const size_t lds = gram_pair_lds(a.dpad, max_lx, max_ly);
+    if (a.split) {
+        if constexpr (sizeof(R) == 4)
+            hipLaunchKernelGGL((k_gram_pair<R, true>), dim3((unsigned)npairs), dim3(256), lds, st, a);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_gram_pair<R, false>), dim3((unsigned)npairs), dim3(256), lds, st, a);
+    }
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -29,8 +29,8 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(L.EXPORTS)
 
 
-def P(scheme=1, order=4, dtype=1, algo=0):
-    return ctypes.byref(L.SkParams(scheme, order, dtype, algo))
+def P(scheme=1, order=4, dtype=1, algo=0, gram=0, flags=0):
+    return ctypes.byref(L.SkParams(scheme, order, dtype, algo, gram, flags))
 
 
 def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
@@ -56,6 +56,9 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=P(), ws=0), L.SK_EINVAL),
     (dict(p=P(), wsb=16), L.SK_EWORKSPACE),
     (dict(p=None), L.SK_EINVAL),
+    (dict(p=P(gram=2)), L.SK_EINVAL),
+    (dict(p=P(gram=1, dtype=0)), L.SK_EUNSUPPORTED),
+    (dict(p=P(flags=2)), L.SK_EINVAL),
 ])
 def test_gram_argument_errors(args, code):
     assert gram(**args) == code
@@ -76,6 +79,14 @@ def test_backward_rejections():
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL
+    # SK_SYMMETRIC needs a Gram call whose Y is X (same pointer and shape)
+    def bwd_sym(op=0, X=1, Y=1, ny=2):
+        return lib.sigkernel_backward(op, vp(X), None, 2, 10, vp(Y), None, ny, 10, 3,
+                                      P(flags=L.SK_SYMMETRIC), vp(1), None, vp(1), None, vp(1),
+                                      1 << 30, None)
+    assert bwd_sym(Y=2) == L.SK_EINVAL
+    assert bwd_sym(ny=3) == L.SK_EINVAL
+    assert bwd_sym(op=1) == L.SK_EINVAL
 
 
 def test_pairs_offset_validation():

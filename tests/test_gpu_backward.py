@@ -181,3 +181,34 @@ def test_saved_state_backward_matches_recompute(sk, dtype):
     tol = 1e-12 if dtype == torch.float64 else 1e-6
     torch.testing.assert_close(Xg.grad, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
     torch.testing.assert_close(Yg.grad, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_symmetric_gram_backward(sk, dtype, tol):
+    # Y is X: one gradient holding both contributions, equal to gX + gY of
+    # the general call; also through autograd and the saved-state path
+    log_banner(f"symmetric backward {dtype}")
+    rng = np.random.default_rng(41)
+    X = dev(bm_paths(rng, 3, 90, 3, 0.05), dtype)
+    gK = dev(rng.normal(size=(3, 3)), dtype)
+    gX, gY = sk.gram_backward(X, X.clone(), gK, "approx", 5)
+    ref = gX + gY
+    gS, none = sk.gram_backward(X, X, gK, "approx", 5, symmetric=True)
+    assert none is None
+    scale = float(ref.abs().max())
+    torch.testing.assert_close(gS, ref, rtol=tol, atol=tol * scale)
+    Xg = X.clone().requires_grad_(True)
+    (sk.sig_gram(Xg, Xg, "approx", 5) * gK).sum().backward()
+    torch.testing.assert_close(Xg.grad, ref, rtol=tol, atol=tol * scale)
+
+
+def test_bf16x3_backward_matches_native(sk):
+    log_banner("bf16x3 backward")
+    rng = np.random.default_rng(42)
+    X = dev(bm_paths(rng, 2, 130, 16, 0.02), torch.float32)
+    Y = dev(bm_paths(rng, 3, 70, 16, 0.02), torch.float32)
+    gK = dev(rng.normal(size=(2, 3)), torch.float32)
+    gX1, gY1 = sk.gram_backward(X, Y, gK, "approx", 6)
+    gX3, gY3 = sk.gram_backward(X, Y, gK, "approx", 6, gram_mode="bf16x3")
+    for a, b in ((gX1, gX3), (gY1, gY3)):
+        torch.testing.assert_close(b, a, rtol=1e-4, atol=1e-4 * float(a.abs().max()))

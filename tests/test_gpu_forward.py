@@ -32,22 +32,42 @@ def dev(a, dtype):
 # ---------------------------------------------------------------------------
 # increment Gram (MFMA) -- exact up to FP rounding of a length-d dot product
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dtype,mode", [(torch.float64, "native"), (torch.float32, "native"),
+                                        (torch.float32, "bf16x3")])
 @pytest.mark.parametrize("shape", [(2, 65, 3, 130, 4), (3, 7, 2, 200, 9), (1, 150, 1, 64, 33)])
-def test_cell_constants_match_increment_products(sk, dtype, shape):
+def test_cell_constants_match_increment_products(sk, dtype, mode, shape):
     nx, lxp, ny, lyp, d = shape
-    log_banner(f"cell_constants {dtype} {shape}")
+    log_banner(f"cell_constants {dtype} {mode} {shape}")
     rng = np.random.default_rng(1)
     X = rng.normal(size=(nx, lxp, d))
     Y = rng.normal(size=(ny, lyp, d))
     Xt, Yt = dev(X, dtype), dev(Y, dtype)
-    Cg = sk.cell_constants(Xt, Yt).cpu().numpy()
+    Cg = sk.cell_constants(Xt, Yt, gram_mode=mode).cpu().numpy()
     Xr, Yr = Xt.cpu().double().numpy(), Yt.cpu().double().numpy()
     dX, dY = np.diff(Xr, axis=1), np.diff(Yr, axis=1)
     want = np.einsum("aik,bjk->abij", dX, dY)
     scale = np.einsum("aik,bjk->abij", np.abs(dX), np.abs(dY))
-    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    # FP32: increments rounded once each (2 * 2^-24), products and a length-d
+    # accumulation (d * 2^-24); the bf16 split adds the dropped products
+    # mid*lo, lo*mid, lo*lo (< 3 * 2^-24) relative to sum |dx_k dy_k|
+    tol = 1e-13 if dtype == torch.float64 else (d + 8) * 2.0 ** -24
     assert np.all(np.abs(Cg - want) <= tol * scale + 1e-300)
+
+
+def test_bf16x3_gram_matches_oracle_and_fp32(sk):
+    # paths in R^32 scaled so that std(c) = 1 (|c| up to about 5)
+    import workloads as W
+    log_banner("bf16x3 gram")
+    X, Y = W.large_gram(0, n=4, steps=200)
+    Xt, Yt = dev(X, torch.float32), dev(Y, torch.float32)
+    K3, E3 = sk.gram(Xt, Yt, "approx", 8, return_exp=True, gram_mode="bf16x3")
+    K1, E1 = sk.gram(Xt, Yt, "approx", 8, return_exp=True)
+    m, e = oracle_gram(X.astype(np.float64), Y.astype(np.float64), "approx", 8)
+    err3 = rel_err_exp(K3.cpu().numpy(), E3.cpu().numpy(), m, e)
+    err1 = rel_err_exp(K1.cpu().numpy(), E1.cpu().numpy(), m, e)
+    # both within the FP32 conditioning floor of these pairs, and of the same size
+    assert err3.max() < 1e-3 and err1.max() < 1e-3, (err3.max(), err1.max())
+    assert err3.mean() < 3 * err1.mean() + 1e-6, (err3.mean(), err1.mean())
 
 
 # ---------------------------------------------------------------------------

@@ -13,9 +13,10 @@ oracle computes one by one.
   sampled Kxy entries (MAPE <= 1e-6) and dMMD^2/dX on sampled coordinates
   within 1e-5 relative of central differences of the oracle.
 * 1024x1024 Gram (R^32, 1024 steps, unit-variance cell constants,
-  approximation N=8, FP32 with exponents): sampled pairs within 1e-3
-  relative (kernels near 10^350; FP32 rounding amplified by the problem's
-  conditioning, about 2e-5 at this size).
+  approximation N=8, FP32 with exponents, increment Gram by bf16 3-way
+  split MFMAs): sampled pairs within 1e-3 relative (kernels near 10^350;
+  FP32 rounding amplified by the problem's conditioning, about 2e-5 at this
+  size).
 """
 import numpy as np
 import pytest
@@ -128,7 +129,7 @@ def test_large_gram_full_size_sampled(sk):
     X, Y = W.large_gram(0)
     Xt = torch.tensor(X, device="cuda")
     Yt = torch.tensor(Y, device="cuda")
-    K, Ke = sk.gram(Xt, Yt, "approx", 8, return_exp=True)
+    K, Ke = sk.gram(Xt, Yt, "approx", 8, return_exp=True, gram_mode="bf16x3")
     K, Ke = K.cpu().numpy(), Ke.cpu().numpy()
     assert np.isfinite(K).all()
     rng = np.random.default_rng(3)
