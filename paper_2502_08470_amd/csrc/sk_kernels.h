@@ -826,27 +826,25 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
             for (int u = 0; u < 8; ++u) {
                 const int tau = t0 + u;
                 const int j = tau - r - s * g.Tp;
+                // lane 0 receives zero (the DPP shift fills it), which starts
+                // the column's sum
 #pragma unroll
                 for (int k = 0; k < DMAX; ++k) accy[k] = lane_from_prev(accy[k]);
-                if (r == 0) {
-#pragma unroll
-                    for (int k = 0; k < DMAX; ++k) accy[k] = (R)0;
-                }
                 const bool ok = rowok && j >= j0 && j < j1 && tau <= tend;
-                if (ok) {
-                    const R gv = gb[u];
-                    const R* yj = ycl + (j - j0) * DMAX;
+                // cells outside the chunk contribute zero (no branch): their
+                // partial sums are never stored
+                const R gv = ok ? gb[u] : (R)0;
+                const R* yj = ycl + (ok ? j - j0 : 0) * DMAX;
 #pragma unroll
-                    for (int k = 0; k < DMAX; ++k) {
-                        accx[k] = fma(gv, yj[k], accx[k]);
-                        accy[k] = fma(gv, xi[k], accy[k]);
-                    }
-                    if (r == last_r) {
-                        R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j) * d;
+                for (int k = 0; k < DMAX; ++k) {
+                    accx[k] = fma(gv, yj[k], accx[k]);
+                    accy[k] = fma(gv, xi[k], accy[k]);
+                }
+                if (ok && r == last_r) {
+                    R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j) * d;
 #pragma unroll
-                        for (int k = 0; k < DMAX; ++k)
-                            if (k < d) dyo[k] = accy[k];
-                    }
+                    for (int k = 0; k < DMAX; ++k)
+                        if (k < d) dyo[k] = accy[k];
                 }
             }
 #pragma unroll
@@ -873,50 +871,82 @@ struct ReduceGramArgs {
     R* gY;
 };
 
+// Both reductions: a workgroup of 256 threads owns 64 consecutive output
+// elements; its four 64-thread groups sum interleaved quarters of the pairs
+// (4x the memory-level parallelism of one thread per element) and combine
+// through LDS.
 template <typename R>
-__global__ void k_reduce_gram_x(const ReduceGramArgs<R> a) {
-    const int64_t lx = a.lx_pts - 1, d = a.d;
-    const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
-    const int64_t per = a.lx_pts * d;
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (a_hi - a_lo + 1) * per) return;
-    const int64_t ai = a_lo + e / per, rem = e % per, t = rem / d, k = rem % d;
-    int64_t p0 = ai * a.ny, p1 = p0 + a.ny;
-    if (p0 < a.first) p0 = a.first;
-    if (p1 > a.first + a.count) p1 = a.first + a.count;
-    R sum = (R)0;
-    for (int64_t p = p0; p < p1; ++p) {
-        const R* dx = a.dxp + (p - a.first) * a.dx_stride;
-        R v = (R)0;
-        if (t > 0) v += dx[(t - 1) * d + k];
-        if (t < lx) v -= dx[t * d + k];
-        sum += v;
-    }
-    a.gX[ai * per + t * d + k] += sum;
+__device__ __forceinline__ R sk_group4_sum(R v, int tid) {
+    __shared__ R part[256];
+    part[tid] = v;
+    __syncthreads();
+    R s = (R)0;
+    if (tid < 64) s = (part[tid] + part[tid + 64]) + (part[tid + 128] + part[tid + 192]);
+    return s;
 }
 
 template <typename R>
-__global__ void k_reduce_gram_y(const ReduceGramArgs<R> a) {
-    const int64_t ly = a.ly_pts - 1, d = a.d;
-    const int64_t per = a.ly_pts * d;
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.ny * per) return;
-    const int64_t bi = e / per, rem = e % per, t = rem / d, k = rem % d;
+__global__ __launch_bounds__(256) void k_reduce_gram_x(const ReduceGramArgs<R> a) {
+    const int tid = threadIdx.x, grp = tid >> 6;
+    const int64_t lx = a.lx_pts - 1, d = a.d;
     const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
+    const int64_t per = a.lx_pts * d;
+    const int64_t e = (int64_t)blockIdx.x * 64 + (tid & 63);
+    const bool live = e < (a_hi - a_lo + 1) * per;
+    int64_t ai = 0, t = 0, k = 0;
     R sum = (R)0;
-    for (int64_t ai = a_lo; ai <= a_hi; ++ai) {
-        const int64_t p = ai * a.ny + bi;
-        if (p < a.first || p >= a.first + a.count) continue;
-        const R* dy = a.dyp + (p - a.first) * a.dy_stride;
-        for (int64_t s = 0; s < a.nstrips; ++s) {
-            const R* dys = dy + s * ly * d;
+    if (live) {
+        ai = a_lo + e / per;
+        const int64_t rem = e % per;
+        t = rem / d;
+        k = rem % d;
+        int64_t p0 = ai * a.ny, p1 = p0 + a.ny;
+        if (p0 < a.first) p0 = a.first;
+        if (p1 > a.first + a.count) p1 = a.first + a.count;
+#pragma unroll 4
+        for (int64_t p = p0 + grp; p < p1; p += 4) {
+            const R* dx = a.dxp + (p - a.first) * a.dx_stride;
             R v = (R)0;
-            if (t > 0) v += dys[(t - 1) * d + k];
-            if (t < ly) v -= dys[t * d + k];
+            if (t > 0) v += dx[(t - 1) * d + k];
+            if (t < lx) v -= dx[t * d + k];
             sum += v;
         }
     }
-    a.gY[bi * per + t * d + k] += sum;
+    sum = sk_group4_sum(sum, tid);
+    if (live && tid < 64) a.gX[ai * per + t * d + k] += sum;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce_gram_y(const ReduceGramArgs<R> a) {
+    const int tid = threadIdx.x, grp = tid >> 6;
+    const int64_t ly = a.ly_pts - 1, d = a.d;
+    const int64_t per = a.ly_pts * d;
+    const int64_t e = (int64_t)blockIdx.x * 64 + (tid & 63);
+    const bool live = e < a.ny * per;
+    int64_t bi = 0, t = 0, k = 0;
+    R sum = (R)0;
+    if (live) {
+        bi = e / per;
+        const int64_t rem = e % per;
+        t = rem / d;
+        k = rem % d;
+        const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
+        for (int64_t ai = a_lo + grp; ai <= a_hi; ai += 4) {
+            const int64_t p = ai * a.ny + bi;
+            if (p < a.first || p >= a.first + a.count) continue;
+            const R* dy = a.dyp + (p - a.first) * a.dy_stride;
+#pragma unroll 4
+            for (int64_t s = 0; s < a.nstrips; ++s) {
+                const R* dys = dy + s * ly * d;
+                R v = (R)0;
+                if (t > 0) v += dys[(t - 1) * d + k];
+                if (t < ly) v -= dys[t * d + k];
+                sum += v;
+            }
+        }
+    }
+    sum = sk_group4_sum(sum, tid);
+    if (live && tid < 64) a.gY[bi * per + t * d + k] += sum;
 }
 
 // List mode: every pair owns its own x and y points.

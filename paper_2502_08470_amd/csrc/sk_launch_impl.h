@@ -162,9 +162,9 @@ hipError_t SkLaunch<R>::reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st) 
     const int64_t a_lo = a.first / a.ny, a_hi = (a.first + a.count - 1) / a.ny;
     int64_t nx_e = (a_hi - a_lo + 1) * a.lx_pts * a.d;
     int64_t ny_e = a.ny * a.ly_pts * a.d;
-    hipLaunchKernelGGL(k_reduce_gram_x<R>, dim3((unsigned)((nx_e + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_gram_x<R>, dim3((unsigned)((nx_e + 63) / 64)), dim3(256), 0, st, a);
     SK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_reduce_gram_y<R>, dim3((unsigned)((ny_e + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_gram_y<R>, dim3((unsigned)((ny_e + 63) / 64)), dim3(256), 0, st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
