@@ -29,7 +29,7 @@
  *     SK_F64: double).
  *   - Calls are asynchronous and ordered on `stream`, except that
  *     sigkernel_pairs / sigkernel_backward(SK_OP_PAIRS) synchronise `stream`
- *     once per chunk to upload per-pair descriptors.
+ *     once to upload per-pair descriptors (plans avoid even that).
  *   - No call allocates device memory: the caller passes a workspace `ws` of
  *     `ws_bytes` bytes (size it with sigkernel_*_workspace).  A smaller
  *     workspace is accepted as long as it holds one pair: work is then done
@@ -170,6 +170,54 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
                        const void* Y, const int64_t* y_off, int64_t ny, int64_t ly_pts, int64_t d,
                        const sk_params* p, const void* gK, const int32_t* gK_exp, void* gX,
                        void* gY, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Plans for repeated pairs calls over fixed offsets (the ragged batching of
+ * many independent pairs).  A plan fixes on the host: the launch order of
+ * the pairs (longest first by wavefront steps, or as given), whether each
+ * pair is computed transposed (k(x, y) = k(y, x) holds for every scheme, so
+ * the shorter path can take the role whose edges are held in LDS), the
+ * grouping of pairs into launches by the LDS size their sweep needs, the
+ * chunking for a given workspace size and the workspace layout.
+ * sigkernel_plan_upload copies the per-pair descriptors into the workspace
+ * once (it synchronises `stream`); afterwards sigkernel_plan_forward and
+ * sigkernel_plan_backward only queue kernels, with no host synchronisation,
+ * copy or allocation, so they may be captured into a HIP graph and replayed
+ * (the workspace and every buffer must then stay where they were).
+ *   x_off, y_off: HOST offsets as for sigkernel_pairs (copied into the plan).
+ *   backward != 0: the plan also serves sigkernel_plan_backward.
+ *   ws_bytes: size of the workspace the plan will run with (chunks are sized
+ *   to it); 0 lets sigkernel_plan_workspace report the size for one chunk
+ *   per LDS class (capped at a few GiB).
+ * sigkernel_plan_tune times every configuration of the forward on the given
+ * inputs (three runs each, device time), keeps the fastest in the plan,
+ * uploads it, and remembers it for plans and one-shot sigkernel_pairs /
+ * sigkernel_backward calls of the same shape in this process (shape = params,
+ * d and the sequence of path lengths).  best_ms (nullable) receives its time.
+ * sigkernel_plan_config reports the configuration in use and the number of
+ * launches (chunks) of one forward; sigkernel_plan_configure sets it by hand
+ * (each flag 0 or 1; the plan must be uploaded again).  The caller owns the plan and destroys
+ * it with sigkernel_plan_destroy; a plan may be used from one thread at a
+ * time.  Errors: as for sigkernel_pairs; SK_EINVAL for a plan that was not
+ * uploaded to this workspace, or a backward on a forward-only plan.
+ */
+typedef struct sk_plan sk_plan;
+int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t npairs, int64_t d,
+                          const sk_params* p, int32_t backward, size_t ws_bytes, sk_plan** plan);
+size_t sigkernel_plan_workspace(const sk_plan* plan);
+int sigkernel_plan_upload(sk_plan* plan, void* ws, size_t ws_bytes, hipStream_t stream);
+int sigkernel_plan_forward(const sk_plan* plan, const void* Xcat, const void* Ycat, void* k,
+                           int32_t* k_exp, void* ws, size_t ws_bytes, hipStream_t stream);
+int sigkernel_plan_backward(const sk_plan* plan, const void* Xcat, const void* Ycat,
+                            const void* gk, const int32_t* gk_exp, void* gX, void* gY, void* ws,
+                            size_t ws_bytes, hipStream_t stream);
+int sigkernel_plan_tune(sk_plan* plan, const void* Xcat, const void* Ycat, void* ws,
+                        size_t ws_bytes, hipStream_t stream, double* best_ms);
+int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, int32_t* buckets,
+                          int64_t* launches);
+int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,
+                             size_t ws_bytes);
+void sigkernel_plan_destroy(sk_plan* plan);
 
 /*
  * Forward and backward of a Gram call with the backward's state kept in

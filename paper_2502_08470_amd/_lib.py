@@ -33,6 +33,15 @@ EXPORTS = (
     "sigkernel_last_error",
     "sigkernel_profile_enable",
     "sigkernel_profile_read",
+    "sigkernel_plan_create",
+    "sigkernel_plan_workspace",
+    "sigkernel_plan_upload",
+    "sigkernel_plan_forward",
+    "sigkernel_plan_backward",
+    "sigkernel_plan_tune",
+    "sigkernel_plan_config",
+    "sigkernel_plan_configure",
+    "sigkernel_plan_destroy",
 )
 
 
@@ -82,6 +91,26 @@ def lib():
     L.sigkernel_gram_backward_saved.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp,
                                                 vp, vp, sz, vp]
     L.sigkernel_gram_backward_saved.restype = ctypes.c_int
+    L.sigkernel_plan_create.argtypes = [i64p, i64p, i64, i64, pp, i32, sz,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+    L.sigkernel_plan_create.restype = ctypes.c_int
+    L.sigkernel_plan_workspace.argtypes = [vp]
+    L.sigkernel_plan_workspace.restype = sz
+    L.sigkernel_plan_upload.argtypes = [vp, vp, sz, vp]
+    L.sigkernel_plan_upload.restype = ctypes.c_int
+    L.sigkernel_plan_forward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sigkernel_plan_forward.restype = ctypes.c_int
+    L.sigkernel_plan_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sigkernel_plan_backward.restype = ctypes.c_int
+    L.sigkernel_plan_tune.argtypes = [vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
+    L.sigkernel_plan_tune.restype = ctypes.c_int
+    L.sigkernel_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.sigkernel_plan_config.restype = ctypes.c_int
+    L.sigkernel_plan_configure.argtypes = [vp, i32, i32, i32, sz]
+    L.sigkernel_plan_configure.restype = ctypes.c_int
+    L.sigkernel_plan_destroy.argtypes = [vp]
+    L.sigkernel_plan_destroy.restype = None
     L.sigkernel_error_string.argtypes = [ctypes.c_int]
     L.sigkernel_error_string.restype = ctypes.c_char_p
     L.sigkernel_last_error.argtypes = []

@@ -246,6 +246,87 @@ def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
 
 
 # ---------------------------------------------------------------------------
+# plans: repeated pairs calls, capturable in a HIP graph
+# ---------------------------------------------------------------------------
+class PairsPlan:
+    """A plan for pairs calls over fixed path lengths (sigkernel_plan_*).
+
+    ``xs``/``ys`` as for :func:`pairs` (only the lengths, dtype and device are
+    taken from them).  The plan owns its workspace; after construction,
+    :meth:`forward` and :meth:`backward` only launch kernels on the current
+    stream, so they can be captured with ``torch.cuda.graph`` and replayed
+    (outputs are written into the tensors passed in)."""
+
+    def __init__(self, xs, ys, scheme: str = "approx", order: int = 4, backward: bool = False,
+                 gram_mode: str = "native"):
+        Xc, xo = _concat(xs)
+        Yc, yo = _concat(ys)
+        if len(xo) != len(yo):
+            raise ValueError("xs and ys must hold the same number of paths")
+        self.npairs, self.d = len(xo) - 1, int(Xc.shape[1])
+        self.dtype, self.device = Xc.dtype, Xc.device
+        self.x_off, self.y_off = xo, yo
+        self._p = _params(Xc.dtype, scheme, order, "batched", gram_mode)
+        self._lib = L.lib()
+        h = ctypes.c_void_p(0)
+        L.check(self._lib.sigkernel_plan_create(_i64arr(xo), _i64arr(yo), self.npairs, self.d,
+                                                ctypes.byref(self._p), 1 if backward else 0, 0,
+                                                ctypes.byref(h)))
+        self._h = h
+        nb = self._lib.sigkernel_plan_workspace(self._h)
+        self.ws = _workspace(nb, self.device)
+        self._upload()
+
+    def _upload(self):
+        L.check(self._lib.sigkernel_plan_upload(self._h, _ptr(self.ws), self.ws.numel(),
+                                                _stream(self.ws)))
+
+    def tune(self, Xcat: torch.Tensor, Ycat: torch.Tensor) -> float:
+        """Time every configuration on these inputs and keep the fastest;
+        returns its forward time in ms."""
+        ms = ctypes.c_double(0.0)
+        L.check(self._lib.sigkernel_plan_tune(self._h, _ptr(_dev(Xcat)), _ptr(_dev(Ycat)),
+                                              _ptr(self.ws), self.ws.numel(), _stream(self.ws),
+                                              ctypes.byref(ms)))
+        return ms.value
+
+    def config(self) -> dict:
+        o, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        n = ctypes.c_int64()
+        L.check(self._lib.sigkernel_plan_config(self._h, ctypes.byref(o), ctypes.byref(w),
+                                                ctypes.byref(b), ctypes.byref(n)))
+        return {"longest_first": bool(o.value), "transpose": bool(w.value),
+                "lds_classes": bool(b.value), "launches": int(n.value)}
+
+    def configure(self, longest_first: bool, transpose: bool, lds_classes: bool):
+        """Set the configuration by hand (rebuilds and uploads the plan)."""
+        L.check(self._lib.sigkernel_plan_configure(self._h, int(longest_first), int(transpose),
+                                                   int(lds_classes), self.ws.numel()))
+        self._upload()
+
+    def forward(self, Xcat: torch.Tensor, Ycat: torch.Tensor, k: torch.Tensor,
+                k_exp: Optional[torch.Tensor] = None) -> torch.Tensor:
+        L.check(self._lib.sigkernel_plan_forward(self._h, _ptr(Xcat), _ptr(Ycat), _ptr(k),
+                                                 _ptr(k_exp), _ptr(self.ws), self.ws.numel(),
+                                                 _stream(Xcat)))
+        return k
+
+    def backward(self, Xcat: torch.Tensor, Ycat: torch.Tensor, gk: torch.Tensor,
+                 gX: torch.Tensor, gY: torch.Tensor, gk_exp: Optional[torch.Tensor] = None):
+        L.check(self._lib.sigkernel_plan_backward(self._h, _ptr(Xcat), _ptr(Ycat), _ptr(gk),
+                                                  _ptr(gk_exp), _ptr(gX), _ptr(gY),
+                                                  _ptr(self.ws), self.ws.numel(),
+                                                  _stream(Xcat)))
+        return gX, gY
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.sigkernel_plan_destroy(h)
+            self._h = None
+
+
+# ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
 def _state_budget(device) -> int:

@@ -424,122 +424,6 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
     return SK_OK;
 }
 
-// List mode planning: greedy chunks by bytes.
-struct ListChunk {
-    int64_t first, count;
-    SkPairSizes tot;
-    int max_nsteps_pad, max_lx, max_ly;
-    int64_t max_pts;
-};
-
-int plan_pairs(const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
-               const sk_params& p, bool backward, size_t wsb, std::vector<ListChunk>& out,
-               size_t* need_all) {
-    const int lam = lam_of(p);
-    const size_t es = esize(p);
-    ListChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0};
-    size_t max_one = 0;
-    for (int64_t i = 0; i < npairs; ++i) {
-        const int lx = (int)(xo[i + 1] - xo[i] - 1), ly = (int)(yo[i + 1] - yo[i] - 1);
-        const SkPairSizes z = sk_pair_sizes(lx, ly, lam, p.order, ckpt_stride(p), d, backward);
-        const SkGeom g = sk_make_geom(lx << lam, ly << lam);
-        ListChunk nxt = cur;
-        nxt.count += 1;
-        nxt.tot = add(cur.tot, z);
-        nxt.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
-        nxt.max_lx = std::max(cur.max_lx, lx);
-        nxt.max_ly = std::max(cur.max_ly, ly);
-        nxt.max_pts = std::max<int64_t>(cur.max_pts, std::max(lx, ly) + 1);
-        const size_t bytes = (size_t)layout_for(nxt.tot, nxt.count, es, backward, true, p.order).total;
-        max_one = std::max(max_one, (size_t)layout_for(z, 1, es, backward, true, p.order).total);
-        if (bytes > wsb && cur.count > 0) {
-            out.push_back(cur);
-            cur = {i, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0};
-            --i;
-            continue;
-        }
-        cur = nxt;
-    }
-    if (cur.count > 0) out.push_back(cur);
-    if (need_all) *need_all = max_one;
-    return SK_OK;
-}
-
-std::vector<SkPairDesc> make_desc(const int64_t* xo, const int64_t* yo, const ListChunk& c,
-                                  const sk_params& p, int64_t d, bool backward) {
-    std::vector<SkPairDesc> v(c.count);
-    SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
-    const int lam = lam_of(p);
-    for (int64_t k = 0; k < c.count; ++k) {
-        const int64_t i = c.first + k;
-        SkPairDesc& q = v[k];
-        q.x_off = xo[i];
-        q.y_off = yo[i];
-        q.lx = (int32_t)(xo[i + 1] - xo[i] - 1);
-        q.ly = (int32_t)(yo[i + 1] - yo[i] - 1);
-        q.k_idx = i;
-        q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
-        q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
-        run = add(run, sk_pair_sizes(q.lx, q.ly, lam, p.order, ckpt_stride(p), d, backward));
-    }
-    return v;
-}
-
-template <typename R>
-int pairs_forward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
-                  int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
-                  hipStream_t st) {
-    if (npairs == 0) return SK_OK;
-    const int lam = lam_of(p);
-    if (p.algo == SK_ALGO_PLAIN) {
-        PlainArgs<R> pa;
-        std::memset(&pa, 0, sizeof(pa));
-        pa.d = d; pa.lam = lam; pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
-        pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
-        for (int64_t i = 0; i < npairs; ++i) {
-            const int64_t lx = xo[i + 1] - xo[i] - 1, ly = yo[i + 1] - yo[i] - 1;
-            const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
-            if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
-            pa.x = Xc + xo[i] * d; pa.y = Yc + yo[i] * d; pa.lx = (int)lx; pa.ly = (int)ly;
-            pa.k_idx = i;
-            if (lx == 0 || ly == 0) {
-                SK_TRY_HIP(SkLaunch<R>::fill(K + i, 1, (R)1, st), "fill");
-                if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + i), 1, st), "fill");
-                continue;
-            }
-            if (p.scheme == SK_FD)
-                SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
-            else
-                SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
-                          "plain polynomial sweep");
-        }
-        return SK_OK;
-    }
-    std::vector<ListChunk> chunks;
-    size_t need_one = 0;
-    plan_pairs(xo, yo, npairs, d, p, false, wsb, chunks, &need_one);
-    if (need_one > wsb) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
-    int max_ly = 0;
-    for (auto& c : chunks) max_ly = std::max(max_ly, c.max_ly);
-    int rc = check_lds<R>(p, max_ly, d);
-    if (rc) return rc;
-    for (const ListChunk& c : chunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), false, true, p.order);
-        std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, false);
-        SkPairDesc* ddesc = reinterpret_cast<SkPairDesc*>((char*)ws + L.desc);
-        SK_TRY_HIP(hipMemcpyAsync(ddesc, desc.data(), desc.size() * sizeof(SkPairDesc),
-                                  hipMemcpyHostToDevice, st), "descriptor upload");
-        SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
-        SkPairSrc src;
-        std::memset(&src, 0, sizeof(src));
-        src.desc = ddesc;
-        rc = run_chunk_forward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                  c.max_ly, (char*)ws, L, K, Kexp, st);
-        if (rc) return rc;
-    }
-    return SK_OK;
-}
-
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
@@ -722,51 +606,375 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
     return SK_OK;
 }
 
-template <typename R>
-int pairs_backward(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
-                   int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX, R* gY,
-                   void* ws, size_t wsb, hipStream_t st) {
-    if (npairs == 0) return SK_OK;
-    std::vector<ListChunk> chunks;
-    size_t need_one = 0;
-    plan_pairs(xo, yo, npairs, d, p, true, wsb, chunks, &need_one);
-    if (need_one > wsb) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
-    int max_ly = 0;
-    for (auto& c : chunks) max_ly = std::max(max_ly, c.max_ly);
-    int rc = check_lds<R>(p, max_ly, d);
+// ---------------------------------------------------------------------------
+// pair plans (independent pairs of uneven lengths)
+// ---------------------------------------------------------------------------
+// A plan fixes, for one set of offsets: the order in which pairs are
+// launched, whether each pair is transposed (k(x, y) = k(y, x), so the
+// shorter path can be the one whose edges wait in LDS), how pairs are grouped
+// into launches, and the workspace layout.  All descriptors are uploaded
+// once, so running a plan only launches kernels.
+struct PlanCfg {
+    int32_t order;    // 1: longest pairs first (by wavefront steps); 0: given order
+    int32_t swap;     // 1: transpose pairs whose second path is longer
+    int32_t buckets;  // 1: separate launches per LDS class of the sweep
+};
+
+struct PlanChunk {
+    int64_t first, count;  // range of the plan's descriptor array
+    SkPairSizes tot;
+    int max_nsteps_pad, max_lx, max_ly, max_strips;
+    int64_t max_pts;
+};
+
+struct PlanImpl {
+    sk_params p;
+    int64_t npairs = 0, d = 0;
+    bool backward = false;
+    std::vector<int64_t> xo, yo;
+    PlanCfg cfg = {1, 1, 1};
+    std::vector<SkPairDesc> desc;
+    std::vector<PlanChunk> chunks;
+    int max_ly = 0;  // longest column count of any pair (LDS check)
+    // workspace regions (bytes): descriptors, kernel-value scratch, chunk scratch
+    int64_t desc_off = 0, kbuf_off = 0, kexp_off = 0, scratch_off = 0, total = 0;
+    const void* uploaded = nullptr;
+};
+
+size_t sweep_lds_bytes(const sk_params& p, int ly) {
+    if (p.scheme == SK_FD) return (size_t)(ly << lam_of(p)) * esize(p);
+    return p.dtype == SK_F32 ? SkLaunch<float>::sweep_lds(p.order, ly)
+                             : SkLaunch<double>::sweep_lds(p.order, ly);
+}
+
+int lds_class(const sk_params& p, int ly) {
+    const size_t b = sweep_lds_bytes(p, ly);
+    return b <= (16u << 10) ? 0 : b <= (32u << 10) ? 1 : b <= (64u << 10) ? 2 : 3;
+}
+
+// Build descriptors and chunks for `cfg`, with chunk scratch sized to fit a
+// workspace of ws_bytes (SIZE_MAX: the default chunk cap).
+int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes);
+
+// Transactional: the plan is left unchanged when the build fails.
+int plan_build(PlanImpl& P0, const PlanCfg& cfg, size_t ws_bytes) {
+    PlanImpl P = P0;
+    const int rc = plan_build_into(P, cfg, ws_bytes);
+    if (rc == SK_OK) P0 = std::move(P);
+    return rc;
+}
+
+int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
+    const sk_params& p = P.p;
+    const int lam = lam_of(p);
+    const size_t es = esize(p);
+    const int64_t n = P.npairs;
+    P.cfg = cfg;
+    P.uploaded = nullptr;
+    std::vector<int32_t> ex(n), ey(n), sw(n), cls(n);
+    std::vector<int64_t> cost(n), seq(n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int lx = (int)(P.xo[i + 1] - P.xo[i] - 1), ly = (int)(P.yo[i + 1] - P.yo[i] - 1);
+        sw[i] = (cfg.swap && ly > lx) ? 1 : 0;
+        ex[i] = sw[i] ? ly : lx;
+        ey[i] = sw[i] ? lx : ly;
+        cost[i] = sk_make_geom(ex[i] << lam, ey[i] << lam).nsteps;
+        cls[i] = cfg.buckets ? lds_class(p, ey[i]) : 0;
+        seq[i] = i;
+    }
+    std::stable_sort(seq.begin(), seq.end(), [&](int64_t u, int64_t v) {
+        if (cls[u] != cls[v]) return cls[u] > cls[v];
+        return cfg.order ? cost[u] > cost[v] : false;
+    });
+    P.desc_off = 0;
+    P.kbuf_off = align_up(n * (int64_t)sizeof(SkPairDesc));
+    P.kexp_off = P.kbuf_off + align_up(n * (int64_t)es);
+    P.scratch_off = P.kexp_off + align_up(n * 4);
+    size_t cap = kDefaultCap;
+    if (ws_bytes != SIZE_MAX) {
+        if (ws_bytes <= (size_t)P.scratch_off)
+            return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
+        cap = ws_bytes - (size_t)P.scratch_off;
+    }
+    P.desc.assign(n, SkPairDesc());
+    P.chunks.clear();
+    P.max_ly = 0;
+    int64_t scratch = 0;
+    PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
+    SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
+    auto close = [&]() {
+        if (cur.count == 0) return;
+        scratch = std::max(scratch, layout_for(cur.tot, cur.count, es, P.backward, false, p.order).total);
+        P.chunks.push_back(cur);
+    };
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = seq[k];
+        const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, P.backward);
+        const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
+        const bool new_class = cur.count > 0 && cfg.buckets && cls[i] != cls[seq[cur.first]];
+        const SkPairSizes t = add(cur.tot, z);
+        const bool too_big = cur.count > 0 &&
+            (size_t)layout_for(t, cur.count + 1, es, P.backward, false, p.order).total > cap;
+        if (new_class || too_big) {
+            close();
+            cur = {k, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
+            run = {0, 0, 0, 0, 0, 0, 0};
+        }
+        if ((size_t)layout_for(z, 1, es, P.backward, false, p.order).total > cap)
+            return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
+        SkPairDesc& q = P.desc[k];
+        q.x_off = sw[i] ? P.yo[i] : P.xo[i];
+        q.y_off = sw[i] ? P.xo[i] : P.yo[i];
+        q.lx = ex[i];
+        q.ly = ey[i];
+        q.swap = sw[i];
+        q.k_idx = i;
+        q.g_idx = i;
+        q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
+        q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
+        run = add(run, z);
+        cur.count += 1;
+        cur.tot = add(cur.tot, z);
+        cur.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
+        cur.max_lx = std::max(cur.max_lx, ex[i]);
+        cur.max_ly = std::max(cur.max_ly, ey[i]);
+        cur.max_strips = std::max(cur.max_strips, g.nstrips);
+        cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
+        P.max_ly = std::max(P.max_ly, ey[i]);
+    }
+    close();
+    P.total = P.scratch_off + std::max<int64_t>(scratch, 256);
+    return SK_OK;
+}
+
+int plan_init(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
+              const sk_params& p, bool backward) {
+    P.p = p;
+    P.npairs = npairs;
+    P.d = d;
+    P.backward = backward;
+    P.xo.assign(xo, xo + npairs + 1);
+    P.yo.assign(yo, yo + npairs + 1);
+    return SK_OK;
+}
+
+// Tuned configurations, keyed by everything that shapes the plan.
+struct TuneKey {
+    sk_params p;
+    int64_t npairs, d;
+    uint64_t lens;  // hash of the (lx, ly) sequence
+    bool operator==(const TuneKey& o) const {
+        return std::memcmp(&p, &o.p, sizeof(p)) == 0 && npairs == o.npairs && d == o.d &&
+               lens == o.lens;
+    }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, PlanCfg>> g_tune_cache;
+
+TuneKey tune_key(const PlanImpl& P) {
+    TuneKey k;
+    std::memset(&k, 0, sizeof(k));
+    k.p = P.p;
+    k.p.flags = 0;
+    k.npairs = P.npairs;
+    k.d = P.d;
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the segment counts
+    for (int64_t i = 0; i < P.npairs; ++i) {
+        uint64_t v = (uint64_t)(P.xo[i + 1] - P.xo[i]) * 1000003ull + (uint64_t)(P.yo[i + 1] - P.yo[i]);
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    }
+    k.lens = h;
+    return k;
+}
+
+bool tuned_cfg(const PlanImpl& P, PlanCfg* cfg) {
+    const TuneKey k = tune_key(P);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& e : g_tune_cache)
+        if (e.first == k) {
+            *cfg = e.second;
+            return true;
+        }
+    return false;
+}
+
+void remember_cfg(const PlanImpl& P, const PlanCfg& cfg) {
+    const TuneKey k = tune_key(P);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (auto& e : g_tune_cache)
+        if (e.first == k) {
+            e.second = cfg;
+            return;
+        }
+    g_tune_cache.push_back({k, cfg});
+}
+
+int plan_check_device(const PlanImpl& P) {
+    if (P.npairs == 0) return SK_OK;
+    return P.p.dtype == SK_F32 ? check_lds<float>(P.p, P.max_ly, P.d)
+                               : check_lds<double>(P.p, P.max_ly, P.d);
+}
+
+int plan_upload(PlanImpl& P, void* ws, size_t wsb, hipStream_t st) {
+    if ((size_t)P.total > wsb)
+        return fail(SK_EWORKSPACE, "plan needs %lld bytes, got %zu", (long long)P.total, wsb);
+    int rc = plan_check_device(P);
     if (rc) return rc;
-    SK_TRY_HIP(SkLaunch<R>::fill(gX, xo[npairs] * d, (R)0, st), "fill");
-    SK_TRY_HIP(SkLaunch<R>::fill(gY, yo[npairs] * d, (R)0, st), "fill");
-    for (const ListChunk& c : chunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, true, p.order);
-        std::vector<SkPairDesc> desc = make_desc(xo, yo, c, p, d, true);
-        // the checkpoint pass writes kernel values by k_idx: route them to the
-        // chunk's scratch slots
-        for (int64_t k = 0; k < c.count; ++k) desc[k].k_idx = k;
-        SkPairDesc* ddesc = reinterpret_cast<SkPairDesc*>((char*)ws + L.desc);
-        SK_TRY_HIP(hipMemcpyAsync(ddesc, desc.data(), desc.size() * sizeof(SkPairDesc),
-                                  hipMemcpyHostToDevice, st), "descriptor upload");
+    if (P.npairs > 0) {
+        SK_TRY_HIP(hipMemcpyAsync((char*)ws + P.desc_off, P.desc.data(),
+                                  P.desc.size() * sizeof(SkPairDesc), hipMemcpyHostToDevice, st),
+                   "descriptor upload");
         SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
+    }
+    P.uploaded = ws;
+    return SK_OK;
+}
+
+int plan_ready(const PlanImpl& P, const void* ws, size_t wsb) {
+    if (!ws) return fail(SK_EINVAL, "NULL workspace");
+    if (P.uploaded != ws) return fail(SK_EINVAL, "plan descriptors were not uploaded to this workspace");
+    if ((size_t)P.total > wsb)
+        return fail(SK_EWORKSPACE, "plan needs %lld bytes, got %zu", (long long)P.total, wsb);
+    return SK_OK;
+}
+
+template <typename R>
+int plan_forward(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kexp, void* ws,
+                 hipStream_t st) {
+    char* base = (char*)ws;
+    for (const PlanChunk& c : P.chunks) {
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), P.backward, false, P.p.order);
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
-        src.desc = ddesc;
-        int max_strips = 0;
-        for (const auto& q : desc) max_strips = std::max(max_strips, sk_make_geom(q.lx, q.ly).nstrips);
-        rc = run_chunk_backward<R>(p, Xc, Yc, d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                   c.max_ly, max_strips, (char*)ws, L, gK + c.first,
-                                   gKexp ? gKexp + c.first : nullptr, st);
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.desc_off) + c.first;
+        int rc = run_chunk_forward<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                      c.max_ly, base + P.scratch_off, L, K, Kexp, st);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
+template <typename R>
+int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, const int32_t* gKexp,
+                  R* gX, R* gY, void* ws, hipStream_t st) {
+    char* base = (char*)ws;
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, P.xo[P.npairs] * P.d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, P.yo[P.npairs] * P.d, (R)0, st), "fill");
+    // kernel values of the checkpoint pass: scratch indexed by k_idx
+    R* kbuf = reinterpret_cast<R*>(base + P.kbuf_off);
+    int32_t* kexp = reinterpret_cast<int32_t*>(base + P.kexp_off);
+    for (const PlanChunk& c : P.chunks) {
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, false, P.p.order);
+        char* ws_c = base + P.scratch_off;
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.desc_off) + c.first;
+        int rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                      c.max_ly, ws_c, L, kbuf, kexp, st);
+        if (rc) return rc;
+        rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.max_strips, ws_c, L,
+                                  gK, gKexp, st);
         if (rc) return rc;
         ReducePairsArgs<R> ra;
-        ra.desc = ddesc; ra.count = c.count; ra.d = d; ra.max_pts = c.max_pts;
-        ra.dxp = reinterpret_cast<const R*>((char*)ws + L.dxp);
-        ra.dyp = reinterpret_cast<const R*>((char*)ws + L.dyp);
+        ra.desc = src.desc; ra.count = c.count; ra.d = P.d; ra.max_pts = c.max_pts;
+        ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
+        ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
         ra.gX = gX; ra.gY = gY;
         SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_pairs(ra, st), "gradient reduction");
     }
     return SK_OK;
 }
 
+// Time every configuration's forward (best of two runs after a warm-up),
+// keep the fastest, remember it for plans of the same shape.
+template <typename R>
+int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipStream_t st,
+              double* best_ms) {
+    hipEvent_t e0, e1;
+    SK_TRY_HIP(hipEventCreate(&e0), "event");
+    SK_TRY_HIP(hipEventCreate(&e1), "event");
+    PlanCfg best = P.cfg;
+    double best_t = -1.0;
+    int rc = SK_OK;
+    for (int o = 0; o < 2 && !rc; ++o)
+        for (int w = 0; w < 2 && !rc; ++w)
+            for (int b = 0; b < 2 && !rc; ++b) {
+                const PlanCfg cfg = {o, w, b};
+                if ((rc = plan_build(P, cfg, wsb)) || (rc = plan_upload(P, ws, wsb, st))) break;
+                R* K = reinterpret_cast<R*>((char*)ws + P.kbuf_off);
+                double t = 1e30;
+                for (int rep = 0; rep < 3 && !rc; ++rep) {
+                    hipError_t he = hipEventRecord(e0, st);
+                    if (he == hipSuccess) rc = plan_forward<R>(P, Xc, Yc, K, nullptr, ws, st);
+                    if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
+                    if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                    if (he != hipSuccess) rc = hip_fail(he, "tuning run");
+                    if (!rc && rep > 0) t = std::min(t, (double)ms);
+                }
+                if (!rc && (best_t < 0 || t < best_t)) {
+                    best_t = t;
+                    best = cfg;
+                }
+            }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = plan_build(P, best, wsb)) || (rc = plan_upload(P, ws, wsb, st))) return rc;
+    remember_cfg(P, best);
+    if (best_ms) *best_ms = best_t;
+    return SK_OK;
+}
+
+// The plain algorithm on a list of pairs: one launch per pair, FP64.
+template <typename R>
+int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
+                int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+                hipStream_t st) {
+    const int lam = lam_of(p);
+    PlainArgs<R> pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.d = d; pa.lam = lam; pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
+    pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int64_t lx = xo[i + 1] - xo[i] - 1, ly = yo[i + 1] - yo[i] - 1;
+        const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
+        if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
+        pa.x = Xc + xo[i] * d; pa.y = Yc + yo[i] * d; pa.lx = (int)lx; pa.ly = (int)ly;
+        pa.k_idx = i;
+        if (lx == 0 || ly == 0) {
+            SK_TRY_HIP(SkLaunch<R>::fill(K + i, 1, (R)1, st), "fill");
+            if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + i), 1, st), "fill");
+            continue;
+        }
+        if (p.scheme == SK_FD)
+            SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
+        else
+            SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+                      "plain polynomial sweep");
+    }
+    return SK_OK;
+}
+
+// One-shot pairs calls: a plan with the tuned configuration of this shape if
+// there is one, else longest-first, transposed and bucketed.
+int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
+                 const sk_params& p, bool backward, size_t wsb) {
+    plan_init(P, xo, yo, npairs, d, p, backward);
+    PlanCfg cfg = {1, 1, 1};
+    tuned_cfg(P, &cfg);
+    return plan_build(P, cfg, wsb);
+}
+
 }  // namespace
+
+struct sk_plan {
+    PlanImpl impl;
+};
 
 // ===========================================================================
 // exported C ABI
@@ -855,13 +1063,14 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
         }
         return (size_t)need;
     }
-    std::vector<ListChunk> chunks;
-    size_t need_one = 0;
-    plan_pairs(x_off, y_off, npairs, d, *p, backward != 0, kDefaultCap, chunks, &need_one);
-    size_t best = need_one;
-    for (const ListChunk& c : chunks)
-        best = std::max(best, (size_t)layout_for(c.tot, c.count, esize(*p), backward != 0, true, p->order).total);
-    return std::max<size_t>(best, 256);
+    try {
+        PlanImpl P;
+        if (oneshot_plan(P, x_off, y_off, npairs, d, *p, backward != 0, SIZE_MAX)) return 0;
+        return (size_t)P.total;
+    } catch (...) {
+        fail(SK_EINVAL, "internal exception");
+        return 0;
+    }
 }
 
 int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
@@ -901,11 +1110,22 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
         return rc;
     if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
+        if (p->algo == SK_ALGO_PLAIN) {
+            if (p->dtype == SK_F32)
+                return pairs_plain<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
+                                          npairs, d, *p, (float*)k, k_exp, ws, ws_bytes, stream);
+            return pairs_plain<double>((const double*)Xcat, x_off, (const double*)Ycat, y_off,
+                                       npairs, d, *p, (double*)k, k_exp, ws, ws_bytes, stream);
+        }
+        PlanImpl P;
+        if ((rc = oneshot_plan(P, x_off, y_off, npairs, d, *p, false, ws_bytes)) ||
+            (rc = plan_upload(P, ws, ws_bytes, stream)))
+            return rc;
         if (p->dtype == SK_F32)
-            return pairs_forward<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
-                                        npairs, d, *p, (float*)k, k_exp, ws, ws_bytes, stream);
-        return pairs_forward<double>((const double*)Xcat, x_off, (const double*)Ycat, y_off,
-                                     npairs, d, *p, (double*)k, k_exp, ws, ws_bytes, stream);
+            return plan_forward<float>(P, (const float*)Xcat, (const float*)Ycat, (float*)k, k_exp,
+                                       ws, stream);
+        return plan_forward<double>(P, (const double*)Xcat, (const double*)Ycat, (double*)k, k_exp,
+                                    ws, stream);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
     }
@@ -940,17 +1160,155 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
                                          ly_pts, d, *p, (const double*)gK, gK_exp, (double*)gX,
                                          (double*)gY, ws, ws_bytes, stream);
         }
+        PlanImpl P;
+        if ((rc = oneshot_plan(P, x_off, y_off, nx, d, *p, true, ws_bytes)) ||
+            (rc = plan_upload(P, ws, ws_bytes, stream)))
+            return rc;
         if (p->dtype == SK_F32)
-            return pairs_backward<float>((const float*)X, x_off, (const float*)Y, y_off, nx, d, *p,
-                                         (const float*)gK, gK_exp, (float*)gX, (float*)gY, ws,
-                                         ws_bytes, stream);
-        return pairs_backward<double>((const double*)X, x_off, (const double*)Y, y_off, nx, d, *p,
-                                      (const double*)gK, gK_exp, (double*)gX, (double*)gY, ws,
-                                      ws_bytes, stream);
+            return plan_backward<float>(P, (const float*)X, (const float*)Y, (const float*)gK,
+                                        gK_exp, (float*)gX, (float*)gY, ws, stream);
+        return plan_backward<double>(P, (const double*)X, (const double*)Y, (const double*)gK,
+                                     gK_exp, (double*)gX, (double*)gY, ws, stream);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
     }
 }
+
+int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t npairs, int64_t d,
+                          const sk_params* p, int32_t backward, size_t ws_bytes, sk_plan** plan) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    int rc = check_params(p, backward != 0);
+    if (!rc) rc = check_dims(d, backward != 0);
+    if (rc) return rc;
+    if (p->algo != SK_ALGO_BATCHED) return fail(SK_EUNSUPPORTED, "plans run the batched algorithm");
+    if (p->flags & SK_SYMMETRIC) return fail(SK_EINVAL, "SK_SYMMETRIC applies to Gram calls");
+    if (npairs < 0) return fail(SK_EINVAL, "negative npairs");
+    const int lam = backward ? 0 : lam_of(*p);
+    if ((rc = check_offsets(x_off, npairs, lam, "x")) || (rc = check_offsets(y_off, npairs, lam, "y")))
+        return rc;
+    try {
+        sk_plan* P = new sk_plan();
+        plan_init(P->impl, x_off, y_off, npairs, d, *p, backward != 0);
+        PlanCfg cfg = {1, 1, 1};
+        tuned_cfg(P->impl, &cfg);
+        rc = plan_build(P->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
+        if (rc) {
+            delete P;
+            return rc;
+        }
+        *plan = P;
+        return SK_OK;
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+size_t sigkernel_plan_workspace(const sk_plan* plan) {
+    g_last_error.clear();
+    if (!plan) {
+        fail(SK_EINVAL, "plan is NULL");
+        return 0;
+    }
+    return (size_t)plan->impl.total;
+}
+
+int sigkernel_plan_upload(sk_plan* plan, void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan || !ws) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        return plan_upload(plan->impl, ws, ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_forward(const sk_plan* plan, const void* Xcat, const void* Ycat, void* k,
+                           int32_t* k_exp, void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    const PlanImpl& P = plan->impl;
+    int rc = plan_ready(P, ws, ws_bytes);
+    if (rc) return rc;
+    if (P.npairs == 0) return SK_OK;
+    if (!Xcat || !Ycat || !k) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (P.p.dtype == SK_F32)
+            return plan_forward<float>(P, (const float*)Xcat, (const float*)Ycat, (float*)k, k_exp,
+                                       ws, stream);
+        return plan_forward<double>(P, (const double*)Xcat, (const double*)Ycat, (double*)k, k_exp,
+                                    ws, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_backward(const sk_plan* plan, const void* Xcat, const void* Ycat,
+                            const void* gk, const int32_t* gk_exp, void* gX, void* gY, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    const PlanImpl& P = plan->impl;
+    if (!P.backward) return fail(SK_EINVAL, "plan was created without backward");
+    int rc = plan_ready(P, ws, ws_bytes);
+    if (rc) return rc;
+    if (P.npairs == 0) return SK_OK;
+    if (!Xcat || !Ycat || !gk || !gX || !gY) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (P.p.dtype == SK_F32)
+            return plan_backward<float>(P, (const float*)Xcat, (const float*)Ycat,
+                                        (const float*)gk, gk_exp, (float*)gX, (float*)gY, ws,
+                                        stream);
+        return plan_backward<double>(P, (const double*)Xcat, (const double*)Ycat,
+                                     (const double*)gk, gk_exp, (double*)gX, (double*)gY, ws,
+                                     stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_tune(sk_plan* plan, const void* Xcat, const void* Ycat, void* ws,
+                        size_t ws_bytes, hipStream_t stream, double* best_ms) {
+    g_last_error.clear();
+    if (!plan || !Xcat || !Ycat || !ws) return fail(SK_EINVAL, "NULL pointer");
+    if (plan->impl.npairs == 0) return SK_OK;
+    try {
+        if (plan->impl.p.dtype == SK_F32)
+            return plan_tune<float>(plan->impl, (const float*)Xcat, (const float*)Ycat, ws,
+                                    ws_bytes, stream, best_ms);
+        return plan_tune<double>(plan->impl, (const double*)Xcat, (const double*)Ycat, ws,
+                                 ws_bytes, stream, best_ms);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, int32_t* buckets,
+                          int64_t* launches) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    if (order) *order = plan->impl.cfg.order;
+    if (swap) *swap = plan->impl.cfg.swap;
+    if (buckets) *buckets = plan->impl.cfg.buckets;
+    if (launches) *launches = (int64_t)plan->impl.chunks.size();
+    return SK_OK;
+}
+
+int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,
+                             size_t ws_bytes) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    if ((order | swap | buckets) & ~1) return fail(SK_EINVAL, "configuration flags are 0 or 1");
+    try {
+        const PlanCfg cfg = {order, swap, buckets};
+        return plan_build(plan->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+void sigkernel_plan_destroy(sk_plan* plan) { delete plan; }
 
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p) {

@@ -59,7 +59,11 @@ struct SkPairDesc {
     int64_t x_off;    // offset of the first point of x, in points
     int64_t y_off;    // offset of the first point of y, in points
     int32_t lx, ly;   // segments of x and y (unrefined)
+    int32_t swap;     // 1: x is read from the second path array and y from the
+                      // first (k(x, y) = k(y, x); the kernels see the pair
+                      // transposed so that the columns are the shorter path)
     int64_t k_idx;    // output index of the pair
+    int64_t g_idx;    // index of the pair's gradient seed dL/dk
     // element offsets of the pair's blocks in the chunk's workspace arrays
     int64_t c_off;    // skewed cell constants / skewed dL/dc
     int64_t ck_off;   // lane checkpoints (backward only)
@@ -112,7 +116,9 @@ __host__ __device__ inline SkPairDesc sk_pair(const SkPairSrc& s, int64_t local)
     d.y_off = b * s.ly_pts;
     d.lx = (int32_t)(s.lx_pts - 1);
     d.ly = (int32_t)(s.ly_pts - 1);
+    d.swap = 0;
     d.k_idx = p;
+    d.g_idx = p;
     d.c_off = local * s.stride.c;
     d.ck_off = local * s.stride.ck;
     d.ce_off = local * s.stride.ce;

@@ -138,8 +138,8 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     R* Xs = reinterpret_cast<R*>(sk_smem);          // [64][dp]
     R* Ys = Xs + 64 * dp;                            // [128][dp]
     R* Tt = Ys + 128 * dp;                           // [64][66]: diagonal reads conflict-free
-    const R* X = a.X + pd.x_off * a.d;
-    const R* Y = a.Y + pd.y_off * a.d;
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
 
     R val[16];
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
     R* Tt = reinterpret_cast<R*>(sk_smem);  // [64][66]
     R* Xs = Tt + 64 * 66;                    // [lx][dp]
     R* Ys = Xs + (size_t)pd.lx * dp;         // [ly][dp]
-    const R* X = a.X + pd.x_off * a.d;
-    const R* Y = a.Y + pd.y_off * a.d;
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
     for (int e = tid; e < pd.lx * dp; e += 256) {
         const int i = e / dp, k = e - i * dp;
@@ -540,8 +540,8 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     int* ltag = reinterpret_cast<int*>(llds + (size_t)g.ly * (N + 1));
     const R* cs = a.cskew + pd.c_off;
     R* gs = a.gskew + pd.c_off;
-    const R gk = a.gK[pd.k_idx];
-    const int gexp = a.gKexp ? a.gKexp[pd.k_idx] : 0;
+    const R gk = a.gK[pd.g_idx];
+    const int gexp = a.gKexp ? a.gKexp[pd.g_idx] : 0;
 
     // adjoint state: lp (own, exponent El), lqs (sent to lane r-1, exponent Els)
     R lp[N + 1], lqs[N + 1];
@@ -785,8 +785,8 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const int64_t d = a.d;
     const int jc = a.jchunk;
     R* ycl = reinterpret_cast<R*>(sk_smem);  // [jc][DMAX] y increments of the chunk
-    const R* X = a.X + pd.x_off * d;
-    const R* Y = a.Y + pd.y_off * d;
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
     const R* gsk = a.gskew + pd.c_off;
     const int i = s * 64 + r;
     const bool rowok = i < g.lx;
@@ -976,7 +976,7 @@ __global__ void k_reduce_pairs(const ReducePairsArgs<R> a) {
                 if (t > 0) v += dx[(t - 1) * d + k];
                 if (t < pd.lx) v -= dx[t * d + k];
             }
-            a.gX[(pd.x_off + t) * d + k] = v;
+            (pd.swap ? a.gY : a.gX)[(pd.x_off + t) * d + k] = v;
         }
         if (t <= pd.ly) {
             R v = (R)0;
@@ -987,7 +987,7 @@ __global__ void k_reduce_pairs(const ReducePairsArgs<R> a) {
                     if (t < pd.ly) v -= dy[t * d + k];
                 }
             }
-            a.gY[(pd.y_off + t) * d + k] = v;
+            (pd.swap ? a.gX : a.gY)[(pd.y_off + t) * d + k] = v;
         }
     }
 }

@@ -129,3 +129,41 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(root, f)).read()
                 assert "from oracle" not in src and "import oracle" not in src, f
+
+
+def test_plan_host_side_checks():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    xo = (ctypes.c_int64 * 4)(0, 5, 6, 40)
+    yo = (ctypes.c_int64 * 4)(0, 30, 32, 33)
+    h = vp(0)
+    assert lib.sigkernel_plan_create(xo, yo, 3, 3, P(), 0, 0, None) == L.SK_EINVAL
+    assert lib.sigkernel_plan_create(xo, yo, 3, 3, P(order=1), 0, 0, ctypes.byref(h)) == L.SK_EINVAL
+    assert lib.sigkernel_plan_create(xo, yo, 3, 3, P(algo=1, dtype=0), 0, 0,
+                                     ctypes.byref(h)) == L.SK_EUNSUPPORTED
+    assert lib.sigkernel_plan_create(xo, yo, -1, 3, P(), 0, 0, ctypes.byref(h)) == L.SK_EINVAL
+    bad = (ctypes.c_int64 * 4)(1, 5, 6, 40)
+    assert lib.sigkernel_plan_create(bad, yo, 3, 3, P(), 0, 0, ctypes.byref(h)) == L.SK_EINVAL
+    assert lib.sigkernel_plan_create(xo, yo, 3, 3, P(), 0, 0, ctypes.byref(h)) == L.SK_OK
+    assert h.value
+    need = lib.sigkernel_plan_workspace(h)
+    assert need > 0
+    # not uploaded: refused before any device work
+    assert lib.sigkernel_plan_forward(h, vp(1), vp(1), vp(1), None, vp(1), need, None) == L.SK_EINVAL
+    # forward-only plan: no backward
+    assert lib.sigkernel_plan_backward(h, vp(1), vp(1), vp(1), None, vp(1), vp(1), vp(1), need,
+                                       None) == L.SK_EINVAL
+    o, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    n = ctypes.c_int64()
+    assert lib.sigkernel_plan_config(h, ctypes.byref(o), ctypes.byref(w), ctypes.byref(b),
+                                     ctypes.byref(n)) == L.SK_OK
+    assert (o.value, w.value, b.value) == (1, 1, 1) and n.value >= 1
+    assert lib.sigkernel_plan_configure(h, 0, 0, 0, 0) == L.SK_OK
+    assert lib.sigkernel_plan_config(h, ctypes.byref(o), ctypes.byref(w), ctypes.byref(b),
+                                     ctypes.byref(n)) == L.SK_OK
+    assert (o.value, w.value, b.value, n.value) == (0, 0, 0, 1)
+    assert lib.sigkernel_plan_configure(h, 2, 0, 0, 0) == L.SK_EINVAL
+    # a workspace too small for the descriptors and one pair
+    assert lib.sigkernel_plan_configure(h, 1, 1, 1, 64) == L.SK_EWORKSPACE
+    lib.sigkernel_plan_destroy(h)
+    lib.sigkernel_plan_destroy(None)

@@ -1,0 +1,122 @@
+"""Plans for uneven pairs: every launch configuration against the FP64
+oracle, HIP-graph capture and replay against the eager result, the tuner,
+and the plan backward against the one-shot backward."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import bm_paths, log_banner, rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2502_08470_amd as P
+    from paper_2502_08470_amd import _lib
+    _lib.lib()
+    return P
+
+
+def uneven(rng, n, d, lo, hi):
+    lx = rng.integers(lo, hi + 1, size=n)
+    ly = rng.integers(lo, hi + 1, size=n)
+    xs = [bm_paths(rng, 1, int(m) - 1, d, 0.3 / np.sqrt(m))[0] for m in lx]
+    ys = [bm_paths(rng, 1, int(m) - 1, d, 0.3 / np.sqrt(m))[0] for m in ly]
+    return xs, ys
+
+
+def cat(paths, dtype):
+    return torch.tensor(np.concatenate(paths, 0), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 6), ("interp", 5), ("fd", 1)])
+def test_every_configuration_matches_oracle(sk, scheme, order):
+    from oracle import c_oracle as C
+    log_banner(f"plan configurations {scheme} {order}")
+    rng = np.random.default_rng(51)
+    xs, ys = uneven(rng, 40, 3, 1, 700)
+    xs[3], ys[3] = xs[3][:1], ys[3]  # one single-point path
+    Xc, Yc = cat(xs, torch.float64), cat(ys, torch.float64)
+    plan = sk.PairsPlan([torch.empty(len(a), 3, dtype=torch.float64, device="cuda") for a in xs],
+                        [torch.empty(len(b), 3, dtype=torch.float64, device="cuda") for b in ys],
+                        scheme, order)
+    kind = {"approx": C.APPROX, "interp": C.INTERP, "fd": C.FD}[scheme]
+    m, e = C.pairs(xs, ys, kind, order)
+    ref = np.ldexp(m, e)
+    for o in (0, 1):
+        for w in (0, 1):
+            for b in (0, 1):
+                plan.configure(o, w, b)
+                k = torch.full((len(xs),), float("nan"), dtype=torch.float64, device="cuda")
+                plan.forward(Xc, Yc, k)
+                err = rel_err(k.cpu().numpy(), ref)
+                assert err.max() < 1e-11, ((o, w, b), err.max(), plan.config())
+
+
+def test_graph_capture_replays_match_eager(sk):
+    log_banner("plan graph capture")
+    rng = np.random.default_rng(52)
+    xs, ys = uneven(rng, 64, 4, 2, 400)
+    Xc, Yc = cat(xs, torch.float32), cat(ys, torch.float32)
+    lens_x = [torch.empty(len(a), 4, device="cuda") for a in xs]
+    lens_y = [torch.empty(len(b), 4, device="cuda") for b in ys]
+    plan = sk.PairsPlan(lens_x, lens_y, "interp", 6)
+    k_eager = torch.empty(len(xs), device="cuda")
+    plan.forward(Xc, Yc, k_eager)
+    torch.cuda.synchronize()
+    k = torch.zeros(len(xs), device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        plan.forward(Xc, Yc, k)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(Xc, Yc, k)
+    for rep in range(3):
+        k.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(k, k_eager), rep
+        assert torch.isfinite(junk)
+
+
+def test_tune_then_oneshot_calls_agree(sk):
+    log_banner("plan tuning")
+    rng = np.random.default_rng(53)
+    xs, ys = uneven(rng, 96, 5, 2, 900)
+    Xc, Yc = cat(xs, torch.float32), cat(ys, torch.float32)
+    xl = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in xs]
+    yl = [torch.tensor(b, dtype=torch.float32, device="cuda") for b in ys]
+    plan = sk.PairsPlan(xl, yl, "approx", 8)
+    ms = plan.tune(Xc, Yc)
+    assert ms > 0
+    cfg = plan.config()
+    assert cfg["launches"] >= 1
+    k = torch.empty(len(xs), device="cuda")
+    plan.forward(Xc, Yc, k)
+    k1 = sk.pairs(xl, yl, "approx", 8)  # one-shot call: uses the tuned configuration
+    torch.testing.assert_close(k1, k, rtol=0, atol=0)
+
+
+def test_plan_backward_matches_oneshot(sk):
+    log_banner("plan backward")
+    rng = np.random.default_rng(54)
+    xs, ys = uneven(rng, 24, 3, 2, 300)
+    xl = [torch.tensor(a, device="cuda") for a in xs]
+    yl = [torch.tensor(b, device="cuda") for b in ys]
+    Xc, Yc = cat(xs, torch.float64), cat(ys, torch.float64)
+    gk = torch.tensor(rng.normal(size=len(xs)), device="cuda")
+    gX0, gY0, _, _ = sk.pairs_backward(xl, yl, gk, "approx", 5)
+    plan = sk.PairsPlan(xl, yl, "approx", 5, backward=True)
+    for o, w, b in ((0, 0, 0), (1, 1, 1), (1, 0, 1), (0, 1, 0)):
+        plan.configure(o, w, b)
+        gX = torch.full_like(Xc, float("nan"))
+        gY = torch.full_like(Yc, float("nan"))
+        plan.backward(Xc, Yc, gk, gX, gY)
+        torch.testing.assert_close(gX, gX0, rtol=1e-12, atol=1e-12 * float(gX0.abs().max()))
+        torch.testing.assert_close(gY, gY0, rtol=1e-12, atol=1e-12 * float(gY0.abs().max()))
