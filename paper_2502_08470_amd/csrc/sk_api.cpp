@@ -633,11 +633,13 @@ struct PlanImpl {
     bool backward = false;
     std::vector<int64_t> xo, yo;
     PlanCfg cfg = {1, 1, 1};
-    std::vector<SkPairDesc> desc;
-    std::vector<PlanChunk> chunks;
+    // forward and backward chunkings (the backward keeps more state per pair,
+    // so its chunks are smaller); descriptors hold chunk-relative offsets
+    std::vector<SkPairDesc> fdesc, bdesc;
+    std::vector<PlanChunk> fchunks, bchunks;
     int max_ly = 0;  // longest column count of any pair (LDS check)
     // workspace regions (bytes): descriptors, kernel-value scratch, chunk scratch
-    int64_t desc_off = 0, kbuf_off = 0, kexp_off = 0, scratch_off = 0, total = 0;
+    int64_t fdesc_off = 0, bdesc_off = 0, kbuf_off = 0, kexp_off = 0, scratch_off = 0, total = 0;
     const void* uploaded = nullptr;
 };
 
@@ -686,8 +688,10 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         if (cls[u] != cls[v]) return cls[u] > cls[v];
         return cfg.order ? cost[u] > cost[v] : false;
     });
-    P.desc_off = 0;
-    P.kbuf_off = align_up(n * (int64_t)sizeof(SkPairDesc));
+    const int64_t dbytes = align_up(n * (int64_t)sizeof(SkPairDesc));
+    P.fdesc_off = 0;
+    P.bdesc_off = dbytes;
+    P.kbuf_off = P.bdesc_off + (P.backward ? dbytes : 0);
     P.kexp_off = P.kbuf_off + align_up(n * (int64_t)es);
     P.scratch_off = P.kexp_off + align_up(n * 4);
     size_t cap = kDefaultCap;
@@ -696,54 +700,69 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
             return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
         cap = ws_bytes - (size_t)P.scratch_off;
     }
-    P.desc.assign(n, SkPairDesc());
-    P.chunks.clear();
     P.max_ly = 0;
-    int64_t scratch = 0;
-    PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
-    SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
-    auto close = [&]() {
-        if (cur.count == 0) return;
-        scratch = std::max(scratch, layout_for(cur.tot, cur.count, es, P.backward, false, p.order).total);
-        P.chunks.push_back(cur);
-    };
-    for (int64_t k = 0; k < n; ++k) {
-        const int64_t i = seq[k];
-        const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, P.backward);
-        const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
-        const bool new_class = cur.count > 0 && cfg.buckets && cls[i] != cls[seq[cur.first]];
-        const SkPairSizes t = add(cur.tot, z);
-        const bool too_big = cur.count > 0 &&
-            (size_t)layout_for(t, cur.count + 1, es, P.backward, false, p.order).total > cap;
-        if (new_class || too_big) {
-            close();
-            cur = {k, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
-            run = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) P.max_ly = std::max(P.max_ly, ey[i]);
+    // greedy chunks along the launch order, split at LDS classes and at the
+    // workspace capacity
+    auto chunk = [&](bool bwd, std::vector<SkPairDesc>& desc, std::vector<PlanChunk>& chunks,
+                     int64_t* scratch) -> int {
+        desc.assign(n, SkPairDesc());
+        chunks.clear();
+        *scratch = 0;
+        PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
+        SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
+        auto close = [&]() {
+            if (cur.count == 0) return;
+            *scratch = std::max(*scratch, layout_for(cur.tot, cur.count, es, bwd, false, p.order).total);
+            chunks.push_back(cur);
+        };
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t i = seq[k];
+            const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd);
+            const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
+            const bool new_class = cur.count > 0 && cfg.buckets && cls[i] != cls[seq[cur.first]];
+            const bool too_big = cur.count > 0 &&
+                (size_t)layout_for(add(cur.tot, z), cur.count + 1, es, bwd, false, p.order).total > cap;
+            if (new_class || too_big) {
+                close();
+                cur = {k, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
+                run = {0, 0, 0, 0, 0, 0, 0};
+            }
+            if ((size_t)layout_for(z, 1, es, bwd, false, p.order).total > cap)
+                return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
+            SkPairDesc& q = desc[k];
+            q.x_off = sw[i] ? P.yo[i] : P.xo[i];
+            q.y_off = sw[i] ? P.xo[i] : P.yo[i];
+            q.lx = ex[i];
+            q.ly = ey[i];
+            q.swap = sw[i];
+            q.k_idx = i;
+            q.g_idx = i;
+            q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
+            q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
+            run = add(run, z);
+            cur.count += 1;
+            cur.tot = add(cur.tot, z);
+            cur.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
+            cur.max_lx = std::max(cur.max_lx, ex[i]);
+            cur.max_ly = std::max(cur.max_ly, ey[i]);
+            cur.max_strips = std::max(cur.max_strips, g.nstrips);
+            cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
         }
-        if ((size_t)layout_for(z, 1, es, P.backward, false, p.order).total > cap)
-            return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
-        SkPairDesc& q = P.desc[k];
-        q.x_off = sw[i] ? P.yo[i] : P.xo[i];
-        q.y_off = sw[i] ? P.xo[i] : P.yo[i];
-        q.lx = ex[i];
-        q.ly = ey[i];
-        q.swap = sw[i];
-        q.k_idx = i;
-        q.g_idx = i;
-        q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
-        q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
-        run = add(run, z);
-        cur.count += 1;
-        cur.tot = add(cur.tot, z);
-        cur.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
-        cur.max_lx = std::max(cur.max_lx, ex[i]);
-        cur.max_ly = std::max(cur.max_ly, ey[i]);
-        cur.max_strips = std::max(cur.max_strips, g.nstrips);
-        cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
-        P.max_ly = std::max(P.max_ly, ey[i]);
+        close();
+        return SK_OK;
+    };
+    int64_t fs = 0, bs = 0;
+    int rc = chunk(false, P.fdesc, P.fchunks, &fs);
+    if (rc) return rc;
+    if (P.backward) {
+        rc = chunk(true, P.bdesc, P.bchunks, &bs);
+        if (rc) return rc;
+    } else {
+        P.bdesc.clear();
+        P.bchunks.clear();
     }
-    close();
-    P.total = P.scratch_off + std::max<int64_t>(scratch, 256);
+    P.total = P.scratch_off + std::max<int64_t>(std::max(fs, bs), 256);
     return SK_OK;
 }
 
@@ -824,9 +843,14 @@ int plan_upload(PlanImpl& P, void* ws, size_t wsb, hipStream_t st) {
     int rc = plan_check_device(P);
     if (rc) return rc;
     if (P.npairs > 0) {
-        SK_TRY_HIP(hipMemcpyAsync((char*)ws + P.desc_off, P.desc.data(),
-                                  P.desc.size() * sizeof(SkPairDesc), hipMemcpyHostToDevice, st),
+        SK_TRY_HIP(hipMemcpyAsync((char*)ws + P.fdesc_off, P.fdesc.data(),
+                                  P.fdesc.size() * sizeof(SkPairDesc), hipMemcpyHostToDevice, st),
                    "descriptor upload");
+        if (P.backward)
+            SK_TRY_HIP(hipMemcpyAsync((char*)ws + P.bdesc_off, P.bdesc.data(),
+                                      P.bdesc.size() * sizeof(SkPairDesc), hipMemcpyHostToDevice,
+                                      st),
+                       "descriptor upload");
         SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
     }
     P.uploaded = ws;
@@ -845,11 +869,11 @@ template <typename R>
 int plan_forward(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kexp, void* ws,
                  hipStream_t st) {
     char* base = (char*)ws;
-    for (const PlanChunk& c : P.chunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), P.backward, false, P.p.order);
+    for (const PlanChunk& c : P.fchunks) {
+        const Layout L = layout_for(c.tot, c.count, sizeof(R), false, false, P.p.order);
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
-        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.desc_off) + c.first;
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.fdesc_off) + c.first;
         int rc = run_chunk_forward<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
                                       c.max_ly, base + P.scratch_off, L, K, Kexp, st);
         if (rc) return rc;
@@ -866,12 +890,12 @@ int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, cons
     // kernel values of the checkpoint pass: scratch indexed by k_idx
     R* kbuf = reinterpret_cast<R*>(base + P.kbuf_off);
     int32_t* kexp = reinterpret_cast<int32_t*>(base + P.kexp_off);
-    for (const PlanChunk& c : P.chunks) {
+    for (const PlanChunk& c : P.bchunks) {
         const Layout L = layout_for(c.tot, c.count, sizeof(R), true, false, P.p.order);
         char* ws_c = base + P.scratch_off;
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
-        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.desc_off) + c.first;
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
         int rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
                                       c.max_ly, ws_c, L, kbuf, kexp, st);
         if (rc) return rc;
@@ -1291,7 +1315,7 @@ int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, in
     if (order) *order = plan->impl.cfg.order;
     if (swap) *swap = plan->impl.cfg.swap;
     if (buckets) *buckets = plan->impl.cfg.buckets;
-    if (launches) *launches = (int64_t)plan->impl.chunks.size();
+    if (launches) *launches = (int64_t)plan->impl.fchunks.size();
     return SK_OK;
 }
 
