@@ -299,9 +299,13 @@ class PairsPlan:
                 "lds_classes": bool(b.value), "launches": int(n.value)}
 
     def configure(self, longest_first: bool, transpose: bool, lds_classes: bool):
-        """Set the configuration by hand (rebuilds and uploads the plan)."""
+        """Set the configuration by hand (rebuilds the plan, grows the
+        workspace if this configuration needs more, and uploads)."""
         L.check(self._lib.sigkernel_plan_configure(self._h, int(longest_first), int(transpose),
-                                                   int(lds_classes), self.ws.numel()))
+                                                   int(lds_classes), 0))
+        nb = self._lib.sigkernel_plan_workspace(self._h)
+        if nb > self.ws.numel():
+            self.ws = _workspace(nb, self.device)
         self._upload()
 
     def forward(self, Xcat: torch.Tensor, Ycat: torch.Tensor, k: torch.Tensor,

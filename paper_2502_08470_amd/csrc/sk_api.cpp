@@ -246,6 +246,29 @@ int check_offsets(const int64_t* off, int64_t npairs, int lam, const char* what)
 
 size_t esize(const sk_params& p) { return p.dtype == SK_F32 ? 4 : 8; }
 int lam_of(const sk_params& p) { return p.scheme == SK_FD ? p.order : 0; }
+// LDS budgets of the strip-boundary rings; pairs that would need more pass
+// their edges through the global exchange.  The forward sweep (about five
+// waves per SIMD by registers) loses occupancy to its ring beyond ~16 KiB;
+// the adjoint (two waves per SIMD, one with the exchange code) only when the
+// ring would leave fewer than four waves per CU.
+constexpr int kGxFwdLds = 16 << 10;
+constexpr int kGxAdjLds = 38 << 10;
+int gx_cols_fwd(const sk_params& p) {
+    return std::max(SK_GX_MIN_COLS, kGxFwdLds / sk_ring_col_bytes_fwd(p.order, (int)esize(p)));
+}
+int gx_cols_adj(const sk_params& p) {
+    return std::max(SK_GX_MIN_COLS, kGxAdjLds / sk_ring_col_bytes_adj(p.order, (int)esize(p)));
+}
+// words per column of a pair's global exchange records (0: none needed)
+int xb_words_of(const sk_params& p, int ly) {
+    if (p.scheme == SK_FD) return 0;
+    return ly > std::min(gx_cols_fwd(p), gx_cols_adj(p)) ? sk_gx_words(p.order, (int)esize(p)) : 0;
+}
+// LDS ring columns a pair with ly columns needs (0: global exchange)
+int ring_fwd_of(const sk_params& p, int ly) {
+    return (p.scheme != SK_FD && ly > gx_cols_fwd(p)) ? 0 : ly;
+}
+int ring_adj_of(const sk_params& p, int ly) { return ly > gx_cols_adj(p) ? 0 : ly; }
 int ckpt_stride(const sk_params& p) {
     return p.dtype == SK_F32 ? SkCkptStride<float>::value : SkCkptStride<double>::value;
 }
@@ -254,7 +277,7 @@ int ckpt_stride(const sk_params& p) {
 // workspace layout of one chunk
 // ---------------------------------------------------------------------------
 struct Layout {
-    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, total;
+    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, xb, total;
 };
 
 // Region sizes for P pairs with total per-array element counts `z` (sum over
@@ -278,18 +301,19 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     L.kbuf = backward ? take(P * (int64_t)es) : off;
     L.kexp = backward ? take(P * 4) : off;
     L.desc = list ? take(P * (int64_t)sizeof(SkPairDesc)) : off;
+    L.xb = take(z.xb * 4);
     L.total = off;
     return L;
 }
 
 SkPairSizes scale(const SkPairSizes& z, int64_t P) {
-    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P};
+    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P, z.xb * P};
     return o;
 }
 
 SkPairSizes add(const SkPairSizes& a, const SkPairSizes& b) {
     SkPairSizes o = {a.c + b.c, a.ck + b.ck, a.ce + b.ce, a.qb + b.qb,
-                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy};
+                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy, a.xb + b.xb};
     return o;
 }
 
@@ -336,7 +360,7 @@ hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int
 
 template <typename R>
 int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, const SkPairSrc& src,
-                      int64_t P, int max_nsteps_pad, int max_lx, int max_ly, char* ws,
+                      int64_t P, int max_nsteps_pad, int max_lx, int max_ly, int ring, char* ws,
                       const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     const int lam = lam_of(p);
@@ -354,7 +378,10 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
         std::memset(&sa, 0, sizeof(sa));
         sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
         sa.K = K; sa.Kexp = Kexp;
-        SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, max_ly, st), "sweep");
+        sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+        sa.gx_cols = gx_cols_fwd(p);
+        SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, ring,
+                                                  max_ly > sa.gx_cols, st), "sweep");
     }
     return SK_OK;
 }
@@ -363,8 +390,10 @@ template <typename R>
 int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
     size_t lim = 0;
     SK_TRY_HIP(lds_limit(&lim), "device query");
-    size_t need = p.scheme == SK_FD ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
-                                    : SkLaunch<R>::sweep_lds(p.order, (int)max_ly);
+    size_t need = p.scheme == SK_FD
+                      ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
+                      : std::max(SkLaunch<R>::sweep_lds(p.order, std::min<int>((int)max_ly, gx_cols_fwd(p))),
+                                 SkLaunch<R>::adjoint_lds(p.order, std::min<int>((int)max_ly, gx_cols_adj(p))));
     need = std::max(need, SkLaunch<R>::gram_lds(gram_dpad(p, d)));
     if (need > lim)
         return fail(SK_EUNSUPPORTED, "paths too long for one workgroup's LDS (%zu > %zu bytes)",
@@ -404,7 +433,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
             }
         return SK_OK;
     }
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false);
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false, xb_words_of(p, (int)ly));
     const int64_t P = gram_chunk(per, npairs, sizeof(R), false, wsb, p.order);
     if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
     int rc = check_lds<R>(p, ly, d);
@@ -417,8 +446,8 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
         std::memset(&src, 0, sizeof(src));
         src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
         src.desc = nullptr;
-        rc = run_chunk_forward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly, (char*)ws,
-                                  L, K, Kexp, st);
+        rc = run_chunk_forward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly,
+                                  ring_fwd_of(p, (int)ly), (char*)ws, L, K, Kexp, st);
         if (rc) return rc;
     }
     return SK_OK;
@@ -433,7 +462,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
 template <typename R>
 int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
                       const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx, int max_ly,
-                      char* ws,
+                      int ring, char* ws,
                       const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
@@ -450,7 +479,10 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     sa.qb = reinterpret_cast<R*>(ws + L.qb);
     sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
-    SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, max_ly, st), "checkpoint sweep");
+    sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+    sa.gx_cols = gx_cols_fwd(p);
+    SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, ring,
+                                                       max_ly > sa.gx_cols, st), "checkpoint sweep");
     return SK_OK;
 }
 
@@ -458,7 +490,7 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
 // state left by run_chunk_prepare.
 template <typename R>
 int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
-                      const SkPairSrc& src, int64_t P, int max_ly, int max_strips, char* ws,
+                      const SkPairSrc& src, int64_t P, int max_ly, int ring, int max_strips, char* ws,
                       const Layout& L, const R* gK, const int32_t* gKexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     AdjArgs<R> aa;
@@ -470,7 +502,10 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.qb = reinterpret_cast<const R*>(ws + L.qb);
     aa.qe = reinterpret_cast<const int32_t*>(ws + L.qe);
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
-    SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, max_ly, st), "adjoint sweep");
+    aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+    aa.gx_cols = gx_cols_adj(p);
+    SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, ring,
+                                                  max_ly > aa.gx_cols, st), "adjoint sweep");
     ContractArgs<R> ca;
     ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = aa.gskew;
     ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
@@ -484,17 +519,18 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
 template <typename R>
 int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
                        const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
-                       int max_ly, int max_strips, char* ws, const Layout& L, const R* gK,
+                       int max_ly, int ring_f, int ring_a, int max_strips, char* ws, const Layout& L,
+                       const R* gK,
                        const int32_t* gKexp, hipStream_t st) {
     // the checkpoint pass's kernel values go to the chunk's scratch slots
     // (Gram mode: k_idx - first; list mode: descriptors carry local k_idx)
     const int64_t kbase = src.desc ? 0 : src.first;
     R* kbuf = reinterpret_cast<R*>(ws + L.kbuf) - kbase;
     int32_t* kexp = reinterpret_cast<int32_t*>(ws + L.kexp) - kbase;
-    int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_lx, max_ly, ws, L, kbuf,
+    int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_lx, max_ly, ring_f, ws, L, kbuf,
                                   kexp, st);
     if (rc) return rc;
-    return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, max_strips, ws, L, gK, gKexp, st);
+    return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, ring_a, max_strips, ws, L, gK, gKexp, st);
 }
 
 // Forward that keeps the whole backward state of a Gram call in `state`
@@ -503,7 +539,8 @@ template <typename R>
 int gram_state_layout(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
                       const sk_params& p, SkPairSizes* per, Layout* L) {
     const int64_t npairs = nx * ny;
-    *per = sk_pair_sizes((int)(lxp - 1), (int)(lyp - 1), 0, p.order, ckpt_stride(p), d, true);
+    *per = sk_pair_sizes((int)(lxp - 1), (int)(lyp - 1), 0, p.order, ckpt_stride(p), d, true,
+                         xb_words_of(p, (int)(lyp - 1)));
     *L = layout_for(scale(*per, npairs), npairs, sizeof(R), true, false, p.order);
     return SK_OK;
 }
@@ -530,7 +567,7 @@ int gram_save(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64
     std::memset(&src, 0, sizeof(src));
     src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
     return run_chunk_prepare<R>(p, X, Y, d, src, npairs, g.nsteps_pad, (int)lx, (int)ly,
-                                (char*)state, L, K, Kexp, st);
+                                ring_fwd_of(p, (int)ly), (char*)state, L, K, Kexp, st);
 }
 
 template <typename R>
@@ -552,8 +589,8 @@ int gram_backward_saved(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t
     SkPairSrc src;
     std::memset(&src, 0, sizeof(src));
     src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
-    rc = run_chunk_adjoint<R>(p, X, Y, d, src, npairs, (int)ly, g.nstrips, (char*)state, L, gK,
-                              gKexp, st);
+    rc = run_chunk_adjoint<R>(p, X, Y, d, src, npairs, (int)ly, ring_adj_of(p, (int)ly), g.nstrips,
+                              (char*)state, L, gK, gKexp, st);
     if (rc) return rc;
     ReduceGramArgs<R> ra;
     ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
@@ -577,7 +614,7 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
         SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
         return SK_OK;
     }
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true);
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true, xb_words_of(p, (int)ly));
     const int64_t P = gram_chunk(per, npairs, sizeof(R), true, wsb, p.order);
     if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
     int rc = check_lds<R>(p, ly, d);
@@ -592,7 +629,8 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
         std::memset(&src, 0, sizeof(src));
         src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
         rc = run_chunk_backward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly,
-                                   g.nstrips, (char*)ws, L, gK, gKexp, st);
+                                   ring_fwd_of(p, (int)ly), ring_adj_of(p, (int)ly), g.nstrips,
+                                   (char*)ws, L, gK, gKexp, st);
         if (rc) return rc;
         ReduceGramArgs<R> ra;
         ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
@@ -624,6 +662,7 @@ struct PlanChunk {
     int64_t first, count;  // range of the plan's descriptor array
     SkPairSizes tot;
     int max_nsteps_pad, max_lx, max_ly, max_strips;
+    int ring_fwd, ring_adj;  // LDS ring columns (largest among pairs not using the global exchange)
     int64_t max_pts;
 };
 
@@ -649,9 +688,12 @@ size_t sweep_lds_bytes(const sk_params& p, int ly) {
                              : SkLaunch<double>::sweep_lds(p.order, ly);
 }
 
+// Launch groups: pairs whose edges go through the global exchange, then LDS
+// rings up to 4, 8 and 16 KiB (and longer FD rings).
 int lds_class(const sk_params& p, int ly) {
+    if (ring_fwd_of(p, ly) == 0) return 4;
     const size_t b = sweep_lds_bytes(p, ly);
-    return b <= (16u << 10) ? 0 : b <= (32u << 10) ? 1 : b <= (64u << 10) ? 2 : 3;
+    return b <= (4u << 10) ? 0 : b <= (8u << 10) ? 1 : b <= (17u << 10) ? 2 : 3;
 }
 
 // Build descriptors and chunks for `cfg`, with chunk scratch sized to fit a
@@ -709,8 +751,8 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         desc.assign(n, SkPairDesc());
         chunks.clear();
         *scratch = 0;
-        PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
-        SkPairSizes run = {0, 0, 0, 0, 0, 0, 0};
+        PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
+        SkPairSizes run = {0, 0, 0, 0, 0, 0, 0, 0};
         auto close = [&]() {
             if (cur.count == 0) return;
             *scratch = std::max(*scratch, layout_for(cur.tot, cur.count, es, bwd, false, p.order).total);
@@ -718,15 +760,16 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         };
         for (int64_t k = 0; k < n; ++k) {
             const int64_t i = seq[k];
-            const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd);
+            const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
+                                                xb_words_of(p, ey[i]));
             const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
             const bool new_class = cur.count > 0 && cfg.buckets && cls[i] != cls[seq[cur.first]];
             const bool too_big = cur.count > 0 &&
                 (size_t)layout_for(add(cur.tot, z), cur.count + 1, es, bwd, false, p.order).total > cap;
             if (new_class || too_big) {
                 close();
-                cur = {k, 0, {0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0};
-                run = {0, 0, 0, 0, 0, 0, 0};
+                cur = {k, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
+                run = {0, 0, 0, 0, 0, 0, 0, 0};
             }
             if ((size_t)layout_for(z, 1, es, bwd, false, p.order).total > cap)
                 return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
@@ -739,7 +782,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
             q.k_idx = i;
             q.g_idx = i;
             q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
-            q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy;
+            q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy; q.xb_off = run.xb;
             run = add(run, z);
             cur.count += 1;
             cur.tot = add(cur.tot, z);
@@ -747,6 +790,8 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
             cur.max_lx = std::max(cur.max_lx, ex[i]);
             cur.max_ly = std::max(cur.max_ly, ey[i]);
             cur.max_strips = std::max(cur.max_strips, g.nstrips);
+            cur.ring_fwd = std::max(cur.ring_fwd, ring_fwd_of(p, ey[i]));
+            cur.ring_adj = std::max(cur.ring_adj, ring_adj_of(p, ey[i]));
             cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
         }
         close();
@@ -875,7 +920,7 @@ int plan_forward(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kex
         std::memset(&src, 0, sizeof(src));
         src.desc = reinterpret_cast<const SkPairDesc*>(base + P.fdesc_off) + c.first;
         int rc = run_chunk_forward<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                      c.max_ly, base + P.scratch_off, L, K, Kexp, st);
+                                      c.max_ly, c.ring_fwd, base + P.scratch_off, L, K, Kexp, st);
         if (rc) return rc;
     }
     return SK_OK;
@@ -897,10 +942,10 @@ int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, cons
         std::memset(&src, 0, sizeof(src));
         src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
         int rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                      c.max_ly, ws_c, L, kbuf, kexp, st);
+                                      c.max_ly, c.ring_fwd, ws_c, L, kbuf, kexp, st);
         if (rc) return rc;
-        rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.max_strips, ws_c, L,
-                                  gK, gKexp, st);
+        rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj,
+                                  c.max_strips, ws_c, L, gK, gKexp, st);
         if (rc) return rc;
         ReducePairsArgs<R> ra;
         ra.desc = src.desc; ra.count = c.count; ra.d = P.d; ra.max_pts = c.max_pts;
@@ -927,7 +972,13 @@ int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipSt
         for (int w = 0; w < 2 && !rc; ++w)
             for (int b = 0; b < 2 && !rc; ++b) {
                 const PlanCfg cfg = {o, w, b};
-                if ((rc = plan_build(P, cfg, wsb)) || (rc = plan_upload(P, ws, wsb, st))) break;
+                rc = plan_build(P, cfg, wsb);
+                if (rc == SK_EWORKSPACE) {  // this configuration does not fit: skip it
+                    rc = SK_OK;
+                    g_last_error.clear();
+                    continue;
+                }
+                if (rc || (rc = plan_upload(P, ws, wsb, st))) break;
                 R* K = reinterpret_cast<R*>((char*)ws + P.kbuf_off);
                 double t = 1e30;
                 for (int rep = 0; rep < 3 && !rc; ++rep) {
@@ -948,6 +999,7 @@ int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipSt
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
+    if (best_t < 0) return fail(SK_EWORKSPACE, "no configuration fits a workspace of %zu bytes", wsb);
     if ((rc = plan_build(P, best, wsb)) || (rc = plan_upload(P, ws, wsb, st))) return rc;
     remember_cfg(P, best);
     if (best_ms) *best_ms = best_t;
@@ -1064,7 +1116,8 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
                                                                3 * ((lx << lam) + 1)) * 8);
     }
     const SkPairSizes per = sk_pair_sizes((int)(lx_pts - 1), (int)(ly_pts - 1), lam, p->order,
-                                          ckpt_stride(*p), d, backward != 0);
+                                          ckpt_stride(*p), d, backward != 0,
+                                          xb_words_of(*p, (int)(ly_pts - 1)));
     const int64_t npairs = std::max<int64_t>(1, nx * ny);
     int64_t P = gram_chunk(per, npairs, esize(*p), backward != 0, kDefaultCap, p->order);
     if (P <= 0) P = 1;
@@ -1411,7 +1464,7 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
     if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
     if (!X || !Y || !C || !ws) return fail(SK_EINVAL, "NULL pointer");
     const size_t es = esize(p);
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, false);
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, false, xb_words_of(p, (int)ly));
     const int64_t P = gram_chunk(per, npairs, es, false, ws_bytes, p.order);
     if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
     const Layout L = layout_for(scale(per, P), P, es, false, false, p.order);

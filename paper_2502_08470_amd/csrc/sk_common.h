@@ -53,6 +53,28 @@ __host__ __device__ inline SkGeom sk_make_geom(int32_t lx, int32_t ly) {
     return g;
 }
 
+// Strip-boundary exchange.  Lane 63 of strip s hands the right edge of each
+// column to lane 0 of strip s+1 (in the adjoint, lane 0 hands the adjoint of
+// the left edge back to lane 63 of strip s-1), Tp - 63 steps before it is
+// consumed.  Those edges wait in a ring of one entry per column: in LDS for
+// pairs up to a column count the host chooses per kernel (gx_cols), longer
+// pairs through a per-pair global buffer whose entries are staged through
+// LDS one 8-step block ahead (so long pairs do not cap occupancy through
+// their LDS).  The global protocol needs Tp > 78; the host never sets
+// gx_cols below SK_GX_MIN_COLS.
+#define SK_GX_BLOCK 8
+#define SK_GX_MIN_COLS 96
+__host__ __device__ constexpr int sk_ring_col_bytes_fwd(int N, int es) { return 16 + (N - 1) * es + 4; }
+__host__ __device__ constexpr int sk_ring_col_bytes_adj(int N, int es) { return (N + 1) * es + 4; }
+// 32-bit words of one global exchange record, rounded up to 16 bytes:
+// forward: FP64 coefficients 0 and 1, coefficients 2..N, exponent;
+// adjoint: coefficients 0..N, exponent
+__host__ __device__ constexpr int sk_gx_words(int N, int es) {
+    return ((4 + (N - 1) * es / 4 + 1 > (N + 1) * es / 4 + 1 ? 4 + (N - 1) * es / 4 + 1
+                                                             : (N + 1) * es / 4 + 1) + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int sk_gx_stage_bytes(int N, int es) { return SK_GX_BLOCK * sk_gx_words(N, es) * 4; }
+
 // Per-pair description.  Gram calls derive it from the pair index; list
 // (ragged) calls read it from a device array.
 struct SkPairDesc {
@@ -72,19 +94,23 @@ struct SkPairDesc {
     int64_t qe_off;   // strip-boundary exponents (int32 elements)
     int64_t dx_off;   // per-pair dL/d(dx) partials
     int64_t dy_off;   // per-pair, per-strip dL/d(dy) partials
+    int64_t xb_off;   // global strip-boundary exchange records (32-bit words)
 };
 
 // Per-pair workspace strides, all derived from the pair's geometry.
 struct SkPairSizes {
-    int64_t c, ck, ce, qb, qe, dx, dy;
+    int64_t c, ck, ce, qb, qe, dx, dy, xb;
 };
 
+// xb_words: 32-bit words per column of the pair's global exchange records
+// (0 when it needs none)
 __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int32_t lam,
                                                      int32_t N, int32_t S, int64_t d,
-                                                     bool backward) {
-    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0};
+                                                     bool backward, int xb_words) {
+    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0};
     SkGeom g = sk_make_geom(lx << lam, ly << lam);
     z.c = (int64_t)g.nsteps_pad * SK_LANES;
+    if (g.nsteps > 0) z.xb = (int64_t)ly * xb_words;
     if (backward && g.nsteps > 0) {
         int64_t nck = (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;
@@ -126,5 +152,6 @@ __host__ __device__ inline SkPairDesc sk_pair(const SkPairSrc& s, int64_t local)
     d.qe_off = local * s.stride.qe;
     d.dx_off = local * s.stride.dx;
     d.dy_off = local * s.stride.dy;
+    d.xb_off = local * s.stride.xb;
     return d;
 }

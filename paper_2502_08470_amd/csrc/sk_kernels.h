@@ -314,7 +314,38 @@ struct SweepArgs {
     int32_t* ce;
     R* qb;
     int32_t* qe;
+    unsigned* xb;          // global strip-boundary exchange records (long pairs)
+    int32_t gx_cols;       // pairs with more columns use the global exchange
 };
+
+// Global strip-boundary exchange, consumer side: at the start of every
+// 8-step block the wave (1) fences, so that the records stored by the
+// producing lane in earlier blocks are visible, (2) moves the records it
+// loaded one block earlier into the LDS staging slot, and (3) loads the
+// records the consuming lane will read in the next block.  `want(tau)`
+// gives the record index (column) the consumer reads at step tau, or -1.
+// A record is stored at least Tp - 63 - 15 steps before the block start
+// that loads it, so Tp > 78 (exchange pairs have more than SK_GX_MIN_COLS
+// columns) puts a fence between every store and its load.
+template <int W, typename F>
+__device__ __forceinline__ void sk_gx_stage(unsigned (&xr)[(8 * W + 63) / 64], unsigned* stage,
+                                            const unsigned* xg, int t_next, int r, F want) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+#pragma unroll
+    for (int h = 0; h < (8 * W + 63) / 64; ++h)
+        if (r + 64 * h < 8 * W) stage[r + 64 * h] = xr[h];
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < (8 * W + 63) / 64; ++h) {
+        const int w = r + 64 * h;
+        xr[h] = 0u;
+        if (w < 8 * W) {
+            const int m = w / W, q = w - m * W;
+            const int col = want(t_next + m);
+            if (col >= 0) xr[h] = xg[(int64_t)col * W + q];
+        }
+    }
+}
 
 template <typename R>
 __device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, double v, int E) {
@@ -335,7 +366,10 @@ __device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, dou
 // to the larger exponent (the smaller input loses only bits below the
 // working precision of the larger one).  Every 8 steps each lane rescales its
 // own state back into [2^-band, 2^band].
-template <typename R, int N, int TMAX, bool CKPT, int S>
+// GX: the launch may hold pairs whose strip-boundary edges go through the
+// global exchange (compiled separately so launches without such pairs keep
+// their register budget).
+template <typename R, int N, int TMAX, bool CKPT, int S, bool GX>
 __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     const int r = threadIdx.x;
     const int64_t local = blockIdx.x;
@@ -345,12 +379,25 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
         if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
         return;
     }
-    // LDS ring of strip-boundary edges: FP64 corners, coefficients 1..N,
-    // exponent tags
+    // strip-boundary edges (FP64 coefficients 0, 1, coefficients 2..N,
+    // exponent tags): an LDS ring of one entry per column, or for long pairs
+    // global records staged through LDS one block ahead
+    constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
+    const bool gx = GX && g.ly > a.gx_cols;  // wave-uniform
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    double* qlds0 = reinterpret_cast<double*>(sk_smem);          // [ly][2]
+    unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);                // [8][GXW]
+    double* qlds0 = reinterpret_cast<double*>(sk_smem + sk_gx_stage_bytes(N, ES));  // [ly][2]
     R* qlds = reinterpret_cast<R*>(qlds0 + 2 * (size_t)g.ly);     // [ly][N-1]
     int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N - 1));
+    unsigned* xg = a.xb + pd.xb_off;  // [ly][GXW] (exchange pairs only)
+    unsigned xr[(8 * GXW + 63) / 64];
+#pragma unroll
+    for (int h = 0; h < (8 * GXW + 63) / 64; ++h) xr[h] = 0u;
+    // column lane 0 reads at step tau (strips >= 1), or -1
+    auto lane0_col = [&](int tau) -> int {
+        const int s0 = tau / g.Tp, j0 = tau - s0 * g.Tp;
+        return (tau < g.nsteps && s0 >= 1 && s0 < g.nstrips && j0 < g.ly) ? j0 : -1;
+    };
     const R* cs = a.cskew + pd.c_off;
 
     R P[N + 1], Qs[N + 1];
@@ -368,6 +415,7 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) cb[u] = cs[u * 64 + r];
     for (int t0 = 0; t0 < nst8; t0 += 8) {
+        if (gx) sk_gx_stage<GXW>(xr, stage, xg, t0 + 8, r, lane0_col);
         if (t0 + 8 < g.nsteps_pad) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) cn[u] = cs[(int64_t)(t0 + 8 + u) * 64 + r];
@@ -397,6 +445,14 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 #pragma unroll
                         for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
                         Ein = 0;
+                    } else if (gx) {
+                        const unsigned* rec = stage + u * GXW;
+                        Qin0 = *reinterpret_cast<const double*>(rec);
+                        Qin1 = *reinterpret_cast<const double*>(rec + 2);
+#pragma unroll
+                        for (int n = 2; n <= N; ++n)
+                            Qin[n] = *reinterpret_cast<const R*>(rec + 4 + (n - 2) * (ES / 4));
+                        Ein = (int)rec[4 + (N - 1) * (ES / 4)];
                     } else {
                         Qin0 = qlds0[2 * j];
                         Qin1 = qlds0[2 * j + 1];
@@ -450,11 +506,21 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             Es = E;
             if (live) {
                 if (r == 63 && s + 1 < g.nstrips) {
-                    qlds0[2 * j] = Qo0;
-                    qlds0[2 * j + 1] = Qo1;
+                    if (gx) {
+                        unsigned* rec = xg + (int64_t)j * GXW;
+                        *reinterpret_cast<double*>(rec) = Qo0;
+                        *reinterpret_cast<double*>(rec + 2) = Qo1;
 #pragma unroll
-                    for (int n = 2; n <= N; ++n) qlds[j * (N - 1) + n - 2] = Qo[n];
-                    qtag[j] = E;
+                        for (int n = 2; n <= N; ++n)
+                            *reinterpret_cast<R*>(rec + 4 + (n - 2) * (ES / 4)) = Qo[n];
+                        rec[4 + (N - 1) * (ES / 4)] = (unsigned)E;
+                    } else {
+                        qlds0[2 * j] = Qo0;
+                        qlds0[2 * j + 1] = Qo1;
+#pragma unroll
+                        for (int n = 2; n <= N; ++n) qlds[j * (N - 1) + n - 2] = Qo[n];
+                        qtag[j] = E;
+                    }
                     if (CKPT) {
                         const int64_t o = (int64_t)(s + 1) * g.ly + j;
 #pragma unroll
@@ -522,22 +588,40 @@ struct AdjArgs {
     const R* qb;
     const int32_t* qe;
     R* gskew;              // out: skewed dL/dc
+    unsigned* xb;          // global strip-boundary exchange records (long pairs)
+    int32_t gx_cols;       // pairs with more columns use the global exchange
 };
 
 // Exponent of an adjoint vector that is zero by construction: below any
 // real exponent, so alignment to the larger exponent ignores it.
 #define SK_ZERO_EXP (-(1 << 29))
 
-template <typename R, int N, int TMAX, int S>
+template <typename R, int N, int TMAX, int S, bool GX>
 __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const int r = threadIdx.x;
     const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
     if (g.nsteps == 0) return;
+    // adjoint strip-boundary vectors handed from lane 0 of strip s to lane 63
+    // of strip s-1: LDS ring, or global records staged one block ahead
+    constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
+    const bool gx = GX && g.ly > a.gx_cols;  // wave-uniform
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    R* llds = reinterpret_cast<R*>(sk_smem);
+    unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
+    R* llds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES));
     int* ltag = reinterpret_cast<int*>(llds + (size_t)g.ly * (N + 1));
+    unsigned* xg = a.xb + pd.xb_off;
+    unsigned xr[(8 * GXW + 63) / 64];
+#pragma unroll
+    for (int h = 0; h < (8 * GXW + 63) / 64; ++h) xr[h] = 0u;
+    // column lane 63 reads at step tau (rows that are not the last), or -1
+    auto lane63_col = [&](int tau) -> int {
+        const int L63 = tau - 63;
+        if (tau < 0 || L63 < 0) return -1;
+        const int s6 = L63 / g.Tp, j6 = L63 - s6 * g.Tp, i6 = s6 * 64 + 63;
+        return (s6 < g.nstrips && j6 < g.ly && i6 < g.lx - 1) ? j6 : -1;
+    };
     const R* cs = a.cskew + pd.c_off;
     R* gs = a.gskew + pd.c_off;
     const R gk = a.gK[pd.g_idx];
@@ -554,6 +638,10 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const int nck = (g.nsteps + S - 1) / S;
     for (int kk = nck - 1; kk >= 0; --kk) {
         const int tau0 = kk * S;
+        // blocks of 8 steps, processed from the top; a segment never
+        // straddles two blocks (S divides 8)
+        if (gx && (kk == nck - 1 || ((tau0 + S) & 7) == 0))
+            sk_gx_stage<GXW>(xr, stage, xg, (tau0 & ~7) - 8, r, lane63_col);
         R cseg[S];
 #pragma unroll
         for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
@@ -677,7 +765,13 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                     ea = El;
                 }
                 if (!last_row) {
-                    if (r == 63) {
+                    if (r == 63 && gx) {
+                        const unsigned* rec = stage + (tau & 7) * GXW;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n)
+                            aq[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
+                        eb = (int)rec[(N + 1) * (ES / 4)];
+                    } else if (r == 63) {
 #pragma unroll
                         for (int n = 0; n <= N; ++n) aq[n] = llds[jj * (N + 1) + n];
                         eb = ltag[jj];
@@ -704,9 +798,16 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             El = Ec;
             Els = Ec;
             if (live && r == 0 && ss > 0) {
+                if (gx) {
+                    unsigned* rec = xg + (int64_t)jj * GXW;
 #pragma unroll
-                for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
-                ltag[jj] = Ec;
+                    for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(rec + n * (ES / 4)) = lqs[n];
+                    rec[(N + 1) * (ES / 4)] = (unsigned)Ec;
+                } else {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
+                    ltag[jj] = Ec;
+                }
             }
             gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, Ec + Est[u]) : (R)0;
             if ((tau & 7) == 0 && live) {
@@ -735,20 +836,21 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
 // Two entry points of the same body: where the register footprint allows it,
 // the compiler is asked to fit two waves per SIMD (the adjoint is latency
 // bound at one); elsewhere forcing it would spill to scratch.
-template <typename R, int N, int TMAX>
+template <typename R, int N, int TMAX, bool GX>
 constexpr bool sk_adj_two_waves() {
-    return sizeof(R) == 4 ? (TMAX == 0 || N <= 6) : (TMAX == 0 && N <= 6);
+    return sizeof(R) == 4 ? (GX ? (TMAX == 0 && N <= 6) : (TMAX == 0 || N <= 6))
+                          : (TMAX == 0 && N <= 6 && !GX);
 }
 
-template <typename R, int N, int TMAX, int S>
+template <typename R, int N, int TMAX, int S, bool GX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_adjoint_w2(const AdjArgs<R> a) {
-    sk_adjoint_body<R, N, TMAX, S>(a);
+    sk_adjoint_body<R, N, TMAX, S, GX>(a);
 }
 
-template <typename R, int N, int TMAX, int S>
+template <typename R, int N, int TMAX, int S, bool GX>
 __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
-    sk_adjoint_body<R, N, TMAX, S>(a);
+    sk_adjoint_body<R, N, TMAX, S, GX>(a);
 }
 
 // ---------------------------------------------------------------------------

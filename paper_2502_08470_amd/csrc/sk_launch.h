@@ -24,10 +24,13 @@ struct SkLaunch {
     // are unrefined segment counts
     static hipError_t gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
                                 hipStream_t st);
+    // ring: LDS ring columns of the launch (largest among its pairs that do
+    // not use the global strip-boundary exchange)
+    // gx: some pair of the launch uses the global strip-boundary exchange
     static hipError_t sweep(const SweepArgs<R>& a, int N, bool interp, bool ckpt, int64_t npairs,
-                            int max_ly, hipStream_t st);
-    static hipError_t adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs, int max_ly,
-                              hipStream_t st);
+                            int ring, bool gx, hipStream_t st);
+    static hipError_t adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs, int ring,
+                              bool gx, hipStream_t st);
     static hipError_t contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                hipStream_t st);
     static hipError_t reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st);
@@ -38,13 +41,16 @@ struct SkLaunch {
     static hipError_t plain_fd(const PlainArgs<R>& a, hipStream_t st);
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
-    // LDS bytes needed per workgroup by the sweep / adjoint for a given column count
-    // forward: 2 FP64 coefficients + N-1 coefficients + tag per column;
-    // adjoint: N+1 coefficients + tag per column
-    static size_t sweep_lds(int N, int ly) {
-        const size_t f = (size_t)ly * 16 + (size_t)ly * (N - 1) * sizeof(R) + (size_t)ly * 4;
-        const size_t b = (size_t)ly * (N + 1) * sizeof(R) + (size_t)ly * 4;
-        return f > b ? f : b;
+    // LDS bytes per workgroup: the global-exchange staging slot plus an LDS
+    // ring of `ring` columns (forward: 2 FP64 coefficients + N-1
+    // coefficients + tag per column; adjoint: N+1 coefficients + tag)
+    static size_t sweep_lds(int N, int ring) {
+        return (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)) +
+               (size_t)ring * sk_ring_col_bytes_fwd(N, (int)sizeof(R));
+    }
+    static size_t adjoint_lds(int N, int ring) {
+        return (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)) +
+               (size_t)ring * sk_ring_col_bytes_adj(N, (int)sizeof(R));
     }
     static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
     static size_t gram_pair_lds(int dpad, int max_lx, int max_ly) {

@@ -64,74 +64,86 @@ hipError_t SkLaunch<R>::gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, 
 }
 
 template <typename R, int N, int TMAX>
-static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int max_ly,
+static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
                              hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
-    size_t lds = SkLaunch<R>::sweep_lds(N, max_ly);
-    if (ckpt)
-        hipLaunchKernelGGL((k_sweep<R, N, TMAX, true, S>), dim3((unsigned)npairs), dim3(64), lds,
-                           st, a);
+    size_t lds = SkLaunch<R>::sweep_lds(N, ring);
+    dim3 grid((unsigned)npairs), blk(64);
+    if (ckpt && gx)
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, true, S, true>), grid, blk, lds, st, a);
+    else if (ckpt)
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, true, S, false>), grid, blk, lds, st, a);
+    else if (gx)
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, false, S, true>), grid, blk, lds, st, a);
     else
-        hipLaunchKernelGGL((k_sweep<R, N, TMAX, false, S>), dim3((unsigned)npairs), dim3(64), lds,
-                           st, a);
+        hipLaunchKernelGGL((k_sweep<R, N, TMAX, false, S, false>), grid, blk, lds, st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 template <typename R, int N>
 static hipError_t sk_sweep_t(const SweepArgs<R>& a, bool interp, bool ckpt, int64_t npairs,
-                             int max_ly, hipStream_t st) {
-    return interp ? sk_sweep_n<R, N, SkTailMax<R>::value>(a, ckpt, npairs, max_ly, st)
-                  : sk_sweep_n<R, N, 0>(a, ckpt, npairs, max_ly, st);
+                             int ring, bool gx, hipStream_t st) {
+    return interp ? sk_sweep_n<R, N, SkTailMax<R>::value>(a, ckpt, npairs, ring, gx, st)
+                  : sk_sweep_n<R, N, 0>(a, ckpt, npairs, ring, gx, st);
 }
 
 template <typename R>
 hipError_t SkLaunch<R>::sweep(const SweepArgs<R>& a, int N, bool interp, bool ckpt,
-                              int64_t npairs, int max_ly, hipStream_t st) {
+                              int64_t npairs, int ring, bool gx, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
     switch (N) {
-        case 2: return sk_sweep_t<R, 2>(a, interp, ckpt, npairs, max_ly, st);
-        case 3: return sk_sweep_t<R, 3>(a, interp, ckpt, npairs, max_ly, st);
-        case 4: return sk_sweep_t<R, 4>(a, interp, ckpt, npairs, max_ly, st);
-        case 5: return sk_sweep_t<R, 5>(a, interp, ckpt, npairs, max_ly, st);
-        case 6: return sk_sweep_t<R, 6>(a, interp, ckpt, npairs, max_ly, st);
-        case 7: return sk_sweep_t<R, 7>(a, interp, ckpt, npairs, max_ly, st);
-        case 8: return sk_sweep_t<R, 8>(a, interp, ckpt, npairs, max_ly, st);
+        case 2: return sk_sweep_t<R, 2>(a, interp, ckpt, npairs, ring, gx, st);
+        case 3: return sk_sweep_t<R, 3>(a, interp, ckpt, npairs, ring, gx, st);
+        case 4: return sk_sweep_t<R, 4>(a, interp, ckpt, npairs, ring, gx, st);
+        case 5: return sk_sweep_t<R, 5>(a, interp, ckpt, npairs, ring, gx, st);
+        case 6: return sk_sweep_t<R, 6>(a, interp, ckpt, npairs, ring, gx, st);
+        case 7: return sk_sweep_t<R, 7>(a, interp, ckpt, npairs, ring, gx, st);
+        case 8: return sk_sweep_t<R, 8>(a, interp, ckpt, npairs, ring, gx, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename R, int N, int TMAX>
-static hipError_t sk_adj_n(const AdjArgs<R>& a, int64_t npairs, int max_ly, hipStream_t st) {
+template <typename R, int N, int TMAX, bool GX>
+static hipError_t sk_adj_g(const AdjArgs<R>& a, int64_t npairs, int ring, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
-    size_t lds = SkLaunch<R>::sweep_lds(N, max_ly);
-    if constexpr (sk_adj_two_waves<R, N, TMAX>())
-        hipLaunchKernelGGL((k_adjoint_w2<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
+    size_t lds = SkLaunch<R>::adjoint_lds(N, ring);
+    if constexpr (sk_adj_two_waves<R, N, TMAX, GX>())
+        hipLaunchKernelGGL((k_adjoint_w2<R, N, TMAX, S, GX>), dim3((unsigned)npairs), dim3(64), lds,
+                           st, a);
     else
-        hipLaunchKernelGGL((k_adjoint<R, N, TMAX, S>), dim3((unsigned)npairs), dim3(64), lds, st, a);
+        hipLaunchKernelGGL((k_adjoint<R, N, TMAX, S, GX>), dim3((unsigned)npairs), dim3(64), lds,
+                           st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
 
-template <typename R, int N>
-static hipError_t sk_adj_t(const AdjArgs<R>& a, bool interp, int64_t npairs, int max_ly,
+template <typename R, int N, int TMAX>
+static hipError_t sk_adj_n(const AdjArgs<R>& a, int64_t npairs, int ring, bool gx,
                            hipStream_t st) {
-    return interp ? sk_adj_n<R, N, SkTailMax<R>::value>(a, npairs, max_ly, st)
-                  : sk_adj_n<R, N, 0>(a, npairs, max_ly, st);
+    return gx ? sk_adj_g<R, N, TMAX, true>(a, npairs, ring, st)
+              : sk_adj_g<R, N, TMAX, false>(a, npairs, ring, st);
+}
+
+template <typename R, int N>
+static hipError_t sk_adj_t(const AdjArgs<R>& a, bool interp, int64_t npairs, int ring, bool gx,
+                           hipStream_t st) {
+    return interp ? sk_adj_n<R, N, SkTailMax<R>::value>(a, npairs, ring, gx, st)
+                  : sk_adj_n<R, N, 0>(a, npairs, ring, gx, st);
 }
 
 template <typename R>
 hipError_t SkLaunch<R>::adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs,
-                                int max_ly, hipStream_t st) {
+                                int ring, bool gx, hipStream_t st) {
     if (npairs <= 0) return hipSuccess;
     switch (N) {
-        case 2: return sk_adj_t<R, 2>(a, interp, npairs, max_ly, st);
-        case 3: return sk_adj_t<R, 3>(a, interp, npairs, max_ly, st);
-        case 4: return sk_adj_t<R, 4>(a, interp, npairs, max_ly, st);
-        case 5: return sk_adj_t<R, 5>(a, interp, npairs, max_ly, st);
-        case 6: return sk_adj_t<R, 6>(a, interp, npairs, max_ly, st);
-        case 7: return sk_adj_t<R, 7>(a, interp, npairs, max_ly, st);
-        case 8: return sk_adj_t<R, 8>(a, interp, npairs, max_ly, st);
+        case 2: return sk_adj_t<R, 2>(a, interp, npairs, ring, gx, st);
+        case 3: return sk_adj_t<R, 3>(a, interp, npairs, ring, gx, st);
+        case 4: return sk_adj_t<R, 4>(a, interp, npairs, ring, gx, st);
+        case 5: return sk_adj_t<R, 5>(a, interp, npairs, ring, gx, st);
+        case 6: return sk_adj_t<R, 6>(a, interp, npairs, ring, gx, st);
+        case 7: return sk_adj_t<R, 7>(a, interp, npairs, ring, gx, st);
+        case 8: return sk_adj_t<R, 8>(a, interp, npairs, ring, gx, st);
         default: return hipErrorInvalidValue;
     }
 }
