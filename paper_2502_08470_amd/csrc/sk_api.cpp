@@ -77,7 +77,7 @@ struct ProfScope {
     } while (0)
 
 constexpr int64_t kAlign = 256;
-constexpr size_t kDefaultCap = (size_t)16 << 30;  // bytes of one default chunk
+constexpr size_t kDefaultCap = (size_t)64 << 30;  // bytes of one default chunk (of 288 GB HBM)
 
 inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -688,9 +688,11 @@ size_t sweep_lds_bytes(const sk_params& p, int ly) {
                              : SkLaunch<double>::sweep_lds(p.order, ly);
 }
 
-// Launch groups: pairs whose edges go through the global exchange, then LDS
-// rings up to 4, 8 and 16 KiB (and longer FD rings).
+// Launch groups: pairs whose edges go through the global exchange in the
+// adjoint (and the forward), in the forward only, then LDS rings up to 4, 8
+// and 17 KiB (and longer FD rings).
 int lds_class(const sk_params& p, int ly) {
+    if (p.scheme != SK_FD && ring_adj_of(p, ly) == 0) return 5;
     if (ring_fwd_of(p, ly) == 0) return 4;
     const size_t b = sweep_lds_bytes(p, ly);
     return b <= (4u << 10) ? 0 : b <= (8u << 10) ? 1 : b <= (17u << 10) ? 2 : 3;
@@ -744,57 +746,89 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     }
     P.max_ly = 0;
     for (int64_t i = 0; i < n; ++i) P.max_ly = std::max(P.max_ly, ey[i]);
-    // greedy chunks along the launch order, split at LDS classes and at the
-    // workspace capacity
+    // Chunks: within each LDS class (one class without buckets), as few
+    // chunks as the workspace allows, filled longest pair first into the
+    // chunk with the least work that still fits, so that every launch mixes
+    // long and short pairs (a chunk of only the longest pairs would leave
+    // most of the GPU idle).  Each chunk launches its pairs longest first.
     auto chunk = [&](bool bwd, std::vector<SkPairDesc>& desc, std::vector<PlanChunk>& chunks,
                      int64_t* scratch) -> int {
         desc.assign(n, SkPairDesc());
         chunks.clear();
         *scratch = 0;
-        PlanChunk cur = {0, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
-        SkPairSizes run = {0, 0, 0, 0, 0, 0, 0, 0};
-        auto close = [&]() {
-            if (cur.count == 0) return;
-            *scratch = std::max(*scratch, layout_for(cur.tot, cur.count, es, bwd, false, p.order).total);
-            chunks.push_back(cur);
-        };
-        for (int64_t k = 0; k < n; ++k) {
-            const int64_t i = seq[k];
-            const SkPairSizes z = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
-                                                xb_words_of(p, ey[i]));
-            const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
-            const bool new_class = cur.count > 0 && cfg.buckets && cls[i] != cls[seq[cur.first]];
-            const bool too_big = cur.count > 0 &&
-                (size_t)layout_for(add(cur.tot, z), cur.count + 1, es, bwd, false, p.order).total > cap;
-            if (new_class || too_big) {
-                close();
-                cur = {k, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
-                run = {0, 0, 0, 0, 0, 0, 0, 0};
+        std::vector<SkPairSizes> zs(n);
+        for (int64_t i = 0; i < n; ++i)
+            zs[i] = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
+                                  xb_words_of(p, ey[i]));
+        int64_t pos = 0;
+        for (int64_t g0 = 0; g0 < n;) {
+            int64_t g1 = g0 + 1;
+            while (g1 < n && (!cfg.buckets || cls[seq[g1]] == cls[seq[g0]])) ++g1;
+            // bins of this group
+            struct Bin { SkPairSizes tot; int64_t count, work; std::vector<int64_t> pairs; };
+            std::vector<Bin> bins;
+            SkPairSizes all = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int64_t k = g0; k < g1; ++k) all = add(all, zs[seq[k]]);
+            const int64_t total = layout_for(all, g1 - g0, es, bwd, false, p.order).total;
+            const int64_t nb = std::max<int64_t>(1, (int64_t)((double)total / (double)cap * 1.05) + 1);
+            bins.resize(total <= (int64_t)cap ? 1 : nb);
+            for (Bin& bn : bins) { bn.tot = {0, 0, 0, 0, 0, 0, 0, 0}; bn.count = 0; bn.work = 0; }
+            for (int64_t k = g0; k < g1; ++k) {
+                const int64_t i = seq[k];
+                if ((size_t)layout_for(zs[i], 1, es, bwd, false, p.order).total > cap)
+                    return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
+                int64_t best = -1;
+                for (int64_t q = 0; q < (int64_t)bins.size(); ++q) {
+                    const Bin& bn = bins[q];
+                    if ((size_t)layout_for(add(bn.tot, zs[i]), bn.count + 1, es, bwd, false, p.order).total > cap)
+                        continue;
+                    if (best < 0 || bn.work < bins[best].work) best = q;
+                }
+                if (best < 0) {
+                    bins.push_back(Bin());
+                    best = (int64_t)bins.size() - 1;
+                    bins[best].tot = {0, 0, 0, 0, 0, 0, 0, 0};
+                    bins[best].count = 0;
+                    bins[best].work = 0;
+                }
+                Bin& bn = bins[best];
+                bn.tot = add(bn.tot, zs[i]);
+                bn.count += 1;
+                bn.work += cost[i];
+                bn.pairs.push_back(i);
             }
-            if ((size_t)layout_for(z, 1, es, bwd, false, p.order).total > cap)
-                return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", ws_bytes);
-            SkPairDesc& q = desc[k];
-            q.x_off = sw[i] ? P.yo[i] : P.xo[i];
-            q.y_off = sw[i] ? P.xo[i] : P.yo[i];
-            q.lx = ex[i];
-            q.ly = ey[i];
-            q.swap = sw[i];
-            q.k_idx = i;
-            q.g_idx = i;
-            q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
-            q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy; q.xb_off = run.xb;
-            run = add(run, z);
-            cur.count += 1;
-            cur.tot = add(cur.tot, z);
-            cur.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
-            cur.max_lx = std::max(cur.max_lx, ex[i]);
-            cur.max_ly = std::max(cur.max_ly, ey[i]);
-            cur.max_strips = std::max(cur.max_strips, g.nstrips);
-            cur.ring_fwd = std::max(cur.ring_fwd, ring_fwd_of(p, ey[i]));
-            cur.ring_adj = std::max(cur.ring_adj, ring_adj_of(p, ey[i]));
-            cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
+            for (const Bin& bn : bins) {
+                if (bn.count == 0) continue;
+                PlanChunk cur = {pos, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
+                SkPairSizes run = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (const int64_t i : bn.pairs) {  // already longest first
+                    const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
+                    SkPairDesc& q = desc[pos++];
+                    q.x_off = sw[i] ? P.yo[i] : P.xo[i];
+                    q.y_off = sw[i] ? P.xo[i] : P.yo[i];
+                    q.lx = ex[i];
+                    q.ly = ey[i];
+                    q.swap = sw[i];
+                    q.k_idx = i;
+                    q.g_idx = i;
+                    q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
+                    q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy; q.xb_off = run.xb;
+                    run = add(run, zs[i]);
+                    cur.count += 1;
+                    cur.tot = add(cur.tot, zs[i]);
+                    cur.max_nsteps_pad = std::max(cur.max_nsteps_pad, g.nsteps_pad);
+                    cur.max_lx = std::max(cur.max_lx, ex[i]);
+                    cur.max_ly = std::max(cur.max_ly, ey[i]);
+                    cur.max_strips = std::max(cur.max_strips, g.nstrips);
+                    cur.ring_fwd = std::max(cur.ring_fwd, ring_fwd_of(p, ey[i]));
+                    cur.ring_adj = std::max(cur.ring_adj, ring_adj_of(p, ey[i]));
+                    cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
+                }
+                *scratch = std::max(*scratch, layout_for(cur.tot, cur.count, es, bwd, false, p.order).total);
+                chunks.push_back(cur);
+            }
+            g0 = g1;
         }
-        close();
         return SK_OK;
     };
     int64_t fs = 0, bs = 0;
