@@ -175,11 +175,15 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
 #pragma unroll
     for (int m = 1; m <= M; ++m) {
         cp[m] = cp[m - 1] * c;
-        w[m] = w[m - 1] * (c * (R)(1.0 / m));
+        // the sweep's state takes c^m/m! by its own recurrence (independent
+        // rounding of the Toeplitz and Hankel parts measured about twice as
+        // accurate); where FP32 accuracy is enough one multiply does
+        w[m] = HI ? w[m - 1] * (c * (R)(1.0 / m)) : cp[m] * ifact<R>(m);
     }
     if (WD) {
+        // rows 0..N-1 are always written; tail rows only when kept
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
+        for (int r = N; r < M; ++r) {
             DP[r] = (R)0;
             DQ[r] = (R)0;
         }
@@ -326,37 +330,38 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
 #pragma unroll
     for (int m = 1; m <= M; ++m) {
         cp[m] = cp[m - 1] * c;
-        w[m] = w[m - 1] * (c * (R)(1.0 / m));
+        w[m] = cp[m] * ifact<R>(m);  // gradients need FP32 accuracy only
     }
+    // row 0 initialises the outputs (w_0 = c^0 = 1)
+    aP[0] = a[0];
+    aQ[0] = b[0];
 #pragma unroll
-    for (int k = 0; k <= N; ++k) {
-        aP[k] = (R)0;
-        aQ[k] = (R)0;
+    for (int k = 1; k <= N; ++k) {
+        aP[k] = b[0] * ifact<R>(k);
+        aQ[k] = a[0] * ifact<R>(k);
     }
     R gacc = (R)0;
     // T is the same in every lane; reading it into a scalar register makes
     // the early exit a branch instead of masked execution of every tail row
     const int Tu = __builtin_amdgcn_readfirstlane(T);
 #pragma unroll
-    for (int r = 0; r <= M; ++r) {
+    for (int r = 1; r <= M; ++r) {
         if (r > N && r - N > Tu) break;
         R ea, eb;
         if (r <= N) {
             ea = a[r];
             eb = b[r];
         } else {
-            ea = (R)0;
-            eb = (R)0;
+            ea = tab.rs[0][r - N - 1] * a[0];
+            eb = tab.rs[0][r - N - 1] * b[0];
 #pragma unroll
-            for (int n = 0; n <= N; ++n) {
+            for (int n = 1; n <= N; ++n) {
                 ea = fma(tab.rs[n][r - N - 1], a[n], ea);
                 eb = fma(tab.rs[n][r - N - 1], b[n], eb);
             }
         }
-        if (r >= 1) {
-            gacc = fma(ea, DP[r - 1], gacc);
-            gacc = fma(eb, DQ[r - 1], gacc);
-        }
+        gacc = r == 1 ? ea * DP[0] : fma(ea, DP[r - 1], gacc);
+        gacc = fma(eb, DQ[r - 1], gacc);
 #pragma unroll
         for (int k = (r < N ? r : N); k >= 0; --k) {
             aP[k] = fma(w[r - k], ea, aP[k]);
