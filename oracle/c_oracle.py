@@ -12,7 +12,7 @@ import numpy as np
 
 from . import build as _build
 
-FD, APPROX, INTERP = 0, 1, 2
+FD, APPROX, INTERP, FD2 = 0, 1, 2, 3
 _lib = None
 
 

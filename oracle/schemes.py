@@ -8,6 +8,9 @@ fusion or reformulation:
 * ``fd_scheme``           -- Definition "Dyadic finite differences approximation
                              scheme" (Section 2), first-order explicit rule on
                              the lambda-refined grid.
+* ``fd2_scheme``          -- the second-order explicit rule of Remark
+                             "higherfd" (eq. secondexplicitscheme) on the same
+                             refined grid.
 * ``approx_cell``         -- Proposition "approxsolution" (eqs. powerseries1/2)
                              truncated at order N, i.e. the explicit map of the
                              remark after Definition "Polynomial approximation
@@ -55,6 +58,7 @@ __all__ = [
     "increments",
     "cell_constants",
     "fd_scheme",
+    "fd2_scheme",
     "approx_cell",
     "approx_scheme",
     "hyp0f1",
@@ -121,6 +125,32 @@ def fd_scheme(x, y, lam: int = 0) -> float:
             inner = np.dot(dxr[i], dyr[j])
             k[i + 1, j + 1] = (k[i + 1, j] + k[i, j + 1] - k[i, j]
                                + 0.5 * inner * (k[i + 1, j] + k[i, j + 1]))
+    return k[m, n]
+
+
+def fd2_scheme(x, y, lam: int = 0) -> float:
+    """Second-order explicit finite-difference scheme (Remark "higherfd",
+    eq. secondexplicitscheme) on the lambda-order dyadic refinement: the
+    first-order rule plus the c^2 term of the quadrature,
+
+        k(s_{i+1}, t_{j+1}) = k(s_{i+1}, t_j) + k(s_i, t_{j+1}) - k(s_i, t_j)
+                              + 1/2 c (k(s_{i+1}, t_j) + k(s_i, t_{j+1}))
+                              + 1/12 c^2 (k(s_{i+1}, t_j) + k(s_i, t_{j+1}) + k(s_i, t_j)),
+
+    with c = <dx_i, dy_j> of the refined pieces (the time steps cancel as in
+    the first-order rule)."""
+    dx, dy = increments(x), increments(y)
+    r = 2 ** lam
+    dxr = np.repeat(dx / r, r, axis=0)
+    dyr = np.repeat(dy / r, r, axis=0)
+    m, n = len(dxr), len(dyr)
+    k = np.ones((m + 1, n + 1), dtype=np.result_type(dx, dy))
+    for i in range(m):
+        for j in range(n):
+            c = np.dot(dxr[i], dyr[j])
+            k[i + 1, j + 1] = (k[i + 1, j] + k[i, j + 1] - k[i, j]
+                               + 0.5 * c * (k[i + 1, j] + k[i, j + 1])
+                               + c * c / 12.0 * (k[i + 1, j] + k[i, j + 1] + k[i, j]))
     return k[m, n]
 
 

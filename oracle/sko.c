@@ -4,6 +4,8 @@
  *
  * Written from "Numerical Schemes for Signature Kernels" (Cass, Piatti, Pei):
  *   - sko_fd:      Definition "Dyadic finite differences approximation scheme"
+ *   - sko_fd2:     the second-order explicit rule of Remark "higherfd"
+ *                  (eq. secondexplicitscheme) on the same refined grid
  *                  (Section 2), first-order explicit rule, lambda-refined grid.
  *   - sko_approx:  Definition "Polynomial approximation numerical scheme"
  *                  (Section 3.2) with the explicit truncated map of the remark
@@ -63,8 +65,8 @@ static double dot(const double* a, const double* b, int64_t d) {
 /* ------------------------------------------------------------------------ */
 /* Finite differences                                                        */
 /* ------------------------------------------------------------------------ */
-int sko_fd(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
-           int lam, double* mant, int64_t* expo) {
+static int fd_rule(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
+                   int lam, int second, double* mant, int64_t* expo) {
     if (nx_pts < 1 || ny_pts < 1 || d < 1 || lam < 0 || lam > 12) return -1;
     int64_t lx = nx_pts - 1, ly = ny_pts - 1;
     *expo = 0;
@@ -84,12 +86,24 @@ int sko_fd(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int
             /* refined increments are the segment increments divided by 2^lam */
             double inner = dot(dx + (i / r) * d, dy + (j / r) * d, d) / (double)(r * r);
             cur[j + 1] = cur[j] + prev[j + 1] - prev[j] + 0.5 * inner * (cur[j] + prev[j + 1]);
+            if (second) /* + c^2/12 (k(s_{i+1},t_j) + k(s_i,t_{j+1}) + k(s_i,t_j)) */
+                cur[j + 1] += inner * inner / 12.0 * (cur[j] + prev[j + 1] + prev[j]);
         }
         double* t = prev; prev = cur; cur = t;
     }
     *mant = prev[n];
     free(dx); free(dy); free(prev); free(cur);
     return 0;
+}
+
+int sko_fd(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
+           int lam, double* mant, int64_t* expo) {
+    return fd_rule(x, nx_pts, y, ny_pts, d, lam, 0, mant, expo);
+}
+
+int sko_fd2(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
+            int lam, double* mant, int64_t* expo) {
+    return fd_rule(x, nx_pts, y, ny_pts, d, lam, 1, mant, expo);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -272,7 +286,7 @@ int sko_interp(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
 /* ------------------------------------------------------------------------ */
 /* Batches (OpenMP over pairs)                                               */
 /* ------------------------------------------------------------------------ */
-enum { SKO_FD = 0, SKO_APPROX = 1, SKO_INTERP = 2 };
+enum { SKO_FD = 0, SKO_APPROX = 1, SKO_INTERP = 2, SKO_FD2 = 3 };
 
 static int run_one(int scheme, int order, const double* x, int64_t nx, const double* y,
                    int64_t ny, int64_t d, double* mant, int64_t* expo) {
@@ -280,6 +294,7 @@ static int run_one(int scheme, int order, const double* x, int64_t nx, const dou
         case SKO_FD: return sko_fd(x, nx, y, ny, d, order, mant, expo);
         case SKO_APPROX: return sko_approx(x, nx, y, ny, d, order, mant, expo);
         case SKO_INTERP: return sko_interp(x, nx, y, ny, d, order, mant, expo);
+        case SKO_FD2: return sko_fd2(x, nx, y, ny, d, order, mant, expo);
         default: return -1;
     }
 }

@@ -70,6 +70,17 @@ def test_one_cell_finite_difference(c):
     assert C.value(m, e)[0, 0] == pytest.approx(1.0 + c, rel=1e-15, abs=1e-15)
 
 
+@pytest.mark.parametrize("c", CS)
+def test_one_cell_second_order_finite_difference(c):
+    # Remark "higherfd", eq. secondexplicitscheme, lambda = 0: the c^2 term adds
+    # c^2/12 (1 + 1 + 1), so k(1,1) = 1 + c + c^2/4.
+    x, y = one_cell(c)
+    want = 1.0 + c + c * c / 4.0
+    assert S.fd2_scheme(x, y, 0) == pytest.approx(want, rel=1e-15, abs=1e-15)
+    m, e = C.gram(x[None], y[None], C.FD2, 0)
+    assert C.value(m, e)[0, 0] == pytest.approx(want, rel=1e-15, abs=1e-15)
+
+
 def first_row_closed_form(cs, N):
     """One x-segment against a y-polyline whose cells have constants cs.
 

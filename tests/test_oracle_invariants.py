@@ -76,6 +76,31 @@ def test_fd_converges_at_second_order_rate():
     assert np.all(np.abs(ratios - 4.0) < 0.35), ratios
 
 
+def test_second_order_fd_is_more_accurate_and_converges():
+    # Remark "higherfd": the extra c^2 term of the quadrature shrinks the
+    # error constant, and on the dyadic refinement the error still falls at
+    # least like 4^-lambda (two refinement levels cut it by 8 or more; the
+    # ratio of single levels approaches 4 but can jump where the error's
+    # leading terms cancel).
+    for seed in (0, 5):
+        rng = np.random.default_rng(seed)
+        x, y = bm(rng, 3, 2, 0.5), bm(rng, 3, 2, 0.5)
+        exact = S.approx_scheme(x, y, 24)
+        e1 = [abs(C.value(*C.gram(x[None], y[None], C.FD, lam))[0, 0] - exact) for lam in range(7)]
+        e2 = [abs(C.value(*C.gram(x[None], y[None], C.FD2, lam))[0, 0] - exact) for lam in range(7)]
+        assert all(b < a / 3 for a, b in zip(e1, e2)), (e1, e2)
+        assert all(e2[lam + 2] <= e2[lam] / 8 for lam in range(2, 5)), e2
+
+
+def test_second_order_fd_symmetric_and_c_matches_numpy():
+    rng = np.random.default_rng(7)
+    x, y = bm(rng, 4, 3, 0.5), bm(rng, 6, 3, 0.5)
+    for lam in (0, 1, 2):
+        a = S.fd2_scheme(x, y, lam)
+        assert S.fd2_scheme(y, x, lam) == pytest.approx(a, rel=1e-14)
+        assert C.value(*C.gram(x[None], y[None], C.FD2, lam))[0, 0] == pytest.approx(a, rel=1e-13)
+
+
 def test_approx_error_decreases_with_order():
     rng = np.random.default_rng(6)
     x, y = bm(rng, 8, 2, 0.4), bm(rng, 8, 2, 0.4)
