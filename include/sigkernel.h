@@ -17,6 +17,10 @@
  *   SK_POLY_INTERP  polynomial interpolation scheme of order N at the N+1
  *                   Chebyshev extrema (Section 3.3, Definition "Polynomial
  *                   interpolation numerical scheme"); `order` = N.
+ *   SK_FD2          second-order explicit finite differences (Remark
+ *                   "higherfd", eq. secondexplicitscheme: the first-order
+ *                   rule plus c^2/12 times the three known corners) on the
+ *                   lambda-order dyadic refinement; `order` = lambda.
  *
  * Paths are given by their points only: the time partition drops out of all
  * schemes once each cell is normalised to the unit square, so only the cell
@@ -70,6 +74,7 @@ extern "C" {
 #define SK_FD 0
 #define SK_POLY_APPROX 1
 #define SK_POLY_INTERP 2
+#define SK_FD2 3
 
 /* element / arithmetic type of paths, outputs and the cell sweep */
 #define SK_F64 0
@@ -102,9 +107,9 @@ extern "C" {
 #define SK_MAX_BACKWARD_DIM 64
 
 typedef struct sk_params {
-    int32_t scheme; /* SK_FD, SK_POLY_APPROX or SK_POLY_INTERP                      */
+    int32_t scheme; /* SK_FD, SK_POLY_APPROX, SK_POLY_INTERP or SK_FD2              */
     int32_t order;  /* N in [SK_MIN_POLY_ORDER, SK_MAX_POLY_ORDER] for the polynomial
-                       schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD          */
+                       schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD, SK_FD2  */
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
     int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
     int32_t gram;   /* SK_GRAM_NATIVE or SK_GRAM_BF16X3 (batched algorithm)           */

@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-_SCHEMES = {"fd": L.SK_FD, "approx": L.SK_POLY_APPROX, "interp": L.SK_POLY_INTERP}
+_SCHEMES = {"fd": L.SK_FD, "fd2": L.SK_FD2, "approx": L.SK_POLY_APPROX,
+            "interp": L.SK_POLY_INTERP}
 _ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN}
 _GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3}
 
@@ -355,7 +356,7 @@ class SigKernelGram(torch.autograd.Function):
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
         ctx.state = None
-        if scheme != "fd" and (X.requires_grad or Y.requires_grad):
+        if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
             if gram_state_size(X, Y, scheme, order, gram_mode) <= _state_budget(X.device):
                 K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode)
                 return K

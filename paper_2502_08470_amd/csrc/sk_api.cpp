@@ -169,12 +169,14 @@ SkTab<R> table_for(const sk_params& p) {
 // ---------------------------------------------------------------------------
 // argument checks
 // ---------------------------------------------------------------------------
+bool is_fd(const sk_params& p) { return p.scheme == SK_FD || p.scheme == SK_FD2; }
+
 int check_params(const sk_params* p, bool backward) {
     if (!p) return fail(SK_EINVAL, "params is NULL");
     if (p->dtype != SK_F32 && p->dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", p->dtype);
     if (p->algo != SK_ALGO_BATCHED && p->algo != SK_ALGO_PLAIN)
         return fail(SK_EINVAL, "algo %d", p->algo);
-    if (p->scheme == SK_FD) {
+    if (is_fd(*p)) {
         if (p->order < 0) return fail(SK_EINVAL, "dyadic order %d < 0", p->order);
         if (p->order > SK_MAX_DYADIC_ORDER)
             return fail(SK_EUNSUPPORTED, "dyadic order %d > %d", p->order, SK_MAX_DYADIC_ORDER);
@@ -245,7 +247,7 @@ int check_offsets(const int64_t* off, int64_t npairs, int lam, const char* what)
 }
 
 size_t esize(const sk_params& p) { return p.dtype == SK_F32 ? 4 : 8; }
-int lam_of(const sk_params& p) { return p.scheme == SK_FD ? p.order : 0; }
+int lam_of(const sk_params& p) { return is_fd(p) ? p.order : 0; }
 // LDS budgets of the strip-boundary rings; pairs that would need more pass
 // their edges through the global exchange.  The forward sweep (about five
 // waves per SIMD by registers) loses occupancy to its ring beyond ~16 KiB;
@@ -261,12 +263,12 @@ int gx_cols_adj(const sk_params& p) {
 }
 // words per column of a pair's global exchange records (0: none needed)
 int xb_words_of(const sk_params& p, int ly) {
-    if (p.scheme == SK_FD) return 0;
+    if (is_fd(p)) return 0;
     return ly > std::min(gx_cols_fwd(p), gx_cols_adj(p)) ? sk_gx_words(p.order, (int)esize(p)) : 0;
 }
 // LDS ring columns a pair with ly columns needs (0: global exchange)
 int ring_fwd_of(const sk_params& p, int ly) {
-    return (p.scheme != SK_FD && ly > gx_cols_fwd(p)) ? 0 : ly;
+    return (!is_fd(p) && ly > gx_cols_fwd(p)) ? 0 : ly;
 }
 int ring_adj_of(const sk_params& p, int ly) { return ly > gx_cols_adj(p) ? 0 : ly; }
 int ckpt_stride(const sk_params& p) {
@@ -369,9 +371,10 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
     SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
-    if (p.scheme == SK_FD) {
+    if (is_fd(p)) {
         FdArgs<R> fa;
         fa.src = src; fa.lam = lam; fa.cskew = cskew; fa.K = K; fa.Kexp = Kexp;
+        fa.second = p.scheme == SK_FD2;
         SK_LAUNCH("fd_sweep", st, SkLaunch<R>::sweep_fd(fa, P, max_ly << lam, st), "finite-difference sweep");
     } else {
         SweepArgs<R> sa;
@@ -390,7 +393,7 @@ template <typename R>
 int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
     size_t lim = 0;
     SK_TRY_HIP(lds_limit(&lim), "device query");
-    size_t need = p.scheme == SK_FD
+    size_t need = is_fd(p)
                       ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
                       : std::max(SkLaunch<R>::sweep_lds(p.order, std::min<int>((int)max_ly, gx_cols_fwd(p))),
                                  SkLaunch<R>::adjoint_lds(p.order, std::min<int>((int)max_ly, gx_cols_adj(p))));
@@ -417,6 +420,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
         pa.d = d; pa.lx = (int)lx; pa.ly = (int)ly; pa.lam = lam;
         pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
         pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
+        pa.second = p.scheme == SK_FD2;
         for (int64_t a = 0; a < nx; ++a)
             for (int64_t b = 0; b < ny; ++b) {
                 pa.x = X + a * lxp * d; pa.y = Y + b * lyp * d; pa.k_idx = a * ny + b;
@@ -425,7 +429,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
                     if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + pa.k_idx), 1, st), "fill");
                     continue;
                 }
-                if (p.scheme == SK_FD)
+                if (is_fd(p))
                     SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
                 else
                     SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
@@ -683,7 +687,7 @@ struct PlanImpl {
 };
 
 size_t sweep_lds_bytes(const sk_params& p, int ly) {
-    if (p.scheme == SK_FD) return (size_t)(ly << lam_of(p)) * esize(p);
+    if (is_fd(p)) return (size_t)(ly << lam_of(p)) * esize(p);
     return p.dtype == SK_F32 ? SkLaunch<float>::sweep_lds(p.order, ly)
                              : SkLaunch<double>::sweep_lds(p.order, ly);
 }
@@ -692,7 +696,7 @@ size_t sweep_lds_bytes(const sk_params& p, int ly) {
 // adjoint (and the forward), in the forward only, then LDS rings up to 4, 8
 // and 17 KiB (and longer FD rings).
 int lds_class(const sk_params& p, int ly) {
-    if (p.scheme != SK_FD && ring_adj_of(p, ly) == 0) return 5;
+    if (!is_fd(p) && ring_adj_of(p, ly) == 0) return 5;
     if (ring_fwd_of(p, ly) == 0) return 4;
     const size_t b = sweep_lds_bytes(p, ly);
     return b <= (4u << 10) ? 0 : b <= (8u << 10) ? 1 : b <= (17u << 10) ? 2 : 3;
@@ -1049,6 +1053,7 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
     PlainArgs<R> pa;
     std::memset(&pa, 0, sizeof(pa));
     pa.d = d; pa.lam = lam; pa.tab = table_for<R>(p); pa.K = K; pa.Kexp = Kexp;
+    pa.second = p.scheme == SK_FD2;
     pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
     for (int64_t i = 0; i < npairs; ++i) {
         const int64_t lx = xo[i + 1] - xo[i] - 1, ly = yo[i + 1] - yo[i] - 1;
@@ -1061,7 +1066,7 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
             if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp + i), 1, st), "fill");
             continue;
         }
-        if (p.scheme == SK_FD)
+        if (is_fd(p))
             SK_LAUNCH("plain", st, SkLaunch<R>::plain_fd(pa, st), "plain finite differences");
         else
             SK_LAUNCH("plain", st, SkLaunch<R>::plain_poly(pa, p.order, p.scheme == SK_POLY_INTERP, st),
@@ -1250,7 +1255,7 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
     if (rc) return rc;
-    if (p->scheme == SK_FD) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
+    if (is_fd(*p)) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
     if (op != SK_OP_GRAM && op != SK_OP_PAIRS) return fail(SK_EINVAL, "op %d", op);
     if (nx < 0 || (op == SK_OP_GRAM && ny < 0)) return fail(SK_EINVAL, "negative batch");
     if (op == SK_OP_GRAM) {

@@ -1101,6 +1101,7 @@ template <typename R>
 struct FdArgs {
     SkPairSrc src;
     int32_t lam;
+    int32_t second;   // second-order explicit rule (adds the c^2 term)
     const R* cskew;   // skewed refined constants c / 4^lam
     R* K;
     int32_t* Kexp;
@@ -1142,6 +1143,7 @@ __global__ __launch_bounds__(64) void k_sweep_fd(const FdArgs<R> a) {
                 kij = (s == 0 || j == 0) ? (R)1 : blds[j - 1];
             }
             out = kown + b - kij + (R)0.5 * c * (kown + b);
+            if (a.second) out = fma(c * c * (R)(1.0 / 12.0), kown + b + kij, out);
             kown = out;
             bprev = b;
             if (r == 63 && s + 1 < g.nstrips) blds[j] = out;
@@ -1168,6 +1170,7 @@ struct PlainArgs {
     int64_t d;
     int32_t lx, ly;    // segments
     int32_t lam;
+    int32_t second;    // finite differences: second-order explicit rule
     R* pst;            // polynomial: [lx][N+1] bottom edges, [ly][N+1] left edges
     R* diag;           // finite differences: 3 rotating node diagonals of length lx*2^lam + 1
     SkTab<R> tab;
@@ -1244,7 +1247,8 @@ __global__ __launch_bounds__(256) void k_plain_fd(const PlainArgs<R> a) {
             const int j = dg - i;
             const R c = sk_dot_inc(a.x, a.y, a.d, i >> a.lam, j >> a.lam) * sc;
             const R k00 = d0[i], k10 = d1[i + 1], k01 = d1[i];
-            const R k11 = k10 + k01 - k00 + (R)0.5 * c * (k10 + k01);
+            R k11 = k10 + k01 - k00 + (R)0.5 * c * (k10 + k01);
+            if (a.second) k11 = fma(c * c * (R)(1.0 / 12.0), k10 + k01 + k00, k11);
             d2[i + 1] = k11;
             if (i == m - 1 && j == n - 1) sk_write_k(a.K, a.Kexp, a.k_idx, k11, 0);
         }

@@ -5,7 +5,7 @@ import numpy as np
 
 from oracle import c_oracle as C
 
-SCHEME_ID = {"fd": C.FD, "approx": C.APPROX, "interp": C.INTERP}
+SCHEME_ID = {"fd": C.FD, "fd2": C.FD2, "approx": C.APPROX, "interp": C.INTERP}
 
 
 def oracle_gram(X, Y, scheme, order):

@@ -76,6 +76,7 @@ def test_backward_rejections():
         return lib.sigkernel_backward(op, vp(1), None, 2, 10, vp(1), None, 2, 10, d, p, vp(1),
                                       None, vp(1), vp(1), vp(1), 1 << 30, None)
     assert bwd(P(scheme=0, order=0)) == L.SK_EUNSUPPORTED
+    assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL

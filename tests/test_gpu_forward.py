@@ -74,7 +74,8 @@ def test_bf16x3_gram_matches_oracle_and_fp32(sk):
 # small FP64 Gram: 8x8, R^3 + time, 64 steps; approximation N=4 and FD lambda=0
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("algo", ["batched", "plain"])
-@pytest.mark.parametrize("scheme,order", [("approx", 4), ("fd", 0), ("interp", 4), ("fd", 2)])
+@pytest.mark.parametrize("scheme,order", [("approx", 4), ("fd", 0), ("interp", 4), ("fd", 2),
+                                          ("fd2", 0), ("fd2", 2)])
 def test_small_fp64_gram(sk, algo, scheme, order):
     import workloads as W
     log_banner(f"small_fp64_gram {algo} {scheme} {order}")
@@ -166,3 +167,28 @@ def test_pairs_uneven_lengths(sk, dtype, tol):
     m, e = C.pairs(xs, ys, C.INTERP, 5)
     err = rel_err(k2.cpu().numpy(), np.ldexp(m, e))
     assert err.max() < tol, err
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-8)])
+def test_second_order_fd_pairs_and_fp32(sk, dtype, tol):
+    # ragged pairs (several strips, a one-point path) through the batched
+    # second-order rule, against the oracle.  FP32: the recurrence carries
+    # every node's rounding to all later nodes, so the error grows about
+    # linearly with the refined cell count (a float32 emulation of the rule
+    # itself is 4.3e-5 off on the 140 x 90 pair); the bound is tol per cell.
+    from oracle import c_oracle as C
+    log_banner(f"fd2 pairs {dtype}")
+    rng = np.random.default_rng(71)
+    lens_x, lens_y = [70, 1, 140, 9], [33, 20, 90, 200]
+    xs = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0] for n in lens_x]
+    ys = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0] for n in lens_y]
+    if dtype == torch.float32:
+        xs = [a.astype(np.float32).astype(np.float64) for a in xs]
+        ys = [b.astype(np.float32).astype(np.float64) for b in ys]
+    for lam in (0, 1):
+        k = sk.pairs([dev(a, dtype) for a in xs], [dev(b, dtype) for b in ys], "fd2", lam)
+        m, e = C.pairs(xs, ys, C.FD2, lam)
+        err = rel_err(k.cpu().numpy(), np.ldexp(m, e))
+        cells = np.array([(a - 1) * (b - 1) for a, b in zip(lens_x, lens_y)], float) * 4 ** lam
+        bound = tol * (cells if dtype == torch.float32 else 1.0)
+        assert np.all(err <= bound), (lam, err)
