@@ -69,6 +69,8 @@ __all__ = [
     "truncated_signature_kernel",
     "gram",
     "mmd2_unbiased",
+    "mmd_permutation_stats",
+    "mmd_permutation_pvalue",
 ]
 
 
@@ -404,3 +406,25 @@ def mmd2_unbiased(Kxx: np.ndarray, Kyy: np.ndarray, Kxy: np.ndarray) -> float:
     syy = (Kyy.sum() - np.trace(Kyy)) / (m * (m - 1))
     sxy = Kxy.mean()
     return float(sxx + syy - 2.0 * sxy)
+
+
+def mmd_permutation_stats(Kzz: np.ndarray, m: int, perms: np.ndarray) -> np.ndarray:
+    """Unbiased MMD^2 of every relabelling of a pooled sample (the permutation
+    two-sample test the paper's library offers with its MMD tools; the test
+    itself is the standard one, the paper gives no formula).
+
+    Kzz: (m+n) x (m+n) Gram matrix of the pooled paths; perms: rows that are
+    permutations of 0..m+n-1, whose first m entries form the first sample.
+    Returns one statistic per row."""
+    out = np.empty(len(perms))
+    for p, pi in enumerate(np.asarray(perms)):
+        a, b = pi[:m], pi[m:]
+        out[p] = mmd2_unbiased(Kzz[np.ix_(a, a)], Kzz[np.ix_(b, b)], Kzz[np.ix_(a, b)])
+    return out
+
+
+def mmd_permutation_pvalue(stats: np.ndarray) -> float:
+    """p-value of the statistic stats[0] (the observed split) against the
+    permutation statistics stats[1:]: (1 + #{stats[1:] >= stats[0]}) / len(stats)."""
+    stats = np.asarray(stats)
+    return float((1 + np.count_nonzero(stats[1:] >= stats[0])) / len(stats))

@@ -191,3 +191,31 @@ def test_mmd_unbiased_linear_kernel():
     want = ((sx @ sx - (X * X).sum()) / 30 + (sy @ sy - (Y * Y).sum()) / 20
             - 2 * (X.mean(0) @ Y.mean(0)))
     assert S.mmd2_unbiased(Kxx, Kyy, Kxy) == pytest.approx(want, rel=1e-13)
+
+
+def test_mmd_permutation_statistics_pins():
+    # The unbiased MMD^2 of a relabelled pooled sample, checked against an
+    # explicit double loop over its definition, and its invariances: any
+    # reordering inside the two groups leaves it unchanged, and with equal
+    # sizes exchanging the groups does too.
+    rng = np.random.default_rng(21)
+    m, n = 4, 5
+    A = rng.normal(size=(m + n, 3))
+    K = np.exp(-((A[:, None, :] - A[None, :, :]) ** 2).sum(-1))  # any symmetric Gram
+    perms = np.stack([rng.permutation(m + n) for _ in range(6)] + [np.arange(m + n)])
+    got = S.mmd_permutation_stats(K, m, perms)
+    for p, pi in enumerate(perms):
+        X, Y = pi[:m], pi[m:]
+        sxx = sum(K[a, b] for a in X for b in X if a != b) / (m * (m - 1))
+        syy = sum(K[a, b] for a in Y for b in Y if a != b) / (n * (n - 1))
+        sxy = sum(K[a, b] for a in X for b in Y) / (m * n)
+        assert got[p] == pytest.approx(sxx + syy - 2 * sxy, rel=1e-13, abs=1e-15)
+    pi = perms[0]
+    shuffled = np.concatenate([rng.permutation(pi[:m]), rng.permutation(pi[m:])])
+    assert S.mmd_permutation_stats(K, m, shuffled[None])[0] == pytest.approx(got[0], rel=1e-13)
+    K2 = K[:8, :8]
+    pi = rng.permutation(8)
+    swapped = np.concatenate([pi[4:], pi[:4]])
+    a, b = S.mmd_permutation_stats(K2, 4, np.stack([pi, swapped]))
+    assert a == pytest.approx(b, rel=1e-13)
+    assert S.mmd_permutation_pvalue([0.5, 0.1, 0.7, 0.5, 0.2]) == pytest.approx(3 / 5)
