@@ -225,6 +225,28 @@ int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t
 void sigkernel_plan_destroy(sk_plan* plan);
 
 /*
+ * Permutation two-sample test on the unbiased MMD^2 (the statistical testing
+ * the paper's library offers with its MMD tools; the procedure is the
+ * standard permutation test).
+ *   Kzz: (m + n) x (m + n) Gram matrix of the pooled paths (first sample
+ *   then second), row-major, dtype SK_F32 or SK_F64, device.
+ *   perms: nperm rows of m + n int32, device; each row a permutation of
+ *   0..m+n-1 whose first m entries form the first group.  Row 0 should be
+ *   the identity (the observed split); the caller draws the others.
+ *   stats: nperm outputs (dtype), stats[p] = unbiased MMD^2 of split p,
+ *   within-group diagonals excluded, accumulated in FP64.
+ *   p_value: nullable device double, (1 + #{p >= 1 : stats[p] >= stats[0]})
+ *   / nperm.
+ * Errors: SK_EINVAL for m < 2, n < 2, nperm < 1, a NULL pointer or a bad
+ * dtype; SK_EUNSUPPORTED above 2^20 pooled paths.  The rows of perms are not
+ * checked: the first group of a row is the set of its first m entries that
+ * lie in 0..m+n-1, every other path is in the second group.
+ */
+int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32_t* perms,
+                              int64_t nperm, int32_t dtype, void* stats, double* p_value,
+                              hipStream_t stream);
+
+/*
  * Forward and backward of a Gram call with the backward's state kept in
  * between (trading memory for the recomputation sigkernel_backward does).
  * sigkernel_gram_save computes K (and K_exp) like sigkernel_gram with the

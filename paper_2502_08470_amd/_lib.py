@@ -42,6 +42,7 @@ EXPORTS = (
     "sigkernel_plan_config",
     "sigkernel_plan_configure",
     "sigkernel_plan_destroy",
+    "sigkernel_mmd_permutation",
 )
 
 
@@ -111,6 +112,8 @@ def lib():
     L.sigkernel_plan_configure.restype = ctypes.c_int
     L.sigkernel_plan_destroy.argtypes = [vp]
     L.sigkernel_plan_destroy.restype = None
+    L.sigkernel_mmd_permutation.argtypes = [vp, i64, i64, vp, i64, i32, vp, vp, vp]
+    L.sigkernel_mmd_permutation.restype = ctypes.c_int
     L.sigkernel_error_string.argtypes = [ctypes.c_int]
     L.sigkernel_error_string.restype = ctypes.c_char_p
     L.sigkernel_last_error.argtypes = []

@@ -1426,6 +1426,33 @@ int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t
 
 void sigkernel_plan_destroy(sk_plan* plan) { delete plan; }
 
+int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32_t* perms,
+                              int64_t nperm, int32_t dtype, void* stats, double* p_value,
+                              hipStream_t stream) {
+    g_last_error.clear();
+    if (dtype != SK_F32 && dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", dtype);
+    if (m < 2 || n < 2) return fail(SK_EINVAL, "each sample needs at least 2 paths (m=%lld, n=%lld)",
+                                    (long long)m, (long long)n);
+    if (m + n > (1 << 20)) return fail(SK_EUNSUPPORTED, "pooled sample above 2^20 paths");
+    if (nperm < 1) return fail(SK_EINVAL, "nperm %lld < 1", (long long)nperm);
+    if (!Kzz || !perms || !stats) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (dtype == SK_F32)
+            SK_LAUNCH("mmd_perm", stream,
+                      SkLaunch<float>::mmd_perm((const float*)Kzz, m, n, perms, nperm,
+                                                (float*)stats, p_value, stream),
+                      "MMD permutation statistics");
+        else
+            SK_LAUNCH("mmd_perm", stream,
+                      SkLaunch<double>::mmd_perm((const double*)Kzz, m, n, perms, nperm,
+                                                 (double*)stats, p_value, stream),
+                      "MMD permutation statistics");
+        return SK_OK;
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p) {
     g_last_error.clear();

@@ -1260,6 +1260,65 @@ __global__ __launch_bounds__(256) void k_plain_fd(const PlainArgs<R> a) {
 }
 
 // ---------------------------------------------------------------------------
+// MMD permutation two-sample test
+// ---------------------------------------------------------------------------
+// One workgroup per permutation p of the pooled sample (m + n paths): the
+// first m entries of perms[p] form the first group.  stats[p] is the
+// unbiased MMD^2 of that split, sum over a != b of K[a][b] w(group a, group b)
+// with w = 1/(m(m-1)), 1/(n(n-1)) within groups and -1/(mn) across, read
+// row-major (coalesced) with the group labels in LDS, accumulated in FP64.
+template <typename R>
+__global__ __launch_bounds__(256) void k_mmd_perm(const R* K, int64_t m, int64_t n,
+                                                  const int32_t* perms, R* stats) {
+    const int64_t p = blockIdx.x, tot = m + n;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    unsigned char* lab = sk_smem;                                  // [tot]
+    double* red = reinterpret_cast<double*>(sk_smem + ((tot + 15) / 16) * 16);  // [256]
+    const int32_t* pi = perms + p * tot;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) lab[t] = 1;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+        const int32_t v = pi[t];
+        if (v >= 0 && v < tot) lab[v] = 0;  // rows are not validated: stay in bounds
+    }
+    __syncthreads();
+    const double wxx = m > 1 ? 1.0 / ((double)m * (double)(m - 1)) : 0.0;
+    const double wyy = n > 1 ? 1.0 / ((double)n * (double)(n - 1)) : 0.0;
+    const double wxy = -1.0 / ((double)m * (double)n);
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < tot * tot; e += blockDim.x) {
+        const int64_t a = e / tot, b = e - a * tot;
+        if (a == b) continue;
+        const int la = lab[a], lb = lab[b];
+        const double w = la != lb ? wxy : (la == 0 ? wxx : wyy);
+        acc += w * (double)K[e];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) stats[p] = (R)red[0];
+}
+
+// p-value of stats[0] (the observed split) against stats[1..]:
+// (1 + #{stats[q] >= stats[0], q >= 1}) / nperm, one workgroup.
+template <typename R>
+__global__ __launch_bounds__(256) void k_mmd_pvalue(const R* stats, int64_t nperm, double* pvalue) {
+    __shared__ int64_t red[256];
+    int64_t c = 0;
+    for (int64_t q = 1 + threadIdx.x; q < nperm; q += blockDim.x) c += stats[q] >= stats[0] ? 1 : 0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *pvalue = (double)(1 + red[0]) / (double)nperm;
+}
+
+// ---------------------------------------------------------------------------
 // diagnostics: skewed constants back to row-major C[p][i][j]
 // ---------------------------------------------------------------------------
 template <typename R>

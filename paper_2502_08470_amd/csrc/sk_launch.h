@@ -39,6 +39,8 @@ struct SkLaunch {
                                hipStream_t st);
     static hipError_t plain_poly(const PlainArgs<R>& a, int N, bool interp, hipStream_t st);
     static hipError_t plain_fd(const PlainArgs<R>& a, hipStream_t st);
+    static hipError_t mmd_perm(const R* K, int64_t m, int64_t n, const int32_t* perms,
+                               int64_t nperm, R* stats, double* pvalue, hipStream_t st);
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
     // LDS bytes per workgroup: the global-exchange staging slot plus an LDS

@@ -234,6 +234,21 @@ hipError_t SkLaunch<R>::plain_fd(const PlainArgs<R>& a, hipStream_t st) {
 }
 
 template <typename R>
+hipError_t SkLaunch<R>::mmd_perm(const R* K, int64_t m, int64_t n, const int32_t* perms,
+                                 int64_t nperm, R* stats, double* pvalue, hipStream_t st) {
+    if (nperm <= 0) return hipSuccess;
+    const size_t lds = (size_t)((m + n + 15) / 16) * 16 + 256 * sizeof(double);
+    hipLaunchKernelGGL(k_mmd_perm<R>, dim3((unsigned)nperm), dim3(256), lds, st, K, m, n, perms,
+                       stats);
+    SK_CHECK_LAUNCH();
+    if (pvalue) {
+        hipLaunchKernelGGL(k_mmd_pvalue<R>, dim3(1), dim3(256), 0, st, stats, nperm, pvalue);
+        SK_CHECK_LAUNCH();
+    }
+    return hipSuccess;
+}
+
+template <typename R>
 hipError_t SkLaunch<R>::unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                                int64_t npairs, int64_t cells, hipStream_t st) {
     if (npairs <= 0 || cells <= 0) return hipSuccess;

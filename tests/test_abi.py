@@ -168,3 +168,17 @@ def test_plan_host_side_checks():
     assert lib.sigkernel_plan_configure(h, 1, 1, 1, 64) == L.SK_EWORKSPACE
     lib.sigkernel_plan_destroy(h)
     lib.sigkernel_plan_destroy(None)
+
+
+def test_mmd_permutation_argument_errors():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    def call(m=4, n=4, nperm=3, dtype=1, K=1, P=1, S=1):
+        return lib.sigkernel_mmd_permutation(vp(K), m, n, vp(P), nperm, dtype, vp(S), None, None)
+    assert call(m=1) == L.SK_EINVAL
+    assert call(n=1) == L.SK_EINVAL
+    assert call(nperm=0) == L.SK_EINVAL
+    assert call(dtype=7) == L.SK_EINVAL
+    assert call(K=0) == L.SK_EINVAL
+    assert call(P=0) == L.SK_EINVAL
+    assert call(m=1 << 20, n=8) == L.SK_EUNSUPPORTED
