@@ -44,8 +44,20 @@ def default_threads() -> int:
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
-def gram(X, Y, scheme: int, order: int, threads: int | None = None):
-    """Mantissa/exponent Gram K[a, b] of paths X (nx, lx_pts, d), Y (ny, ly_pts, d)."""
+def _refine(paths, lam: int):
+    """Dyadic refinement of the points (hybrid method: the polynomial scheme
+    on the refined grid); no scheme arithmetic."""
+    from .schemes import refine_points
+    return [refine_points(p, lam) for p in paths]
+
+
+def gram(X, Y, scheme: int, order: int, threads: int | None = None, lam: int = 0):
+    """Mantissa/exponent Gram K[a, b] of paths X (nx, lx_pts, d), Y (ny, ly_pts, d).
+    lam > 0 with a polynomial scheme: the hybrid method (scheme on the
+    lam-order dyadic refinement of the grid)."""
+    if lam and scheme in (APPROX, INTERP):
+        X = np.stack(_refine(np.asarray(X, dtype=np.float64), lam))
+        Y = np.stack(_refine(np.asarray(Y, dtype=np.float64), lam))
     X = np.ascontiguousarray(X, dtype=np.float64)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     nx, lxp, d = X.shape
@@ -60,9 +72,13 @@ def gram(X, Y, scheme: int, order: int, threads: int | None = None):
     return mant, expo
 
 
-def pairs(xs, ys, scheme: int, order: int, threads: int | None = None):
-    """Mantissa/exponent of k(xs[p], ys[p]) for lists of (len_p, d) point arrays."""
+def pairs(xs, ys, scheme: int, order: int, threads: int | None = None, lam: int = 0):
+    """Mantissa/exponent of k(xs[p], ys[p]) for lists of (len_p, d) point arrays
+    (lam > 0 with a polynomial scheme: the hybrid method, as in gram)."""
     assert len(xs) == len(ys)
+    if lam and scheme in (APPROX, INTERP):
+        xs = _refine([np.asarray(a, dtype=np.float64) for a in xs], lam)
+        ys = _refine([np.asarray(b, dtype=np.float64) for b in ys], lam)
     d = xs[0].shape[1]
     xoff = np.zeros(len(xs) + 1, dtype=np.int64)
     yoff = np.zeros(len(ys) + 1, dtype=np.int64)

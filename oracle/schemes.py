@@ -25,6 +25,11 @@ fusion or reformulation:
                              operator of Definition "interpooperator".
 * ``interp_scheme``       -- Definition "Polynomial interpolation numerical
                              scheme" (Section 3.3).
+* ``refine_points`` / ``hybrid_scheme`` -- the hybrid method of the remark
+                             after Theorem "prop:globalte": a polynomial scheme
+                             run on the lambda-order dyadic refinement of the
+                             grid (every segment split into 2**lam equal
+                             pieces, as in the finite-difference refinement).
 * ``truncated_signature_kernel`` -- the benchmark method of Section 4: inner
                              product of signatures truncated at a level, with
                              signatures from the definition in Section 1 (Chen
@@ -69,6 +74,8 @@ __all__ = [
     "truncated_signature_kernel",
     "gram",
     "mmd2_unbiased",
+    "refine_points",
+    "hybrid_scheme",
     "mmd_permutation_stats",
     "mmd_permutation_pvalue",
 ]
@@ -342,6 +349,27 @@ def interp_scheme(x, y, N: int, s=None, t=None, track_exponent: bool = False):
     right = sum(h[n] * dt ** n for n in range(N + 1))
     m = 0.5 * (top + right)
     return (m, E) if track_exponent else m * 2.0 ** E
+
+
+def refine_points(x, lam: int) -> np.ndarray:
+    """Points of the piecewise-linear path x with every segment split into
+    2**lam equal pieces (the dyadic refinement of Definition "Dyadic finite
+    differences approximation scheme" applied to the path itself)."""
+    x = np.asarray(x)
+    r = 2 ** lam
+    if len(x) < 2 or r == 1:
+        return x.copy()
+    frac = np.arange(r) / r
+    pts = x[:-1, None, :] + frac[None, :, None] * (x[1:] - x[:-1])[:, None, :]
+    return np.concatenate([pts.reshape(-1, x.shape[1]), x[-1:]], 0)
+
+
+def hybrid_scheme(x, y, N: int, lam: int, scheme: str = "approx", track_exponent: bool = False):
+    """Hybrid of the finite-difference refinement and a polynomial scheme
+    (remark after Theorem "prop:globalte"): the approximation or
+    interpolation scheme of order N on the lambda-refined grid."""
+    fn = approx_scheme if scheme == "approx" else interp_scheme
+    return fn(refine_points(x, lam), refine_points(y, lam), N, track_exponent=track_exponent)
 
 
 # ---------------------------------------------------------------------------

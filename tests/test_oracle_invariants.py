@@ -219,3 +219,27 @@ def test_mmd_permutation_statistics_pins():
     a, b = S.mmd_permutation_stats(K2, 4, np.stack([pi, swapped]))
     assert a == pytest.approx(b, rel=1e-13)
     assert S.mmd_permutation_pvalue([0.5, 0.1, 0.7, 0.5, 0.2]) == pytest.approx(3 / 5)
+
+
+def test_hybrid_refined_grid_scheme_pins():
+    # Hybrid method (remark after Theorem "prop:globalte"): a polynomial scheme
+    # on the dyadically refined grid.  The exact kernel does not change when
+    # collinear points are inserted, so refinement must leave the converged
+    # kernel unchanged; the hybrid converges to it as lambda grows (by more
+    # than 3x per level here, the interpolation scheme faster); lambda = 0
+    # is the plain scheme; the C oracle on refined points matches numpy.
+    rng = np.random.default_rng(3)
+    x, y = bm(rng, 4, 2, 0.5), bm(rng, 5, 2, 0.5)
+    exact = S.approx_scheme(x, y, 24)
+    assert S.approx_scheme(S.refine_points(x, 2), S.refine_points(y, 2), 24) == pytest.approx(exact, rel=1e-13)
+    assert S.hybrid_scheme(x, y, 3, 0) == S.approx_scheme(x, y, 3)
+    for sch in ("approx", "interp"):
+        errs = [abs(S.hybrid_scheme(x, y, 2, lam, sch) - exact) for lam in range(4)]
+        assert all(errs[i + 1] < errs[i] / 3 for i in range(3)), (sch, errs)
+    r = S.refine_points(x, 2)
+    assert len(r) == 4 * (len(x) - 1) + 1
+    np.testing.assert_allclose(r[::4], x, rtol=0, atol=1e-15)
+    kind = {"approx": C.APPROX, "interp": C.INTERP}
+    for sch in ("approx", "interp"):
+        m, e = C.gram(x[None], y[None], kind[sch], 4, lam=2)
+        assert C.value(m, e)[0, 0] == pytest.approx(S.hybrid_scheme(x, y, 4, 2, sch), rel=1e-12)
