@@ -114,6 +114,10 @@ typedef struct sk_params {
     int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
     int32_t gram;   /* SK_GRAM_NATIVE or SK_GRAM_BF16X3 (batched algorithm)           */
     int32_t flags;  /* 0 or SK_SYMMETRIC                                              */
+    int32_t dyadic; /* polynomial schemes: lambda in [0, SK_MAX_DYADIC_ORDER] runs the
+                       scheme on the lambda-order dyadic refinement of the grid (the
+                       hybrid method of the remark after Theorem "prop:globalte");
+                       forward only; must be 0 for SK_FD, SK_FD2                    */
 } sk_params;
 
 /*

@@ -49,7 +49,8 @@ EXPORTS = (
 class SkParams(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
-                ("gram", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("gram", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("dyadic", ctypes.c_int32)]
 
 
 class SigKernelError(RuntimeError):

@@ -20,7 +20,7 @@ _GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3}
 
 
 def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: str = "native",
-            flags: int = 0) -> L.SkParams:
+            flags: int = 0, dyadic: int = 0) -> L.SkParams:
     if dtype == torch.float32:
         dt = L.SK_F32
     elif dtype == torch.float64:
@@ -33,7 +33,8 @@ def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: s
         raise ValueError(f"algo must be one of {sorted(_ALGOS)}")
     if gram_mode not in _GRAMS:
         raise ValueError(f"gram_mode must be one of {sorted(_GRAMS)}")
-    return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo], _GRAMS[gram_mode], int(flags))
+    return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo], _GRAMS[gram_mode], int(flags),
+                      int(dyadic))
 
 
 def _dev(t: torch.Tensor) -> torch.Tensor:
@@ -65,16 +66,19 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 # forward
 # ---------------------------------------------------------------------------
 def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-         algo: str = "batched", return_exp: bool = False, gram_mode: str = "native"):
+         algo: str = "batched", return_exp: bool = False, gram_mode: str = "native",
+         dyadic: int = 0):
     """K[a, b] = k(X[a], Y[b]) for paths X (nx, lx_pts, d), Y (ny, ly_pts, d).
 
     With ``return_exp`` returns (mantissa, exponent) with value
     mantissa * 2**exponent (exponent int32).  ``gram_mode`` "bf16x3"
-    computes the cell constants of float32 paths by bf16 split MFMAs."""
+    computes the cell constants of float32 paths by bf16 split MFMAs.
+    ``dyadic`` > 0 runs a polynomial scheme on the dyadically refined grid
+    (hybrid method)."""
     X, Y = _dev(X), _dev(Y)
     if X.dim() != 3 or Y.dim() != 3 or X.shape[2] != Y.shape[2] or X.dtype != Y.dtype:
         raise ValueError("X and Y must be (n, points, d) with the same d and dtype")
-    p = _params(X.dtype, scheme, order, algo, gram_mode)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     lib = L.lib()
@@ -102,7 +106,7 @@ def _concat(paths: Union[Sequence[torch.Tensor], Tuple[torch.Tensor, Sequence[in
 
 
 def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
-          return_exp: bool = False, gram_mode: str = "native"):
+          return_exp: bool = False, gram_mode: str = "native", dyadic: int = 0):
     """k[i] = k(xs[i], ys[i]) for lists of (points_i, d) tensors of uneven
     lengths, or (concatenated points, offsets) tuples."""
     Xc, xo = _concat(xs)
@@ -111,7 +115,7 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
         raise ValueError("xs and ys must hold the same number of paths")
     npairs = len(xo) - 1
     d = Xc.shape[1]
-    p = _params(Xc.dtype, scheme, order, algo, gram_mode)
+    p = _params(Xc.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
     lib = L.lib()
     k = torch.empty(npairs, dtype=Xc.dtype, device=Xc.device)
     ke = torch.empty(npairs, dtype=torch.int32, device=Xc.device) if return_exp else None

@@ -181,7 +181,14 @@ int check_params(const sk_params* p, bool backward) {
         if (p->order > SK_MAX_DYADIC_ORDER)
             return fail(SK_EUNSUPPORTED, "dyadic order %d > %d", p->order, SK_MAX_DYADIC_ORDER);
         if (backward) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
+        if (p->dyadic != 0)
+            return fail(SK_EINVAL, "finite differences take their refinement from `order`");
     } else if (p->scheme == SK_POLY_APPROX || p->scheme == SK_POLY_INTERP) {
+        if (p->dyadic < 0) return fail(SK_EINVAL, "dyadic refinement %d < 0", p->dyadic);
+        if (p->dyadic > SK_MAX_DYADIC_ORDER)
+            return fail(SK_EUNSUPPORTED, "dyadic refinement %d > %d", p->dyadic, SK_MAX_DYADIC_ORDER);
+        if (p->dyadic > 0 && backward)
+            return fail(SK_EUNSUPPORTED, "backward of the refined-grid (hybrid) scheme");
         if (p->order < SK_MIN_POLY_ORDER)
             return fail(SK_EINVAL, "polynomial order %d < %d", p->order, SK_MIN_POLY_ORDER);
         if (p->order > SK_MAX_POLY_ORDER)
@@ -247,7 +254,9 @@ int check_offsets(const int64_t* off, int64_t npairs, int lam, const char* what)
 }
 
 size_t esize(const sk_params& p) { return p.dtype == SK_F32 ? 4 : 8; }
-int lam_of(const sk_params& p) { return is_fd(p) ? p.order : 0; }
+// dyadic refinement of the grid: `order` for finite differences, `dyadic`
+// for the polynomial schemes (the hybrid method)
+int lam_of(const sk_params& p) { return is_fd(p) ? p.order : p.dyadic; }
 // LDS budgets of the strip-boundary rings; pairs that would need more pass
 // their edges through the global exchange.  The forward sweep (about five
 // waves per SIMD by registers) loses occupancy to its ring beyond ~16 KiB;
@@ -261,16 +270,24 @@ int gx_cols_fwd(const sk_params& p) {
 int gx_cols_adj(const sk_params& p) {
     return std::max(SK_GX_MIN_COLS, kGxAdjLds / sk_ring_col_bytes_adj(p.order, (int)esize(p)));
 }
+// All column counts below are of the (possibly refined) grid: ly segments
+// of y become ly << lam_of(p) columns.
+int grid_cols(const sk_params& p, int ly) { return ly << lam_of(p); }
 // words per column of a pair's global exchange records (0: none needed)
 int xb_words_of(const sk_params& p, int ly) {
     if (is_fd(p)) return 0;
-    return ly > std::min(gx_cols_fwd(p), gx_cols_adj(p)) ? sk_gx_words(p.order, (int)esize(p)) : 0;
+    return grid_cols(p, ly) > std::min(gx_cols_fwd(p), gx_cols_adj(p))
+               ? sk_gx_words(p.order, (int)esize(p)) : 0;
 }
-// LDS ring columns a pair with ly columns needs (0: global exchange)
+// LDS ring columns a pair with ly segments of y needs (0: global exchange)
 int ring_fwd_of(const sk_params& p, int ly) {
-    return (!is_fd(p) && ly > gx_cols_fwd(p)) ? 0 : ly;
+    const int c = grid_cols(p, ly);
+    return (!is_fd(p) && c > gx_cols_fwd(p)) ? 0 : c;
 }
-int ring_adj_of(const sk_params& p, int ly) { return ly > gx_cols_adj(p) ? 0 : ly; }
+int ring_adj_of(const sk_params& p, int ly) {
+    const int c = grid_cols(p, ly);
+    return c > gx_cols_adj(p) ? 0 : c;
+}
 int ckpt_stride(const sk_params& p) {
     return p.dtype == SK_F32 ? SkCkptStride<float>::value : SkCkptStride<double>::value;
 }
@@ -383,8 +400,9 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
         sa.K = K; sa.Kexp = Kexp;
         sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
         sa.gx_cols = gx_cols_fwd(p);
+        sa.lam = lam;
         SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, ring,
-                                                  max_ly > sa.gx_cols, st), "sweep");
+                                                  grid_cols(p, max_ly) > sa.gx_cols, st), "sweep");
     }
     return SK_OK;
 }
@@ -395,8 +413,8 @@ int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
     SK_TRY_HIP(lds_limit(&lim), "device query");
     size_t need = is_fd(p)
                       ? (size_t)(max_ly << lam_of(p)) * sizeof(R)
-                      : std::max(SkLaunch<R>::sweep_lds(p.order, std::min<int>((int)max_ly, gx_cols_fwd(p))),
-                                 SkLaunch<R>::adjoint_lds(p.order, std::min<int>((int)max_ly, gx_cols_adj(p))));
+                      : std::max(SkLaunch<R>::sweep_lds(p.order, std::min<int>(grid_cols(p, (int)max_ly), gx_cols_fwd(p))),
+                                 SkLaunch<R>::adjoint_lds(p.order, std::min<int>(grid_cols(p, (int)max_ly), gx_cols_adj(p))));
     need = std::max(need, SkLaunch<R>::gram_lds(gram_dpad(p, d)));
     if (need > lim)
         return fail(SK_EUNSUPPORTED, "paths too long for one workgroup's LDS (%zu > %zu bytes)",
@@ -413,7 +431,7 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
     const int lam = lam_of(p);
     const int64_t lx = lxp - 1, ly = lyp - 1;
     if (p.algo == SK_ALGO_PLAIN) {
-        const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
+        const int64_t need = std::max<int64_t>(((lx + ly) << lam) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
         if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
         PlainArgs<R> pa;
         std::memset(&pa, 0, sizeof(pa));
@@ -688,8 +706,8 @@ struct PlanImpl {
 
 size_t sweep_lds_bytes(const sk_params& p, int ly) {
     if (is_fd(p)) return (size_t)(ly << lam_of(p)) * esize(p);
-    return p.dtype == SK_F32 ? SkLaunch<float>::sweep_lds(p.order, ly)
-                             : SkLaunch<double>::sweep_lds(p.order, ly);
+    return p.dtype == SK_F32 ? SkLaunch<float>::sweep_lds(p.order, grid_cols(p, ly))
+                             : SkLaunch<double>::sweep_lds(p.order, grid_cols(p, ly));
 }
 
 // Launch groups: pairs whose edges go through the global exchange in the
@@ -1057,7 +1075,7 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
     pa.pst = reinterpret_cast<R*>(ws); pa.diag = reinterpret_cast<R*>(ws);
     for (int64_t i = 0; i < npairs; ++i) {
         const int64_t lx = xo[i + 1] - xo[i] - 1, ly = yo[i + 1] - yo[i] - 1;
-        const int64_t need = std::max<int64_t>((lx + ly) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
+        const int64_t need = std::max<int64_t>(((lx + ly) << lam) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
         if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
         pa.x = Xc + xo[i] * d; pa.y = Yc + yo[i] * d; pa.lx = (int)lx; pa.ly = (int)ly;
         pa.k_idx = i;
@@ -1151,7 +1169,7 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
     const int lam = lam_of(*p);
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t lx = lx_pts - 1, ly = ly_pts - 1;
-        return (size_t)std::max<int64_t>(256, std::max<int64_t>((lx + ly) * (p->order + 1),
+        return (size_t)std::max<int64_t>(256, std::max<int64_t>(((lx + ly) << lam) * (p->order + 1),
                                                                3 * ((lx << lam) + 1)) * 8);
     }
     const SkPairSizes per = sk_pair_sizes((int)(lx_pts - 1), (int)(ly_pts - 1), lam, p->order,
@@ -1175,7 +1193,7 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
         int64_t need = 256;
         for (int64_t i = 0; i < npairs; ++i) {
             int64_t lx = x_off[i + 1] - x_off[i] - 1, ly = y_off[i + 1] - y_off[i] - 1;
-            need = std::max(need, std::max<int64_t>((lx + ly) * (p->order + 1), 3 * ((lx << lam) + 1)) * 8);
+            need = std::max(need, std::max<int64_t>(((lx + ly) << lam) * (p->order + 1), 3 * ((lx << lam) + 1)) * 8);
         }
         return (size_t)need;
     }

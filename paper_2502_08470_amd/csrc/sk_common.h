@@ -110,7 +110,7 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
     SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0};
     SkGeom g = sk_make_geom(lx << lam, ly << lam);
     z.c = (int64_t)g.nsteps_pad * SK_LANES;
-    if (g.nsteps > 0) z.xb = (int64_t)ly * xb_words;
+    if (g.nsteps > 0) z.xb = (int64_t)g.ly * xb_words;
     if (backward && g.nsteps > 0) {
         int64_t nck = (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;

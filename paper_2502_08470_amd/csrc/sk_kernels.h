@@ -316,6 +316,7 @@ struct SweepArgs {
     int32_t* qe;
     unsigned* xb;          // global strip-boundary exchange records (long pairs)
     int32_t gx_cols;       // pairs with more columns use the global exchange
+    int32_t lam;           // dyadic refinement of the grid (hybrid method), forward only
 };
 
 // Global strip-boundary exchange, consumer side: at the start of every
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     const int r = threadIdx.x;
     const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
-    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
     if (g.nsteps == 0) {
         if (r == 0) sk_write_k(a.K, a.Kexp, pd.k_idx, (R)1, 0);
         return;
@@ -1190,7 +1191,9 @@ __device__ __forceinline__ R sk_dot_inc(const R* x, const R* y, int64_t d, int i
 
 template <typename R, int N, int TMAX>
 __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
-    const int lx = a.lx, ly = a.ly;
+    // grid of the lam-order dyadic refinement (lam = 0: the path grid)
+    const int lx = a.lx << a.lam, ly = a.ly << a.lam;
+    const R sc = (R)1 / (R)((int64_t)1 << (2 * a.lam));
     R* pe = a.pst;                         // p^{i, j}
     R* qe = a.pst + (int64_t)lx * (N + 1); // q^{i, j}
     for (int e = threadIdx.x; e < (lx + ly) * (N + 1); e += blockDim.x)
@@ -1202,7 +1205,7 @@ __global__ __launch_bounds__(256) void k_plain_poly(const PlainArgs<R> a) {
         const int i_hi = dg < lx - 1 ? dg : lx - 1;
         for (int i = i_lo + threadIdx.x; i <= i_hi; i += blockDim.x) {
             const int j = dg - i;
-            const R c = sk_dot_inc(a.x, a.y, a.d, i, j);
+            const R c = sk_dot_inc(a.x, a.y, a.d, i >> a.lam, j >> a.lam) * sc;
             R P[N + 1], Q[N + 1], Po[N + 1], Qo[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) {

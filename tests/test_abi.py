@@ -29,8 +29,8 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(L.EXPORTS)
 
 
-def P(scheme=1, order=4, dtype=1, algo=0, gram=0, flags=0):
-    return ctypes.byref(L.SkParams(scheme, order, dtype, algo, gram, flags))
+def P(scheme=1, order=4, dtype=1, algo=0, gram=0, flags=0, dyadic=0):
+    return ctypes.byref(L.SkParams(scheme, order, dtype, algo, gram, flags, dyadic))
 
 
 def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
@@ -59,6 +59,9 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=P(gram=2)), L.SK_EINVAL),
     (dict(p=P(gram=1, dtype=0)), L.SK_EUNSUPPORTED),
     (dict(p=P(flags=2)), L.SK_EINVAL),
+    (dict(p=P(dyadic=-1)), L.SK_EINVAL),
+    (dict(p=P(dyadic=9)), L.SK_EUNSUPPORTED),
+    (dict(p=P(scheme=0, order=1, dyadic=1)), L.SK_EINVAL),
 ])
 def test_gram_argument_errors(args, code):
     assert gram(**args) == code
@@ -77,6 +80,7 @@ def test_backward_rejections():
                                       None, vp(1), vp(1), vp(1), 1 << 30, None)
     assert bwd(P(scheme=0, order=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
+    assert bwd(P(dyadic=1)) == L.SK_EUNSUPPORTED  # hybrid refined grid: forward only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL

@@ -192,3 +192,37 @@ def test_second_order_fd_pairs_and_fp32(sk, dtype, tol):
         cells = np.array([(a - 1) * (b - 1) for a, b in zip(lens_x, lens_y)], float) * 4 ** lam
         bound = tol * (cells if dtype == torch.float32 else 1.0)
         assert np.all(err <= bound), (lam, err)
+
+
+# ---------------------------------------------------------------------------
+# hybrid: polynomial schemes on the dyadically refined grid
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("algo", ["batched", "plain"])
+@pytest.mark.parametrize("scheme,order,lam", [("approx", 4, 1), ("interp", 3, 2), ("approx", 2, 3)])
+def test_hybrid_refined_grid_fp64(sk, algo, scheme, order, lam):
+    from oracle import c_oracle as C
+    log_banner(f"hybrid {algo} {scheme} {order} lambda={lam}")
+    rng = np.random.default_rng(91)
+    X = bm_paths(rng, 3, 40, 3, 0.15)
+    Y = bm_paths(rng, 2, 25, 3, 0.15)
+    K = sk.gram(dev(X, torch.float64), dev(Y, torch.float64), scheme, order, algo=algo, dyadic=lam)
+    kind = C.APPROX if scheme == "approx" else C.INTERP
+    m, e = C.gram(X, Y, kind, order, lam=lam)
+    err = rel_err(K.cpu().numpy(), np.ldexp(m, e))
+    tol = 1e-12 if scheme == "approx" else 1e-12 + 2e-17 * (40 * 25 * 4 ** lam)
+    assert err.max() < tol, err
+
+
+def test_hybrid_pairs_fp32(sk):
+    from oracle import c_oracle as C
+    log_banner("hybrid pairs fp32")
+    rng = np.random.default_rng(92)
+    lens_x, lens_y = [70, 1, 140, 9], [33, 20, 90, 200]
+    xs = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0].astype(np.float32) for n in lens_x]
+    ys = [bm_paths(rng, 1, n - 1, 3, 0.3 / np.sqrt(n))[0].astype(np.float32) for n in lens_y]
+    k = sk.pairs([dev(a, torch.float32) for a in xs], [dev(b, torch.float32) for b in ys],
+                 "approx", 6, dyadic=1)
+    m, e = C.pairs([a.astype(np.float64) for a in xs], [b.astype(np.float64) for b in ys],
+                   C.APPROX, 6, lam=1)
+    err = rel_err(k.cpu().numpy(), np.ldexp(m, e))
+    assert err.max() < 2e-5, err
