@@ -24,6 +24,7 @@ Inputs are resident on the GPU before timing.  Reported:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
+       python bench.py --accuracy-study   (synthetic re-run of the paper's accuracy tables)
 """
 from __future__ import annotations
 
@@ -139,6 +140,46 @@ def fwd_cell_flops(N: int, T: int) -> float:
     return 2.0 * ((N + 1) * (3 * N + 4) + 6 * T * (N + 1)) + 3 * N
 
 
+def accuracy_study() -> int:
+    """MAPE (fraction) of every scheme against the converged kernel on 8 x 8
+    Grams of 2-d Brownian motions on [0, 1] with 10, 50 and 200 steps, the
+    setting of the paper's accuracy tables (Section 4, Appendix B; its paths
+    and seeds are not given, so only the trends compare).  Every scheme runs
+    on the GPU in FP64 (batched); the reference is the FP64 oracle's
+    approximation scheme at N = 24 with exponent tracking (converged; it
+    stands in for the level-21 truncated signature kernel)."""
+    import torch
+    import paper_2502_08470_amd as sk
+    from paper_2502_08470_amd import _lib
+    from oracle import c_oracle as C
+
+    _lib.lib()
+    dev = torch.device("cuda:0")
+    rows = []
+    for steps in (10, 50, 200):
+        rng = np.random.default_rng(steps)
+        X = np.concatenate([np.zeros((8, 1, 2)),
+                            np.cumsum(rng.normal(0, np.sqrt(1.0 / steps), (8, steps, 2)), 1)], 1)
+        Y = np.concatenate([np.zeros((8, 1, 2)),
+                            np.cumsum(rng.normal(0, np.sqrt(1.0 / steps), (8, steps, 2)), 1)], 1)
+        ref = C.value(*C.gram(X, Y, C.APPROX, 24))
+        Xt, Yt = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+
+        def mape(scheme, order):
+            K = sk.gram(Xt, Yt, scheme, order).cpu().numpy()
+            return float(np.mean(np.abs(K / ref - 1.0)))
+        for N in range(2, 9):  # compiled orders
+            rows.append({"steps": steps, "scheme": "approx", "order": N, "mape": mape("approx", N)})
+            rows.append({"steps": steps, "scheme": "interp", "order": N, "mape": mape("interp", N)})
+        for lam in range(0, 5):
+            rows.append({"steps": steps, "scheme": "fd", "refinement": 2 ** lam, "mape": mape("fd", lam)})
+            rows.append({"steps": steps, "scheme": "fd2", "refinement": 2 ** lam, "mape": mape("fd2", lam)})
+        print(f"[bench] accuracy study: {steps} steps done", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "MAPE vs converged kernel, 8x8 Grams of 2-d Brownian motions",
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,7 +192,11 @@ def main(argv=None) -> int:
                          "kernel of known size, to scale HBM byte counters)")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
                     help="summarise two rocprofv3 --pmc runs into HBM bytes per dispatch")
+    ap.add_argument("--accuracy-study", action="store_true",
+                    help="MAPE of every scheme vs the converged kernel (paper's accuracy tables)")
     args = ap.parse_args(argv)
+    if args.accuracy_study:
+        return accuracy_study()
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
