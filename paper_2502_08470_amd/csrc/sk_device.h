@@ -127,14 +127,16 @@ __device__ __forceinline__ int sk_rescale_shift(R m) {
 // ---------------------------------------------------------------------------
 // adaptive tail of the interpolation scheme
 // ---------------------------------------------------------------------------
-// Tail rows r = N+1, N+2, ... are added while any active lane of the wave
-// still needs them (a wave-uniform decision).  After row r a lane is done
-// when (i) its projected contribution is below the working precision
-// relative to the edge scale, 2 |A_r| max_n |Rs[n][r]| <= eps (|A_0^P| +
-// |A_0^Q|), and (ii) the rows not yet computed shrink at least geometrically
-// with ratio 1/2, which holds once |c| <= (r - N + 1) / 2 (each further row
-// multiplies the dominant Toeplitz term by c / (r + 1 - k), k <= N).  Under
-// (i) and (ii) all dropped rows together stay below eps relative.
+// Tail rows r = N+1, N+2, ... are computed one at a time, and folded while
+// any active lane of the wave still needs them (a wave-uniform decision).  A
+// lane no longer needs row r nor any later row when (i) the projection of
+// row r, doubled, is below the working precision relative to the edge scale,
+// 2 |A_r| max_n |Rs[n][r]| <= eps (|A_0^P| + |A_0^Q|), and (ii) the rows from
+// r on shrink at least geometrically with ratio 1/2, which holds once
+// |c| <= (r - N + 1) / 2 (each further row multiplies the dominant Toeplitz
+// term by c / (r + 1 - k), k <= N).  Under (i) and (ii) row r and everything
+// after it together stay below eps relative, so row r is then dropped too:
+// the row that decides is computed but not folded.
 template <typename R> struct SkEps;
 template <> struct SkEps<float> { static constexpr double value = 1.0 / (1 << 26); };
 template <> struct SkEps<double> { static constexpr double value = 1.0 / (double)(1ull << 55); };
@@ -276,6 +278,9 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 hp = fma(P[k], ifact<R>(r + k), hp);
             }
             const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+            const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
+            const bool need = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
+            if (!sk_wave_any(need)) break;
             if (WD) {
                 const R rc = (R)r * cp[r - 1];
                 DP[r - 1] = fma(rc, hq, tpp);
@@ -293,9 +298,6 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 Po[n] = fma(tab.rs[n][t], arp, Po[n]);
                 Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
-            const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
-            const bool more = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
-            if (!sk_wave_any(more)) break;
         }
         Po0 += (double)t0p;
         Qo0 += (double)t0q;

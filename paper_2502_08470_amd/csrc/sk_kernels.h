@@ -737,51 +737,46 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             const int tau = tau0 + u;
             const bool live = lv[u];
             const int ss = sst[u], jj = jst[u], i = ss * 64 + r;
+            const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
+            // adjoint of the right edge: from lane r+1, or for lane 63 from
+            // the next strip's lane 0 through the ring or the staging slot
             R lq_recv[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
-            const int El_recv = lane_from_next(Els);
+            int El_recv = lane_from_next(Els);
+            if (r == 63 && live && !last_row) {
+                if (gx) {
+                    const unsigned* rec = stage + (tau & 7) * GXW;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n)
+                        lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
+                    El_recv = (int)rec[(N + 1) * (ES / 4)];
+                } else {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) lq_recv[n] = llds[jj * (N + 1) + n];
+                    El_recv = ltag[jj];
+                }
+            }
+            // top edge from this lane's previous (later) cell, right edge as
+            // above; outputs nobody consumes have zero adjoint
+            const bool ta = live && !last_col, tb = live && !last_row;
             R ap[N + 1], aq[N + 1];
-            int ea = SK_ZERO_EXP, eb = SK_ZERO_EXP;
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
-                ap[n] = (R)0;
-                aq[n] = (R)0;
+                ap[n] = ta ? lp[n] : (R)0;
+                aq[n] = tb ? lq_recv[n] : (R)0;
             }
-            if (live) {
-                const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
-                if (last_col && last_row) {
-                    // endpoint seed: L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
+            int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+            // endpoint seed (once per pair): L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
+            const bool seed = live && last_col && last_row;
+            if (sk_wave_any(seed) && seed) {
 #pragma unroll
-                    for (int n = 0; n <= N; ++n) {
-                        ap[n] = (R)0.5 * gk * ifact<R>(n);
-                        aq[n] = ap[n];
-                    }
-                    ea = gexp;
-                    eb = gexp;
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = (R)0.5 * gk * ifact<R>(n);
+                    aq[n] = ap[n];
                 }
-                if (!last_col) {
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) ap[n] = lp[n];
-                    ea = El;
-                }
-                if (!last_row) {
-                    if (r == 63 && gx) {
-                        const unsigned* rec = stage + (tau & 7) * GXW;
-#pragma unroll
-                        for (int n = 0; n <= N; ++n)
-                            aq[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
-                        eb = (int)rec[(N + 1) * (ES / 4)];
-                    } else if (r == 63) {
-#pragma unroll
-                        for (int n = 0; n <= N; ++n) aq[n] = llds[jj * (N + 1) + n];
-                        eb = ltag[jj];
-                    } else {
-#pragma unroll
-                        for (int n = 0; n <= N; ++n) aq[n] = lq_recv[n];
-                        eb = El_recv;
-                    }
-                }
+                ea = gexp;
+                eb = gexp;
             }
             const int Ec = ea > eb ? ea : eb;
             // vectors tagged SK_ZERO_EXP are zero: only real exponents below
