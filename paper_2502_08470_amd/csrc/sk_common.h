@@ -89,7 +89,9 @@ struct SkPairDesc {
     // element offsets of the pair's blocks in the chunk's workspace arrays
     int64_t c_off;    // skewed cell constants / skewed dL/dc
     int64_t ck_off;   // lane checkpoints (backward only)
-    int64_t ce_off;   // checkpoint exponents (int32 elements)
+    int64_t ce_off;   // per checkpoint: 64 lane exponents, then one word with the
+                      // interpolation tail length of each of the segment's steps
+                      // (8 bits per step; int32 elements)
     int64_t qb_off;   // strip-boundary edge vectors (backward only)
     int64_t qe_off;   // strip-boundary exponents (int32 elements)
     int64_t dx_off;   // per-pair dL/d(dx) partials
@@ -114,7 +116,7 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
     if (backward && g.nsteps > 0) {
         int64_t nck = (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;
-        z.ce = nck * SK_LANES;  // per-lane exponents
+        z.ce = nck * (SK_LANES + 1);  // per-lane exponents + the segment's tail lengths
         z.qb = (int64_t)g.nstrips * g.ly * (N + 1);
         z.qe = (int64_t)g.nstrips * g.ly;
         z.dx = (int64_t)lx * d;

@@ -163,13 +163,16 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // HI = false: every row in R (the FP64 arguments are ignored and the FP64
 // outputs are the R results widened); used where FP32 accuracy of the state
 // is enough, e.g. the adjoint's short replays.
-template <typename R, int N, int TMAX, bool WD = false, bool HI = true>
+// Tkept (nullable): receives the number of tail rows folded (wave-uniform).
+// FIXT: fold exactly Tfix tail rows (wave-uniform) instead of deciding, so that
+// a replay repeats the decisions of the forward it replays.
+template <typename R, int N, int TMAX, bool WD = false, bool HI = true, bool FIXT = false>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
                                             double P1, double Q0, double Q1, R c, bool active,
                                             const SkTab<R>& tab, R (&Po)[N + 1], R (&Qo)[N + 1],
                                             double& Po0, double& Po1, double& Qo0, double& Qo1,
                                             R* DP = nullptr, R* DQ = nullptr,
-                                            int* Tkept = nullptr) {
+                                            int* Tkept = nullptr, int Tfix = 0) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
@@ -189,8 +192,8 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
             DP[r] = (R)0;
             DQ[r] = (R)0;
         }
-        *Tkept = 0;
     }
+    if (Tkept) *Tkept = 0;
     // rows 0 and 1 (in FP64 when HI):
     //   A_0 = P'_0 + sum_{k>=1} Q'_k/k!,  A_1 = P'_1 + c (P'_0 + sum_{k>=1} Q'_k/(k+1)!)
     double HQ1, HP1;
@@ -264,6 +267,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         R t0p = (R)0, t0q = (R)0, t1p = (R)0, t1q = (R)0;  // tail into rows 0, 1
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
+            if (FIXT && t >= Tfix) break;
             const int r = N + 1 + t;
             R tp = (R)0, tq = (R)0;
 #pragma unroll
@@ -278,17 +282,19 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 hp = fma(P[k], ifact<R>(r + k), hp);
             }
             const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
-            const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
-            const bool need = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
-            if (!sk_wave_any(need)) break;
+            if (!FIXT) {
+                const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
+                const bool need = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
+                if (!sk_wave_any(need)) break;
+            }
             if (WD) {
                 const R rc = (R)r * cp[r - 1];
                 DP[r - 1] = fma(rc, hq, tpp);
                 DQ[r - 1] = fma(rc, hp, tqp);
                 tpp = tp;
                 tqp = tq;
-                *Tkept = t + 1;
             }
+            if (Tkept) *Tkept = t + 1;
             t0p = fma(tab.rs[0][t], arp, t0p);
             t0q = fma(tab.rs[0][t], arq, t0q);
             t1p = fma(tab.rs[1][t], arp, t1p);
@@ -299,10 +305,17 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
         }
-        Po0 += (double)t0p;
-        Qo0 += (double)t0q;
-        Po1 += (double)t1p;
-        Qo1 += (double)t1q;
+        if (HI) {
+            Po0 += (double)t0p;
+            Qo0 += (double)t0q;
+            Po1 += (double)t1p;
+            Qo1 += (double)t1q;
+        } else {  // rows 0 and 1 are R values here: no FP64 arithmetic
+            Po0 = (double)((R)Po0 + t0p);
+            Qo0 = (double)((R)Qo0 + t0q);
+            Po1 = (double)((R)Po1 + t1p);
+            Qo1 = (double)((R)Qo1 + t1q);
+        }
     }
     Po[0] = (R)Po0;
     Qo[0] = (R)Qo0;

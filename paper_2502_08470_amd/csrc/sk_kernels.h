@@ -415,6 +415,7 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     R cb[8], cn[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) cb[u] = cs[u * 64 + r];
+    unsigned tword = 0u;  // tail lengths of the current checkpoint segment
     for (int t0 = 0; t0 < nst8; t0 += 8) {
         if (gx) sk_gx_stage<GXW>(xr, stage, xg, t0 + 8, r, lane0_col);
         if (t0 + 8 < g.nsteps_pad) {
@@ -489,12 +490,23 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                     ck[n * 64 + r] = P[n];
                     ck[(N + 1 + n) * 64 + r] = Qin[n];
                 }
-                a.ce[pd.ce_off + kk * 64 + r] = E;
+                a.ce[pd.ce_off + kk * (SK_LANES + 1) + r] = E;
             }
             R Po[N + 1], Qo[N + 1];
             double Po0, Po1, Qo0, Qo1;
+            int Tc = 0;
             sk_cell_fwd<R, N, TMAX>(P, Qin, P0, P1, Qin0, Qin1, cb[u], live, a.tab, Po, Qo, Po0,
-                                    Po1, Qo0, Qo1);
+                                    Po1, Qo0, Qo1, nullptr, nullptr,
+                                    (CKPT && TMAX > 0) ? &Tc : nullptr);
+            if (CKPT && TMAX > 0) {
+                // the adjoint's replay folds the same tail rows
+                tword |= (unsigned)Tc << (8 * (u % S));
+                if (u % S == S - 1) {
+                    if (r == 0 && tau - (S - 1) < g.nsteps)
+                        a.ce[pd.ce_off + (int64_t)(tau / S) * (SK_LANES + 1) + SK_LANES] = (int)tword;
+                    tword = 0u;
+                }
+            }
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
@@ -654,7 +666,12 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
         bool lv[S];
         int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
-        int E = a.ce[pd.ce_off + (int64_t)kk * 64 + r];
+        int E = a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r];
+        // tail lengths the forward folded at the segment's steps
+        const unsigned tword =
+            TMAX > 0 ? (unsigned)__builtin_amdgcn_readfirstlane(
+                           a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + SK_LANES])
+                     : 0u;
         R P[N + 1], Qs[N + 1];
 #pragma unroll
         for (int n = 0; n <= N; ++n) {
@@ -715,8 +732,10 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             Est[u] = E;
             R Po[N + 1], Qo[N + 1];
             double Po0, Po1, Qo0, Qo1;
-            sk_cell_fwd<R, N, TMAX, true, false>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live, a.tab,
-                                                 Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u], Dq[u], &Tst[u]);
+            Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
+            sk_cell_fwd<R, N, TMAX, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
+                                                       a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
+                                                       Dq[u], nullptr, Tst[u]);
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
                 P[n] = Po[n];
