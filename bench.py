@@ -253,10 +253,13 @@ def main(argv=None) -> int:
 
     # roofline of the dominant kernel (largest total event time)
     # interpolation tail on this workload (|c| < 0.05): the first tail row is
-    # computed, found below the working precision and not folded
+    # computed, found below the working precision and not folded (T = 0); the
+    # adjoint replays the forward with the recorded T (no deciding row) and
+    # applies the transposed map: 2 forwards without the deciding row (the
+    # dL/dc terms are not counted)
     fl_fwd = fwd_cell_flops(ORDER, 0, deciding=True)
     flops_per_cell = {"sweep": fl_fwd, "sweep_ckpt": fl_fwd,
-                      "adjoint": 2.0 * fl_fwd,  # transpose map + dL/dc (recompute not counted)
+                      "adjoint": 2.0 * fwd_cell_flops(ORDER, 0),
                       "gram": 2.0 * DIM, "contract": 4.0 * DIM}
     dom = max((k for k in flops_per_cell if ktimes[k][1] > 0), key=lambda k: ktimes[k][0])
     dom_ms, dom_n = ktimes[dom]
