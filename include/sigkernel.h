@@ -85,11 +85,14 @@ extern "C" {
 #define SK_ALGO_PLAIN 1   /* one launch per pair, one workgroup sweeping the
                              anti-diagonals (FP64, forward only)             */
 
-/* arithmetic of the increment Gram C_ij = <dx_i, dy_j> (MFMA) */
-#define SK_GRAM_NATIVE 0 /* products in the path dtype (FP32 or FP64 16x16x4 MFMA)      */
+/* arithmetic of the increment Gram C_ij = <dx_i, dy_j> */
+#define SK_GRAM_NATIVE 0 /* products in the path dtype: a d-term FMA chain per cell for
+                            d <= 16 when a pair's increments fit in LDS, otherwise
+                            FP32 or FP64 16x16x4 MFMA                                  */
 #define SK_GRAM_BF16X3 1 /* SK_F32 only: each increment split into three bf16 parts,
                             the six leading cross products on bf16 MFMA with FP32
                             accumulation (error at the FP32 level, 2^-24 |dx||dy|) */
+#define SK_GRAM_MFMA 2   /* products in the path dtype, always on 16x16x4 MFMA       */
 
 /* flags */
 #define SK_SYMMETRIC 1 /* backward of a Gram call whose Y is the same array as X:
@@ -112,7 +115,7 @@ typedef struct sk_params {
                        schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD, SK_FD2  */
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
     int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
-    int32_t gram;   /* SK_GRAM_NATIVE or SK_GRAM_BF16X3 (batched algorithm)           */
+    int32_t gram;   /* SK_GRAM_NATIVE, SK_GRAM_BF16X3 or SK_GRAM_MFMA (batched algorithm) */
     int32_t flags;  /* 0 or SK_SYMMETRIC                                              */
     int32_t dyadic; /* polynomial schemes: lambda in [0, SK_MAX_DYADIC_ORDER] runs the
                        scheme on the lambda-order dyadic refinement of the grid (the

@@ -16,7 +16,7 @@ from . import _lib as L
 _SCHEMES = {"fd": L.SK_FD, "fd2": L.SK_FD2, "approx": L.SK_POLY_APPROX,
             "interp": L.SK_POLY_INTERP}
 _ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN}
-_GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3}
+_GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3, "mfma": L.SK_GRAM_MFMA}
 
 
 def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: str = "native",
@@ -72,7 +72,9 @@ def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 
 
     With ``return_exp`` returns (mantissa, exponent) with value
     mantissa * 2**exponent (exponent int32).  ``gram_mode`` "bf16x3"
-    computes the cell constants of float32 paths by bf16 split MFMAs.
+    computes the cell constants of float32 paths by bf16 split MFMAs, "mfma"
+    always by MFMA in the path dtype; "native" (default) uses a d-term FMA
+    chain per cell for d <= 16 and MFMA otherwise.
     ``dyadic`` > 0 runs a polynomial scheme on the dyadically refined grid
     (hybrid method)."""
     X, Y = _dev(X), _dev(Y)
@@ -185,7 +187,7 @@ def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int 
 
 def cell_constants(X: torch.Tensor, Y: torch.Tensor, gram_mode: str = "native") -> torch.Tensor:
     """C[a, b, i, j] = <X[a, i+1] - X[a, i], Y[b, j+1] - Y[b, j]> from the
-    library's MFMA increment-Gram kernel."""
+    increment-Gram kernel the path uses for ``gram_mode``."""
     X, Y = _dev(X), _dev(Y)
     p = _params(X.dtype, "approx", 2, "batched", gram_mode)
     nx, lxp, d = X.shape

@@ -200,7 +200,7 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dtype != SK_F64) return fail(SK_EUNSUPPORTED, "the plain algorithm is FP64 only");
         if (backward) return fail(SK_EUNSUPPORTED, "the plain algorithm is forward only");
     }
-    if (p->gram != SK_GRAM_NATIVE && p->gram != SK_GRAM_BF16X3)
+    if (p->gram != SK_GRAM_NATIVE && p->gram != SK_GRAM_BF16X3 && p->gram != SK_GRAM_MFMA)
         return fail(SK_EINVAL, "gram mode %d", p->gram);
     if (p->gram == SK_GRAM_BF16X3 && p->dtype != SK_F32)
         return fail(SK_EUNSUPPORTED, "the bf16 split Gram is for SK_F32 paths");
@@ -371,7 +371,10 @@ constexpr size_t kGramPairLds = 64 << 10;
 
 template <typename R>
 hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int max_lx,
-                       int max_ly, hipStream_t st) {
+                       int max_ly, bool direct, hipStream_t st) {
+    if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX &&
+        SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
+        return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
@@ -387,7 +390,7 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
     GramArgs<R> ga;
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
-    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st), "increment Gram");
     if (is_fd(p)) {
         FdArgs<R> fa;
         fa.src = src; fa.lam = lam; fa.cskew = cskew; fa.K = K; fa.Kexp = Kexp;
@@ -491,7 +494,7 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     GramArgs<R> ga;
     ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = 0;
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
-    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, st), "increment Gram");
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st), "increment Gram");
     SweepArgs<R> sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.src = src; sa.cskew = cskew; sa.tab = table_for<R>(p);
@@ -1563,14 +1566,16 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
             ga.X = (const float*)X; ga.Y = (const float*)Y; ga.d = d; ga.dpad = gram_dpad(p, d);
             ga.lam = 0; ga.src = src; ga.cskew = (float*)((char*)ws + L.cskew); ga.maxc = nullptr;
             ga.split = p.gram == SK_GRAM_BF16X3;
-            SK_TRY_HIP(SkLaunch<float>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
+            SK_TRY_HIP(launch_gram(ga, cnt, g.nsteps_pad, (int)lx, (int)ly, p.gram == SK_GRAM_NATIVE, stream),
+                       "increment Gram");
             SK_TRY_HIP(SkLaunch<float>::unskew(src, ga.cskew, (float*)C, first, cnt, lx * ly, stream), "unskew");
         } else {
             GramArgs<double> ga;
             ga.X = (const double*)X; ga.Y = (const double*)Y; ga.d = d; ga.dpad = gram_dpad(p, d);
             ga.lam = 0; ga.src = src; ga.cskew = (double*)((char*)ws + L.cskew); ga.maxc = nullptr;
             ga.split = 0;
-            SK_TRY_HIP(SkLaunch<double>::gram(ga, g.nsteps_pad / 64, cnt, stream), "increment Gram");
+            SK_TRY_HIP(launch_gram(ga, cnt, g.nsteps_pad, (int)lx, (int)ly, p.gram == SK_GRAM_NATIVE, stream),
+                       "increment Gram");
             SK_TRY_HIP(SkLaunch<double>::unskew(src, ga.cskew, (double*)C, first, cnt, lx * ly, stream), "unskew");
         }
     }

@@ -219,6 +219,91 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     }
 }
 
+// Direct variant for small d (native precision): one workgroup (4 waves) per
+// pair stages the pair's increments in LDS once, then each wave writes a
+// contiguous quarter of the skewed rows; lane r of row tau computes its own
+// cell (64 s + r, L - s Tp), L = tau - r, as a d-term FMA chain.  Nothing is
+// computed twice and there is no barrier after the staging.  The lane keeps
+// the x increment of its row in registers (reloaded when its strip changes)
+// and reads the y increment of its column from LDS, whose rows are padded so
+// that the 8-byte reads of 16 consecutive lanes (consecutive columns) hit
+// distinct banks.  Refined grids read cell (i >> lam, j >> lam) scaled by
+// 4^-lam.
+template <typename R> struct SkGramDirectPad;
+template <> struct SkGramDirectPad<float> { static constexpr int value = 2; };
+template <> struct SkGramDirectPad<double> { static constexpr int value = 1; };
+#define SK_GRAM_DIRECT_DMAX 16
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gram_direct(const GramArgs<R> a) {
+    constexpr int DMAX = SK_GRAM_DIRECT_DMAX;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, r = tid & 63;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0) return;
+    const int dp = a.dpad;  // multiple of 4, <= DMAX
+    const int ys = dp + SkGramDirectPad<R>::value;  // padded LDS row of a y increment
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* Xs = reinterpret_cast<R*>(sk_smem);  // [lx][dp]
+    R* Ys = Xs + (size_t)pd.lx * dp;        // [ly][ys]
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
+    for (int e = tid; e < pd.lx * dp; e += 256) {
+        const int i = e / dp, k = e - i * dp;
+        Xs[e] = k < a.d ? X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k] : (R)0;
+    }
+    for (int e = tid; e < pd.ly * dp; e += 256) {
+        const int j = e / dp, k = e - j * dp;
+        Ys[j * ys + k] = k < a.d ? Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k] : (R)0;
+    }
+    __syncthreads();
+    const R scale = (R)1 / (R)(1 << (2 * a.lam));
+    const int nr = g.nsteps_pad / 4;  // rows per wave (a multiple of 16)
+    const int tau0 = wave * nr;
+    // lane state at row tau0: linear index L, strip s, column j
+    int L = tau0 - r, s = 0, j = 0;
+    if (L >= 0) {
+        s = L / g.Tp;
+        j = L - s * g.Tp;
+    }
+    int xs_loaded = -1;  // strip whose x increment is in xr
+    R xr[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) xr[k] = (R)0;
+    R* out = a.cskew + pd.c_off;
+    for (int t = 0; t < nr; ++t) {
+        const int tau = tau0 + t;
+        const int i = s * 64 + r;
+        const bool live = L >= 0 && s < g.nstrips && j < g.ly && i < g.lx;
+        R c = (R)0;
+        if (live) {
+            if (s != xs_loaded) {
+                const R* xrow = Xs + (size_t)(i >> a.lam) * dp;
+#pragma unroll
+                for (int k = 0; k < DMAX; ++k) xr[k] = k < dp ? xrow[k] : (R)0;
+                xs_loaded = s;
+            }
+            const R* yrow = Ys + (size_t)(j >> a.lam) * ys;
+#pragma unroll
+            for (int k = 0; k < DMAX; k += 2) {
+                if (k < dp) {
+                    c = fma(xr[k], yrow[k], c);
+                    c = fma(xr[k + 1], yrow[k + 1], c);
+                }
+            }
+            c *= scale;
+        }
+        out[(int64_t)tau * 64 + r] = c;
+        ++L;
+        if (L > 0 && ++j == g.Tp) {
+            j = 0;
+            ++s;
+        }
+    }
+}
+
 // Pair-resident variant: one workgroup (4 waves) per pair stages the pair's
 // increments in LDS once ([lx][dp] and [ly][dp], unrefined; refined rows
 // index i >> lam) and then produces all skewed row blocks of the pair in

@@ -24,6 +24,9 @@ struct SkLaunch {
     // are unrefined segment counts
     static hipError_t gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
                                 hipStream_t st);
+    // direct (VALU) Gram for dpad <= SK_GRAM_DIRECT_DMAX, native precision
+    static hipError_t gram_direct(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
+                                  hipStream_t st);
     // ring: LDS ring columns of the launch (largest among its pairs that do
     // not use the global strip-boundary exchange)
     // gx: some pair of the launch uses the global strip-boundary exchange
@@ -57,6 +60,10 @@ struct SkLaunch {
     static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
     static size_t gram_pair_lds(int dpad, int max_lx, int max_ly) {
         return ((size_t)64 * 66 + (size_t)(max_lx + max_ly) * dpad) * sizeof(R);
+    }
+    static size_t gram_direct_lds(int dpad, int max_lx, int max_ly) {
+        return ((size_t)max_lx * dpad + (size_t)max_ly * (dpad + SkGramDirectPad<R>::value)) *
+               sizeof(R);
     }
 };
 

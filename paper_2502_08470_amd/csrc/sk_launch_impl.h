@@ -63,6 +63,17 @@ hipError_t SkLaunch<R>::gram_pair(const GramArgs<R>& a, int max_lx, int max_ly, 
     return hipSuccess;
 }
 
+template <typename R>
+hipError_t SkLaunch<R>::gram_direct(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
+                                    hipStream_t st) {
+    if (npairs <= 0) return hipSuccess;
+    if (a.split || a.dpad > SK_GRAM_DIRECT_DMAX) return hipErrorInvalidValue;
+    const size_t lds = gram_direct_lds(a.dpad, max_lx, max_ly);
+    hipLaunchKernelGGL((k_gram_direct<R>), dim3((unsigned)npairs), dim3(256), lds, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 template <typename R, int N, int TMAX>
 static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
                              hipStream_t st) {

@@ -56,7 +56,7 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=P(), ws=0), L.SK_EINVAL),
     (dict(p=P(), wsb=16), L.SK_EWORKSPACE),
     (dict(p=None), L.SK_EINVAL),
-    (dict(p=P(gram=2)), L.SK_EINVAL),
+    (dict(p=P(gram=3)), L.SK_EINVAL),
     (dict(p=P(gram=1, dtype=0)), L.SK_EUNSUPPORTED),
     (dict(p=P(flags=2)), L.SK_EINVAL),
     (dict(p=P(dyadic=-1)), L.SK_EINVAL),
