@@ -25,6 +25,7 @@ Inputs are resident on the GPU before timing.  Reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
        python bench.py --accuracy-study   (synthetic re-run of the paper's accuracy tables)
+       python bench.py --long-pair 16384  (strip pipeline on one long pair)
 """
 from __future__ import annotations
 
@@ -182,6 +183,46 @@ def accuracy_study() -> int:
     return 0
 
 
+def long_pair_study(steps: int = 16384) -> int:
+    """One pair of R^8 Brownian paths with `steps` steps (FP32): forward time
+    of the strip pipeline (strips on co-resident workgroups) against the
+    batched algorithm (one wave sweeps the strips in turn), approximation
+    N = 8 and interpolation N = 6.  The pipeline's rate is bounded by the
+    pair's parallelism (one wave per 64-row strip, a 64 + 16-step lag per
+    strip), not by the chip: it is reported as cells/s and as the FLOP rate
+    of the forward cell count against the FP32 VALU peak."""
+    import torch
+    import paper_2502_08470_amd as sk
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    x, y = W.long_pair(0, steps, 8)
+    X, Y = torch.tensor(x, device=dev), torch.tensor(y, device=dev)
+    cells = float(steps) * steps
+    rows = []
+    for scheme, order in (("approx", 8), ("interp", 6)):
+        for algo in ("pipeline", "batched"):
+            reps = 5 if algo == "pipeline" else 2
+            k = sk.gram(X, Y, scheme, order, algo=algo)  # warm-up (and the tables)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                k = sk.gram(X, Y, scheme, order, algo=algo)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            fl = fwd_cell_flops(order, 0, deciding=scheme == "interp")
+            rows.append({"scheme": scheme, "order": order, "algo": algo, "ms": ms,
+                         "cells_per_s": cells / (ms * 1e-3),
+                         "tflops": fl * cells / (ms * 1e-3) / 1e12,
+                         "frac_of_fp32_peak": fl * cells / (ms * 1e-3) / PEAK_FP32_VALU,
+                         "k": float(k.cpu()[0, 0])})
+            print(f"[bench] long pair {scheme} {order} {algo}: {ms:.2f} ms", file=sys.stderr,
+                  flush=True)
+    print(json.dumps({"study": f"single pair of {steps + 1}-point paths in R^8, FP32 forward",
+                      "cells": cells, "rows": rows}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,9 +237,13 @@ def main(argv=None) -> int:
                     help="summarise two rocprofv3 --pmc runs into HBM bytes per dispatch")
     ap.add_argument("--accuracy-study", action="store_true",
                     help="MAPE of every scheme vs the converged kernel (paper's accuracy tables)")
+    ap.add_argument("--long-pair", type=int, default=0, metavar="STEPS",
+                    help="strip pipeline vs batched on one pair of STEPS-step paths")
     args = ap.parse_args(argv)
     if args.accuracy_study:
         return accuracy_study()
+    if args.long_pair:
+        return long_pair_study(args.long_pair)
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:

@@ -84,6 +84,13 @@ extern "C" {
 #define SK_ALGO_BATCHED 0 /* all pairs of a chunk in one wavefront launch   */
 #define SK_ALGO_PLAIN 1   /* one launch per pair, one workgroup sweeping the
                              anti-diagonals (FP64, forward only)             */
+#define SK_ALGO_PIPELINE 2 /* one pair at a time, its 64-row strips spread over
+                             co-resident workgroups that hand strip-boundary
+                             edges on through global memory (Section 3.2's
+                             wavefront over strips; for a few very long
+                             pairs).  Polynomial schemes, forward only; a
+                             value that could not be completed (a bounded
+                             wait gave up) is written as NaN               */
 
 /* arithmetic of the increment Gram C_ij = <dx_i, dy_j> */
 #define SK_GRAM_NATIVE 0 /* products in the path dtype: a d-term FMA chain per cell for
@@ -114,7 +121,7 @@ typedef struct sk_params {
     int32_t order;  /* N in [SK_MIN_POLY_ORDER, SK_MAX_POLY_ORDER] for the polynomial
                        schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD, SK_FD2  */
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
-    int32_t algo;   /* SK_ALGO_BATCHED or SK_ALGO_PLAIN                              */
+    int32_t algo;   /* SK_ALGO_BATCHED, SK_ALGO_PLAIN or SK_ALGO_PIPELINE            */
     int32_t gram;   /* SK_GRAM_NATIVE, SK_GRAM_BF16X3 or SK_GRAM_MFMA (batched algorithm) */
     int32_t flags;  /* 0 or SK_SYMMETRIC                                              */
     int32_t dyadic; /* polynomial schemes: lambda in [0, SK_MAX_DYADIC_ORDER] runs the

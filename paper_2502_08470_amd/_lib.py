@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsigkernel.so")
 SK_OK, SK_EINVAL, SK_EWORKSPACE, SK_EUNSUPPORTED, SK_EHIP = 0, -1, -2, -3, -4
 SK_FD, SK_POLY_APPROX, SK_POLY_INTERP, SK_FD2 = 0, 1, 2, 3
 SK_F64, SK_F32 = 0, 1
-SK_ALGO_BATCHED, SK_ALGO_PLAIN = 0, 1
+SK_ALGO_BATCHED, SK_ALGO_PLAIN, SK_ALGO_PIPELINE = 0, 1, 2
 SK_OP_GRAM, SK_OP_PAIRS = 0, 1
 SK_GRAM_NATIVE, SK_GRAM_BF16X3, SK_GRAM_MFMA = 0, 1, 2
 SK_SYMMETRIC = 1

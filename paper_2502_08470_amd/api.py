@@ -15,7 +15,7 @@ from . import _lib as L
 
 _SCHEMES = {"fd": L.SK_FD, "fd2": L.SK_FD2, "approx": L.SK_POLY_APPROX,
             "interp": L.SK_POLY_INTERP}
-_ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN}
+_ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN, "pipeline": L.SK_ALGO_PIPELINE}
 _GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3, "mfma": L.SK_GRAM_MFMA}
 
 

@@ -174,7 +174,7 @@ bool is_fd(const sk_params& p) { return p.scheme == SK_FD || p.scheme == SK_FD2;
 int check_params(const sk_params* p, bool backward) {
     if (!p) return fail(SK_EINVAL, "params is NULL");
     if (p->dtype != SK_F32 && p->dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", p->dtype);
-    if (p->algo != SK_ALGO_BATCHED && p->algo != SK_ALGO_PLAIN)
+    if (p->algo != SK_ALGO_BATCHED && p->algo != SK_ALGO_PLAIN && p->algo != SK_ALGO_PIPELINE)
         return fail(SK_EINVAL, "algo %d", p->algo);
     if (is_fd(*p)) {
         if (p->order < 0) return fail(SK_EINVAL, "dyadic order %d < 0", p->order);
@@ -200,12 +200,16 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dtype != SK_F64) return fail(SK_EUNSUPPORTED, "the plain algorithm is FP64 only");
         if (backward) return fail(SK_EUNSUPPORTED, "the plain algorithm is forward only");
     }
+    if (p->algo == SK_ALGO_PIPELINE) {
+        if (is_fd(*p)) return fail(SK_EUNSUPPORTED, "the strip pipeline runs the polynomial schemes");
+        if (backward) return fail(SK_EUNSUPPORTED, "the strip pipeline is forward only");
+    }
     if (p->gram != SK_GRAM_NATIVE && p->gram != SK_GRAM_BF16X3 && p->gram != SK_GRAM_MFMA)
         return fail(SK_EINVAL, "gram mode %d", p->gram);
     if (p->gram == SK_GRAM_BF16X3 && p->dtype != SK_F32)
         return fail(SK_EUNSUPPORTED, "the bf16 split Gram is for SK_F32 paths");
-    if (p->gram == SK_GRAM_BF16X3 && p->algo != SK_ALGO_BATCHED)
-        return fail(SK_EUNSUPPORTED, "the bf16 split Gram is a batched-algorithm mode");
+    if (p->gram == SK_GRAM_BF16X3 && p->algo == SK_ALGO_PLAIN)
+        return fail(SK_EUNSUPPORTED, "the bf16 split Gram is not a plain-algorithm mode");
     if (p->flags & ~SK_SYMMETRIC) return fail(SK_EINVAL, "unknown flags 0x%x", p->flags);
     return SK_OK;
 }
@@ -426,6 +430,10 @@ int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
 }
 
 template <typename R>
+int pipe_pair(const sk_params& p, const R* x, int64_t lx_pts, const R* y, int64_t ly_pts, int64_t d,
+              R* K, int32_t* Kexp, int64_t k_idx, void* ws, size_t wsb, hipStream_t st);
+
+template <typename R>
 int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
                  int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
                  hipStream_t st) {
@@ -433,6 +441,15 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
     if (npairs == 0) return SK_OK;
     const int lam = lam_of(p);
     const int64_t lx = lxp - 1, ly = lyp - 1;
+    if (p.algo == SK_ALGO_PIPELINE) {
+        for (int64_t a = 0; a < nx; ++a)
+            for (int64_t b = 0; b < ny; ++b) {
+                const int rc = pipe_pair<R>(p, X + a * lxp * d, lxp, Y + b * lyp * d, lyp, d, K, Kexp,
+                                            a * ny + b, ws, wsb, st);
+                if (rc) return rc;
+            }
+        return SK_OK;
+    }
     if (p.algo == SK_ALGO_PLAIN) {
         const int64_t need = std::max<int64_t>(((lx + ly) << lam) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
         if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
@@ -1096,6 +1113,87 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
     return SK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// strip pipeline (SK_ALGO_PIPELINE): one pair at a time, its strips on
+// co-resident workgroups
+// ---------------------------------------------------------------------------
+// polls of a pipeline wait before it gives up (about ten seconds)
+constexpr int kPipeSpinLimit = 1 << 24;
+
+struct PipeLayout {
+    int64_t c, xb, prog, abort, total;
+};
+
+// Workspace of one pair with lx, ly (unrefined) segments.
+PipeLayout pipe_layout(int64_t lx, int64_t ly, const sk_params& p) {
+    const int lam = lam_of(p);
+    const size_t es = esize(p);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    PipeLayout L;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.c = take((int64_t)g.nsteps_pad * SK_LANES * (int64_t)es);
+    L.xb = take(2 * (int64_t)g.ly * sk_gx_words(p.order, (int)es) * 4);
+    L.prog = take(4 * (int64_t)std::max(1, g.nstrips));
+    L.abort = take(4);
+    L.total = off;
+    return L;
+}
+
+// One pair: increment Gram into the skewed layout, then the pipelined sweep.
+template <typename R>
+int pipe_pair(const sk_params& p, const R* x, int64_t lx_pts, const R* y, int64_t ly_pts, int64_t d,
+              R* K, int32_t* Kexp, int64_t k_idx, void* ws, size_t wsb, hipStream_t st) {
+    const int lam = lam_of(p);
+    const int64_t lx = lx_pts - 1, ly = ly_pts - 1;
+    const PipeLayout L = pipe_layout(lx, ly, p);
+    if (wsb < (size_t)L.total)
+        return fail(SK_EWORKSPACE, "the strip pipeline needs %lld bytes", (long long)L.total);
+    char* w = static_cast<char*>(ws);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    R* cskew = reinterpret_cast<R*>(w + L.c);
+    if (g.nsteps > 0) {
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.ny = 1; src.lx_pts = lx_pts; src.ly_pts = ly_pts; src.first = 0; src.desc = nullptr;
+        src.stride = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false, 0);
+        GramArgs<R> ga;
+        ga.X = x; ga.Y = y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam;
+        ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
+        SK_LAUNCH("gram", st, launch_gram(ga, 1, g.nsteps_pad, (int)lx, (int)ly, p.gram == SK_GRAM_NATIVE, st),
+                  "increment Gram");
+    }
+    int* prog = reinterpret_cast<int*>(w + L.prog);
+    int* abrt = reinterpret_cast<int*>(w + L.abort);
+    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), std::max(1, g.nstrips), st), "fill");
+    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(abrt), 1, st), "fill");
+    PipeArgs<R> pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.cskew = cskew; pa.tab = table_for<R>(p); pa.lx = g.lx; pa.ly = g.ly;
+    pa.K = K; pa.Kexp = Kexp; pa.k_idx = k_idx;
+    pa.xb = reinterpret_cast<unsigned*>(w + L.xb); pa.progress = prog; pa.abort = abrt;
+    pa.spin_limit = kPipeSpinLimit;
+    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+              "pipelined strip sweep");
+    return SK_OK;
+}
+
+template <typename R>
+int pairs_pipe(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
+               int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+               hipStream_t st) {
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int rc = pipe_pair<R>(p, Xc + xo[i] * d, xo[i + 1] - xo[i], Yc + yo[i] * d,
+                                    yo[i + 1] - yo[i], d, K, Kexp, i, ws, wsb, st);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
 // One-shot pairs calls: a plan with the tuned configuration of this shape if
 // there is one, else longest-first, transposed and bucketed.
 int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
@@ -1170,6 +1268,8 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     const int lam = lam_of(*p);
+    if (p->algo == SK_ALGO_PIPELINE)
+        return std::max<size_t>(256, (size_t)pipe_layout(lx_pts - 1, ly_pts - 1, *p).total);
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t lx = lx_pts - 1, ly = ly_pts - 1;
         return (size_t)std::max<int64_t>(256, std::max<int64_t>(((lx + ly) << lam) * (p->order + 1),
@@ -1192,6 +1292,12 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     if (check_offsets(x_off, npairs, lam_of(*p), "x") || check_offsets(y_off, npairs, lam_of(*p), "y"))
         return 0;
     const int lam = lam_of(*p);
+    if (p->algo == SK_ALGO_PIPELINE) {
+        int64_t need = 256;
+        for (int64_t i = 0; i < npairs; ++i)
+            need = std::max(need, pipe_layout(x_off[i + 1] - x_off[i] - 1, y_off[i + 1] - y_off[i] - 1, *p).total);
+        return (size_t)need;
+    }
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t need = 256;
         for (int64_t i = 0; i < npairs; ++i) {
@@ -1247,6 +1353,13 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
         return rc;
     if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
+        if (p->algo == SK_ALGO_PIPELINE) {
+            if (p->dtype == SK_F32)
+                return pairs_pipe<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
+                                         npairs, d, *p, (float*)k, k_exp, ws, ws_bytes, stream);
+            return pairs_pipe<double>((const double*)Xcat, x_off, (const double*)Ycat, y_off,
+                                      npairs, d, *p, (double*)k, k_exp, ws, ws_bytes, stream);
+        }
         if (p->algo == SK_ALGO_PLAIN) {
             if (p->dtype == SK_F32)
                 return pairs_plain<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,

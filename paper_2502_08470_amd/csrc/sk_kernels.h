@@ -672,6 +672,235 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 }
 
 // ---------------------------------------------------------------------------
+// (c') strip pipeline for single long pairs: the strips of one pair run on
+// different co-resident workgroups (one wave each; workgroup w takes strips
+// w, w + W, ...), in the anti-diagonal order of Section 3.2 applied to strips
+// instead of cells.  Strip s hands the right edge of every column to strip
+// s+1 through global records (two slots by strip parity) and publishes how
+// many columns it has handed over; strip s+1 waits for that count before it
+// loads the records of a block of columns, one 8-step block ahead of their
+// use.  Strip s+2 rewrites a slot only after strip s+1 has loaded it (it
+// depends on strip s+1's later columns), so two slots suffice.  Waits are
+// bounded: a wave that waits too long raises the abort flag, and every
+// waiting wave leaves on it, writing NaN for the pair.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PipeArgs {
+    const R* cskew;        // the pair's skewed cell constants (rows s Tp + t)
+    SkTab<R> tab;
+    int32_t lx, ly;        // grid segments (refined)
+    R* K;
+    int32_t* Kexp;         // nullable
+    int64_t k_idx;
+    unsigned* xb;          // records [2][ly][sk_gx_words]
+    int* progress;         // [nstrips], zero at launch: columns handed over
+    int* abort;            // zero at launch
+    int32_t spin_limit;    // polls before a wait gives up
+};
+
+// Wave-uniform bounded wait until *prog >= need.  Returns false on abort.
+__device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* abort, int limit) {
+    for (int it = 0;; ++it) {
+        if (__hip_atomic_load(prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (it >= limit) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
+template <typename R, int N, int TMAX>
+__global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
+    const int r = threadIdx.x;
+    const SkGeom g = sk_make_geom(a.lx, a.ly);
+    if (g.nsteps == 0) {
+        if (blockIdx.x == 0 && r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (R)1, 0);
+        return;
+    }
+    constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
+    constexpr int XR = (8 * GXW + 63) / 64;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
+    const int ly = g.ly;
+    const int nloc = (ly + 63 + 7) & ~7;  // local steps of one strip
+    // lane 0 reads column t at local step t
+    auto col0 = [&](int t) -> int { return t < ly ? t : -1; };
+    for (int s = blockIdx.x; s < g.nstrips; s += gridDim.x) {
+        const int i = s * 64 + r;
+        const bool rowok = i < g.lx;
+        const bool has_next = s + 1 < g.nstrips;
+        const unsigned* rin = a.xb + (size_t)((s + 1) & 1) * ly * GXW;  // strip s-1's slot
+        unsigned* rout = a.xb + (size_t)(s & 1) * ly * GXW;
+        const R* cs = a.cskew + (int64_t)s * g.Tp * 64;
+        const int64_t rows_left = (int64_t)g.nsteps_pad - (int64_t)s * g.Tp;
+        R P[N + 1], Qs[N + 1];
+        double P0 = 0.0, P1 = 0.0, Qs0 = 0.0, Qs1 = 0.0;
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            P[n] = (R)0;
+            Qs[n] = (R)0;
+        }
+        int E = 0, Es = 0;
+        unsigned xr[XR];
+#pragma unroll
+        for (int h = 0; h < XR; ++h) xr[h] = 0u;
+        bool ok = true;
+        if (s > 0) {  // records of columns 0..7
+            ok = sk_wait_count(a.progress + s - 1, ly < 8 ? ly : 8, a.abort, a.spin_limit);
+            if (ok) {
+#pragma unroll
+                for (int h = 0; h < XR; ++h) {
+                    const int w = r + 64 * h;
+                    if (w < 8 * GXW) {
+                        const int m = w / GXW, q = w - m * GXW;
+                        const int col = col0(m);
+                        if (col >= 0) xr[h] = rin[(int64_t)col * GXW + q];
+                    }
+                }
+            }
+        }
+        int published = 0;
+        for (int t0 = 0; ok && t0 < nloc; t0 += 8) {
+            if (s > 0) {
+                const int need = t0 + 16 < ly ? t0 + 16 : ly;
+                ok = sk_wait_count(a.progress + s - 1, need, a.abort, a.spin_limit);
+                if (!ok) break;
+                sk_gx_stage<GXW>(xr, stage, rin, t0 + 8, r, col0);
+            }
+            R cb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cb[u] = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
+            bool live = false;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = t0 + u, j = t - r;
+                R Qin[N + 1];
+#pragma unroll
+                for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                double Qin0 = lane_from_prev(Qs0), Qin1 = lane_from_prev(Qs1);
+                int Ein = lane_from_prev(Es);
+                live = rowok && j >= 0 && j < ly;
+                if (live) {
+                    if (j == 0) {
+                        P0 = 1.0;
+                        P1 = 0.0;
+#pragma unroll
+                        for (int n = 2; n <= N; ++n) P[n] = (R)0;
+                        E = 0;
+                    }
+                    if (r == 0) {
+                        if (s == 0) {
+                            Qin0 = 1.0;
+                            Qin1 = 0.0;
+#pragma unroll
+                            for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
+                            Ein = 0;
+                        } else {
+                            const unsigned* rec = stage + u * GXW;
+                            Qin0 = *reinterpret_cast<const double*>(rec);
+                            Qin1 = *reinterpret_cast<const double*>(rec + 2);
+#pragma unroll
+                            for (int n = 2; n <= N; ++n)
+                                Qin[n] = *reinterpret_cast<const R*>(rec + 4 + (n - 2) * (ES / 4));
+                            Ein = (int)rec[4 + (N - 1) * (ES / 4)];
+                        }
+                    }
+                    const int Ec = E > Ein ? E : Ein;
+                    const int dp = E - Ec, dq = Ein - Ec;
+                    if (sk_wave_any(dp != 0 || dq != 0)) {
+                        P0 = ldexp(P0, dp);
+                        P1 = ldexp(P1, dp);
+                        Qin0 = ldexp(Qin0, dq);
+                        Qin1 = ldexp(Qin1, dq);
+#pragma unroll
+                        for (int n = 2; n <= N; ++n) {
+                            P[n] = sk_ldexp(P[n], dp);
+                            Qin[n] = sk_ldexp(Qin[n], dq);
+                        }
+                    }
+                    E = Ec;
+                }
+                P[0] = (R)P0;
+                P[1] = (R)P1;
+                Qin[0] = (R)Qin0;
+                Qin[1] = (R)Qin1;
+                R Po[N + 1], Qo[N + 1];
+                double Po0, Po1, Qo0, Qo1;
+                sk_cell_fwd<R, N, TMAX>(P, Qin, P0, P1, Qin0, Qin1, cb[u], live, a.tab, Po, Qo, Po0,
+                                        Po1, Qo0, Qo1);
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    P[n] = Po[n];
+                    Qs[n] = Qo[n];
+                }
+                P0 = Po0;
+                P1 = Po1;
+                Qs0 = Qo0;
+                Qs1 = Qo1;
+                Es = E;
+                if (live) {
+                    if (r == 63 && has_next) {
+                        unsigned* rec = rout + (int64_t)j * GXW;
+                        *reinterpret_cast<double*>(rec) = Qo0;
+                        *reinterpret_cast<double*>(rec + 2) = Qo1;
+#pragma unroll
+                        for (int n = 2; n <= N; ++n)
+                            *reinterpret_cast<R*>(rec + 4 + (n - 2) * (ES / 4)) = Qo[n];
+                        rec[4 + (N - 1) * (ES / 4)] = (unsigned)E;
+                    }
+                    if (i == g.lx - 1 && j == ly - 1) {
+                        R kr = (R)0;
+#pragma unroll
+                        for (int n = N; n >= 2; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
+                        const double kv = 0.5 * (Po0 + Qo0 + Po1 + Qo1 + (double)kr);
+                        sk_write_k(a.K, a.Kexp, a.k_idx, kv, E);
+                    }
+                }
+            }
+            // lane 63 has handed over the columns j <= t0 + 7 - 63: publish
+            // them (its release store orders its record stores before the count)
+            int done = t0 + 8 - 63;
+            done = done < 0 ? 0 : (done > ly ? ly : done);
+            if (has_next && done > published) {
+                if (r == 63)
+                    __hip_atomic_store(a.progress + s, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                published = done;
+            }
+            // per-lane rescale of the live state (exact: powers of two)
+            if (live) {
+                R m = (R)fmax(fmax(fabs(P0), fabs(Qs0)), fmax(fabs(P1), fabs(Qs1)));
+#pragma unroll
+                for (int n = 2; n <= N; ++n) {
+                    R ap = sk_abs(P[n]), aq = sk_abs(Qs[n]);
+                    m = ap > m ? ap : m;
+                    m = aq > m ? aq : m;
+                }
+                const int sh = sk_rescale_shift<R>(m);
+                if (sh != 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        P[n] = sk_ldexp(P[n], -sh);
+                        Qs[n] = sk_ldexp(Qs[n], -sh);
+                    }
+                    P0 = ldexp(P0, -sh);
+                    P1 = ldexp(P1, -sh);
+                    Qs0 = ldexp(Qs0, -sh);
+                    Qs1 = ldexp(Qs1, -sh);
+                    E += sh;
+                    Es = E;
+                }
+            }
+        }
+        if (!ok) {  // a wait gave up: the pair's value is unknown
+            if (r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (double)NAN, 0);
+            return;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // (d) adjoint sweep: reversed wavefront with segment recompute
 // ---------------------------------------------------------------------------
 template <typename R>

@@ -1,5 +1,7 @@
 // Definitions of SkLaunch<R> (included once per real type).
 #pragma once
+#include <algorithm>
+
 #include "sk_launch.h"
 
 #define SK_CHECK_LAUNCH() \
@@ -111,6 +113,38 @@ hipError_t SkLaunch<R>::sweep(const SweepArgs<R>& a, int N, bool interp, bool ck
         case 6: return sk_sweep_t<R, 6>(a, interp, ckpt, npairs, ring, gx, st);
         case 7: return sk_sweep_t<R, 7>(a, interp, ckpt, npairs, ring, gx, st);
         case 8: return sk_sweep_t<R, 8>(a, interp, ckpt, npairs, ring, gx, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int N, int TMAX>
+static hipError_t sk_pipe_n(const PipeArgs<R>& a, hipStream_t st) {
+    const void* kern = reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX>);
+    const size_t lds = (size_t)sk_gx_stage_bytes(N, (int)sizeof(R));
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64, lds);
+    if (e != hipSuccess) return e;
+    const SkGeom g = sk_make_geom(a.lx, a.ly);
+    int64_t W = std::min<int64_t>(std::max(1, g.nstrips), (int64_t)per * ncu);
+    if (W < 1) return hipErrorInvalidConfiguration;
+    PipeArgs<R> arg = a;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(kern, dim3((unsigned)W), dim3(64), args, (unsigned)lds, st);
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, hipStream_t st) {
+    constexpr int T = SkTailMax<R>::value;
+    switch (N) {
+        case 2: return interp ? sk_pipe_n<R, 2, T>(a, st) : sk_pipe_n<R, 2, 0>(a, st);
+        case 3: return interp ? sk_pipe_n<R, 3, T>(a, st) : sk_pipe_n<R, 3, 0>(a, st);
+        case 4: return interp ? sk_pipe_n<R, 4, T>(a, st) : sk_pipe_n<R, 4, 0>(a, st);
+        case 5: return interp ? sk_pipe_n<R, 5, T>(a, st) : sk_pipe_n<R, 5, 0>(a, st);
+        case 6: return interp ? sk_pipe_n<R, 6, T>(a, st) : sk_pipe_n<R, 6, 0>(a, st);
+        case 7: return interp ? sk_pipe_n<R, 7, T>(a, st) : sk_pipe_n<R, 7, 0>(a, st);
+        case 8: return interp ? sk_pipe_n<R, 8, T>(a, st) : sk_pipe_n<R, 8, 0>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -48,6 +48,8 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=P(dtype=3)), L.SK_EINVAL),
     (dict(p=P(algo=5)), L.SK_EINVAL),
     (dict(p=P(algo=1, dtype=1)), L.SK_EUNSUPPORTED),
+    (dict(p=P(algo=2, scheme=0, order=1)), L.SK_EUNSUPPORTED),  # pipeline: polynomial schemes
+    (dict(p=P(algo=3)), L.SK_EINVAL),
     (dict(p=P(), d=0), L.SK_EINVAL),
     (dict(p=P(), lxp=0), L.SK_EINVAL),
     (dict(p=P(), nx=-1), L.SK_EINVAL),
@@ -55,6 +57,7 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=P(), K=0), L.SK_EINVAL),
     (dict(p=P(), ws=0), L.SK_EINVAL),
     (dict(p=P(), wsb=16), L.SK_EWORKSPACE),
+    (dict(p=P(algo=2), wsb=16), L.SK_EWORKSPACE),
     (dict(p=None), L.SK_EINVAL),
     (dict(p=P(gram=3)), L.SK_EINVAL),
     (dict(p=P(gram=1, dtype=0)), L.SK_EUNSUPPORTED),
@@ -82,6 +85,7 @@ def test_backward_rejections():
     assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
     assert bwd(P(dyadic=1)) == L.SK_EUNSUPPORTED  # hybrid refined grid: forward only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
+    assert bwd(P(algo=2)) == L.SK_EUNSUPPORTED  # strip pipeline: forward only
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL
     # SK_SYMMETRIC needs a Gram call whose Y is X (same pointer and shape)

@@ -1,0 +1,124 @@
+"""Strip pipeline (SK_ALGO_PIPELINE): the strips of one long pair run on
+co-resident workgroups that hand their strip-boundary edges on through
+global memory (the anti-diagonal wavefront of Section 3.2 over strips).
+Parity with the FP64 oracle and with the batched algorithm, which runs the
+same cell arithmetic on one wave per pair."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import bm_paths, log_banner, rel_err, rel_err_exp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sk():
+    import paper_2502_08470_amd as P
+    from paper_2502_08470_amd import _lib
+    _lib.lib()
+    return P
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda")
+
+
+# point counts: 16 strips, 3 strips with a 1-row last strip, 2 strips, 1 strip,
+# one point; y shorter than a strip (padded strip period) and one segment
+LENS_X = [1001, 130, 66, 40, 1, 700]
+LENS_Y = [300, 37, 201, 2, 50, 650]
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 4), ("interp", 5), ("approx", 8)])
+def test_pipeline_fp64_matches_oracle(sk, scheme, order):
+    from oracle import c_oracle as C
+    log_banner(f"pipeline fp64 {scheme} {order}")
+    rng = np.random.default_rng(81)
+    xs = [bm_paths(rng, 1, n - 1, 3, 0.4 / np.sqrt(n))[0] for n in LENS_X]
+    ys = [bm_paths(rng, 1, n - 1, 3, 0.4 / np.sqrt(n))[0] for n in LENS_Y]
+    k = sk.pairs([dev(a, torch.float64) for a in xs], [dev(b, torch.float64) for b in ys],
+                 scheme, order, algo="pipeline").cpu().numpy()
+    kind = C.APPROX if scheme == "approx" else C.INTERP
+    m, e = C.pairs(xs, ys, kind, order)
+    err = rel_err(k, np.ldexp(m, e))
+    cells = np.array([(a - 1) * (b - 1) for a, b in zip(LENS_X, LENS_Y)], dtype=np.float64)
+    # interpolation: the literal oracle's own Vandermonde rounding grows with the cells
+    tol = 1e-12 if scheme == "approx" else 1e-12 + 2e-17 * cells
+    assert np.all(err < tol), err
+    assert k[4] == 1.0
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 6), ("interp", 6)])
+def test_pipeline_matches_batched_fp32(sk, scheme, order):
+    # same cell arithmetic, different wave grouping: bit-identical for the
+    # approximation scheme; the interpolation tail is decided per wave, so a
+    # row below 2^-26 of the edge scale may be folded in one and not the other
+    log_banner(f"pipeline vs batched fp32 {scheme} {order}")
+    rng = np.random.default_rng(82)
+    xs = [bm_paths(rng, 1, n - 1, 6, 0.5 / np.sqrt(n))[0].astype(np.float32) for n in LENS_X]
+    ys = [bm_paths(rng, 1, n - 1, 6, 0.5 / np.sqrt(n))[0].astype(np.float32) for n in LENS_Y]
+    # one-pair Grams: the batched algorithm then keeps the pair's orientation
+    kp, kb = [], []
+    for a, b in zip(xs, ys):
+        at, bt = dev(a[None], torch.float32), dev(b[None], torch.float32)
+        kp.append(sk.gram(at, bt, scheme, order, algo="pipeline").cpu().numpy()[0, 0])
+        kb.append(sk.gram(at, bt, scheme, order).cpu().numpy()[0, 0])
+    kp, kb = np.array(kp), np.array(kb)
+    if scheme == "approx":
+        assert np.array_equal(kp, kb), (kp, kb)
+    else:
+        assert rel_err(kp, kb).max() < 1e-6
+
+
+def test_pipeline_exponent_tracking_fp32(sk):
+    # kernel values far beyond the FP32 range (|c| large on long paths)
+    from oracle import c_oracle as C
+    log_banner("pipeline exponent tracking fp32")
+    rng = np.random.default_rng(83)
+    X = bm_paths(rng, 1, 600, 4, 0.35).astype(np.float32)
+    Y = bm_paths(rng, 1, 500, 4, 0.35).astype(np.float32)
+    Xt, Yt = dev(X, torch.float32), dev(Y, torch.float32)
+    Kp, Ep = sk.gram(Xt, Yt, "approx", 8, algo="pipeline", return_exp=True)
+    Kb, Eb = sk.gram(Xt, Yt, "approx", 8, return_exp=True)
+    assert int(Ep.cpu().numpy()[0, 0]) > 128
+    assert np.array_equal(Kp.cpu().numpy(), Kb.cpu().numpy())
+    assert np.array_equal(Ep.cpu().numpy(), Eb.cpu().numpy())
+    # the value (about -0.11 * 2^178) comes out of heavy cancellation, so the
+    # FP32 result is only a sanity check against the oracle
+    m, e = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX, 8)
+    assert rel_err_exp(Kp.cpu().numpy(), Ep.cpu().numpy(), m, e).max() < 1e-2
+
+
+def test_pipeline_hybrid_fp64(sk):
+    from oracle import c_oracle as C
+    log_banner("pipeline hybrid fp64")
+    rng = np.random.default_rng(84)
+    X = bm_paths(rng, 2, 180, 3, 0.05)
+    Y = bm_paths(rng, 1, 90, 3, 0.05)
+    K = sk.gram(dev(X, torch.float64), dev(Y, torch.float64), "approx", 4, algo="pipeline",
+                dyadic=1).cpu().numpy()
+    m, e = C.gram(X, Y, C.APPROX, 4, lam=1)
+    assert rel_err(K, np.ldexp(m, e)).max() < 1e-12
+
+
+def test_pipeline_full_size_fp32(sk):
+    # one pair of 2049-point paths in R^8 (32 strips of 2048 columns):
+    # against the oracle; one pair of 8193-point paths (128 strips) against
+    # the batched algorithm (bit-identical)
+    from oracle import c_oracle as C
+    log_banner("pipeline full size fp32")
+    rng = np.random.default_rng(85)
+    X = bm_paths(rng, 1, 2048, 8, 0.5 / np.sqrt(2048)).astype(np.float32)
+    Y = bm_paths(rng, 1, 2048, 8, 0.5 / np.sqrt(2048)).astype(np.float32)
+    K = sk.gram(dev(X, torch.float32), dev(Y, torch.float32), "approx", 8, algo="pipeline")
+    m, e = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX, 8)
+    assert rel_err(K.cpu().numpy(), np.ldexp(m, e)).max() < 2e-5
+    X = bm_paths(rng, 1, 8192, 8, 0.5 / np.sqrt(8192)).astype(np.float32)
+    Y = bm_paths(rng, 1, 8192, 8, 0.5 / np.sqrt(8192)).astype(np.float32)
+    Xt, Yt = dev(X, torch.float32), dev(Y, torch.float32)
+    log_banner("pipeline 8193 x 8193")
+    Kp = sk.gram(Xt, Yt, "approx", 8, algo="pipeline").cpu().numpy()
+    log_banner("batched 8193 x 8193")
+    Kb = sk.gram(Xt, Yt, "approx", 8).cpu().numpy()
+    assert np.isfinite(Kp).all() and np.array_equal(Kp, Kb), (Kp, Kb)

@@ -30,6 +30,7 @@ __all__ = [
     "uneven_pairs",
     "mmd_sets",
     "large_gram",
+    "long_pair",
     "WORKLOADS",
 ]
 
@@ -132,10 +133,22 @@ def large_gram(seed: int = 0, n: int = 1024, steps: int = 1024, d: int = 32):
     return x.astype(np.float32), y.astype(np.float32)
 
 
+def long_pair(seed: int = 0, steps: int = 16384, d: int = 8):
+    """One pair of long paths (far more rows than one wave's 64 lanes): R^d
+    Brownian paths with `steps` steps of std 0.5/sqrt(steps), x then y.
+    FP32 (rounded here)."""
+    rng = np.random.default_rng(seed)
+    std = 0.5 / np.sqrt(steps)
+    x = brownian(rng, 1, steps, d, std)
+    y = brownian(rng, 1, steps, d, std)
+    return x.astype(np.float32), y.astype(np.float32)
+
+
 WORKLOADS = {
     "small_fp64_gram": small_fp64_gram,
     "batched_interp_gram": batched_interp_gram,
     "uneven_pairs": uneven_pairs,
     "mmd_sets": mmd_sets,
     "large_gram": large_gram,
+    "long_pair": long_pair,
 }
