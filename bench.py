@@ -193,6 +193,7 @@ def long_pair_study(steps: int = 16384) -> int:
     of the forward cell count against the FP32 VALU peak."""
     import torch
     import paper_2502_08470_amd as sk
+    from paper_2502_08470_amd import _lib
     import workloads as W
 
     dev = torch.device("cuda:0")
@@ -205,13 +206,20 @@ def long_pair_study(steps: int = 16384) -> int:
             reps = 5 if algo == "pipeline" else 2
             k = sk.gram(X, Y, scheme, order, algo=algo)  # warm-up (and the tables)
             torch.cuda.synchronize()
+            _lib.profile_enable(True)
             t0 = time.perf_counter()
             for _ in range(reps):
                 k = sk.gram(X, Y, scheme, order, algo=algo)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / reps
+            # HIP-event kernel times on the launch stream (the cooperative
+            # launch of the pipeline is not traced by the profiler tools here)
+            kern = {name: _lib.profile_read(name)[0] / reps
+                    for name in ("gram", "sweep", "sweep_pipe")}
+            _lib.profile_enable(False)
             fl = fwd_cell_flops(order, 0, deciding=scheme == "interp")
             rows.append({"scheme": scheme, "order": order, "algo": algo, "ms": ms,
+                         "kernel_ms": {n: v for n, v in kern.items() if v > 0},
                          "cells_per_s": cells / (ms * 1e-3),
                          "tflops": fl * cells / (ms * 1e-3) / 1e12,
                          "frac_of_fp32_peak": fl * cells / (ms * 1e-3) / PEAK_FP32_VALU,
