@@ -81,14 +81,14 @@ def _interior(p: np.ndarray, q: np.ndarray, c: float, M: int) -> np.ndarray:
     "prop:a1": the p part (n >= 1) contributes to alpha = n + m, beta = m and
     the q part (n >= 0) to alpha = m, beta = n + m, each with weight
     c^m n! / (m! (n + m)!)."""
-    f = math.factorial
+    fact = np.array([float(math.factorial(k)) for k in range(M + 1)])
     a = np.zeros((M + 1, M + 1))
-    for n in range(1, len(p)):
-        for m in range(0, M + 1 - n):
-            a[n + m, m] += p[n] * c ** m * f(n) / (f(m) * f(n + m))
-    for n in range(0, len(q)):
-        for m in range(0, M + 1 - n):
-            a[m, n + m] += q[n] * c ** m * f(n) / (f(m) * f(n + m))
+    for n in range(1, min(len(p), M + 1)):
+        m = np.arange(0, M + 1 - n)
+        a[n + m, m] += p[n] * c ** m * fact[n] / (fact[m] * fact[n + m])
+    for n in range(0, min(len(q), M + 1)):
+        m = np.arange(0, M + 1 - n)
+        a[m, n + m] += q[n] * c ** m * fact[n] / (fact[m] * fact[n + m])
     return a
 
 
