@@ -174,19 +174,24 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                                             R* DP = nullptr, R* DQ = nullptr,
                                             int* Tkept = nullptr, int Tfix = 0) {
     constexpr int M = N + TMAX;
+    // powers of c needed before the tail (the deciding row N+1 unless the
+    // tail length is given); the tail computes its own as it goes
+    constexpr int MU = (TMAX > 0 && !FIXT) ? N + 1 : N;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
     cp[0] = (R)1;
-#pragma unroll
-    for (int m = 1; m <= M; ++m) {
+    // the sweep's state takes c^m/m! by its own recurrence (independent
+    // rounding of the Toeplitz and Hankel parts measured about twice as
+    // accurate); where FP32 accuracy is enough one multiply does
+    auto power = [&](int m) {
         cp[m] = cp[m - 1] * c;
-        // the sweep's state takes c^m/m! by its own recurrence (independent
-        // rounding of the Toeplitz and Hankel parts measured about twice as
-        // accurate); where FP32 accuracy is enough one multiply does
         w[m] = HI ? w[m - 1] * (c * (R)(1.0 / m)) : cp[m] * ifact<R>(m);
-    }
-    if (WD) {
-        // rows 0..N-1 are always written; tail rows only when kept
+    };
+#pragma unroll
+    for (int m = 1; m <= MU; ++m) power(m);
+    if (WD && !FIXT) {
+        // rows 0..N-1 are always written; tail rows only when kept (a replay
+        // with the tail length given reads exactly the rows it folds)
 #pragma unroll
         for (int r = N; r < M; ++r) {
             DP[r] = (R)0;
@@ -265,10 +270,12 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         const R scale = (R)SkEps<R>::value * (R)(fabs(Po0) + fabs(Qo0));
         const R ac = sk_abs(c);
         R t0p = (R)0, t0q = (R)0, t1p = (R)0, t1q = (R)0;  // tail into rows 0, 1
+        int folded = 0;  // wave-uniform
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
             if (FIXT && t >= Tfix) break;
             const int r = N + 1 + t;
+            if (r > MU) power(r);
             R tp = (R)0, tq = (R)0;
 #pragma unroll
             for (int k = N; k >= 0; --k) {
@@ -295,6 +302,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 tqp = tq;
             }
             if (Tkept) *Tkept = t + 1;
+            folded = t + 1;
             t0p = fma(tab.rs[0][t], arp, t0p);
             t0q = fma(tab.rs[0][t], arq, t0q);
             t1p = fma(tab.rs[1][t], arp, t1p);
@@ -305,7 +313,9 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
         }
-        if (HI) {
+        if (folded == 0) {
+            // nothing folded (the common case for small |c|): rows 0, 1 stand
+        } else if (HI) {
             Po0 += (double)t0p;
             Qo0 += (double)t0q;
             Po1 += (double)t1p;
@@ -342,11 +352,12 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
     cp[0] = (R)1;
-#pragma unroll
-    for (int m = 1; m <= M; ++m) {
+    auto power = [&](int m) {
         cp[m] = cp[m - 1] * c;
         w[m] = cp[m] * ifact<R>(m);  // gradients need FP32 accuracy only
-    }
+    };
+#pragma unroll
+    for (int m = 1; m <= N; ++m) power(m);  // tail rows compute theirs as they go
     // row 0 initialises the outputs (w_0 = c^0 = 1)
     aP[0] = a[0];
     aQ[0] = b[0];
@@ -362,6 +373,7 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
 #pragma unroll
     for (int r = 1; r <= M; ++r) {
         if (r > N && r - N > Tu) break;
+        if (r > N) power(r);
         R ea, eb;
         if (r <= N) {
             ea = a[r];
