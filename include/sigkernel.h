@@ -196,8 +196,11 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
  * the pairs (longest first by wavefront steps, or as given), whether each
  * pair is computed transposed (k(x, y) = k(y, x) holds for every scheme, so
  * the shorter path can take the role whose edges are held in LDS), the
- * grouping of pairs into launches by the LDS size their sweep needs, the
- * chunking for a given workspace size and the workspace layout.
+ * grouping of pairs into launches by the LDS size their sweep needs, whether
+ * the forward of pairs with several 64-row strips runs on the strip pipeline
+ * (their strips as jobs on co-resident workgroups, which balances the load
+ * strip by strip; see SK_ALGO_PIPELINE), the chunking for a given workspace
+ * size and the workspace layout.
  * sigkernel_plan_upload copies the per-pair descriptors into the workspace
  * once (it synchronises `stream`); afterwards sigkernel_plan_forward and
  * sigkernel_plan_backward only queue kernels, with no host synchronisation,
@@ -233,9 +236,9 @@ int sigkernel_plan_backward(const sk_plan* plan, const void* Xcat, const void* Y
 int sigkernel_plan_tune(sk_plan* plan, const void* Xcat, const void* Ycat, void* ws,
                         size_t ws_bytes, hipStream_t stream, double* best_ms);
 int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, int32_t* buckets,
-                          int64_t* launches);
+                          int32_t* pipeline, int64_t* launches);
 int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,
-                             size_t ws_bytes);
+                             int32_t pipeline, size_t ws_bytes);
 void sigkernel_plan_destroy(sk_plan* plan);
 
 /*

@@ -107,9 +107,10 @@ def lib():
     L.sigkernel_plan_tune.argtypes = [vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
     L.sigkernel_plan_tune.restype = ctypes.c_int
     L.sigkernel_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                        ctypes.POINTER(i32), ctypes.POINTER(i64)]
+                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i64)]
     L.sigkernel_plan_config.restype = ctypes.c_int
-    L.sigkernel_plan_configure.argtypes = [vp, i32, i32, i32, sz]
+    L.sigkernel_plan_configure.argtypes = [vp, i32, i32, i32, i32, sz]
     L.sigkernel_plan_configure.restype = ctypes.c_int
     L.sigkernel_plan_destroy.argtypes = [vp]
     L.sigkernel_plan_destroy.restype = None

@@ -298,18 +298,20 @@ class PairsPlan:
         return ms.value
 
     def config(self) -> dict:
-        o, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        o, w, b, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         n = ctypes.c_int64()
         L.check(self._lib.sigkernel_plan_config(self._h, ctypes.byref(o), ctypes.byref(w),
-                                                ctypes.byref(b), ctypes.byref(n)))
+                                                ctypes.byref(b), ctypes.byref(p), ctypes.byref(n)))
         return {"longest_first": bool(o.value), "transpose": bool(w.value),
-                "lds_classes": bool(b.value), "launches": int(n.value)}
+                "lds_classes": bool(b.value), "pipeline": bool(p.value), "launches": int(n.value)}
 
-    def configure(self, longest_first: bool, transpose: bool, lds_classes: bool):
+    def configure(self, longest_first: bool, transpose: bool, lds_classes: bool,
+                  pipeline: bool = False):
         """Set the configuration by hand (rebuilds the plan, grows the
-        workspace if this configuration needs more, and uploads)."""
+        workspace if this configuration needs more, and uploads).  ``pipeline``
+        runs the forward of pairs with several strips on the strip pipeline."""
         L.check(self._lib.sigkernel_plan_configure(self._h, int(longest_first), int(transpose),
-                                                   int(lds_classes), 0))
+                                                   int(lds_classes), int(pipeline), 0))
         nb = self._lib.sigkernel_plan_workspace(self._h)
         if nb > self.ws.numel():
             self.ws = _workspace(nb, self.device)

@@ -78,6 +78,8 @@ struct ProfScope {
 
 constexpr int64_t kAlign = 256;
 constexpr size_t kDefaultCap = (size_t)64 << 30;  // bytes of one default chunk (of 288 GB HBM)
+// polls of a strip-pipeline wait before it gives up (about ten seconds)
+constexpr int kPipeSpinLimit = 1 << 24;
 
 inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -300,7 +302,7 @@ int ckpt_stride(const sk_params& p) {
 // workspace layout of one chunk
 // ---------------------------------------------------------------------------
 struct Layout {
-    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, xb, total;
+    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, xb, pg, total;
 };
 
 // Region sizes for P pairs with total per-array element counts `z` (sum over
@@ -325,18 +327,19 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     L.kexp = backward ? take(P * 4) : off;
     L.desc = list ? take(P * (int64_t)sizeof(SkPairDesc)) : off;
     L.xb = take(z.xb * 4);
+    L.pg = take((z.pg + 1) * 4);  // strip-pipeline progress counters, then the abort flag
     L.total = off;
     return L;
 }
 
 SkPairSizes scale(const SkPairSizes& z, int64_t P) {
-    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P, z.xb * P};
+    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P, z.xb * P, z.pg * P};
     return o;
 }
 
 SkPairSizes add(const SkPairSizes& a, const SkPairSizes& b) {
     SkPairSizes o = {a.c + b.c, a.ck + b.ck, a.ce + b.ce, a.qb + b.qb,
-                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy, a.xb + b.xb};
+                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy, a.xb + b.xb, a.pg + b.pg};
     return o;
 }
 
@@ -411,6 +414,36 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
         SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, ring,
                                                   grid_cols(p, max_ly) > sa.gx_cols, st), "sweep");
     }
+    return SK_OK;
+}
+
+// Forward of a chunk of strip-pipeline pairs: increment Gram, then the
+// pipelined sweep over the chunk's job list (strips on co-resident waves).
+template <typename R>
+int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
+                           const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
+                           int max_ly, const int2* jobs, int64_t njobs, char* ws, const Layout& L,
+                           R* K, int32_t* Kexp, hipStream_t st) {
+    R* cskew = reinterpret_cast<R*>(ws + L.cskew);
+    GramArgs<R> ga;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam_of(p);
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st),
+              "increment Gram");
+    // progress counters of every pair, then the abort flag: zero
+    const int64_t npg = (L.total - L.pg) / 4;
+    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(ws + L.pg), npg, st), "fill");
+    PipeArgs<R> pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.cskew = cskew; pa.tab = table_for<R>(p);
+    pa.K = K; pa.Kexp = Kexp;
+    pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+    pa.progress = reinterpret_cast<int*>(ws + L.pg);
+    pa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
+    pa.spin_limit = kPipeSpinLimit;
+    pa.desc = src.desc; pa.jobs = jobs; pa.njobs = njobs; pa.lam = lam_of(p);
+    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+              "pipelined strip sweep");
     return SK_OK;
 }
 
@@ -698,14 +731,17 @@ struct PlanCfg {
     int32_t order;    // 1: longest pairs first (by wavefront steps); 0: given order
     int32_t swap;     // 1: transpose pairs whose second path is longer
     int32_t buckets;  // 1: separate launches per LDS class of the sweep
+    int32_t pipe;     // 1: forward of pairs with several strips on the strip pipeline
 };
 
 struct PlanChunk {
-    int64_t first, count;  // range of the plan's descriptor array
-    SkPairSizes tot;
-    int max_nsteps_pad, max_lx, max_ly, max_strips;
-    int ring_fwd, ring_adj;  // LDS ring columns (largest among pairs not using the global exchange)
-    int64_t max_pts;
+    int64_t first = 0, count = 0;  // range of the plan's descriptor array
+    SkPairSizes tot = {};
+    int max_nsteps_pad = 0, max_lx = 0, max_ly = 0, max_strips = 0;
+    int ring_fwd = 0, ring_adj = 0;  // LDS ring columns (largest among pairs not using the global exchange)
+    int64_t max_pts = 0;
+    bool pipe = false;               // forward on the strip pipeline: jobs of the plan's job list
+    int64_t jobs_first = 0, njobs = 0;
 };
 
 struct PlanImpl {
@@ -713,14 +749,17 @@ struct PlanImpl {
     int64_t npairs = 0, d = 0;
     bool backward = false;
     std::vector<int64_t> xo, yo;
-    PlanCfg cfg = {1, 1, 1};
+    PlanCfg cfg = {1, 1, 1, 1};
     // forward and backward chunkings (the backward keeps more state per pair,
     // so its chunks are smaller); descriptors hold chunk-relative offsets
     std::vector<SkPairDesc> fdesc, bdesc;
     std::vector<PlanChunk> fchunks, bchunks;
+    // strip-pipeline jobs (chunk-local pair, strip) of the forward's pipeline chunks
+    std::vector<int2> jobs;
     int max_ly = 0;  // longest column count of any pair (LDS check)
-    // workspace regions (bytes): descriptors, kernel-value scratch, chunk scratch
-    int64_t fdesc_off = 0, bdesc_off = 0, kbuf_off = 0, kexp_off = 0, scratch_off = 0, total = 0;
+    // workspace regions (bytes): descriptors, kernel-value scratch, jobs, chunk scratch
+    int64_t fdesc_off = 0, bdesc_off = 0, kbuf_off = 0, kexp_off = 0, jobs_off = 0, scratch_off = 0,
+            total = 0;
     const void* uploaded = nullptr;
 };
 
@@ -759,19 +798,31 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     const int64_t n = P.npairs;
     P.cfg = cfg;
     P.uploaded = nullptr;
-    std::vector<int32_t> ex(n), ey(n), sw(n), cls(n);
-    std::vector<int64_t> cost(n), seq(n);
+    std::vector<int32_t> ex(n), ey(n), sw(n), clsb(n), clsf(n), pipe(n), nstr(n);
+    std::vector<int64_t> cost(n), seqb(n), seqf(n);
+    int64_t njobs_all = 0;
     for (int64_t i = 0; i < n; ++i) {
         const int lx = (int)(P.xo[i + 1] - P.xo[i] - 1), ly = (int)(P.yo[i + 1] - P.yo[i] - 1);
         sw[i] = (cfg.swap && ly > lx) ? 1 : 0;
         ex[i] = sw[i] ? ly : lx;
         ey[i] = sw[i] ? lx : ly;
-        cost[i] = sk_make_geom(ex[i] << lam, ey[i] << lam).nsteps;
-        cls[i] = cfg.buckets ? lds_class(p, ey[i]) : 0;
-        seq[i] = i;
+        const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
+        cost[i] = g.nsteps;
+        nstr[i] = g.nstrips;
+        clsb[i] = cfg.buckets ? lds_class(p, ey[i]) : 0;
+        // forward: pairs of several strips go to the strip pipeline (class 6),
+        // which balances the load strip by strip instead of pair by pair
+        pipe[i] = (cfg.pipe && !is_fd(p) && g.nstrips >= 2) ? 1 : 0;
+        clsf[i] = pipe[i] ? 6 : clsb[i];
+        if (pipe[i]) njobs_all += g.nstrips;
+        seqb[i] = seqf[i] = i;
     }
-    std::stable_sort(seq.begin(), seq.end(), [&](int64_t u, int64_t v) {
-        if (cls[u] != cls[v]) return cls[u] > cls[v];
+    std::stable_sort(seqb.begin(), seqb.end(), [&](int64_t u, int64_t v) {
+        if (clsb[u] != clsb[v]) return clsb[u] > clsb[v];
+        return cfg.order ? cost[u] > cost[v] : false;
+    });
+    std::stable_sort(seqf.begin(), seqf.end(), [&](int64_t u, int64_t v) {
+        if (clsf[u] != clsf[v]) return clsf[u] > clsf[v];
         return cfg.order ? cost[u] > cost[v] : false;
     });
     const int64_t dbytes = align_up(n * (int64_t)sizeof(SkPairDesc));
@@ -779,7 +830,9 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     P.bdesc_off = dbytes;
     P.kbuf_off = P.bdesc_off + (P.backward ? dbytes : 0);
     P.kexp_off = P.kbuf_off + align_up(n * (int64_t)es);
-    P.scratch_off = P.kexp_off + align_up(n * 4);
+    P.jobs_off = P.kexp_off + align_up(n * 4);
+    P.scratch_off = P.jobs_off + align_up(njobs_all * (int64_t)sizeof(int2));
+    P.jobs.clear();
     size_t cap = kDefaultCap;
     if (ws_bytes != SIZE_MAX) {
         if (ws_bytes <= (size_t)P.scratch_off)
@@ -795,26 +848,35 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     // most of the GPU idle).  Each chunk launches its pairs longest first.
     auto chunk = [&](bool bwd, std::vector<SkPairDesc>& desc, std::vector<PlanChunk>& chunks,
                      int64_t* scratch) -> int {
+        const std::vector<int32_t>& cls = bwd ? clsb : clsf;
+        const std::vector<int64_t>& seq = bwd ? seqb : seqf;
         desc.assign(n, SkPairDesc());
         chunks.clear();
         *scratch = 0;
         std::vector<SkPairSizes> zs(n);
-        for (int64_t i = 0; i < n; ++i)
+        for (int64_t i = 0; i < n; ++i) {
+            const bool pp = !bwd && pipe[i];  // two record slots, a progress counter per strip
             zs[i] = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
-                                  xb_words_of(p, ey[i]));
+                                  pp ? 2 * sk_gx_words(p.order, (int)es) : xb_words_of(p, ey[i]), pp);
+        }
         int64_t pos = 0;
         for (int64_t g0 = 0; g0 < n;) {
             int64_t g1 = g0 + 1;
-            while (g1 < n && (!cfg.buckets || cls[seq[g1]] == cls[seq[g0]])) ++g1;
+            // a group: one LDS class (any class without buckets); strip-pipeline
+            // pairs always form their own group
+            auto same = [&](int64_t u, int64_t v) {
+                return (cls[u] == 6) == (cls[v] == 6) && (!cfg.buckets || cls[u] == cls[v]);
+            };
+            while (g1 < n && same(seq[g1], seq[g0])) ++g1;
             // bins of this group
             struct Bin { SkPairSizes tot; int64_t count, work; std::vector<int64_t> pairs; };
             std::vector<Bin> bins;
-            SkPairSizes all = {0, 0, 0, 0, 0, 0, 0, 0};
+            SkPairSizes all = SkPairSizes{};
             for (int64_t k = g0; k < g1; ++k) all = add(all, zs[seq[k]]);
             const int64_t total = layout_for(all, g1 - g0, es, bwd, false, p.order).total;
             const int64_t nb = std::max<int64_t>(1, (int64_t)((double)total / (double)cap * 1.05) + 1);
             bins.resize(total <= (int64_t)cap ? 1 : nb);
-            for (Bin& bn : bins) { bn.tot = {0, 0, 0, 0, 0, 0, 0, 0}; bn.count = 0; bn.work = 0; }
+            for (Bin& bn : bins) { bn.tot = SkPairSizes{}; bn.count = 0; bn.work = 0; }
             for (int64_t k = g0; k < g1; ++k) {
                 const int64_t i = seq[k];
                 if ((size_t)layout_for(zs[i], 1, es, bwd, false, p.order).total > cap)
@@ -829,7 +891,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
                 if (best < 0) {
                     bins.push_back(Bin());
                     best = (int64_t)bins.size() - 1;
-                    bins[best].tot = {0, 0, 0, 0, 0, 0, 0, 0};
+                    bins[best].tot = SkPairSizes{};
                     bins[best].count = 0;
                     bins[best].work = 0;
                 }
@@ -841,8 +903,10 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
             }
             for (const Bin& bn : bins) {
                 if (bn.count == 0) continue;
-                PlanChunk cur = {pos, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0, 0, 0, 0, 0, 0, 0};
-                SkPairSizes run = {0, 0, 0, 0, 0, 0, 0, 0};
+                PlanChunk cur;
+                cur.first = pos;
+                cur.pipe = cls[bn.pairs[0]] == 6;
+                SkPairSizes run = SkPairSizes{};
                 for (const int64_t i : bn.pairs) {  // already longest first
                     const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
                     SkPairDesc& q = desc[pos++];
@@ -855,6 +919,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
                     q.g_idx = i;
                     q.c_off = run.c; q.ck_off = run.ck; q.ce_off = run.ce; q.qb_off = run.qb;
                     q.qe_off = run.qe; q.dx_off = run.dx; q.dy_off = run.dy; q.xb_off = run.xb;
+                    q.pg_off = run.pg;
                     run = add(run, zs[i]);
                     cur.count += 1;
                     cur.tot = add(cur.tot, zs[i]);
@@ -867,6 +932,15 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
                     cur.max_pts = std::max<int64_t>(cur.max_pts, std::max(ex[i], ey[i]) + 1);
                 }
                 *scratch = std::max(*scratch, layout_for(cur.tot, cur.count, es, bwd, false, p.order).total);
+                if (cur.pipe) {
+                    // jobs strip by strip across the chunk's pairs: every pair's
+                    // strips in increasing order, all pairs' first strips first
+                    cur.jobs_first = (int64_t)P.jobs.size();
+                    for (int st = 0; st < cur.max_strips; ++st)
+                        for (int64_t li = 0; li < cur.count; ++li)
+                            if (nstr[bn.pairs[li]] > st) P.jobs.push_back(make_int2((int)li, st));
+                    cur.njobs = (int64_t)P.jobs.size() - cur.jobs_first;
+                }
                 chunks.push_back(cur);
             }
             g0 = g1;
@@ -972,6 +1046,10 @@ int plan_upload(PlanImpl& P, void* ws, size_t wsb, hipStream_t st) {
                                       P.bdesc.size() * sizeof(SkPairDesc), hipMemcpyHostToDevice,
                                       st),
                        "descriptor upload");
+        if (!P.jobs.empty())
+            SK_TRY_HIP(hipMemcpyAsync((char*)ws + P.jobs_off, P.jobs.data(),
+                                      P.jobs.size() * sizeof(int2), hipMemcpyHostToDevice, st),
+                       "job list upload");
         SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
     }
     P.uploaded = ws;
@@ -995,8 +1073,12 @@ int plan_forward(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kex
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
         src.desc = reinterpret_cast<const SkPairDesc*>(base + P.fdesc_off) + c.first;
-        int rc = run_chunk_forward<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                      c.max_ly, c.ring_fwd, base + P.scratch_off, L, K, Kexp, st);
+        int rc = c.pipe ? run_chunk_forward_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad,
+                                                    c.max_lx, c.max_ly,
+                                                    reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first,
+                                                    c.njobs, base + P.scratch_off, L, K, Kexp, st)
+                        : run_chunk_forward<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                               c.max_ly, c.ring_fwd, base + P.scratch_off, L, K, Kexp, st);
         if (rc) return rc;
     }
     return SK_OK;
@@ -1046,8 +1128,9 @@ int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipSt
     int rc = SK_OK;
     for (int o = 0; o < 2 && !rc; ++o)
         for (int w = 0; w < 2 && !rc; ++w)
-            for (int b = 0; b < 2 && !rc; ++b) {
-                const PlanCfg cfg = {o, w, b};
+            for (int b = 0; b < 2 && !rc; ++b)
+            for (int pp = 0; pp < 2 && !rc; ++pp) {
+                const PlanCfg cfg = {o, w, b, pp};
                 rc = plan_build(P, cfg, wsb);
                 if (rc == SK_EWORKSPACE) {  // this configuration does not fit: skip it
                     rc = SK_OK;
@@ -1117,9 +1200,6 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
 // strip pipeline (SK_ALGO_PIPELINE): one pair at a time, its strips on
 // co-resident workgroups
 // ---------------------------------------------------------------------------
-// polls of a pipeline wait before it gives up (about ten seconds)
-constexpr int kPipeSpinLimit = 1 << 24;
-
 struct PipeLayout {
     int64_t c, xb, prog, abort, total;
 };
@@ -1199,7 +1279,7 @@ int pairs_pipe(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, i
 int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
                  const sk_params& p, bool backward, size_t wsb) {
     plan_init(P, xo, yo, npairs, d, p, backward);
-    PlanCfg cfg = {1, 1, 1};
+    PlanCfg cfg = {1, 1, 1, 1};
     tuned_cfg(P, &cfg);
     return plan_build(P, cfg, wsb);
 }
@@ -1441,7 +1521,7 @@ int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t np
     try {
         sk_plan* P = new sk_plan();
         plan_init(P->impl, x_off, y_off, npairs, d, *p, backward != 0);
-        PlanCfg cfg = {1, 1, 1};
+        PlanCfg cfg = {1, 1, 1, 1};
         tuned_cfg(P->impl, &cfg);
         rc = plan_build(P->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
         if (rc) {
@@ -1535,23 +1615,24 @@ int sigkernel_plan_tune(sk_plan* plan, const void* Xcat, const void* Ycat, void*
 }
 
 int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, int32_t* buckets,
-                          int64_t* launches) {
+                          int32_t* pipeline, int64_t* launches) {
     g_last_error.clear();
     if (!plan) return fail(SK_EINVAL, "plan is NULL");
     if (order) *order = plan->impl.cfg.order;
     if (swap) *swap = plan->impl.cfg.swap;
     if (buckets) *buckets = plan->impl.cfg.buckets;
+    if (pipeline) *pipeline = plan->impl.cfg.pipe;
     if (launches) *launches = (int64_t)plan->impl.fchunks.size();
     return SK_OK;
 }
 
 int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,
-                             size_t ws_bytes) {
+                             int32_t pipeline, size_t ws_bytes) {
     g_last_error.clear();
     if (!plan) return fail(SK_EINVAL, "plan is NULL");
-    if ((order | swap | buckets) & ~1) return fail(SK_EINVAL, "configuration flags are 0 or 1");
+    if ((order | swap | buckets | pipeline) & ~1) return fail(SK_EINVAL, "configuration flags are 0 or 1");
     try {
-        const PlanCfg cfg = {order, swap, buckets};
+        const PlanCfg cfg = {order, swap, buckets, pipeline};
         return plan_build(plan->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");

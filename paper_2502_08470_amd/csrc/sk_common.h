@@ -97,22 +97,27 @@ struct SkPairDesc {
     int64_t dx_off;   // per-pair dL/d(dx) partials
     int64_t dy_off;   // per-pair, per-strip dL/d(dy) partials
     int64_t xb_off;   // global strip-boundary exchange records (32-bit words)
+    int64_t pg_off;   // strip-pipeline progress counters (int32 elements)
 };
 
 // Per-pair workspace strides, all derived from the pair's geometry.
 struct SkPairSizes {
-    int64_t c, ck, ce, qb, qe, dx, dy, xb;
+    int64_t c, ck, ce, qb, qe, dx, dy, xb, pg;
 };
 
 // xb_words: 32-bit words per column of the pair's global exchange records
-// (0 when it needs none)
+// (0 when it needs none; twice the record for a strip-pipeline pair, whose
+// records alternate between two slots)
+// pipe: the pair runs on the strip pipeline (one progress counter per strip)
 __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int32_t lam,
                                                      int32_t N, int32_t S, int64_t d,
-                                                     bool backward, int xb_words) {
-    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0};
+                                                     bool backward, int xb_words,
+                                                     bool pipe = false) {
+    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     SkGeom g = sk_make_geom(lx << lam, ly << lam);
     z.c = (int64_t)g.nsteps_pad * SK_LANES;
     if (g.nsteps > 0) z.xb = (int64_t)g.ly * xb_words;
+    if (pipe && g.nsteps > 0) z.pg = g.nstrips;
     if (backward && g.nsteps > 0) {
         int64_t nck = (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;
@@ -155,5 +160,6 @@ __host__ __device__ inline SkPairDesc sk_pair(const SkPairSrc& s, int64_t local)
     d.dx_off = local * s.stride.dx;
     d.dy_off = local * s.stride.dy;
     d.xb_off = local * s.stride.xb;
+    d.pg_off = local * s.stride.pg;
     return d;
 }

@@ -413,7 +413,9 @@ struct SweepArgs {
 // A record is stored at least Tp - 63 - 15 steps before the block start
 // that loads it, so Tp > 78 (exchange pairs have more than SK_GX_MIN_COLS
 // columns) puts a fence between every store and its load.
-template <int W, typename F>
+// COHERENT: the records come from other workgroups (strip pipeline) and are
+// read with device-coherent loads.
+template <int W, bool COHERENT = false, typename F>
 __device__ __forceinline__ void sk_gx_stage(unsigned (&xr)[(8 * W + 63) / 64], unsigned* stage,
                                             const unsigned* xg, int t_next, int r, F want) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -428,7 +430,10 @@ __device__ __forceinline__ void sk_gx_stage(unsigned (&xr)[(8 * W + 63) / 64], u
         if (w < 8 * W) {
             const int m = w / W, q = w - m * W;
             const int col = want(t_next + m);
-            if (col >= 0) xr[h] = xg[(int64_t)col * W + q];
+            if (col >= 0)
+                xr[h] = COHERENT ? __hip_atomic_load(xg + (int64_t)col * W + q, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : xg[(int64_t)col * W + q];
         }
     }
 }
@@ -684,24 +689,51 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 // bounded: a wave that waits too long raises the abort flag, and every
 // waiting wave leaves on it, writing NaN for the pair.
 // ---------------------------------------------------------------------------
+// Jobs are strips.  One pair (desc == nullptr): the fields below describe
+// it and job q is its strip q.  A job list (desc != nullptr): job q is strip
+// jobs[q].y of the pair desc[jobs[q].x], whose arrays sit at the descriptor's
+// offsets from the base pointers; every pair's strips appear in increasing
+// order in the list (a wave only waits for jobs listed before its own).
 template <typename R>
 struct PipeArgs {
-    const R* cskew;        // the pair's skewed cell constants (rows s Tp + t)
+    const R* cskew;        // skewed cell constants (rows s Tp + t of a pair)
     SkTab<R> tab;
-    int32_t lx, ly;        // grid segments (refined)
+    int32_t lx, ly;        // one pair: grid segments (refined)
     R* K;
     int32_t* Kexp;         // nullable
-    int64_t k_idx;
-    unsigned* xb;          // records [2][ly][sk_gx_words]
-    int* progress;         // [nstrips], zero at launch: columns handed over
+    int64_t k_idx;         // one pair: output index
+    unsigned* xb;          // records [2][ly][sk_gx_words] per pair
+    int* progress;         // [nstrips] per pair, zero at launch: columns handed over
     int* abort;            // zero at launch
     int32_t spin_limit;    // polls before a wait gives up
+    const SkPairDesc* desc;  // job list mode: pair descriptors
+    const int2* jobs;        // job list mode: (pair, strip)
+    int64_t njobs;
+    int32_t lam;             // job list mode: dyadic refinement of the pairs' grids
 };
+
+// Hand-over without cache-wide fences: the producer stores its records and
+// counts with device-coherent stores and waits for its stores to complete
+// before it raises a count; the consumer polls the count with
+// device-coherent loads and only then issues its device-coherent record
+// loads.  (An agent-scope release/acquire would write back or invalidate a
+// whole L2 per block, which thousands of concurrent strips cannot afford.)
+__device__ __forceinline__ void sk_store_coherent(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void sk_stores_complete() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // every counter of this wave at zero
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // Wave-uniform bounded wait until *prog >= need.  Returns false on abort.
 __device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* abort, int limit) {
     for (int it = 0;; ++it) {
-        if (__hip_atomic_load(prog, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+        if (__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // record loads stay after the poll
+            return true;
+        }
         if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         if (it >= limit) {
             __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -714,26 +746,53 @@ __device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* ab
 template <typename R, int N, int TMAX>
 __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
     const int r = threadIdx.x;
-    const SkGeom g = sk_make_geom(a.lx, a.ly);
-    if (g.nsteps == 0) {
-        if (blockIdx.x == 0 && r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (R)1, 0);
-        return;
+    if (!a.desc) {
+        const SkGeom g1 = sk_make_geom(a.lx, a.ly);
+        if (g1.nsteps == 0) {
+            if (blockIdx.x == 0 && r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (R)1, 0);
+            return;
+        }
     }
     constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
     constexpr int XR = (8 * GXW + 63) / 64;
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
-    const int ly = g.ly;
-    const int nloc = (ly + 63 + 7) & ~7;  // local steps of one strip
-    // lane 0 reads column t at local step t
-    auto col0 = [&](int t) -> int { return t < ly ? t : -1; };
-    for (int s = blockIdx.x; s < g.nstrips; s += gridDim.x) {
+    const int64_t njobs = a.desc ? a.njobs : sk_make_geom(a.lx, a.ly).nstrips;
+    for (int64_t q = blockIdx.x; q < njobs; q += gridDim.x) {
+        // the job: strip s of a pair with geometry g and arrays at these bases
+        int s;
+        SkGeom g;
+        const R* cbase;
+        unsigned* xbase;
+        int* prog;
+        int64_t k_idx;
+        if (a.desc) {
+            const int2 jb = a.jobs[q];
+            const SkPairDesc pd = a.desc[jb.x];
+            s = jb.y;
+            g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+            cbase = a.cskew + pd.c_off;
+            xbase = a.xb + pd.xb_off;
+            prog = a.progress + pd.pg_off;
+            k_idx = pd.k_idx;
+        } else {
+            s = (int)q;
+            g = sk_make_geom(a.lx, a.ly);
+            cbase = a.cskew;
+            xbase = a.xb;
+            prog = a.progress;
+            k_idx = a.k_idx;
+        }
+        const int ly = g.ly;
+        const int nloc = (ly + 63 + 7) & ~7;  // local steps of one strip
+        // lane 0 reads column t at local step t
+        auto col0 = [&](int t) -> int { return t < ly ? t : -1; };
         const int i = s * 64 + r;
         const bool rowok = i < g.lx;
         const bool has_next = s + 1 < g.nstrips;
-        const unsigned* rin = a.xb + (size_t)((s + 1) & 1) * ly * GXW;  // strip s-1's slot
-        unsigned* rout = a.xb + (size_t)(s & 1) * ly * GXW;
-        const R* cs = a.cskew + (int64_t)s * g.Tp * 64;
+        const unsigned* rin = xbase + (size_t)((s + 1) & 1) * ly * GXW;  // strip s-1's slot
+        unsigned* rout = xbase + (size_t)(s & 1) * ly * GXW;
+        const R* cs = cbase + (int64_t)s * g.Tp * 64;
         const int64_t rows_left = (int64_t)g.nsteps_pad - (int64_t)s * g.Tp;
         R P[N + 1], Qs[N + 1];
         double P0 = 0.0, P1 = 0.0, Qs0 = 0.0, Qs1 = 0.0;
@@ -748,15 +807,17 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
         for (int h = 0; h < XR; ++h) xr[h] = 0u;
         bool ok = true;
         if (s > 0) {  // records of columns 0..7
-            ok = sk_wait_count(a.progress + s - 1, ly < 8 ? ly : 8, a.abort, a.spin_limit);
+            ok = sk_wait_count(prog + s - 1, ly < 8 ? ly : 8, a.abort, a.spin_limit);
             if (ok) {
 #pragma unroll
                 for (int h = 0; h < XR; ++h) {
                     const int w = r + 64 * h;
                     if (w < 8 * GXW) {
-                        const int m = w / GXW, q = w - m * GXW;
+                        const int m = w / GXW, qw = w - m * GXW;
                         const int col = col0(m);
-                        if (col >= 0) xr[h] = rin[(int64_t)col * GXW + q];
+                        if (col >= 0)
+                            xr[h] = __hip_atomic_load(rin + (int64_t)col * GXW + qw, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
@@ -765,9 +826,9 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
         for (int t0 = 0; ok && t0 < nloc; t0 += 8) {
             if (s > 0) {
                 const int need = t0 + 16 < ly ? t0 + 16 : ly;
-                ok = sk_wait_count(a.progress + s - 1, need, a.abort, a.spin_limit);
+                ok = sk_wait_count(prog + s - 1, need, a.abort, a.spin_limit);
                 if (!ok) break;
-                sk_gx_stage<GXW>(xr, stage, rin, t0 + 8, r, col0);
+                sk_gx_stage<GXW, true>(xr, stage, rin, t0 + 8, r, col0);
             }
             R cb[8];
 #pragma unroll
@@ -843,29 +904,32 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                 if (live) {
                     if (r == 63 && has_next) {
                         unsigned* rec = rout + (int64_t)j * GXW;
-                        *reinterpret_cast<double*>(rec) = Qo0;
-                        *reinterpret_cast<double*>(rec + 2) = Qo1;
+                        unsigned wd[4 + (N - 1) * (ES / 4) + 1];
+                        *reinterpret_cast<double*>(wd) = Qo0;
+                        *reinterpret_cast<double*>(wd + 2) = Qo1;
 #pragma unroll
                         for (int n = 2; n <= N; ++n)
-                            *reinterpret_cast<R*>(rec + 4 + (n - 2) * (ES / 4)) = Qo[n];
-                        rec[4 + (N - 1) * (ES / 4)] = (unsigned)E;
+                            *reinterpret_cast<R*>(wd + 4 + (n - 2) * (ES / 4)) = Qo[n];
+                        wd[4 + (N - 1) * (ES / 4)] = (unsigned)E;
+#pragma unroll
+                        for (int k = 0; k < 4 + (N - 1) * (ES / 4) + 1; ++k) sk_store_coherent(rec + k, wd[k]);
                     }
                     if (i == g.lx - 1 && j == ly - 1) {
                         R kr = (R)0;
 #pragma unroll
                         for (int n = N; n >= 2; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
                         const double kv = 0.5 * (Po0 + Qo0 + Po1 + Qo1 + (double)kr);
-                        sk_write_k(a.K, a.Kexp, a.k_idx, kv, E);
+                        sk_write_k(a.K, a.Kexp, k_idx, kv, E);
                     }
                 }
             }
             // lane 63 has handed over the columns j <= t0 + 7 - 63: publish
-            // them (its release store orders its record stores before the count)
+            // them once its record stores have completed
             int done = t0 + 8 - 63;
             done = done < 0 ? 0 : (done > ly ? ly : done);
             if (has_next && done > published) {
-                if (r == 63)
-                    __hip_atomic_store(a.progress + s, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                sk_stores_complete();
+                if (r == 63) sk_store_coherent(reinterpret_cast<unsigned*>(prog + s), (unsigned)done);
                 published = done;
             }
             // per-lane rescale of the live state (exact: powers of two)
@@ -894,7 +958,7 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
             }
         }
         if (!ok) {  // a wait gave up: the pair's value is unknown
-            if (r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (double)NAN, 0);
+            if (r == 0) sk_write_k(a.K, a.Kexp, k_idx, (double)NAN, 0);
             return;
         }
     }

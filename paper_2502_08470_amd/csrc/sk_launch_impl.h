@@ -126,8 +126,9 @@ static hipError_t sk_pipe_n(const PipeArgs<R>& a, hipStream_t st) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64, lds);
     if (e != hipSuccess) return e;
-    const SkGeom g = sk_make_geom(a.lx, a.ly);
-    int64_t W = std::min<int64_t>(std::max(1, g.nstrips), (int64_t)per * ncu);
+    // jobs: the strips of the single pair, or the job list
+    const int64_t njobs = a.desc ? a.njobs : (int64_t)sk_make_geom(a.lx, a.ly).nstrips;
+    int64_t W = std::min<int64_t>(std::max<int64_t>(1, njobs), (int64_t)per * ncu);
     if (W < 1) return hipErrorInvalidConfiguration;
     PipeArgs<R> arg = a;
     void* args[] = {&arg};

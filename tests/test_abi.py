@@ -162,18 +162,19 @@ def test_plan_host_side_checks():
     # forward-only plan: no backward
     assert lib.sigkernel_plan_backward(h, vp(1), vp(1), vp(1), None, vp(1), vp(1), vp(1), need,
                                        None) == L.SK_EINVAL
-    o, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    o, w, b, pp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     n = ctypes.c_int64()
     assert lib.sigkernel_plan_config(h, ctypes.byref(o), ctypes.byref(w), ctypes.byref(b),
-                                     ctypes.byref(n)) == L.SK_OK
-    assert (o.value, w.value, b.value) == (1, 1, 1) and n.value >= 1
-    assert lib.sigkernel_plan_configure(h, 0, 0, 0, 0) == L.SK_OK
+                                     ctypes.byref(pp), ctypes.byref(n)) == L.SK_OK
+    assert (o.value, w.value, b.value, pp.value) == (1, 1, 1, 1) and n.value >= 1
+    assert lib.sigkernel_plan_configure(h, 0, 0, 0, 0, 0) == L.SK_OK
     assert lib.sigkernel_plan_config(h, ctypes.byref(o), ctypes.byref(w), ctypes.byref(b),
-                                     ctypes.byref(n)) == L.SK_OK
-    assert (o.value, w.value, b.value, n.value) == (0, 0, 0, 1)
-    assert lib.sigkernel_plan_configure(h, 2, 0, 0, 0) == L.SK_EINVAL
+                                     ctypes.byref(pp), ctypes.byref(n)) == L.SK_OK
+    assert (o.value, w.value, b.value, pp.value, n.value) == (0, 0, 0, 0, 1)
+    assert lib.sigkernel_plan_configure(h, 2, 0, 0, 0, 0) == L.SK_EINVAL
+    assert lib.sigkernel_plan_configure(h, 0, 0, 0, 2, 0) == L.SK_EINVAL
     # a workspace too small for the descriptors and one pair
-    assert lib.sigkernel_plan_configure(h, 1, 1, 1, 64) == L.SK_EWORKSPACE
+    assert lib.sigkernel_plan_configure(h, 1, 1, 1, 1, 64) == L.SK_EWORKSPACE
     lib.sigkernel_plan_destroy(h)
     lib.sigkernel_plan_destroy(None)
 

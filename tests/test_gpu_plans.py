@@ -47,11 +47,12 @@ def test_every_configuration_matches_oracle(sk, scheme, order):
     for o in (0, 1):
         for w in (0, 1):
             for b in (0, 1):
-                plan.configure(o, w, b)
-                k = torch.full((len(xs),), float("nan"), dtype=torch.float64, device="cuda")
-                plan.forward(Xc, Yc, k)
-                err = rel_err(k.cpu().numpy(), ref)
-                assert err.max() < 1e-11, ((o, w, b), err.max(), plan.config())
+                for pp in (0, 1):  # strip pipeline for pairs of several strips
+                    plan.configure(o, w, b, pp)
+                    k = torch.full((len(xs),), float("nan"), dtype=torch.float64, device="cuda")
+                    plan.forward(Xc, Yc, k)
+                    err = rel_err(k.cpu().numpy(), ref)
+                    assert err.max() < 1e-11, ((o, w, b, pp), err.max(), plan.config())
 
 
 def test_graph_capture_replays_match_eager(sk):
@@ -62,6 +63,7 @@ def test_graph_capture_replays_match_eager(sk):
     lens_x = [torch.empty(len(a), 4, device="cuda") for a in xs]
     lens_y = [torch.empty(len(b), 4, device="cuda") for b in ys]
     plan = sk.PairsPlan(lens_x, lens_y, "interp", 6)
+    plan.configure(1, 1, 1, False)
     k_eager = torch.empty(len(xs), device="cuda")
     plan.forward(Xc, Yc, k_eager)
     torch.cuda.synchronize()
@@ -120,3 +122,57 @@ def test_plan_backward_matches_oneshot(sk):
         plan.backward(Xc, Yc, gk, gX, gY)
         torch.testing.assert_close(gX, gX0, rtol=1e-12, atol=1e-12 * float(gX0.abs().max()))
         torch.testing.assert_close(gY, gY0, rtol=1e-12, atol=1e-12 * float(gY0.abs().max()))
+
+
+def test_pipeline_plan_matches_batched_plan(sk):
+    # the forward of pairs with several strips on the strip pipeline against
+    # the batched launch of the same plan: bit-identical for the
+    # approximation scheme (same cell arithmetic, same orientation)
+    log_banner("plan strip pipeline vs batched")
+    rng = np.random.default_rng(55)
+    xs, ys = uneven(rng, 200, 6, 2, 1500)
+    Xc, Yc = cat(xs, torch.float32), cat(ys, torch.float32)
+    xl = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in xs]
+    yl = [torch.tensor(b, dtype=torch.float32, device="cuda") for b in ys]
+    plan = sk.PairsPlan(xl, yl, "approx", 8)
+    plan.configure(1, 1, 0, True)
+    assert plan.config()["pipeline"]
+    kp = torch.full((len(xs),), float("nan"), device="cuda")
+    plan.forward(Xc, Yc, kp)
+    plan.configure(1, 1, 0, False)
+    kb = torch.full((len(xs),), float("nan"), device="cuda")
+    plan.forward(Xc, Yc, kb)
+    assert torch.equal(kp, kb)
+
+
+def test_pipeline_plan_graph_replays_match_eager(sk):
+    # the strip-pipeline forward (a cooperative launch and a counter fill)
+    # captured into a HIP graph: every replay equals the eager result
+    log_banner("plan strip pipeline graph capture")
+    rng = np.random.default_rng(56)
+    xs, ys = uneven(rng, 48, 4, 60, 900)
+    Xc, Yc = cat(xs, torch.float32), cat(ys, torch.float32)
+    plan = sk.PairsPlan([torch.empty(len(a), 4, device="cuda") for a in xs],
+                        [torch.empty(len(b), 4, device="cuda") for b in ys], "approx", 6)
+    plan.configure(1, 1, 0, True)
+    k_eager = torch.empty(len(xs), device="cuda")
+    plan.forward(Xc, Yc, k_eager)
+    torch.cuda.synchronize()
+    k = torch.zeros(len(xs), device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(Xc, Yc, k)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward(Xc, Yc, k)
+    for rep in range(3):
+        k.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(k, k_eager), rep
+        assert torch.isfinite(junk)
