@@ -132,7 +132,7 @@ typedef struct sk_params {
 
 /*
  * Workspace sizes (bytes) for processing all pairs in one chunk (capped at
- * 64 GiB, beyond which work is chunked).  Host-only, no device access.
+ * 160 GiB of the 288 GB of HBM, beyond which work is chunked).  Host-only, no device access.
  * Returns 0 on invalid arguments (see sigkernel_last_error).
  * `backward` != 0 sizes the workspace of sigkernel_backward.
  */
@@ -210,7 +210,7 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
  *   backward != 0: the plan also serves sigkernel_plan_backward.
  *   ws_bytes: size of the workspace the plan will run with (chunks are sized
  *   to it); 0 lets sigkernel_plan_workspace report the size for one chunk
- *   per LDS class (capped at 64 GiB).
+ *   per LDS class (capped at 160 GiB).
  * sigkernel_plan_tune times every configuration of the forward on the given
  * inputs (three runs each, device time), keeps the fastest in the plan,
  * uploads it, and remembers it for plans and one-shot sigkernel_pairs /

@@ -77,7 +77,7 @@ struct ProfScope {
     } while (0)
 
 constexpr int64_t kAlign = 256;
-constexpr size_t kDefaultCap = (size_t)64 << 30;  // bytes of one default chunk (of 288 GB HBM)
+constexpr size_t kDefaultCap = (size_t)160 << 30;  // bytes of one default chunk (of 288 GB HBM)
 // polls of a strip-pipeline wait before it gives up (about ten seconds)
 constexpr int kPipeSpinLimit = 1 << 24;
 
