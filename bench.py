@@ -26,6 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
        python bench.py --accuracy-study   (synthetic re-run of the paper's accuracy tables)
        python bench.py --long-pair 16384  (strip pipeline on one long pair)
+       python bench.py --workloads        (time of every named workload)
 """
 from __future__ import annotations
 
@@ -231,6 +232,107 @@ def long_pair_study(steps: int = 16384) -> int:
     return 0
 
 
+def workload_study(large_rows: int = 256) -> int:
+    """Time of each named workload on one GPU with its cell count (inputs
+    resident on the GPU; best of a few calls after a warm-up):
+    * the 8x8 FP64 Gram with a time channel: approximation N=4 and FD lambda=0,
+      batched and plain (one launch per pair), forward;
+    * 4096 uneven oscillatory pairs, approximation N=8, FP32: forward with the
+      tuned plan, the same replayed from a HIP graph, and forward + backward;
+    * the MMD sets: unbiased MMD^2 (approximation N=8, FP32) forward and
+      backward through autograd (three Grams, XX and YY symmetric);
+    * the first `large_rows` rows of the 1024x1024 d=32 Gram (approximation
+      N=8, FP32 sweep, BF16 3-way split Gram, exponents), forward."""
+    import torch
+    import paper_2502_08470_amd as sk
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def best_ms(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best * 1e3
+
+    def say(msg):
+        print(f"[bench] workloads: {msg}", file=sys.stderr, flush=True)
+
+    X, Y = W.small_fp64_gram(0)
+    Xt, Yt = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+    cells = float(X.shape[0] * Y.shape[0] * (X.shape[1] - 1) * (Y.shape[1] - 1))
+    small = {}
+    for scheme, order in (("approx", 4), ("fd", 0)):
+        for algo in ("batched", "plain"):
+            ms = best_ms(lambda: sk.gram(Xt, Yt, scheme, order, algo=algo), 5)
+            small[f"{scheme}{order}_{algo}"] = {"ms": ms, "cells_per_s": cells / ms * 1e3}
+    out["small_fp64_gram"] = {"cells": cells, "forward": small}
+    say("small FP64 Gram done")
+
+    xs, ys = W.uneven_pairs(0)
+    xl = [torch.tensor(a, device=dev) for a in xs]
+    yl = [torch.tensor(b, device=dev) for b in ys]
+    Xc, Yc = torch.cat(xl), torch.cat(yl)
+    cells = float(sum((len(a) - 1) * (len(b) - 1) for a, b in zip(xs, ys)))
+    plan = sk.PairsPlan(xl, yl, "approx", 8, backward=True)
+    plan.tune(Xc, Yc)
+    k = torch.empty(len(xs), device=dev)
+    fwd = best_ms(lambda: plan.forward(Xc, Yc, k))
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.forward(Xc, Yc, k)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.forward(Xc, Yc, k)
+    graph = best_ms(lambda: g.replay())
+    gk = torch.ones(len(xs), device=dev)
+    gX, gY = torch.empty_like(Xc), torch.empty_like(Yc)
+    fb = best_ms(lambda: (plan.forward(Xc, Yc, k), plan.backward(Xc, Yc, gk, gX, gY)), 2)
+    out["uneven_pairs"] = {"cells": cells, "plan": plan.config(),
+                           "forward_ms": fwd, "forward_graph_ms": graph, "fwd_bwd_ms": fb,
+                           "forward_cells_per_s": cells / fwd * 1e3,
+                           "fwd_bwd_cells_per_s": cells / fb * 1e3}
+    del plan, xl, yl, Xc, Yc, gX, gY, g
+    say("uneven pairs done")
+
+    X, Y = W.mmd_sets(0)
+    Xt = torch.tensor(X, device=dev).requires_grad_(True)
+    Yt = torch.tensor(Y, device=dev).requires_grad_(True)
+
+    def mmd_step():
+        Xt.grad = None
+        Yt.grad = None
+        sk.mmd2(Xt, Yt, "approx", 8).backward()
+
+    ms = best_ms(mmd_step)
+    cells = 3.0 * X.shape[0] * Y.shape[0] * (X.shape[1] - 1) ** 2
+    out["mmd_sets"] = {"cells": cells, "fwd_bwd_ms": ms, "fwd_bwd_cells_per_s": cells / ms * 1e3}
+    del Xt, Yt
+    say("MMD sets done")
+
+    X, Y = W.large_gram(0)
+    Xt = torch.tensor(X[:large_rows], device=dev)
+    Yt = torch.tensor(Y, device=dev)
+    del X, Y
+    cells = float(Xt.shape[0] * Yt.shape[0] * (Xt.shape[1] - 1) * (Yt.shape[1] - 1))
+    ms = best_ms(lambda: sk.gram(Xt, Yt, "approx", 8, return_exp=True, gram_mode="bf16x3"), 1)
+    out["large_gram_block"] = {"rows": large_rows, "cells": cells, "forward_ms": ms,
+                               "forward_cells_per_s": cells / ms * 1e3,
+                               "full_gram_forward_s_at_this_rate": 1024 * 1024 * 1024.0 ** 2 / (cells / ms * 1e3)}
+    say("large Gram block done")
+    print(json.dumps({"study": "named workloads, one MI355X", "workloads": out}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +349,11 @@ def main(argv=None) -> int:
                     help="MAPE of every scheme vs the converged kernel (paper's accuracy tables)")
     ap.add_argument("--long-pair", type=int, default=0, metavar="STEPS",
                     help="strip pipeline vs batched on one pair of STEPS-step paths")
+    ap.add_argument("--workloads", action="store_true",
+                    help="time every named workload (small FP64 Gram, uneven pairs, MMD, large Gram block)")
     args = ap.parse_args(argv)
+    if args.workloads:
+        return workload_study()
     if args.accuracy_study:
         return accuracy_study()
     if args.long_pair:
