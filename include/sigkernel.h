@@ -88,9 +88,14 @@ extern "C" {
                              co-resident workgroups that hand strip-boundary
                              edges on through global memory (Section 3.2's
                              wavefront over strips; for a few very long
-                             pairs).  Polynomial schemes, forward only; a
-                             value that could not be completed (a bounded
-                             wait gave up) is written as NaN               */
+                             pairs).  Polynomial schemes.  Backward: pair
+                             lists only (SK_OP_PAIRS; Gram-mode backward
+                             entry points return SK_EUNSUPPORTED), where
+                             every pair with several strips runs a pipelined
+                             checkpoint sweep and a pipelined adjoint (the
+                             strips in reverse order).  A value that could
+                             not be completed (a bounded wait gave up) is
+                             written as NaN, and so is a gradient           */
 
 /* arithmetic of the increment Gram C_ij = <dx_i, dy_j> */
 #define SK_GRAM_NATIVE 0 /* products in the path dtype: a d-term FMA chain per cell for
@@ -168,10 +173,12 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Reverse-mode derivative of a forward call (polynomial schemes, batched
- * algorithm): the exact gradient of the computed scheme (discrete adjoint of
- * the cell recursion), for the loss L = sum_i gK[i] * K[i] with K[i] the
- * forward outputs.
+ * Reverse-mode derivative of a forward call (polynomial schemes; batched
+ * algorithm, or for SK_OP_PAIRS the strip pipeline): the exact gradient of
+ * the computed scheme (discrete adjoint of the cell recursion), for the loss
+ * L = sum_i gK[i] * K[i] with K[i] the forward outputs.  SK_OP_PAIRS runs a
+ * one-shot plan (tuned configuration of the shape if there is one; with
+ * SK_ALGO_PIPELINE every pair of several strips on the pipeline).
  *   op == SK_OP_GRAM : X, nx, lx_pts, Y, ny, ly_pts as in sigkernel_gram;
  *                      x_off, y_off ignored; gK has nx * ny entries;
  *                      gX (nx, lx_pts, d) and gY (ny, ly_pts, d) are
@@ -197,10 +204,10 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
  * pair is computed transposed (k(x, y) = k(y, x) holds for every scheme, so
  * the shorter path can take the role whose edges are held in LDS), the
  * grouping of pairs into launches by the LDS size their sweep needs, whether
- * the forward of pairs with several 64-row strips runs on the strip pipeline
- * (their strips as jobs on co-resident workgroups, which balances the load
- * strip by strip; see SK_ALGO_PIPELINE), the chunking for a given workspace
- * size and the workspace layout.
+ * pairs with several 64-row strips run on the strip pipeline (their strips
+ * as jobs on co-resident workgroups, which balances the load strip by strip;
+ * see SK_ALGO_PIPELINE; in a backward plan their checkpoint sweep and adjoint
+ * too), the chunking for a given workspace size and the workspace layout.
  * sigkernel_plan_upload copies the per-pair descriptors into the workspace
  * once (it synchronises `stream`); afterwards sigkernel_plan_forward and
  * sigkernel_plan_backward only queue kernels, with no host synchronisation,

@@ -163,14 +163,19 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
 
 
 def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int = 4,
-                   gk_exp: Optional[torch.Tensor] = None):
+                   gk_exp: Optional[torch.Tensor] = None, algo: str = "batched"):
     """Gradients of sum(gk * pairs(xs, ys)) with respect to the concatenated
-    points; returns (gXcat, gYcat, x_offsets, y_offsets)."""
+    points; returns (gXcat, gYcat, x_offsets, y_offsets).  ``algo`` "batched"
+    uses the tuned (or default) plan configuration of this shape; "pipeline"
+    runs every pair with several strips on the pipelined checkpoint sweep and
+    adjoint."""
     Xc, xo = _concat(xs)
     Yc, yo = _concat(ys)
     npairs = len(xo) - 1
     d = Xc.shape[1]
-    p = _params(Xc.dtype, scheme, order, "batched")
+    if algo not in ("batched", "pipeline"):
+        raise ValueError("pairs_backward runs the batched algorithm or the strip pipeline")
+    p = _params(Xc.dtype, scheme, order, algo)
     lib = L.lib()
     gk = _dev(gk.to(Xc.dtype))
     gX = torch.empty_like(Xc)
@@ -309,7 +314,8 @@ class PairsPlan:
                   pipeline: bool = False):
         """Set the configuration by hand (rebuilds the plan, grows the
         workspace if this configuration needs more, and uploads).  ``pipeline``
-        runs the forward of pairs with several strips on the strip pipeline."""
+        runs pairs with several strips on the strip pipeline: their forward,
+        and for a backward plan their checkpoint sweep and adjoint."""
         L.check(self._lib.sigkernel_plan_configure(self._h, int(longest_first), int(transpose),
                                                    int(lds_classes), int(pipeline), 0))
         nb = self._lib.sigkernel_plan_workspace(self._h)

@@ -173,6 +173,14 @@ SkTab<R> table_for(const sk_params& p) {
 // ---------------------------------------------------------------------------
 bool is_fd(const sk_params& p) { return p.scheme == SK_FD || p.scheme == SK_FD2; }
 
+// The strip pipeline's backward runs on pair lists (plans); Gram-mode
+// backward entry points reject it.
+int check_gram_backward_algo(const sk_params* p) {
+    if (p->algo == SK_ALGO_PIPELINE)
+        return fail(SK_EUNSUPPORTED, "the strip pipeline's backward takes pair lists (SK_OP_PAIRS)");
+    return SK_OK;
+}
+
 int check_params(const sk_params* p, bool backward) {
     if (!p) return fail(SK_EINVAL, "params is NULL");
     if (p->dtype != SK_F32 && p->dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", p->dtype);
@@ -202,10 +210,8 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dtype != SK_F64) return fail(SK_EUNSUPPORTED, "the plain algorithm is FP64 only");
         if (backward) return fail(SK_EUNSUPPORTED, "the plain algorithm is forward only");
     }
-    if (p->algo == SK_ALGO_PIPELINE) {
-        if (is_fd(*p)) return fail(SK_EUNSUPPORTED, "the strip pipeline runs the polynomial schemes");
-        if (backward) return fail(SK_EUNSUPPORTED, "the strip pipeline is forward only");
-    }
+    if (p->algo == SK_ALGO_PIPELINE && is_fd(*p))
+        return fail(SK_EUNSUPPORTED, "the strip pipeline runs the polynomial schemes");
     if (p->gram != SK_GRAM_NATIVE && p->gram != SK_GRAM_BF16X3 && p->gram != SK_GRAM_MFMA)
         return fail(SK_EINVAL, "gram mode %d", p->gram);
     if (p->gram == SK_GRAM_BF16X3 && p->dtype != SK_F32)
@@ -442,9 +448,60 @@ int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
     pa.spin_limit = kPipeSpinLimit;
     pa.desc = src.desc; pa.jobs = jobs; pa.njobs = njobs; pa.lam = lam_of(p);
-    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, false, st),
               "pipelined strip sweep");
     return SK_OK;
+}
+
+template <typename R>
+int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P, int max_ly,
+                 int max_strips, char* ws, const Layout& L, hipStream_t st);
+
+// Backward of a chunk of strip-pipeline pairs: increment Gram, the pipelined
+// checkpoint sweep over the forward job list (kernel values to K), the
+// pipelined adjoint over the reversed job list, and the contraction.
+template <typename R>
+int run_chunk_backward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
+                            const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
+                            int max_ly, int max_strips, const int2* jobs_fwd,
+                            const int2* jobs_adj, int64_t njobs, char* ws, const Layout& L, R* K,
+                            int32_t* Kexp, const R* gK, const int32_t* gKexp, hipStream_t st) {
+    const bool interp = p.scheme == SK_POLY_INTERP;
+    R* cskew = reinterpret_cast<R*>(ws + L.cskew);
+    GramArgs<R> ga;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = 0;
+    ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
+    SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st),
+              "increment Gram");
+    const int64_t npg = (L.total - L.pg) / 4;  // progress counters, then the abort flag
+    int* prog = reinterpret_cast<int*>(ws + L.pg);
+    int* abrt = reinterpret_cast<int*>(ws + L.total) - 1;
+    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), npg, st), "fill");
+    PipeArgs<R> pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.cskew = cskew; pa.tab = table_for<R>(p);
+    pa.K = K; pa.Kexp = Kexp;
+    pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+    pa.progress = prog; pa.abort = abrt; pa.spin_limit = kPipeSpinLimit;
+    pa.desc = src.desc; pa.jobs = jobs_fwd; pa.njobs = njobs; pa.lam = 0;
+    pa.ck = reinterpret_cast<R*>(ws + L.ck);
+    pa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
+    pa.qb = reinterpret_cast<R*>(ws + L.qb);
+    pa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
+    SK_LAUNCH("sweep_ckpt_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, interp, true, st),
+              "pipelined checkpoint sweep");
+    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), npg, st), "fill");
+    AdjPipeArgs<R> aa;
+    std::memset(&aa, 0, sizeof(aa));
+    aa.cskew = cskew; aa.tab = table_for<R>(p);
+    aa.gK = gK; aa.gKexp = gKexp;
+    aa.ck = pa.ck; aa.ce = pa.ce; aa.qb = pa.qb; aa.qe = pa.qe;
+    aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
+    aa.xb = pa.xb; aa.progress = prog; aa.abort = abrt; aa.spin_limit = kPipeSpinLimit;
+    aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs;
+    SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
+              "pipelined adjoint sweep");
+    return run_contract<R>(X, Y, d, src, P, max_ly, max_strips, ws, L, st);
 }
 
 template <typename R>
@@ -561,6 +618,20 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     return SK_OK;
 }
 
+// dL/dc (skewed) -> per-pair partials dL/d(dx), dL/d(dy).
+template <typename R>
+int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P, int max_ly,
+                 int max_strips, char* ws, const Layout& L, hipStream_t st) {
+    ContractArgs<R> ca;
+    ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = reinterpret_cast<const R*>(ws + L.gskew);
+    ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
+    ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
+    const int64_t dmax = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64;
+    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (dmax * (int64_t)sizeof(R))));
+    SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
+    return SK_OK;
+}
+
 // Backward, second half: adjoint sweep and gradient contraction from the
 // state left by run_chunk_prepare.
 template <typename R>
@@ -581,14 +652,7 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.gx_cols = gx_cols_adj(p);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, ring,
                                                   max_ly > aa.gx_cols, st), "adjoint sweep");
-    ContractArgs<R> ca;
-    ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = aa.gskew;
-    ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
-    ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
-    const int64_t dmax = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64;
-    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (dmax * (int64_t)sizeof(R))));
-    SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
-    return SK_OK;
+    return run_contract<R>(X, Y, d, src, P, max_ly, max_strips, ws, L, st);
 }
 
 template <typename R>
@@ -730,8 +794,8 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
 struct PlanCfg {
     int32_t order;    // 1: longest pairs first (by wavefront steps); 0: given order
     int32_t swap;     // 1: transpose pairs whose second path is longer
-    int32_t buckets;  // 1: separate launches per LDS class of the sweep
-    int32_t pipe;     // 1: forward of pairs with several strips on the strip pipeline
+    int32_t buckets;  // 1: separate launches per LDS class of the forward sweep
+    int32_t pipe;     // 1: pairs with several strips on the strip pipeline (forward and backward)
 };
 
 struct PlanChunk {
@@ -740,8 +804,9 @@ struct PlanChunk {
     int max_nsteps_pad = 0, max_lx = 0, max_ly = 0, max_strips = 0;
     int ring_fwd = 0, ring_adj = 0;  // LDS ring columns (largest among pairs not using the global exchange)
     int64_t max_pts = 0;
-    bool pipe = false;               // forward on the strip pipeline: jobs of the plan's job list
-    int64_t jobs_first = 0, njobs = 0;
+    bool pipe = false;               // strip pipeline: jobs of the plan's job list
+    int64_t jobs_first = 0, njobs = 0;  // the sweep's jobs; a backward chunk's adjoint
+                                        // jobs follow them (njobs more)
 };
 
 struct PlanImpl {
@@ -754,7 +819,7 @@ struct PlanImpl {
     // so its chunks are smaller); descriptors hold chunk-relative offsets
     std::vector<SkPairDesc> fdesc, bdesc;
     std::vector<PlanChunk> fchunks, bchunks;
-    // strip-pipeline jobs (chunk-local pair, strip) of the forward's pipeline chunks
+    // strip-pipeline jobs (chunk-local pair, strip) of the pipeline chunks
     std::vector<int2> jobs;
     int max_ly = 0;  // longest column count of any pair (LDS check)
     // workspace regions (bytes): descriptors, kernel-value scratch, jobs, chunk scratch
@@ -809,17 +874,18 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         const SkGeom g = sk_make_geom(ex[i] << lam, ey[i] << lam);
         cost[i] = g.nsteps;
         nstr[i] = g.nstrips;
-        // the backward runs every pair in one launch per chunk: a launch per
-        // LDS class pays the longest pairs' sequential tail once per class,
-        // more than lower occupancy costs (one class measured 1.45x faster
-        // on 4096 uneven pairs); the classes shape the forward only
-        clsb[i] = 0;
         const int32_t cls_fwd = cfg.buckets ? lds_class(p, ey[i]) : 0;
-        // forward: pairs of several strips go to the strip pipeline (class 6),
-        // which balances the load strip by strip instead of pair by pair
+        // pairs of several strips go to the strip pipeline (class 6), which
+        // balances the load strip by strip instead of pair by pair
         pipe[i] = (cfg.pipe && !is_fd(p) && g.nstrips >= 2) ? 1 : 0;
         clsf[i] = pipe[i] ? 6 : cls_fwd;
-        if (pipe[i]) njobs_all += g.nstrips;
+        // the backward runs its other pairs in one launch per chunk: a launch
+        // per LDS class pays the longest pairs' sequential tail once per
+        // class, more than lower occupancy costs (one class measured 1.45x
+        // faster on 4096 uneven pairs); the classes shape the forward only
+        clsb[i] = pipe[i] ? 6 : 0;
+        // forward jobs; a backward adds the checkpoint sweep's and the adjoint's
+        if (pipe[i]) njobs_all += (int64_t)g.nstrips * (P.backward ? 3 : 1);
         seqb[i] = seqf[i] = i;
     }
     std::stable_sort(seqb.begin(), seqb.end(), [&](int64_t u, int64_t v) {
@@ -860,7 +926,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         *scratch = 0;
         std::vector<SkPairSizes> zs(n);
         for (int64_t i = 0; i < n; ++i) {
-            const bool pp = !bwd && pipe[i];  // two record slots, a progress counter per strip
+            const bool pp = pipe[i] != 0;  // two record slots, a progress counter per strip
             zs[i] = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
                                   pp ? 2 * sk_gx_words(p.order, (int)es) : xb_words_of(p, ey[i]), pp);
         }
@@ -945,6 +1011,13 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
                         for (int64_t li = 0; li < cur.count; ++li)
                             if (nstr[bn.pairs[li]] > st) P.jobs.push_back(make_int2((int)li, st));
                     cur.njobs = (int64_t)P.jobs.size() - cur.jobs_first;
+                    if (bwd)  // the adjoint's: every pair's strips in decreasing
+                              // order, all pairs' last strips first
+                        for (int k = 0; k < cur.max_strips; ++k)
+                            for (int64_t li = 0; li < cur.count; ++li) {
+                                const int ns = nstr[bn.pairs[li]];
+                                if (ns > k) P.jobs.push_back(make_int2((int)li, ns - 1 - k));
+                            }
                 }
                 chunks.push_back(cur);
             }
@@ -1104,11 +1177,19 @@ int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, cons
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
         src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
-        int rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+        int rc;
+        if (c.pipe) {
+            const int2* jobs = reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first;
+            rc = run_chunk_backward_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                            c.max_ly, c.max_strips, jobs, jobs + c.njobs, c.njobs,
+                                            ws_c, L, kbuf, kexp, gK, gKexp, st);
+        } else {
+            rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
                                       c.max_ly, c.ring_fwd, ws_c, L, kbuf, kexp, st);
-        if (rc) return rc;
-        rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj,
-                                  c.max_strips, ws_c, L, gK, gKexp, st);
+            if (!rc)
+                rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj,
+                                          c.max_strips, ws_c, L, gK, gKexp, st);
+        }
         if (rc) return rc;
         ReducePairsArgs<R> ra;
         ra.desc = src.desc; ra.count = c.count; ra.d = P.d; ra.max_pts = c.max_pts;
@@ -1262,7 +1343,7 @@ int pipe_pair(const sk_params& p, const R* x, int64_t lx_pts, const R* y, int64_
     pa.K = K; pa.Kexp = Kexp; pa.k_idx = k_idx;
     pa.xb = reinterpret_cast<unsigned*>(w + L.xb); pa.progress = prog; pa.abort = abrt;
     pa.spin_limit = kPipeSpinLimit;
-    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, st),
+    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, false, st),
               "pipelined strip sweep");
     return SK_OK;
 }
@@ -1280,12 +1361,14 @@ int pairs_pipe(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, i
 }
 
 // One-shot pairs calls: a plan with the tuned configuration of this shape if
-// there is one, else longest-first, transposed and bucketed.
+// there is one, else longest-first, transposed, bucketed and pipelined
+// (SK_ALGO_PIPELINE: the backward of pairs calls, pipelined in any case).
 int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
                  const sk_params& p, bool backward, size_t wsb) {
     plan_init(P, xo, yo, npairs, d, p, backward);
     PlanCfg cfg = {1, 1, 1, 1};
     tuned_cfg(P, &cfg);
+    if (p.algo == SK_ALGO_PIPELINE) cfg.pipe = 1;  // the pipeline wherever a pair has several strips
     return plan_build(P, cfg, wsb);
 }
 
@@ -1349,7 +1432,8 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
                                 const sk_params* p, int32_t backward) {
     g_last_error.clear();
     if (check_params(p, backward != 0) || check_dims(d, backward != 0) ||
-        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y"))
+        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y") ||
+        (backward && check_gram_backward_algo(p)))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     const int lam = lam_of(*p);
@@ -1377,7 +1461,7 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     if (check_offsets(x_off, npairs, lam_of(*p), "x") || check_offsets(y_off, npairs, lam_of(*p), "y"))
         return 0;
     const int lam = lam_of(*p);
-    if (p->algo == SK_ALGO_PIPELINE) {
+    if (p->algo == SK_ALGO_PIPELINE && !backward) {
         int64_t need = 256;
         for (int64_t i = 0; i < npairs; ++i)
             need = std::max(need, pipe_layout(x_off[i + 1] - x_off[i] - 1, y_off[i + 1] - y_off[i] - 1, *p).total);
@@ -1476,6 +1560,7 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     if (rc) return rc;
     if (is_fd(*p)) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
     if (op != SK_OP_GRAM && op != SK_OP_PAIRS) return fail(SK_EINVAL, "op %d", op);
+    if (op == SK_OP_GRAM && (rc = check_gram_backward_algo(p))) return rc;
     if (nx < 0 || (op == SK_OP_GRAM && ny < 0)) return fail(SK_EINVAL, "negative batch");
     if (op == SK_OP_GRAM) {
         if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
@@ -1677,7 +1762,7 @@ size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t
                                  const sk_params* p) {
     g_last_error.clear();
     if (check_params(p, true) || check_dims(d, true) || check_len(lx_pts, 0, "x") ||
-        check_len(ly_pts, 0, "y"))
+        check_len(ly_pts, 0, "y") || check_gram_backward_algo(p))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     SkPairSizes per;
@@ -1693,6 +1778,7 @@ int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y
     g_last_error.clear();
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
+    if (!rc) rc = check_gram_backward_algo(p);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
     if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
@@ -1716,6 +1802,7 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
     g_last_error.clear();
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
+    if (!rc) rc = check_gram_backward_algo(p);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
     if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;

@@ -75,6 +75,11 @@ __host__ __device__ constexpr int sk_gx_words(int N, int es) {
 }
 __host__ __device__ constexpr int sk_gx_stage_bytes(int N, int es) { return SK_GX_BLOCK * sk_gx_words(N, es) * 4; }
 
+// Local steps of one strip on the strip pipeline: lane r processes column
+// t - r at local step t, so lane 63 finishes the last column at step
+// ly + 62; rounded up to whole 8-step blocks.
+__host__ __device__ inline int32_t sk_pipe_steps(int32_t ly) { return (ly + 63 + 7) & ~7; }
+
 // Per-pair description.  Gram calls derive it from the pair index; list
 // (ragged) calls read it from a device array.
 struct SkPairDesc {
@@ -88,7 +93,8 @@ struct SkPairDesc {
     int64_t g_idx;    // index of the pair's gradient seed dL/dk
     // element offsets of the pair's blocks in the chunk's workspace arrays
     int64_t c_off;    // skewed cell constants / skewed dL/dc
-    int64_t ck_off;   // lane checkpoints (backward only)
+    int64_t ck_off;   // lane checkpoints (backward only; strip-pipeline pairs keep
+                      // them per strip, on the strip's local steps)
     int64_t ce_off;   // per checkpoint: 64 lane exponents, then one word with the
                       // interpolation tail length of each of the segment's steps
                       // (8 bits per step; int32 elements)
@@ -108,7 +114,8 @@ struct SkPairSizes {
 // xb_words: 32-bit words per column of the pair's global exchange records
 // (0 when it needs none; twice the record for a strip-pipeline pair, whose
 // records alternate between two slots)
-// pipe: the pair runs on the strip pipeline (one progress counter per strip)
+// pipe: the pair runs on the strip pipeline (one progress counter per strip;
+// backward: checkpoints per strip, every S of its sk_pipe_steps local steps)
 __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int32_t lam,
                                                      int32_t N, int32_t S, int64_t d,
                                                      bool backward, int xb_words,
@@ -119,7 +126,8 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
     if (g.nsteps > 0) z.xb = (int64_t)g.ly * xb_words;
     if (pipe && g.nsteps > 0) z.pg = g.nstrips;
     if (backward && g.nsteps > 0) {
-        int64_t nck = (g.nsteps + S - 1) / S;
+        const int64_t nck = pipe ? (int64_t)g.nstrips * (sk_pipe_steps(g.ly) / S)
+                                 : (g.nsteps + S - 1) / S;
         z.ck = nck * 2 * (N + 1) * SK_LANES;
         z.ce = nck * (SK_LANES + 1);  // per-lane exponents + the segment's tail lengths
         z.qb = (int64_t)g.nstrips * g.ly * (N + 1);

@@ -694,6 +694,9 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 // jobs[q].y of the pair desc[jobs[q].x], whose arrays sit at the descriptor's
 // offsets from the base pointers; every pair's strips appear in increasing
 // order in the list (a wave only waits for jobs listed before its own).
+// CKPT (job lists only): the sweep also stores what the pipelined adjoint
+// replays: each strip's lane states every S local steps with their exponents
+// and tail lengths, and the strip-boundary edges.
 template <typename R>
 struct PipeArgs {
     const R* cskew;        // skewed cell constants (rows s Tp + t of a pair)
@@ -710,6 +713,10 @@ struct PipeArgs {
     const int2* jobs;        // job list mode: (pair, strip)
     int64_t njobs;
     int32_t lam;             // job list mode: dyadic refinement of the pairs' grids
+    R* ck;                   // CKPT: per strip, [sk_pipe_steps / S][2][N + 1][64]
+    int32_t* ce;             // CKPT: per strip, [sk_pipe_steps / S][64 + 1]
+    R* qb;                   // CKPT: strip-boundary edges [nstrips][ly][N + 1]
+    int32_t* qe;             // CKPT: their exponents [nstrips][ly]
 };
 
 // Hand-over without cache-wide fences: the producer stores its records and
@@ -743,7 +750,7 @@ __device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* ab
     }
 }
 
-template <typename R, int N, int TMAX>
+template <typename R, int N, int TMAX, bool CKPT, int S>
 __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
     const int r = threadIdx.x;
     if (!a.desc) {
@@ -766,9 +773,10 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
         unsigned* xbase;
         int* prog;
         int64_t k_idx;
+        SkPairDesc pd = {};
         if (a.desc) {
             const int2 jb = a.jobs[q];
-            const SkPairDesc pd = a.desc[jb.x];
+            pd = a.desc[jb.x];
             s = jb.y;
             g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
             cbase = a.cskew + pd.c_off;
@@ -784,7 +792,7 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
             k_idx = a.k_idx;
         }
         const int ly = g.ly;
-        const int nloc = (ly + 63 + 7) & ~7;  // local steps of one strip
+        const int nloc = sk_pipe_steps(ly);
         // lane 0 reads column t at local step t
         auto col0 = [&](int t) -> int { return t < ly ? t : -1; };
         const int i = s * 64 + r;
@@ -794,6 +802,14 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
         unsigned* rout = xbase + (size_t)(s & 1) * ly * GXW;
         const R* cs = cbase + (int64_t)s * g.Tp * 64;
         const int64_t rows_left = (int64_t)g.nsteps_pad - (int64_t)s * g.Tp;
+        R* ckb = nullptr;
+        int32_t* ceb = nullptr;
+        if (CKPT) {
+            const int64_t nckl = nloc / S;
+            ckb = a.ck + pd.ck_off + (int64_t)s * nckl * 2 * (N + 1) * 64;
+            ceb = a.ce + pd.ce_off + (int64_t)s * nckl * (SK_LANES + 1);
+        }
+        unsigned tword = 0u;  // tail lengths of the current checkpoint segment
         R P[N + 1], Qs[N + 1];
         double P0 = 0.0, P1 = 0.0, Qs0 = 0.0, Qs1 = 0.0;
 #pragma unroll
@@ -887,10 +903,29 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                 P[1] = (R)P1;
                 Qin[0] = (R)Qin0;
                 Qin[1] = (R)Qin1;
+                if (CKPT && (t % S) == 0) {
+                    R* ck = ckb + (int64_t)(t / S) * 2 * (N + 1) * 64;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        ck[n * 64 + r] = P[n];
+                        ck[(N + 1 + n) * 64 + r] = Qin[n];
+                    }
+                    ceb[(int64_t)(t / S) * (SK_LANES + 1) + r] = E;
+                }
                 R Po[N + 1], Qo[N + 1];
                 double Po0, Po1, Qo0, Qo1;
+                int Tc = 0;
                 sk_cell_fwd<R, N, TMAX>(P, Qin, P0, P1, Qin0, Qin1, cb[u], live, a.tab, Po, Qo, Po0,
-                                        Po1, Qo0, Qo1);
+                                        Po1, Qo0, Qo1, nullptr, nullptr,
+                                        (CKPT && TMAX > 0) ? &Tc : nullptr);
+                if (CKPT && TMAX > 0) {
+                    // the adjoint's replay folds the same tail rows
+                    tword |= (unsigned)Tc << (8 * (t % S));
+                    if (t % S == S - 1) {
+                        if (r == 0) ceb[(int64_t)(t / S) * (SK_LANES + 1) + SK_LANES] = (int)tword;
+                        tword = 0u;
+                    }
+                }
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
                     P[n] = Po[n];
@@ -913,6 +948,12 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                         wd[4 + (N - 1) * (ES / 4)] = (unsigned)E;
 #pragma unroll
                         for (int k = 0; k < 4 + (N - 1) * (ES / 4) + 1; ++k) sk_store_coherent(rec + k, wd[k]);
+                        if (CKPT) {
+                            const int64_t o = (int64_t)(s + 1) * ly + j;
+#pragma unroll
+                            for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
+                            a.qe[pd.qe_off + o] = E;
+                        }
                     }
                     if (i == g.lx - 1 && j == ly - 1) {
                         R kr = (R)0;
@@ -957,9 +998,9 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                 }
             }
         }
-        if (!ok) {  // a wait gave up: the pair's value is unknown
+        if (!ok) {  // a wait gave up: the pair's value is unknown (later
+                    // jobs still run: their waits end at once on the flag)
             if (r == 0) sk_write_k(a.K, a.Kexp, k_idx, (double)NAN, 0);
-            return;
         }
     }
 }
@@ -1244,6 +1285,309 @@ void k_adjoint_w2(const AdjArgs<R> a) {
 template <typename R, int N, int TMAX, int S, bool GX>
 __global__ __launch_bounds__(64) void k_adjoint(const AdjArgs<R> a) {
     sk_adjoint_body<R, N, TMAX, S, GX>(a);
+}
+
+// ---------------------------------------------------------------------------
+// (d') strip pipeline of the adjoint: the reversed grid's strips on
+// co-resident workgroups.  The adjoint flows from the last cell back to the
+// first, so strip s needs, at lane 63, the adjoint of the left edge that
+// lane 0 of strip s+1 produces: strip s+1 runs ahead.  Within a strip the
+// local steps run backwards; lane r holds column t - r at local step t, so
+// lane 0 hands over column j at step j and lane 63 consumes it at step
+// j + 63.  The hand-over mirrors the forward pipeline's: records in two slots
+// by strip parity (slot s & 1 written by strip s), device-coherent stores,
+// a count of columns handed over from the top published by lane 0 once the
+// block's stores have completed, bounded waits with the abort flag, and
+// records loaded one 8-step block ahead through the LDS staging slot.  The
+// lane states come from the checkpoints of the pipelined checkpoint sweep
+// (per strip, on the same local steps), replayed S steps at a time as in
+// the batched adjoint.  Only the strip's own cells of dL/dc are written: the
+// skewed rows of neighbouring strips overlap it.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct AdjPipeArgs {
+    const R* cskew;
+    SkTab<R> tab;
+    const R* gK;            // dL/dK per output index
+    const int32_t* gKexp;   // nullable: seed = gK * 2^gKexp
+    const R* ck;            // per strip, [sk_pipe_steps / S][2][N + 1][64]
+    const int32_t* ce;      // per strip, [sk_pipe_steps / S][64 + 1]
+    const R* qb;            // strip-boundary edges [nstrips][ly][N + 1]
+    const int32_t* qe;
+    R* gskew;               // out: skewed dL/dc (the strips' own cells)
+    unsigned* xb;           // records [2][ly][sk_gx_words] per pair
+    int* progress;          // [nstrips] per pair, zero at launch
+    int* abort;             // zero at launch
+    int32_t spin_limit;
+    const SkPairDesc* desc;
+    const int2* jobs;       // (pair, strip), every pair's strips in decreasing order
+    int64_t njobs;
+};
+
+template <typename R, int N, int TMAX, int S>
+__device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
+    const int r = threadIdx.x;
+    constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
+    constexpr int XR = (8 * GXW + 63) / 64, M = N + TMAX, RW = (N + 1) * (ES / 4) + 1;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
+    for (int64_t q = blockIdx.x; q < a.njobs; q += gridDim.x) {
+        const int2 jb = a.jobs[q];
+        const SkPairDesc pd = a.desc[jb.x];
+        const int s = jb.y;
+        const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+        const int ly = g.ly;
+        const int nloc = sk_pipe_steps(ly), nckl = nloc / S;
+        const int i = s * 64 + r;
+        const bool rowok = i < g.lx;
+        const bool has_next = s + 1 < g.nstrips;  // lane 63 receives from strip s+1
+        const unsigned* rin = a.xb + pd.xb_off + (size_t)((s + 1) & 1) * ly * GXW;
+        unsigned* rout = a.xb + pd.xb_off + (size_t)(s & 1) * ly * GXW;
+        int* prog = a.progress + pd.pg_off;
+        const R* cs = a.cskew + pd.c_off + (int64_t)s * g.Tp * 64;
+        R* gs = a.gskew + pd.c_off + (int64_t)s * g.Tp * 64;
+        const int64_t rows_left = (int64_t)g.nsteps_pad - (int64_t)s * g.Tp;
+        const R* ckb = a.ck + pd.ck_off + (int64_t)s * nckl * 2 * (N + 1) * 64;
+        const int32_t* ceb = a.ce + pd.ce_off + (int64_t)s * nckl * (SK_LANES + 1);
+        const R gk = a.gK[pd.g_idx];
+        const int gexp = a.gKexp ? a.gKexp[pd.g_idx] : 0;
+        // column lane 63 reads at local step t, or -1
+        auto col63 = [&](int t) -> int {
+            const int j = t - 63;
+            return (has_next && j >= 0 && j < ly) ? j : -1;
+        };
+        // count of strip s+1 (columns handed over from the top) that covers
+        // the columns of the block of steps b .. b+7
+        auto need_of = [&](int b) -> int {
+            const int lo = b - 63, hi = b + 7 - 63;
+            if (!has_next || hi < 0 || lo >= ly) return 0;
+            return ly - (lo < 0 ? 0 : lo);
+        };
+        R lp[N + 1], lqs[N + 1];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            lp[n] = (R)0;
+            lqs[n] = (R)0;
+        }
+        int El = SK_ZERO_EXP, Els = SK_ZERO_EXP;
+        unsigned xr[XR];
+#pragma unroll
+        for (int h = 0; h < XR; ++h) xr[h] = 0u;
+        bool ok = true;
+        {  // records of the first (topmost) block
+            const int nd = need_of(nloc - 8);
+            if (nd > 0) {
+                ok = sk_wait_count(prog + s + 1, nd, a.abort, a.spin_limit);
+                if (ok) {
+#pragma unroll
+                    for (int h = 0; h < XR; ++h) {
+                        const int w = r + 64 * h;
+                        if (w < 8 * GXW) {
+                            const int m = w / GXW, qw = w - m * GXW;
+                            const int col = col63(nloc - 8 + m);
+                            if (col >= 0)
+                                xr[h] = __hip_atomic_load(rin + (int64_t)col * GXW + qw, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+        }
+        int published = 0;
+        for (int kk = nckl - 1; ok && kk >= 0; --kk) {
+            const int t0 = kk * S;
+            if (has_next && ((t0 + S) & 7) == 0) {  // a block b = t0 + S - 8 starts
+                const int b = t0 + S - 8;
+                const int nd = need_of(b - 8);
+                if (nd > 0) {
+                    ok = sk_wait_count(prog + s + 1, nd, a.abort, a.spin_limit);
+                    if (!ok) break;
+                }
+                sk_gx_stage<GXW, true>(xr, stage, rin, b - 8, r, col63);
+            }
+            R cseg[S];
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+                cseg[u] = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
+            // ---- replay the segment's forward from the checkpoint
+            R Dp[S][M], Dq[S][M];
+            int Tst[S], Est[S], jst[S];
+            bool lv[S];
+            const R* ck = ckb + (int64_t)kk * 2 * (N + 1) * 64;
+            int E = ceb[(int64_t)kk * (SK_LANES + 1) + r];
+            const unsigned tword =
+                TMAX > 0 ? (unsigned)__builtin_amdgcn_readfirstlane(ceb[(int64_t)kk * (SK_LANES + 1) + SK_LANES])
+                         : 0u;
+            R P[N + 1], Qs[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                P[n] = ck[n * 64 + r];
+                Qs[n] = ck[(N + 1 + n) * 64 + r];
+            }
+            int Es = E;
+#pragma unroll
+            for (int u = 0; u < S; ++u) {
+                const int j = t0 + u - r;
+                const bool live = rowok && j >= 0 && j < ly;
+                R Qin[N + 1];
+                if (u == 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
+                } else {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+                    int Ein = lane_from_prev(Es);
+                    if (live) {
+                        if (j == 0) {
+#pragma unroll
+                            for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
+                            E = 0;
+                        }
+                        if (r == 0) {
+                            if (s == 0) {
+#pragma unroll
+                                for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
+                                Ein = 0;
+                            } else {
+                                const int64_t o = (int64_t)s * ly + j;
+#pragma unroll
+                                for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                                Ein = a.qe[pd.qe_off + o];
+                            }
+                        }
+                        const int Ec = E > Ein ? E : Ein;
+                        const int dp = E - Ec, dq = Ein - Ec;
+                        if (sk_wave_any(dp != 0 || dq != 0)) {
+#pragma unroll
+                            for (int n = 0; n <= N; ++n) {
+                                P[n] = sk_ldexp(P[n], dp);
+                                Qin[n] = sk_ldexp(Qin[n], dq);
+                            }
+                        }
+                        E = Ec;
+                    }
+                }
+                lv[u] = live;
+                jst[u] = j;
+                Est[u] = E;
+                R Po[N + 1], Qo[N + 1];
+                double Po0, Po1, Qo0, Qo1;
+                Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
+                sk_cell_fwd<R, N, TMAX, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
+                                                           a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
+                                                           Dq[u], nullptr, Tst[u]);
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    P[n] = Po[n];
+                    Qs[n] = Qo[n];
+                }
+                Es = E;
+            }
+            // ---- adjoint steps in reverse
+#pragma unroll
+            for (int u = S - 1; u >= 0; --u) {
+                const int t = t0 + u;
+                const bool live = lv[u];
+                const int jj = jst[u];
+                const bool last_row = (i == g.lx - 1), last_col = (jj == ly - 1);
+                R lq_recv[N + 1];
+#pragma unroll
+                for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
+                int El_recv = lane_from_next(Els);
+                if (r == 63 && live && !last_row) {  // from strip s+1's lane 0
+                    const unsigned* rec = stage + (t & 7) * GXW;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
+                    El_recv = (int)rec[(N + 1) * (ES / 4)];
+                }
+                const bool ta = live && !last_col, tb = live && !last_row;
+                R ap[N + 1], aq[N + 1];
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = ta ? lp[n] : (R)0;
+                    aq[n] = tb ? lq_recv[n] : (R)0;
+                }
+                int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+                const bool seed = live && last_col && last_row;
+                if (sk_wave_any(seed) && seed) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        ap[n] = (R)0.5 * gk * ifact<R>(n);
+                        aq[n] = ap[n];
+                    }
+                    ea = gexp;
+                    eb = gexp;
+                }
+                const int Ec = ea > eb ? ea : eb;
+                const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
+                if (sk_wave_any(sa || sb)) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        ap[n] = sk_ldexp(ap[n], ea - Ec);
+                        aq[n] = sk_ldexp(aq[n], eb - Ec);
+                    }
+                }
+                R gv;
+                sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
+                El = Ec;
+                Els = Ec;
+                if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
+                    unsigned wd[RW];
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(wd + n * (ES / 4)) = lqs[n];
+                    wd[RW - 1] = (unsigned)Ec;
+                    unsigned* rec = rout + (int64_t)jj * GXW;
+#pragma unroll
+                    for (int k = 0; k < RW; ++k) sk_store_coherent(rec + k, wd[k]);
+                }
+                if (live) gs[(int64_t)t * 64 + r] = sk_ldexp(gv, Ec + Est[u]);
+                if ((t & 7) == 0 && live) {
+                    R m = (R)0;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
+                        m = x1 > m ? x1 : m;
+                        m = x2 > m ? x2 : m;
+                    }
+                    const int sh = sk_rescale_shift<R>(m);
+                    if (sh != 0) {
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) {
+                            lp[n] = sk_ldexp(lp[n], -sh);
+                            lqs[n] = sk_ldexp(lqs[n], -sh);
+                        }
+                        El += sh;
+                        Els = El;
+                    }
+                }
+            }
+            // lane 0 has handed over the columns j >= t0: publish them once
+            // its record stores have completed
+            if (s > 0 && (t0 & 7) == 0) {
+                int done = ly - t0;
+                done = done < 0 ? 0 : (done > ly ? ly : done);
+                if (done > published) {
+                    sk_stores_complete();
+                    if (r == 0) sk_store_coherent(reinterpret_cast<unsigned*>(prog + s), (unsigned)done);
+                    published = done;
+                }
+            }
+        }
+        if (!ok) {  // a wait gave up: the pair's gradient is unknown
+            if (rowok) gs[(int64_t)r * 64 + r] = (R)NAN;
+        }
+    }
+}
+
+template <typename R, int N, int TMAX, int S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
+void k_adjoint_pipe_w2(const AdjPipeArgs<R> a) {
+    sk_adjoint_pipe_body<R, N, TMAX, S>(a);
+}
+
+template <typename R, int N, int TMAX, int S>
+__global__ __launch_bounds__(64) void k_adjoint_pipe(const AdjPipeArgs<R> a) {
+    sk_adjoint_pipe_body<R, N, TMAX, S>(a);
 }
 
 // ---------------------------------------------------------------------------

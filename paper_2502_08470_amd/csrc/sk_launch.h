@@ -34,9 +34,13 @@ struct SkLaunch {
                             int ring, bool gx, hipStream_t st);
     static hipError_t adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t npairs, int ring,
                               bool gx, hipStream_t st);
-    // strip pipeline of one pair on co-resident workgroups (cooperative
-    // launch; at most one workgroup per strip)
-    static hipError_t sweep_pipe(const PipeArgs<R>& a, int N, bool interp, hipStream_t st);
+    // strip pipeline: strips of one pair, or of a job list, on co-resident
+    // workgroups (cooperative launch; at most one workgroup per job).
+    // ckpt: also store the pipelined adjoint's checkpoints (job lists only)
+    static hipError_t sweep_pipe(const PipeArgs<R>& a, int N, bool interp, bool ckpt, hipStream_t st);
+    // adjoint of strip-pipeline pairs: the job list's strips, each pair's in
+    // decreasing order, on co-resident workgroups
+    static hipError_t adjoint_pipe(const AdjPipeArgs<R>& a, int N, bool interp, hipStream_t st);
     static hipError_t contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                hipStream_t st);
     static hipError_t reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st);

@@ -117,35 +117,81 @@ hipError_t SkLaunch<R>::sweep(const SweepArgs<R>& a, int N, bool interp, bool ck
     }
 }
 
-template <typename R, int N, int TMAX>
-static hipError_t sk_pipe_n(const PipeArgs<R>& a, hipStream_t st) {
-    const void* kern = reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX>);
-    const size_t lds = (size_t)sk_gx_stage_bytes(N, (int)sizeof(R));
+// Cooperative launch of a strip-pipeline kernel: as many one-wave
+// workgroups as fit on the device at once (every wave that another waits for
+// must be resident), at most one per job.
+template <typename Args>
+static hipError_t sk_coop_launch(const void* kern, const Args& a, int64_t njobs, size_t lds,
+                                 hipStream_t st) {
     int dev = 0, ncu = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64, lds);
     if (e != hipSuccess) return e;
-    // jobs: the strips of the single pair, or the job list
-    const int64_t njobs = a.desc ? a.njobs : (int64_t)sk_make_geom(a.lx, a.ly).nstrips;
     int64_t W = std::min<int64_t>(std::max<int64_t>(1, njobs), (int64_t)per * ncu);
     if (W < 1) return hipErrorInvalidConfiguration;
-    PipeArgs<R> arg = a;
+    Args arg = a;
     void* args[] = {&arg};
     return hipLaunchCooperativeKernel(kern, dim3((unsigned)W), dim3(64), args, (unsigned)lds, st);
 }
 
+template <typename R, int N, int TMAX>
+static hipError_t sk_pipe_n(const PipeArgs<R>& a, bool ckpt, hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    const void* kern = ckpt ? reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, true, S>)
+                            : reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, false, S>);
+    // jobs: the strips of the single pair, or the job list
+    const int64_t njobs = a.desc ? a.njobs : (int64_t)sk_make_geom(a.lx, a.ly).nstrips;
+    return sk_coop_launch(kern, a, njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
+}
+
 template <typename R>
-hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, hipStream_t st) {
+hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, bool ckpt, hipStream_t st) {
+    if (ckpt && !a.desc) return hipErrorInvalidValue;
     constexpr int T = SkTailMax<R>::value;
     switch (N) {
-        case 2: return interp ? sk_pipe_n<R, 2, T>(a, st) : sk_pipe_n<R, 2, 0>(a, st);
-        case 3: return interp ? sk_pipe_n<R, 3, T>(a, st) : sk_pipe_n<R, 3, 0>(a, st);
-        case 4: return interp ? sk_pipe_n<R, 4, T>(a, st) : sk_pipe_n<R, 4, 0>(a, st);
-        case 5: return interp ? sk_pipe_n<R, 5, T>(a, st) : sk_pipe_n<R, 5, 0>(a, st);
-        case 6: return interp ? sk_pipe_n<R, 6, T>(a, st) : sk_pipe_n<R, 6, 0>(a, st);
-        case 7: return interp ? sk_pipe_n<R, 7, T>(a, st) : sk_pipe_n<R, 7, 0>(a, st);
-        case 8: return interp ? sk_pipe_n<R, 8, T>(a, st) : sk_pipe_n<R, 8, 0>(a, st);
+        case 2: return interp ? sk_pipe_n<R, 2, T>(a, ckpt, st) : sk_pipe_n<R, 2, 0>(a, ckpt, st);
+        case 3: return interp ? sk_pipe_n<R, 3, T>(a, ckpt, st) : sk_pipe_n<R, 3, 0>(a, ckpt, st);
+        case 4: return interp ? sk_pipe_n<R, 4, T>(a, ckpt, st) : sk_pipe_n<R, 4, 0>(a, ckpt, st);
+        case 5: return interp ? sk_pipe_n<R, 5, T>(a, ckpt, st) : sk_pipe_n<R, 5, 0>(a, ckpt, st);
+        case 6: return interp ? sk_pipe_n<R, 6, T>(a, ckpt, st) : sk_pipe_n<R, 6, 0>(a, ckpt, st);
+        case 7: return interp ? sk_pipe_n<R, 7, T>(a, ckpt, st) : sk_pipe_n<R, 7, 0>(a, ckpt, st);
+        case 8: return interp ? sk_pipe_n<R, 8, T>(a, ckpt, st) : sk_pipe_n<R, 8, 0>(a, ckpt, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Two waves per SIMD for the pipelined adjoint where half the register file
+// holds it without spilling (FP32 N <= 7 approximation or N <= 6
+// interpolation; FP64 N <= 6 approximation or N <= 4 interpolation), and for
+// FP32 N = 8 approximation, whose 17 spilled registers cost less than a
+// second wave gains (adjoint of 4096 uneven pairs: 155 -> 111 ms).
+template <typename R, int N, int TMAX>
+constexpr bool sk_adj_pipe_two_waves() {
+    return sizeof(R) == 4 ? (TMAX == 0 || N <= 6) : (TMAX == 0 ? N <= 6 : N <= 4);
+}
+
+template <typename R, int N, int TMAX>
+static hipError_t sk_adj_pipe_n(const AdjPipeArgs<R>& a, hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    const void* kern = sk_adj_pipe_two_waves<R, N, TMAX>()
+                           ? reinterpret_cast<const void*>(&k_adjoint_pipe_w2<R, N, TMAX, S>)
+                           : reinterpret_cast<const void*>(&k_adjoint_pipe<R, N, TMAX, S>);
+    return sk_coop_launch(kern, a, a.njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::adjoint_pipe(const AdjPipeArgs<R>& a, int N, bool interp, hipStream_t st) {
+    if (a.njobs <= 0) return hipSuccess;
+    constexpr int T = SkTailMax<R>::value;
+    switch (N) {
+        case 2: return interp ? sk_adj_pipe_n<R, 2, T>(a, st) : sk_adj_pipe_n<R, 2, 0>(a, st);
+        case 3: return interp ? sk_adj_pipe_n<R, 3, T>(a, st) : sk_adj_pipe_n<R, 3, 0>(a, st);
+        case 4: return interp ? sk_adj_pipe_n<R, 4, T>(a, st) : sk_adj_pipe_n<R, 4, 0>(a, st);
+        case 5: return interp ? sk_adj_pipe_n<R, 5, T>(a, st) : sk_adj_pipe_n<R, 5, 0>(a, st);
+        case 6: return interp ? sk_adj_pipe_n<R, 6, T>(a, st) : sk_adj_pipe_n<R, 6, 0>(a, st);
+        case 7: return interp ? sk_adj_pipe_n<R, 7, T>(a, st) : sk_adj_pipe_n<R, 7, 0>(a, st);
+        case 8: return interp ? sk_adj_pipe_n<R, 8, T>(a, st) : sk_adj_pipe_n<R, 8, 0>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

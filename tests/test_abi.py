@@ -85,7 +85,7 @@ def test_backward_rejections():
     assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
     assert bwd(P(dyadic=1)) == L.SK_EUNSUPPORTED  # hybrid refined grid: forward only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
-    assert bwd(P(algo=2)) == L.SK_EUNSUPPORTED  # strip pipeline: forward only
+    assert bwd(P(algo=2)) == L.SK_EUNSUPPORTED  # strip pipeline backward: pair lists only
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL
     # SK_SYMMETRIC needs a Gram call whose Y is X (same pointer and shape)

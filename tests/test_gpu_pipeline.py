@@ -122,3 +122,133 @@ def test_pipeline_full_size_fp32(sk):
     log_banner("batched 8193 x 8193")
     Kb = sk.gram(Xt, Yt, "approx", 8).cpu().numpy()
     assert np.isfinite(Kp).all() and np.array_equal(Kp, Kb), (Kp, Kb)
+
+
+# ---------------------------------------------------------------------------
+# backward: pipelined checkpoint sweep + pipelined adjoint
+# ---------------------------------------------------------------------------
+# point counts: 5 and 11 strips, 3 strips with a 1-row last strip, a pair
+# transposed by the plan (y longer), one strip, a 1-segment y, one point
+LENS_BX = [300, 129, 66, 40, 1, 700, 65]
+LENS_BY = [200, 37, 201, 2, 50, 130, 700]
+
+
+def _cat(paths, dtype):
+    return torch.tensor(np.concatenate(paths, 0), dtype=dtype, device="cuda")
+
+
+def _plan_grads(sk, plan, Xc, Yc, gk, pipeline):
+    plan.configure(1, 1, 0, pipeline)
+    assert plan.config()["pipeline"] == pipeline
+    gX = torch.full_like(Xc, float("nan"))
+    gY = torch.full_like(Yc, float("nan"))
+    plan.backward(Xc, Yc, gk, gX, gY)
+    return gX, gY
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 5), ("interp", 4)])
+def test_pipeline_backward_fp64_matches_batched_and_fd(sk, scheme, order):
+    from oracle import c_oracle as C
+    log_banner(f"pipeline backward fp64 {scheme} {order}")
+    rng = np.random.default_rng(86)
+    xs = [bm_paths(rng, 1, n - 1, 3, 0.4 / np.sqrt(n))[0] for n in LENS_BX]
+    ys = [bm_paths(rng, 1, n - 1, 3, 0.4 / np.sqrt(n))[0] for n in LENS_BY]
+    gk = rng.normal(size=len(xs))
+    xl = [dev(a, torch.float64) for a in xs]
+    yl = [dev(b, torch.float64) for b in ys]
+    Xc, Yc = _cat(xs, torch.float64), _cat(ys, torch.float64)
+    gkt = dev(gk, torch.float64)
+    plan = sk.PairsPlan(xl, yl, scheme, order, backward=True)
+    gXb, gYb = _plan_grads(sk, plan, Xc, Yc, gkt, False)
+    gXp, gYp = _plan_grads(sk, plan, Xc, Yc, gkt, True)
+    assert torch.isfinite(gXp).all() and torch.isfinite(gYp).all()
+    torch.testing.assert_close(gXp, gXb, rtol=1e-11, atol=1e-11 * float(gXb.abs().max()))
+    torch.testing.assert_close(gYp, gYb, rtol=1e-11, atol=1e-11 * float(gYb.abs().max()))
+    # the one-shot call with the pipeline algorithm runs the same launches
+    gX1, gY1, xo, yo = sk.pairs_backward(xl, yl, gkt, scheme, order, algo="pipeline")
+    assert torch.equal(gX1, gXp) and torch.equal(gY1, gYp)
+    # central differences of the FP64 oracle: last point of a 5-strip x,
+    # interior points of the 11-strip x and of the transposed pair's long y
+    kind = C.APPROX if scheme == "approx" else C.INTERP
+    gXn, gYn = gXp.cpu().numpy(), gYp.cpu().numpy()
+    h = 1e-4
+    for side, p, t, k in [("x", 0, 299, 2), ("x", 0, 0, 0), ("x", 5, 350, 1), ("y", 6, 640, 0),
+                          ("x", 6, 64, 2), ("y", 2, 100, 1)]:
+        base = xs[p] if side == "x" else ys[p]
+        def loss(v):
+            a, b = (v, ys[p]) if side == "x" else (xs[p], v)
+            m, e = C.pairs([a], [b], kind, order)
+            return gk[p] * float(np.ldexp(m, e)[0])
+        v = base.copy()
+        v[t, k] += h
+        lp = loss(v)
+        v[t, k] -= 2 * h
+        lm = loss(v)
+        fd = (lp - lm) / (2 * h)
+        g = gXn[xo[p] + t, k] if side == "x" else gYn[yo[p] + t, k]
+        assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (side, p, t, k, g, fd)
+
+
+def test_pipeline_backward_fp32_interp_matches_batched(sk):
+    # the bench's scheme (interpolation N = 6, FP32) on 96 uneven pairs of up
+    # to 1500 points: same cell arithmetic, different rescaling schedule
+    log_banner("pipeline backward fp32 interp")
+    rng = np.random.default_rng(87)
+    lx = rng.integers(32, 1501, size=96)
+    ly = rng.integers(32, 1501, size=96)
+    xs = [bm_paths(rng, 1, int(m) - 1, 8, 0.5 / np.sqrt(m))[0].astype(np.float32) for m in lx]
+    ys = [bm_paths(rng, 1, int(m) - 1, 8, 0.5 / np.sqrt(m))[0].astype(np.float32) for m in ly]
+    xl = [dev(a, torch.float32) for a in xs]
+    yl = [dev(b, torch.float32) for b in ys]
+    Xc, Yc = _cat(xs, torch.float32), _cat(ys, torch.float32)
+    gk = dev(rng.normal(size=len(xs)), torch.float32)
+    plan = sk.PairsPlan(xl, yl, "interp", 6, backward=True)
+    gXb, gYb = _plan_grads(sk, plan, Xc, Yc, gk, False)
+    gXp, gYp = _plan_grads(sk, plan, Xc, Yc, gk, True)
+    assert torch.isfinite(gXp).all() and torch.isfinite(gYp).all()
+    # per path: relative to the path's largest gradient entry
+    xo = np.concatenate([[0], np.cumsum(lx)])
+    yo = np.concatenate([[0], np.cumsum(ly)])
+    for g1, g0, off in ((gXp, gXb, xo), (gYp, gYb, yo)):
+        a, b = g1.cpu().numpy(), g0.cpu().numpy()
+        for i in range(len(off) - 1):
+            s = np.abs(b[off[i]:off[i + 1]]).max()
+            assert np.abs(a[off[i]:off[i + 1]] - b[off[i]:off[i + 1]]).max() <= 2e-5 * s, i
+
+
+def test_pipeline_backward_graph_replays_match_eager(sk):
+    # the pipelined backward (Gram, two cooperative launches, counter fills,
+    # contraction, reduction) captured into a HIP graph: every replay equals
+    # the eager result
+    log_banner("pipeline backward graph capture")
+    rng = np.random.default_rng(88)
+    lx = rng.integers(40, 700, size=32)
+    ly = rng.integers(40, 700, size=32)
+    xs = [bm_paths(rng, 1, int(m) - 1, 4, 0.4 / np.sqrt(m))[0].astype(np.float32) for m in lx]
+    ys = [bm_paths(rng, 1, int(m) - 1, 4, 0.4 / np.sqrt(m))[0].astype(np.float32) for m in ly]
+    xl = [dev(a, torch.float32) for a in xs]
+    yl = [dev(b, torch.float32) for b in ys]
+    Xc, Yc = _cat(xs, torch.float32), _cat(ys, torch.float32)
+    gk = dev(rng.normal(size=len(xs)), torch.float32)
+    plan = sk.PairsPlan(xl, yl, "approx", 6, backward=True)
+    gX0, gY0 = _plan_grads(sk, plan, Xc, Yc, gk, True)
+    torch.cuda.synchronize()
+    gX, gY = torch.zeros_like(Xc), torch.zeros_like(Yc)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.backward(Xc, Yc, gk, gX, gY)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.backward(Xc, Yc, gk, gX, gY)
+    for rep in range(3):
+        gX.zero_()
+        gY.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert torch.equal(gX, gX0) and torch.equal(gY, gY0), rep
