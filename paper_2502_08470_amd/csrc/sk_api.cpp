@@ -626,8 +626,6 @@ int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_
     ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = reinterpret_cast<const R*>(ws + L.gskew);
     ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
     ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
-    const int64_t dmax = d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 64;
-    ca.jchunk = (int)std::max<int64_t>(1, std::min<int64_t>(max_ly, 32768 / (dmax * (int64_t)sizeof(R))));
     SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
     return SK_OK;
 }

@@ -1602,16 +1602,22 @@ struct ContractArgs {
     const R* gskew;
     R* dxp;   // [pair][lx][d]
     R* dyp;   // [pair][strip][ly][d]
-    int32_t jchunk;  // columns per LDS pass
 };
+
+// Row stride of the contraction's LDS ring of y increments (padded by 16
+// bytes so that 64 consecutive columns spread over the banks).
+template <typename R, int DMAX>
+constexpr int sk_contract_ys() { return DMAX + 16 / (int)sizeof(R); }
 
 // One wave per (pair, strip): lane r accumulates dL/d(dx_i) for its row
 // i = 64 s + r in registers.  dL/d(dy_j) for the strip is a sum down the
 // column j, whose cells lanes r = 0..63 visit at consecutive steps; the
 // partial sum therefore travels with the wavefront (lane r-1 -> lane r, one
 // DPP move per step) and the strip's last row writes it out.  The y
-// increments of a column chunk are staged in LDS; rows of dL/dc are
-// prefetched eight steps ahead.
+// increments sit in an LDS ring of 128 columns (column j in row j mod 128):
+// at step t the lanes read columns t-63 .. t, and every 8 steps the next 8
+// columns, loaded one block ahead, replace columns that no lane reads again.
+// Rows of dL/dc are prefetched eight steps ahead.
 template <typename R, int DMAX>
 __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const int r = threadIdx.x;
@@ -1620,75 +1626,88 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
     if (g.nsteps == 0 || s >= g.nstrips) return;
+    constexpr int YS = sk_contract_ys<R, DMAX>();
+    constexpr int NV = (8 * DMAX + 63) / 64;  // ring values per lane per 8 columns
     extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* ring = reinterpret_cast<R*>(sk_smem);  // [128][YS]
     const int64_t d = a.d;
-    const int jc = a.jchunk;
-    R* ycl = reinterpret_cast<R*>(sk_smem);  // [jc][DMAX] y increments of the chunk
+    const int ly = g.ly;
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
-    const R* gsk = a.gskew + pd.c_off;
+    const R* gsk = a.gskew + pd.c_off + (int64_t)s * g.Tp * 64;
     const int i = s * 64 + r;
     const bool rowok = i < g.lx;
     const int last_r = (g.lx - 1 - s * 64) < 63 ? (g.lx - 1 - s * 64) : 63;
-    R xi[DMAX], accx[DMAX];
+    const int nt = ly + last_r;  // local steps: the last row reaches column ly-1 at ly-1+last_r
+    R xi[DMAX], accx[DMAX], accy[DMAX];
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
         xi[k] = (R)0;
         accx[k] = (R)0;
+        accy[k] = (R)0;
         if (k < d && rowok) xi[k] = X[(int64_t)(i + 1) * d + k] - X[(int64_t)i * d + k];
     }
-    for (int j0 = 0; j0 < g.ly; j0 += jc) {
-        const int j1 = (j0 + jc < g.ly) ? j0 + jc : g.ly;
-        __syncthreads();
-        for (int e = r; e < (j1 - j0) * DMAX; e += 64) {
-            const int jj = e / DMAX, k = e % DMAX;
-            const int64_t j = j0 + jj;
-            ycl[e] = k < d ? Y[(j + 1) * d + k] - Y[j * d + k] : (R)0;
+    // y increments of the 8 columns from c0: value w is column c0 + w / DMAX, dimension w % DMAX
+    R yv[NV];
+    auto load_y = [&](int c0) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX, c = c0 + m;
+            yv[h] = (R)0;
+            if (w < 8 * DMAX && k < d && c < ly)
+                yv[h] = Y[(int64_t)(c + 1) * d + k] - Y[(int64_t)c * d + k];
         }
-        __syncthreads();
-        R accy[DMAX];
+    };
+    auto store_y = [&](int c0) {
 #pragma unroll
-        for (int k = 0; k < DMAX; ++k) accy[k] = (R)0;
-        const int tbeg = s * g.Tp + j0;
-        int tend = s * g.Tp + j1 - 1 + 63;
-        if (tend > g.nsteps - 1) tend = g.nsteps - 1;
-        R gb[8], gn[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) gb[u] = tbeg + u <= tend ? gsk[(int64_t)(tbeg + u) * 64 + r] : (R)0;
-        for (int t0 = tbeg; t0 <= tend; t0 += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int tau = t0 + 8 + u;
-                gn[u] = tau <= tend ? gsk[(int64_t)tau * 64 + r] : (R)0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int tau = t0 + u;
-                const int j = tau - r - s * g.Tp;
-                // lane 0 receives zero (the DPP shift fills it), which starts
-                // the column's sum
-#pragma unroll
-                for (int k = 0; k < DMAX; ++k) accy[k] = lane_from_prev(accy[k]);
-                const bool ok = rowok && j >= j0 && j < j1 && tau <= tend;
-                // cells outside the chunk contribute zero (no branch): their
-                // partial sums are never stored
-                const R gv = ok ? gb[u] : (R)0;
-                const R* yj = ycl + (ok ? j - j0 : 0) * DMAX;
-#pragma unroll
-                for (int k = 0; k < DMAX; ++k) {
-                    accx[k] = fma(gv, yj[k], accx[k]);
-                    accy[k] = fma(gv, xi[k], accy[k]);
-                }
-                if (ok && r == last_r) {
-                    R* dyo = a.dyp + pd.dy_off + ((int64_t)s * g.ly + j) * d;
-#pragma unroll
-                    for (int k = 0; k < DMAX; ++k)
-                        if (k < d) dyo[k] = accy[k];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) gb[u] = gn[u];
+        for (int h = 0; h < NV; ++h) {
+            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX;
+            if (w < 8 * DMAX) ring[((c0 + m) & 127) * YS + k] = yv[h];
         }
+    };
+    load_y(0);
+    R gb[8], gn[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) gb[u] = u < nt ? gsk[(int64_t)u * 64 + r] : (R)0;
+    for (int t0 = 0; t0 < nt; t0 += 8) {
+        // columns t0 .. t0+7 into the ring (their rows held columns t0-128 ..
+        // t0-121, which no lane reads again), then the next block's loads
+        store_y(t0);
+        __syncthreads();
+        load_y(t0 + 8);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 8 + u;
+            gn[u] = t < nt ? gsk[(int64_t)t * 64 + r] : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u, j = t - r;
+            // lane 0 receives zero (the DPP shift fills it), which starts the
+            // column's sum
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) accy[k] = lane_from_prev(accy[k]);
+            const bool ok = rowok && j >= 0 && j < ly && t < nt;
+            // cells outside the strip contribute zero (no branch)
+            const R gv = ok ? gb[u] : (R)0;
+            const R* yj = ring + ((ok ? j : 0) & 127) * YS;
+#pragma unroll
+            for (int k = 0; k < DMAX; ++k) {
+                accx[k] = fma(gv, yj[k], accx[k]);
+                accy[k] = fma(gv, xi[k], accy[k]);
+            }
+            if (ok && r == last_r) {
+                R* dyo = a.dyp + pd.dy_off + ((int64_t)s * ly + j) * d;
+#pragma unroll
+                for (int k = 0; k < DMAX; ++k)
+                    if (k < d) dyo[k] = accy[k];
+            }
+            // keep each step's ring reads in its step (hoisting them holds
+            // 8 * DMAX values in registers and halves the occupancy)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gb[u] = gn[u];
     }
     if (rowok) {
 #pragma unroll

@@ -240,22 +240,22 @@ hipError_t SkLaunch<R>::adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t
     }
 }
 
+template <typename R, int DMAX>
+static void sk_contract_d(const ContractArgs<R>& a, dim3 grid, hipStream_t st) {
+    const size_t lds = (size_t)128 * sk_contract_ys<R, DMAX>() * sizeof(R);
+    hipLaunchKernelGGL((k_contract<R, DMAX>), grid, dim3(64), lds, st, a);
+}
+
 template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
     dim3 grid((unsigned)npairs, max_strips);
-    const size_t jc = (size_t)a.jchunk;
-    if (a.d <= 4)
-        hipLaunchKernelGGL((k_contract<R, 4>), grid, dim3(64), jc * 4 * sizeof(R), st, a);
-    else if (a.d <= 8)
-        hipLaunchKernelGGL((k_contract<R, 8>), grid, dim3(64), jc * 8 * sizeof(R), st, a);
-    else if (a.d <= 16)
-        hipLaunchKernelGGL((k_contract<R, 16>), grid, dim3(64), jc * 16 * sizeof(R), st, a);
-    else if (a.d <= 32)
-        hipLaunchKernelGGL((k_contract<R, 32>), grid, dim3(64), jc * 32 * sizeof(R), st, a);
-    else
-        hipLaunchKernelGGL((k_contract<R, 64>), grid, dim3(64), jc * 64 * sizeof(R), st, a);
+    if (a.d <= 4) sk_contract_d<R, 4>(a, grid, st);
+    else if (a.d <= 8) sk_contract_d<R, 8>(a, grid, st);
+    else if (a.d <= 16) sk_contract_d<R, 16>(a, grid, st);
+    else if (a.d <= 32) sk_contract_d<R, 32>(a, grid, st);
+    else sk_contract_d<R, 64>(a, grid, st);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
