@@ -385,9 +385,11 @@ constexpr size_t kGramPairLds = 64 << 10;
 template <typename R>
 hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int max_lx,
                        int max_ly, bool direct, hipStream_t st) {
-    if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX &&
-        SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
-        return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
+    if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX) {
+        if (SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
+            return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
+        return SkLaunch<R>::gram_strip(ga, ((max_lx << ga.lam) + SK_LANES - 1) / SK_LANES, P, st);
+    }
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);

@@ -38,6 +38,11 @@ struct GramArgs {
 };
 
 template <typename R> struct SkMfma;
+
+// Row stride of an LDS ring of y increments, one row per column (padded by
+// 16 bytes so that 64 consecutive columns spread over the banks).
+template <typename R, int DMAX>
+constexpr int sk_ring_ys() { return DMAX + 16 / (int)sizeof(R); }
 // 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
 // accumulator element v of lane l holds D[row(l, v)][l % 16].  The FP32 and
 // FP64 instructions place the four output rows of a lane differently.
@@ -300,6 +305,104 @@ __global__ __launch_bounds__(256) void k_gram_direct(const GramArgs<R> a) {
         if (L > 0 && ++j == g.Tp) {
             j = 0;
             ++s;
+        }
+    }
+}
+
+// Direct variant for pairs whose increments exceed one workgroup's LDS: one
+// wave per (pair, strip s) writes the skewed rows [s Tp, (s+1) Tp) (the last
+// strip up to nsteps_pad), whole.  Lane r's cell at row s Tp + t has linear
+// index s Tp + v, v = t - r: row 64 s + r and column v when v >= 0, row
+// 64 (s-1) + r and column Tp + v (strip s-1) when v < 0.  The lane keeps the
+// x increments of both rows in registers; the y increments of the 64
+// virtual columns t-63 .. t sit in an LDS ring of 128 (slot v mod 128),
+// 8 columns added every 8 steps, loaded one block ahead.  Same FMA order
+// and scaling as k_gram_direct, so both give identical constants.
+template <typename R, int DMAX>
+__global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
+    const int r = threadIdx.x;
+    const int s = blockIdx.y;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0 || s >= g.nstrips) return;
+    constexpr int YS = sk_ring_ys<R, DMAX>();
+    constexpr int NV = (8 * DMAX + 63) / 64;  // ring values per lane per 8 columns
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* ring = reinterpret_cast<R*>(sk_smem);  // [128][YS]
+    const int64_t d = a.d;
+    const int lam = a.lam;
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
+    const int Tend = (s == g.nstrips - 1) ? g.nsteps_pad - s * g.Tp : g.Tp;
+    // x increments (segment i >> lam, unrefined) of the lane's rows in
+    // strips s and s-1 (every row of a strip before the last exists)
+    const int ia = s * 64 + r, ib = ia - 64;
+    const bool oka = ia < g.lx, okb = s > 0;
+    R xa[DMAX], xb[DMAX];
+#pragma unroll
+    for (int k = 0; k < DMAX; ++k) {
+        xa[k] = (R)0;
+        xb[k] = (R)0;
+        if (k < d && oka) xa[k] = X[(int64_t)((ia >> lam) + 1) * d + k] - X[(int64_t)(ia >> lam) * d + k];
+        if (k < d && okb) xb[k] = X[(int64_t)((ib >> lam) + 1) * d + k] - X[(int64_t)(ib >> lam) * d + k];
+    }
+    // y increments of the 8 virtual columns from v0: value w is column
+    // v0 + w / DMAX, dimension w % DMAX
+    R yv[NV];
+    auto load_y = [&](int v0) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX, v = v0 + m;
+            const int col = v >= 0 ? v : g.Tp + v;
+            yv[h] = (R)0;
+            if (w < 8 * DMAX && k < d && (v >= 0 || s > 0) && col < g.ly) {
+                const int j = col >> lam;
+                yv[h] = Y[(int64_t)(j + 1) * d + k] - Y[(int64_t)j * d + k];
+            }
+        }
+    };
+    auto store_y = [&](int v0) {
+#pragma unroll
+        for (int h = 0; h < NV; ++h) {
+            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX;
+            if (w < 8 * DMAX) ring[((v0 + m) & 127) * YS + k] = yv[h];
+        }
+    };
+    for (int v0 = -64; v0 <= 0; v0 += 8) {
+        load_y(v0);
+        store_y(v0);
+    }
+    load_y(8);
+    __syncthreads();
+    const R scale = (R)1 / (R)(1 << (2 * lam));
+    R* out = a.cskew + pd.c_off + (int64_t)s * g.Tp * 64;
+    for (int t0 = 0; t0 < Tend; t0 += 8) {
+        if (t0 > 0) {  // columns t0 .. t0+7 replace t0-128 .. t0-121, which no lane reads again
+            store_y(t0);
+            __syncthreads();
+            load_y(t0 + 8);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u, v = t - r;
+            if (t >= Tend) break;
+            const bool lo = v < 0;
+            const int col = lo ? g.Tp + v : v;
+            const bool live = (lo ? okb : oka) && col < g.ly;
+            R c = (R)0;
+            if (live) {
+                const R* yr = ring + (v & 127) * YS;
+#pragma unroll
+                for (int k = 0; k < DMAX; k += 2) {
+                    c = fma(lo ? xb[k] : xa[k], yr[k], c);
+                    c = fma(lo ? xb[k + 1] : xa[k + 1], yr[k + 1], c);
+                }
+                c *= scale;
+            }
+            out[(int64_t)t * 64 + r] = c;
+            // keep each step's ring reads in its step
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
     }
 }
@@ -1604,11 +1707,6 @@ struct ContractArgs {
     R* dyp;   // [pair][strip][ly][d]
 };
 
-// Row stride of the contraction's LDS ring of y increments (padded by 16
-// bytes so that 64 consecutive columns spread over the banks).
-template <typename R, int DMAX>
-constexpr int sk_contract_ys() { return DMAX + 16 / (int)sizeof(R); }
-
 // One wave per (pair, strip): lane r accumulates dL/d(dx_i) for its row
 // i = 64 s + r in registers.  dL/d(dy_j) for the strip is a sum down the
 // column j, whose cells lanes r = 0..63 visit at consecutive steps; the
@@ -1626,7 +1724,7 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx, pd.ly);
     if (g.nsteps == 0 || s >= g.nstrips) return;
-    constexpr int YS = sk_contract_ys<R, DMAX>();
+    constexpr int YS = sk_ring_ys<R, DMAX>();
     constexpr int NV = (8 * DMAX + 63) / 64;  // ring values per lane per 8 columns
     extern __shared__ __align__(16) unsigned char sk_smem[];
     R* ring = reinterpret_cast<R*>(sk_smem);  // [128][YS]

@@ -76,6 +76,22 @@ hipError_t SkLaunch<R>::gram_direct(const GramArgs<R>& a, int max_lx, int max_ly
     return hipSuccess;
 }
 
+template <typename R>
+hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a, int max_strips, int64_t npairs,
+                                   hipStream_t st) {
+    if (npairs <= 0 || max_strips <= 0) return hipSuccess;
+    if (a.split || a.dpad > SK_GRAM_DIRECT_DMAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)npairs, (unsigned)max_strips);
+    if (a.dpad <= 4)
+        hipLaunchKernelGGL((k_gram_strip<R, 4>), grid, dim3(64), (128 * sk_ring_ys<R, 4>() * sizeof(R)), st, a);
+    else if (a.dpad <= 8)
+        hipLaunchKernelGGL((k_gram_strip<R, 8>), grid, dim3(64), (128 * sk_ring_ys<R, 8>() * sizeof(R)), st, a);
+    else
+        hipLaunchKernelGGL((k_gram_strip<R, 16>), grid, dim3(64), (128 * sk_ring_ys<R, 16>() * sizeof(R)), st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
 template <typename R, int N, int TMAX>
 static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
                              hipStream_t st) {
@@ -242,7 +258,7 @@ hipError_t SkLaunch<R>::adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t
 
 template <typename R, int DMAX>
 static void sk_contract_d(const ContractArgs<R>& a, dim3 grid, hipStream_t st) {
-    const size_t lds = (size_t)128 * sk_contract_ys<R, DMAX>() * sizeof(R);
+    const size_t lds = (size_t)128 * sk_ring_ys<R, DMAX>() * sizeof(R);
     hipLaunchKernelGGL((k_contract<R, DMAX>), grid, dim3(64), lds, st, a);
 }
 
