@@ -388,7 +388,9 @@ hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int
     if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX) {
         if (SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
             return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
-        return SkLaunch<R>::gram_strip(ga, ((max_lx << ga.lam) + SK_LANES - 1) / SK_LANES, P, st);
+        // a strip's skewed rows: Tp = max(ly, min(lx, 64)), the last strip up to 127 more
+        const int rows = std::max(max_ly << ga.lam, SK_LANES) + 2 * SK_LANES;
+        return SkLaunch<R>::gram_strip(ga, ((max_lx << ga.lam) + SK_LANES - 1) / SK_LANES, rows, P, st);
     }
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);

@@ -35,6 +35,7 @@ struct GramArgs {
     R* cskew;           // chunk buffer of skewed constants
     unsigned* maxc;     // per chunk-local pair: bits of max |c| (nullable)
     int32_t split;      // FP32 only: BF16 3-way split products instead of FP32 MFMA
+    int32_t rseg;       // k_gram_strip: rows of a strip per workgroup (a multiple of 8)
 };
 
 template <typename R> struct SkMfma;
@@ -310,8 +311,9 @@ __global__ __launch_bounds__(256) void k_gram_direct(const GramArgs<R> a) {
 }
 
 // Direct variant for pairs whose increments exceed one workgroup's LDS: one
-// wave per (pair, strip s) writes the skewed rows [s Tp, (s+1) Tp) (the last
-// strip up to nsteps_pad), whole.  Lane r's cell at row s Tp + t has linear
+// wave per (pair, strip s, segment z) writes the skewed rows s Tp + t,
+// t in [z rseg, (z+1) rseg), of the strip's rows t < Tp (the last strip's
+// up to nsteps_pad), whole.  Lane r's cell at row s Tp + t has linear
 // index s Tp + v, v = t - r: row 64 s + r and column v when v >= 0, row
 // 64 (s-1) + r and column Tp + v (strip s-1) when v < 0.  The lane keeps the
 // x increments of both rows in registers; the y increments of the 64
@@ -334,7 +336,10 @@ __global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
     const int lam = a.lam;
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
-    const int Tend = (s == g.nstrips - 1) ? g.nsteps_pad - s * g.Tp : g.Tp;
+    const int Tstrip = (s == g.nstrips - 1) ? g.nsteps_pad - s * g.Tp : g.Tp;
+    const int tbeg = (int)blockIdx.z * a.rseg;
+    if (tbeg >= Tstrip) return;
+    const int Tend = tbeg + a.rseg < Tstrip ? tbeg + a.rseg : Tstrip;
     // x increments (segment i >> lam, unrefined) of the lane's rows in
     // strips s and s-1 (every row of a strip before the last exists)
     const int ia = s * 64 + r, ib = ia - 64;
@@ -369,16 +374,16 @@ __global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
             if (w < 8 * DMAX) ring[((v0 + m) & 127) * YS + k] = yv[h];
         }
     };
-    for (int v0 = -64; v0 <= 0; v0 += 8) {
+    for (int v0 = tbeg - 64; v0 <= tbeg; v0 += 8) {
         load_y(v0);
         store_y(v0);
     }
-    load_y(8);
+    load_y(tbeg + 8);
     __syncthreads();
     const R scale = (R)1 / (R)(1 << (2 * lam));
     R* out = a.cskew + pd.c_off + (int64_t)s * g.Tp * 64;
-    for (int t0 = 0; t0 < Tend; t0 += 8) {
-        if (t0 > 0) {  // columns t0 .. t0+7 replace t0-128 .. t0-121, which no lane reads again
+    for (int t0 = tbeg; t0 < Tend; t0 += 8) {
+        if (t0 > tbeg) {  // columns t0 .. t0+7 replace t0-128 .. t0-121, which no lane reads again
             store_y(t0);
             __syncthreads();
             load_y(t0 + 8);

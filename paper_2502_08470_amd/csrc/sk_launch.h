@@ -27,10 +27,11 @@ struct SkLaunch {
     // direct (VALU) Gram for dpad <= SK_GRAM_DIRECT_DMAX, native precision
     static hipError_t gram_direct(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
                                   hipStream_t st);
-    // the same arithmetic, one wave per (pair, strip), for pairs whose
-    // increments exceed the LDS of one workgroup; max_strips of the refined grids
-    static hipError_t gram_strip(const GramArgs<R>& a, int max_strips, int64_t npairs,
-                                 hipStream_t st);
+    // the same arithmetic, one wave per (pair, strip, row segment), for pairs
+    // whose increments exceed the LDS of one workgroup; max_strips and
+    // max_rows (skewed rows of the longest strip) of the refined grids
+    static hipError_t gram_strip(const GramArgs<R>& a, int max_strips, int max_rows,
+                                 int64_t npairs, hipStream_t st);
     // ring: LDS ring columns of the launch (largest among its pairs that do
     // not use the global strip-boundary exchange)
     // gx: some pair of the launch uses the global strip-boundary exchange

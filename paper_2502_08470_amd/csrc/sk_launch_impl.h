@@ -77,11 +77,20 @@ hipError_t SkLaunch<R>::gram_direct(const GramArgs<R>& a, int max_lx, int max_ly
 }
 
 template <typename R>
-hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a, int max_strips, int64_t npairs,
-                                   hipStream_t st) {
-    if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    if (a.split || a.dpad > SK_GRAM_DIRECT_DMAX) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)npairs, (unsigned)max_strips);
+hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int max_rows,
+                                   int64_t npairs, hipStream_t st) {
+    if (npairs <= 0 || max_strips <= 0 || max_rows <= 0) return hipSuccess;
+    if (a0.split || a0.dpad > SK_GRAM_DIRECT_DMAX) return hipErrorInvalidValue;
+    // split each strip's rows so that the launch has about 8 waves per SIMD
+    // (a few long pairs have few strips), segments of at least 256 rows
+    const int64_t waves = npairs * (int64_t)max_strips;
+    const int64_t want = 8192;
+    int64_t nseg = waves >= want ? 1 : (want + waves - 1) / waves;
+    nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, max_rows / 256));
+    GramArgs<R> a = a0;
+    a.rseg = (int)(((max_rows + nseg - 1) / nseg + 7) / 8 * 8);
+    nseg = (max_rows + a.rseg - 1) / a.rseg;
+    const dim3 grid((unsigned)npairs, (unsigned)max_strips, (unsigned)nseg);
     if (a.dpad <= 4)
         hipLaunchKernelGGL((k_gram_strip<R, 4>), grid, dim3(64), (128 * sk_ring_ys<R, 4>() * sizeof(R)), st, a);
     else if (a.dpad <= 8)
