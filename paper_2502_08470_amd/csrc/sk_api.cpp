@@ -385,15 +385,20 @@ constexpr size_t kGramPairLds = 64 << 10;
 template <typename R>
 hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int max_lx,
                        int max_ly, bool direct, hipStream_t st) {
+    // a strip's skewed rows: Tp = max(ly, min(lx, 64)), the last strip up to 127 more
+    const int rows = std::max(max_ly << ga.lam, SK_LANES) + 2 * SK_LANES;
+    const int strips = ((max_lx << ga.lam) + SK_LANES - 1) / SK_LANES;
     if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX) {
         if (SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
             return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
-        // a strip's skewed rows: Tp = max(ly, min(lx, 64)), the last strip up to 127 more
-        const int rows = std::max(max_ly << ga.lam, SK_LANES) + 2 * SK_LANES;
-        return SkLaunch<R>::gram_strip(ga, ((max_lx << ga.lam) + SK_LANES - 1) / SK_LANES, rows, P, st);
+        return SkLaunch<R>::gram_strip(ga, strips, rows, P, st);
     }
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
+#ifndef SK_EXP_SKEW
+    if (SkLaunch<R>::gram_band_lds(ga.dpad) <= kGramPairLds)
+        return SkLaunch<R>::gram_band(ga, strips, rows, P, st);
+#endif
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
 }
 

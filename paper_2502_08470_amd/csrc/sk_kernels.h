@@ -225,6 +225,101 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     }
 }
 
+// Strip-band variant: one workgroup (4 waves) per (pair, strip s, segment z
+// of rseg rows, a multiple of 64) computes the strip's 64 x ly band of C one
+// 64-column tile at a time and writes the skewed rows s Tp + t of the
+// segment.  At lane r, row t needs virtual column v = t - r (column v of
+// strip s, or column Tp + v of strip s-1 when v < 0), which lies in the
+// current tile or the previous one; both stay in LDS.  Every increment is
+// loaded once per workgroup and every tile element computed once (the
+// 64-row block kernel reloads 128 y columns and computes a 64 x 128 tile for
+// every 64 rows).  Same tiles and MFMA order as k_gram_skew, so both give
+// identical constants.
+template <typename R, bool SPLIT>
+__global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int s = blockIdx.y;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0 || s >= g.nstrips) return;
+    const int Tstrip = (s == g.nstrips - 1) ? g.nsteps_pad - s * g.Tp : g.Tp;
+    const int tbeg = (int)blockIdx.z * a.rseg;
+    if (tbeg >= Tstrip) return;
+    const int tend = tbeg + a.rseg < Tstrip ? tbeg + a.rseg : Tstrip;
+    const int dp = a.dpad;
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    R* Xs = reinterpret_cast<R*>(sk_smem);  // [64][dp]
+    R* Ys = Xs + 64 * dp;                    // [64][dp]
+    R* Tt = Ys + 64 * dp;                    // [2][64][66]: tiles by parity
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
+    const R rscale = (R)1 / (R)(1 << a.lam);
+    auto stage_x = [&](int strip) {  // rows 64 strip .. + 63 (refined: segment i >> lam)
+        for (int e = tid; e < 64 * dp; e += 256) {
+            const int rr = e / dp, k = e - rr * dp, ir = strip * 64 + rr;
+            R v = (R)0;
+            if (ir >= 0 && ir < g.lx && k < a.d) {
+                const int i = ir >> a.lam;
+                v = (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale;
+            }
+            Xs[e] = v;
+        }
+    };
+    auto stage_y = [&](int c0) {  // virtual columns c0 .. c0 + 63
+        for (int e = tid; e < 64 * dp; e += 256) {
+            const int cc = e / dp, k = e - cc * dp, vv = c0 + cc;
+            const int col = vv >= 0 ? vv : g.Tp + vv;
+            R v = (R)0;
+            if (k < a.d && (vv >= 0 || s > 0) && col >= 0 && col < g.ly) {
+                const int j = col >> a.lam;
+                v = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
+            }
+            Ys[e] = v;
+        }
+    };
+    auto tile = [&](R* T) {  // T[r][c] = sum_k Xs[r][k] Ys[c][k]; wave w: rows 16w .. 16w+15
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const auto acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * dp, true,
+                                                    Ys + (16 * ni + (lane & 15)) * dp, true, dp, lane);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                T[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];
+        }
+    };
+    const int k0 = tbeg / 64;
+    // the tile of virtual columns 64 (k0-1) .. 64 k0 - 1 (k0 = 0: strip s-1's
+    // last 64 columns, rows of strip s-1)
+    stage_x(k0 == 0 ? s - 1 : s);
+    stage_y(64 * (k0 - 1));
+    __syncthreads();
+    tile(Tt + ((k0 - 1) & 1) * 64 * 66);
+    if (k0 == 0) {
+        __syncthreads();
+        stage_x(s);
+    }
+    R* out = a.cskew + pd.c_off + (int64_t)s * g.Tp * 64;
+    for (int k = k0; 64 * k < tend; ++k) {
+        __syncthreads();  // the previous rows are written: Ys and the older tile are free
+        stage_y(64 * k);
+        __syncthreads();
+        R* Tc = Tt + (k & 1) * 64 * 66;
+        const R* Tq = Tt + ((k - 1) & 1) * 64 * 66;
+        tile(Tc);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = tid + 256 * q, t = 64 * k + (e >> 6), r = e & 63;
+            if (t < tend) {
+                const int c = t - r - 64 * k;
+                out[(int64_t)t * 64 + r] = c >= 0 ? Tc[r * 66 + c] : Tq[r * 66 + c + 64];
+            }
+        }
+    }
+}
+
 // Direct variant for small d (native precision): one workgroup (4 waves) per
 // pair stages the pair's increments in LDS once, then each wave writes a
 // contiguous quarter of the skewed rows; lane r of row tau computes its own
@@ -1377,10 +1472,12 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
 
 // Two entry points of the same body: where the register footprint allows it,
 // the compiler is asked to fit two waves per SIMD (the adjoint is latency
-// bound at one); elsewhere forcing it would spill to scratch.
+// bound at one); elsewhere forcing it would spill to scratch.  The FP32
+// exchange variant for N = 8 (approximation) spills 6 registers at two waves
+// and is still faster (1024 x 1024 d = 32 Gram, 32 rows: 1021 -> 647 ms).
 template <typename R, int N, int TMAX, bool GX>
 constexpr bool sk_adj_two_waves() {
-    return sizeof(R) == 4 ? (GX ? (TMAX == 0 && N <= 6) : (TMAX == 0 || N <= 6))
+    return sizeof(R) == 4 ? (GX ? TMAX == 0 : (TMAX == 0 || N <= 6))
                           : (TMAX == 0 && N <= 6 && !GX);
 }
 

@@ -27,6 +27,10 @@ struct SkLaunch {
     // direct (VALU) Gram for dpad <= SK_GRAM_DIRECT_DMAX, native precision
     static hipError_t gram_direct(const GramArgs<R>& a, int max_lx, int max_ly, int64_t npairs,
                                   hipStream_t st);
+    // MFMA tiles of a strip's 64 x ly band, one workgroup per (pair, strip,
+    // row segment); max_strips and max_rows as for gram_strip
+    static hipError_t gram_band(const GramArgs<R>& a, int max_strips, int max_rows,
+                                int64_t npairs, hipStream_t st);
     // the same arithmetic, one wave per (pair, strip, row segment), for pairs
     // whose increments exceed the LDS of one workgroup; max_strips and
     // max_rows (skewed rows of the longest strip) of the refined grids
@@ -70,6 +74,7 @@ struct SkLaunch {
                (size_t)ring * sk_ring_col_bytes_adj(N, (int)sizeof(R));
     }
     static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
+    static size_t gram_band_lds(int dpad) { return (size_t)(128 * dpad + 2 * 64 * 66) * sizeof(R); }
     static size_t gram_pair_lds(int dpad, int max_lx, int max_ly) {
         return ((size_t)64 * 66 + (size_t)(max_lx + max_ly) * dpad) * sizeof(R);
     }

@@ -77,6 +77,32 @@ hipError_t SkLaunch<R>::gram_direct(const GramArgs<R>& a, int max_lx, int max_ly
 }
 
 template <typename R>
+hipError_t SkLaunch<R>::gram_band(const GramArgs<R>& a0, int max_strips, int max_rows,
+                                  int64_t npairs, hipStream_t st) {
+    if (npairs <= 0 || max_strips <= 0 || max_rows <= 0) return hipSuccess;
+    // split each strip's rows so that the launch has about 2048 workgroups,
+    // segments of at least 256 rows (a multiple of 64)
+    const int64_t wgs = npairs * (int64_t)max_strips;
+    int64_t nseg = wgs >= 2048 ? 1 : (2048 + wgs - 1) / wgs;
+    nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, max_rows / 256));
+    GramArgs<R> a = a0;
+    a.rseg = (int)(((max_rows + nseg - 1) / nseg + 63) / 64 * 64);
+    nseg = (max_rows + a.rseg - 1) / a.rseg;
+    const dim3 grid((unsigned)npairs, (unsigned)max_strips, (unsigned)nseg);
+    const size_t lds = gram_band_lds(a.dpad);
+    if (a.split) {
+        if constexpr (sizeof(R) == 4)
+            hipLaunchKernelGGL((k_gram_band<R, true>), grid, dim3(256), lds, st, a);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_gram_band<R, false>), grid, dim3(256), lds, st, a);
+    }
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
 hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int max_rows,
                                    int64_t npairs, hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0 || max_rows <= 0) return hipSuccess;

@@ -36,7 +36,8 @@ def dev(a, dtype):
 # first two shapes), or one wave per strip with the y increments in an LDS
 # ring (the last two, whose increments exceed the LDS budget; the last has a
 # strip period above ly); MFMA for d > 16.  mfma / bf16x3: the pair-resident
-# MFMA kernel, and for the last two shapes the 64-row block kernel
+# MFMA kernel, and for the last two shapes the strip-band MFMA kernel (FP32)
+# or the 64-row block kernel (FP64, whose band tiles exceed the LDS budget)
 @pytest.mark.parametrize("dtype,mode", [(torch.float64, "native"), (torch.float32, "native"),
                                         (torch.float64, "mfma"), (torch.float32, "mfma"),
                                         (torch.float32, "bf16x3")])
