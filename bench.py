@@ -242,7 +242,8 @@ def workload_study(large_rows: int = 256) -> int:
     * the MMD sets: unbiased MMD^2 (approximation N=8, FP32) forward and
       backward through autograd (three Grams, XX and YY symmetric);
     * the first `large_rows` rows of the 1024x1024 d=32 Gram (approximation
-      N=8, FP32 sweep, BF16 3-way split Gram, exponents), forward."""
+      N=8, FP32 sweep, BF16 3-way split Gram, exponents), forward, and the
+      first 16 rows forward + backward."""
     import torch
     import paper_2502_08470_amd as sk
     import workloads as W
@@ -329,6 +330,23 @@ def workload_study(large_rows: int = 256) -> int:
                                "forward_cells_per_s": cells / ms * 1e3,
                                "full_gram_forward_s_at_this_rate": 1024 * 1024 * 1024.0 ** 2 / (cells / ms * 1e3)}
     say("large Gram block done")
+    # forward + backward of a smaller block (the backward recomputes the
+    # forward with checkpoints under the default 160 GiB chunk cap); the seed
+    # 2^-E K makes the loss the sum of the kernel values' mantissas
+    bw_rows = 16
+    Xb = Xt[:bw_rows].contiguous()
+    del Xt
+    torch.cuda.empty_cache()
+    cells = float(Xb.shape[0] * Yt.shape[0] * (Xb.shape[1] - 1) * (Yt.shape[1] - 1))
+
+    def large_fb():
+        K, E = sk.gram(Xb, Yt, "approx", 8, return_exp=True, gram_mode="bf16x3")
+        sk.gram_backward(Xb, Yt, torch.ones_like(K), "approx", 8, gK_exp=-E, gram_mode="bf16x3")
+
+    ms = best_ms(large_fb, 1)
+    out["large_gram_block_fwd_bwd"] = {"rows": bw_rows, "cells": cells, "fwd_bwd_ms": ms,
+                                       "fwd_bwd_cells_per_s": cells / ms * 1e3}
+    say("large Gram block forward + backward done")
     print(json.dumps({"study": "named workloads, one MI355X", "workloads": out}), flush=True)
     return 0
 

@@ -1809,8 +1809,9 @@ struct ContractArgs {
     R* dyp;   // [pair][strip][ly][d]
 };
 
-// One wave per (pair, strip): lane r accumulates dL/d(dx_i) for its row
-// i = 64 s + r in registers.  dL/d(dy_j) for the strip is a sum down the
+// One wave per (pair, strip, 16-dimension slice): lane r accumulates
+// dL/d(dx_i) over the slice's dimensions for its row i = 64 s + r in
+// registers (slices keep the register count at four waves per SIMD).  dL/d(dy_j) for the strip is a sum down the
 // column j, whose cells lanes r = 0..63 visit at consecutive steps; the
 // partial sum therefore travels with the wavefront (lane r-1 -> lane r, one
 // DPP move per step) and the strip's last row writes it out.  The y
@@ -1830,10 +1831,12 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     constexpr int NV = (8 * DMAX + 63) / 64;  // ring values per lane per 8 columns
     extern __shared__ __align__(16) unsigned char sk_smem[];
     R* ring = reinterpret_cast<R*>(sk_smem);  // [128][YS]
-    const int64_t d = a.d;
+    const int64_t k0 = (int64_t)blockIdx.z * DMAX;  // first dimension of the slice
+    const int64_t d = a.d - k0 < DMAX ? a.d - k0 : DMAX;  // dimensions of the slice
+    const int64_t ld = a.d;
     const int ly = g.ly;
-    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
-    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
+    const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * ld + k0;
+    const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * ld + k0;
     const R* gsk = a.gskew + pd.c_off + (int64_t)s * g.Tp * 64;
     const int i = s * 64 + r;
     const bool rowok = i < g.lx;
@@ -1845,7 +1848,7 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
         xi[k] = (R)0;
         accx[k] = (R)0;
         accy[k] = (R)0;
-        if (k < d && rowok) xi[k] = X[(int64_t)(i + 1) * d + k] - X[(int64_t)i * d + k];
+        if (k < d && rowok) xi[k] = X[(int64_t)(i + 1) * ld + k] - X[(int64_t)i * ld + k];
     }
     // y increments of the 8 columns from c0: value w is column c0 + w / DMAX, dimension w % DMAX
     R yv[NV];
@@ -1855,7 +1858,7 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
             const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX, c = c0 + m;
             yv[h] = (R)0;
             if (w < 8 * DMAX && k < d && c < ly)
-                yv[h] = Y[(int64_t)(c + 1) * d + k] - Y[(int64_t)c * d + k];
+                yv[h] = Y[(int64_t)(c + 1) * ld + k] - Y[(int64_t)c * ld + k];
         }
     };
     auto store_y = [&](int c0) {
@@ -1897,7 +1900,7 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
                 accy[k] = fma(gv, xi[k], accy[k]);
             }
             if (ok && r == last_r) {
-                R* dyo = a.dyp + pd.dy_off + ((int64_t)s * ly + j) * d;
+                R* dyo = a.dyp + pd.dy_off + ((int64_t)s * ly + j) * ld + k0;
 #pragma unroll
                 for (int k = 0; k < DMAX; ++k)
                     if (k < d) dyo[k] = accy[k];
@@ -1912,7 +1915,7 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     if (rowok) {
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
-            if (k < d) a.dxp[pd.dx_off + (int64_t)i * d + k] = accx[k];
+            if (k < d) a.dxp[pd.dx_off + (int64_t)i * ld + k0 + k] = accx[k];
     }
 }
 

@@ -301,12 +301,11 @@ template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    dim3 grid((unsigned)npairs, max_strips);
+    // d > 16: slices of 16 dimensions on separate waves
+    dim3 grid((unsigned)npairs, max_strips, (unsigned)((a.d + 15) / 16));
     if (a.d <= 4) sk_contract_d<R, 4>(a, grid, st);
     else if (a.d <= 8) sk_contract_d<R, 8>(a, grid, st);
-    else if (a.d <= 16) sk_contract_d<R, 16>(a, grid, st);
-    else if (a.d <= 32) sk_contract_d<R, 32>(a, grid, st);
-    else sk_contract_d<R, 64>(a, grid, st);
+    else sk_contract_d<R, 16>(a, grid, st);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }

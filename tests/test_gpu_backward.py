@@ -85,6 +85,24 @@ def test_multi_strip_gradient_matches_finite_differences(sk, dtype, tol, scheme,
         assert abs(got - fd) <= tol * scale, (which, idx, got, fd)
 
 
+def test_wide_dimension_gradient_matches_finite_differences(sk):
+    # d = 37: the contraction runs three 16-dimension slices (the last of 5)
+    log_banner("wide-dimension gradient")
+    rng = np.random.default_rng(22)
+    X = bm_paths(rng, 2, 100, 37, 0.2 / np.sqrt(100))
+    Y = bm_paths(rng, 1, 80, 37, 0.2 / np.sqrt(80))
+    gK = rng.normal(size=(2, 1))
+    gX, gY = sk.gram_backward(dev(X, torch.float64), dev(Y, torch.float64),
+                              dev(gK, torch.float64), "approx", 5)
+    gX, gY = gX.cpu().numpy(), gY.cpu().numpy()
+    scale = max(np.abs(gX).max(), np.abs(gY).max())
+    for which, idx in [("x", (0, 0, 0)), ("x", (1, 64, 15)), ("x", (0, 99, 16)), ("x", (1, 100, 36)),
+                       ("y", (0, 0, 31)), ("y", (0, 40, 32)), ("y", (0, 80, 36))]:
+        fd = fd_gram_grad(X, Y, gK, "approx", 5, idx, which)
+        got = gX[idx] if which == "x" else gY[idx]
+        assert abs(got - fd) <= 1e-6 * scale, (which, idx, got, fd)
+
+
 def test_gradient_seed_exponent(sk):
     rng = np.random.default_rng(4)
     X = dev(bm_paths(rng, 2, 70, 3, 0.05), torch.float64)
