@@ -395,10 +395,8 @@ hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int
     }
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
-#ifndef SK_EXP_SKEW
     if (SkLaunch<R>::gram_band_lds(ga.dpad) <= kGramPairLds)
         return SkLaunch<R>::gram_band(ga, strips, rows, P, st);
-#endif
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
 }
 

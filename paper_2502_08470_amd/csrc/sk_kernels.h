@@ -139,11 +139,11 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
     const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
     const int b = blockIdx.y;
     if (64 * b >= g.nsteps_pad) return;
-    const int dp = a.dpad;
+    const int dp = a.dpad, ds = dp + 1;  // odd row stride: the 16 rows a tile reads hit distinct banks
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    R* Xs = reinterpret_cast<R*>(sk_smem);          // [64][dp]
-    R* Ys = Xs + 64 * dp;                            // [128][dp]
-    R* Tt = Ys + 128 * dp;                           // [64][66]: diagonal reads conflict-free
+    R* Xs = reinterpret_cast<R*>(sk_smem);          // [64][ds]
+    R* Ys = Xs + 64 * ds;                            // [128][ds]
+    R* Tt = Ys + 128 * ds;                           // [64][66]: diagonal reads conflict-free
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
                 int i = ir >> a.lam;
                 v = (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale;
             }
-            Xs[e] = v;
+            Xs[rr * ds + k] = v;
         }
         for (int e = tid; e < 128 * dp; e += 256) {
             int cc = e / dp, k = e - cc * dp;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
                 int j = jr >> a.lam;
                 v = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
             }
-            Ys[e] = v;
+            Ys[cc * ds + k] = v;
         }
         for (int h = 0; h < 2; ++h) {
             __syncthreads();
@@ -191,8 +191,8 @@ __global__ __launch_bounds__(256) void k_gram_skew(const GramArgs<R> a) {
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni) {
                 const int col0 = 64 * h + 16 * ni;
-                const acc_t acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * dp, true,
-                                                         Ys + (col0 + (lane & 15)) * dp, true, dp,
+                const acc_t acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * ds, true,
+                                                         Ys + (col0 + (lane & 15)) * ds, true, dp,
                                                          lane);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
@@ -248,11 +248,11 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
     const int tbeg = (int)blockIdx.z * a.rseg;
     if (tbeg >= Tstrip) return;
     const int tend = tbeg + a.rseg < Tstrip ? tbeg + a.rseg : Tstrip;
-    const int dp = a.dpad;
+    const int dp = a.dpad, ds = dp + 1;  // odd row stride: the 16 rows a tile reads hit distinct banks
     extern __shared__ __align__(16) unsigned char sk_smem[];
-    R* Xs = reinterpret_cast<R*>(sk_smem);  // [64][dp]
-    R* Ys = Xs + 64 * dp;                    // [64][dp]
-    R* Tt = Ys + 64 * dp;                    // [2][64][66]: tiles by parity
+    R* Xs = reinterpret_cast<R*>(sk_smem);  // [64][ds]
+    R* Ys = Xs + 64 * ds;                    // [64][ds]
+    R* Tt = Ys + 64 * ds;                    // [2][64][66]: tiles by parity
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
                 const int i = ir >> a.lam;
                 v = (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale;
             }
-            Xs[e] = v;
+            Xs[rr * ds + k] = v;
         }
     };
     auto stage_y = [&](int c0) {  // virtual columns c0 .. c0 + 63
@@ -276,14 +276,14 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
                 const int j = col >> a.lam;
                 v = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
             }
-            Ys[e] = v;
+            Ys[cc * ds + k] = v;
         }
     };
     auto tile = [&](R* T) {  // T[r][c] = sum_k Xs[r][k] Ys[c][k]; wave w: rows 16w .. 16w+15
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
-            const auto acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * dp, true,
-                                                    Ys + (16 * ni + (lane & 15)) * dp, true, dp, lane);
+            const auto acc = sk_gram_tile<R, SPLIT>(Xs + (16 * wave + (lane & 15)) * ds, true,
+                                                    Ys + (16 * ni + (lane & 15)) * ds, true, dp, lane);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 T[(16 * wave + SkMfma<R>::row(lane, v)) * 66 + 16 * ni + (lane & 15)] = acc[v];
@@ -520,21 +520,21 @@ __global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
     if (g.nsteps == 0) return;
-    const int dp = a.dpad;
+    const int dp = a.dpad, ds = dp + 1;  // odd row stride: the 16 rows a tile reads hit distinct banks
     extern __shared__ __align__(16) unsigned char sk_smem[];
     R* Tt = reinterpret_cast<R*>(sk_smem);  // [64][66]
-    R* Xs = Tt + 64 * 66;                    // [lx][dp]
-    R* Ys = Xs + (size_t)pd.lx * dp;         // [ly][dp]
+    R* Xs = Tt + 64 * 66;                    // [lx][ds]
+    R* Ys = Xs + (size_t)pd.lx * ds;         // [ly][ds]
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * a.d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * a.d;
     const R rscale = (R)1 / (R)(1 << a.lam);
     for (int e = tid; e < pd.lx * dp; e += 256) {
         const int i = e / dp, k = e - i * dp;
-        Xs[e] = k < a.d ? (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale : (R)0;
+        Xs[i * ds + k] = k < a.d ? (X[(int64_t)(i + 1) * a.d + k] - X[(int64_t)i * a.d + k]) * rscale : (R)0;
     }
     for (int e = tid; e < pd.ly * dp; e += 256) {
         const int j = e / dp, k = e - j * dp;
-        Ys[e] = k < a.d ? (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale : (R)0;
+        Ys[j * ds + k] = k < a.d ? (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale : (R)0;
     }
     typedef typename SkMfma<R>::acc_t acc_t;
     const int nblk = g.nsteps_pad / 64;
@@ -555,14 +555,14 @@ __global__ __launch_bounds__(256) void k_gram_pair(const GramArgs<R> a) {
             const int jb = Lmin - s * g.Tp;
             const int ir = s * 64 + 16 * wave + (lane & 15);
             const bool rok = ir < g.lx;
-            const R* xrow = Xs + (size_t)(ir >> a.lam) * dp;
+            const R* xrow = Xs + (size_t)(ir >> a.lam) * ds;
             for (int h = 0; h < 2; ++h) {
                 __syncthreads();  // staging done / previous tile consumed
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) {
                     const int jr = jb + 64 * h + 16 * ni + (lane & 15);
                     const bool cok = jr >= 0 && jr < g.ly;
-                    const R* yrow = Ys + (size_t)(cok ? (jr >> a.lam) : 0) * dp;
+                    const R* yrow = Ys + (size_t)(cok ? (jr >> a.lam) : 0) * ds;
                     const acc_t acc = sk_gram_tile<R, SPLIT>(xrow, rok, yrow, cok, dp, lane);
 #pragma unroll
                     for (int v = 0; v < 4; ++v)

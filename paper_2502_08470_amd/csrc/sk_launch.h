@@ -73,10 +73,10 @@ struct SkLaunch {
         return (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)) +
                (size_t)ring * sk_ring_col_bytes_adj(N, (int)sizeof(R));
     }
-    static size_t gram_lds(int dpad) { return (size_t)(192 * dpad + 64 * 66) * sizeof(R); }
-    static size_t gram_band_lds(int dpad) { return (size_t)(128 * dpad + 2 * 64 * 66) * sizeof(R); }
+    static size_t gram_lds(int dpad) { return (size_t)(192 * (dpad + 1) + 64 * 66) * sizeof(R); }
+    static size_t gram_band_lds(int dpad) { return (size_t)(128 * (dpad + 1) + 2 * 64 * 66) * sizeof(R); }
     static size_t gram_pair_lds(int dpad, int max_lx, int max_ly) {
-        return ((size_t)64 * 66 + (size_t)(max_lx + max_ly) * dpad) * sizeof(R);
+        return ((size_t)64 * 66 + (size_t)(max_lx + max_ly) * (dpad + 1)) * sizeof(R);
     }
     static size_t gram_direct_lds(int dpad, int max_lx, int max_ly) {
         return ((size_t)max_lx * dpad + (size_t)max_ly * (dpad + SkGramDirectPad<R>::value)) *
