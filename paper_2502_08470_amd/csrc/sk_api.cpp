@@ -378,8 +378,10 @@ hipError_t lds_limit(size_t* out) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
-// LDS budget under which the increment Gram keeps a whole pair's increments
-// resident (one workgroup per pair); longer pairs use 64-row blocks.
+// LDS budget of the increment Gram kernels: a whole pair's increments
+// resident in one workgroup (direct FMA chain for d <= 16 in the path dtype,
+// else MFMA), else one wave per strip (FMA chain) or one workgroup per strip
+// band (MFMA), else 64-row blocks.
 constexpr size_t kGramPairLds = 64 << 10;
 
 template <typename R>
@@ -461,7 +463,7 @@ int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
 }
 
 template <typename R>
-int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P, int max_ly,
+int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P,
                  int max_strips, char* ws, const Layout& L, hipStream_t st);
 
 // Backward of a chunk of strip-pipeline pairs: increment Gram, the pipelined
@@ -508,7 +510,7 @@ int run_chunk_backward_pipe(const sk_params& p, const R* X, const R* Y, int64_t 
     aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs;
     SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
               "pipelined adjoint sweep");
-    return run_contract<R>(X, Y, d, src, P, max_ly, max_strips, ws, L, st);
+    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
 }
 
 template <typename R>
@@ -627,7 +629,7 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
 
 // dL/dc (skewed) -> per-pair partials dL/d(dx), dL/d(dy).
 template <typename R>
-int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P, int max_ly,
+int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P,
                  int max_strips, char* ws, const Layout& L, hipStream_t st) {
     ContractArgs<R> ca;
     ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = reinterpret_cast<const R*>(ws + L.gskew);
@@ -657,7 +659,7 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.gx_cols = gx_cols_adj(p);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, ring,
                                                   max_ly > aa.gx_cols, st), "adjoint sweep");
-    return run_contract<R>(X, Y, d, src, P, max_ly, max_strips, ws, L, st);
+    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
 }
 
 template <typename R>
