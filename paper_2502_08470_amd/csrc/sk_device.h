@@ -166,7 +166,10 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // Tkept (nullable): receives the number of tail rows folded (wave-uniform).
 // FIXT: fold exactly Tfix tail rows (wave-uniform) instead of deciding, so that
 // a replay repeats the decisions of the forward it replays.
-template <typename R, int N, int TMAX, bool WD = false, bool HI = true, bool FIXT = false>
+// DS: element stride of DP and DQ (1 for registers; 64 for an LDS array with
+// one slot per lane).
+template <typename R, int N, int TMAX, bool WD = false, bool HI = true, bool FIXT = false,
+          int DS = 1>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
                                             double P1, double Q0, double Q1, R c, bool active,
                                             const SkTab<R>& tab, R (&Po)[N + 1], R (&Qo)[N + 1],
@@ -194,8 +197,8 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         // with the tail length given reads exactly the rows it folds)
 #pragma unroll
         for (int r = N; r < M; ++r) {
-            DP[r] = (R)0;
-            DQ[r] = (R)0;
+            DP[r * DS] = (R)0;
+            DQ[r * DS] = (R)0;
         }
     }
     if (Tkept) *Tkept = 0;
@@ -260,8 +263,8 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         Qo[r] = fma(cp[r], hp, tq);
         if (WD) {
             const R rc = (R)r * cp[r - 1];
-            DP[r - 1] = fma(rc, hq, tpp);
-            DQ[r - 1] = fma(rc, hp, tqp);
+            DP[(r - 1) * DS] = fma(rc, hq, tpp);
+            DQ[(r - 1) * DS] = fma(rc, hp, tqp);
             tpp = tp;
             tqp = tq;
         }
@@ -296,8 +299,8 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
             }
             if (WD) {
                 const R rc = (R)r * cp[r - 1];
-                DP[r - 1] = fma(rc, hq, tpp);
-                DQ[r - 1] = fma(rc, hp, tqp);
+                DP[(r - 1) * DS] = fma(rc, hq, tpp);
+                DQ[(r - 1) * DS] = fma(rc, hp, tqp);
                 tpp = tp;
                 tqp = tq;
             }
@@ -344,7 +347,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
 // order, so no per-row arrays stay live:
 //   aP_k += w_{r-k} ea_r (k <= min(r, N)),  aP_k += c^r eb_r / (r+k)! (k >= 1),
 // with ea_r = a_r for r <= N and ea_r = sum_n Rs[n][r] a_n for tail rows.
-template <typename R, int N, int TMAX>
+template <typename R, int N, int TMAX, int DS = 1>
 __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, const R (&a)[N + 1],
                                             const R (&b)[N + 1], const R* DP, const R* DQ,
                                             R (&aP)[N + 1], R (&aQ)[N + 1], R& g) {
@@ -387,8 +390,8 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
                 eb = fma(tab.rs[n][r - N - 1], b[n], eb);
             }
         }
-        gacc = r == 1 ? ea * DP[0] : fma(ea, DP[r - 1], gacc);
-        gacc = fma(eb, DQ[r - 1], gacc);
+        gacc = r == 1 ? ea * DP[0] : fma(ea, DP[(r - 1) * DS], gacc);
+        gacc = fma(eb, DQ[(r - 1) * DS], gacc);
 #pragma unroll
         for (int k = (r < N ? r : N); k >= 0; --k) {
             aP[k] = fma(w[r - k], ea, aP[k]);

@@ -1529,6 +1529,14 @@ struct AdjPipeArgs {
     int64_t njobs;
 };
 
+// LDS of the pipelined adjoint: the exchange staging slot, then the
+// segment's row derivatives [P/Q][S][N + TMAX][64 lanes] (in LDS rather than
+// registers, which leaves room for two waves per SIMD without spilling).
+template <typename R>
+__host__ __device__ constexpr int sk_adj_pipe_lds(int N, int TMAX, int S) {
+    return sk_gx_stage_bytes(N, (int)sizeof(R)) + 2 * S * (N + TMAX) * 64 * (int)sizeof(R);
+}
+
 template <typename R, int N, int TMAX, int S>
 __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     const int r = threadIdx.x;
@@ -1536,6 +1544,9 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     constexpr int XR = (8 * GXW + 63) / 64, M = N + TMAX, RW = (N + 1) * (ES / 4) + 1;
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
+    R* dlds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES)) + r;  // [2][S][M][64], this lane's slot
+    auto DPu = [&](int u) { return dlds + (0 * S + u) * M * 64; };
+    auto DQu = [&](int u) { return dlds + (1 * S + u) * M * 64; };
     for (int64_t q = blockIdx.x; q < a.njobs; q += gridDim.x) {
         const int2 jb = a.jobs[q];
         const SkPairDesc pd = a.desc[jb.x];
@@ -1615,7 +1626,6 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             for (int u = 0; u < S; ++u)
                 cseg[u] = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
             // ---- replay the segment's forward from the checkpoint
-            R Dp[S][M], Dq[S][M];
             int Tst[S], Est[S], jst[S];
             bool lv[S];
             const R* ck = ckb + (int64_t)kk * 2 * (N + 1) * 64;
@@ -1678,9 +1688,9 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                 R Po[N + 1], Qo[N + 1];
                 double Po0, Po1, Qo0, Qo1;
                 Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
-                sk_cell_fwd<R, N, TMAX, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
-                                                           a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
-                                                           Dq[u], nullptr, Tst[u]);
+                sk_cell_fwd<R, N, TMAX, true, false, true, 64>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u],
+                                                               live, a.tab, Po, Qo, Po0, Po1, Qo0, Qo1,
+                                                               DPu(u), DQu(u), nullptr, Tst[u]);
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
                     P[n] = Po[n];
@@ -1733,7 +1743,7 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                     }
                 }
                 R gv;
-                sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
+                sk_cell_adj<R, N, TMAX, 64>(cseg[u], Tst[u], a.tab, ap, aq, DPu(u), DQu(u), lp, lqs, gv);
                 El = Ec;
                 Els = Ec;
                 if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
