@@ -1794,14 +1794,12 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     }
 }
 
+// With the row derivatives in LDS every order fits two waves per SIMD
+// without spilling (at most 245 registers, FP64 N = 8 interpolation), and
+// the derivatives' LDS allows no more.
 template <typename R, int N, int TMAX, int S>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
-void k_adjoint_pipe_w2(const AdjPipeArgs<R> a) {
-    sk_adjoint_pipe_body<R, N, TMAX, S>(a);
-}
-
-template <typename R, int N, int TMAX, int S>
-__global__ __launch_bounds__(64) void k_adjoint_pipe(const AdjPipeArgs<R> a) {
+void k_adjoint_pipe(const AdjPipeArgs<R> a) {
     sk_adjoint_pipe_body<R, N, TMAX, S>(a);
 }
 

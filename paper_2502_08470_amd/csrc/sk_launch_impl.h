@@ -212,21 +212,10 @@ hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, boo
     }
 }
 
-// Two waves per SIMD for the pipelined adjoint where half the register file
-// holds it (with its row derivatives in LDS: FP32 up to N = 8, FP64 N <= 6
-// approximation or N <= 4 interpolation); the LDS of the derivative rows
-// (16 KiB for FP32 N = 8) caps it at two waves in any case.
-template <typename R, int N, int TMAX>
-constexpr bool sk_adj_pipe_two_waves() {
-    return sizeof(R) == 4 ? (TMAX == 0 || N <= 6) : (TMAX == 0 ? N <= 6 : N <= 4);
-}
-
 template <typename R, int N, int TMAX>
 static hipError_t sk_adj_pipe_n(const AdjPipeArgs<R>& a, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
-    const void* kern = sk_adj_pipe_two_waves<R, N, TMAX>()
-                           ? reinterpret_cast<const void*>(&k_adjoint_pipe_w2<R, N, TMAX, S>)
-                           : reinterpret_cast<const void*>(&k_adjoint_pipe<R, N, TMAX, S>);
+    const void* kern = reinterpret_cast<const void*>(&k_adjoint_pipe<R, N, TMAX, S>);
     return sk_coop_launch(kern, a, a.njobs, (size_t)sk_adj_pipe_lds<R>(N, TMAX, S), st);
 }
 
