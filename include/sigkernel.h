@@ -242,6 +242,24 @@ int sigkernel_plan_backward(const sk_plan* plan, const void* Xcat, const void* Y
                             size_t ws_bytes, hipStream_t stream);
 int sigkernel_plan_tune(sk_plan* plan, const void* Xcat, const void* Ycat, void* ws,
                         size_t ws_bytes, hipStream_t stream, double* best_ms);
+/*
+ * Saved-state forward and backward of a backward plan whose backward runs in
+ * one chunk (SK_EWORKSPACE otherwise; sigkernel_plan_config's `launches`
+ * counts forward chunks, the backward's chunking follows the same workspace).
+ * sigkernel_plan_forward_save computes k (and k_exp) as
+ * sigkernel_plan_forward does, through the backward's checkpoint sweep, and
+ * leaves the backward's state (cell constants, checkpoints, strip-boundary
+ * edges) in the plan's workspace; sigkernel_plan_backward_saved then computes
+ * gX, gY exactly as sigkernel_plan_backward would, without recomputing that
+ * state.  Between the two calls the workspace must not be used by any other
+ * call of this plan (a forward, backward or tune overwrites the state, and
+ * the backward then reads the newer state).  Both only queue kernels.
+ */
+int sigkernel_plan_forward_save(const sk_plan* plan, const void* Xcat, const void* Ycat, void* k,
+                                int32_t* k_exp, void* ws, size_t ws_bytes, hipStream_t stream);
+int sigkernel_plan_backward_saved(const sk_plan* plan, const void* Xcat, const void* Ycat,
+                                  const void* gk, const int32_t* gk_exp, void* gX, void* gY,
+                                  void* ws, size_t ws_bytes, hipStream_t stream);
 int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, int32_t* buckets,
                           int32_t* pipeline, int64_t* launches);
 int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,

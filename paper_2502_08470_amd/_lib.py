@@ -38,6 +38,8 @@ EXPORTS = (
     "sigkernel_plan_upload",
     "sigkernel_plan_forward",
     "sigkernel_plan_backward",
+    "sigkernel_plan_forward_save",
+    "sigkernel_plan_backward_saved",
     "sigkernel_plan_tune",
     "sigkernel_plan_config",
     "sigkernel_plan_configure",
@@ -104,6 +106,10 @@ def lib():
     L.sigkernel_plan_forward.restype = ctypes.c_int
     L.sigkernel_plan_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sigkernel_plan_backward.restype = ctypes.c_int
+    L.sigkernel_plan_forward_save.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sigkernel_plan_forward_save.restype = ctypes.c_int
+    L.sigkernel_plan_backward_saved.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sigkernel_plan_backward_saved.restype = ctypes.c_int
     L.sigkernel_plan_tune.argtypes = [vp, vp, vp, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
     L.sigkernel_plan_tune.restype = ctypes.c_int
     L.sigkernel_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),

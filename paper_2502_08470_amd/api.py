@@ -338,6 +338,24 @@ class PairsPlan:
                                                   _stream(Xcat)))
         return gX, gY
 
+    def forward_save(self, Xcat: torch.Tensor, Ycat: torch.Tensor, k: torch.Tensor,
+                     k_exp: Optional[torch.Tensor] = None):
+        """Forward that keeps the backward's state in the plan's workspace
+        (backward plans whose backward is one chunk); :meth:`backward_saved`
+        then starts from it.  No other call of this plan may come between."""
+        L.check(self._lib.sigkernel_plan_forward_save(self._h, _ptr(Xcat), _ptr(Ycat), _ptr(k),
+                                                      _ptr(k_exp), _ptr(self.ws), self.ws.numel(),
+                                                      _stream(Xcat)))
+        return k
+
+    def backward_saved(self, Xcat: torch.Tensor, Ycat: torch.Tensor, gk: torch.Tensor,
+                       gX: torch.Tensor, gY: torch.Tensor, gk_exp: Optional[torch.Tensor] = None):
+        L.check(self._lib.sigkernel_plan_backward_saved(self._h, _ptr(Xcat), _ptr(Ycat), _ptr(gk),
+                                                        _ptr(gk_exp), _ptr(gX), _ptr(gY),
+                                                        _ptr(self.ws), self.ws.numel(),
+                                                        _stream(Xcat)))
+        return gX, gY
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -393,11 +411,71 @@ def sig_gram(X, Y, scheme: str = "approx", order: int = 4,
     return SigKernelGram.apply(X, Y, scheme, order, gram_mode)
 
 
+class SigKernelPairs(torch.autograd.Function):
+    """Differentiable k[i] = k(A[i], B[i]) for equal-length path batches A, B
+    of shape (P, L, d), through a backward plan: a saved-state forward when
+    the plan's backward is one chunk (the backward then starts from the
+    kept state), otherwise a plain forward and a recomputing backward."""
+
+    @staticmethod
+    def forward(ctx, A, B, scheme="approx", order=4, pipeline=False):
+        P, La, d = A.shape
+        Lb = B.shape[1]
+        Ac = A.reshape(P * La, d).contiguous()
+        Bc = B.reshape(P * Lb, d).contiguous()
+        xo = (Ac, [i * La for i in range(P + 1)])
+        yo = (Bc, [i * Lb for i in range(P + 1)])
+        plan = PairsPlan(xo, yo, scheme, order, backward=True)
+        plan.configure(True, True, True, pipeline)
+        k = torch.empty(P, dtype=A.dtype, device=A.device)
+        try:
+            plan.forward_save(Ac, Bc, k)
+            ctx.saved = True
+        except L.SigKernelError as e:
+            if e.status != L.SK_EWORKSPACE:
+                raise
+            plan.forward(Ac, Bc, k)
+            ctx.saved = False
+        ctx.plan, ctx.shapes = plan, (A.shape, B.shape)
+        ctx.save_for_backward(Ac, Bc)
+        return k
+
+    @staticmethod
+    def backward(ctx, gk):
+        Ac, Bc = ctx.saved_tensors
+        gA, gB = torch.empty_like(Ac), torch.empty_like(Bc)
+        gk = gk.contiguous().to(Ac.dtype)
+        if ctx.saved:
+            ctx.plan.backward_saved(Ac, Bc, gk, gA, gB)
+        else:
+            ctx.plan.backward(Ac, Bc, gk, gA, gB)
+        ctx.plan = None
+        sa, sb = ctx.shapes
+        return gA.reshape(sa), gB.reshape(sb), None, None, None
+
+
+def sig_pairs(A, B, scheme: str = "approx", order: int = 4, pipeline: bool = False):
+    return SigKernelPairs.apply(A, B, scheme, order, pipeline)
+
+
 def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
          gram_mode: str = "native") -> torch.Tensor:
     """Unbiased (U-statistic) squared MMD between path sets X and Y, with the
-    within-sample diagonals excluded; differentiable in X and Y."""
+    within-sample diagonals excluded; differentiable in X and Y.  Native Gram
+    arithmetic with equal path lengths: the pairs a < b of each set and all
+    cross pairs, in one pair list (k is symmetric, and the diagonal pairs do
+    not enter), otherwise three Gram matrices."""
     n, m = X.shape[0], Y.shape[0]
+    if gram_mode == "native" and X.shape[1] == Y.shape[1] and scheme not in ("fd", "fd2"):
+        ia, ib = torch.triu_indices(n, n, 1, device=X.device)
+        ja, jb = torch.triu_indices(m, m, 1, device=Y.device)
+        A = torch.cat([X[ia], Y[ja], X.repeat_interleave(m, 0)], 0)
+        B = torch.cat([X[ib], Y[jb], Y.repeat(n, 1, 1)], 0)
+        k = sig_pairs(A, B, scheme, order)
+        nxx, nyy = ia.numel(), ja.numel()
+        sxx = 2.0 * k[:nxx].sum() / (n * (n - 1))
+        syy = 2.0 * k[nxx:nxx + nyy].sum() / (m * (m - 1))
+        return sxx + syy - 2.0 * k[nxx + nyy:].mean()
     Kxx = sig_gram(X, X, scheme, order, gram_mode)
     Kyy = sig_gram(Y, Y, scheme, order, gram_mode)
     Kxy = sig_gram(X, Y, scheme, order, gram_mode)

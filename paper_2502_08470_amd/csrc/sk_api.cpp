@@ -466,15 +466,14 @@ template <typename R>
 int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P,
                  int max_strips, char* ws, const Layout& L, hipStream_t st);
 
-// Backward of a chunk of strip-pipeline pairs: increment Gram, the pipelined
-// checkpoint sweep over the forward job list (kernel values to K), the
-// pipelined adjoint over the reversed job list, and the contraction.
+// Backward of a chunk of strip-pipeline pairs, first half: increment Gram
+// and the pipelined checkpoint sweep over the forward job list (kernel
+// values to K).
 template <typename R>
-int run_chunk_backward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
-                            const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
-                            int max_ly, int max_strips, const int2* jobs_fwd,
-                            const int2* jobs_adj, int64_t njobs, char* ws, const Layout& L, R* K,
-                            int32_t* Kexp, const R* gK, const int32_t* gKexp, hipStream_t st) {
+int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
+                           const SkPairSrc& src, int64_t P, int max_nsteps_pad, int max_lx,
+                           int max_ly, const int2* jobs_fwd, int64_t njobs, char* ws,
+                           const Layout& L, R* K, int32_t* Kexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
@@ -499,14 +498,32 @@ int run_chunk_backward_pipe(const sk_params& p, const R* X, const R* Y, int64_t 
     pa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
     SK_LAUNCH("sweep_ckpt_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, interp, true, st),
               "pipelined checkpoint sweep");
+    return SK_OK;
+}
+
+// Second half: the pipelined adjoint over the reversed job list from the
+// state left by run_chunk_prepare_pipe, and the contraction.
+template <typename R>
+int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
+                           const SkPairSrc& src, int64_t P, int max_strips, const int2* jobs_adj,
+                           int64_t njobs, char* ws, const Layout& L, const R* gK,
+                           const int32_t* gKexp, hipStream_t st) {
+    const bool interp = p.scheme == SK_POLY_INTERP;
+    const int64_t npg = (L.total - L.pg) / 4;
+    int* prog = reinterpret_cast<int*>(ws + L.pg);
     SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), npg, st), "fill");
     AdjPipeArgs<R> aa;
     std::memset(&aa, 0, sizeof(aa));
-    aa.cskew = cskew; aa.tab = table_for<R>(p);
+    aa.cskew = reinterpret_cast<const R*>(ws + L.cskew); aa.tab = table_for<R>(p);
     aa.gK = gK; aa.gKexp = gKexp;
-    aa.ck = pa.ck; aa.ce = pa.ce; aa.qb = pa.qb; aa.qe = pa.qe;
+    aa.ck = reinterpret_cast<const R*>(ws + L.ck);
+    aa.ce = reinterpret_cast<const int32_t*>(ws + L.ce);
+    aa.qb = reinterpret_cast<const R*>(ws + L.qb);
+    aa.qe = reinterpret_cast<const int32_t*>(ws + L.qe);
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
-    aa.xb = pa.xb; aa.progress = prog; aa.abort = abrt; aa.spin_limit = kPipeSpinLimit;
+    aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
+    aa.progress = prog; aa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
+    aa.spin_limit = kPipeSpinLimit;
     aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs;
     SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
               "pipelined adjoint sweep");
@@ -1169,6 +1186,55 @@ int plan_forward(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kex
     return SK_OK;
 }
 
+// Backward state of one plan chunk: increment Gram and checkpoint sweep
+// (kernel values to K, indexed by the descriptors' k_idx) ...
+template <typename R>
+int plan_chunk_prepare(const PlanImpl& P, const PlanChunk& c, const R* Xc, const R* Yc, R* K,
+                       int32_t* Kexp, void* ws, hipStream_t st) {
+    char* base = (char*)ws;
+    const Layout L = layout_for(c.tot, c.count, sizeof(R), true, false, P.p.order);
+    char* ws_c = base + P.scratch_off;
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
+    if (c.pipe) {
+        const int2* jobs = reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first;
+        return run_chunk_prepare_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                         c.max_ly, jobs, c.njobs, ws_c, L, K, Kexp, st);
+    }
+    return run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
+                                c.max_ly, c.ring_fwd, ws_c, L, K, Kexp, st);
+}
+
+// ... then the adjoint, the contraction and the reduction into gX, gY.
+template <typename R>
+int plan_chunk_adjoint(const PlanImpl& P, const PlanChunk& c, const R* Xc, const R* Yc,
+                       const R* gK, const int32_t* gKexp, R* gX, R* gY, void* ws, hipStream_t st) {
+    char* base = (char*)ws;
+    const Layout L = layout_for(c.tot, c.count, sizeof(R), true, false, P.p.order);
+    char* ws_c = base + P.scratch_off;
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
+    int rc;
+    if (c.pipe) {
+        const int2* jobs = reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first;
+        rc = run_chunk_adjoint_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_strips, jobs + c.njobs,
+                                       c.njobs, ws_c, L, gK, gKexp, st);
+    } else {
+        rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj, c.max_strips,
+                                  ws_c, L, gK, gKexp, st);
+    }
+    if (rc) return rc;
+    ReducePairsArgs<R> ra;
+    ra.desc = src.desc; ra.count = c.count; ra.d = P.d; ra.max_pts = c.max_pts;
+    ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
+    ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
+    ra.gX = gX; ra.gY = gY;
+    SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_pairs(ra, st), "gradient reduction");
+    return SK_OK;
+}
+
 template <typename R>
 int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, const int32_t* gKexp,
                   R* gX, R* gY, void* ws, hipStream_t st) {
@@ -1179,33 +1245,33 @@ int plan_backward(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK, cons
     R* kbuf = reinterpret_cast<R*>(base + P.kbuf_off);
     int32_t* kexp = reinterpret_cast<int32_t*>(base + P.kexp_off);
     for (const PlanChunk& c : P.bchunks) {
-        const Layout L = layout_for(c.tot, c.count, sizeof(R), true, false, P.p.order);
-        char* ws_c = base + P.scratch_off;
-        SkPairSrc src;
-        std::memset(&src, 0, sizeof(src));
-        src.desc = reinterpret_cast<const SkPairDesc*>(base + P.bdesc_off) + c.first;
-        int rc;
-        if (c.pipe) {
-            const int2* jobs = reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first;
-            rc = run_chunk_backward_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                            c.max_ly, c.max_strips, jobs, jobs + c.njobs, c.njobs,
-                                            ws_c, L, kbuf, kexp, gK, gKexp, st);
-        } else {
-            rc = run_chunk_prepare<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_nsteps_pad, c.max_lx,
-                                      c.max_ly, c.ring_fwd, ws_c, L, kbuf, kexp, st);
-            if (!rc)
-                rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj,
-                                          c.max_strips, ws_c, L, gK, gKexp, st);
-        }
+        int rc = plan_chunk_prepare<R>(P, c, Xc, Yc, kbuf, kexp, ws, st);
+        if (!rc) rc = plan_chunk_adjoint<R>(P, c, Xc, Yc, gK, gKexp, gX, gY, ws, st);
         if (rc) return rc;
-        ReducePairsArgs<R> ra;
-        ra.desc = src.desc; ra.count = c.count; ra.d = P.d; ra.max_pts = c.max_pts;
-        ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
-        ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
-        ra.gX = gX; ra.gY = gY;
-        SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_pairs(ra, st), "gradient reduction");
     }
     return SK_OK;
+}
+
+// Forward that keeps the backward's state in the plan's workspace (plans
+// whose backward is one chunk), and the backward that starts from it.
+template <typename R>
+int plan_forward_save(const PlanImpl& P, const R* Xc, const R* Yc, R* K, int32_t* Kexp, void* ws,
+                      hipStream_t st) {
+    if (P.bchunks.size() != 1)
+        return fail(SK_EWORKSPACE, "the saved state needs the backward in one chunk (%zu chunks)",
+                    P.bchunks.size());
+    return plan_chunk_prepare<R>(P, P.bchunks[0], Xc, Yc, K, Kexp, ws, st);
+}
+
+template <typename R>
+int plan_backward_saved(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK,
+                        const int32_t* gKexp, R* gX, R* gY, void* ws, hipStream_t st) {
+    if (P.bchunks.size() != 1)
+        return fail(SK_EWORKSPACE, "the saved state needs the backward in one chunk (%zu chunks)",
+                    P.bchunks.size());
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, P.xo[P.npairs] * P.d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, P.yo[P.npairs] * P.d, (R)0, st), "fill");
+    return plan_chunk_adjoint<R>(P, P.bchunks[0], Xc, Yc, gK, gKexp, gX, gY, ws, st);
 }
 
 // Time every configuration's forward (best of two runs after a warm-up),
@@ -1690,6 +1756,51 @@ int sigkernel_plan_backward(const sk_plan* plan, const void* Xcat, const void* Y
         return plan_backward<double>(P, (const double*)Xcat, (const double*)Ycat,
                                      (const double*)gk, gk_exp, (double*)gX, (double*)gY, ws,
                                      stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_forward_save(const sk_plan* plan, const void* Xcat, const void* Ycat, void* k,
+                                int32_t* k_exp, void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    const PlanImpl& P = plan->impl;
+    if (!P.backward) return fail(SK_EINVAL, "plan was created without backward");
+    int rc = plan_ready(P, ws, ws_bytes);
+    if (rc) return rc;
+    if (P.npairs == 0) return SK_OK;
+    if (!Xcat || !Ycat || !k) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (P.p.dtype == SK_F32)
+            return plan_forward_save<float>(P, (const float*)Xcat, (const float*)Ycat, (float*)k,
+                                            k_exp, ws, stream);
+        return plan_forward_save<double>(P, (const double*)Xcat, (const double*)Ycat, (double*)k,
+                                         k_exp, ws, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_plan_backward_saved(const sk_plan* plan, const void* Xcat, const void* Ycat,
+                                  const void* gk, const int32_t* gk_exp, void* gX, void* gY,
+                                  void* ws, size_t ws_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (!plan) return fail(SK_EINVAL, "plan is NULL");
+    const PlanImpl& P = plan->impl;
+    if (!P.backward) return fail(SK_EINVAL, "plan was created without backward");
+    int rc = plan_ready(P, ws, ws_bytes);
+    if (rc) return rc;
+    if (P.npairs == 0) return SK_OK;
+    if (!Xcat || !Ycat || !gk || !gX || !gY) return fail(SK_EINVAL, "NULL pointer");
+    try {
+        if (P.p.dtype == SK_F32)
+            return plan_backward_saved<float>(P, (const float*)Xcat, (const float*)Ycat,
+                                              (const float*)gk, gk_exp, (float*)gX, (float*)gY, ws,
+                                              stream);
+        return plan_backward_saved<double>(P, (const double*)Xcat, (const double*)Ycat,
+                                           (const double*)gk, gk_exp, (double*)gX, (double*)gY, ws,
+                                           stream);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
     }

@@ -75,6 +75,23 @@ def test_empty_batch_is_ok_without_device_work():
     assert gram(P(), nx=0) == L.SK_OK
 
 
+def test_saved_state_plan_calls_need_a_backward_plan():
+    lib = L.lib()
+    xo = (ctypes.c_int64 * 3)(0, 10, 30)
+    yo = (ctypes.c_int64 * 3)(0, 20, 25)
+    h = ctypes.c_void_p(0)
+    assert lib.sigkernel_plan_create(xo, yo, 2, 3, P(), 0, 0, ctypes.byref(h)) == L.SK_OK
+    vp = ctypes.c_void_p
+    try:
+        assert lib.sigkernel_plan_forward_save(h, vp(1), vp(1), vp(1), None, vp(1), 1 << 20,
+                                               None) == L.SK_EINVAL
+        assert lib.sigkernel_plan_backward_saved(h, vp(1), vp(1), vp(1), None, vp(1), vp(1), vp(1),
+                                                 1 << 20, None) == L.SK_EINVAL
+        assert "backward" in L.last_error()
+    finally:
+        lib.sigkernel_plan_destroy(h)
+
+
 def test_backward_rejections():
     lib = L.lib()
     vp = ctypes.c_void_p

@@ -176,3 +176,64 @@ def test_pipeline_plan_graph_replays_match_eager(sk):
         torch.cuda.synchronize()
         assert torch.equal(k, k_eager), rep
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("pipeline", [False, True])
+def test_saved_state_plan_matches_plan(sk, pipeline):
+    # forward_save + backward_saved against forward + backward of the same
+    # plan (same kernels on the same state: identical results)
+    log_banner(f"plan saved state pipeline={pipeline}")
+    rng = np.random.default_rng(57)
+    xs, ys = uneven(rng, 40, 5, 70, 700)  # every pair has several strips
+    Xc, Yc = cat(xs, torch.float32), cat(ys, torch.float32)
+    xl = [torch.tensor(a, dtype=torch.float32, device="cuda") for a in xs]
+    yl = [torch.tensor(b, dtype=torch.float32, device="cuda") for b in ys]
+    plan = sk.PairsPlan(xl, yl, "interp", 6, backward=True)
+    plan.configure(1, 1, 1, pipeline)
+    gk = torch.tensor(rng.normal(size=len(xs)), dtype=torch.float32, device="cuda")
+    k0 = torch.empty(len(xs), device="cuda")
+    plan.forward(Xc, Yc, k0)
+    gX0, gY0 = torch.empty_like(Xc), torch.empty_like(Yc)
+    plan.backward(Xc, Yc, gk, gX0, gY0)
+    k1 = torch.full((len(xs),), float("nan"), device="cuda")
+    plan.forward_save(Xc, Yc, k1)
+    gX1, gY1 = torch.full_like(Xc, float("nan")), torch.full_like(Yc, float("nan"))
+    plan.backward_saved(Xc, Yc, gk, gX1, gY1)
+    if pipeline:
+        assert torch.equal(k1, k0)
+    else:  # the checkpoint sweep's interpolation tail is decided per wave as in the forward
+        torch.testing.assert_close(k1, k0, rtol=1e-6, atol=0)
+    assert torch.equal(gX1, gX0) and torch.equal(gY1, gY0)
+
+
+def test_saved_state_needs_one_backward_chunk(sk):
+    # pairs of one strip and of several strips: two backward chunks
+    log_banner("plan saved state, two chunks")
+    rng = np.random.default_rng(58)
+    xs, ys = uneven(rng, 12, 3, 10, 300)
+    xs[0], ys[0] = xs[0][:20], ys[0][:30]
+    xl = [torch.tensor(a, device="cuda") for a in xs]
+    yl = [torch.tensor(b, device="cuda") for b in ys]
+    plan = sk.PairsPlan(xl, yl, "approx", 4, backward=True)
+    plan.configure(1, 1, 1, True)
+    k = torch.empty(len(xs), dtype=torch.float64, device="cuda")
+    with pytest.raises(sk.SigKernelError) as ei:
+        plan.forward_save(cat(xs, torch.float64), cat(ys, torch.float64), k)
+    assert ei.value.status == -2  # SK_EWORKSPACE
+
+
+def test_mmd_pair_list_matches_three_grams(sk):
+    # the triangular pair-list MMD^2 against the three-Gram U-statistic
+    log_banner("mmd pair list vs grams")
+    import workloads as W
+    X, Y = W.mmd_sets(0, n=6, steps=200)
+    Xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    Yt = torch.tensor(Y, dtype=torch.float64, device="cuda")
+    val = float(sk.mmd2(Xt, Yt, "approx", 6))
+    Kxx = sk.gram(Xt, Xt, "approx", 6)
+    Kyy = sk.gram(Yt, Yt, "approx", 6)
+    Kxy = sk.gram(Xt, Yt, "approx", 6)
+    n = 6
+    want = float((Kxx.sum() - Kxx.diagonal().sum()) / (n * (n - 1))
+                 + (Kyy.sum() - Kyy.diagonal().sum()) / (n * (n - 1)) - 2.0 * Kxy.mean())
+    assert abs(val - want) <= 1e-12 * max(1.0, float(Kxx.abs().max())), (val, want)
