@@ -397,7 +397,7 @@ hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int
     }
     if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
-    if (SkLaunch<R>::gram_band_lds(ga.dpad) <= kGramPairLds)
+    if (ga.dpad <= 60 && SkLaunch<R>::gram_band_lds(ga.dpad) <= kGramPairLds)
         return SkLaunch<R>::gram_band(ga, strips, rows, P, st);
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
 }

@@ -267,16 +267,28 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
             Xs[rr * ds + k] = v;
         }
     };
-    auto stage_y = [&](int c0) {  // virtual columns c0 .. c0 + 63
-        for (int e = tid; e < 64 * dp; e += 256) {
-            const int cc = e / dp, k = e - cc * dp, vv = c0 + cc;
+    // y increments of virtual columns c0 .. c0 + 63, loaded into registers
+    // one tile ahead (their latency overlaps the previous tile) and then
+    // stored to LDS; 64 dp / 256 <= 16 values per thread (dp <= 60 here)
+    constexpr int YV = 16;
+    R yv[YV];
+    auto load_y = [&](int c0) {
+#pragma unroll
+        for (int h = 0; h < YV; ++h) {
+            const int e = tid + 256 * h, cc = e / dp, k = e - cc * dp, vv = c0 + cc;
             const int col = vv >= 0 ? vv : g.Tp + vv;
-            R v = (R)0;
-            if (k < a.d && (vv >= 0 || s > 0) && col >= 0 && col < g.ly) {
+            yv[h] = (R)0;
+            if (e < 64 * dp && k < a.d && (vv >= 0 || s > 0) && col >= 0 && col < g.ly) {
                 const int j = col >> a.lam;
-                v = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
+                yv[h] = (Y[(int64_t)(j + 1) * a.d + k] - Y[(int64_t)j * a.d + k]) * rscale;
             }
-            Ys[cc * ds + k] = v;
+        }
+    };
+    auto store_y = [&]() {
+#pragma unroll
+        for (int h = 0; h < YV; ++h) {
+            const int e = tid + 256 * h, cc = e / dp, k = e - cc * dp;
+            if (e < 64 * dp) Ys[cc * ds + k] = yv[h];
         }
     };
     auto tile = [&](R* T) {  // T[r][c] = sum_k Xs[r][k] Ys[c][k]; wave w: rows 16w .. 16w+15
@@ -293,8 +305,10 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
     // the tile of virtual columns 64 (k0-1) .. 64 k0 - 1 (k0 = 0: strip s-1's
     // last 64 columns, rows of strip s-1)
     stage_x(k0 == 0 ? s - 1 : s);
-    stage_y(64 * (k0 - 1));
+    load_y(64 * (k0 - 1));
+    store_y();
     __syncthreads();
+    load_y(64 * k0);
     tile(Tt + ((k0 - 1) & 1) * 64 * 66);
     if (k0 == 0) {
         __syncthreads();
@@ -303,8 +317,9 @@ __global__ __launch_bounds__(256) void k_gram_band(const GramArgs<R> a) {
     R* out = a.cskew + pd.c_off + (int64_t)s * g.Tp * 64;
     for (int k = k0; 64 * k < tend; ++k) {
         __syncthreads();  // the previous rows are written: Ys and the older tile are free
-        stage_y(64 * k);
+        store_y();
         __syncthreads();
+        if (64 * (k + 1) < tend) load_y(64 * (k + 1));
         R* Tc = Tt + (k & 1) * 64 * 66;
         const R* Tq = Tt + ((k - 1) & 1) * 64 * 66;
         tile(Tc);
