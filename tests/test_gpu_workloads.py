@@ -85,6 +85,77 @@ def test_uneven_pairs_full_size(sk):
     assert err.max() < 1e-8, err
 
 
+def test_uneven_pairs_backward_full_size(sk):
+    # the 4096 uneven pairs' gradient, in the launches the workload study
+    # times (a backward plan whose multi-strip pairs run the pipelined
+    # checkpoint sweep and adjoint): FP64 against the batched backward of the
+    # same plan and against central differences of the oracle; FP32 against
+    # FP64 on the pairs FP32 can resolve (short oscillatory pairs are
+    # ill-conditioned: |k| up to 1e13 out of cancelling terms, where the FP32
+    # forward itself is off by O(1))
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("full 4096 uneven pairs backward")
+    xs, ys = W.uneven_pairs(0)
+    rng = np.random.default_rng(3)
+    gk = rng.normal(size=len(xs))
+    xo = np.concatenate([[0], np.cumsum([len(a) for a in xs])])
+    yo = np.concatenate([[0], np.cumsum([len(b) for b in ys])])
+
+    def run(dtype, pipeline):
+        xl = [torch.tensor(a, dtype=dtype, device="cuda") for a in xs]
+        yl = [torch.tensor(b, dtype=dtype, device="cuda") for b in ys]
+        Xc, Yc = torch.cat(xl), torch.cat(yl)
+        plan = sk.PairsPlan(xl, yl, "approx", 8, backward=True)
+        plan.configure(1, 1, 1, pipeline)
+        k = torch.empty(len(xs), dtype=dtype, device="cuda")
+        plan.forward(Xc, Yc, k)
+        gX, gY = torch.empty_like(Xc), torch.empty_like(Yc)
+        plan.backward(Xc, Yc, torch.tensor(gk, dtype=dtype, device="cuda"), gX, gY)
+        out = (k.cpu().double().numpy(), gX.cpu().double().numpy(), gY.cpu().double().numpy())
+        del plan, xl, yl, Xc, Yc, gX, gY
+        torch.cuda.empty_cache()
+        return out
+
+    def path_err(a, b, i):
+        sx, sy = slice(xo[i], xo[i + 1]), slice(yo[i], yo[i + 1])
+        scale = max(np.abs(b[1][sx]).max(), np.abs(b[2][sy]).max())
+        return max(np.abs(a[1][sx] - b[1][sx]).max(), np.abs(a[2][sy] - b[2][sy]).max()) / scale
+
+    p64, b64, p32 = run(torch.float64, True), run(torch.float64, False), run(torch.float32, True)
+    assert np.isfinite(p32[1]).all() and np.isfinite(p32[2]).all()
+    e64 = max(path_err(p64, b64, i) for i in range(len(xs)))
+    assert e64 <= 1e-9, e64
+    # FP32: a gross-error check on the pairs whose FP32 kernel value is good
+    # to 1e-5 (2904 of 4096; their gradients, derivatives of cancelling sums,
+    # are more sensitive: 4.4e-3 at worst); the code itself is pinned in FP64
+    kerr = np.abs(p32[0] / p64[0] - 1)
+    good = [i for i in range(len(xs)) if kerr[i] <= 1e-5]
+    e32 = max(path_err(p32, p64, i) for i in good)
+    print(f"FP64 pipeline vs batched {e64:.3g}; FP32 vs FP64 on {len(good)} resolved pairs {e32:.3g}",
+          flush=True)
+    assert len(good) >= len(xs) // 2 and e32 <= 1e-2
+    # pairs of 400-600 points (several strips, well conditioned, a few
+    # hundred thousand oracle cells each)
+    small = [i for i in range(len(xs)) if 400 <= len(xs[i]) <= 600 and 400 <= len(ys[i]) <= 600][:2]
+    assert len(small) == 2
+    h = 1e-4
+    for i in small:
+        x64, y64 = xs[i].astype(np.float64), ys[i].astype(np.float64)
+        for t, k in [(1, 3), (len(xs[i]) - 2, 11)]:
+            def loss(v):
+                m, e = C.pairs([v], [y64], C.APPROX, 8)
+                return gk[i] * float(np.ldexp(m, e)[0])
+            v = x64.copy()
+            v[t, k] += h
+            lp = loss(v)
+            v[t, k] -= 2 * h
+            lm = loss(v)
+            fd = (lp - lm) / (2 * h)
+            g = p64[1][xo[i] + t, k]
+            assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (i, t, k, g, fd)
+
+
 def test_mmd_sets_full_size(sk):
     import workloads as W
     from oracle import c_oracle as C
