@@ -349,6 +349,7 @@ template <typename R> struct SkGramDirectPad;
 template <> struct SkGramDirectPad<float> { static constexpr int value = 2; };
 template <> struct SkGramDirectPad<double> { static constexpr int value = 1; };
 #define SK_GRAM_DIRECT_DMAX 16
+#define SK_GRAM_STRIP_DMAX 32
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_gram_direct(const GramArgs<R> a) {

@@ -106,7 +106,7 @@ template <typename R>
 hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int max_rows,
                                    int64_t npairs, hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0 || max_rows <= 0) return hipSuccess;
-    if (a0.split || a0.dpad > SK_GRAM_DIRECT_DMAX) return hipErrorInvalidValue;
+    if (a0.split || a0.dpad > SK_GRAM_STRIP_DMAX) return hipErrorInvalidValue;
     // split each strip's rows so that the launch has about 8 waves per SIMD
     // (a few long pairs have few strips), segments of at least 256 rows
     const int64_t waves = npairs * (int64_t)max_strips;
@@ -121,8 +121,10 @@ hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int ma
         hipLaunchKernelGGL((k_gram_strip<R, 4>), grid, dim3(64), (128 * sk_ring_ys<R, 4>() * sizeof(R)), st, a);
     else if (a.dpad <= 8)
         hipLaunchKernelGGL((k_gram_strip<R, 8>), grid, dim3(64), (128 * sk_ring_ys<R, 8>() * sizeof(R)), st, a);
-    else
+    else if (a.dpad <= 16)
         hipLaunchKernelGGL((k_gram_strip<R, 16>), grid, dim3(64), (128 * sk_ring_ys<R, 16>() * sizeof(R)), st, a);
+    else
+        hipLaunchKernelGGL((k_gram_strip<R, 32>), grid, dim3(64), (128 * sk_ring_ys<R, 32>() * sizeof(R)), st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }

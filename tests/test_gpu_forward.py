@@ -34,15 +34,17 @@ def dev(a, dtype):
 # ---------------------------------------------------------------------------
 # native, d <= 16: the FMA-chain kernel with a pair's increments in LDS (the
 # first two shapes), or one wave per strip with the y increments in an LDS
-# ring (the last two, whose increments exceed the LDS budget; the last has a
-# strip period above ly); MFMA for d > 16.  mfma / bf16x3: the pair-resident
+# ring (the next two, whose increments exceed the LDS budget; the second has a
+# strip period above ly); MFMA for d > 16, except FP64 with d <= 32 on pairs
+# whose MFMA band tiles exceed the LDS budget (the last shape), which runs
+# the strip kernel.  mfma / bf16x3: the pair-resident
 # MFMA kernel, and for the last two shapes the strip-band MFMA kernel (FP32)
 # or the 64-row block kernel (FP64, whose band tiles exceed the LDS budget)
 @pytest.mark.parametrize("dtype,mode", [(torch.float64, "native"), (torch.float32, "native"),
                                         (torch.float64, "mfma"), (torch.float32, "mfma"),
                                         (torch.float32, "bf16x3")])
 @pytest.mark.parametrize("shape", [(2, 65, 3, 130, 4), (3, 7, 2, 200, 9), (1, 150, 1, 64, 33),
-                                   (1, 1500, 1, 1300, 16), (1, 3000, 2, 50, 13)])
+                                   (1, 1500, 1, 1300, 16), (1, 3000, 2, 50, 13), (1, 900, 2, 800, 24)])
 def test_cell_constants_match_increment_products(sk, dtype, mode, shape):
     nx, lxp, ny, lyp, d = shape
     log_banner(f"cell_constants {dtype} {mode} {shape}")
