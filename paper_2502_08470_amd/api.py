@@ -489,15 +489,24 @@ def mmd_permutation_test(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx
                          gram_mode: str = "native"):
     """Two-sample permutation test on the unbiased MMD^2 of path sets X and Y.
 
-    The pooled Gram matrix is one library Gram call; the statistics of the
-    observed split and of n_perm random relabellings (drawn on the host with
+    The pooled Gram matrix comes from one library pairs call over the pairs
+    a < b (k is symmetric and the unbiased statistic leaves out the
+    diagonal, which is set to zero); the statistics of the observed split and
+    of n_perm random relabellings (drawn on the host with
     numpy.random.default_rng(seed)) and the p-value are computed by the
     library's kernels.  Returns (statistic, p_value, permutation statistics)."""
     import numpy as np
     X, Y = _dev(X), _dev(Y)
     m, n = X.shape[0], Y.shape[0]
     Z = torch.cat([X, Y], 0)
-    Kzz = gram(Z, Z, scheme, order, gram_mode=gram_mode)
+    T, Lz, d = Z.shape
+    ia, ib = torch.triu_indices(T, T, 1, device=Z.device)
+    off = [i * Lz for i in range(ia.numel() + 1)]
+    kab = pairs((Z[ia].reshape(-1, d), off), (Z[ib].reshape(-1, d), off), scheme, order,
+                gram_mode=gram_mode)
+    Kzz = torch.zeros(T, T, dtype=Z.dtype, device=Z.device)
+    Kzz[ia, ib] = kab
+    Kzz[ib, ia] = kab
     rng = np.random.default_rng(seed)
     perms = np.empty((n_perm + 1, m + n), dtype=np.int32)
     perms[0] = np.arange(m + n)
