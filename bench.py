@@ -83,6 +83,9 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
                 if row["Counter_Name"] == ctr:
                     d[row["Kernel_Name"]].append(float(row["Counter_Value"]))
         return d
+    def rel(path):
+        return os.path.relpath(os.path.abspath(path), ROOT)
+
     f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
     cal = float(CALIBRATE_MIB << 20)
     copy_f = max(v for k, vs in f.items() if "copyBuffer" in k for v in vs)
@@ -99,14 +102,14 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
     out = {"source_hash": kernel_source_hash(),
            "calibration": {"copy_bytes": cal, "fetch_counter": copy_f, "write_counter": copy_w,
                            "fetch_bytes_per_unit": fscale, "write_bytes_per_unit": wscale},
-           "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -f csv -- "
+           # the commands, with the output folders of the two runs as given
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {rel(os.path.dirname(fetch_csv))} -o fetch -f csv -- "
                         "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
                         f"--calibrate-copy {CALIBRATE_MIB}",
-                        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -f csv -- "
+                        f"rocprofv3 --pmc WRITE_SIZE -d {rel(os.path.dirname(write_csv))} -o write -f csv -- "
                         "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
                         f"--calibrate-copy {CALIBRATE_MIB}",
-                        "python3 bench.py --pmc-summary gpurun_out/pmc_fetch/fetch_counter_collection.csv "
-                        "gpurun_out/pmc_write/write_counter_collection.csv " + os.path.relpath(out_json, ROOT)],
+                        f"python3 bench.py --pmc-summary {rel(fetch_csv)} {rel(write_csv)} {rel(out_json)}"],
            "kernels": kernels}
     with open(out_json, "w") as fh:
         json.dump(out, fh, indent=1)
