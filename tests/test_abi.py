@@ -3,6 +3,7 @@
 Every call here fails in host-side validation before any device work, so it
 runs on a machine without a GPU."""
 import ctypes
+import itertools
 import os
 import re
 
@@ -208,3 +209,48 @@ def test_mmd_permutation_argument_errors():
     assert call(K=0) == L.SK_EINVAL
     assert call(P=0) == L.SK_EINVAL
     assert call(m=1 << 20, n=8) == L.SK_EUNSUPPORTED
+
+
+def test_pipeline_plan_grouping_and_workspace():
+    # host-side plan build: pairs of several 64-row strips form one launch
+    # group on the strip pipeline, the rest run batched; a backward plan keeps
+    # per-strip checkpoints on each strip's local steps, so it needs more
+    # workspace than the batched layout
+    lib = L.lib()
+    lens_x = [300, 40, 700, 65, 10]
+    lens_y = [200, 30, 100, 500, 64]
+    xo = (ctypes.c_int64 * 6)(0, *itertools.accumulate(lens_x))
+    yo = (ctypes.c_int64 * 6)(0, *itertools.accumulate(lens_y))
+    o, w, b, pp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    n = ctypes.c_int64()
+    sizes = {}
+    for backward in (0, 1):
+        h = ctypes.c_void_p(0)
+        assert lib.sigkernel_plan_create(xo, yo, 5, 3, P(order=6), backward, 0, ctypes.byref(h)) == L.SK_OK
+        try:
+            for pipe in (0, 1):
+                assert lib.sigkernel_plan_configure(h, 1, 1, 0, pipe, 0) == L.SK_OK
+                assert lib.sigkernel_plan_config(h, ctypes.byref(o), ctypes.byref(w), ctypes.byref(b),
+                                                 ctypes.byref(pp), ctypes.byref(n)) == L.SK_OK
+                assert pp.value == pipe
+                # one launch group without the pipeline; with it the 3 pairs of
+                # several strips (transposed: 300, 700, 500 points) form their own
+                assert n.value == (2 if pipe else 1), (backward, pipe, n.value)
+                sizes[(backward, pipe)] = lib.sigkernel_plan_workspace(h)
+        finally:
+            lib.sigkernel_plan_destroy(h)
+    assert sizes[(1, 1)] > sizes[(0, 1)] and sizes[(1, 0)] > sizes[(0, 0)]
+
+
+def test_pipeline_workspace_queries():
+    lib = L.lib()
+    xo = (ctypes.c_int64 * 3)(0, 300, 340)
+    yo = (ctypes.c_int64 * 3)(0, 200, 230)
+    # pair lists: the pipeline's backward is a plan
+    assert lib.sigkernel_pairs_workspace(xo, yo, 2, 3, P(algo=2), 1) > 0
+    assert lib.sigkernel_pairs_workspace(xo, yo, 2, 3, P(algo=2), 0) > 0
+    # Gram-mode backward entry points refuse the pipeline
+    assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 1) == 0
+    assert "pair lists" in L.last_error()
+    assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 0) > 0
+    assert lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P(algo=2)) == 0
