@@ -424,37 +424,46 @@ __global__ __launch_bounds__(256) void k_gram_direct(const GramArgs<R> a) {
 // Direct variant for pairs whose increments exceed one workgroup's LDS: one
 // wave per (pair, strip s, segment z) writes the skewed rows s Tp + t,
 // t in [z rseg, (z+1) rseg), of the strip's rows t < Tp (the last strip's
-// up to nsteps_pad), whole.  Lane r's cell at row s Tp + t has linear
-// index s Tp + v, v = t - r: row 64 s + r and column v when v >= 0, row
+// up to nsteps_pad), whole.  Lane r's cell at row s Tp + t has linear index
+// s Tp + v, v = t - r: row 64 s + r and column v when v >= 0, row
 // 64 (s-1) + r and column Tp + v (strip s-1) when v < 0.  The lane keeps the
 // x increments of both rows in registers; the y increments of the 64
 // virtual columns t-63 .. t sit in an LDS ring of 128 (slot v mod 128),
-// 8 columns added every 8 steps, loaded one block ahead.  Same FMA order
-// and scaling as k_gram_direct, so both give identical constants.
+// 8 columns added every 8 steps, loaded one block ahead.  The SW waves of a
+// workgroup take SW consecutive strips in lockstep: their rows need the same
+// virtual columns, so they share one ring (SW times less LDS per wave).
+// Same FMA order and scaling as k_gram_direct, so both give identical
+// constants.
+#define SK_GRAM_STRIP_WAVES 4
 template <typename R, int DMAX>
-__global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
-    const int r = threadIdx.x;
-    const int s = blockIdx.y;
+__global__ __launch_bounds__(64 * SK_GRAM_STRIP_WAVES) void k_gram_strip(const GramArgs<R> a) {
+    constexpr int SW = SK_GRAM_STRIP_WAVES;
+    const int tid = threadIdx.x, r = tid & 63;
+    const int s0 = (int)blockIdx.y * SW, s = s0 + (tid >> 6);
     const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
     const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
-    if (g.nsteps == 0 || s >= g.nstrips) return;
+    if (g.nsteps == 0 || s0 >= g.nstrips) return;  // workgroup-uniform
+    auto rows_of = [&](int st) { return st == g.nstrips - 1 ? g.nsteps_pad - st * g.Tp : g.Tp; };
+    const int slast = s0 + SW - 1 < g.nstrips - 1 ? s0 + SW - 1 : g.nstrips - 1;
+    const int tbeg = (int)blockIdx.z * a.rseg;
+    const int Tmax = rows_of(slast);  // the workgroup's longest strip (the pair's last if it holds it)
+    if (tbeg >= Tmax) return;  // workgroup-uniform
+    const int Tend = tbeg + a.rseg < Tmax ? tbeg + a.rseg : Tmax;
+    const bool sok = s < g.nstrips;
+    const int Tmine = sok ? (tbeg + a.rseg < rows_of(s) ? tbeg + a.rseg : rows_of(s)) : 0;
     constexpr int YS = sk_ring_ys<R, DMAX>();
-    constexpr int NV = (8 * DMAX + 63) / 64;  // ring values per lane per 8 columns
+    constexpr int NV = (8 * DMAX + 64 * SW - 1) / (64 * SW);  // ring values per thread per 8 columns
     extern __shared__ __align__(16) unsigned char sk_smem[];
     R* ring = reinterpret_cast<R*>(sk_smem);  // [128][YS]
     const int64_t d = a.d;
     const int lam = a.lam;
     const R* X = (pd.swap ? a.Y : a.X) + pd.x_off * d;
     const R* Y = (pd.swap ? a.X : a.Y) + pd.y_off * d;
-    const int Tstrip = (s == g.nstrips - 1) ? g.nsteps_pad - s * g.Tp : g.Tp;
-    const int tbeg = (int)blockIdx.z * a.rseg;
-    if (tbeg >= Tstrip) return;
-    const int Tend = tbeg + a.rseg < Tstrip ? tbeg + a.rseg : Tstrip;
     // x increments (segment i >> lam, unrefined) of the lane's rows in
     // strips s and s-1 (every row of a strip before the last exists)
     const int ia = s * 64 + r, ib = ia - 64;
-    const bool oka = ia < g.lx, okb = s > 0;
+    const bool oka = sok && ia < g.lx, okb = sok && s > 0;
     R xa[DMAX], xb[DMAX];
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
@@ -464,15 +473,16 @@ __global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
         if (k < d && okb) xb[k] = X[(int64_t)((ib >> lam) + 1) * d + k] - X[(int64_t)(ib >> lam) * d + k];
     }
     // y increments of the 8 virtual columns from v0: value w is column
-    // v0 + w / DMAX, dimension w % DMAX
+    // v0 + w / DMAX, dimension w % DMAX (negative v: column Tp + v, which
+    // only the strips after the first read)
     R yv[NV];
     auto load_y = [&](int v0) {
 #pragma unroll
         for (int h = 0; h < NV; ++h) {
-            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX, v = v0 + m;
+            const int w = tid + 64 * SW * h, m = w / DMAX, k = w - m * DMAX, v = v0 + m;
             const int col = v >= 0 ? v : g.Tp + v;
             yv[h] = (R)0;
-            if (w < 8 * DMAX && k < d && (v >= 0 || s > 0) && col < g.ly) {
+            if (w < 8 * DMAX && k < d && col >= 0 && col < g.ly) {
                 const int j = col >> lam;
                 yv[h] = Y[(int64_t)(j + 1) * d + k] - Y[(int64_t)j * d + k];
             }
@@ -481,7 +491,7 @@ __global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
     auto store_y = [&](int v0) {
 #pragma unroll
         for (int h = 0; h < NV; ++h) {
-            const int w = r + 64 * h, m = w / DMAX, k = w - m * DMAX;
+            const int w = tid + 64 * SW * h, m = w / DMAX, k = w - m * DMAX;
             if (w < 8 * DMAX) ring[((v0 + m) & 127) * YS + k] = yv[h];
         }
     };
@@ -502,7 +512,7 @@ __global__ __launch_bounds__(64) void k_gram_strip(const GramArgs<R> a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int t = t0 + u, v = t - r;
-            if (t >= Tend) break;
+            if (t >= Tmine) break;  // wave-uniform
             const bool lo = v < 0;
             const int col = lo ? g.Tp + v : v;
             const bool live = (lo ? okb : oka) && col < g.ly;

@@ -107,24 +107,26 @@ hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int ma
                                    int64_t npairs, hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0 || max_rows <= 0) return hipSuccess;
     if (a0.split || a0.dpad > SK_GRAM_STRIP_DMAX) return hipErrorInvalidValue;
-    // split each strip's rows so that the launch has about 8 waves per SIMD
+    // split each strip's rows so that the launch has about 2048 workgroups
     // (a few long pairs have few strips), segments of at least 256 rows
-    const int64_t waves = npairs * (int64_t)max_strips;
-    const int64_t want = 8192;
-    int64_t nseg = waves >= want ? 1 : (want + waves - 1) / waves;
+    constexpr int SW = SK_GRAM_STRIP_WAVES;  // strips per workgroup
+    const int64_t groups = (max_strips + SW - 1) / SW;
+    const int64_t wgs = npairs * groups;
+    const int64_t want = 2048;
+    int64_t nseg = wgs >= want ? 1 : (want + wgs - 1) / wgs;
     nseg = std::max<int64_t>(1, std::min<int64_t>(nseg, max_rows / 256));
     GramArgs<R> a = a0;
     a.rseg = (int)(((max_rows + nseg - 1) / nseg + 7) / 8 * 8);
     nseg = (max_rows + a.rseg - 1) / a.rseg;
-    const dim3 grid((unsigned)npairs, (unsigned)max_strips, (unsigned)nseg);
+    const dim3 grid((unsigned)npairs, (unsigned)groups, (unsigned)nseg), blk(64 * SW);
     if (a.dpad <= 4)
-        hipLaunchKernelGGL((k_gram_strip<R, 4>), grid, dim3(64), (128 * sk_ring_ys<R, 4>() * sizeof(R)), st, a);
+        hipLaunchKernelGGL((k_gram_strip<R, 4>), grid, blk, (128 * sk_ring_ys<R, 4>() * sizeof(R)), st, a);
     else if (a.dpad <= 8)
-        hipLaunchKernelGGL((k_gram_strip<R, 8>), grid, dim3(64), (128 * sk_ring_ys<R, 8>() * sizeof(R)), st, a);
+        hipLaunchKernelGGL((k_gram_strip<R, 8>), grid, blk, (128 * sk_ring_ys<R, 8>() * sizeof(R)), st, a);
     else if (a.dpad <= 16)
-        hipLaunchKernelGGL((k_gram_strip<R, 16>), grid, dim3(64), (128 * sk_ring_ys<R, 16>() * sizeof(R)), st, a);
+        hipLaunchKernelGGL((k_gram_strip<R, 16>), grid, blk, (128 * sk_ring_ys<R, 16>() * sizeof(R)), st, a);
     else
-        hipLaunchKernelGGL((k_gram_strip<R, 32>), grid, dim3(64), (128 * sk_ring_ys<R, 32>() * sizeof(R)), st, a);
+        hipLaunchKernelGGL((k_gram_strip<R, 32>), grid, blk, (128 * sk_ring_ys<R, 32>() * sizeof(R)), st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
