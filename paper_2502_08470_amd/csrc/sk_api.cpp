@@ -393,19 +393,19 @@ hipError_t launch_gram(const GramArgs<R>& ga, int64_t P, int max_nsteps_pad, int
     if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX &&
         SkLaunch<R>::gram_direct_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
         return SkLaunch<R>::gram_direct(ga, max_lx, max_ly, P, st);
-    // pairs too long for one workgroup's LDS: the FMA chain per strip for
-    // d <= 16, else MFMA strip bands where their tiles fit in LDS (FP32 up to
-    // d = 60), else the FMA chain per strip again for d <= 32 (FP64: 368 ms
-    // against 730 ms for the 64-row MFMA blocks on a d = 32 Gram block; in
-    // FP32 the bands are faster, 106 against 149 ms), else 64-row blocks
-    if (direct && !ga.split && ga.dpad <= SK_GRAM_DIRECT_DMAX)
+    // pairs too long for one workgroup's LDS: the FMA chain per strip (the
+    // skewed rows' HBM writes bound it) for d <= 32 in the path dtype (d = 32
+    // block: 74 ms FP32, 139 ms FP64, against 106 ms for the FP32 MFMA strip
+    // bands and 730 ms for the FP64 64-row MFMA blocks); otherwise MFMA strip
+    // bands where their tiles fit in LDS (the BF16 split, FP32 d <= 60), else
+    // 64-row blocks
+    const bool pair_fits = SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds;
+    if (direct && !ga.split &&
+        (ga.dpad <= SK_GRAM_DIRECT_DMAX || (ga.dpad <= SK_GRAM_STRIP_DMAX && !pair_fits)))
         return SkLaunch<R>::gram_strip(ga, strips, rows, P, st);
-    if (SkLaunch<R>::gram_pair_lds(ga.dpad, max_lx, max_ly) <= kGramPairLds)
-        return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
+    if (pair_fits) return SkLaunch<R>::gram_pair(ga, max_lx, max_ly, P, st);
     if (ga.dpad <= 60 && SkLaunch<R>::gram_band_lds(ga.dpad) <= kGramPairLds)
         return SkLaunch<R>::gram_band(ga, strips, rows, P, st);
-    if (direct && !ga.split && ga.dpad <= SK_GRAM_STRIP_DMAX)
-        return SkLaunch<R>::gram_strip(ga, strips, rows, P, st);
     return SkLaunch<R>::gram(ga, max_nsteps_pad / 64, P, st);
 }
 

@@ -35,11 +35,10 @@ def dev(a, dtype):
 # native, d <= 16: the FMA-chain kernel with a pair's increments in LDS (the
 # first two shapes), or one wave per strip with the y increments in an LDS
 # ring (the next two, whose increments exceed the LDS budget; the second has a
-# strip period above ly); MFMA for d > 16, except FP64 with d <= 32 on pairs
-# whose MFMA band tiles exceed the LDS budget (the last shape), which runs
-# the strip kernel.  mfma / bf16x3: the pair-resident
-# MFMA kernel, and for the last two shapes the strip-band MFMA kernel (FP32)
-# or the 64-row block kernel (FP64, whose band tiles exceed the LDS budget)
+# strip period above ly), also for 16 < d <= 32 on pairs too long for the
+# pair-resident MFMA kernel (the last shape); MFMA otherwise for d > 16.  mfma / bf16x3: the pair-resident
+# MFMA kernel, and for the long shapes the strip-band MFMA kernel (FP32) or
+# the 64-row block kernel (FP64, whose band tiles exceed the LDS budget)
 @pytest.mark.parametrize("dtype,mode", [(torch.float64, "native"), (torch.float32, "native"),
                                         (torch.float64, "mfma"), (torch.float32, "mfma"),
                                         (torch.float32, "bf16x3")])
