@@ -14,7 +14,9 @@ Inputs are resident on the GPU before timing.  Reported:
   against the FP64 oracle.
 * roofline: dominant kernel, algorithmic FLOPs / its HIP-event time.
 * cpu_baseline: the FP64 C oracle on the 48 x 64 block X[0:48] x Y[0:64]
-  (about 10-20 s on 16 host cores), all host threads OMP_NUM_THREADS allows.
+  (about 10-20 s on 16 host cores), all host threads OMP_NUM_THREADS allows;
+  its `single_core` entry times one thread on the 4 x 8 block, and `host`
+  names the CPU.
 * roofline.traffic: HBM bytes per launch of the dominant kernel from the
   committed counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by the
   same counters read for a plain 1 GiB device copy), reported only when the
@@ -115,6 +117,17 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
         json.dump(out, fh, indent=1)
         fh.write("\n")
     return 0
+
+
+def cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def traffic_for(label: str, kernel_name_hint: str | None = None):
@@ -498,6 +511,16 @@ def main(argv=None) -> int:
                                          "workload, forward only, FP64 C oracle (literal 0F1 "
                                          "at the Chebyshev extrema + Vandermonde solve)",
                                "seconds": c1 - c0}
+        # one core on a smaller block, and what the host is
+        sx, sy = 4, 8
+        s0 = time.perf_counter()
+        C.gram(Xb[:sx], Yb[:sy], C.INTERP, ORDER, threads=1)
+        s1 = time.perf_counter()
+        out["cpu_baseline"]["single_core"] = {
+            "value": sx * sy * STEPS * STEPS / (s1 - s0), "unit": "cell-updates/s",
+            "sample": f"{sx}x{sy} block X[0:{sx}] x Y[0:{sy}], one thread", "seconds": s1 - s0}
+        out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count(), "model": cpu_model(),
+                                       "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
     if not args.no_plain:
         npl = 16
         Xd = Xt.detach()[:1].double()

@@ -84,18 +84,27 @@ extern "C" {
 #define SK_ALGO_BATCHED 0 /* all pairs of a chunk in one wavefront launch   */
 #define SK_ALGO_PLAIN 1   /* one launch per pair, one workgroup sweeping the
                              anti-diagonals (FP64, forward only)             */
-#define SK_ALGO_PIPELINE 2 /* one pair at a time, its 64-row strips spread over
-                             co-resident workgroups that hand strip-boundary
-                             edges on through global memory (Section 3.2's
-                             wavefront over strips; for a few very long
-                             pairs).  Polynomial schemes.  Backward: pair
-                             lists only (SK_OP_PAIRS; Gram-mode backward
-                             entry points return SK_EUNSUPPORTED), where
-                             every pair with several strips runs a pipelined
-                             checkpoint sweep and a pipelined adjoint (the
-                             strips in reverse order).  A value that could
-                             not be completed (a bounded wait gave up) is
-                             written as NaN, and so is a gradient           */
+#define SK_ALGO_PIPELINE 2 /* the 64-row strips of every pair with several
+                             strips spread over co-resident workgroups that
+                             hand strip-boundary edges on through global
+                             memory (Section 3.2's wavefront over strips),
+                             the pairs of a chunk as one job list of
+                             strips; for few, long pairs.  Pairs of one
+                             strip run batched.  Gram calls build the job
+                             lists on the host and copy them into the head
+                             of the workspace (synchronising `stream` once);
+                             pairs calls run a one-shot plan with the
+                             pipeline on.  Polynomial schemes.  Backward
+                             (sigkernel_backward, both ops): every pair with
+                             several strips runs a pipelined checkpoint
+                             sweep and a pipelined adjoint (the strips in
+                             reverse order), the pairs of a chunk as one
+                             job list; pairs of one strip run batched.  The
+                             saved-state Gram calls (sigkernel_gram_save,
+                             sigkernel_gram_backward_saved) return
+                             SK_EUNSUPPORTED.  A value that could not be
+                             completed (a bounded wait gave up) is written
+                             as NaN, and so is a gradient                   */
 
 /* arithmetic of the increment Gram C_ij = <dx_i, dy_j> */
 #define SK_GRAM_NATIVE 0 /* products in the path dtype: a d-term FMA chain per cell for
@@ -174,11 +183,15 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
 
 /*
  * Reverse-mode derivative of a forward call (polynomial schemes; batched
- * algorithm, or for SK_OP_PAIRS the strip pipeline): the exact gradient of
- * the computed scheme (discrete adjoint of the cell recursion), for the loss
+ * algorithm or strip pipeline): the exact gradient of the computed scheme
+ * (discrete adjoint of the cell recursion), for the loss
  * L = sum_i gK[i] * K[i] with K[i] the forward outputs.  SK_OP_PAIRS runs a
  * one-shot plan (tuned configuration of the shape if there is one; with
  * SK_ALGO_PIPELINE every pair of several strips on the pipeline).
+ * SK_OP_GRAM with SK_ALGO_PIPELINE (paths of several strips) builds the
+ * pairs' descriptors and job lists on the host and copies them into the
+ * head of the workspace, synchronising `stream` once; size the workspace
+ * with sigkernel_gram_workspace(..., backward = 1) and the same params.
  *   op == SK_OP_GRAM : X, nx, lx_pts, Y, ny, ly_pts as in sigkernel_gram;
  *                      x_off, y_off ignored; gK has nx * ny entries;
  *                      gX (nx, lx_pts, d) and gY (ny, ly_pts, d) are

@@ -136,14 +136,19 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
 # ---------------------------------------------------------------------------
 def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
                   order: int = 4, gK_exp: Optional[torch.Tensor] = None,
-                  gram_mode: str = "native", symmetric: bool = False):
+                  gram_mode: str = "native", symmetric: bool = False, algo: str = "batched"):
     """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order).
-    ``symmetric`` (Y is X): returns (dL/dX with both contributions, None)."""
+    ``symmetric`` (Y is X): returns (dL/dX with both contributions, None).
+    ``algo`` "pipeline" runs pairs of several strips on the pipelined
+    checkpoint sweep and adjoint (for few, long paths; the call synchronises
+    the stream once to upload its job lists)."""
     X, Y = _dev(X), _dev(Y)
     if symmetric:
         Y = X
+    if algo not in ("batched", "pipeline"):
+        raise ValueError("gram_backward runs the batched algorithm or the strip pipeline")
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, "batched", gram_mode, L.SK_SYMMETRIC if symmetric else 0)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     if gK.shape != (nx, ny):
@@ -375,19 +380,41 @@ def _state_budget(device) -> int:
     return int(min(0.5 * free, cap))
 
 
+# Gram calls with fewer pairs than this run paths of several 64-row strips
+# on the strip pipeline: the batched algorithm gives every pair one wave,
+# which leaves most of the GPU's 256 CUs x 4 SIMDs idle (an 8 x 8 Gram of
+# 2049-point paths in R^16: backward 173 ms batched, 17 ms pipelined).
+PIPELINE_MAX_PAIRS = 2048
+
+
+def gram_algo(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx") -> str:
+    """"pipeline" for polynomial-scheme Gram calls of few pairs whose paths
+    span several strips, else "batched"."""
+    if scheme in ("fd", "fd2"):
+        return "batched"
+    strips = (X.shape[1] - 2) // 64 + 1 if X.shape[1] > 1 else 0
+    few = X.shape[0] * Y.shape[0] < PIPELINE_MAX_PAIRS
+    return "pipeline" if strips >= 2 and Y.shape[1] > 1 and few else "batched"
+
+
 class SigKernelGram(torch.autograd.Function):
     """Differentiable Gram matrix; the backward runs the library's adjoint
-    sweep (exact gradient of the computed scheme).  When the backward state
-    fits the memory budget the forward keeps it (gram_save) and the backward
-    starts from it; otherwise the backward recomputes it in chunks."""
+    sweep (exact gradient of the computed scheme).  Batched: when the
+    backward state fits the memory budget the forward keeps it (gram_save)
+    and the backward starts from it; otherwise the backward recomputes it in
+    chunks.  Pipeline (``algo``, by default gram_algo's choice): a forward,
+    then the pipelined backward, which recomputes the state."""
 
     @staticmethod
-    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native"):
+    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None):
         ctx.save_for_backward(X, Y)
         ctx.scheme, ctx.order, ctx.gram_mode = scheme, order, gram_mode
+        ctx.algo = algo or gram_algo(X, Y, scheme)
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
         ctx.state = None
+        if ctx.algo == "pipeline":
+            return gram(X, Y, scheme, order, algo="pipeline", gram_mode=gram_mode)
         if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
             if gram_state_size(X, Y, scheme, order, gram_mode) <= _state_budget(X.device):
                 K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode)
@@ -402,13 +429,13 @@ class SigKernelGram(torch.autograd.Function):
             gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
-            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, **kw)
-        return gX, gY, None, None, None
+            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, algo=ctx.algo, **kw)
+        return gX, gY, None, None, None, None
 
 
 def sig_gram(X, Y, scheme: str = "approx", order: int = 4,
-             gram_mode: str = "native") -> torch.Tensor:
-    return SigKernelGram.apply(X, Y, scheme, order, gram_mode)
+             gram_mode: str = "native", algo: Optional[str] = None) -> torch.Tensor:
+    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo)
 
 
 class SigKernelPairs(torch.autograd.Function):

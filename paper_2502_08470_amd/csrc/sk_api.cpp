@@ -60,11 +60,11 @@ struct ProfScope {
             a = b = nullptr;
             return;
         }
-        hipEventRecord(a, st);
+        (void)hipEventRecord(a, st);  // profiling only: a failed record times nothing
     }
     ~ProfScope() {
         if (!a) return;
-        hipEventRecord(b, st);
+        (void)hipEventRecord(b, st);
         std::lock_guard<std::mutex> g(g_prof_mu);
         g_prof_recs.push_back({name, a, b});
     }
@@ -173,11 +173,11 @@ SkTab<R> table_for(const sk_params& p) {
 // ---------------------------------------------------------------------------
 bool is_fd(const sk_params& p) { return p.scheme == SK_FD || p.scheme == SK_FD2; }
 
-// The strip pipeline's backward runs on pair lists (plans); Gram-mode
-// backward entry points reject it.
+// The saved-state Gram calls keep the batched backward's state; they reject
+// the strip pipeline (sigkernel_backward runs Gram calls on it).
 int check_gram_backward_algo(const sk_params* p) {
     if (p->algo == SK_ALGO_PIPELINE)
-        return fail(SK_EUNSUPPORTED, "the strip pipeline's backward takes pair lists (SK_OP_PAIRS)");
+        return fail(SK_EUNSUPPORTED, "the saved-state Gram calls run the batched algorithm");
     return SK_OK;
 }
 
@@ -553,8 +553,9 @@ int check_lds(const sk_params& p, int64_t max_ly, int64_t d) {
 }
 
 template <typename R>
-int pipe_pair(const sk_params& p, const R* x, int64_t lx_pts, const R* y, int64_t ly_pts, int64_t d,
-              R* K, int32_t* Kexp, int64_t k_idx, void* ws, size_t wsb, hipStream_t st);
+int gram_forward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                      int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+                      hipStream_t st);
 
 template <typename R>
 int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
@@ -564,15 +565,8 @@ int gram_forward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, in
     if (npairs == 0) return SK_OK;
     const int lam = lam_of(p);
     const int64_t lx = lxp - 1, ly = lyp - 1;
-    if (p.algo == SK_ALGO_PIPELINE) {
-        for (int64_t a = 0; a < nx; ++a)
-            for (int64_t b = 0; b < ny; ++b) {
-                const int rc = pipe_pair<R>(p, X + a * lxp * d, lxp, Y + b * lyp * d, lyp, d, K, Kexp,
-                                            a * ny + b, ws, wsb, st);
-                if (rc) return rc;
-            }
-        return SK_OK;
-    }
+    if (p.algo == SK_ALGO_PIPELINE)
+        return gram_forward_pipe<R>(X, nx, lxp, Y, ny, lyp, d, p, K, Kexp, ws, wsb, st);
     if (p.algo == SK_ALGO_PLAIN) {
         const int64_t need = std::max<int64_t>(((lx + ly) << lam) * (p.order + 1), 3 * ((lx << lam) + 1)) * 8;
         if (wsb < (size_t)need) return fail(SK_EWORKSPACE, "plain needs %lld bytes", (long long)need);
@@ -808,6 +802,175 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
         ra.nstrips = g.nstrips;
         ra.dxp = reinterpret_cast<const R*>((char*)ws + L.dxp);
         ra.dyp = reinterpret_cast<const R*>((char*)ws + L.dyp);
+        ra.gX = gX; ra.gY = gY;
+        SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
+    }
+    return SK_OK;
+}
+
+// Gram calls on the strip pipeline (SK_ALGO_PIPELINE).  Every pair of a
+// Gram call has the same geometry, so the chunk size, the per-pair
+// descriptors (chunk-relative workspace offsets, the same arrangement the
+// implicit Gram descriptors use, so the Gram reductions apply unchanged) and
+// the job lists are fixed on the host and uploaded once, ahead of the chunk
+// scratch: [descriptors of all pairs][jobs of a full chunk][jobs of the last
+// chunk][chunk scratch].  A job list holds the (checkpoint) sweep's jobs,
+// every pair's first strip, then every pair's second, ..., so that a strip's
+// predecessor always comes earlier in the list; a backward list continues
+// with the adjoint's, every pair's last strip first.
+struct GramPipePlan {
+    SkPairSizes per = {};
+    int64_t P = 0, nstrips = 0, desc = 0, jobs_full = 0, jobs_last = 0, scratch = 0, total = 0;
+};
+
+int gram_pipe_plan(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
+                   const sk_params& p, bool backward, size_t wsb, GramPipePlan* G) {
+    const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
+    const int es = (int)esize(p), lam = lam_of(p);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    G->per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, backward,
+                           2 * sk_gx_words(p.order, es), true);
+    G->nstrips = g.nstrips;
+    const int64_t dbytes = align_up(npairs * (int64_t)sizeof(SkPairDesc));
+    // job lists sized for chunks of every pair (an upper bound for any chunk)
+    const int64_t jbound = align_up((backward ? 2 : 1) * npairs * G->nstrips * (int64_t)sizeof(int2));
+    const int64_t head = dbytes + 2 * jbound;
+    if (wsb <= (size_t)head) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    G->P = gram_chunk(G->per, npairs, (size_t)es, backward, wsb - (size_t)head, p.order);
+    if (G->P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
+    G->desc = 0;
+    G->jobs_full = dbytes;
+    G->jobs_last = dbytes + jbound;
+    G->scratch = head;
+    G->total = head + layout_for(scale(G->per, G->P), G->P, (size_t)es, backward, false, p.order).total;
+    return SK_OK;
+}
+
+// Builds and uploads the descriptors and job lists (synchronises `st`).
+int gram_pipe_upload(const GramPipePlan& G, int64_t nx, int64_t lxp, int64_t ny, int64_t lyp,
+                     bool backward, char* base, hipStream_t st) {
+    const int64_t npairs = nx * ny;
+    const int ns = (int)G.nstrips;
+    std::vector<SkPairDesc> desc((size_t)npairs);
+    for (int64_t q = 0; q < npairs; ++q) {
+        const int64_t local = q % G.P;
+        SkPairDesc& e = desc[(size_t)q];
+        e.x_off = (q / ny) * lxp;
+        e.y_off = (q % ny) * lyp;
+        e.lx = (int32_t)(lxp - 1);
+        e.ly = (int32_t)(lyp - 1);
+        e.swap = 0;
+        // the forward writes K directly; the checkpoint pass's kernel values
+        // go to the chunk scratch
+        e.k_idx = backward ? local : q;
+        e.g_idx = q;
+        e.c_off = local * G.per.c; e.ck_off = local * G.per.ck; e.ce_off = local * G.per.ce;
+        e.qb_off = local * G.per.qb; e.qe_off = local * G.per.qe; e.dx_off = local * G.per.dx;
+        e.dy_off = local * G.per.dy; e.xb_off = local * G.per.xb; e.pg_off = local * G.per.pg;
+    }
+    auto job_list = [&](int64_t cnt) {
+        std::vector<int2> jobs;
+        jobs.reserve((size_t)((backward ? 2 : 1) * cnt * ns));
+        for (int s = 0; s < ns; ++s)
+            for (int64_t li = 0; li < cnt; ++li) jobs.push_back(make_int2((int)li, s));
+        if (backward)
+            for (int s = ns - 1; s >= 0; --s)
+                for (int64_t li = 0; li < cnt; ++li) jobs.push_back(make_int2((int)li, s));
+        return jobs;
+    };
+    const int64_t cnt_last = npairs - (npairs - 1) / G.P * G.P;
+    const std::vector<int2> jf = job_list(G.P), jl = job_list(cnt_last);
+    SK_TRY_HIP(hipMemcpyAsync(base + G.desc, desc.data(), desc.size() * sizeof(SkPairDesc),
+                              hipMemcpyHostToDevice, st), "descriptor upload");
+    SK_TRY_HIP(hipMemcpyAsync(base + G.jobs_full, jf.data(), jf.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st), "job list upload");
+    SK_TRY_HIP(hipMemcpyAsync(base + G.jobs_last, jl.data(), jl.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st), "job list upload");
+    SK_TRY_HIP(hipStreamSynchronize(st), "descriptor upload");
+    return SK_OK;
+}
+
+// Forward: paths of several strips (of the refined grid) on the pipeline,
+// the pairs of a chunk as one job list; others batched.
+template <typename R>
+int gram_forward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                      int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
+                      hipStream_t st) {
+    const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
+    const int lam = lam_of(p);
+    if (lx == 0 || ly == 0) {
+        SK_TRY_HIP(SkLaunch<R>::fill(K, npairs, (R)1, st), "fill");
+        if (Kexp) SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(Kexp), npairs, st), "fill");
+        return SK_OK;
+    }
+    if (sk_make_geom((int)(lx << lam), (int)(ly << lam)).nstrips < 2) {
+        sk_params q = p;
+        q.algo = SK_ALGO_BATCHED;
+        return gram_forward<R>(X, nx, lxp, Y, ny, lyp, d, q, K, Kexp, ws, wsb, st);
+    }
+    GramPipePlan G;
+    int rc = gram_pipe_plan(nx, lxp, ny, lyp, d, p, false, wsb, &G);
+    if (rc) return rc;
+    char* base = static_cast<char*>(ws);
+    if ((rc = gram_pipe_upload(G, nx, lxp, ny, lyp, false, base, st))) return rc;
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), false, false, p.order);
+    char* ws_c = base + G.scratch;
+    for (int64_t first = 0; first < npairs; first += G.P) {
+        const int64_t cnt = std::min(G.P, npairs - first);
+        const int2* jobs = reinterpret_cast<const int2*>(base + (cnt == G.P ? G.jobs_full : G.jobs_last));
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + G.desc) + first;
+        rc = run_chunk_forward_pipe<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly, jobs,
+                                       cnt * G.nstrips, ws_c, L, K, Kexp, st);
+        if (rc) return rc;
+    }
+    return SK_OK;
+}
+
+// Backward: the pipelined checkpoint sweep and adjoint per chunk, then the
+// Gram reductions; paths of one strip run the batched backward.
+template <typename R>
+int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                       int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX,
+                       R* gY, void* ws, size_t wsb, hipStream_t st) {
+    const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
+    if (npairs == 0 || lx == 0 || ly == 0 || sk_make_geom((int)lx, (int)ly).nstrips < 2)
+        return gram_backward<R>(X, nx, lxp, Y, ny, lyp, d, p, gK, gKexp, gX, gY, ws, wsb, st);
+    GramPipePlan G;
+    int rc = gram_pipe_plan(nx, lxp, ny, lyp, d, p, true, wsb, &G);
+    if (rc) return rc;
+    if ((rc = check_lds<R>(p, ly, d))) return rc;
+    char* base = static_cast<char*>(ws);
+    if ((rc = gram_pipe_upload(G, nx, lxp, ny, lyp, true, base, st))) return rc;
+    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    const int ns = g.nstrips;
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+    const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
+    char* ws_c = base + G.scratch;
+    R* kbuf = reinterpret_cast<R*>(ws_c + L.kbuf);
+    int32_t* kexp = reinterpret_cast<int32_t*>(ws_c + L.kexp);
+    for (int64_t first = 0; first < npairs; first += G.P) {
+        const int64_t cnt = std::min(G.P, npairs - first);
+        const int2* jobs = reinterpret_cast<const int2*>(base + (cnt == G.P ? G.jobs_full : G.jobs_last));
+        const int64_t njobs = cnt * ns;
+        SkPairSrc src;
+        std::memset(&src, 0, sizeof(src));
+        src.desc = reinterpret_cast<const SkPairDesc*>(base + G.desc) + first;
+        rc = run_chunk_prepare_pipe<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly, jobs,
+                                       njobs, ws_c, L, kbuf, kexp, st);
+        if (!rc)
+            rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, cnt, ns, jobs + njobs, njobs, ws_c, L, gK,
+                                           gKexp, st);
+        if (rc) return rc;
+        ReduceGramArgs<R> ra;
+        ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
+        ra.first = first; ra.count = cnt; ra.dx_stride = G.per.dx; ra.dy_stride = G.per.dy;
+        ra.nstrips = ns;
+        ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
+        ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
         ra.gX = gX; ra.gY = gY;
         SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
     }
@@ -1321,8 +1484,8 @@ int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipSt
                     best = cfg;
                 }
             }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     if (best_t < 0) return fail(SK_EWORKSPACE, "no configuration fits a workspace of %zu bytes", wsb);
     if ((rc = plan_build(P, best, wsb)) || (rc = plan_upload(P, ws, wsb, st))) return rc;
@@ -1362,87 +1525,9 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
     return SK_OK;
 }
 
-// ---------------------------------------------------------------------------
-// strip pipeline (SK_ALGO_PIPELINE): one pair at a time, its strips on
-// co-resident workgroups
-// ---------------------------------------------------------------------------
-struct PipeLayout {
-    int64_t c, xb, prog, abort, total;
-};
-
-// Workspace of one pair with lx, ly (unrefined) segments.
-PipeLayout pipe_layout(int64_t lx, int64_t ly, const sk_params& p) {
-    const int lam = lam_of(p);
-    const size_t es = esize(p);
-    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
-    PipeLayout L;
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) {
-        int64_t o = off;
-        off += align_up(bytes);
-        return o;
-    };
-    L.c = take((int64_t)g.nsteps_pad * SK_LANES * (int64_t)es);
-    L.xb = take(2 * (int64_t)g.ly * sk_gx_words(p.order, (int)es) * 4);
-    L.prog = take(4 * (int64_t)std::max(1, g.nstrips));
-    L.abort = take(4);
-    L.total = off;
-    return L;
-}
-
-// One pair: increment Gram into the skewed layout, then the pipelined sweep.
-template <typename R>
-int pipe_pair(const sk_params& p, const R* x, int64_t lx_pts, const R* y, int64_t ly_pts, int64_t d,
-              R* K, int32_t* Kexp, int64_t k_idx, void* ws, size_t wsb, hipStream_t st) {
-    const int lam = lam_of(p);
-    const int64_t lx = lx_pts - 1, ly = ly_pts - 1;
-    const PipeLayout L = pipe_layout(lx, ly, p);
-    if (wsb < (size_t)L.total)
-        return fail(SK_EWORKSPACE, "the strip pipeline needs %lld bytes", (long long)L.total);
-    char* w = static_cast<char*>(ws);
-    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
-    R* cskew = reinterpret_cast<R*>(w + L.c);
-    if (g.nsteps > 0) {
-        SkPairSrc src;
-        std::memset(&src, 0, sizeof(src));
-        src.ny = 1; src.lx_pts = lx_pts; src.ly_pts = ly_pts; src.first = 0; src.desc = nullptr;
-        src.stride = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, false, 0);
-        GramArgs<R> ga;
-        ga.X = x; ga.Y = y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam;
-        ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
-        SK_LAUNCH("gram", st, launch_gram(ga, 1, g.nsteps_pad, (int)lx, (int)ly, p.gram == SK_GRAM_NATIVE, st),
-                  "increment Gram");
-    }
-    int* prog = reinterpret_cast<int*>(w + L.prog);
-    int* abrt = reinterpret_cast<int*>(w + L.abort);
-    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), std::max(1, g.nstrips), st), "fill");
-    SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(abrt), 1, st), "fill");
-    PipeArgs<R> pa;
-    std::memset(&pa, 0, sizeof(pa));
-    pa.cskew = cskew; pa.tab = table_for<R>(p); pa.lx = g.lx; pa.ly = g.ly;
-    pa.K = K; pa.Kexp = Kexp; pa.k_idx = k_idx;
-    pa.xb = reinterpret_cast<unsigned*>(w + L.xb); pa.progress = prog; pa.abort = abrt;
-    pa.spin_limit = kPipeSpinLimit;
-    SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, false, st),
-              "pipelined strip sweep");
-    return SK_OK;
-}
-
-template <typename R>
-int pairs_pipe(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, int64_t npairs,
-               int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* ws, size_t wsb,
-               hipStream_t st) {
-    for (int64_t i = 0; i < npairs; ++i) {
-        const int rc = pipe_pair<R>(p, Xc + xo[i] * d, xo[i + 1] - xo[i], Yc + yo[i] * d,
-                                    yo[i + 1] - yo[i], d, K, Kexp, i, ws, wsb, st);
-        if (rc) return rc;
-    }
-    return SK_OK;
-}
-
 // One-shot pairs calls: a plan with the tuned configuration of this shape if
 // there is one, else longest-first, transposed, bucketed and pipelined
-// (SK_ALGO_PIPELINE: the backward of pairs calls, pipelined in any case).
+// (SK_ALGO_PIPELINE: pipelined in any case, forward and backward).
 int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
                  const sk_params& p, bool backward, size_t wsb) {
     plan_init(P, xo, yo, npairs, d, p, backward);
@@ -1480,9 +1565,9 @@ int sigkernel_profile_enable(int32_t on) {
     g_last_error.clear();
     std::lock_guard<std::mutex> g(g_prof_mu);
     for (ProfRec& r : g_prof_recs) {
-        hipEventSynchronize(r.stop);
-        hipEventDestroy(r.start);
-        hipEventDestroy(r.stop);
+        (void)hipEventSynchronize(r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
     }
     g_prof_recs.clear();
     g_prof.store(on != 0);
@@ -1512,13 +1597,17 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
                                 const sk_params* p, int32_t backward) {
     g_last_error.clear();
     if (check_params(p, backward != 0) || check_dims(d, backward != 0) ||
-        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y") ||
-        (backward && check_gram_backward_algo(p)))
+        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y"))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     const int lam = lam_of(*p);
-    if (p->algo == SK_ALGO_PIPELINE)
-        return std::max<size_t>(256, (size_t)pipe_layout(lx_pts - 1, ly_pts - 1, *p).total);
+    // the pipeline where the (refined) grid has several strips, else batched
+    if (p->algo == SK_ALGO_PIPELINE && nx * ny > 0 &&
+        sk_make_geom((int)((lx_pts - 1) << lam), (int)((ly_pts - 1) << lam)).nstrips >= 2) {
+        GramPipePlan G;
+        if (gram_pipe_plan(nx, lx_pts, ny, ly_pts, d, *p, backward != 0, kDefaultCap, &G)) return 0;
+        return std::max<size_t>(256, (size_t)G.total);
+    }
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t lx = lx_pts - 1, ly = ly_pts - 1;
         return (size_t)std::max<int64_t>(256, std::max<int64_t>(((lx + ly) << lam) * (p->order + 1),
@@ -1541,12 +1630,6 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     if (check_offsets(x_off, npairs, lam_of(*p), "x") || check_offsets(y_off, npairs, lam_of(*p), "y"))
         return 0;
     const int lam = lam_of(*p);
-    if (p->algo == SK_ALGO_PIPELINE && !backward) {
-        int64_t need = 256;
-        for (int64_t i = 0; i < npairs; ++i)
-            need = std::max(need, pipe_layout(x_off[i + 1] - x_off[i] - 1, y_off[i + 1] - y_off[i] - 1, *p).total);
-        return (size_t)need;
-    }
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t need = 256;
         for (int64_t i = 0; i < npairs; ++i) {
@@ -1602,13 +1685,6 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
         return rc;
     if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
-        if (p->algo == SK_ALGO_PIPELINE) {
-            if (p->dtype == SK_F32)
-                return pairs_pipe<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
-                                         npairs, d, *p, (float*)k, k_exp, ws, ws_bytes, stream);
-            return pairs_pipe<double>((const double*)Xcat, x_off, (const double*)Ycat, y_off,
-                                      npairs, d, *p, (double*)k, k_exp, ws, ws_bytes, stream);
-        }
         if (p->algo == SK_ALGO_PLAIN) {
             if (p->dtype == SK_F32)
                 return pairs_plain<float>((const float*)Xcat, x_off, (const float*)Ycat, y_off,
@@ -1640,7 +1716,6 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     if (rc) return rc;
     if (is_fd(*p)) return fail(SK_EUNSUPPORTED, "backward of the finite-difference scheme");
     if (op != SK_OP_GRAM && op != SK_OP_PAIRS) return fail(SK_EINVAL, "op %d", op);
-    if (op == SK_OP_GRAM && (rc = check_gram_backward_algo(p))) return rc;
     if (nx < 0 || (op == SK_OP_GRAM && ny < 0)) return fail(SK_EINVAL, "negative batch");
     if (op == SK_OP_GRAM) {
         if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
@@ -1651,6 +1726,15 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     if ((rc = check_symmetric(*p, op, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
+        if (op == SK_OP_GRAM && p->algo == SK_ALGO_PIPELINE) {
+            if (p->dtype == SK_F32)
+                return gram_backward_pipe<float>((const float*)X, nx, lx_pts, (const float*)Y, ny,
+                                                 ly_pts, d, *p, (const float*)gK, gK_exp,
+                                                 (float*)gX, (float*)gY, ws, ws_bytes, stream);
+            return gram_backward_pipe<double>((const double*)X, nx, lx_pts, (const double*)Y, ny,
+                                              ly_pts, d, *p, (const double*)gK, gK_exp,
+                                              (double*)gX, (double*)gY, ws, ws_bytes, stream);
+        }
         if (op == SK_OP_GRAM) {
             if (p->dtype == SK_F32)
                 return gram_backward<float>((const float*)X, nx, lx_pts, (const float*)Y, ny,

@@ -930,18 +930,16 @@ template <typename R>
 struct PipeArgs {
     const R* cskew;        // skewed cell constants (rows s Tp + t of a pair)
     SkTab<R> tab;
-    int32_t lx, ly;        // one pair: grid segments (refined)
-    R* K;
+    R* K;                  // indexed by the descriptors' k_idx
     int32_t* Kexp;         // nullable
-    int64_t k_idx;         // one pair: output index
     unsigned* xb;          // records [2][ly][sk_gx_words] per pair
     int* progress;         // [nstrips] per pair, zero at launch: columns handed over
     int* abort;            // zero at launch
     int32_t spin_limit;    // polls before a wait gives up
-    const SkPairDesc* desc;  // job list mode: pair descriptors
-    const int2* jobs;        // job list mode: (pair, strip)
+    const SkPairDesc* desc;  // pair descriptors
+    const int2* jobs;        // (pair, strip), every pair's strips in increasing order
     int64_t njobs;
-    int32_t lam;             // job list mode: dyadic refinement of the pairs' grids
+    int32_t lam;             // dyadic refinement of the pairs' grids
     R* ck;                   // CKPT: per strip, [sk_pipe_steps / S][2][N + 1][64]
     int32_t* ce;             // CKPT: per strip, [sk_pipe_steps / S][64 + 1]
     R* qb;                   // CKPT: strip-boundary edges [nstrips][ly][N + 1]
@@ -982,44 +980,20 @@ __device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* ab
 template <typename R, int N, int TMAX, bool CKPT, int S>
 __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
     const int r = threadIdx.x;
-    if (!a.desc) {
-        const SkGeom g1 = sk_make_geom(a.lx, a.ly);
-        if (g1.nsteps == 0) {
-            if (blockIdx.x == 0 && r == 0) sk_write_k(a.K, a.Kexp, a.k_idx, (R)1, 0);
-            return;
-        }
-    }
     constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
     constexpr int XR = (8 * GXW + 63) / 64;
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
-    const int64_t njobs = a.desc ? a.njobs : sk_make_geom(a.lx, a.ly).nstrips;
-    for (int64_t q = blockIdx.x; q < njobs; q += gridDim.x) {
+    for (int64_t q = blockIdx.x; q < a.njobs; q += gridDim.x) {
         // the job: strip s of a pair with geometry g and arrays at these bases
-        int s;
-        SkGeom g;
-        const R* cbase;
-        unsigned* xbase;
-        int* prog;
-        int64_t k_idx;
-        SkPairDesc pd = {};
-        if (a.desc) {
-            const int2 jb = a.jobs[q];
-            pd = a.desc[jb.x];
-            s = jb.y;
-            g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
-            cbase = a.cskew + pd.c_off;
-            xbase = a.xb + pd.xb_off;
-            prog = a.progress + pd.pg_off;
-            k_idx = pd.k_idx;
-        } else {
-            s = (int)q;
-            g = sk_make_geom(a.lx, a.ly);
-            cbase = a.cskew;
-            xbase = a.xb;
-            prog = a.progress;
-            k_idx = a.k_idx;
-        }
+        const int2 jb = a.jobs[q];
+        const SkPairDesc pd = a.desc[jb.x];
+        const int s = jb.y;
+        const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+        const R* cbase = a.cskew + pd.c_off;
+        unsigned* xbase = a.xb + pd.xb_off;
+        int* prog = a.progress + pd.pg_off;
+        const int64_t k_idx = pd.k_idx;
         const int ly = g.ly;
         const int nloc = sk_pipe_steps(ly);
         // lane 0 reads column t at local step t

@@ -195,14 +195,12 @@ static hipError_t sk_pipe_n(const PipeArgs<R>& a, bool ckpt, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
     const void* kern = ckpt ? reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, true, S>)
                             : reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, false, S>);
-    // jobs: the strips of the single pair, or the job list
-    const int64_t njobs = a.desc ? a.njobs : (int64_t)sk_make_geom(a.lx, a.ly).nstrips;
-    return sk_coop_launch(kern, a, njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
+    return sk_coop_launch(kern, a, a.njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
 }
 
 template <typename R>
 hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, bool ckpt, hipStream_t st) {
-    if (ckpt && !a.desc) return hipErrorInvalidValue;
+    if (!a.desc || !a.jobs || a.njobs <= 0) return hipErrorInvalidValue;
     constexpr int T = SkTailMax<R>::value;
     switch (N) {
         case 2: return interp ? sk_pipe_n<R, 2, T>(a, ckpt, st) : sk_pipe_n<R, 2, 0>(a, ckpt, st);

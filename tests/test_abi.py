@@ -103,7 +103,7 @@ def test_backward_rejections():
     assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
     assert bwd(P(dyadic=1)) == L.SK_EUNSUPPORTED  # hybrid refined grid: forward only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
-    assert bwd(P(algo=2)) == L.SK_EUNSUPPORTED  # strip pipeline backward: pair lists only
+    assert bwd(P(algo=2, scheme=0, order=0)) == L.SK_EUNSUPPORTED  # pipeline: polynomial schemes
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED
     assert bwd(P(), op=4) == L.SK_EINVAL
     # SK_SYMMETRIC needs a Gram call whose Y is X (same pointer and shape)
@@ -249,8 +249,13 @@ def test_pipeline_workspace_queries():
     # pair lists: the pipeline's backward is a plan
     assert lib.sigkernel_pairs_workspace(xo, yo, 2, 3, P(algo=2), 1) > 0
     assert lib.sigkernel_pairs_workspace(xo, yo, 2, 3, P(algo=2), 0) > 0
-    # Gram-mode backward entry points refuse the pipeline
-    assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 1) == 0
-    assert "pair lists" in L.last_error()
+    # Gram backward on the pipeline: descriptors of all pairs and two job
+    # lists ahead of the chunk scratch; a Gram of one-strip pairs runs batched
+    assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 1) > \
+        lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(), 1) > 0
+    assert lib.sigkernel_gram_workspace(2, 60, 2, 200, 3, P(algo=2), 1) == \
+        lib.sigkernel_gram_workspace(2, 60, 2, 200, 3, P(), 1)
     assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 0) > 0
+    # the saved-state Gram calls keep the batched backward's state
     assert lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P(algo=2)) == 0
+    assert "batched" in L.last_error()

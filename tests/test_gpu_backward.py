@@ -191,14 +191,17 @@ def test_saved_state_backward_matches_recompute(sk, dtype):
         tol = 1e-12 if dtype == torch.float64 else 1e-6
         torch.testing.assert_close(gX1, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
         torch.testing.assert_close(gY1, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
-    # autograd uses the saved path when the state fits
-    Xg = X.clone().requires_grad_(True)
-    Yg = Y.clone().requires_grad_(True)
-    (sk.sig_gram(Xg, Yg, "approx", 5) * gK).sum().backward()
+    # batched autograd uses the saved path when the state fits; these six
+    # pairs of 3-strip paths default to the strip pipeline, the same gradient
     gX0, gY0 = sk.gram_backward(X, Y, gK, "approx", 5)
     tol = 1e-12 if dtype == torch.float64 else 1e-6
-    torch.testing.assert_close(Xg.grad, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
-    torch.testing.assert_close(Yg.grad, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
+    assert sk.api.gram_algo(X, Y) == "pipeline"
+    for algo in ("batched", None):
+        Xg = X.clone().requires_grad_(True)
+        Yg = Y.clone().requires_grad_(True)
+        (sk.sig_gram(Xg, Yg, "approx", 5, algo=algo) * gK).sum().backward()
+        torch.testing.assert_close(Xg.grad, gX0, rtol=tol, atol=tol * float(gX0.abs().max()))
+        torch.testing.assert_close(Yg.grad, gY0, rtol=tol, atol=tol * float(gY0.abs().max()))
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
@@ -215,9 +218,10 @@ def test_symmetric_gram_backward(sk, dtype, tol):
     assert none is None
     scale = float(ref.abs().max())
     torch.testing.assert_close(gS, ref, rtol=tol, atol=tol * scale)
-    Xg = X.clone().requires_grad_(True)
-    (sk.sig_gram(Xg, Xg, "approx", 5) * gK).sum().backward()
-    torch.testing.assert_close(Xg.grad, ref, rtol=tol, atol=tol * scale)
+    for algo in ("batched", "pipeline"):
+        Xg = X.clone().requires_grad_(True)
+        (sk.sig_gram(Xg, Xg, "approx", 5, algo=algo) * gK).sum().backward()
+        torch.testing.assert_close(Xg.grad, ref, rtol=tol, atol=tol * scale)
 
 
 def test_bf16x3_backward_matches_native(sk):

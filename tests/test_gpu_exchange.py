@@ -77,12 +77,16 @@ def test_long_gram_gradients(sk, dtype, tol):
     gK = rng.normal(size=(2, 1))
     Xt = dev(X, dtype).requires_grad_(True)
     Yt = dev(Y, dtype).requires_grad_(True)
-    (sk.sig_gram(Xt, Yt, "approx", 5) * dev(gK, dtype)).sum().backward()
+    # the batched backward (its exchange variant) through autograd, against
+    # the direct call and the pipelined backward
+    (sk.sig_gram(Xt, Yt, "approx", 5, algo="batched") * dev(gK, dtype)).sum().backward()
     gX, gY = Xt.grad.cpu().double().numpy(), Yt.grad.cpu().double().numpy()
-    gX2, gY2 = sk.gram_backward(dev(X, dtype), dev(Y, dtype), dev(gK, dtype), "approx", 5)
     scale = max(np.abs(gX).max(), np.abs(gY).max())
-    np.testing.assert_allclose(gX2.cpu().double().numpy(), gX, rtol=0, atol=tol * scale)
-    np.testing.assert_allclose(gY2.cpu().double().numpy(), gY, rtol=0, atol=tol * scale)
+    for algo in ("batched", "pipeline"):
+        gX2, gY2 = sk.gram_backward(dev(X, dtype), dev(Y, dtype), dev(gK, dtype), "approx", 5,
+                                    algo=algo)
+        np.testing.assert_allclose(gX2.cpu().double().numpy(), gX, rtol=0, atol=tol * scale)
+        np.testing.assert_allclose(gY2.cpu().double().numpy(), gY, rtol=0, atol=tol * scale)
 
     def loss(Xv, Yv):
         m, e = C.gram(Xv, Yv, C.APPROX, 5)

@@ -252,3 +252,94 @@ def test_pipeline_backward_graph_replays_match_eager(sk):
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
         assert torch.equal(gX, gX0) and torch.equal(gY, gY0), rep
+
+
+# ---------------------------------------------------------------------------
+# Gram backward on the pipeline
+# ---------------------------------------------------------------------------
+def _gram_backward_ws(sk, X, Y, gK, scheme, order, ws_bytes=None, symmetric=False):
+    """sigkernel_backward(SK_OP_GRAM) with the pipeline and a chosen workspace."""
+    import ctypes
+    from paper_2502_08470_amd import _lib as L
+    from paper_2502_08470_amd import api as A
+    p = A._params(X.dtype, scheme, order, "pipeline", "native",
+                  L.SK_SYMMETRIC if symmetric else 0)
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    lib = L.lib()
+    if ws_bytes is None:
+        ws_bytes = lib.sigkernel_gram_workspace(nx, lxp, ny, lyp, d, ctypes.byref(p), 1)
+    ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device="cuda")
+    gX = torch.full_like(X, float("nan"))
+    gY = gX if symmetric else torch.full_like(Y, float("nan"))
+    vp = ctypes.c_void_p
+    L.check(lib.sigkernel_backward(L.SK_OP_GRAM, vp(X.data_ptr()), None, nx, lxp,
+                                   vp(Y.data_ptr()), None, ny, lyp, d, ctypes.byref(p),
+                                   vp(gK.data_ptr()), None, vp(gX.data_ptr()),
+                                   vp(gY.data_ptr()), vp(ws.data_ptr()), int(ws_bytes),
+                                   vp(torch.cuda.current_stream().cuda_stream)))
+    return gX, gY
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 5), ("interp", 6)])
+def test_pipeline_gram_backward_fp64_matches_batched_and_fd(sk, scheme, order):
+    # 3 x 2 Gram: x of 200 points (4 strips, a 7-row last strip), y of 90;
+    # every chunk size: all six pairs, then chunks of 4 + 2 (a partial last
+    # chunk with its own job list)
+    from oracle import c_oracle as C
+    log_banner(f"pipeline gram backward fp64 {scheme} {order}")
+    rng = np.random.default_rng(89)
+    X = bm_paths(rng, 3, 199, 3, 0.4 / np.sqrt(200))
+    Y = bm_paths(rng, 2, 89, 3, 0.4 / np.sqrt(90))
+    gK = rng.normal(size=(3, 2))
+    Xt, Yt, gKt = dev(X, torch.float64), dev(Y, torch.float64), dev(gK, torch.float64)
+    gXb, gYb = sk.gram_backward(Xt, Yt, gKt, scheme, order)
+    gXp, gYp = sk.gram_backward(Xt, Yt, gKt, scheme, order, algo="pipeline")
+    assert torch.isfinite(gXp).all() and torch.isfinite(gYp).all()
+    torch.testing.assert_close(gXp, gXb, rtol=1e-11, atol=1e-11 * float(gXb.abs().max()))
+    torch.testing.assert_close(gYp, gYb, rtol=1e-11, atol=1e-11 * float(gYb.abs().max()))
+    import ctypes
+    from paper_2502_08470_amd import _lib as L
+    from paper_2502_08470_amd import api as A
+    p = A._params(torch.float64, scheme, order, "pipeline")
+    ws4 = L.lib().sigkernel_gram_workspace(2, 200, 2, 90, 3, ctypes.byref(p), 1) + (64 << 10)
+    gXc, gYc = _gram_backward_ws(sk, Xt, Yt, gKt, scheme, order, ws_bytes=ws4)
+    assert torch.equal(gXc, gXp) and torch.equal(gYc, gYp)
+    # central differences of the FP64 oracle on the Gram loss
+    kind = C.APPROX if scheme == "approx" else C.INTERP
+    h = 1e-4
+    gXn, gYn = gXp.cpu().numpy(), gYp.cpu().numpy()
+    for side, a, t, k in [("x", 0, 199, 2), ("x", 2, 64, 0), ("x", 1, 130, 1), ("y", 1, 45, 2),
+                          ("y", 0, 0, 0)]:
+        def loss(Xv, Yv):
+            m, e = C.gram(Xv, Yv, kind, order)
+            return float(np.sum(gK * np.ldexp(m, e)))
+        V = (X if side == "x" else Y).copy()
+        V[a, t, k] += h
+        lp = loss(V, Y) if side == "x" else loss(X, V)
+        V[a, t, k] -= 2 * h
+        lm = loss(V, Y) if side == "x" else loss(X, V)
+        fd = (lp - lm) / (2 * h)
+        g = gXn[a, t, k] if side == "x" else gYn[a, t, k]
+        assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (side, a, t, k, g, fd)
+
+
+def test_pipeline_gram_backward_fp32_symmetric_and_one_strip(sk):
+    # FP32 interpolation N = 6 (the bench's scheme) on a symmetric 4 x 4 Gram
+    # of 300-point paths: both contributions in gX, as the batched backward;
+    # one-strip paths fall through to the batched backward unchanged
+    log_banner("pipeline gram backward fp32 symmetric")
+    rng = np.random.default_rng(90)
+    X = bm_paths(rng, 4, 299, 8, 0.5 / np.sqrt(300)).astype(np.float32)
+    gK = rng.normal(size=(4, 4)).astype(np.float32)
+    Xt, gKt = dev(X, torch.float32), dev(gK, torch.float32)
+    gXb, _ = sk.gram_backward(Xt, Xt, gKt, "interp", 6, symmetric=True)
+    gXp, _ = sk.gram_backward(Xt, Xt, gKt, "interp", 6, symmetric=True, algo="pipeline")
+    assert torch.isfinite(gXp).all()
+    for a in range(4):
+        s = float(gXb[a].abs().max())
+        assert float((gXp[a] - gXb[a]).abs().max()) <= 2e-5 * s, a
+    Xs = Xt[:, :60].contiguous()
+    g1, _ = sk.gram_backward(Xs, Xs, gKt, "interp", 6, symmetric=True)
+    g2, _ = sk.gram_backward(Xs, Xs, gKt, "interp", 6, symmetric=True, algo="pipeline")
+    assert torch.equal(g1, g2)
