@@ -257,6 +257,8 @@ def workload_study(large_rows: int = 256) -> int:
       tuned plan, the same replayed from a HIP graph, and forward + backward;
     * the MMD sets: unbiased MMD^2 (approximation N=8, FP32) forward and
       backward through autograd (three Grams, XX and YY symmetric);
+    * a 4x4 Gram of 8193-point paths in R^8 (approximation N=8, FP32):
+      forward and backward on the strip pipeline and batched;
     * the first `large_rows` rows of the 1024x1024 d=32 Gram (approximation
       N=8, FP32 sweep, BF16 3-way split Gram, exponents), forward, and the
       first 16 rows forward + backward."""
@@ -341,6 +343,22 @@ def workload_study(large_rows: int = 256) -> int:
                        "fwd_bwd_computed_cells_per_s": computed / ms * 1e3}
     del Xt, Yt
     say("MMD sets done")
+
+    # few pairs of long paths: the Gram calls' strip pipeline (autograd's
+    # choice for them) against the batched algorithm
+    X, Y = W.long_paths_gram(0)
+    Xt, Yt = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+    cells = float(X.shape[0] * Y.shape[0] * (X.shape[1] - 1) * (Y.shape[1] - 1))
+    gK = torch.ones(X.shape[0], Y.shape[0], device=dev)
+    lp = {"algo_autograd": sk.gram_algo(Xt, Yt, "approx"), "cells": cells}
+    for algo, reps in (("pipeline", 3), ("batched", 1)):
+        fms = best_ms(lambda: sk.gram(Xt, Yt, "approx", 8, algo=algo), reps)
+        bms = best_ms(lambda: sk.gram_backward(Xt, Yt, gK, "approx", 8, algo=algo), reps)
+        lp[algo] = {"forward_ms": fms, "backward_ms": bms,
+                    "fwd_bwd_cells_per_s": cells / (fms + bms) * 1e3}
+    out["long_paths_gram"] = lp
+    del Xt, Yt
+    say("long paths Gram done")
 
     X, Y = W.large_gram(0)
     Xt = torch.tensor(X[:large_rows], device=dev)

@@ -44,3 +44,11 @@ def test_large_gram_cell_constant_scale():
     dy = np.diff(y.astype(np.float64), axis=1)
     c = np.einsum("aid,bjd->abij", dx, dy)
     assert 0.8 < c.std() < 1.2
+
+
+def test_long_paths_gram():
+    x, y = W.long_paths_gram(0, n=2, steps=512)
+    assert x.shape == (2, 513, 8) and y.shape == (2, 513, 8) and x.dtype == np.float32
+    assert np.all(x[:, 0] == 0) and not np.array_equal(x, y)
+    inc = np.diff(x.astype(np.float64), axis=1)
+    assert abs(inc.std() - 0.5 / np.sqrt(512)) < 0.002

@@ -144,6 +144,17 @@ def long_pair(seed: int = 0, steps: int = 16384, d: int = 8):
     return x.astype(np.float32), y.astype(np.float32)
 
 
+def long_paths_gram(seed: int = 0, n: int = 4, steps: int = 8192, d: int = 8):
+    """A small Gram of long paths (few pairs, each spanning many 64-row
+    strips): X then Y, n R^d Brownian paths each with `steps` steps of std
+    0.5/sqrt(steps).  FP32 (rounded here)."""
+    rng = np.random.default_rng(seed)
+    std = 0.5 / np.sqrt(steps)
+    X = brownian(rng, n, steps, d, std)
+    Y = brownian(rng, n, steps, d, std)
+    return X.astype(np.float32), Y.astype(np.float32)
+
+
 WORKLOADS = {
     "small_fp64_gram": small_fp64_gram,
     "batched_interp_gram": batched_interp_gram,
@@ -151,4 +162,5 @@ WORKLOADS = {
     "mmd_sets": mmd_sets,
     "large_gram": large_gram,
     "long_pair": long_pair,
+    "long_paths_gram": long_paths_gram,
 }
