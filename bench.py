@@ -258,7 +258,8 @@ def workload_study(large_rows: int = 256) -> int:
     * the MMD sets: unbiased MMD^2 (approximation N=8, FP32) forward and
       backward through autograd (three Grams, XX and YY symmetric);
     * a 4x4 Gram of 8193-point paths in R^8 (approximation N=8, FP32):
-      forward and backward on the strip pipeline and batched;
+      forward and backward on the strip pipeline and batched, and the
+      autograd step (pipeline, saved state);
     * the first `large_rows` rows of the 1024x1024 d=32 Gram (approximation
       N=8, FP32 sweep, BF16 3-way split Gram, exponents), forward, and the
       first 16 rows forward + backward."""
@@ -356,8 +357,10 @@ def workload_study(large_rows: int = 256) -> int:
         bms = best_ms(lambda: sk.gram_backward(Xt, Yt, gK, "approx", 8, algo=algo), reps)
         lp[algo] = {"forward_ms": fms, "backward_ms": bms,
                     "fwd_bwd_cells_per_s": cells / (fms + bms) * 1e3}
+    Xg = Xt.clone().requires_grad_(True)
+    lp["autograd_fwd_bwd_ms"] = best_ms(lambda: sk.sig_gram(Xg, Yt, "approx", 8).sum().backward(), 3)
     out["long_paths_gram"] = lp
-    del Xt, Yt
+    del Xt, Yt, Xg
     say("long paths Gram done")
 
     X, Y = W.large_gram(0)

@@ -99,12 +99,10 @@ extern "C" {
                              several strips runs a pipelined checkpoint
                              sweep and a pipelined adjoint (the strips in
                              reverse order), the pairs of a chunk as one
-                             job list; pairs of one strip run batched.  The
-                             saved-state Gram calls (sigkernel_gram_save,
-                             sigkernel_gram_backward_saved) return
-                             SK_EUNSUPPORTED.  A value that could not be
-                             completed (a bounded wait gave up) is written
-                             as NaN, and so is a gradient                   */
+                             job list; pairs of one strip run batched; the
+                             saved-state Gram calls likewise.  A value that
+                             could not be completed (a bounded wait gave up)
+                             is written as NaN, and so is a gradient        */
 
 /* arithmetic of the increment Gram C_ij = <dx_i, dy_j> */
 #define SK_GRAM_NATIVE 0 /* products in the path dtype: a d-term FMA chain per cell for
@@ -314,7 +312,9 @@ int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32
  * from that state (which it also uses as scratch).  Calling it with a state
  * not produced by sigkernel_gram_save for the same arguments gives undefined
  * results.  Errors as for sigkernel_backward; SK_EWORKSPACE when the state
- * is too small.
+ * is too small.  With SK_ALGO_PIPELINE (paths of several strips) the state
+ * also holds the pairs' descriptors and job lists, which sigkernel_gram_save
+ * copies in (synchronising `stream` once); both calls take the same params.
  */
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p);

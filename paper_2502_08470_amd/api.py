@@ -212,9 +212,9 @@ def cell_constants(X: torch.Tensor, Y: torch.Tensor, gram_mode: str = "native") 
 
 
 def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
-                    order: int = 4, gram_mode: str = "native") -> int:
+                    order: int = 4, gram_mode: str = "native", algo: str = "batched") -> int:
     """Bytes of the backward state kept by gram_save for these shapes."""
-    p = _params(X.dtype, scheme, order, "batched", gram_mode)
+    p = _params(X.dtype, scheme, order, algo, gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     nb = L.lib().sigkernel_gram_state_size(nx, lxp, ny, lyp, d, ctypes.byref(p))
@@ -224,16 +224,18 @@ def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
 
 
 def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-              return_exp: bool = False, gram_mode: str = "native"):
+              return_exp: bool = False, gram_mode: str = "native", algo: str = "batched"):
     """Gram matrix plus the state its backward needs: returns (K, state) or
-    (K, K_exp, state).  Pass the state to gram_backward_saved."""
+    (K, K_exp, state).  Pass the state to gram_backward_saved with the same
+    ``algo`` ("pipeline": the strip pipeline's checkpoint sweep; the call
+    synchronises the stream once to upload its job lists)."""
     X, Y = _dev(X), _dev(Y)
-    p = _params(X.dtype, scheme, order, "batched", gram_mode)
+    p = _params(X.dtype, scheme, order, algo, gram_mode)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
     Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
-    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode), X.device)
+    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode, algo), X.device)
     L.check(L.lib().sigkernel_gram_save(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
                                         _ptr(K), _ptr(Ke), _ptr(state), state.numel(),
                                         _stream(X)))
@@ -243,13 +245,14 @@ def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: i
 def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
                         state: torch.Tensor, scheme: str = "approx", order: int = 4,
                         gK_exp: Optional[torch.Tensor] = None, gram_mode: str = "native",
-                        symmetric: bool = False):
-    """Same result as gram_backward, from the state left by gram_save(X, Y)."""
+                        symmetric: bool = False, algo: str = "batched"):
+    """Same result as gram_backward, from the state left by gram_save(X, Y)
+    with the same ``algo``."""
     X, Y = _dev(X), _dev(Y)
     if symmetric:
         Y = X
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, "batched", gram_mode, L.SK_SYMMETRIC if symmetric else 0)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     gX = torch.empty_like(X)
@@ -402,8 +405,8 @@ class SigKernelGram(torch.autograd.Function):
     sweep (exact gradient of the computed scheme).  Batched: when the
     backward state fits the memory budget the forward keeps it (gram_save)
     and the backward starts from it; otherwise the backward recomputes it in
-    chunks.  Pipeline (``algo``, by default gram_algo's choice): a forward,
-    then the pipelined backward, which recomputes the state."""
+    chunks.  ``algo`` (by default gram_algo's choice) selects the batched
+    algorithm or the strip pipeline for both."""
 
     @staticmethod
     def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None):
@@ -413,23 +416,22 @@ class SigKernelGram(torch.autograd.Function):
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
         ctx.state = None
-        if ctx.algo == "pipeline":
-            return gram(X, Y, scheme, order, algo="pipeline", gram_mode=gram_mode)
         if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
-            if gram_state_size(X, Y, scheme, order, gram_mode) <= _state_budget(X.device):
-                K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode)
+            size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo)
+            if size <= _state_budget(X.device):
+                K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode, algo=ctx.algo)
                 return K
-        return gram(X, Y, scheme, order, gram_mode=gram_mode)
+        return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode)
 
     @staticmethod
     def backward(ctx, gK):
         X, Y = ctx.saved_tensors
-        kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric)
+        kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric, algo=ctx.algo)
         if ctx.state is not None:
             gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
-            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, algo=ctx.algo, **kw)
+            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, **kw)
         return gX, gY, None, None, None, None
 
 

@@ -173,14 +173,6 @@ SkTab<R> table_for(const sk_params& p) {
 // ---------------------------------------------------------------------------
 bool is_fd(const sk_params& p) { return p.scheme == SK_FD || p.scheme == SK_FD2; }
 
-// The saved-state Gram calls keep the batched backward's state; they reject
-// the strip pipeline (sigkernel_backward runs Gram calls on it).
-int check_gram_backward_algo(const sk_params* p) {
-    if (p->algo == SK_ALGO_PIPELINE)
-        return fail(SK_EUNSUPPORTED, "the saved-state Gram calls run the batched algorithm");
-    return SK_OK;
-}
-
 int check_params(const sk_params* p, bool backward) {
     if (!p) return fail(SK_EINVAL, "params is NULL");
     if (p->dtype != SK_F32 && p->dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", p->dtype);
@@ -974,6 +966,79 @@ int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t 
         ra.gX = gX; ra.gY = gY;
         SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
     }
+    return SK_OK;
+}
+
+// Saved state on the pipeline: the backward's whole state in one chunk
+// (descriptors and job lists at its head), kept between a forward that
+// also stores the checkpoints and the backward that starts from them.
+bool gram_pipe_applies(const sk_params& p, int64_t nx, int64_t lxp, int64_t ny, int64_t lyp) {
+    return p.algo == SK_ALGO_PIPELINE && nx * ny > 0 && lxp > 1 && lyp > 1 &&
+           sk_make_geom((int)(lxp - 1), (int)(lyp - 1)).nstrips >= 2;
+}
+
+int gram_pipe_state(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
+                    const sk_params& p, GramPipePlan* G) {
+    int rc = gram_pipe_plan(nx, lxp, ny, lyp, d, p, true, SIZE_MAX, G);
+    if (!rc && G->P != nx * ny) rc = fail(SK_EWORKSPACE, "the saved state needs one chunk");
+    return rc;
+}
+
+template <typename R>
+int gram_save_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64_t lyp,
+                   int64_t d, const sk_params& p, R* K, int32_t* Kexp, void* state, size_t bytes,
+                   hipStream_t st) {
+    GramPipePlan G;
+    int rc = gram_pipe_state(nx, lxp, ny, lyp, d, p, &G);
+    if (rc) return rc;
+    if ((size_t)G.total > bytes)
+        return fail(SK_EWORKSPACE, "state needs %lld bytes, got %zu", (long long)G.total, bytes);
+    if ((rc = check_lds<R>(p, lyp - 1, d))) return rc;
+    char* base = static_cast<char*>(state);
+    if ((rc = gram_pipe_upload(G, nx, lxp, ny, lyp, true, base, st))) return rc;
+    const SkGeom g = sk_make_geom((int)(lxp - 1), (int)(lyp - 1));
+    const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.desc = reinterpret_cast<const SkPairDesc*>(base + G.desc);
+    // one chunk: the descriptors' chunk-local k_idx is the pair index
+    return run_chunk_prepare_pipe<R>(p, X, Y, d, src, G.P, g.nsteps_pad, (int)(lxp - 1), (int)(lyp - 1),
+                                     reinterpret_cast<const int2*>(base + G.jobs_full),
+                                     G.P * G.nstrips, base + G.scratch, L, K, Kexp, st);
+}
+
+template <typename R>
+int gram_backward_saved_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny,
+                             int64_t lyp, int64_t d, const sk_params& p, const R* gK,
+                             const int32_t* gKexp, R* gX, R* gY, void* state, size_t bytes,
+                             hipStream_t st) {
+    GramPipePlan G;
+    int rc = gram_pipe_state(nx, lxp, ny, lyp, d, p, &G);
+    if (rc) return rc;
+    if ((size_t)G.total > bytes)
+        return fail(SK_EWORKSPACE, "state needs %lld bytes, got %zu", (long long)G.total, bytes);
+    char* base = static_cast<char*>(state);
+    const int ns = (int)G.nstrips;
+    const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
+    char* ws_c = base + G.scratch;
+    SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
+    SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
+    SkPairSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.desc = reinterpret_cast<const SkPairDesc*>(base + G.desc);
+    const int64_t njobs = G.P * ns;
+    rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, G.P, ns,
+                                   reinterpret_cast<const int2*>(base + G.jobs_full) + njobs, njobs,
+                                   ws_c, L, gK, gKexp, st);
+    if (rc) return rc;
+    ReduceGramArgs<R> ra;
+    ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
+    ra.first = 0; ra.count = G.P; ra.dx_stride = G.per.dx; ra.dy_stride = G.per.dy;
+    ra.nstrips = ns;
+    ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
+    ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
+    ra.gX = gX; ra.gY = gY;
+    SK_LAUNCH("reduce", st, SkLaunch<R>::reduce_gram(ra, st), "gradient reduction");
     return SK_OK;
 }
 
@@ -1971,9 +2036,14 @@ size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t
                                  const sk_params* p) {
     g_last_error.clear();
     if (check_params(p, true) || check_dims(d, true) || check_len(lx_pts, 0, "x") ||
-        check_len(ly_pts, 0, "y") || check_gram_backward_algo(p))
+        check_len(ly_pts, 0, "y"))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
+    if (gram_pipe_applies(*p, nx, lx_pts, ny, ly_pts)) {
+        GramPipePlan G;
+        if (gram_pipe_state(nx, lx_pts, ny, ly_pts, d, *p, &G)) return 0;
+        return std::max<size_t>(256, (size_t)G.total);
+    }
     SkPairSizes per;
     Layout L;
     if (p->dtype == SK_F32) gram_state_layout<float>(nx, lx_pts, ny, ly_pts, d, *p, &per, &L);
@@ -1987,13 +2057,19 @@ int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y
     g_last_error.clear();
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
-    if (!rc) rc = check_gram_backward_algo(p);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
     if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
     if (nx * ny == 0) return SK_OK;
     if (!X || !Y || !K || !state) return fail(SK_EINVAL, "NULL pointer");
     try {
+        if (gram_pipe_applies(*p, nx, lx_pts, ny, ly_pts)) {
+            if (p->dtype == SK_F32)
+                return gram_save_pipe<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts,
+                                             d, *p, (float*)K, K_exp, state, state_bytes, stream);
+            return gram_save_pipe<double>((const double*)X, nx, lx_pts, (const double*)Y, ny, ly_pts,
+                                          d, *p, (double*)K, K_exp, state, state_bytes, stream);
+        }
         if (p->dtype == SK_F32)
             return gram_save<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts, d, *p,
                                     (float*)K, K_exp, state, state_bytes, stream);
@@ -2011,13 +2087,23 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
     g_last_error.clear();
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
-    if (!rc) rc = check_gram_backward_algo(p);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
     if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
     if ((rc = check_symmetric(*p, SK_OP_GRAM, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !state) return fail(SK_EINVAL, "NULL pointer");
     try {
+        if (gram_pipe_applies(*p, nx, lx_pts, ny, ly_pts)) {
+            if (p->dtype == SK_F32)
+                return gram_backward_saved_pipe<float>((const float*)X, nx, lx_pts, (const float*)Y,
+                                                       ny, ly_pts, d, *p, (const float*)gK, gK_exp,
+                                                       (float*)gX, (float*)gY, state, state_bytes,
+                                                       stream);
+            return gram_backward_saved_pipe<double>((const double*)X, nx, lx_pts, (const double*)Y,
+                                                    ny, ly_pts, d, *p, (const double*)gK, gK_exp,
+                                                    (double*)gX, (double*)gY, state, state_bytes,
+                                                    stream);
+        }
         if (p->dtype == SK_F32)
             return gram_backward_saved<float>((const float*)X, nx, lx_pts, (const float*)Y, ny,
                                               ly_pts, d, *p, (const float*)gK, gK_exp, (float*)gX,

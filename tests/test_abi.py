@@ -256,6 +256,9 @@ def test_pipeline_workspace_queries():
     assert lib.sigkernel_gram_workspace(2, 60, 2, 200, 3, P(algo=2), 1) == \
         lib.sigkernel_gram_workspace(2, 60, 2, 200, 3, P(), 1)
     assert lib.sigkernel_gram_workspace(2, 300, 2, 200, 3, P(algo=2), 0) > 0
-    # the saved-state Gram calls keep the batched backward's state
-    assert lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P(algo=2)) == 0
-    assert "batched" in L.last_error()
+    # the saved state on the pipeline: one chunk plus descriptors and jobs;
+    # one-strip paths keep the batched state
+    assert lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P(algo=2)) > \
+        lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P()) > 0
+    assert lib.sigkernel_gram_state_size(2, 60, 2, 200, 3, P(algo=2)) == \
+        lib.sigkernel_gram_state_size(2, 60, 2, 200, 3, P())

@@ -343,3 +343,24 @@ def test_pipeline_gram_backward_fp32_symmetric_and_one_strip(sk):
     g1, _ = sk.gram_backward(Xs, Xs, gKt, "interp", 6, symmetric=True)
     g2, _ = sk.gram_backward(Xs, Xs, gKt, "interp", 6, symmetric=True, algo="pipeline")
     assert torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("scheme,order", [("approx", 5), ("interp", 6)])
+def test_pipeline_gram_saved_state(sk, scheme, order):
+    # gram_save on the pipeline (the checkpoint sweep's values) against the
+    # batched forward; gram_backward_saved against the recomputing
+    # pipelined backward (the same kernels from the same state)
+    log_banner(f"pipeline gram saved state {scheme} {order}")
+    rng = np.random.default_rng(91)
+    X = dev(bm_paths(rng, 3, 199, 3, 0.4 / np.sqrt(200)), torch.float64)
+    Y = dev(bm_paths(rng, 2, 89, 3, 0.4 / np.sqrt(90)), torch.float64)
+    gK = dev(rng.normal(size=(3, 2)), torch.float64)
+    K1, state = sk.gram_save(X, Y, scheme, order, algo="pipeline")
+    K0 = sk.gram(X, Y, scheme, order)
+    torch.testing.assert_close(K1, K0, rtol=1e-14, atol=0)
+    gX1, gY1 = sk.gram_backward_saved(X, Y, gK, state, scheme, order, algo="pipeline")
+    gX0, gY0 = sk.gram_backward(X, Y, gK, scheme, order, algo="pipeline")
+    assert torch.equal(gX1, gX0) and torch.equal(gY1, gY0)
+    # the state's size query: the pipeline's own, larger than the batched one
+    assert state.numel() == sk.gram_state_size(X, Y, scheme, order, algo="pipeline") > \
+        sk.gram_state_size(X, Y, scheme, order)
