@@ -28,6 +28,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
        python bench.py --accuracy-study   (synthetic re-run of the paper's accuracy tables)
        python bench.py --long-pair 16384  (strip pipeline on one long pair)
+       python bench.py --long-gram        (4x4 Gram of long paths, pipeline vs batched)
        python bench.py --workloads        (time of every named workload)
 """
 from __future__ import annotations
@@ -248,6 +249,54 @@ def long_pair_study(steps: int = 16384) -> int:
     return 0
 
 
+def long_gram_study() -> int:
+    """A 4x4 Gram of 8193-point R^8 Brownian paths (approximation N = 8,
+    FP32), forward + backward as autograd runs it: on the strip pipeline
+    (gram_save, then gram_backward_saved: checkpoint sweep, adjoint,
+    contraction, reduction) and batched (forward, then a recomputing
+    backward).  Kernel times are HIP events on the launch stream (library
+    profiler), mean of 5 (pipeline) or 1 (batched) steps after a warm-up."""
+    import torch
+    import paper_2502_08470_amd as sk
+    from paper_2502_08470_amd import _lib
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    X, Y = W.long_paths_gram(0)
+    Xt, Yt = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+    gK = torch.ones(X.shape[0], Y.shape[0], device=dev)
+    cells = float(X.shape[0] * Y.shape[0] * (X.shape[1] - 1) * (Y.shape[1] - 1))
+    names = ("gram", "sweep", "sweep_ckpt", "sweep_ckpt_pipe", "adjoint", "adjoint_pipe",
+             "contract", "reduce")
+
+    def step_pipeline():
+        K, state = sk.gram_save(Xt, Yt, "approx", 8, algo="pipeline")
+        sk.gram_backward_saved(Xt, Yt, gK, state, "approx", 8, algo="pipeline")
+
+    def step_batched():
+        sk.gram(Xt, Yt, "approx", 8)
+        sk.gram_backward(Xt, Yt, gK, "approx", 8)
+
+    rows = []
+    for algo, fn, reps in (("pipeline", step_pipeline, 5), ("batched", step_batched, 1)):
+        fn()
+        torch.cuda.synchronize()
+        _lib.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        kern = {n: _lib.profile_read(n)[0] / reps for n in names}
+        _lib.profile_enable(False)
+        rows.append({"algo": algo, "fwd_bwd_ms": ms, "cells_per_s": cells / (ms * 1e-3),
+                     "kernel_ms": {n: v for n, v in kern.items() if v > 0}})
+        print(f"[bench] long-paths Gram {algo}: {ms:.2f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({"study": "4x4 Gram of 8193-point paths in R^8, approximation N=8, FP32, "
+                               "forward + backward", "cells": cells, "rows": rows}), flush=True)
+    return 0
+
+
 def workload_study(large_rows: int = 256) -> int:
     """Time of each named workload on one GPU with its cell count (inputs
     resident on the GPU; best of a few calls after a warm-up):
@@ -408,6 +457,8 @@ def main(argv=None) -> int:
                     help="summarise two rocprofv3 --pmc runs into HBM bytes per dispatch")
     ap.add_argument("--accuracy-study", action="store_true",
                     help="MAPE of every scheme vs the converged kernel (paper's accuracy tables)")
+    ap.add_argument("--long-gram", action="store_true",
+                    help="forward + backward of a 4x4 Gram of 8193-point paths, pipeline vs batched")
     ap.add_argument("--long-pair", type=int, default=0, metavar="STEPS",
                     help="strip pipeline vs batched on one pair of STEPS-step paths")
     ap.add_argument("--workloads", action="store_true",
@@ -419,6 +470,8 @@ def main(argv=None) -> int:
         return accuracy_study()
     if args.long_pair:
         return long_pair_study(args.long_pair)
+    if args.long_gram:
+        return long_gram_study()
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
