@@ -364,3 +364,30 @@ def test_pipeline_gram_saved_state(sk, scheme, order):
     # the state's size query: the pipeline's own, larger than the batched one
     assert state.numel() == sk.gram_state_size(X, Y, scheme, order, algo="pipeline") > \
         sk.gram_state_size(X, Y, scheme, order)
+
+
+def test_pipeline_gram_forward_chunks(sk):
+    # the Gram forward on the pipeline with a workspace of 4 pairs' chunk for
+    # a 3 x 2 Gram (chunks of 4 + 2, the last with its own job list): the
+    # same values as the whole Gram in one chunk, and as the batched forward
+    import ctypes
+    from paper_2502_08470_amd import _lib as L
+    from paper_2502_08470_amd import api as A
+    log_banner("pipeline gram forward chunks")
+    rng = np.random.default_rng(92)
+    X = dev(bm_paths(rng, 3, 199, 3, 0.4 / np.sqrt(200)), torch.float64)
+    Y = dev(bm_paths(rng, 2, 89, 3, 0.4 / np.sqrt(90)), torch.float64)
+    K1 = sk.gram(X, Y, "approx", 6, algo="pipeline")
+    K0 = sk.gram(X, Y, "approx", 6)
+    assert torch.equal(K1, K0)
+    p = A._params(torch.float64, "approx", 6, "pipeline")
+    lib = L.lib()
+    ws4 = lib.sigkernel_gram_workspace(2, 200, 2, 90, 3, ctypes.byref(p), 0) + (16 << 10)
+    assert ws4 < lib.sigkernel_gram_workspace(3, 200, 2, 90, 3, ctypes.byref(p), 0)
+    ws = torch.empty(int(ws4), dtype=torch.uint8, device="cuda")
+    K = torch.full((3, 2), float("nan"), dtype=torch.float64, device="cuda")
+    vp = ctypes.c_void_p
+    L.check(lib.sigkernel_gram(vp(X.data_ptr()), 3, 200, vp(Y.data_ptr()), 2, 90, 3,
+                               ctypes.byref(p), vp(K.data_ptr()), None, vp(ws.data_ptr()),
+                               int(ws4), vp(torch.cuda.current_stream().cuda_stream)))
+    assert torch.equal(K, K1)
