@@ -101,3 +101,62 @@ def test_random_backward_batched_matches_pipeline(sk, i):
     for a, b in ((gXp, gXb), (gYp, gYb)):
         scale = float(b.abs().max()) if b.numel() else 0.0
         torch.testing.assert_close(a, b, rtol=1e-10, atol=1e-10 * max(scale, 1e-300))
+
+
+def draw_pairs_case(i):
+    rng = np.random.default_rng(5000 + i)
+    scheme = ["approx", "interp"][int(rng.integers(0, 2))]
+    dtype = [torch.float64, torch.float32][int(rng.integers(0, 2))]
+    order = int(rng.integers(2, 9))
+    npairs = int(rng.integers(1, 13))
+    d = int(rng.integers(1, 25))
+    lx = rng.integers(1, 400, size=npairs)
+    ly = rng.integers(1, 400, size=npairs)
+    xs = [bm_paths(rng, 1, int(n) - 1, d, 0.3 / np.sqrt(n))[0] for n in lx]
+    ys = [bm_paths(rng, 1, int(n) - 1, d, 0.3 / np.sqrt(n))[0] for n in ly]
+    cfg = [bool(v) for v in rng.integers(0, 2, size=4)]
+    return dict(scheme=scheme, order=order, dtype=dtype, xs=xs, ys=ys, cfg=cfg)
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_random_pair_plans_match_oracle(sk, i):
+    # ragged pair lists through a backward plan in a random configuration
+    # (order, transposition, LDS classes, strip pipeline): forward against
+    # the oracle, and the saved-state backward against the plan's
+    # recomputing backward
+    from oracle import c_oracle as C
+    c = draw_pairs_case(i)
+    dtype, xs, ys = c["dtype"], c["xs"], c["ys"]
+    log_banner(f"random pairs {i}: {c['scheme']} {c['order']} {dtype} cfg {c['cfg']} "
+               f"lengths {[len(a) for a in xs]} x {[len(b) for b in ys]}")
+    if dtype == torch.float32:
+        xs = [a.astype(np.float32).astype(np.float64) for a in xs]
+        ys = [b.astype(np.float32).astype(np.float64) for b in ys]
+    xl = [torch.tensor(a, dtype=dtype, device="cuda") for a in xs]
+    yl = [torch.tensor(b, dtype=dtype, device="cuda") for b in ys]
+    Xc, Yc = torch.cat(xl, 0), torch.cat(yl, 0)
+    plan = sk.PairsPlan(xl, yl, c["scheme"], c["order"], backward=True)
+    plan.configure(*c["cfg"])
+    n = len(xs)
+    k = torch.empty(n, dtype=dtype, device="cuda")
+    ke = torch.empty(n, dtype=torch.int32, device="cuda")
+    plan.forward(Xc, Yc, k, ke)
+    m, e = C.pairs(xs, ys, C.APPROX if c["scheme"] == "approx" else C.INTERP, c["order"])
+    err = rel_err_exp(k.cpu().double().numpy(), ke.cpu().numpy(), m, e)
+    cells = np.array([(len(a) - 1) * (len(b) - 1) for a, b in zip(xs, ys)], dtype=np.float64)
+    if dtype == torch.float64:
+        tol = 1e-9 + 1e-14 * cells if c["scheme"] == "interp" else 1e-11
+    else:
+        tol = 1e-4
+    assert np.all(err <= tol), (err, tol)
+    gk = torch.tensor(np.random.default_rng(i).normal(size=n), dtype=dtype, device="cuda")
+    gX0, gY0 = torch.empty_like(Xc), torch.empty_like(Yc)
+    plan.backward(Xc, Yc, gk, gX0, gY0)
+    try:
+        k1 = torch.empty_like(k)
+        plan.forward_save(Xc, Yc, k1)
+    except sk.SigKernelError:
+        return  # the saved state needs the backward in one chunk
+    gX1, gY1 = torch.empty_like(Xc), torch.empty_like(Yc)
+    plan.backward_saved(Xc, Yc, gk, gX1, gY1)
+    assert torch.equal(gX1, gX0) and torch.equal(gY1, gY0)
