@@ -136,8 +136,10 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
 # ---------------------------------------------------------------------------
 def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
                   order: int = 4, gK_exp: Optional[torch.Tensor] = None,
-                  gram_mode: str = "native", symmetric: bool = False, algo: str = "batched"):
-    """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order).
+                  gram_mode: str = "native", symmetric: bool = False, algo: str = "batched",
+                  dyadic: int = 0):
+    """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order,
+    dyadic=dyadic).
     ``symmetric`` (Y is X): returns (dL/dX with both contributions, None).
     ``algo`` "pipeline" runs pairs of several strips on the pipelined
     checkpoint sweep and adjoint (for few, long paths; the call synchronises
@@ -148,7 +150,8 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
     if algo not in ("batched", "pipeline"):
         raise ValueError("gram_backward runs the batched algorithm or the strip pipeline")
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0,
+                dyadic=dyadic)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     if gK.shape != (nx, ny):
@@ -168,7 +171,8 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
 
 
 def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int = 4,
-                   gk_exp: Optional[torch.Tensor] = None, algo: str = "batched"):
+                   gk_exp: Optional[torch.Tensor] = None, algo: str = "batched",
+                   dyadic: int = 0):
     """Gradients of sum(gk * pairs(xs, ys)) with respect to the concatenated
     points; returns (gXcat, gYcat, x_offsets, y_offsets).  ``algo`` "batched"
     uses the tuned (or default) plan configuration of this shape; "pipeline"
@@ -180,7 +184,7 @@ def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int 
     d = Xc.shape[1]
     if algo not in ("batched", "pipeline"):
         raise ValueError("pairs_backward runs the batched algorithm or the strip pipeline")
-    p = _params(Xc.dtype, scheme, order, algo)
+    p = _params(Xc.dtype, scheme, order, algo, dyadic=dyadic)
     lib = L.lib()
     gk = _dev(gk.to(Xc.dtype))
     gX = torch.empty_like(Xc)
@@ -212,9 +216,10 @@ def cell_constants(X: torch.Tensor, Y: torch.Tensor, gram_mode: str = "native") 
 
 
 def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
-                    order: int = 4, gram_mode: str = "native", algo: str = "batched") -> int:
+                    order: int = 4, gram_mode: str = "native", algo: str = "batched",
+                    dyadic: int = 0) -> int:
     """Bytes of the backward state kept by gram_save for these shapes."""
-    p = _params(X.dtype, scheme, order, algo, gram_mode)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     nb = L.lib().sigkernel_gram_state_size(nx, lxp, ny, lyp, d, ctypes.byref(p))
@@ -224,18 +229,19 @@ def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
 
 
 def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-              return_exp: bool = False, gram_mode: str = "native", algo: str = "batched"):
+              return_exp: bool = False, gram_mode: str = "native", algo: str = "batched",
+              dyadic: int = 0):
     """Gram matrix plus the state its backward needs: returns (K, state) or
     (K, K_exp, state).  Pass the state to gram_backward_saved with the same
     ``algo`` ("pipeline": the strip pipeline's checkpoint sweep; the call
     synchronises the stream once to upload its job lists)."""
     X, Y = _dev(X), _dev(Y)
-    p = _params(X.dtype, scheme, order, algo, gram_mode)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
     Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
-    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode, algo), X.device)
+    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode, algo, dyadic), X.device)
     L.check(L.lib().sigkernel_gram_save(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
                                         _ptr(K), _ptr(Ke), _ptr(state), state.numel(),
                                         _stream(X)))
@@ -245,14 +251,15 @@ def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: i
 def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
                         state: torch.Tensor, scheme: str = "approx", order: int = 4,
                         gK_exp: Optional[torch.Tensor] = None, gram_mode: str = "native",
-                        symmetric: bool = False, algo: str = "batched"):
+                        symmetric: bool = False, algo: str = "batched", dyadic: int = 0):
     """Same result as gram_backward, from the state left by gram_save(X, Y)
-    with the same ``algo``."""
+    with the same ``algo`` and ``dyadic``."""
     X, Y = _dev(X), _dev(Y)
     if symmetric:
         Y = X
     gK = _dev(gK.to(X.dtype))
-    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0,
+                dyadic=dyadic)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     gX = torch.empty_like(X)
@@ -278,7 +285,7 @@ class PairsPlan:
     (outputs are written into the tensors passed in)."""
 
     def __init__(self, xs, ys, scheme: str = "approx", order: int = 4, backward: bool = False,
-                 gram_mode: str = "native"):
+                 gram_mode: str = "native", dyadic: int = 0):
         Xc, xo = _concat(xs)
         Yc, yo = _concat(ys)
         if len(xo) != len(yo):
@@ -286,7 +293,7 @@ class PairsPlan:
         self.npairs, self.d = len(xo) - 1, int(Xc.shape[1])
         self.dtype, self.device = Xc.dtype, Xc.device
         self.x_off, self.y_off = xo, yo
-        self._p = _params(Xc.dtype, scheme, order, "batched", gram_mode)
+        self._p = _params(Xc.dtype, scheme, order, "batched", gram_mode, dyadic=dyadic)
         self._lib = L.lib()
         h = ctypes.c_void_p(0)
         L.check(self._lib.sigkernel_plan_create(_i64arr(xo), _i64arr(yo), self.npairs, self.d,

@@ -189,8 +189,8 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dyadic < 0) return fail(SK_EINVAL, "dyadic refinement %d < 0", p->dyadic);
         if (p->dyadic > SK_MAX_DYADIC_ORDER)
             return fail(SK_EUNSUPPORTED, "dyadic refinement %d > %d", p->dyadic, SK_MAX_DYADIC_ORDER);
-        if (p->dyadic > 0 && backward)
-            return fail(SK_EUNSUPPORTED, "backward of the refined-grid (hybrid) scheme");
+        if (p->dyadic > 0 && backward && p->algo == SK_ALGO_PIPELINE)
+            return fail(SK_EUNSUPPORTED, "backward of the refined-grid (hybrid) scheme on the strip pipeline");
         if (p->order < SK_MIN_POLY_ORDER)
             return fail(SK_EINVAL, "polynomial order %d < %d", p->order, SK_MIN_POLY_ORDER);
         if (p->order > SK_MAX_POLY_ORDER)
@@ -300,7 +300,7 @@ int ckpt_stride(const sk_params& p) {
 // workspace layout of one chunk
 // ---------------------------------------------------------------------------
 struct Layout {
-    int64_t cskew, gskew, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, xb, pg, total;
+    int64_t cskew, gskew, gcu, ck, ce, qb, qe, dxp, dyp, kbuf, kexp, desc, xb, pg, total;
 };
 
 // Region sizes for P pairs with total per-array element counts `z` (sum over
@@ -315,6 +315,7 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
     };
     L.cskew = take(z.c * (int64_t)es);
     L.gskew = backward ? take(z.c * (int64_t)es) : off;
+    L.gcu = backward ? take(z.cu * (int64_t)es) : off;  // refined grids only
     L.ck = backward ? take(z.ck * (int64_t)es) : off;
     L.ce = backward ? take(z.ce * 4) : off;
     L.qb = backward ? take(z.qb * (int64_t)es) : off;
@@ -331,13 +332,14 @@ Layout layout_for(const SkPairSizes& z, int64_t P, size_t es, bool backward, boo
 }
 
 SkPairSizes scale(const SkPairSizes& z, int64_t P) {
-    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P, z.dx * P, z.dy * P, z.xb * P, z.pg * P};
+    SkPairSizes o = {z.c * P, z.ck * P, z.ce * P, z.qb * P, z.qe * P,
+                     z.dx * P, z.dy * P, z.xb * P, z.pg * P, z.cu * P};
     return o;
 }
 
 SkPairSizes add(const SkPairSizes& a, const SkPairSizes& b) {
-    SkPairSizes o = {a.c + b.c, a.ck + b.ck, a.ce + b.ce, a.qb + b.qb,
-                     a.qe + b.qe, a.dx + b.dx, a.dy + b.dy, a.xb + b.xb, a.pg + b.pg};
+    SkPairSizes o = {a.c + b.c, a.ck + b.ck, a.ce + b.ce, a.qb + b.qb, a.qe + b.qe,
+                     a.dx + b.dx, a.dy + b.dy, a.xb + b.xb, a.pg + b.pg, a.cu + b.cu};
     return o;
 }
 
@@ -463,7 +465,7 @@ int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
 
 template <typename R>
 int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P,
-                 int max_strips, char* ws, const Layout& L, hipStream_t st);
+                 int max_strips, char* ws, const Layout& L, hipStream_t st, int64_t gsrc = -1);
 
 // Backward of a chunk of strip-pipeline pairs, first half: increment Gram
 // and the pipelined checkpoint sweep over the forward job list (kernel
@@ -618,7 +620,7 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
-    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = 0;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam_of(p);
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
     SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st), "increment Gram");
     SweepArgs<R> sa;
@@ -632,17 +634,20 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
     sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     sa.gx_cols = gx_cols_fwd(p);
+    sa.lam = lam_of(p);
     SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, ring,
-                                                       max_ly > sa.gx_cols, st), "checkpoint sweep");
+                                                       grid_cols(p, max_ly) > sa.gx_cols, st), "checkpoint sweep");
     return SK_OK;
 }
 
-// dL/dc (skewed) -> per-pair partials dL/d(dx), dL/d(dy).
+// dL/dc (skewed; at byte offset gsrc, default the adjoint's output) ->
+// per-pair partials dL/d(dx), dL/d(dy).
 template <typename R>
 int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_t P,
-                 int max_strips, char* ws, const Layout& L, hipStream_t st) {
+                 int max_strips, char* ws, const Layout& L, hipStream_t st, int64_t gsrc) {
     ContractArgs<R> ca;
-    ca.X = X; ca.Y = Y; ca.d = d; ca.src = src; ca.gskew = reinterpret_cast<const R*>(ws + L.gskew);
+    ca.X = X; ca.Y = Y; ca.d = d; ca.src = src;
+    ca.gskew = reinterpret_cast<const R*>(ws + (gsrc >= 0 ? gsrc : L.gskew));
     ca.dxp = reinterpret_cast<R*>(ws + L.dxp);
     ca.dyp = reinterpret_cast<R*>(ws + L.dyp);
     SK_LAUNCH("contract", st, SkLaunch<R>::contract(ca, max_strips, P, st), "gradient contraction");
@@ -653,8 +658,9 @@ int run_contract(const R* X, const R* Y, int64_t d, const SkPairSrc& src, int64_
 // state left by run_chunk_prepare.
 template <typename R>
 int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
-                      const SkPairSrc& src, int64_t P, int max_ly, int ring, int max_strips, char* ws,
-                      const Layout& L, const R* gK, const int32_t* gKexp, hipStream_t st) {
+                      const SkPairSrc& src, int64_t P, int max_ly, int ring, int max_strips,
+                      int max_nsteps_pad, char* ws, const Layout& L, const R* gK,
+                      const int32_t* gKexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     AdjArgs<R> aa;
     std::memset(&aa, 0, sizeof(aa));
@@ -667,9 +673,18 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     aa.gx_cols = gx_cols_adj(p);
+    aa.lam = lam_of(p);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, ring,
-                                                  max_ly > aa.gx_cols, st), "adjoint sweep");
-    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
+                                                  grid_cols(p, max_ly) > aa.gx_cols, st), "adjoint sweep");
+    if (aa.lam == 0) return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
+    // refined grid: dL/dc' of the sub-cells folded onto the unrefined grid,
+    // whose geometry the contraction and the reductions use
+    FoldArgs<R> fa;
+    fa.src = src; fa.lam = aa.lam;
+    fa.gref = reinterpret_cast<const R*>(ws + L.gskew);
+    fa.gout = reinterpret_cast<R*>(ws + L.gcu);
+    SK_LAUNCH("fold", st, SkLaunch<R>::fold_refined(fa, max_nsteps_pad, P, st), "refined-grid fold");
+    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st, L.gcu);
 }
 
 template <typename R>
@@ -686,7 +701,8 @@ int run_chunk_backward(const sk_params& p, const R* X, const R* Y, int64_t d,
     int rc = run_chunk_prepare<R>(p, X, Y, d, src, P, max_nsteps_pad, max_lx, max_ly, ring_f, ws, L, kbuf,
                                   kexp, st);
     if (rc) return rc;
-    return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, ring_a, max_strips, ws, L, gK, gKexp, st);
+    return run_chunk_adjoint<R>(p, X, Y, d, src, P, max_ly, ring_a, max_strips, max_nsteps_pad, ws, L,
+                                gK, gKexp, st);
 }
 
 // Forward that keeps the whole backward state of a Gram call in `state`
@@ -695,7 +711,7 @@ template <typename R>
 int gram_state_layout(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
                       const sk_params& p, SkPairSizes* per, Layout* L) {
     const int64_t npairs = nx * ny;
-    *per = sk_pair_sizes((int)(lxp - 1), (int)(lyp - 1), 0, p.order, ckpt_stride(p), d, true,
+    *per = sk_pair_sizes((int)(lxp - 1), (int)(lyp - 1), lam_of(p), p.order, ckpt_stride(p), d, true,
                          xb_words_of(p, (int)(lyp - 1)));
     *L = layout_for(scale(*per, npairs), npairs, sizeof(R), true, false, p.order);
     return SK_OK;
@@ -718,7 +734,8 @@ int gram_save(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, int64
     }
     int rc = check_lds<R>(p, ly, d);
     if (rc) return rc;
-    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    const int lam = lam_of(p);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
     SkPairSrc src;
     std::memset(&src, 0, sizeof(src));
     src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
@@ -741,17 +758,20 @@ int gram_backward_saved(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t
     if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
     int rc = check_lds<R>(p, ly, d);
     if (rc) return rc;
-    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    // sweeps on the (refined) grid; contraction and reductions on the unrefined one
+    const int lam = lam_of(p);
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    const int nstrips_u = sk_make_geom((int)lx, (int)ly).nstrips;
     SkPairSrc src;
     std::memset(&src, 0, sizeof(src));
     src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = 0;
-    rc = run_chunk_adjoint<R>(p, X, Y, d, src, npairs, (int)ly, ring_adj_of(p, (int)ly), g.nstrips,
-                              (char*)state, L, gK, gKexp, st);
+    rc = run_chunk_adjoint<R>(p, X, Y, d, src, npairs, (int)ly, ring_adj_of(p, (int)ly), nstrips_u,
+                              g.nsteps_pad, (char*)state, L, gK, gKexp, st);
     if (rc) return rc;
     ReduceGramArgs<R> ra;
     ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
     ra.first = 0; ra.count = npairs; ra.dx_stride = per.dx; ra.dy_stride = per.dy;
-    ra.nstrips = g.nstrips;
+    ra.nstrips = nstrips_u;
     ra.dxp = reinterpret_cast<const R*>((char*)state + L.dxp);
     ra.dyp = reinterpret_cast<const R*>((char*)state + L.dyp);
     ra.gX = gX; ra.gY = gY;
@@ -770,7 +790,8 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
         SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
         return SK_OK;
     }
-    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, 0, p.order, ckpt_stride(p), d, true, xb_words_of(p, (int)ly));
+    const int lam = lam_of(p);
+    const SkPairSizes per = sk_pair_sizes((int)lx, (int)ly, lam, p.order, ckpt_stride(p), d, true, xb_words_of(p, (int)ly));
     const int64_t P = gram_chunk(per, npairs, sizeof(R), true, wsb, p.order);
     if (P <= 0) return fail(SK_EWORKSPACE, "workspace of %zu bytes holds no pair", wsb);
     int rc = check_lds<R>(p, ly, d);
@@ -778,20 +799,22 @@ int gram_backward(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, i
     SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
     SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
     const Layout L = layout_for(scale(per, P), P, sizeof(R), true, false, p.order);
-    const SkGeom g = sk_make_geom((int)lx, (int)ly);
+    // sweeps on the (refined) grid; contraction and reductions on the unrefined one
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    const int nstrips_u = sk_make_geom((int)lx, (int)ly).nstrips;
     for (int64_t first = 0; first < npairs; first += P) {
         const int64_t cnt = std::min(P, npairs - first);
         SkPairSrc src;
         std::memset(&src, 0, sizeof(src));
         src.ny = ny; src.lx_pts = lxp; src.ly_pts = lyp; src.stride = per; src.first = first;
         rc = run_chunk_backward<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly,
-                                   ring_fwd_of(p, (int)ly), ring_adj_of(p, (int)ly), g.nstrips,
+                                   ring_fwd_of(p, (int)ly), ring_adj_of(p, (int)ly), nstrips_u,
                                    (char*)ws, L, gK, gKexp, st);
         if (rc) return rc;
         ReduceGramArgs<R> ra;
         ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
         ra.first = first; ra.count = cnt; ra.dx_stride = per.dx; ra.dy_stride = per.dy;
-        ra.nstrips = g.nstrips;
+        ra.nstrips = nstrips_u;
         ra.dxp = reinterpret_cast<const R*>((char*)ws + L.dxp);
         ra.dyp = reinterpret_cast<const R*>((char*)ws + L.dyp);
         ra.gX = gX; ra.gY = gY;
@@ -1122,7 +1145,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     const int64_t n = P.npairs;
     P.cfg = cfg;
     P.uploaded = nullptr;
-    std::vector<int32_t> ex(n), ey(n), sw(n), clsb(n), clsf(n), pipe(n), nstr(n);
+    std::vector<int32_t> ex(n), ey(n), sw(n), clsb(n), clsf(n), pipe(n), pipeb(n), nstr(n);
     std::vector<int64_t> cost(n), seqb(n), seqf(n);
     int64_t njobs_all = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -1137,14 +1160,17 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         // pairs of several strips go to the strip pipeline (class 6), which
         // balances the load strip by strip instead of pair by pair
         pipe[i] = (cfg.pipe && !is_fd(p) && g.nstrips >= 2) ? 1 : 0;
+        // the pipelined backward runs unrefined grids only
+        pipeb[i] = (pipe[i] && lam == 0) ? 1 : 0;
         clsf[i] = pipe[i] ? 6 : cls_fwd;
         // the backward runs its other pairs in one launch per chunk: a launch
         // per LDS class pays the longest pairs' sequential tail once per
         // class, more than lower occupancy costs (one class measured 1.45x
         // faster on 4096 uneven pairs); the classes shape the forward only
-        clsb[i] = pipe[i] ? 6 : 0;
+        clsb[i] = pipeb[i] ? 6 : 0;
         // forward jobs; a backward adds the checkpoint sweep's and the adjoint's
-        if (pipe[i]) njobs_all += (int64_t)g.nstrips * (P.backward ? 3 : 1);
+        if (pipe[i]) njobs_all += g.nstrips;
+        if (pipeb[i] && P.backward) njobs_all += 2 * (int64_t)g.nstrips;
         seqb[i] = seqf[i] = i;
     }
     std::stable_sort(seqb.begin(), seqb.end(), [&](int64_t u, int64_t v) {
@@ -1185,7 +1211,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         *scratch = 0;
         std::vector<SkPairSizes> zs(n);
         for (int64_t i = 0; i < n; ++i) {
-            const bool pp = pipe[i] != 0;  // two record slots, a progress counter per strip
+            const bool pp = (bwd ? pipeb[i] : pipe[i]) != 0;  // two record slots, a progress counter per strip
             zs[i] = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
                                   pp ? 2 * sk_gx_words(p.order, (int)es) : xb_words_of(p, ey[i]), pp);
         }
@@ -1458,7 +1484,7 @@ int plan_chunk_adjoint(const PlanImpl& P, const PlanChunk& c, const R* Xc, const
                                        c.njobs, ws_c, L, gK, gKexp, st);
     } else {
         rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj, c.max_strips,
-                                  ws_c, L, gK, gKexp, st);
+                                  c.max_nsteps_pad, ws_c, L, gK, gKexp, st);
     }
     if (rc) return rc;
     ReducePairsArgs<R> ra;
@@ -1834,7 +1860,7 @@ int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t np
     if (p->algo != SK_ALGO_BATCHED) return fail(SK_EUNSUPPORTED, "plans run the batched algorithm");
     if (p->flags & SK_SYMMETRIC) return fail(SK_EINVAL, "SK_SYMMETRIC applies to Gram calls");
     if (npairs < 0) return fail(SK_EINVAL, "negative npairs");
-    const int lam = backward ? 0 : lam_of(*p);
+    const int lam = lam_of(*p);
     if ((rc = check_offsets(x_off, npairs, lam, "x")) || (rc = check_offsets(y_off, npairs, lam, "y")))
         return rc;
     try {

@@ -109,6 +109,8 @@ struct SkPairDesc {
 // Per-pair workspace strides, all derived from the pair's geometry.
 struct SkPairSizes {
     int64_t c, ck, ce, qb, qe, dx, dy, xb, pg;
+    int64_t cu;  // backward on a refined grid: dL/dc folded onto the unrefined
+                 // grid's skewed layout (at the pair's c_off, so sized as c)
 };
 
 // xb_words: 32-bit words per column of the pair's global exchange records
@@ -120,7 +122,7 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
                                                      int32_t N, int32_t S, int64_t d,
                                                      bool backward, int xb_words,
                                                      bool pipe = false) {
-    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    SkPairSizes z = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     SkGeom g = sk_make_geom(lx << lam, ly << lam);
     z.c = (int64_t)g.nsteps_pad * SK_LANES;
     if (g.nsteps > 0) z.xb = (int64_t)g.ly * xb_words;
@@ -133,7 +135,8 @@ __host__ __device__ inline SkPairSizes sk_pair_sizes(int32_t lx, int32_t ly, int
         z.qb = (int64_t)g.nstrips * g.ly * (N + 1);
         z.qe = (int64_t)g.nstrips * g.ly;
         z.dx = (int64_t)lx * d;
-        z.dy = (int64_t)g.nstrips * ly * d;
+        z.dy = (int64_t)g.nstrips * ly * d;  // refined strips >= the unrefined grid's
+        if (lam > 0) z.cu = z.c;
     }
     return z;
 }

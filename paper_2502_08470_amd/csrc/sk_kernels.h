@@ -1225,6 +1225,7 @@ struct AdjArgs {
     R* gskew;              // out: skewed dL/dc
     unsigned* xb;          // global strip-boundary exchange records (long pairs)
     int32_t gx_cols;       // pairs with more columns use the global exchange
+    int32_t lam;           // dyadic refinement of the pairs' grids (hybrid scheme)
 };
 
 // Exponent of an adjoint vector that is zero by construction: below any
@@ -1236,7 +1237,7 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const int r = threadIdx.x;
     const int64_t local = blockIdx.x;
     const SkPairDesc pd = sk_pair(a.src, local);
-    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
     if (g.nsteps == 0) return;
     // adjoint strip-boundary vectors handed from lane 0 of strip s to lane 63
     // of strip s-1: LDS ring, or global records staged one block ahead
@@ -1924,6 +1925,48 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
 #pragma unroll
         for (int k = 0; k < DMAX; ++k)
             if (k < d) a.dxp[pd.dx_off + (int64_t)i * ld + k0 + k] = accx[k];
+    }
+}
+
+// Hybrid scheme backward: every sub-cell of cell (i, j) on the lam-order
+// refinement has the constant c_ij / 4^lam, so dL/dc_ij is 4^-lam times the
+// sum of dL/dc' over its 4^lam sub-cells.  One thread per element (tau, r)
+// of the unrefined grid's skewed layout (cell (64 s + r, j) with
+// tau - r = s Tp + j, as the sweeps lay it out) gathers its sub-cells from
+// the refined grid's skewed layout; idle slots get zero.  The contraction
+// and the reductions then run on the unrefined grid.
+template <typename R>
+struct FoldArgs {
+    SkPairSrc src;
+    int32_t lam;
+    const R* gref;  // refined skewed dL/dc', at each pair's c_off
+    R* gout;        // unrefined skewed dL/dc, at each pair's c_off
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fold_refined(const FoldArgs<R> a) {
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    const SkGeom gr = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
+    if (g.nsteps == 0) return;
+    const int64_t ne = (int64_t)g.nsteps_pad * SK_LANES;
+    for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < ne; e += (int64_t)gridDim.y * 256) {
+        const int tau = (int)(e >> 6), r = (int)(e & 63), L = tau - r;
+        R sum = (R)0;
+        if (L >= 0) {
+            const int s = L / g.Tp, j = L - s * g.Tp, i = 64 * s + r;
+            if (i < g.lx && j < g.ly) {
+                const int n = 1 << a.lam;
+                for (int u = 0; u < n; ++u) {
+                    const int ir = i * n + u, sr = ir >> 6, rr = ir & 63;
+                    const int64_t base = pd.c_off + ((int64_t)sr * gr.Tp + rr) * SK_LANES + rr;
+                    for (int v = 0; v < n; ++v) sum += a.gref[base + (int64_t)(j * n + v) * SK_LANES];
+                }
+                sum *= (R)1 / (R)(1 << (2 * a.lam));
+            }
+        }
+        a.gout[pd.c_off + e] = sum;
     }
 }
 

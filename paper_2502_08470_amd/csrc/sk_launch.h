@@ -50,6 +50,8 @@ struct SkLaunch {
     // adjoint of strip-pipeline pairs: the job list's strips, each pair's in
     // decreasing order, on co-resident workgroups
     static hipError_t adjoint_pipe(const AdjPipeArgs<R>& a, int N, bool interp, hipStream_t st);
+    static hipError_t fold_refined(const FoldArgs<R>& a, int max_nsteps_pad, int64_t npairs,
+                                   hipStream_t st);
     static hipError_t contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                hipStream_t st);
     static hipError_t reduce_gram(const ReduceGramArgs<R>& a, hipStream_t st);

@@ -288,6 +288,16 @@ static void sk_contract_d(const ContractArgs<R>& a, dim3 grid, hipStream_t st) {
 }
 
 template <typename R>
+hipError_t SkLaunch<R>::fold_refined(const FoldArgs<R>& a, int max_nsteps_pad, int64_t npairs,
+                                     hipStream_t st) {
+    if (npairs <= 0 || max_nsteps_pad <= 0) return hipSuccess;
+    const int64_t by = std::min<int64_t>(((int64_t)max_nsteps_pad * SK_LANES + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_fold_refined<R>, dim3((unsigned)npairs, (unsigned)by), dim3(256), 0, st, a);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;

@@ -234,3 +234,64 @@ def test_bf16x3_backward_matches_native(sk):
     gX3, gY3 = sk.gram_backward(X, Y, gK, "approx", 6, gram_mode="bf16x3")
     for a, b in ((gX1, gX3), (gY1, gY3)):
         torch.testing.assert_close(b, a, rtol=1e-4, atol=1e-4 * float(a.abs().max()))
+
+
+@pytest.mark.parametrize("scheme,order,lam", [("approx", 4, 1), ("interp", 5, 1), ("approx", 3, 2)])
+def test_hybrid_backward_matches_finite_differences(sk, scheme, order, lam):
+    # the refined-grid (hybrid) scheme's gradient: sweeps on the lam-order
+    # refinement (several refined strips), dL/dc folded onto the unrefined
+    # cells, then the contraction; against central differences of the FP64
+    # oracle of the same hybrid scheme, and the saved-state path against the
+    # recomputing one
+    from oracle import c_oracle as C
+    log_banner(f"hybrid backward {scheme} {order} lam {lam}")
+    rng = np.random.default_rng(51 + lam)
+    X = bm_paths(rng, 2, 45, 3, 0.4 / np.sqrt(45))
+    Y = bm_paths(rng, 2, 30, 3, 0.4 / np.sqrt(30))
+    gK = rng.normal(size=(2, 2))
+    Xt, Yt, gKt = dev(X, torch.float64), dev(Y, torch.float64), dev(gK, torch.float64)
+    gX, gY = sk.gram_backward(Xt, Yt, gKt, scheme, order, dyadic=lam)
+    gX, gY = gX.cpu().numpy(), gY.cpu().numpy()
+    kind = C.APPROX if scheme == "approx" else C.INTERP
+
+    def loss(Xv, Yv):
+        m, e = C.gram(Xv, Yv, kind, order, lam=lam)
+        return float(np.sum(gK * np.ldexp(m, e)))
+    h = 1e-4
+    scale = max(np.abs(gX).max(), np.abs(gY).max())
+    for which, idx in [("x", (0, 0, 0)), ("x", (1, 33, 1)), ("x", (0, 45, 2)), ("y", (1, 0, 2)),
+                       ("y", (0, 17, 0)), ("y", (1, 30, 1))]:
+        P = (X if which == "x" else Y).copy()
+        P[idx] += h
+        lp = loss(P, Y) if which == "x" else loss(X, P)
+        P[idx] -= 2 * h
+        lm = loss(P, Y) if which == "x" else loss(X, P)
+        fd = (lp - lm) / (2 * h)
+        got = gX[idx] if which == "x" else gY[idx]
+        assert abs(got - fd) <= 1e-6 * max(1.0, abs(fd)), (which, idx, got, fd)
+    K1, state = sk.gram_save(Xt, Yt, scheme, order, dyadic=lam)
+    gX1, gY1 = sk.gram_backward_saved(Xt, Yt, gKt, state, scheme, order, dyadic=lam)
+    assert np.array_equal(gX1.cpu().numpy(), gX) and np.array_equal(gY1.cpu().numpy(), gY)
+    K0 = sk.gram(Xt, Yt, scheme, order, dyadic=lam)
+    torch.testing.assert_close(K1, K0, rtol=1e-14, atol=0)
+
+
+def test_hybrid_backward_pairs_and_long_columns(sk):
+    # ragged pairs through a backward plan on the refined grid (the 1200
+    # refined columns of the long pair exceed the adjoint's LDS ring, so its
+    # global exchange runs too), against Gram backward calls of each pair
+    log_banner("hybrid backward pairs")
+    rng = np.random.default_rng(57)
+    lens_x, lens_y = [40, 300, 2, 70], [301, 25, 9, 1]
+    xs = [bm_paths(rng, 1, n - 1, 4, 0.4 / np.sqrt(n))[0] for n in lens_x]
+    ys = [bm_paths(rng, 1, n - 1, 4, 0.4 / np.sqrt(n))[0] for n in lens_y]
+    gk = rng.normal(size=len(xs))
+    xl = [dev(a, torch.float64) for a in xs]
+    yl = [dev(b, torch.float64) for b in ys]
+    gX, gY, xo, yo = sk.pairs_backward(xl, yl, dev(gk, torch.float64), "approx", 5, dyadic=2)
+    for i in range(len(xs)):
+        gXi, gYi = sk.gram_backward(xl[i][None], yl[i][None], dev([[gk[i]]], torch.float64),
+                                    "approx", 5, dyadic=2)
+        s = max(float(gXi.abs().max()), float(gYi.abs().max()), 1e-300)
+        torch.testing.assert_close(gX[xo[i]:xo[i + 1]], gXi[0], rtol=1e-11, atol=1e-11 * s)
+        torch.testing.assert_close(gY[yo[i]:yo[i + 1]], gYi[0], rtol=1e-11, atol=1e-11 * s)
