@@ -139,10 +139,9 @@ typedef struct sk_params {
     int32_t dyadic; /* polynomial schemes: lambda in [0, SK_MAX_DYADIC_ORDER] runs the
                        scheme on the lambda-order dyadic refinement of the grid (the
                        hybrid method of the remark after Theorem "prop:globalte");
-                       its backward (batched algorithm and plans) sweeps the refined
-                       grid and sums dL/dc over each cell's 4^lambda sub-cells,
-                       times 4^-lambda, before the contraction; the strip
-                       pipeline's backward needs 0; must be 0 for SK_FD, SK_FD2     */
+                       its backward sweeps the refined grid and sums dL/dc over
+                       each cell's 4^lambda sub-cells, times 4^-lambda, before the
+                       contraction; must be 0 for SK_FD, SK_FD2                     */
 } sk_params;
 
 /*

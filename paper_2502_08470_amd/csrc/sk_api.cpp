@@ -189,8 +189,6 @@ int check_params(const sk_params* p, bool backward) {
         if (p->dyadic < 0) return fail(SK_EINVAL, "dyadic refinement %d < 0", p->dyadic);
         if (p->dyadic > SK_MAX_DYADIC_ORDER)
             return fail(SK_EUNSUPPORTED, "dyadic refinement %d > %d", p->dyadic, SK_MAX_DYADIC_ORDER);
-        if (p->dyadic > 0 && backward && p->algo == SK_ALGO_PIPELINE)
-            return fail(SK_EUNSUPPORTED, "backward of the refined-grid (hybrid) scheme on the strip pipeline");
         if (p->order < SK_MIN_POLY_ORDER)
             return fail(SK_EINVAL, "polynomial order %d < %d", p->order, SK_MIN_POLY_ORDER);
         if (p->order > SK_MAX_POLY_ORDER)
@@ -478,7 +476,7 @@ int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     const bool interp = p.scheme == SK_POLY_INTERP;
     R* cskew = reinterpret_cast<R*>(ws + L.cskew);
     GramArgs<R> ga;
-    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = 0;
+    ga.X = X; ga.Y = Y; ga.d = d; ga.dpad = gram_dpad(p, d); ga.lam = lam_of(p);
     ga.src = src; ga.cskew = cskew; ga.maxc = nullptr; ga.split = p.gram == SK_GRAM_BF16X3;
     SK_LAUNCH("gram", st, launch_gram(ga, P, max_nsteps_pad, max_lx, max_ly, p.gram == SK_GRAM_NATIVE, st),
               "increment Gram");
@@ -492,7 +490,7 @@ int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.K = K; pa.Kexp = Kexp;
     pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     pa.progress = prog; pa.abort = abrt; pa.spin_limit = kPipeSpinLimit;
-    pa.desc = src.desc; pa.jobs = jobs_fwd; pa.njobs = njobs; pa.lam = 0;
+    pa.desc = src.desc; pa.jobs = jobs_fwd; pa.njobs = njobs; pa.lam = lam_of(p);
     pa.ck = reinterpret_cast<R*>(ws + L.ck);
     pa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     pa.qb = reinterpret_cast<R*>(ws + L.qb);
@@ -506,9 +504,9 @@ int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
 // state left by run_chunk_prepare_pipe, and the contraction.
 template <typename R>
 int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d,
-                           const SkPairSrc& src, int64_t P, int max_strips, const int2* jobs_adj,
-                           int64_t njobs, char* ws, const Layout& L, const R* gK,
-                           const int32_t* gKexp, hipStream_t st) {
+                           const SkPairSrc& src, int64_t P, int max_strips, int max_nsteps_pad,
+                           const int2* jobs_adj, int64_t njobs, char* ws, const Layout& L,
+                           const R* gK, const int32_t* gKexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
     const int64_t npg = (L.total - L.pg) / 4;
     int* prog = reinterpret_cast<int*>(ws + L.pg);
@@ -525,10 +523,16 @@ int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     aa.progress = prog; aa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
     aa.spin_limit = kPipeSpinLimit;
-    aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs;
+    aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs; aa.lam = lam_of(p);
     SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
               "pipelined adjoint sweep");
-    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
+    if (aa.lam == 0) return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
+    FoldArgs<R> fa;  // refined grid: dL/dc' folded onto the unrefined cells
+    fa.src = src; fa.lam = aa.lam;
+    fa.gref = reinterpret_cast<const R*>(ws + L.gskew);
+    fa.gout = reinterpret_cast<R*>(ws + L.gcu);
+    SK_LAUNCH("fold", st, SkLaunch<R>::fold_refined(fa, max_nsteps_pad, P, st), "refined-grid fold");
+    return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st, L.gcu);
 }
 
 template <typename R>
@@ -951,7 +955,8 @@ int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t 
                        int64_t d, const sk_params& p, const R* gK, const int32_t* gKexp, R* gX,
                        R* gY, void* ws, size_t wsb, hipStream_t st) {
     const int64_t npairs = nx * ny, lx = lxp - 1, ly = lyp - 1;
-    if (npairs == 0 || lx == 0 || ly == 0 || sk_make_geom((int)lx, (int)ly).nstrips < 2)
+    const int lam = lam_of(p);
+    if (npairs == 0 || lx == 0 || ly == 0 || sk_make_geom((int)(lx << lam), (int)(ly << lam)).nstrips < 2)
         return gram_backward<R>(X, nx, lxp, Y, ny, lyp, d, p, gK, gKexp, gX, gY, ws, wsb, st);
     GramPipePlan G;
     int rc = gram_pipe_plan(nx, lxp, ny, lyp, d, p, true, wsb, &G);
@@ -959,8 +964,10 @@ int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t 
     if ((rc = check_lds<R>(p, ly, d))) return rc;
     char* base = static_cast<char*>(ws);
     if ((rc = gram_pipe_upload(G, nx, lxp, ny, lyp, true, base, st))) return rc;
-    const SkGeom g = sk_make_geom((int)lx, (int)ly);
-    const int ns = g.nstrips;
+    // strips of the (refined) grid on the pipeline; the contraction and the
+    // reductions on the unrefined one
+    const SkGeom g = sk_make_geom((int)(lx << lam), (int)(ly << lam));
+    const int ns = g.nstrips, nstrips_u = sk_make_geom((int)lx, (int)ly).nstrips;
     SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
     SK_TRY_HIP(SkLaunch<R>::fill(gY, ny * lyp * d, (R)0, st), "fill");
     const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
@@ -977,13 +984,13 @@ int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t 
         rc = run_chunk_prepare_pipe<R>(p, X, Y, d, src, cnt, g.nsteps_pad, (int)lx, (int)ly, jobs,
                                        njobs, ws_c, L, kbuf, kexp, st);
         if (!rc)
-            rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, cnt, ns, jobs + njobs, njobs, ws_c, L, gK,
-                                           gKexp, st);
+            rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, cnt, nstrips_u, g.nsteps_pad, jobs + njobs,
+                                           njobs, ws_c, L, gK, gKexp, st);
         if (rc) return rc;
         ReduceGramArgs<R> ra;
         ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
         ra.first = first; ra.count = cnt; ra.dx_stride = G.per.dx; ra.dy_stride = G.per.dy;
-        ra.nstrips = ns;
+        ra.nstrips = nstrips_u;
         ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
         ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
         ra.gX = gX; ra.gY = gY;
@@ -996,8 +1003,9 @@ int gram_backward_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t 
 // (descriptors and job lists at its head), kept between a forward that
 // also stores the checkpoints and the backward that starts from them.
 bool gram_pipe_applies(const sk_params& p, int64_t nx, int64_t lxp, int64_t ny, int64_t lyp) {
+    const int lam = lam_of(p);
     return p.algo == SK_ALGO_PIPELINE && nx * ny > 0 && lxp > 1 && lyp > 1 &&
-           sk_make_geom((int)(lxp - 1), (int)(lyp - 1)).nstrips >= 2;
+           sk_make_geom((int)((lxp - 1) << lam), (int)((lyp - 1) << lam)).nstrips >= 2;
 }
 
 int gram_pipe_state(int64_t nx, int64_t lxp, int64_t ny, int64_t lyp, int64_t d,
@@ -1019,7 +1027,8 @@ int gram_save_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, int64_t ny, 
     if ((rc = check_lds<R>(p, lyp - 1, d))) return rc;
     char* base = static_cast<char*>(state);
     if ((rc = gram_pipe_upload(G, nx, lxp, ny, lyp, true, base, st))) return rc;
-    const SkGeom g = sk_make_geom((int)(lxp - 1), (int)(lyp - 1));
+    const int lam = lam_of(p);
+    const SkGeom g = sk_make_geom((int)((lxp - 1) << lam), (int)((lyp - 1) << lam));
     const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
     SkPairSrc src;
     std::memset(&src, 0, sizeof(src));
@@ -1041,7 +1050,9 @@ int gram_backward_saved_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, in
     if ((size_t)G.total > bytes)
         return fail(SK_EWORKSPACE, "state needs %lld bytes, got %zu", (long long)G.total, bytes);
     char* base = static_cast<char*>(state);
-    const int ns = (int)G.nstrips;
+    const int lam = lam_of(p);
+    const int ns = (int)G.nstrips, nstrips_u = sk_make_geom((int)(lxp - 1), (int)(lyp - 1)).nstrips;
+    const int nsteps_pad = sk_make_geom((int)((lxp - 1) << lam), (int)((lyp - 1) << lam)).nsteps_pad;
     const Layout L = layout_for(scale(G.per, G.P), G.P, sizeof(R), true, false, p.order);
     char* ws_c = base + G.scratch;
     SK_TRY_HIP(SkLaunch<R>::fill(gX, nx * lxp * d, (R)0, st), "fill");
@@ -1050,14 +1061,14 @@ int gram_backward_saved_pipe(const R* X, int64_t nx, int64_t lxp, const R* Y, in
     std::memset(&src, 0, sizeof(src));
     src.desc = reinterpret_cast<const SkPairDesc*>(base + G.desc);
     const int64_t njobs = G.P * ns;
-    rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, G.P, ns,
+    rc = run_chunk_adjoint_pipe<R>(p, X, Y, d, src, G.P, nstrips_u, nsteps_pad,
                                    reinterpret_cast<const int2*>(base + G.jobs_full) + njobs, njobs,
                                    ws_c, L, gK, gKexp, st);
     if (rc) return rc;
     ReduceGramArgs<R> ra;
     ra.nx = nx; ra.ny = ny; ra.lx_pts = lxp; ra.ly_pts = lyp; ra.d = d;
     ra.first = 0; ra.count = G.P; ra.dx_stride = G.per.dx; ra.dy_stride = G.per.dy;
-    ra.nstrips = ns;
+    ra.nstrips = nstrips_u;
     ra.dxp = reinterpret_cast<const R*>(ws_c + L.dxp);
     ra.dyp = reinterpret_cast<const R*>(ws_c + L.dyp);
     ra.gX = gX; ra.gY = gY;
@@ -1145,7 +1156,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
     const int64_t n = P.npairs;
     P.cfg = cfg;
     P.uploaded = nullptr;
-    std::vector<int32_t> ex(n), ey(n), sw(n), clsb(n), clsf(n), pipe(n), pipeb(n), nstr(n);
+    std::vector<int32_t> ex(n), ey(n), sw(n), clsb(n), clsf(n), pipe(n), nstr(n);
     std::vector<int64_t> cost(n), seqb(n), seqf(n);
     int64_t njobs_all = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -1160,17 +1171,14 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         // pairs of several strips go to the strip pipeline (class 6), which
         // balances the load strip by strip instead of pair by pair
         pipe[i] = (cfg.pipe && !is_fd(p) && g.nstrips >= 2) ? 1 : 0;
-        // the pipelined backward runs unrefined grids only
-        pipeb[i] = (pipe[i] && lam == 0) ? 1 : 0;
         clsf[i] = pipe[i] ? 6 : cls_fwd;
         // the backward runs its other pairs in one launch per chunk: a launch
         // per LDS class pays the longest pairs' sequential tail once per
         // class, more than lower occupancy costs (one class measured 1.45x
         // faster on 4096 uneven pairs); the classes shape the forward only
-        clsb[i] = pipeb[i] ? 6 : 0;
+        clsb[i] = pipe[i] ? 6 : 0;
         // forward jobs; a backward adds the checkpoint sweep's and the adjoint's
-        if (pipe[i]) njobs_all += g.nstrips;
-        if (pipeb[i] && P.backward) njobs_all += 2 * (int64_t)g.nstrips;
+        if (pipe[i]) njobs_all += (int64_t)g.nstrips * (P.backward ? 3 : 1);
         seqb[i] = seqf[i] = i;
     }
     std::stable_sort(seqb.begin(), seqb.end(), [&](int64_t u, int64_t v) {
@@ -1211,7 +1219,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         *scratch = 0;
         std::vector<SkPairSizes> zs(n);
         for (int64_t i = 0; i < n; ++i) {
-            const bool pp = (bwd ? pipeb[i] : pipe[i]) != 0;  // two record slots, a progress counter per strip
+            const bool pp = pipe[i] != 0;  // two record slots, a progress counter per strip
             zs[i] = sk_pair_sizes(ex[i], ey[i], lam, p.order, ckpt_stride(p), P.d, bwd,
                                   pp ? 2 * sk_gx_words(p.order, (int)es) : xb_words_of(p, ey[i]), pp);
         }
@@ -1480,8 +1488,8 @@ int plan_chunk_adjoint(const PlanImpl& P, const PlanChunk& c, const R* Xc, const
     int rc;
     if (c.pipe) {
         const int2* jobs = reinterpret_cast<const int2*>(base + P.jobs_off) + c.jobs_first;
-        rc = run_chunk_adjoint_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_strips, jobs + c.njobs,
-                                       c.njobs, ws_c, L, gK, gKexp, st);
+        rc = run_chunk_adjoint_pipe<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_strips, c.max_nsteps_pad,
+                                       jobs + c.njobs, c.njobs, ws_c, L, gK, gKexp, st);
     } else {
         rc = run_chunk_adjoint<R>(P.p, Xc, Yc, P.d, src, c.count, c.max_ly, c.ring_adj, c.max_strips,
                                   c.max_nsteps_pad, ws_c, L, gK, gKexp, st);

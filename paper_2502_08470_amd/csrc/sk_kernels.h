@@ -1528,6 +1528,7 @@ struct AdjPipeArgs {
     const SkPairDesc* desc;
     const int2* jobs;       // (pair, strip), every pair's strips in decreasing order
     int64_t njobs;
+    int32_t lam;            // dyadic refinement of the pairs' grids (hybrid scheme)
 };
 
 // LDS of the pipelined adjoint: the exchange staging slot, then the
@@ -1552,7 +1553,7 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
         const int2 jb = a.jobs[q];
         const SkPairDesc pd = a.desc[jb.x];
         const int s = jb.y;
-        const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+        const SkGeom g = sk_make_geom(pd.lx << a.lam, pd.ly << a.lam);
         const int ly = g.ly;
         const int nloc = sk_pipe_steps(ly), nckl = nloc / S;
         const int i = s * 64 + r;

@@ -101,7 +101,6 @@ def test_backward_rejections():
                                       None, vp(1), vp(1), vp(1), 1 << 30, None)
     assert bwd(P(scheme=0, order=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(scheme=3, order=1)) == L.SK_EUNSUPPORTED  # second-order FD: forward only
-    assert bwd(P(dyadic=1, algo=2)) == L.SK_EUNSUPPORTED  # hybrid backward: batched only
     assert bwd(P(algo=1, dtype=0)) == L.SK_EUNSUPPORTED
     assert bwd(P(algo=2, scheme=0, order=0)) == L.SK_EUNSUPPORTED  # pipeline: polynomial schemes
     assert bwd(P(), d=65) == L.SK_EUNSUPPORTED

@@ -274,6 +274,14 @@ def test_hybrid_backward_matches_finite_differences(sk, scheme, order, lam):
     assert np.array_equal(gX1.cpu().numpy(), gX) and np.array_equal(gY1.cpu().numpy(), gY)
     K0 = sk.gram(Xt, Yt, scheme, order, dyadic=lam)
     torch.testing.assert_close(K1, K0, rtol=1e-14, atol=0)
+    # the strip pipeline on the refined grid: recomputing and saved-state
+    gXp, gYp = sk.gram_backward(Xt, Yt, gKt, scheme, order, dyadic=lam, algo="pipeline")
+    K2, state2 = sk.gram_save(Xt, Yt, scheme, order, dyadic=lam, algo="pipeline")
+    gX2, gY2 = sk.gram_backward_saved(Xt, Yt, gKt, state2, scheme, order, dyadic=lam,
+                                      algo="pipeline")
+    torch.testing.assert_close(K2, K0, rtol=1e-14, atol=0)
+    for a, b in ((gXp, gX), (gYp, gY), (gX2, gX), (gY2, gY)):
+        np.testing.assert_allclose(a.cpu().numpy(), b, rtol=0, atol=1e-11 * scale)
 
 
 def test_hybrid_backward_pairs_and_long_columns(sk):
@@ -289,6 +297,10 @@ def test_hybrid_backward_pairs_and_long_columns(sk):
     xl = [dev(a, torch.float64) for a in xs]
     yl = [dev(b, torch.float64) for b in ys]
     gX, gY, xo, yo = sk.pairs_backward(xl, yl, dev(gk, torch.float64), "approx", 5, dyadic=2)
+    gXp, gYp, _, _ = sk.pairs_backward(xl, yl, dev(gk, torch.float64), "approx", 5, dyadic=2,
+                                       algo="pipeline")
+    for a, b in ((gXp, gX), (gYp, gY)):
+        torch.testing.assert_close(a, b, rtol=1e-11, atol=1e-11 * float(b.abs().max()))
     for i in range(len(xs)):
         gXi, gYi = sk.gram_backward(xl[i][None], yl[i][None], dev([[gk[i]]], torch.float64),
                                     "approx", 5, dyadic=2)
