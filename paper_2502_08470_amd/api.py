@@ -416,35 +416,39 @@ class SigKernelGram(torch.autograd.Function):
     algorithm or the strip pipeline for both."""
 
     @staticmethod
-    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None):
+    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None, dyadic=0):
         ctx.save_for_backward(X, Y)
-        ctx.scheme, ctx.order, ctx.gram_mode = scheme, order, gram_mode
+        ctx.scheme, ctx.order, ctx.gram_mode, ctx.dyadic = scheme, order, gram_mode, dyadic
         ctx.algo = algo or gram_algo(X, Y, scheme)
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
         ctx.state = None
         if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
-            size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo)
+            size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo, dyadic)
             if size <= _state_budget(X.device):
-                K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode, algo=ctx.algo)
+                K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode, algo=ctx.algo,
+                                         dyadic=dyadic)
                 return K
-        return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode)
+        return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode, dyadic=dyadic)
 
     @staticmethod
     def backward(ctx, gK):
         X, Y = ctx.saved_tensors
-        kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric, algo=ctx.algo)
+        kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric, algo=ctx.algo,
+                  dyadic=ctx.dyadic)
         if ctx.state is not None:
             gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
             gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, **kw)
-        return gX, gY, None, None, None, None
+        return gX, gY, None, None, None, None, None
 
 
-def sig_gram(X, Y, scheme: str = "approx", order: int = 4,
-             gram_mode: str = "native", algo: Optional[str] = None) -> torch.Tensor:
-    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo)
+def sig_gram(X, Y, scheme: str = "approx", order: int = 4, gram_mode: str = "native",
+             algo: Optional[str] = None, dyadic: int = 0) -> torch.Tensor:
+    """Differentiable Gram matrix (SigKernelGram); ``dyadic`` > 0 runs the
+    hybrid scheme on the dyadically refined grid."""
+    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo, dyadic)
 
 
 class SigKernelPairs(torch.autograd.Function):
@@ -454,14 +458,14 @@ class SigKernelPairs(torch.autograd.Function):
     kept state), otherwise a plain forward and a recomputing backward."""
 
     @staticmethod
-    def forward(ctx, A, B, scheme="approx", order=4, pipeline=False):
+    def forward(ctx, A, B, scheme="approx", order=4, pipeline=False, dyadic=0):
         P, La, d = A.shape
         Lb = B.shape[1]
         Ac = A.reshape(P * La, d).contiguous()
         Bc = B.reshape(P * Lb, d).contiguous()
         xo = (Ac, [i * La for i in range(P + 1)])
         yo = (Bc, [i * Lb for i in range(P + 1)])
-        plan = PairsPlan(xo, yo, scheme, order, backward=True)
+        plan = PairsPlan(xo, yo, scheme, order, backward=True, dyadic=dyadic)
         plan.configure(True, True, True, pipeline)
         k = torch.empty(P, dtype=A.dtype, device=A.device)
         try:
@@ -487,11 +491,13 @@ class SigKernelPairs(torch.autograd.Function):
             ctx.plan.backward(Ac, Bc, gk, gA, gB)
         ctx.plan = None
         sa, sb = ctx.shapes
-        return gA.reshape(sa), gB.reshape(sb), None, None, None
+        return gA.reshape(sa), gB.reshape(sb), None, None, None, None
 
 
-def sig_pairs(A, B, scheme: str = "approx", order: int = 4, pipeline: bool = False):
-    return SigKernelPairs.apply(A, B, scheme, order, pipeline)
+def sig_pairs(A, B, scheme: str = "approx", order: int = 4, pipeline: bool = False,
+              dyadic: int = 0):
+    """Differentiable k(A[i], B[i]) (SigKernelPairs); ``dyadic`` as for sig_gram."""
+    return SigKernelPairs.apply(A, B, scheme, order, pipeline, dyadic)
 
 
 def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,

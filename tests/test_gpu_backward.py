@@ -307,3 +307,30 @@ def test_hybrid_backward_pairs_and_long_columns(sk):
         s = max(float(gXi.abs().max()), float(gYi.abs().max()), 1e-300)
         torch.testing.assert_close(gX[xo[i]:xo[i + 1]], gXi[0], rtol=1e-11, atol=1e-11 * s)
         torch.testing.assert_close(gY[yo[i]:yo[i + 1]], gYi[0], rtol=1e-11, atol=1e-11 * s)
+
+
+def test_hybrid_autograd(sk):
+    # sig_gram and sig_pairs with the refined grid: autograd (saved state;
+    # sig_gram takes the strip pipeline for these six pairs of 2-strip
+    # paths) against the direct backward calls (batched Gram; pairs on a
+    # plan with the pipeline on): different wave groupings, 1e-11
+    log_banner("hybrid autograd")
+    rng = np.random.default_rng(58)
+    X = dev(bm_paths(rng, 2, 70, 3, 0.05), torch.float64)
+    Y = dev(bm_paths(rng, 3, 40, 3, 0.05), torch.float64)
+    gK = dev(rng.normal(size=(2, 3)), torch.float64)
+    Xg, Yg = X.clone().requires_grad_(True), Y.clone().requires_grad_(True)
+    (sk.sig_gram(Xg, Yg, "interp", 5, dyadic=1) * gK).sum().backward()
+    gX, gY = sk.gram_backward(X, Y, gK, "interp", 5, dyadic=1)
+    torch.testing.assert_close(Xg.grad, gX, rtol=1e-11, atol=1e-11 * float(gX.abs().max()))
+    torch.testing.assert_close(Yg.grad, gY, rtol=1e-11, atol=1e-11 * float(gY.abs().max()))
+    A = dev(bm_paths(rng, 4, 66, 3, 0.05), torch.float64)
+    B = dev(bm_paths(rng, 4, 90, 3, 0.05), torch.float64)
+    gk = dev(rng.normal(size=4), torch.float64)
+    Ag, Bg = A.clone().requires_grad_(True), B.clone().requires_grad_(True)
+    (sk.sig_pairs(Ag, Bg, "approx", 4, dyadic=2) * gk).sum().backward()
+    gA, gB, _, _ = sk.pairs_backward([a for a in A], [b for b in B], gk, "approx", 4, dyadic=2)
+    torch.testing.assert_close(Ag.grad.reshape(-1, 3), gA, rtol=1e-11,
+                               atol=1e-11 * float(gA.abs().max()))
+    torch.testing.assert_close(Bg.grad.reshape(-1, 3), gB, rtol=1e-11,
+                               atol=1e-11 * float(gB.abs().max()))
