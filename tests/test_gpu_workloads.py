@@ -209,3 +209,23 @@ def test_large_gram_full_size_sampled(sk):
     err = rel_err_exp(K[np.ix_(ia, ib)], Ke[np.ix_(ia, ib)], m, e)
     assert (e + np.log2(np.abs(m))).min() > 500  # far beyond FP32 and FP64 ranges
     assert err.max() < 1e-3, err
+
+
+def test_large_gram_fp64_sampled_block(sk):
+    # the accurate mode of the 1024 x 1024, d = 32 Gram: FP64 paths (native
+    # FMA-chain Gram on the strips, FP64 sweep) on a sampled 3 x 3 block at
+    # full size, against the oracle; kernel values beyond 2^500, exponent
+    # output
+    import workloads as W
+    from oracle import c_oracle as C
+    log_banner("1024-point d=32 Gram block, FP64")
+    X, Y = W.large_gram(0)
+    rng = np.random.default_rng(4)
+    ia, ib = np.sort(rng.choice(1024, 3, replace=False)), np.sort(rng.choice(1024, 3, replace=False))
+    Xs, Ys = X[ia].astype(np.float64), Y[ib].astype(np.float64)
+    K, Ke = sk.gram(torch.tensor(Xs, device="cuda"), torch.tensor(Ys, device="cuda"), "approx", 8,
+                    return_exp=True)
+    m, e = C.gram(Xs, Ys, C.APPROX, 8)
+    err = rel_err_exp(K.cpu().numpy(), Ke.cpu().numpy(), m, e)
+    assert (e + np.log2(np.abs(m))).min() > 500
+    assert err.max() < 1e-11, err
