@@ -16,7 +16,11 @@
  *                   `order` = N.
  *   SK_POLY_INTERP  polynomial interpolation scheme of order N at the N+1
  *                   Chebyshev extrema (Section 3.3, Definition "Polynomial
- *                   interpolation numerical scheme"); `order` = N.
+ *                   interpolation numerical scheme"); `order` = N.  Exact
+ *                   (to the working precision) for cell constants |c| up to
+ *                   about 10; a cell beyond the compiled tail makes its
+ *                   pair's value and gradient NaN and raises
+ *                   SK_STATUS_TAIL_CAP (sigkernel_status).
  *   SK_FD2          second-order explicit finite differences (Remark
  *                   "higherfd", eq. secondexplicitscheme: the first-order
  *                   rule plus c^2/12 times the three known corners) on the
@@ -352,6 +356,46 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
  */
 int sigkernel_profile_enable(int32_t on);
 int sigkernel_profile_read(const char* name, double* total_ms, int64_t* launches);
+
+/*
+ * Device status (diagnostics).  Kernels raise bits in a per-device status
+ * word, which keeps them until cleared:
+ *   SK_STATUS_TAIL_CAP   an interpolation cell needed more tail rows than the
+ *                        compiled cap (cells with |c| beyond about 10; see
+ *                        SK_POLY_INTERP): its pair's value (and gradient) is
+ *                        NaN.
+ *   SK_STATUS_WAIT_ABORT a bounded wait of the strip pipeline gave up: the
+ *                        values (gradients) it could not complete are NaN.
+ * sigkernel_status synchronises `stream`, then writes the bits raised on the
+ * current device since the last clear to *flags, and clears them when
+ * `clear` != 0.  Bits are shared by every stream and call on the device.
+ */
+#define SK_STATUS_TAIL_CAP 1u
+#define SK_STATUS_WAIT_ABORT 2u
+int sigkernel_status(hipStream_t stream, int32_t clear, uint32_t* flags);
+/*
+ * Polls a strip-pipeline wait makes before it gives up (diagnostics, for
+ * tests of that path; process-wide, read when a call queues its kernels).
+ * 0 restores the default of 2^24 polls (about ten seconds).  SK_EINVAL for a
+ * negative count.
+ */
+int sigkernel_set_spin_limit(int32_t polls);
+
+/*
+ * The interpolation scheme's tail tables (diagnostics; host only).  The
+ * interpolation of u^r at the order-N Chebyshev extrema, in the factorial
+ * basis: rs[n * SK_TAIL_TABLE + t] = R[n][r] n!/r! for tail row r = N+1+t,
+ * t < SK_TAIL_TABLE (rs holds (N + 1) * SK_TAIL_TABLE doubles); rmax[t] =
+ * max_n |rs[n][t]| and cmax[t], the |c| up to which the projected rows from
+ * r on shrink at least by half per row (SK_TAIL_TABLE + 1 doubles each);
+ * *tail_cap = the longest tail compiled for `dtype`.  A cell folds tail rows
+ * while 2 rmax[t] (|A^P_r| + |A^Q_r|) exceeds the working precision times
+ * its corner values or |c| > cmax[t], for at most *tail_cap rows.
+ * SK_EINVAL for an order outside [SK_MIN_POLY_ORDER, 12] or a NULL pointer.
+ */
+#define SK_TAIL_TABLE 20
+int sigkernel_interp_table(int32_t order, int32_t dtype, double* rs, double* rmax, double* cmax,
+                           int32_t* tail_cap);
 
 /* Static description of a status code. */
 const char* sigkernel_error_string(int status);

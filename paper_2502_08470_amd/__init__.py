@@ -1,7 +1,8 @@
 """MI355X (gfx950) signature-kernel solvers: finite-difference, polynomial
 approximation and polynomial interpolation schemes for the Goursat PDE of
 the signature kernel, batched over path pairs, forward and adjoint."""
-from .api import (PairsPlan, SigKernelGram, SigKernelPairs, cell_constants, gram, gram_algo,
+from .api import (PairsPlan, SigKernelGram, SigKernelPairs, cell_constants, device_status, gram,
+                  gram_algo,
                   gram_backward, gram_backward_saved, gram_save, gram_state_size, mmd2,
                   mmd_permutation_test, pairs, pairs_backward, sig_gram, sig_pairs)
 from ._lib import SigKernelError
@@ -9,4 +10,4 @@ from ._lib import SigKernelError
 __all__ = ["gram", "gram_algo", "pairs", "gram_backward", "pairs_backward", "cell_constants", "gram_save",
            "gram_backward_saved", "gram_state_size",
            "PairsPlan", "SigKernelGram", "sig_gram", "SigKernelPairs", "sig_pairs", "mmd2", "mmd_permutation_test",
-           "SigKernelError"]
+           "SigKernelError", "device_status"]

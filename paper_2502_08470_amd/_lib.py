@@ -18,6 +18,8 @@ SK_ALGO_BATCHED, SK_ALGO_PLAIN, SK_ALGO_PIPELINE = 0, 1, 2
 SK_OP_GRAM, SK_OP_PAIRS = 0, 1
 SK_GRAM_NATIVE, SK_GRAM_BF16X3, SK_GRAM_MFMA = 0, 1, 2
 SK_SYMMETRIC = 1
+SK_STATUS_TAIL_CAP, SK_STATUS_WAIT_ABORT = 1, 2
+SK_TAIL_TABLE = 20
 
 EXPORTS = (
     "sigkernel_gram_workspace",
@@ -45,6 +47,9 @@ EXPORTS = (
     "sigkernel_plan_configure",
     "sigkernel_plan_destroy",
     "sigkernel_mmd_permutation",
+    "sigkernel_status",
+    "sigkernel_set_spin_limit",
+    "sigkernel_interp_table",
 )
 
 
@@ -122,6 +127,13 @@ def lib():
     L.sigkernel_plan_destroy.restype = None
     L.sigkernel_mmd_permutation.argtypes = [vp, i64, i64, vp, i64, i32, vp, vp, vp]
     L.sigkernel_mmd_permutation.restype = ctypes.c_int
+    L.sigkernel_status.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32)]
+    L.sigkernel_status.restype = ctypes.c_int
+    L.sigkernel_set_spin_limit.argtypes = [i32]
+    L.sigkernel_set_spin_limit.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.sigkernel_interp_table.argtypes = [i32, i32, dp, dp, dp, ctypes.POINTER(i32)]
+    L.sigkernel_interp_table.restype = ctypes.c_int
     L.sigkernel_error_string.argtypes = [ctypes.c_int]
     L.sigkernel_error_string.restype = ctypes.c_char_p
     L.sigkernel_last_error.argtypes = []
@@ -156,3 +168,29 @@ def profile_read(name: str):
     n = ctypes.c_int64(0)
     check(lib().sigkernel_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def status(stream: int, clear: bool = True) -> int:
+    """Device status bits (SK_STATUS_*) raised since the last clear; waits for ``stream``."""
+    f = ctypes.c_uint32(0)
+    check(lib().sigkernel_status(ctypes.c_void_p(stream), 1 if clear else 0, ctypes.byref(f)))
+    return f.value
+
+
+def set_spin_limit(polls: int) -> None:
+    """Polls of a strip-pipeline wait before it gives up (0: the default)."""
+    check(lib().sigkernel_set_spin_limit(int(polls)))
+
+
+def interp_table(order: int, dtype: int):
+    """(rs [N+1][SK_TAIL_TABLE], rmax, cmax, tail cap) of the interpolation tail (host only)."""
+    import numpy as np
+    rs = np.zeros((order + 1) * SK_TAIL_TABLE)
+    rmax = np.zeros(SK_TAIL_TABLE + 1)
+    cmax = np.zeros(SK_TAIL_TABLE + 1)
+    cap = ctypes.c_int32(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().sigkernel_interp_table(int(order), int(dtype), rs.ctypes.data_as(dp),
+                                       rmax.ctypes.data_as(dp), cmax.ctypes.data_as(dp),
+                                       ctypes.byref(cap)))
+    return rs.reshape(order + 1, SK_TAIL_TABLE), rmax, cmax, cap.value

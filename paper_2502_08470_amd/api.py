@@ -62,6 +62,15 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
 
 
+def device_status(device=None, clear: bool = True) -> int:
+    """Status bits (``_lib.SK_STATUS_*``) the kernels raised on ``device`` since
+    the last clear: a cell past the interpolation scheme's compiled tail, a
+    strip-pipeline wait that gave up.  Waits for the current stream."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    with torch.cuda.device(dev):
+        return L.status(torch.cuda.current_stream(dev).cuda_stream, clear)
+
+
 # ---------------------------------------------------------------------------
 # forward
 # ---------------------------------------------------------------------------

@@ -78,8 +78,10 @@ struct ProfScope {
 
 constexpr int64_t kAlign = 256;
 constexpr size_t kDefaultCap = (size_t)160 << 30;  // bytes of one default chunk (of 288 GB HBM)
-// polls of a strip-pipeline wait before it gives up (about ten seconds)
+// polls of a strip-pipeline wait before it gives up (about ten seconds);
+// sigkernel_set_spin_limit changes it (diagnostics)
 constexpr int kPipeSpinLimit = 1 << 24;
+std::atomic<int> g_spin_limit{kPipeSpinLimit};
 
 inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -90,9 +92,11 @@ inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; 
 // interpolant's monomial coefficients R[n][r], from a partial-pivoting LU
 // solve of the Vandermonde system.  Scaled to the factorial basis:
 // Rs[n][r] = R[n][r] n! / r!.
+static_assert(SK_TMAX == SK_TAIL_TABLE, "the exported tail table has SK_TMAX rows");
 struct InterpTableF64 {
     double rs[SK_NMAX + 1][SK_TMAX];
-    double rmax[SK_TMAX];
+    double rmax[SK_TMAX + 1];
+    double cmax[SK_TMAX + 1];
 };
 
 double fact(int n) {
@@ -124,6 +128,10 @@ void lu_solve_inplace(std::vector<double> a, int M, std::vector<double>& b) {
     }
 }
 
+// Rows of the tail looked at when bounding how fast the projected rows
+// shrink: far enough that the ratio has settled (it tends to 1/(r+1)).
+constexpr int kTailHorizon = 160;
+
 InterpTableF64 build_interp_table(int N) {
     const int M = N + 1;
     std::vector<double> u(M), V(M * M);
@@ -132,15 +140,28 @@ InterpTableF64 build_interp_table(int N) {
         for (int n = 0; n <= N; ++n) V[m * M + n] = std::pow(u[m], n);
     InterpTableF64 t;
     std::memset(&t, 0, sizeof(t));
-    for (int k = 0; k < SK_TMAX; ++k) {
+    // q[k] = max_n |R[n][r]| n! for r = N+1+k (the projection weight without
+    // its 1/r!, which would underflow this far out)
+    std::vector<double> q(kTailHorizon + 1, 0.0);
+    for (int k = 0; k <= kTailHorizon; ++k) {
         const int r = N + 1 + k;
         std::vector<double> b(M);
         for (int m = 0; m <= N; ++m) b[m] = std::pow(u[m], r);
         lu_solve_inplace(V, M, b);
         for (int n = 0; n <= N; ++n) {
-            t.rs[n][k] = b[n] * fact(n) / fact(r);
-            t.rmax[k] = std::max(t.rmax[k], std::fabs(t.rs[n][k]));
+            q[k] = std::max(q[k], std::fabs(b[n]) * fact(n));
+            if (k < SK_TMAX) t.rs[n][k] = b[n] * fact(n) / fact(r);
         }
+        if (k <= SK_TMAX) t.rmax[k] = q[k] / fact(r);
+    }
+    // rho_k: largest growth factor of the weight from one row to the next
+    // over rows k, k+1, ... (5% margin for the rounding of the solves);
+    // cmax[k] = (k + 2) / (2 rho_k), see the decision rule of the device map
+    for (int k = 0; k <= SK_TMAX; ++k) {
+        double rho = 0.0;
+        for (int j = k; j < kTailHorizon; ++j)
+            rho = std::max(rho, q[j + 1] / (q[j] * (double)(N + 2 + j)));
+        t.cmax[k] = (k + 2) / (2.0 * 1.05 * rho);
     }
     return t;
 }
@@ -155,7 +176,11 @@ const SkTab<R>& interp_table(int N) {
         std::memset(&o, 0, sizeof(o));
         for (int n = 0; n <= N; ++n)
             for (int k = 0; k < SK_TMAX; ++k) o.rs[n][k] = (R)t.rs[n][k];
-        for (int k = 0; k < SK_TMAX; ++k) o.rmax[k] = (R)t.rmax[k];
+        for (int k = 0; k <= SK_TMAX; ++k) {
+            o.rmax[k] = (R)t.rmax[k];
+            o.cmax[k] = (R)t.cmax[k];
+        }
+        for (int m = 0; m < SK_IFA; ++m) o.ifa[m] = (R)(1.0 / fact(m));
     });
     return tabs[N];
 }
@@ -252,6 +277,40 @@ int check_offsets(const int64_t* off, int64_t npairs, int lam, const char* what)
         int rc = check_len(n, lam, what);
         if (rc) return rc;
     }
+    return SK_OK;
+}
+
+// Wavefront steps of one pair, in 64 bits (the kernels index steps in 32
+// bits): computed for both orientations, since plans may transpose a pair.
+constexpr int64_t kMaxSteps = (int64_t)1 << 30;
+int64_t steps64(int64_t lx, int64_t ly) {
+    if (lx <= 0 || ly <= 0) return 0;
+    const int64_t W = std::min<int64_t>(lx, SK_LANES), nstrips = (lx + SK_LANES - 1) / SK_LANES;
+    const int64_t Tp = std::max(ly, W), rlast = (lx - 1) - (nstrips - 1) * SK_LANES;
+    return (nstrips - 1) * Tp + (ly - 1) + rlast + 1;
+}
+int check_geom(int64_t lx_pts, int64_t ly_pts, int lam) {
+    const int64_t lx = (lx_pts - 1) << lam, ly = (ly_pts - 1) << lam;
+    const int64_t st = std::max(steps64(lx, ly), steps64(ly, lx));
+    if (st > kMaxSteps)
+        return fail(SK_EUNSUPPORTED,
+                    "a pair of %lld x %lld (refined) segments takes %lld wavefront steps (limit 2^30)",
+                    (long long)lx, (long long)ly, (long long)st);
+    return SK_OK;
+}
+// Both paths of a Gram call: point counts, refined lengths, pair geometry.
+int check_gram_geom(int64_t lx_pts, int64_t ly_pts, int lam) {
+    int rc;
+    if ((rc = check_len(lx_pts, lam, "x")) || (rc = check_len(ly_pts, lam, "y"))) return rc;
+    return check_geom(lx_pts, ly_pts, lam);
+}
+// Every pair of a pair list (host offsets).
+int check_pairs_geom(const int64_t* x_off, const int64_t* y_off, int64_t npairs, int lam) {
+    int rc;
+    if ((rc = check_offsets(x_off, npairs, lam, "x")) || (rc = check_offsets(y_off, npairs, lam, "y")))
+        return rc;
+    for (int64_t i = 0; i < npairs; ++i)
+        if ((rc = check_geom(x_off[i + 1] - x_off[i], y_off[i + 1] - y_off[i], lam))) return rc;
     return SK_OK;
 }
 
@@ -454,7 +513,7 @@ int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     pa.progress = reinterpret_cast<int*>(ws + L.pg);
     pa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
-    pa.spin_limit = kPipeSpinLimit;
+    pa.spin_limit = g_spin_limit.load();
     pa.desc = src.desc; pa.jobs = jobs; pa.njobs = njobs; pa.lam = lam_of(p);
     SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, false, st),
               "pipelined strip sweep");
@@ -489,7 +548,7 @@ int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.cskew = cskew; pa.tab = table_for<R>(p);
     pa.K = K; pa.Kexp = Kexp;
     pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
-    pa.progress = prog; pa.abort = abrt; pa.spin_limit = kPipeSpinLimit;
+    pa.progress = prog; pa.abort = abrt; pa.spin_limit = g_spin_limit.load();
     pa.desc = src.desc; pa.jobs = jobs_fwd; pa.njobs = njobs; pa.lam = lam_of(p);
     pa.ck = reinterpret_cast<R*>(ws + L.ck);
     pa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
@@ -508,7 +567,9 @@ int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
                            const int2* jobs_adj, int64_t njobs, char* ws, const Layout& L,
                            const R* gK, const int32_t* gKexp, hipStream_t st) {
     const bool interp = p.scheme == SK_POLY_INTERP;
-    const int64_t npg = (L.total - L.pg) / 4;
+    // progress counters only: the abort flag keeps the checkpoint sweep's
+    // (a strip whose checkpoints were not completed must not be replayed)
+    const int64_t npg = (L.total - L.pg) / 4 - 1;
     int* prog = reinterpret_cast<int*>(ws + L.pg);
     SK_TRY_HIP(SkLaunch<float>::fill_u32(reinterpret_cast<unsigned*>(prog), npg, st), "fill");
     AdjPipeArgs<R> aa;
@@ -522,7 +583,7 @@ int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     aa.progress = prog; aa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
-    aa.spin_limit = kPipeSpinLimit;
+    aa.spin_limit = g_spin_limit.load();
     aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs; aa.lam = lam_of(p);
     SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
               "pipelined adjoint sweep");
@@ -1660,6 +1721,52 @@ const char* sigkernel_error_string(int status) {
 
 const char* sigkernel_last_error(void) { return g_last_error.c_str(); }
 
+int sigkernel_status(hipStream_t stream, int32_t clear, uint32_t* flags) {
+    g_last_error.clear();
+    if (!flags) return fail(SK_EINVAL, "flags is NULL");
+    SK_TRY_HIP(hipStreamSynchronize(stream), "stream synchronize");
+    unsigned* w[2] = {nullptr, nullptr};
+    SK_TRY_HIP(SkLaunch<float>::status_word(&w[0]), "status word (FP32 kernels)");
+    SK_TRY_HIP(SkLaunch<double>::status_word(&w[1]), "status word (FP64 kernels)");
+    uint32_t f = 0;
+    for (unsigned* p : w) {
+        unsigned v = 0;
+        SK_TRY_HIP(hipMemcpy(&v, p, sizeof(v), hipMemcpyDeviceToHost), "status read");
+        f |= v;
+        if (clear) {
+            const unsigned z = 0;
+            SK_TRY_HIP(hipMemcpy(p, &z, sizeof(z), hipMemcpyHostToDevice), "status clear");
+        }
+    }
+    *flags = f;
+    return SK_OK;
+}
+
+int sigkernel_interp_table(int32_t order, int32_t dtype, double* rs, double* rmax, double* cmax,
+                           int32_t* tail_cap) {
+    g_last_error.clear();
+    if (order < SK_MIN_POLY_ORDER || order > SK_NMAX)
+        return fail(SK_EINVAL, "order %d outside [%d, %d]", order, SK_MIN_POLY_ORDER, SK_NMAX);
+    if (dtype != SK_F32 && dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", dtype);
+    if (!rs || !rmax || !cmax || !tail_cap) return fail(SK_EINVAL, "NULL pointer");
+    const InterpTableF64 t = build_interp_table(order);
+    for (int n = 0; n <= order; ++n)
+        for (int k = 0; k < SK_TMAX; ++k) rs[n * SK_TMAX + k] = t.rs[n][k];
+    for (int k = 0; k <= SK_TMAX; ++k) {
+        rmax[k] = t.rmax[k];
+        cmax[k] = t.cmax[k];
+    }
+    *tail_cap = dtype == SK_F32 ? SkTailMax<float>::value : SkTailMax<double>::value;
+    return SK_OK;
+}
+
+int sigkernel_set_spin_limit(int32_t polls) {
+    g_last_error.clear();
+    if (polls < 0) return fail(SK_EINVAL, "spin limit %d < 0", polls);
+    g_spin_limit.store(polls == 0 ? kPipeSpinLimit : polls);
+    return SK_OK;
+}
+
 int sigkernel_profile_enable(int32_t on) {
     g_last_error.clear();
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -1696,7 +1803,7 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
                                 const sk_params* p, int32_t backward) {
     g_last_error.clear();
     if (check_params(p, backward != 0) || check_dims(d, backward != 0) ||
-        check_len(lx_pts, lam_of(*p), "x") || check_len(ly_pts, lam_of(*p), "y"))
+        check_gram_geom(lx_pts, ly_pts, lam_of(*p)))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     const int lam = lam_of(*p);
@@ -1726,7 +1833,7 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     g_last_error.clear();
     if (check_params(p, backward != 0) || check_dims(d, backward != 0)) return 0;
     if (npairs < 0) { fail(SK_EINVAL, "negative npairs"); return 0; }
-    if (check_offsets(x_off, npairs, lam_of(*p), "x") || check_offsets(y_off, npairs, lam_of(*p), "y"))
+    if (check_pairs_geom(x_off, y_off, npairs, lam_of(*p)))
         return 0;
     const int lam = lam_of(*p);
     if (p->algo == SK_ALGO_PLAIN) {
@@ -1755,7 +1862,7 @@ int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int
     if (!rc) rc = check_dims(d, false);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
-    if ((rc = check_len(lx_pts, lam_of(*p), "x")) || (rc = check_len(ly_pts, lam_of(*p), "y")))
+    if ((rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p))))
         return rc;
     if (nx * ny == 0) return SK_OK;
     if (!X || !Y || !K || !ws) return fail(SK_EINVAL, "NULL pointer");
@@ -1779,8 +1886,7 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
     if (rc) return rc;
     if (npairs < 0) return fail(SK_EINVAL, "negative npairs");
     if (npairs == 0) return SK_OK;
-    if ((rc = check_offsets(x_off, npairs, lam_of(*p), "x")) ||
-        (rc = check_offsets(y_off, npairs, lam_of(*p), "y")))
+    if ((rc = check_pairs_geom(x_off, y_off, npairs, lam_of(*p))))
         return rc;
     if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
     try {
@@ -1817,9 +1923,9 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     if (op != SK_OP_GRAM && op != SK_OP_PAIRS) return fail(SK_EINVAL, "op %d", op);
     if (nx < 0 || (op == SK_OP_GRAM && ny < 0)) return fail(SK_EINVAL, "negative batch");
     if (op == SK_OP_GRAM) {
-        if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+        if ((rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p)))) return rc;
     } else {
-        if ((rc = check_offsets(x_off, nx, 0, "x")) || (rc = check_offsets(y_off, nx, 0, "y")))
+        if ((rc = check_pairs_geom(x_off, y_off, nx, lam_of(*p))))
             return rc;
     }
     if ((rc = check_symmetric(*p, op, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
@@ -1869,7 +1975,7 @@ int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t np
     if (p->flags & SK_SYMMETRIC) return fail(SK_EINVAL, "SK_SYMMETRIC applies to Gram calls");
     if (npairs < 0) return fail(SK_EINVAL, "negative npairs");
     const int lam = lam_of(*p);
-    if ((rc = check_offsets(x_off, npairs, lam, "x")) || (rc = check_offsets(y_off, npairs, lam, "y")))
+    if ((rc = check_pairs_geom(x_off, y_off, npairs, lam_of(*p))))
         return rc;
     try {
         sk_plan* P = new sk_plan();
@@ -2069,8 +2175,7 @@ int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p) {
     g_last_error.clear();
-    if (check_params(p, true) || check_dims(d, true) || check_len(lx_pts, 0, "x") ||
-        check_len(ly_pts, 0, "y"))
+    if (check_params(p, true) || check_dims(d, true) || check_gram_geom(lx_pts, ly_pts, lam_of(*p)))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
     if (gram_pipe_applies(*p, nx, lx_pts, ny, ly_pts)) {
@@ -2093,7 +2198,7 @@ int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y
     if (!rc) rc = check_dims(d, true);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
-    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if ((rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p)))) return rc;
     if (nx * ny == 0) return SK_OK;
     if (!X || !Y || !K || !state) return fail(SK_EINVAL, "NULL pointer");
     try {
@@ -2123,7 +2228,7 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
     if (!rc) rc = check_dims(d, true);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
-    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if ((rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p)))) return rc;
     if ((rc = check_symmetric(*p, SK_OP_GRAM, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !state) return fail(SK_EINVAL, "NULL pointer");
     try {
@@ -2161,7 +2266,7 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
     if (!rc) rc = check_dims(d, false);
     if (rc) return rc;
     if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
-    if ((rc = check_len(lx_pts, 0, "x")) || (rc = check_len(ly_pts, 0, "y"))) return rc;
+    if ((rc = check_gram_geom(lx_pts, ly_pts, 0))) return rc;
     const int64_t npairs = nx * ny, lx = lx_pts - 1, ly = ly_pts - 1;
     if (npairs == 0 || lx == 0 || ly == 0) return SK_OK;
     if (!X || !Y || !C || !ws) return fail(SK_EINVAL, "NULL pointer");

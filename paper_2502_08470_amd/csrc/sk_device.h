@@ -29,19 +29,42 @@
 #include <stdint.h>
 
 #define SK_NMAX 12   // largest compiled polynomial order
-#define SK_TMAX 6    // longest interpolation tail (table size)
+#define SK_TMAX 20   // longest interpolation tail (table size)
+#define SK_IFA (2 * SK_NMAX + SK_TMAX + 4)  // 1/m! entries the tail rows index
 
-// Longest interpolation tail compiled per working precision: FP32 reaches
-// its precision with fewer rows than FP64 at the same |c|.
+// Longest interpolation tail compiled per working precision.  The tail a
+// cell needs grows with |c| and with the precision: FP64 needs 17 rows at
+// |c| = 8 and FP32 12 (the decision rule below), so these caps hold every
+// cell with |c| up to about 10.  A cell that still needs rows after the cap
+// is not computed: its outputs are NaN (which reaches the pair's kernel value
+// and gradient) and the device status word records SK_STATUS_TAIL_CAP.
 template <typename R> struct SkTailMax;
-template <> struct SkTailMax<float> { static constexpr int value = 3; };
-template <> struct SkTailMax<double> { static constexpr int value = 6; };
+template <> struct SkTailMax<float> { static constexpr int value = 14; };
+template <> struct SkTailMax<double> { static constexpr int value = 20; };
+// Tail rows whose row derivatives the adjoints keep per replayed step (in
+// registers, or LDS for the strip pipeline).  A checkpoint segment with a
+// longer tail takes the adjoints' slower path, which recomputes each step's
+// inputs and derives the rows on the fly.
+template <typename R> struct SkTailReg;
+template <> struct SkTailReg<float> { static constexpr int value = 3; };
+template <> struct SkTailReg<double> { static constexpr int value = 6; };
+
+// Device status bits (a per-device word, read with sigkernel_status).
+#define SK_STATUS_TAIL_CAP 1u   // an interpolation cell needed more tail rows than compiled
+#define SK_STATUS_WAIT_ABORT 2u // a strip-pipeline wait gave up
+// One word per translation unit that launches kernels; the host reads each
+// through hipGetSymbolAddress.  Written only with vector atomics.
+static __device__ unsigned sk_status_word;
+__device__ __forceinline__ void sk_raise_status(unsigned bit) { atomicOr(&sk_status_word, bit); }
 
 // Kernel-argument tables of the interpolation scheme.
 template <typename R>
 struct SkTab {
     R rs[SK_NMAX + 1][SK_TMAX];  // scaled projection of tail row N+1+t onto row n
-    R rmax[SK_TMAX];             // max_n |rs[n][t]|
+    R rmax[SK_TMAX + 1];         // max_n |rs[n][t]|
+    R cmax[SK_TMAX + 1];         // |c| up to which the projected rows from N+1+t on
+                                 // shrink at least by half per row
+    R ifa[SK_IFA];               // 1/m!, for rows indexed at run time
 };
 
 // ---------------------------------------------------------------------------
@@ -131,12 +154,16 @@ __device__ __forceinline__ int sk_rescale_shift(R m) {
 // any active lane of the wave still needs them (a wave-uniform decision).  A
 // lane no longer needs row r nor any later row when (i) the projection of
 // row r, doubled, is below the working precision relative to the edge scale,
-// 2 |A_r| max_n |Rs[n][r]| <= eps (|A_0^P| + |A_0^Q|), and (ii) the rows from
-// r on shrink at least geometrically with ratio 1/2, which holds once
-// |c| <= (r - N + 1) / 2 (each further row multiplies the dominant Toeplitz
-// term by c / (r + 1 - k), k <= N).  Under (i) and (ii) row r and everything
-// after it together stay below eps relative, so row r is then dropped too:
-// the row that decides is computed but not folded.
+// 2 |A_r| max_n |Rs[n][r]| <= eps (|A_0^P| + |A_0^Q|), and (ii) the projected
+// rows from r on shrink at least geometrically with ratio 1/2.  Each further
+// row multiplies the terms of A by at most |c| / (r + 1 - N), and the
+// projection weights max_n |Rs[n][r']| by at most rho_t from one row to the
+// next (rho_t: the largest such ratio over all later rows, measured on the
+// host), so (ii) holds once |c| <= cmax[t] = (t + 2) / (2 rho_t), t = r - N - 1.
+// Under (i) and (ii) row r and everything after it together stay below eps
+// relative, so row r is then dropped too: the row that decides is computed
+// but not folded.  After TMAX folded rows one more row decides; a lane that
+// still needs it is past the compiled cap (see SkTailMax).
 template <typename R> struct SkEps;
 template <> struct SkEps<float> { static constexpr double value = 1.0 / (1 << 26); };
 template <> struct SkEps<double> { static constexpr double value = 1.0 / (double)(1ull << 55); };
@@ -176,7 +203,11 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                                             double& Po0, double& Po1, double& Qo0, double& Qo1,
                                             R* DP = nullptr, R* DQ = nullptr,
                                             int* Tkept = nullptr, int Tfix = 0) {
-    constexpr int M = N + TMAX;
+    // tail rows unrolled with constant indices (the rest in a loop)
+    constexpr int TU = TMAX < SkTailReg<R>::value ? TMAX : SkTailReg<R>::value;
+    // rows up to N + TU in the unrolled part (+1 that only decides, when
+    // that part reaches the cap)
+    constexpr int M = N + TU + ((TMAX > 0 && !FIXT && TMAX == TU) ? 1 : 0);
     // powers of c needed before the tail (the deciding row N+1 unless the
     // tail length is given); the tail computes its own as it goes
     constexpr int MU = (TMAX > 0 && !FIXT) ? N + 1 : N;
@@ -196,7 +227,7 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         // rows 0..N-1 are always written; tail rows only when kept (a replay
         // with the tail length given reads exactly the rows it folds)
 #pragma unroll
-        for (int r = N; r < M; ++r) {
+        for (int r = N; r < N + TU; ++r) {
             DP[r * DS] = (R)0;
             DQ[r * DS] = (R)0;
         }
@@ -273,32 +304,29 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         const R scale = (R)SkEps<R>::value * (R)(fabs(Po0) + fabs(Qo0));
         const R ac = sk_abs(c);
         R t0p = (R)0, t0q = (R)0, t1p = (R)0, t1q = (R)0;  // tail into rows 0, 1
-        int folded = 0;  // wave-uniform
-#pragma unroll
-        for (int t = 0; t < TMAX; ++t) {
-            if (FIXT && t >= Tfix) break;
-            const int r = N + 1 + t;
-            if (r > MU) power(r);
-            R tp = (R)0, tq = (R)0;
-#pragma unroll
-            for (int k = N; k >= 0; --k) {
-                tp = fma(w[r - k], P[k], tp);
-                tq = fma(w[r - k], Q[k], tq);
-            }
-            R hq = (R)0, hp = (R)0;
-#pragma unroll
-            for (int k = N; k >= 1; --k) {
-                hq = fma(Q[k], ifact<R>(r + k), hq);
-                hp = fma(P[k], ifact<R>(r + k), hp);
-            }
-            const R arp = fma(cp[r], hq, tp), arq = fma(cp[r], hp, tq);
+        int folded = 0;        // wave-uniform
+        bool capped = false;   // wave-uniform: some lane went past the cap
+        bool poison = false;   // this lane's cell is past the cap
+        // Tail row t (row r = N + 1 + t) with Toeplitz parts tp, tq and
+        // Hankel parts hq, hp: decide whether it is needed and fold it.
+        // Returns false once the tail has ended (wave-uniform).
+        auto tail_row = [&](int t, int r, R cpr, R cpr1, R tp, R tq, R hq, R hp) -> bool {
+            const R arp = fma(cpr, hq, tp), arq = fma(cpr, hp, tq);
             if (!FIXT) {
                 const R tail = (R)2 * tab.rmax[t] * (sk_abs(arp) + sk_abs(arq));
-                const bool need = active && (!(tail <= scale) || ac > (R)(0.5 * (t + 2)));
-                if (!sk_wave_any(need)) break;
+                const bool need = active && (!(tail <= scale) || ac > tab.cmax[t]);
+                if (!sk_wave_any(need)) return false;
+                if (t == TMAX) {  // past the compiled cap: these lanes' cells are not computed
+                    capped = true;
+                    poison = need;
+                    if (Tkept) *Tkept = TMAX + 1;
+                    if (need && __builtin_amdgcn_readfirstlane(__lane_id()) == __lane_id())
+                        sk_raise_status(SK_STATUS_TAIL_CAP);
+                    return false;
+                }
             }
             if (WD) {
-                const R rc = (R)r * cp[r - 1];
+                const R rc = (R)r * cpr1;
                 DP[(r - 1) * DS] = fma(rc, hq, tpp);
                 DQ[(r - 1) * DS] = fma(rc, hp, tqp);
                 tpp = tp;
@@ -315,6 +343,74 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                 Po[n] = fma(tab.rs[n][t], arp, Po[n]);
                 Qo[n] = fma(tab.rs[n][t], arq, Qo[n]);
             }
+            return true;
+        };
+        // The first TU rows are unrolled (constant indices; the common tails
+        // end here).  A longer tail continues in a loop over a sliding window
+        // of the powers, with the table entries indexed by the row.
+        bool more = true;
+#pragma unroll
+        for (int t = 0; t < TU + ((!FIXT && TMAX == TU) ? 1 : 0); ++t) {
+            if (FIXT && t >= Tfix) {
+                more = false;
+                break;
+            }
+            const int r = N + 1 + t;
+            if (r > MU) power(r);
+            R tp = (R)0, tq = (R)0;
+#pragma unroll
+            for (int k = N; k >= 0; --k) {
+                tp = fma(w[r - k], P[k], tp);
+                tq = fma(w[r - k], Q[k], tq);
+            }
+            R hq = (R)0, hp = (R)0;
+#pragma unroll
+            for (int k = N; k >= 1; --k) {
+                hq = fma(Q[k], ifact<R>(r + k), hq);
+                hp = fma(P[k], ifact<R>(r + k), hp);
+            }
+            if (!tail_row(t, r, cp[r], cp[r - 1], tp, tq, hq, hp)) {
+                more = false;
+                break;
+            }
+        }
+        if constexpr (TMAX > TU) {
+            static_assert(!WD || DS > 1, "row derivatives past the unrolled tail need an LDS array");
+            if (__builtin_expect(more, false)) {  // wave-uniform; rare: laid out off the hot path
+                R win[N + 1];  // win[k] = c^(r-k) / (r-k)! for the current row r
+#pragma unroll
+                for (int k = 0; k <= N; ++k) win[k] = w[N + TU - k];
+                R cpr = cp[N + TU];
+                const int tend = FIXT ? (Tfix < TMAX ? Tfix : TMAX) : TMAX + 1;
+                // kept rolled: unrolled, the table entries would be hoisted
+                // into scalar registers for the whole kernel
+#pragma unroll 1
+                for (int t = TU; t < tend; ++t) {
+                    const int r = N + 1 + t;
+                    const R cpr1 = cpr;
+                    cpr = cpr * c;
+#pragma unroll
+                    for (int k = N; k >= 1; --k) win[k] = win[k - 1];
+                    win[0] = cpr * tab.ifa[r];
+                    R tp = (R)0, tq = (R)0;
+#pragma unroll
+                    for (int k = N; k >= 0; --k) {
+                        tp = fma(win[k], P[k], tp);
+                        tq = fma(win[k], Q[k], tq);
+                    }
+                    R hq = (R)0, hp = (R)0;
+#pragma unroll
+                    for (int k = N; k >= 1; --k) {
+                        hq = fma(Q[k], tab.ifa[r + k], hq);
+                        hp = fma(P[k], tab.ifa[r + k], hp);
+                    }
+                    if (!tail_row(t, r, cpr, cpr1, tp, tq, hq, hp)) break;
+                }
+            }
+        }
+        if (FIXT && Tfix > TMAX) {  // the forward went past its cap here
+            capped = true;
+            poison = active;
         }
         if (folded == 0) {
             // nothing folded (the common case for small |c|): rows 0, 1 stand
@@ -328,6 +424,13 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
             Qo0 = (double)((R)Qo0 + t0q);
             Po1 = (double)((R)Po1 + t1p);
             Qo1 = (double)((R)Qo1 + t1q);
+        }
+        // a scalar branch around the per-lane poisoning keeps the selects
+        // off the common path
+        if (__builtin_expect(capped, false) && poison) {
+            Po0 = Qo0 = Po1 = Qo1 = (double)NAN;
+#pragma unroll
+            for (int n = 2; n <= N; ++n) Po[n] = Qo[n] = (R)NAN;
         }
     }
     Po[0] = (R)Po0;
@@ -405,4 +508,113 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
         }
     }
     g = gacc;
+}
+
+// The same transposed map, with the row derivatives D^P_r, D^Q_r computed
+// here from the cell's inputs (P, Q) instead of read from a forward replay:
+// D^P_r = sum_{k<=min(r-1,N)} w_{r-1-k} P'_k + r c^{r-1} sum_{k=1}^{N} Q'_k/(r+k)!.
+// Used for the rare checkpoint segments whose tail is longer than the
+// adjoints keep derivatives for (SkTailReg); T > TMAX (a cell past the
+// compiled cap in the forward) gives g = NaN.
+template <typename R, int N, int TMAX>
+__device__ __forceinline__ void sk_cell_adj_in(R c, int T, const SkTab<R>& tab, const R (&a)[N + 1],
+                                               const R (&b)[N + 1], const R (&P)[N + 1],
+                                               const R (&Q)[N + 1], R (&aP)[N + 1],
+                                               R (&aQ)[N + 1], R& g) {
+    R w[N + 1], cp[N + 1];
+    w[0] = (R)1;
+    cp[0] = (R)1;
+#pragma unroll
+    for (int m = 1; m <= N; ++m) {
+        cp[m] = cp[m - 1] * c;
+        w[m] = cp[m] * ifact<R>(m);
+    }
+    aP[0] = a[0];
+    aQ[0] = b[0];
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        aP[k] = b[0] * ifact<R>(k);
+        aQ[k] = a[0] * ifact<R>(k);
+    }
+    R gacc = (R)0;
+    // rows 1..N (constant indices)
+#pragma unroll
+    for (int r = 1; r <= N; ++r) {
+        const R ea = a[r], eb = b[r];
+        R tp = (R)0, tq = (R)0;
+#pragma unroll
+        for (int k = r - 1; k >= 0; --k) {
+            tp = fma(w[r - 1 - k], P[k], tp);
+            tq = fma(w[r - 1 - k], Q[k], tq);
+        }
+        R hq = (R)0, hp = (R)0;
+#pragma unroll
+        for (int k = N; k >= 1; --k) {
+            hq = fma(Q[k], ifact<R>(r + k), hq);
+            hp = fma(P[k], ifact<R>(r + k), hp);
+        }
+        const R rc = (R)r * cp[r - 1];
+        gacc = fma(ea, fma(rc, hq, tp), gacc);
+        gacc = fma(eb, fma(rc, hp, tq), gacc);
+#pragma unroll
+        for (int k = r; k >= 0; --k) {
+            aP[k] = fma(w[r - k], ea, aP[k]);
+            aQ[k] = fma(w[r - k], eb, aQ[k]);
+        }
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            aP[k] = fma(cp[r] * eb, ifact<R>(r + k), aP[k]);
+            aQ[k] = fma(cp[r] * ea, ifact<R>(r + k), aQ[k]);
+        }
+    }
+    // tail rows r = N+1 .. N+T, in a loop: win[i] = c^(r-i) / (r-i)!
+    const int Tu = __builtin_amdgcn_readfirstlane(T);
+    const int tend = Tu < TMAX ? Tu : TMAX;
+    R win[N + 2];
+#pragma unroll
+    for (int i = 0; i <= N; ++i) win[i] = w[N - i];
+    win[N + 1] = (R)0;
+    R cpr = cp[N];
+#pragma unroll 1
+    for (int t = 0; t < tend; ++t) {
+        const int r = N + 1 + t;
+        const R cpr1 = cpr;
+        cpr = cpr * c;
+#pragma unroll
+        for (int i = N + 1; i >= 1; --i) win[i] = win[i - 1];
+        win[0] = cpr * tab.ifa[r];
+        R ea = tab.rs[0][t] * a[0], eb = tab.rs[0][t] * b[0];
+#pragma unroll
+        for (int n = 1; n <= N; ++n) {
+            ea = fma(tab.rs[n][t], a[n], ea);
+            eb = fma(tab.rs[n][t], b[n], eb);
+        }
+        R tp = (R)0, tq = (R)0;
+#pragma unroll
+        for (int k = N; k >= 0; --k) {
+            tp = fma(win[k + 1], P[k], tp);
+            tq = fma(win[k + 1], Q[k], tq);
+        }
+        R hq = (R)0, hp = (R)0;
+#pragma unroll
+        for (int k = N; k >= 1; --k) {
+            hq = fma(Q[k], tab.ifa[r + k], hq);
+            hp = fma(P[k], tab.ifa[r + k], hp);
+        }
+        const R rc = (R)r * cpr1;
+        gacc = fma(ea, fma(rc, hq, tp), gacc);
+        gacc = fma(eb, fma(rc, hp, tq), gacc);
+#pragma unroll
+        for (int k = N; k >= 0; --k) {
+            aP[k] = fma(win[k], ea, aP[k]);
+            aQ[k] = fma(win[k], eb, aQ[k]);
+        }
+        const R cb = cpr * eb, ca = cpr * ea;
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            aP[k] = fma(cb, tab.ifa[r + k], aP[k]);
+            aQ[k] = fma(ca, tab.ifa[r + k], aQ[k]);
+        }
+    }
+    g = T > TMAX ? (R)NAN : gacc;
 }

@@ -971,6 +971,8 @@ __device__ __forceinline__ bool sk_wait_count(const int* prog, int need, int* ab
         if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         if (it >= limit) {
             __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__builtin_amdgcn_readfirstlane(__lane_id()) == __lane_id())
+                sk_raise_status(SK_STATUS_WAIT_ABORT);
             return false;
         }
         __builtin_amdgcn_s_sleep(4);
@@ -1272,200 +1274,277 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     }
     int El = SK_ZERO_EXP, Els = SK_ZERO_EXP;
     const int nck = (g.nsteps + S - 1) / S;
+    // tail rows whose derivatives a replayed step keeps; segments with a
+    // longer tail take the slow path below
+    constexpr int TR = TMAX > 0 ? SkTailReg<R>::value : 0;
+    // Inputs of replayed step u of a segment: the bottom edge P (this lane's
+    // state) and the left edge Qin (from lane r-1, or the strip boundary /
+    // the initial edge for lane 0), aligned to a common exponent E.  Step 0
+    // takes the checkpoint as it is.  Returns whether the cell is live.
+    auto replay_in = [&](int u, R (&P)[N + 1], const R (&Qs)[N + 1], R (&Qin)[N + 1], int& E,
+                         int Es, int L, int s, int j) -> bool {
+        const int i = s * 64 + r;
+        const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
+        if (u == 0) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
+            return live;
+        }
+#pragma unroll
+        for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+        int Ein = lane_from_prev(Es);
+        if (live) {
+            if (j == 0) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
+                E = 0;
+            }
+            if (r == 0) {
+                if (s == 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
+                    Ein = 0;
+                } else {
+                    const int64_t o = (int64_t)s * g.ly + j;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                    Ein = a.qe[pd.qe_off + o];
+                }
+            }
+            const int Ec = E > Ein ? E : Ein;
+            const int dp = E - Ec, dq = Ein - Ec;
+            if (sk_wave_any(dp != 0 || dq != 0)) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    P[n] = sk_ldexp(P[n], dp);
+                    Qin[n] = sk_ldexp(Qin[n], dq);
+                }
+            }
+            E = Ec;
+        }
+        return live;
+    };
+    // One adjoint step (replayed step u of the segment at tau0): the adjoint
+    // of the cell's top edge comes from this lane's later cell, that of its
+    // right edge from lane r+1 (lane 63: the next strip's lane 0, through the
+    // ring or the staging slot); `cell(ap, aq, gv)` maps them to the inputs'
+    // adjoints (lp, lqs) and dL/dc.
+    auto adj_step = [&](int u, int tau0, bool live, int ss, int jj, int Eu, auto&& cell) {
+        const int tau = tau0 + u;
+        const int i = ss * 64 + r;
+        const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
+        R lq_recv[N + 1];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
+        int El_recv = lane_from_next(Els);
+        if (r == 63 && live && !last_row) {
+            if (gx) {
+                const unsigned* rec = stage + (tau & 7) * GXW;
+#pragma unroll
+                for (int n = 0; n <= N; ++n)
+                    lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
+                El_recv = (int)rec[(N + 1) * (ES / 4)];
+            } else {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) lq_recv[n] = llds[jj * (N + 1) + n];
+                El_recv = ltag[jj];
+            }
+        }
+        // outputs nobody consumes have zero adjoint
+        const bool ta = live && !last_col, tb = live && !last_row;
+        R ap[N + 1], aq[N + 1];
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            ap[n] = ta ? lp[n] : (R)0;
+            aq[n] = tb ? lq_recv[n] : (R)0;
+        }
+        int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+        // endpoint seed (once per pair): L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
+        const bool seed = live && last_col && last_row;
+        if (sk_wave_any(seed) && seed) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = (R)0.5 * gk * ifact<R>(n);
+                aq[n] = ap[n];
+            }
+            ea = gexp;
+            eb = gexp;
+        }
+        const int Ec = ea > eb ? ea : eb;
+        // vectors tagged SK_ZERO_EXP are zero: only real exponents below
+        // Ec need a shift, which is rare
+        const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
+        if (sk_wave_any(sa || sb)) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = sk_ldexp(ap[n], ea - Ec);
+                aq[n] = sk_ldexp(aq[n], eb - Ec);
+            }
+        }
+        R gv;
+        cell(ap, aq, gv);
+        El = Ec;
+        Els = Ec;
+        if (live && r == 0 && ss > 0) {
+            if (gx) {
+                unsigned* rec = xg + (int64_t)jj * GXW;
+#pragma unroll
+                for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(rec + n * (ES / 4)) = lqs[n];
+                rec[(N + 1) * (ES / 4)] = (unsigned)Ec;
+            } else {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
+                ltag[jj] = Ec;
+            }
+        }
+        gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, Ec + Eu) : (R)0;
+        if ((tau & 7) == 0 && live) {
+            R m = (R)0;
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
+                m = x1 > m ? x1 : m;
+                m = x2 > m ? x2 : m;
+            }
+            const int sh = sk_rescale_shift<R>(m);
+            if (sh != 0) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    lp[n] = sk_ldexp(lp[n], -sh);
+                    lqs[n] = sk_ldexp(lqs[n], -sh);
+                }
+                El += sh;
+                Els = El;
+            }
+        }
+    };
     for (int kk = nck - 1; kk >= 0; --kk) {
         const int tau0 = kk * S;
         // blocks of 8 steps, processed from the top; a segment never
         // straddles two blocks (S divides 8)
         if (gx && (kk == nck - 1 || ((tau0 + S) & 7) == 0))
             sk_gx_stage<GXW>(xr, stage, xg, (tau0 & ~7) - 8, r, lane63_col);
-        R cseg[S];
-#pragma unroll
-        for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
-        // ---- replay the segment's forward from the checkpoint, recording
-        // each cell's row derivatives, kept tail length and exponent
-        constexpr int M = N + TMAX;
-        R Dp[S][M], Dq[S][M];
-        int Tst[S], Est[S];
-        bool lv[S];
-        int sst[S], jst[S];
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
-        int E = a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r];
+        const int E0 = a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r];
         // tail lengths the forward folded at the segment's steps
         const unsigned tword =
             TMAX > 0 ? (unsigned)__builtin_amdgcn_readfirstlane(
                            a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + SK_LANES])
                      : 0u;
-        R P[N + 1], Qs[N + 1];
-#pragma unroll
-        for (int n = 0; n <= N; ++n) {
-            P[n] = ck[n * 64 + r];
-            Qs[n] = ck[(N + 1 + n) * 64 + r];
-        }
-        int Es = E;
-        int L = tau0 - r, s = 0, j = 0;
-        if (L >= 0) {
-            s = L / g.Tp;
-            j = L - s * g.Tp;
-        }
+        unsigned tseg = 0u;  // longest tail of the segment (wave-uniform)
 #pragma unroll
         for (int u = 0; u < S; ++u) {
-            const int i = s * 64 + r;
-            const bool live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
-            R Qin[N + 1];
-            if (u == 0) {
-#pragma unroll
-                for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
-            } else {
-#pragma unroll
-                for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
-                int Ein = lane_from_prev(Es);
-                if (live) {
-                    if (j == 0) {
-#pragma unroll
-                        for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
-                        E = 0;
-                    }
-                    if (r == 0) {
-                        if (s == 0) {
-#pragma unroll
-                            for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
-                            Ein = 0;
-                        } else {
-                            const int64_t o = (int64_t)s * g.ly + j;
-#pragma unroll
-                            for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
-                            Ein = a.qe[pd.qe_off + o];
-                        }
-                    }
-                    const int Ec = E > Ein ? E : Ein;
-                    const int dp = E - Ec, dq = Ein - Ec;
-                    if (sk_wave_any(dp != 0 || dq != 0)) {
-#pragma unroll
-                        for (int n = 0; n <= N; ++n) {
-                            P[n] = sk_ldexp(P[n], dp);
-                            Qin[n] = sk_ldexp(Qin[n], dq);
-                        }
-                    }
-                    E = Ec;
-                }
-            }
-            lv[u] = live;
-            sst[u] = s;
-            jst[u] = j;
-            Est[u] = E;
-            R Po[N + 1], Qo[N + 1];
-            double Po0, Po1, Qo0, Qo1;
-            Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
-            sk_cell_fwd<R, N, TMAX, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
-                                                       a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
-                                                       Dq[u], nullptr, Tst[u]);
-#pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                P[n] = Po[n];
-                Qs[n] = Qo[n];
-            }
-            Es = E;
-            if (L >= 0) {
-                if (++j == g.Tp) {
-                    j = 0;
-                    ++s;
-                }
-            }
-            ++L;
+            const unsigned tu = (tword >> (8 * u)) & 0xffu;
+            tseg = tu > tseg ? tu : tseg;
         }
-        // ---- adjoint steps in reverse
+        if (TMAX == 0 || tseg <= (unsigned)TR) {
+            R cseg[S];
 #pragma unroll
-        for (int u = S - 1; u >= 0; --u) {
-            const int tau = tau0 + u;
-            const bool live = lv[u];
-            const int ss = sst[u], jj = jst[u], i = ss * 64 + r;
-            const bool last_row = (i == g.lx - 1), last_col = (jj == g.ly - 1);
-            // adjoint of the right edge: from lane r+1, or for lane 63 from
-            // the next strip's lane 0 through the ring or the staging slot
-            R lq_recv[N + 1];
-#pragma unroll
-            for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
-            int El_recv = lane_from_next(Els);
-            if (r == 63 && live && !last_row) {
-                if (gx) {
-                    const unsigned* rec = stage + (tau & 7) * GXW;
-#pragma unroll
-                    for (int n = 0; n <= N; ++n)
-                        lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
-                    El_recv = (int)rec[(N + 1) * (ES / 4)];
-                } else {
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) lq_recv[n] = llds[jj * (N + 1) + n];
-                    El_recv = ltag[jj];
-                }
-            }
-            // top edge from this lane's previous (later) cell, right edge as
-            // above; outputs nobody consumes have zero adjoint
-            const bool ta = live && !last_col, tb = live && !last_row;
-            R ap[N + 1], aq[N + 1];
+            for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
+            // ---- replay the segment's forward from the checkpoint, recording
+            // each cell's row derivatives, kept tail length and exponent
+            constexpr int M = N + TR;
+            R Dp[S][M], Dq[S][M];
+            int Tst[S], Est[S];
+            bool lv[S];
+            int sst[S], jst[S];
+            int E = E0;
+            R P[N + 1], Qs[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
-                ap[n] = ta ? lp[n] : (R)0;
-                aq[n] = tb ? lq_recv[n] : (R)0;
+                P[n] = ck[n * 64 + r];
+                Qs[n] = ck[(N + 1 + n) * 64 + r];
             }
-            int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
-            // endpoint seed (once per pair): L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
-            const bool seed = live && last_col && last_row;
-            if (sk_wave_any(seed) && seed) {
+            int Es = E;
+            int L = tau0 - r, s = 0, j = 0;
+            if (L >= 0) {
+                s = L / g.Tp;
+                j = L - s * g.Tp;
+            }
+#pragma unroll
+            for (int u = 0; u < S; ++u) {
+                R Qin[N + 1];
+                const bool live = replay_in(u, P, Qs, Qin, E, Es, L, s, j);
+                lv[u] = live;
+                sst[u] = s;
+                jst[u] = j;
+                Est[u] = E;
+                R Po[N + 1], Qo[N + 1];
+                double Po0, Po1, Qo0, Qo1;
+                Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
+                sk_cell_fwd<R, N, TR, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
+                                                         a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
+                                                         Dq[u], nullptr, Tst[u]);
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
-                    ap[n] = (R)0.5 * gk * ifact<R>(n);
-                    aq[n] = ap[n];
+                    P[n] = Po[n];
+                    Qs[n] = Qo[n];
                 }
-                ea = gexp;
-                eb = gexp;
+                Es = E;
+                if (L >= 0) {
+                    if (++j == g.Tp) {
+                        j = 0;
+                        ++s;
+                    }
+                }
+                ++L;
             }
-            const int Ec = ea > eb ? ea : eb;
-            // vectors tagged SK_ZERO_EXP are zero: only real exponents below
-            // Ec need a shift, which is rare
-            const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
-            if (sk_wave_any(sa || sb)) {
+            // ---- adjoint steps in reverse
+#pragma unroll
+            for (int u = S - 1; u >= 0; --u)
+                adj_step(u, tau0, lv[u], sst[u], jst[u], Est[u], [&](R (&ap)[N + 1], R (&aq)[N + 1], R& gv) {
+                    sk_cell_adj<R, N, TR>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
+                });
+        } else {
+            // ---- slow path (a tail longer than TR rows in this segment):
+            // for each step u, from the last, replay steps 0..u-1 from the
+            // checkpoint to recover the cell's inputs, then take the adjoint
+            // step with the row derivatives computed from those inputs
+#pragma unroll 1
+            for (int u = S - 1; u >= 0; --u) {
+                int E = E0;
+                R P[N + 1], Qs[N + 1], Qin[N + 1];
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
-                    ap[n] = sk_ldexp(ap[n], ea - Ec);
-                    aq[n] = sk_ldexp(aq[n], eb - Ec);
+                    P[n] = ck[n * 64 + r];
+                    Qs[n] = ck[(N + 1 + n) * 64 + r];
                 }
-            }
-            R gv;
-            sk_cell_adj<R, N, TMAX>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
-            El = Ec;
-            Els = Ec;
-            if (live && r == 0 && ss > 0) {
-                if (gx) {
-                    unsigned* rec = xg + (int64_t)jj * GXW;
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(rec + n * (ES / 4)) = lqs[n];
-                    rec[(N + 1) * (ES / 4)] = (unsigned)Ec;
-                } else {
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
-                    ltag[jj] = Ec;
+                int Es = E;
+                int L = tau0 - r, s = 0, j = 0;
+                if (L >= 0) {
+                    s = L / g.Tp;
+                    j = L - s * g.Tp;
                 }
-            }
-            gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, Ec + Est[u]) : (R)0;
-            if ((tau & 7) == 0 && live) {
-                R m = (R)0;
-#pragma unroll
-                for (int n = 0; n <= N; ++n) {
-                    R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
-                    m = x1 > m ? x1 : m;
-                    m = x2 > m ? x2 : m;
-                }
-                const int sh = sk_rescale_shift<R>(m);
-                if (sh != 0) {
+                bool live = false;
+#pragma unroll 1
+                for (int v = 0;; ++v) {
+                    live = replay_in(v, P, Qs, Qin, E, Es, L, s, j);
+                    if (v == u) break;
+                    R Po[N + 1], Qo[N + 1];
+                    double Po0, Po1, Qo0, Qo1;
+                    const int Tv = (int)((tword >> (8 * v)) & 0xffu);
+                    sk_cell_fwd<R, N, TMAX, false, false, true>(
+                        P, Qin, 0.0, 0.0, 0.0, 0.0, cs[(int64_t)(tau0 + v) * 64 + r], live, a.tab,
+                        Po, Qo, Po0, Po1, Qo0, Qo1, nullptr, nullptr, nullptr, Tv);
 #pragma unroll
                     for (int n = 0; n <= N; ++n) {
-                        lp[n] = sk_ldexp(lp[n], -sh);
-                        lqs[n] = sk_ldexp(lqs[n], -sh);
+                        P[n] = Po[n];
+                        Qs[n] = Qo[n];
                     }
-                    El += sh;
-                    Els = El;
+                    Es = E;
+                    if (L >= 0) {
+                        if (++j == g.Tp) {
+                            j = 0;
+                            ++s;
+                        }
+                    }
+                    ++L;
                 }
+                const int Tu = (int)((tword >> (8 * u)) & 0xffu);
+                const R cu = cs[(int64_t)(tau0 + u) * 64 + r];
+                adj_step(u, tau0, live, s, j, E, [&](R (&ap)[N + 1], R (&aq)[N + 1], R& gv) {
+                    sk_cell_adj_in<R, N, TMAX>(cu, Tu, a.tab, ap, aq, P, Qin, lp, lqs, gv);
+                });
             }
         }
     }
@@ -1532,18 +1611,22 @@ struct AdjPipeArgs {
 };
 
 // LDS of the pipelined adjoint: the exchange staging slot, then the
-// segment's row derivatives [P/Q][S][N + TMAX][64 lanes] (in LDS rather than
-// registers, which leaves room for two waves per SIMD without spilling).
+// segment's row derivatives [P/Q][S][N + TR][64 lanes] (in LDS rather than
+// registers, which leaves room for two waves per SIMD without spilling), TR
+// the tail rows kept per step (SkTailReg; 0 for the approximation scheme,
+// TMAX = 0).
 template <typename R>
 __host__ __device__ constexpr int sk_adj_pipe_lds(int N, int TMAX, int S) {
-    return sk_gx_stage_bytes(N, (int)sizeof(R)) + 2 * S * (N + TMAX) * 64 * (int)sizeof(R);
+    return sk_gx_stage_bytes(N, (int)sizeof(R)) +
+           2 * S * (N + (TMAX > 0 ? SkTailReg<R>::value : 0)) * 64 * (int)sizeof(R);
 }
 
 template <typename R, int N, int TMAX, int S>
 __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     const int r = threadIdx.x;
     constexpr int ES = (int)sizeof(R), GXW = sk_gx_words(N, ES);
-    constexpr int XR = (8 * GXW + 63) / 64, M = N + TMAX, RW = (N + 1) * (ES / 4) + 1;
+    constexpr int TR = TMAX > 0 ? SkTailReg<R>::value : 0;
+    constexpr int XR = (8 * GXW + 63) / 64, M = N + TR, RW = (N + 1) * (ES / 4) + 1;
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
     R* dlds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES)) + r;  // [2][S][M][64], this lane's slot
@@ -1591,8 +1674,9 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
         unsigned xr[XR];
 #pragma unroll
         for (int h = 0; h < XR; ++h) xr[h] = 0u;
-        bool ok = true;
-        {  // records of the first (topmost) block
+        // a checkpoint sweep that gave up left incomplete checkpoints: no replay
+        bool ok = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        if (ok) {  // records of the first (topmost) block
             const int nd = need_of(nloc - 8);
             if (nd > 0) {
                 ok = sk_wait_count(prog + s + 1, nd, a.abort, a.spin_limit);
@@ -1611,6 +1695,124 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                 }
             }
         }
+        // inputs of replayed step u (column j of this lane): as in the
+        // batched adjoint, with the strip's own first column and boundary
+        auto replay_in = [&](int u, int j, R (&P)[N + 1], const R (&Qs)[N + 1], R (&Qin)[N + 1],
+                             int& E, int Es) -> bool {
+            const bool live = rowok && j >= 0 && j < ly;
+            if (u == 0) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
+                return live;
+            }
+#pragma unroll
+            for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
+            int Ein = lane_from_prev(Es);
+            if (live) {
+                if (j == 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
+                    E = 0;
+                }
+                if (r == 0) {
+                    if (s == 0) {
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
+                        Ein = 0;
+                    } else {
+                        const int64_t o = (int64_t)s * ly + j;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                        Ein = a.qe[pd.qe_off + o];
+                    }
+                }
+                const int Ec = E > Ein ? E : Ein;
+                const int dp = E - Ec, dq = Ein - Ec;
+                if (sk_wave_any(dp != 0 || dq != 0)) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        P[n] = sk_ldexp(P[n], dp);
+                        Qin[n] = sk_ldexp(Qin[n], dq);
+                    }
+                }
+                E = Ec;
+            }
+            return live;
+        };
+        // one adjoint step at local step t (column jj of this lane)
+        auto adj_step = [&](int t, bool live, int jj, int Eu, auto&& cell) {
+            const bool last_row = (i == g.lx - 1), last_col = (jj == ly - 1);
+            R lq_recv[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
+            int El_recv = lane_from_next(Els);
+            if (r == 63 && live && !last_row) {  // from strip s+1's lane 0
+                const unsigned* rec = stage + (t & 7) * GXW;
+#pragma unroll
+                for (int n = 0; n <= N; ++n) lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
+                El_recv = (int)rec[(N + 1) * (ES / 4)];
+            }
+            const bool ta = live && !last_col, tb = live && !last_row;
+            R ap[N + 1], aq[N + 1];
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = ta ? lp[n] : (R)0;
+                aq[n] = tb ? lq_recv[n] : (R)0;
+            }
+            int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+            const bool seed = live && last_col && last_row;
+            if (sk_wave_any(seed) && seed) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = (R)0.5 * gk * ifact<R>(n);
+                    aq[n] = ap[n];
+                }
+                ea = gexp;
+                eb = gexp;
+            }
+            const int Ec = ea > eb ? ea : eb;
+            const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
+            if (sk_wave_any(sa || sb)) {
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = sk_ldexp(ap[n], ea - Ec);
+                    aq[n] = sk_ldexp(aq[n], eb - Ec);
+                }
+            }
+            R gv;
+            cell(ap, aq, gv);
+            El = Ec;
+            Els = Ec;
+            if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
+                unsigned wd[RW];
+#pragma unroll
+                for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(wd + n * (ES / 4)) = lqs[n];
+                wd[RW - 1] = (unsigned)Ec;
+                unsigned* rec = rout + (int64_t)jj * GXW;
+#pragma unroll
+                for (int k = 0; k < RW; ++k) sk_store_coherent(rec + k, wd[k]);
+            }
+            if (live) gs[(int64_t)t * 64 + r] = sk_ldexp(gv, Ec + Eu);
+            if ((t & 7) == 0 && live) {
+                R m = (R)0;
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
+                    m = x1 > m ? x1 : m;
+                    m = x2 > m ? x2 : m;
+                }
+                const int sh = sk_rescale_shift<R>(m);
+                if (sh != 0) {
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) {
+                        lp[n] = sk_ldexp(lp[n], -sh);
+                        lqs[n] = sk_ldexp(lqs[n], -sh);
+                    }
+                    El += sh;
+                    Els = El;
+                }
+            }
+        };
         int published = 0;
         for (int kk = nckl - 1; ok && kk >= 0; --kk) {
             const int t0 = kk * S;
@@ -1623,159 +1825,99 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                 }
                 sk_gx_stage<GXW, true>(xr, stage, rin, b - 8, r, col63);
             }
-            R cseg[S];
-#pragma unroll
-            for (int u = 0; u < S; ++u)
-                cseg[u] = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
-            // ---- replay the segment's forward from the checkpoint
-            int Tst[S], Est[S], jst[S];
-            bool lv[S];
             const R* ck = ckb + (int64_t)kk * 2 * (N + 1) * 64;
-            int E = ceb[(int64_t)kk * (SK_LANES + 1) + r];
+            const int E0 = ceb[(int64_t)kk * (SK_LANES + 1) + r];
             const unsigned tword =
                 TMAX > 0 ? (unsigned)__builtin_amdgcn_readfirstlane(ceb[(int64_t)kk * (SK_LANES + 1) + SK_LANES])
                          : 0u;
-            R P[N + 1], Qs[N + 1];
-#pragma unroll
-            for (int n = 0; n <= N; ++n) {
-                P[n] = ck[n * 64 + r];
-                Qs[n] = ck[(N + 1 + n) * 64 + r];
-            }
-            int Es = E;
+            unsigned tseg = 0u;  // longest tail of the segment (wave-uniform)
 #pragma unroll
             for (int u = 0; u < S; ++u) {
-                const int j = t0 + u - r;
-                const bool live = rowok && j >= 0 && j < ly;
-                R Qin[N + 1];
-                if (u == 0) {
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) Qin[n] = Qs[n];
-                } else {
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
-                    int Ein = lane_from_prev(Es);
-                    if (live) {
-                        if (j == 0) {
-#pragma unroll
-                            for (int n = 0; n <= N; ++n) P[n] = n == 0 ? (R)1 : (R)0;
-                            E = 0;
-                        }
-                        if (r == 0) {
-                            if (s == 0) {
-#pragma unroll
-                                for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
-                                Ein = 0;
-                            } else {
-                                const int64_t o = (int64_t)s * ly + j;
-#pragma unroll
-                                for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
-                                Ein = a.qe[pd.qe_off + o];
-                            }
-                        }
-                        const int Ec = E > Ein ? E : Ein;
-                        const int dp = E - Ec, dq = Ein - Ec;
-                        if (sk_wave_any(dp != 0 || dq != 0)) {
-#pragma unroll
-                            for (int n = 0; n <= N; ++n) {
-                                P[n] = sk_ldexp(P[n], dp);
-                                Qin[n] = sk_ldexp(Qin[n], dq);
-                            }
-                        }
-                        E = Ec;
-                    }
-                }
-                lv[u] = live;
-                jst[u] = j;
-                Est[u] = E;
-                R Po[N + 1], Qo[N + 1];
-                double Po0, Po1, Qo0, Qo1;
-                Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
-                sk_cell_fwd<R, N, TMAX, true, false, true, 64>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u],
-                                                               live, a.tab, Po, Qo, Po0, Po1, Qo0, Qo1,
-                                                               DPu(u), DQu(u), nullptr, Tst[u]);
-#pragma unroll
-                for (int n = 0; n <= N; ++n) {
-                    P[n] = Po[n];
-                    Qs[n] = Qo[n];
-                }
-                Es = E;
+                const unsigned tu = (tword >> (8 * u)) & 0xffu;
+                tseg = tu > tseg ? tu : tseg;
             }
-            // ---- adjoint steps in reverse
+            if (TMAX == 0 || tseg <= (unsigned)TR) {
+                R cseg[S];
 #pragma unroll
-            for (int u = S - 1; u >= 0; --u) {
-                const int t = t0 + u;
-                const bool live = lv[u];
-                const int jj = jst[u];
-                const bool last_row = (i == g.lx - 1), last_col = (jj == ly - 1);
-                R lq_recv[N + 1];
-#pragma unroll
-                for (int n = 0; n <= N; ++n) lq_recv[n] = lane_from_next(lqs[n]);
-                int El_recv = lane_from_next(Els);
-                if (r == 63 && live && !last_row) {  // from strip s+1's lane 0
-                    const unsigned* rec = stage + (t & 7) * GXW;
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) lq_recv[n] = *reinterpret_cast<const R*>(rec + n * (ES / 4));
-                    El_recv = (int)rec[(N + 1) * (ES / 4)];
-                }
-                const bool ta = live && !last_col, tb = live && !last_row;
-                R ap[N + 1], aq[N + 1];
+                for (int u = 0; u < S; ++u)
+                    cseg[u] = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
+                // ---- replay the segment's forward from the checkpoint
+                int Tst[S], Est[S], jst[S];
+                bool lv[S];
+                int E = E0;
+                R P[N + 1], Qs[N + 1];
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
-                    ap[n] = ta ? lp[n] : (R)0;
-                    aq[n] = tb ? lq_recv[n] : (R)0;
+                    P[n] = ck[n * 64 + r];
+                    Qs[n] = ck[(N + 1 + n) * 64 + r];
                 }
-                int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
-                const bool seed = live && last_col && last_row;
-                if (sk_wave_any(seed) && seed) {
+                int Es = E;
+#pragma unroll
+                for (int u = 0; u < S; ++u) {
+                    R Qin[N + 1];
+                    const int j = t0 + u - r;
+                    const bool live = replay_in(u, j, P, Qs, Qin, E, Es);
+                    lv[u] = live;
+                    jst[u] = j;
+                    Est[u] = E;
+                    R Po[N + 1], Qo[N + 1];
+                    double Po0, Po1, Qo0, Qo1;
+                    Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
+                    sk_cell_fwd<R, N, TR, true, false, true, 64>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u],
+                                                                 live, a.tab, Po, Qo, Po0, Po1, Qo0, Qo1,
+                                                                 DPu(u), DQu(u), nullptr, Tst[u]);
 #pragma unroll
                     for (int n = 0; n <= N; ++n) {
-                        ap[n] = (R)0.5 * gk * ifact<R>(n);
-                        aq[n] = ap[n];
+                        P[n] = Po[n];
+                        Qs[n] = Qo[n];
                     }
-                    ea = gexp;
-                    eb = gexp;
+                    Es = E;
                 }
-                const int Ec = ea > eb ? ea : eb;
-                const bool sa = ea != Ec && ea != SK_ZERO_EXP, sb = eb != Ec && eb != SK_ZERO_EXP;
-                if (sk_wave_any(sa || sb)) {
+                // ---- adjoint steps in reverse
+#pragma unroll
+                for (int u = S - 1; u >= 0; --u)
+                    adj_step(t0 + u, lv[u], jst[u], Est[u], [&](R (&ap)[N + 1], R (&aq)[N + 1], R& gv) {
+                        sk_cell_adj<R, N, TR, 64>(cseg[u], Tst[u], a.tab, ap, aq, DPu(u), DQu(u), lp,
+                                                  lqs, gv);
+                    });
+            } else {
+                // ---- slow path (a tail longer than TR rows in this segment):
+                // replay steps 0..u-1 for each step u, from the last, and take
+                // the adjoint step with derivatives from the cell's inputs
+#pragma unroll 1
+                for (int u = S - 1; u >= 0; --u) {
+                    int E = E0;
+                    R P[N + 1], Qs[N + 1], Qin[N + 1];
 #pragma unroll
                     for (int n = 0; n <= N; ++n) {
-                        ap[n] = sk_ldexp(ap[n], ea - Ec);
-                        aq[n] = sk_ldexp(aq[n], eb - Ec);
+                        P[n] = ck[n * 64 + r];
+                        Qs[n] = ck[(N + 1 + n) * 64 + r];
                     }
-                }
-                R gv;
-                sk_cell_adj<R, N, TMAX, 64>(cseg[u], Tst[u], a.tab, ap, aq, DPu(u), DQu(u), lp, lqs, gv);
-                El = Ec;
-                Els = Ec;
-                if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
-                    unsigned wd[RW];
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(wd + n * (ES / 4)) = lqs[n];
-                    wd[RW - 1] = (unsigned)Ec;
-                    unsigned* rec = rout + (int64_t)jj * GXW;
-#pragma unroll
-                    for (int k = 0; k < RW; ++k) sk_store_coherent(rec + k, wd[k]);
-                }
-                if (live) gs[(int64_t)t * 64 + r] = sk_ldexp(gv, Ec + Est[u]);
-                if ((t & 7) == 0 && live) {
-                    R m = (R)0;
-#pragma unroll
-                    for (int n = 0; n <= N; ++n) {
-                        R x1 = sk_abs(lp[n]), x2 = sk_abs(lqs[n]);
-                        m = x1 > m ? x1 : m;
-                        m = x2 > m ? x2 : m;
-                    }
-                    const int sh = sk_rescale_shift<R>(m);
-                    if (sh != 0) {
+                    int Es = E;
+                    bool live = false;
+#pragma unroll 1
+                    for (int v = 0;; ++v) {
+                        live = replay_in(v, t0 + v - r, P, Qs, Qin, E, Es);
+                        if (v == u) break;
+                        R Po[N + 1], Qo[N + 1];
+                        double Po0, Po1, Qo0, Qo1;
+                        const int Tv = (int)((tword >> (8 * v)) & 0xffu);
+                        const R cv = (t0 + v < rows_left) ? cs[(int64_t)(t0 + v) * 64 + r] : (R)0;
+                        sk_cell_fwd<R, N, TMAX, false, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cv, live,
+                                                                    a.tab, Po, Qo, Po0, Po1, Qo0, Qo1,
+                                                                    nullptr, nullptr, nullptr, Tv);
 #pragma unroll
                         for (int n = 0; n <= N; ++n) {
-                            lp[n] = sk_ldexp(lp[n], -sh);
-                            lqs[n] = sk_ldexp(lqs[n], -sh);
+                            P[n] = Po[n];
+                            Qs[n] = Qo[n];
                         }
-                        El += sh;
-                        Els = El;
+                        Es = E;
                     }
+                    const int Tu = (int)((tword >> (8 * u)) & 0xffu);
+                    const R cu = (t0 + u < rows_left) ? cs[(int64_t)(t0 + u) * 64 + r] : (R)0;
+                    adj_step(t0 + u, live, t0 + u - r, E, [&](R (&ap)[N + 1], R (&aq)[N + 1], R& gv) {
+                        sk_cell_adj_in<R, N, TMAX>(cu, Tu, a.tab, ap, aq, P, Qin, lp, lqs, gv);
+                    });
                 }
             }
             // lane 0 has handed over the columns j >= t0: publish them once

@@ -64,6 +64,9 @@ struct SkLaunch {
                                int64_t nperm, R* stats, double* pvalue, hipStream_t st);
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
+    // device address of the status word the kernels of this instantiation
+    // raise bits in (SK_STATUS_*), for the current device
+    static hipError_t status_word(unsigned** p);
     // LDS bytes per workgroup: the global-exchange staging slot plus an LDS
     // ring of `ring` columns (forward: 2 FP64 coefficients + N-1
     // coefficients + tag per column; adjoint: N+1 coefficients + tag)

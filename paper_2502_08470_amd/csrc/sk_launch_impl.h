@@ -401,3 +401,8 @@ hipError_t SkLaunch<R>::unskew(const SkPairSrc& src, const R* cskew, R* C, int64
     SK_CHECK_LAUNCH();
     return hipSuccess;
 }
+
+template <typename R>
+hipError_t SkLaunch<R>::status_word(unsigned** p) {
+    return hipGetSymbolAddress(reinterpret_cast<void**>(p), HIP_SYMBOL(sk_status_word));
+}

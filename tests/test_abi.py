@@ -261,3 +261,60 @@ def test_pipeline_workspace_queries():
         lib.sigkernel_gram_state_size(2, 300, 2, 200, 3, P()) > 0
     assert lib.sigkernel_gram_state_size(2, 60, 2, 200, 3, P(algo=2)) == \
         lib.sigkernel_gram_state_size(2, 60, 2, 200, 3, P())
+
+
+# ---------------------------------------------------------------------------
+# pair geometry: wavefront step counts are checked in 64 bits on the host
+# ---------------------------------------------------------------------------
+def _steps_error():
+    return "wavefront steps" in L.last_error() or "exceed 2^24" in L.last_error()
+
+
+@pytest.mark.parametrize("lxp,lyp,p", [
+    (524289, 524289, dict(scheme=1, order=4)),      # 2^19 segments each: ~4.3e9 steps
+    (1500, 1500, dict(scheme=0, order=8)),          # FD, 1499 * 256 refined segments each
+    (1500, 1500, dict(scheme=2, order=6, dyadic=8)),  # hybrid scheme, same refined grid
+    ((1 << 17) + 1, (1 << 20) + 1, dict(scheme=1, order=4)),  # ~2^31 steps either way round
+])
+def test_workspace_queries_reject_pairs_beyond_the_step_limit(lxp, lyp, p):
+    lib = L.lib()
+    for bwd in (0, 1):
+        if bwd and p["scheme"] == 0:
+            continue
+        assert lib.sigkernel_gram_workspace(1, lxp, 1, lyp, 2, P(**p), bwd) == 0
+        assert _steps_error(), L.last_error()
+        xo = (ctypes.c_int64 * 2)(0, lxp)
+        yo = (ctypes.c_int64 * 2)(0, lyp)
+        assert lib.sigkernel_pairs_workspace(xo, yo, 1, 2, P(**p), bwd) == 0
+        assert _steps_error(), L.last_error()
+    if p["scheme"] != 0:
+        assert lib.sigkernel_gram_state_size(1, lxp, 1, lyp, 2, P(**p)) == 0
+        assert _steps_error(), L.last_error()
+
+
+def test_backward_checks_the_refined_length_of_the_hybrid_scheme():
+    # 70000 points refined 2^8 times exceed 2^24 segments; the backward used
+    # to check the unrefined length only
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    rc = lib.sigkernel_backward(L.SK_OP_GRAM, vp(1), None, 1, 70000, vp(1), None, 1, 70000, 2,
+                                P(scheme=1, order=4, dyadic=8), vp(1), None, vp(1), vp(1), vp(1),
+                                1 << 30, None)
+    assert rc == L.SK_EUNSUPPORTED and "2^24" in L.last_error()
+    assert lib.sigkernel_gram_state_size(1, 70000, 1, 70000, 2, P(scheme=1, order=4, dyadic=8)) == 0
+
+
+def test_long_pairs_within_the_step_limit_are_sized():
+    lib = L.lib()
+    # one 16385-point pair: 256 strips, about 4.2e6 steps
+    assert lib.sigkernel_gram_workspace(1, 16385, 1, 16385, 8, P(scheme=1, order=8), 1) > 0
+    xo = (ctypes.c_int64 * 3)(0, 16385, 16387)
+    yo = (ctypes.c_int64 * 3)(0, 16385, 16386)
+    assert lib.sigkernel_pairs_workspace(xo, yo, 2, 8, P(scheme=2, order=6), 0) > 0
+
+
+def test_status_and_spin_limit_argument_errors():
+    lib = L.lib()
+    assert lib.sigkernel_status(None, 0, None) == L.SK_EINVAL
+    assert lib.sigkernel_set_spin_limit(-1) == L.SK_EINVAL
+    assert lib.sigkernel_set_spin_limit(0) == L.SK_OK
