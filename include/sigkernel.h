@@ -174,6 +174,27 @@ int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int
                    void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * sigkernel_gram for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and outputs, with no workspace argument.  The
+ * library's own static per-device scratch of SK_STATIC_SCRATCH_BYTES serves
+ * as workspace (allocated when the library's code is loaded on a device and
+ * held by that device until the process ends); work is chunked to it.  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library call.
+ * Batched and plain algorithms (SK_EUNSUPPORTED for SK_ALGO_PIPELINE).
+ * SK_EWORKSPACE, before any device work, when one pair needs more than the
+ * scratch (e.g. pairs of about 4000 x 4000 FP32 cells and more: use
+ * sigkernel_gram with a workspace).  Every call on a device shares that
+ * device's scratch, which keeps the last call's contents: calls that overlap
+ * on one device (other streams, other host threads) race and must be
+ * serialised by the caller.  `stream` must belong to the current device.
+ */
+#define SK_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int sigkernel_gram_static(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                          int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                          hipStream_t stream);
+
+/*
  * Independent pairs of uneven lengths: k[i] = k(x_i, y_i).
  *   Xcat: all x paths concatenated, shape (x_off[npairs], d); path x_i is
  *   rows [x_off[i], x_off[i+1]).  Likewise Ycat, y_off.  x_off and y_off are

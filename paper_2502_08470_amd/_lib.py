@@ -20,6 +20,7 @@ SK_GRAM_NATIVE, SK_GRAM_BF16X3, SK_GRAM_MFMA = 0, 1, 2
 SK_SYMMETRIC = 1
 SK_STATUS_TAIL_CAP, SK_STATUS_WAIT_ABORT = 1, 2
 SK_TAIL_TABLE = 20
+SK_STATIC_SCRATCH_BYTES = 256 << 20
 
 EXPORTS = (
     "sigkernel_gram_workspace",
@@ -50,6 +51,7 @@ EXPORTS = (
     "sigkernel_status",
     "sigkernel_set_spin_limit",
     "sigkernel_interp_table",
+    "sigkernel_gram_static",
 )
 
 
@@ -86,6 +88,8 @@ def lib():
     L.sigkernel_pairs_workspace.restype = sz
     L.sigkernel_gram.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp, sz, vp]
     L.sigkernel_gram.restype = ctypes.c_int
+    L.sigkernel_gram_static.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, vp, vp, vp]
+    L.sigkernel_gram_static.restype = ctypes.c_int
     L.sigkernel_pairs.argtypes = [vp, i64p, vp, i64p, i64, i64, pp, vp, vp, vp, sz, vp]
     L.sigkernel_pairs.restype = ctypes.c_int
     L.sigkernel_backward.argtypes = [i32, vp, i64p, i64, i64, vp, i64p, i64, i64, i64, pp,

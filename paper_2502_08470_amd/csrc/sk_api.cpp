@@ -15,6 +15,12 @@
 #include "../../include/sigkernel.h"
 #include "sk_launch.h"
 
+// Static per-device scratch of sigkernel_gram_static (the workspace of
+// callers that cannot allocate).  Host code never uses this name as an
+// address: it reads the array's device address once per device with
+// hipGetSymbolAddress (scratch_of_current_device) and passes that on.
+static __device__ __align__(256) unsigned char scratch[SK_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -1697,6 +1703,27 @@ int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npai
     return plan_build(P, cfg, wsb);
 }
 
+// Device address of `scratch` on the current device, looked up on the first
+// call on each device and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    SK_TRY_HIP(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SK_EUNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        SK_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static scratch address");
+        if (!ptr) return fail(SK_EHIP, "static scratch address is NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SK_OK;
+}
+
 }  // namespace
 
 struct sk_plan {
@@ -1872,6 +1899,39 @@ int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int
                                        *p, (float*)K, K_exp, ws, ws_bytes, stream);
         return gram_forward<double>((const double*)X, nx, lx_pts, (const double*)Y, ny, ly_pts, d,
                                     *p, (double*)K, K_exp, ws, ws_bytes, stream);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_gram_static(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                          int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
+                          hipStream_t stream) {
+    g_last_error.clear();
+    int rc = check_params(p, false);
+    if (!rc) rc = check_dims(d, false);
+    if (rc) return rc;
+    if (p->algo == SK_ALGO_PIPELINE)
+        return fail(SK_EUNSUPPORTED, "the static-scratch Gram runs the batched and plain algorithms");
+    if (nx < 0 || ny < 0) return fail(SK_EINVAL, "negative batch");
+    if ((rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p)))) return rc;
+    if (nx * ny == 0) return SK_OK;
+    if (!X || !Y || !K) return fail(SK_EINVAL, "NULL pointer");
+    // one pair must fit in the scratch (work is chunked to it)
+    const size_t one = sigkernel_gram_workspace(1, lx_pts, 1, ly_pts, d, p, 0);
+    if (one == 0) return SK_EINVAL;
+    if (one > SK_STATIC_SCRATCH_BYTES)
+        return fail(SK_EWORKSPACE,
+                    "one pair needs %zu bytes of workspace, more than the %zu-byte static scratch "
+                    "(use sigkernel_gram with a workspace)", one, (size_t)SK_STATIC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((rc = scratch_of_current_device(&ws))) return rc;
+    try {
+        if (p->dtype == SK_F32)
+            return gram_forward<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts, d,
+                                       *p, (float*)K, K_exp, ws, SK_STATIC_SCRATCH_BYTES, stream);
+        return gram_forward<double>((const double*)X, nx, lx_pts, (const double*)Y, ny, ly_pts, d,
+                                    *p, (double*)K, K_exp, ws, SK_STATIC_SCRATCH_BYTES, stream);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
     }
