@@ -121,6 +121,21 @@ extern "C" {
 #define SK_SYMMETRIC 1 /* backward of a Gram call whose Y is the same array as X:
                           dL/dX sums both contributions and is written to gX
                           (gY is not used and may be NULL)                       */
+#define SK_SWEEP_F64 2 /* SK_F32 paths swept in FP64: the points (and a backward's
+                          seeds) are promoted to FP64 in the head of the
+                          workspace, the cell constants and the sweep run on
+                          the FP64 path, and the outputs are rounded to FP32.
+                          For conditioning-limited workloads whose FP32 state
+                          cannot reach the target accuracy (large |c|, long
+                          paths): on this GPU an FP64 FMA issues at the rate
+                          of an FP32 one, so the FP64 state costs about 1.5x
+                          the FP32 sweep (registers, bytes), less than any
+                          compensated FP32 state.  sigkernel_gram,
+                          sigkernel_pairs, sigkernel_backward and their
+                          workspace queries (which include the FP64 copies);
+                          not with SK_GRAM_BF16X3 (the constants are FP64),
+                          plans, the saved-state calls or the static-scratch
+                          Gram (SK_EUNSUPPORTED)                               */
 
 /* backward operations */
 #define SK_OP_GRAM 0
@@ -139,7 +154,7 @@ typedef struct sk_params {
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
     int32_t algo;   /* SK_ALGO_BATCHED, SK_ALGO_PLAIN or SK_ALGO_PIPELINE            */
     int32_t gram;   /* SK_GRAM_NATIVE, SK_GRAM_BF16X3 or SK_GRAM_MFMA (batched algorithm) */
-    int32_t flags;  /* 0 or SK_SYMMETRIC                                              */
+    int32_t flags;  /* 0, SK_SYMMETRIC and/or SK_SWEEP_F64                            */
     int32_t dyadic; /* polynomial schemes: lambda in [0, SK_MAX_DYADIC_ORDER] runs the
                        scheme on the lambda-order dyadic refinement of the grid (the
                        hybrid method of the remark after Theorem "prop:globalte");

@@ -13,6 +13,11 @@ import numpy as np
 from . import build as _build
 
 FD, APPROX, INTERP, FD2 = 0, 1, 2, 3
+# the approximation scheme evaluated with FP32-rounded increments, constants
+# and edge coefficients of degree >= 2 (FP64 arithmetic): a pair's
+# conditioning floor for evaluation with that FP32 state, used to tell
+# FP32-resolvable pairs apart (not a scheme)
+APPROX_F32MODEL = 4
 _lib = None
 
 

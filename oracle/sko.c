@@ -11,6 +11,11 @@
  *                  (Section 3.2) with the explicit truncated map of the remark
  *                  after it (Proposition "approxsolution" truncated at N); the
  *                  factorial factors are precomputed as that section suggests.
+ *   - sko_approx_f32model: the approximation scheme with increments, cell
+ *                  constants and the edge coefficients of degree >= 2
+ *                  rounded to FP32 (FP64 arithmetic), a diagnostic: its
+ *                  distance from sko_approx is a pair's conditioning floor
+ *                  for evaluation with that FP32 state.
  *   - sko_interp:  Definition "Polynomial interpolation numerical scheme"
  *                  (Section 3.3): Proposition "propinterp" (eq. interpformula)
  *                  evaluated at the N+1 Chebyshev extrema (eq. chebextr),
@@ -109,8 +114,15 @@ int sko_fd2(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, in
 /* ------------------------------------------------------------------------ */
 /* Polynomial approximation scheme                                           */
 /* ------------------------------------------------------------------------ */
-int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
-               int N, double* mant, int64_t* expo) {
+/* f32model != 0: the same scheme with the increments, the cell constants
+   and, after every cell, the edge coefficients of degree 2 and above rounded
+   to FP32 (arithmetic in FP64; degrees 0 and 1, the corner value and the
+   slope, stay FP64).  Its distance from the FP64 scheme estimates how far an
+   evaluation with that FP32 state can be trusted on a pair: the pair's
+   conditioning floor (a diagnostic for FP32 parity tests, not part of the
+   scheme). */
+static int approx_impl(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
+                       int64_t d, int N, int f32model, double* mant, int64_t* expo) {
     if (nx_pts < 1 || ny_pts < 1 || d < 1 || N < 2 || N > SKO_NMAX) return -1;
     int64_t lx = nx_pts - 1, ly = ny_pts - 1;
     *expo = 0;
@@ -131,6 +143,10 @@ int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
     double* q = st + lx * M;
     increments(x, nx_pts, d, dx);
     increments(y, ny_pts, d, dy);
+    if (f32model) {
+        for (int64_t k = 0; k < lx * d; ++k) dx[k] = (double)(float)dx[k];
+        for (int64_t k = 0; k < ly * d; ++k) dy[k] = (double)(float)dy[k];
+    }
     for (int64_t i = 0; i < lx; ++i) {
         for (int n = 0; n < M; ++n) st[i * M + n] = 0.0;
         st[i * M] = 1.0;
@@ -143,6 +159,7 @@ int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
         for (int64_t i = 0; i < lx; ++i) {
             double* p = st + i * M;
             double c = dot(dx + i * d, dy + j * d, d);
+            if (f32model) c = (double)(float)c;
             cp[0] = 1.0;
             for (int n = 1; n <= N; ++n) cp[n] = cp[n - 1] * c;
             for (int n = 0; n <= N; ++n) {
@@ -155,8 +172,8 @@ int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
                     a += q[k] * cp[n] * B[n][k];
                     b += p[k] * cp[n] * B[n][k];
                 }
-                pt[n] = a;
-                qt[n] = b;
+                pt[n] = (f32model && n >= 2) ? (double)(float)a : a;
+                qt[n] = (f32model && n >= 2) ? (double)(float)b : b;
             }
             memcpy(p, pt, sizeof(double) * M);
             memcpy(q, qt, sizeof(double) * M);
@@ -169,6 +186,16 @@ int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
     *expo = E;
     free(dx); free(dy); free(st);
     return 0;
+}
+
+int sko_approx(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts, int64_t d,
+               int N, double* mant, int64_t* expo) {
+    return approx_impl(x, nx_pts, y, ny_pts, d, N, 0, mant, expo);
+}
+
+int sko_approx_f32model(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
+                        int64_t d, int N, double* mant, int64_t* expo) {
+    return approx_impl(x, nx_pts, y, ny_pts, d, N, 1, mant, expo);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -286,7 +313,7 @@ int sko_interp(const double* x, int64_t nx_pts, const double* y, int64_t ny_pts,
 /* ------------------------------------------------------------------------ */
 /* Batches (OpenMP over pairs)                                               */
 /* ------------------------------------------------------------------------ */
-enum { SKO_FD = 0, SKO_APPROX = 1, SKO_INTERP = 2, SKO_FD2 = 3 };
+enum { SKO_FD = 0, SKO_APPROX = 1, SKO_INTERP = 2, SKO_FD2 = 3, SKO_APPROX_F32MODEL = 4 };
 
 static int run_one(int scheme, int order, const double* x, int64_t nx, const double* y,
                    int64_t ny, int64_t d, double* mant, int64_t* expo) {
@@ -295,6 +322,7 @@ static int run_one(int scheme, int order, const double* x, int64_t nx, const dou
         case SKO_APPROX: return sko_approx(x, nx, y, ny, d, order, mant, expo);
         case SKO_INTERP: return sko_interp(x, nx, y, ny, d, order, mant, expo);
         case SKO_FD2: return sko_fd2(x, nx, y, ny, d, order, mant, expo);
+        case SKO_APPROX_F32MODEL: return sko_approx_f32model(x, nx, y, ny, d, order, mant, expo);
         default: return -1;
     }
 }

@@ -18,6 +18,7 @@ SK_ALGO_BATCHED, SK_ALGO_PLAIN, SK_ALGO_PIPELINE = 0, 1, 2
 SK_OP_GRAM, SK_OP_PAIRS = 0, 1
 SK_GRAM_NATIVE, SK_GRAM_BF16X3, SK_GRAM_MFMA = 0, 1, 2
 SK_SYMMETRIC = 1
+SK_SWEEP_F64 = 2
 SK_STATUS_TAIL_CAP, SK_STATUS_WAIT_ABORT = 1, 2
 SK_TAIL_TABLE = 20
 SK_STATIC_SCRATCH_BYTES = 256 << 20

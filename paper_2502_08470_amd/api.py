@@ -20,7 +20,7 @@ _GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3, "mfma": L.SK_G
 
 
 def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: str = "native",
-            flags: int = 0, dyadic: int = 0) -> L.SkParams:
+            flags: int = 0, dyadic: int = 0, sweep: str = "native") -> L.SkParams:
     if dtype == torch.float32:
         dt = L.SK_F32
     elif dtype == torch.float64:
@@ -33,6 +33,10 @@ def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: s
         raise ValueError(f"algo must be one of {sorted(_ALGOS)}")
     if gram_mode not in _GRAMS:
         raise ValueError(f"gram_mode must be one of {sorted(_GRAMS)}")
+    if sweep not in ("native", "f64"):
+        raise ValueError('sweep must be "native" or "f64"')
+    if sweep == "f64":
+        flags |= L.SK_SWEEP_F64
     return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo], _GRAMS[gram_mode], int(flags),
                       int(dyadic))
 
@@ -76,7 +80,7 @@ def device_status(device=None, clear: bool = True) -> int:
 # ---------------------------------------------------------------------------
 def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
          algo: str = "batched", return_exp: bool = False, gram_mode: str = "native",
-         dyadic: int = 0):
+         dyadic: int = 0, sweep: str = "native"):
     """K[a, b] = k(X[a], Y[b]) for paths X (nx, lx_pts, d), Y (ny, ly_pts, d).
 
     With ``return_exp`` returns (mantissa, exponent) with value
@@ -85,11 +89,12 @@ def gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 
     always by MFMA in the path dtype; "native" (default) uses a d-term FMA
     chain per cell for d <= 16 and MFMA otherwise.
     ``dyadic`` > 0 runs a polynomial scheme on the dyadically refined grid
-    (hybrid method)."""
+    (hybrid method).  ``sweep`` "f64" sweeps float32 paths in FP64 (cell
+    constants and state; outputs rounded to float32)."""
     X, Y = _dev(X), _dev(Y)
     if X.dim() != 3 or Y.dim() != 3 or X.shape[2] != Y.shape[2] or X.dtype != Y.dtype:
         raise ValueError("X and Y must be (n, points, d) with the same d and dtype")
-    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic, sweep=sweep)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     lib = L.lib()
@@ -117,16 +122,17 @@ def _concat(paths: Union[Sequence[torch.Tensor], Tuple[torch.Tensor, Sequence[in
 
 
 def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
-          return_exp: bool = False, gram_mode: str = "native", dyadic: int = 0):
+          return_exp: bool = False, gram_mode: str = "native", dyadic: int = 0,
+          sweep: str = "native"):
     """k[i] = k(xs[i], ys[i]) for lists of (points_i, d) tensors of uneven
-    lengths, or (concatenated points, offsets) tuples."""
+    lengths, or (concatenated points, offsets) tuples (``sweep`` as in gram)."""
     Xc, xo = _concat(xs)
     Yc, yo = _concat(ys)
     if len(xo) != len(yo):
         raise ValueError("xs and ys must hold the same number of paths")
     npairs = len(xo) - 1
     d = Xc.shape[1]
-    p = _params(Xc.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
+    p = _params(Xc.dtype, scheme, order, algo, gram_mode, dyadic=dyadic, sweep=sweep)
     lib = L.lib()
     k = torch.empty(npairs, dtype=Xc.dtype, device=Xc.device)
     ke = torch.empty(npairs, dtype=torch.int32, device=Xc.device) if return_exp else None
@@ -146,9 +152,9 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
 def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
                   order: int = 4, gK_exp: Optional[torch.Tensor] = None,
                   gram_mode: str = "native", symmetric: bool = False, algo: str = "batched",
-                  dyadic: int = 0):
+                  dyadic: int = 0, sweep: str = "native"):
     """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order,
-    dyadic=dyadic).
+    dyadic=dyadic, sweep=sweep).
     ``symmetric`` (Y is X): returns (dL/dX with both contributions, None).
     ``algo`` "pipeline" runs pairs of several strips on the pipelined
     checkpoint sweep and adjoint (for few, long paths; the call synchronises
@@ -160,7 +166,7 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
         raise ValueError("gram_backward runs the batched algorithm or the strip pipeline")
     gK = _dev(gK.to(X.dtype))
     p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0,
-                dyadic=dyadic)
+                dyadic=dyadic, sweep=sweep)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     if gK.shape != (nx, ny):
@@ -181,7 +187,7 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
 
 def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int = 4,
                    gk_exp: Optional[torch.Tensor] = None, algo: str = "batched",
-                   dyadic: int = 0):
+                   dyadic: int = 0, sweep: str = "native"):
     """Gradients of sum(gk * pairs(xs, ys)) with respect to the concatenated
     points; returns (gXcat, gYcat, x_offsets, y_offsets).  ``algo`` "batched"
     uses the tuned (or default) plan configuration of this shape; "pipeline"
@@ -193,7 +199,7 @@ def pairs_backward(xs, ys, gk: torch.Tensor, scheme: str = "approx", order: int 
     d = Xc.shape[1]
     if algo not in ("batched", "pipeline"):
         raise ValueError("pairs_backward runs the batched algorithm or the strip pipeline")
-    p = _params(Xc.dtype, scheme, order, algo, dyadic=dyadic)
+    p = _params(Xc.dtype, scheme, order, algo, dyadic=dyadic, sweep=sweep)
     lib = L.lib()
     gk = _dev(gk.to(Xc.dtype))
     gX = torch.empty_like(Xc)
@@ -425,13 +431,18 @@ class SigKernelGram(torch.autograd.Function):
     algorithm or the strip pipeline for both."""
 
     @staticmethod
-    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None, dyadic=0):
+    def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None, dyadic=0,
+                sweep="native"):
         ctx.save_for_backward(X, Y)
         ctx.scheme, ctx.order, ctx.gram_mode, ctx.dyadic = scheme, order, gram_mode, dyadic
+        ctx.sweep = sweep
         ctx.algo = algo or gram_algo(X, Y, scheme)
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
         ctx.state = None
+        if sweep == "f64":  # no saved state in this mode: the backward recomputes
+            return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode, dyadic=dyadic,
+                        sweep=sweep)
         if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
             size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo, dyadic)
             if size <= _state_budget(X.device):
@@ -449,15 +460,16 @@ class SigKernelGram(torch.autograd.Function):
             gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
-            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, **kw)
-        return gX, gY, None, None, None, None, None
+            gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, sweep=ctx.sweep, **kw)
+        return gX, gY, None, None, None, None, None, None
 
 
 def sig_gram(X, Y, scheme: str = "approx", order: int = 4, gram_mode: str = "native",
-             algo: Optional[str] = None, dyadic: int = 0) -> torch.Tensor:
+             algo: Optional[str] = None, dyadic: int = 0, sweep: str = "native") -> torch.Tensor:
     """Differentiable Gram matrix (SigKernelGram); ``dyadic`` > 0 runs the
-    hybrid scheme on the dyadically refined grid."""
-    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo, dyadic)
+    hybrid scheme on the dyadically refined grid; ``sweep`` "f64" sweeps
+    float32 paths in FP64."""
+    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo, dyadic, sweep)
 
 
 class SigKernelPairs(torch.autograd.Function):
@@ -467,13 +479,19 @@ class SigKernelPairs(torch.autograd.Function):
     kept state), otherwise a plain forward and a recomputing backward."""
 
     @staticmethod
-    def forward(ctx, A, B, scheme="approx", order=4, pipeline=False, dyadic=0):
+    def forward(ctx, A, B, scheme="approx", order=4, pipeline=False, dyadic=0, sweep="native"):
         P, La, d = A.shape
         Lb = B.shape[1]
         Ac = A.reshape(P * La, d).contiguous()
         Bc = B.reshape(P * Lb, d).contiguous()
         xo = (Ac, [i * La for i in range(P + 1)])
         yo = (Bc, [i * Lb for i in range(P + 1)])
+        ctx.shapes, ctx.sweep = (A.shape, B.shape), sweep
+        if sweep == "f64":  # one-shot calls (plans do not offer the FP64 sweep)
+            ctx.plan, ctx.args = None, (xo[1], yo[1], scheme, order, dyadic,
+                                        "pipeline" if pipeline else "batched")
+            ctx.save_for_backward(Ac, Bc)
+            return pairs(xo, yo, scheme, order, algo=ctx.args[5], dyadic=dyadic, sweep=sweep)
         plan = PairsPlan(xo, yo, scheme, order, backward=True, dyadic=dyadic)
         plan.configure(True, True, True, pipeline)
         k = torch.empty(P, dtype=A.dtype, device=A.device)
@@ -485,51 +503,59 @@ class SigKernelPairs(torch.autograd.Function):
                 raise
             plan.forward(Ac, Bc, k)
             ctx.saved = False
-        ctx.plan, ctx.shapes = plan, (A.shape, B.shape)
+        ctx.plan = plan
         ctx.save_for_backward(Ac, Bc)
         return k
 
     @staticmethod
     def backward(ctx, gk):
         Ac, Bc = ctx.saved_tensors
-        gA, gB = torch.empty_like(Ac), torch.empty_like(Bc)
         gk = gk.contiguous().to(Ac.dtype)
+        sa, sb = ctx.shapes
+        if ctx.sweep == "f64":
+            xo, yo, scheme, order, dyadic, algo = ctx.args
+            gA, gB, _, _ = pairs_backward((Ac, xo), (Bc, yo), gk, scheme, order, algo=algo,
+                                          dyadic=dyadic, sweep="f64")
+            return gA.reshape(sa), gB.reshape(sb), None, None, None, None, None
+        gA, gB = torch.empty_like(Ac), torch.empty_like(Bc)
         if ctx.saved:
             ctx.plan.backward_saved(Ac, Bc, gk, gA, gB)
         else:
             ctx.plan.backward(Ac, Bc, gk, gA, gB)
         ctx.plan = None
-        sa, sb = ctx.shapes
-        return gA.reshape(sa), gB.reshape(sb), None, None, None, None
+        return gA.reshape(sa), gB.reshape(sb), None, None, None, None, None
 
 
 def sig_pairs(A, B, scheme: str = "approx", order: int = 4, pipeline: bool = False,
-              dyadic: int = 0):
-    """Differentiable k(A[i], B[i]) (SigKernelPairs); ``dyadic`` as for sig_gram."""
-    return SigKernelPairs.apply(A, B, scheme, order, pipeline, dyadic)
+              dyadic: int = 0, sweep: str = "native"):
+    """Differentiable k(A[i], B[i]) (SigKernelPairs); ``dyadic`` and ``sweep``
+    as for sig_gram."""
+    return SigKernelPairs.apply(A, B, scheme, order, pipeline, dyadic, sweep)
 
 
 def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
-         gram_mode: str = "native") -> torch.Tensor:
+         gram_mode: str = "native", sweep: str = "native") -> torch.Tensor:
     """Unbiased (U-statistic) squared MMD between path sets X and Y, with the
     within-sample diagonals excluded; differentiable in X and Y.  Native Gram
     arithmetic with equal path lengths: the pairs a < b of each set and all
     cross pairs, in one pair list (k is symmetric, and the diagonal pairs do
-    not enter), otherwise three Gram matrices."""
+    not enter), otherwise three Gram matrices.  ``sweep`` "f64" sweeps
+    float32 paths in FP64 (the statistic is a difference of nearly equal
+    means, so its gradient loses digits the FP32 state cannot spare)."""
     n, m = X.shape[0], Y.shape[0]
     if gram_mode == "native" and X.shape[1] == Y.shape[1] and scheme not in ("fd", "fd2"):
         ia, ib = torch.triu_indices(n, n, 1, device=X.device)
         ja, jb = torch.triu_indices(m, m, 1, device=Y.device)
         A = torch.cat([X[ia], Y[ja], X.repeat_interleave(m, 0)], 0)
         B = torch.cat([X[ib], Y[jb], Y.repeat(n, 1, 1)], 0)
-        k = sig_pairs(A, B, scheme, order)
+        k = sig_pairs(A, B, scheme, order, sweep=sweep)
         nxx, nyy = ia.numel(), ja.numel()
         sxx = 2.0 * k[:nxx].sum() / (n * (n - 1))
         syy = 2.0 * k[nxx:nxx + nyy].sum() / (m * (m - 1))
         return sxx + syy - 2.0 * k[nxx + nyy:].mean()
-    Kxx = sig_gram(X, X, scheme, order, gram_mode)
-    Kyy = sig_gram(Y, Y, scheme, order, gram_mode)
-    Kxy = sig_gram(X, Y, scheme, order, gram_mode)
+    Kxx = sig_gram(X, X, scheme, order, gram_mode, sweep=sweep)
+    Kyy = sig_gram(Y, Y, scheme, order, gram_mode, sweep=sweep)
+    Kxy = sig_gram(X, Y, scheme, order, gram_mode, sweep=sweep)
     sxx = (Kxx.sum() - torch.diagonal(Kxx).sum()) / (n * (n - 1))
     syy = (Kyy.sum() - torch.diagonal(Kyy).sum()) / (m * (m - 1))
     return sxx + syy - 2.0 * Kxy.mean()

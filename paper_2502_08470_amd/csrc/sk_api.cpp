@@ -239,7 +239,12 @@ int check_params(const sk_params* p, bool backward) {
         return fail(SK_EUNSUPPORTED, "the bf16 split Gram is for SK_F32 paths");
     if (p->gram == SK_GRAM_BF16X3 && p->algo == SK_ALGO_PLAIN)
         return fail(SK_EUNSUPPORTED, "the bf16 split Gram is not a plain-algorithm mode");
-    if (p->flags & ~SK_SYMMETRIC) return fail(SK_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(SK_SYMMETRIC | SK_SWEEP_F64)) return fail(SK_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & SK_SWEEP_F64) {
+        if (p->dtype != SK_F32) return fail(SK_EINVAL, "SK_SWEEP_F64 applies to SK_F32 paths");
+        if (p->gram == SK_GRAM_BF16X3)
+            return fail(SK_EUNSUPPORTED, "SK_SWEEP_F64 computes the cell constants in FP64 (no bf16 split)");
+    }
     return SK_OK;
 }
 
@@ -1703,6 +1708,39 @@ int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npai
     return plan_build(P, cfg, wsb);
 }
 
+// ---------------------------------------------------------------------------
+// SK_SWEEP_F64: FP32 paths swept in FP64.  The points (and a backward's
+// seeds) are promoted into the head of the workspace, the call runs on the
+// FP64 path (cell constants of the promoted points in FP64, FP64 state),
+// and its outputs are rounded back to FP32.
+// ---------------------------------------------------------------------------
+sk_params promoted(const sk_params& p) {
+    sk_params q = p;
+    q.dtype = SK_F64;
+    q.flags &= ~SK_SWEEP_F64;
+    return q;
+}
+// Head of the workspace: byte offsets of the FP64 copies.
+struct PromoHead {
+    int64_t x, y, k, gx, gy, total;
+};
+PromoHead promo_head(int64_t xn, int64_t yn, int64_t kn, bool backward, bool symmetric) {
+    PromoHead h;
+    int64_t o = 0;
+    auto take = [&](int64_t n) { const int64_t at = o; o += align_up(n * 8); return at; };
+    h.x = take(xn);
+    h.y = symmetric ? h.x : take(yn);
+    h.k = take(kn);  // K (forward) or gK (backward)
+    h.gx = backward ? take(xn) : 0;
+    h.gy = backward && !symmetric ? take(yn) : 0;
+    h.total = o;
+    return h;
+}
+int no_sweep_f64(const sk_params* p, const char* what) {
+    if (p && (p->flags & SK_SWEEP_F64)) return fail(SK_EUNSUPPORTED, "SK_SWEEP_F64 is not offered by %s", what);
+    return SK_OK;
+}
+
 // Device address of `scratch` on the current device, looked up on the first
 // call on each device and kept.
 constexpr int kMaxDevices = 64;
@@ -1833,6 +1871,13 @@ size_t sigkernel_gram_workspace(int64_t nx, int64_t lx_pts, int64_t ny, int64_t 
         check_gram_geom(lx_pts, ly_pts, lam_of(*p)))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
+    if (p->flags & SK_SWEEP_F64) {
+        const sk_params q = promoted(*p);
+        const size_t inner = sigkernel_gram_workspace(nx, lx_pts, ny, ly_pts, d, &q, backward);
+        if (!inner) return 0;
+        const bool sym = (p->flags & SK_SYMMETRIC) != 0;
+        return (size_t)promo_head(nx * lx_pts * d, ny * ly_pts * d, nx * ny, backward != 0, sym).total + inner;
+    }
     const int lam = lam_of(*p);
     // the pipeline where the (refined) grid has several strips, else batched
     if (p->algo == SK_ALGO_PIPELINE && nx * ny > 0 &&
@@ -1862,6 +1907,12 @@ size_t sigkernel_pairs_workspace(const int64_t* x_off, const int64_t* y_off, int
     if (npairs < 0) { fail(SK_EINVAL, "negative npairs"); return 0; }
     if (check_pairs_geom(x_off, y_off, npairs, lam_of(*p)))
         return 0;
+    if (p->flags & SK_SWEEP_F64) {
+        const sk_params q = promoted(*p);
+        const size_t inner = sigkernel_pairs_workspace(x_off, y_off, npairs, d, &q, backward);
+        if (!inner) return 0;
+        return (size_t)promo_head(x_off[npairs] * d, y_off[npairs] * d, npairs, backward != 0, false).total + inner;
+    }
     const int lam = lam_of(*p);
     if (p->algo == SK_ALGO_PLAIN) {
         int64_t need = 256;
@@ -1893,6 +1944,20 @@ int sigkernel_gram(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int
         return rc;
     if (nx * ny == 0) return SK_OK;
     if (!X || !Y || !K || !ws) return fail(SK_EINVAL, "NULL pointer");
+    if (p->flags & SK_SWEEP_F64) {
+        const PromoHead h = promo_head(nx * lx_pts * d, ny * ly_pts * d, nx * ny, false, false);
+        if (ws_bytes < (size_t)h.total) return fail(SK_EWORKSPACE, "workspace smaller than the FP64 copies");
+        char* w = (char*)ws;
+        double *X64 = (double*)(w + h.x), *Y64 = (double*)(w + h.y), *K64 = (double*)(w + h.k);
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)X, X64, nx * lx_pts * d, stream), "promote X");
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)Y, Y64, ny * ly_pts * d, stream), "promote Y");
+        const sk_params q = promoted(*p);
+        if ((rc = sigkernel_gram(X64, nx, lx_pts, Y64, ny, ly_pts, d, &q, K64, K_exp, w + h.total,
+                                 ws_bytes - h.total, stream)))
+            return rc;
+        SK_TRY_HIP(SkLaunch<float>::from_f64(K64, (float*)K, nx * ny, stream), "round K");
+        return SK_OK;
+    }
     try {
         if (p->dtype == SK_F32)
             return gram_forward<float>((const float*)X, nx, lx_pts, (const float*)Y, ny, ly_pts, d,
@@ -1908,6 +1973,7 @@ int sigkernel_gram_static(const void* X, int64_t nx, int64_t lx_pts, const void*
                           int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
                           hipStream_t stream) {
     g_last_error.clear();
+    if (no_sweep_f64(p, "the static-scratch Gram")) return SK_EUNSUPPORTED;
     int rc = check_params(p, false);
     if (!rc) rc = check_dims(d, false);
     if (rc) return rc;
@@ -1949,6 +2015,21 @@ int sigkernel_pairs(const void* Xcat, const int64_t* x_off, const void* Ycat, co
     if ((rc = check_pairs_geom(x_off, y_off, npairs, lam_of(*p))))
         return rc;
     if (!Xcat || !Ycat || !k || !ws) return fail(SK_EINVAL, "NULL pointer");
+    if (p->flags & SK_SWEEP_F64) {
+        const int64_t xn = x_off[npairs] * d, yn = y_off[npairs] * d;
+        const PromoHead h = promo_head(xn, yn, npairs, false, false);
+        if (ws_bytes < (size_t)h.total) return fail(SK_EWORKSPACE, "workspace smaller than the FP64 copies");
+        char* w = (char*)ws;
+        double *X64 = (double*)(w + h.x), *Y64 = (double*)(w + h.y), *k64 = (double*)(w + h.k);
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)Xcat, X64, xn, stream), "promote X");
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)Ycat, Y64, yn, stream), "promote Y");
+        const sk_params q = promoted(*p);
+        if ((rc = sigkernel_pairs(X64, x_off, Y64, y_off, npairs, d, &q, k64, k_exp, w + h.total,
+                                  ws_bytes - h.total, stream)))
+            return rc;
+        SK_TRY_HIP(SkLaunch<float>::from_f64(k64, (float*)k, npairs, stream), "round k");
+        return SK_OK;
+    }
     try {
         if (p->algo == SK_ALGO_PLAIN) {
             if (p->dtype == SK_F32)
@@ -1990,6 +2071,27 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
     }
     if ((rc = check_symmetric(*p, op, X, nx, lx_pts, Y, ny, ly_pts, gX, &gY))) return rc;
     if (!X || !Y || !gK || !gX || !gY || !ws) return fail(SK_EINVAL, "NULL pointer");
+    if (p->flags & SK_SWEEP_F64) {
+        const bool sym = (p->flags & SK_SYMMETRIC) != 0;
+        const int64_t xn = (op == SK_OP_GRAM ? nx * lx_pts : x_off[nx]) * d;
+        const int64_t yn = (op == SK_OP_GRAM ? ny * ly_pts : y_off[nx]) * d;
+        const int64_t kn = op == SK_OP_GRAM ? nx * ny : nx;
+        const PromoHead h = promo_head(xn, yn, kn, true, sym);
+        if (ws_bytes < (size_t)h.total) return fail(SK_EWORKSPACE, "workspace smaller than the FP64 copies");
+        char* w = (char*)ws;
+        double *X64 = (double*)(w + h.x), *Y64 = (double*)(w + h.y), *gK64 = (double*)(w + h.k);
+        double *gX64 = (double*)(w + h.gx), *gY64 = sym ? gX64 : (double*)(w + h.gy);
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)X, X64, xn, stream), "promote X");
+        if (!sym) SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)Y, Y64, yn, stream), "promote Y");
+        SK_TRY_HIP(SkLaunch<float>::to_f64((const float*)gK, gK64, kn, stream), "promote gK");
+        const sk_params q = promoted(*p);
+        if ((rc = sigkernel_backward(op, X64, x_off, nx, lx_pts, Y64, y_off, ny, ly_pts, d, &q, gK64,
+                                     gK_exp, gX64, gY64, w + h.total, ws_bytes - h.total, stream)))
+            return rc;
+        SK_TRY_HIP(SkLaunch<float>::from_f64(gX64, (float*)gX, xn, stream), "round gX");
+        if (!sym) SK_TRY_HIP(SkLaunch<float>::from_f64(gY64, (float*)gY, yn, stream), "round gY");
+        return SK_OK;
+    }
     try {
         if (op == SK_OP_GRAM && p->algo == SK_ALGO_PIPELINE) {
             if (p->dtype == SK_F32)
@@ -2028,6 +2130,7 @@ int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t np
     g_last_error.clear();
     if (!plan) return fail(SK_EINVAL, "plan is NULL");
     *plan = nullptr;
+    if (no_sweep_f64(p, "plans")) return SK_EUNSUPPORTED;
     int rc = check_params(p, backward != 0);
     if (!rc) rc = check_dims(d, backward != 0);
     if (rc) return rc;
@@ -2235,6 +2338,7 @@ int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p) {
     g_last_error.clear();
+    if (no_sweep_f64(p, "the saved-state calls")) return 0;
     if (check_params(p, true) || check_dims(d, true) || check_gram_geom(lx_pts, ly_pts, lam_of(*p)))
         return 0;
     if (nx < 0 || ny < 0) { fail(SK_EINVAL, "negative batch"); return 0; }
@@ -2254,6 +2358,7 @@ int sigkernel_gram_save(const void* X, int64_t nx, int64_t lx_pts, const void* Y
                         int64_t ly_pts, int64_t d, const sk_params* p, void* K, int32_t* K_exp,
                         void* state, size_t state_bytes, hipStream_t stream) {
     g_last_error.clear();
+    if (no_sweep_f64(p, "the saved-state calls")) return SK_EUNSUPPORTED;
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
     if (rc) return rc;
@@ -2284,6 +2389,8 @@ int sigkernel_gram_backward_saved(const void* X, int64_t nx, int64_t lx_pts, con
                                   const void* gK, const int32_t* gK_exp, void* gX, void* gY,
                                   void* state, size_t state_bytes, hipStream_t stream) {
     g_last_error.clear();
+    if (no_sweep_f64(p, "the saved-state calls")) return SK_EUNSUPPORTED;
+    if (no_sweep_f64(p, "the saved-state calls")) return SK_EUNSUPPORTED;
     int rc = check_params(p, true);
     if (!rc) rc = check_dims(d, true);
     if (rc) return rc;

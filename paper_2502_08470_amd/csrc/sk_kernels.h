@@ -21,6 +21,14 @@ __global__ void k_fill(T* p, int64_t n, T v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+// element-wise type conversion (FP32 paths swept in FP64, SK_SWEEP_F64)
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+
 // ---------------------------------------------------------------------------
 // (a) increment Gram: skewed cell constants by MFMA
 // ---------------------------------------------------------------------------

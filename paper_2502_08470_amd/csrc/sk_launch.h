@@ -19,6 +19,9 @@ template <typename R>
 struct SkLaunch {
     static hipError_t fill(R* p, int64_t n, R v, hipStream_t st);
     static hipError_t fill_u32(unsigned* p, int64_t n, hipStream_t st);
+    // dst = (double)src and dst = (R)src, n elements
+    static hipError_t to_f64(const R* src, double* dst, int64_t n, hipStream_t st);
+    static hipError_t from_f64(const double* src, R* dst, int64_t n, hipStream_t st);
     static hipError_t gram(const GramArgs<R>& a, int ntau_blocks, int64_t npairs, hipStream_t st);
     // pair-resident Gram (all row blocks of a pair in one workgroup); max_lx, max_ly
     // are unrefined segment counts

@@ -21,6 +21,24 @@ hipError_t SkLaunch<R>::fill(R* p, int64_t n, R v, hipStream_t st) {
 }
 
 template <typename R>
+hipError_t SkLaunch<R>::to_f64(const R* src, double* dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_convert<R, double>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::from_f64(const double* src, R* dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_convert<double, R>), dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
 hipError_t SkLaunch<R>::fill_u32(unsigned* p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;

@@ -62,7 +62,9 @@ def gram(p, nx=2, lxp=10, ny=2, lyp=10, d=3, X=1, Y=1, K=1, ws=1, wsb=1 << 30):
     (dict(p=None), L.SK_EINVAL),
     (dict(p=P(gram=3)), L.SK_EINVAL),
     (dict(p=P(gram=1, dtype=0)), L.SK_EUNSUPPORTED),
-    (dict(p=P(flags=2)), L.SK_EINVAL),
+    (dict(p=P(flags=4)), L.SK_EINVAL),
+    (dict(p=P(flags=L.SK_SWEEP_F64, dtype=0)), L.SK_EINVAL),       # FP32 paths only
+    (dict(p=P(flags=L.SK_SWEEP_F64, gram=1)), L.SK_EUNSUPPORTED),  # FP64 constants, no bf16 split
     (dict(p=P(dyadic=-1)), L.SK_EINVAL),
     (dict(p=P(dyadic=9)), L.SK_EUNSUPPORTED),
     (dict(p=P(scheme=0, order=1, dyadic=1)), L.SK_EINVAL),
@@ -318,3 +320,30 @@ def test_status_and_spin_limit_argument_errors():
     assert lib.sigkernel_status(None, 0, None) == L.SK_EINVAL
     assert lib.sigkernel_set_spin_limit(-1) == L.SK_EINVAL
     assert lib.sigkernel_set_spin_limit(0) == L.SK_OK
+
+
+def test_sweep_f64_is_refused_where_not_offered():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    p = P(flags=L.SK_SWEEP_F64)
+    assert lib.sigkernel_gram_static(vp(1), 1, 10, vp(1), 1, 10, 3, p, vp(1), None, None) == \
+        L.SK_EUNSUPPORTED
+    assert lib.sigkernel_gram_state_size(1, 10, 1, 10, 3, p) == 0
+    xo = (ctypes.c_int64 * 2)(0, 10)
+    plan = ctypes.c_void_p()
+    assert lib.sigkernel_plan_create(xo, xo, 1, 3, p, 1, 0, ctypes.byref(plan)) == L.SK_EUNSUPPORTED
+
+
+def test_sweep_f64_workspace_adds_the_fp64_copies():
+    lib = L.lib()
+    p32 = P(scheme=1, order=8, dtype=1)
+    pf = P(scheme=1, order=8, dtype=1, flags=L.SK_SWEEP_F64)
+    p64 = P(scheme=1, order=8, dtype=0)
+    for bwd in (0, 1):
+        w64 = lib.sigkernel_gram_workspace(3, 100, 5, 70, 4, p64, bwd)
+        wf = lib.sigkernel_gram_workspace(3, 100, 5, 70, 4, pf, bwd)
+        head = (3 * 100 * 4 * 8 + 255) // 256 * 256 + (5 * 70 * 4 * 8 + 255) // 256 * 256 + 256
+        if bwd:
+            head += (3 * 100 * 4 * 8 + 255) // 256 * 256 + (5 * 70 * 4 * 8 + 255) // 256 * 256
+        assert wf == w64 + head, (bwd, wf, w64, head)
+        assert lib.sigkernel_gram_workspace(3, 100, 5, 70, 4, p32, bwd) < wf

@@ -243,3 +243,26 @@ def test_hybrid_refined_grid_scheme_pins():
     for sch in ("approx", "interp"):
         m, e = C.gram(x[None], y[None], kind[sch], 4, lam=2)
         assert C.value(m, e)[0, 0] == pytest.approx(S.hybrid_scheme(x, y, 4, 2, sch), rel=1e-12)
+
+
+def test_f32_model_is_the_scheme_to_fp32_resolution():
+    """The FP32 model (a conditioning diagnostic) is the approximation scheme
+    evaluated with FP32-rounded increments, constants and edge coefficients
+    of degree >= 2: on a well-conditioned pair it departs from the FP64
+    scheme by about the FP32 resolution -- not at all would mean nothing is
+    rounded, much more would mean a different scheme."""
+    from oracle import c_oracle as C
+    rng = np.random.default_rng(12)
+    X = np.concatenate([np.zeros((2, 1, 3)), np.cumsum(rng.normal(0, 0.15, (2, 60, 3)), 1)], 1)
+    Y = np.concatenate([np.zeros((2, 1, 3)), np.cumsum(rng.normal(0, 0.15, (2, 45, 3)), 1)], 1)
+    ref = np.ldexp(*C.gram(X, Y, C.APPROX, 6))
+    f32 = np.ldexp(*C.gram(X, Y, C.APPROX_F32MODEL, 6))
+    rel = np.abs(f32 / ref - 1)
+    assert np.all(rel > 1e-12) and np.all(rel < 1e-5), rel
+    # inputs whose increments, constants and state are exact in FP32 (one
+    # cell, c = 1/4, N = 2: 1 + c + c^2/4 in dyadic rationals) give the FP64
+    # value exactly
+    x = np.array([[0.0], [0.5]])
+    m0, e0 = C.gram(x[None], x[None], C.APPROX, 2)
+    m1, e1 = C.gram(x[None], x[None], C.APPROX_F32MODEL, 2)
+    assert np.ldexp(m0, e0)[0, 0] == np.ldexp(m1, e1)[0, 0] == 1 + 0.25 + 0.25 ** 2 / 4
