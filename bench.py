@@ -2,8 +2,10 @@
 
 One step = forward Gram + backward (adjoint) of a 128 x 128 Gram matrix of
 paths in R^8 with 256 Brownian steps (std 0.5/sqrt(256) per coordinate),
-polynomial interpolation scheme of order 6, FP32 cell sweep and FP32 MFMA
-increment Gram; loss L = sum(K), differentiated with torch.autograd through
+polynomial interpolation scheme of order 6, FP32 cell sweep and FP32
+increment Gram (an 8-term FMA chain per cell, k_gram_direct: at d = 8 the
+16x16x4 MFMA tiles are slower; `gram_mfma_ms` times them on the same
+input); loss L = sum(K), differentiated with torch.autograd through
 the library's SigKernelGram (gradients with respect to both path sets).
 Inputs are resident on the GPU before timing.  Reported:
 
@@ -21,8 +23,15 @@ Inputs are resident on the GPU before timing.  Reported:
   committed counter summary (FETCH_SIZE and WRITE_SIZE runs, scaled by the
   same counters read for a plain 1 GiB device copy), reported only when the
   kernel sources hash to the value recorded with the counters, else null.
-* plain_fp64: the plain single-pair FP64 kernel (one launch per pair,
-  forward only) on a sample of pairs of the same workload.
+* plain_fp64: the 8 x 8 FP64 Gram of R^3 paths with a time channel (64
+  steps, approximation N = 4, and the finite-difference baseline): the plain
+  single-pair kernel (one launch per pair, forward only) next to the batched
+  kernels (forward, and forward + backward), with the largest relative
+  departure from the oracle.
+* large_gram_block: 16 rows x 1024 columns of the 1024 x 1024 R^32 Gram
+  (1024 steps, approximation N = 8, kernels near 2^1200), forward + backward
+  through log K, with the FP32 sweep (bf16 3-way split Gram) and with the
+  FP32 points swept in FP64; MAPE of each on 8 sampled pairs of the block.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pmc-summary FETCH.csv WRITE.csv OUT.json   (no GPU)
@@ -56,7 +65,7 @@ CPU_BLOCK = (48, 64)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_interp_gram_128x128.json")
 CALIBRATE_MIB = 1024
 # bench kernel label -> prefix of the kernel symbol
-KERNEL_SYMBOL = {"gram": "k_gram_skew<", "sweep": "k_sweep<", "sweep_ckpt": "k_sweep<",
+KERNEL_SYMBOL = {"gram": "k_gram_direct<", "sweep": "k_sweep<", "sweep_ckpt": "k_sweep<",
                  "adjoint": "k_adjoint", "contract": "k_contract<", "reduce": "k_reduce"}
 
 
@@ -443,6 +452,91 @@ def workload_study(large_rows: int = 256) -> int:
     return 0
 
 
+def best_of(torch, fn, reps=3):
+    """Smallest wall time (ms) of `reps` synchronised calls, after one warm call."""
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, (time.perf_counter() - t0) * 1e3)
+    return best
+
+
+def plain_leg(sk, torch, dev) -> dict:
+    """The small FP64 Gram (8 x 8, R^3 + time channel, 64 steps): the plain
+    one-pair-per-launch kernel against the batched kernels, approximation
+    N = 4 and finite differences (dyadic order 0)."""
+    import workloads as W
+    from oracle import c_oracle as C
+    X, Y = W.small_fp64_gram(0)
+    Xt, Yt = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+    cells = float(X.shape[0] * Y.shape[0] * (X.shape[1] - 1) * (Y.shape[1] - 1))
+    out = {"workload": "8x8 Gram, R^3 Brownian (variance 1/64 per step) + time channel, "
+                       "64 steps, FP64", "cells": cells, "unit": "cell-updates/s"}
+    for scheme, order, cid in (("approx", 4, C.APPROX), ("fd", 0, C.FD)):
+        ref = np.ldexp(*C.gram(X, Y, cid, order))
+        row = {}
+        for algo in ("plain", "batched"):
+            ms = best_of(torch, lambda: sk.gram(Xt, Yt, scheme, order, algo=algo))
+            K = sk.gram(Xt, Yt, scheme, order, algo=algo).cpu().numpy()
+            row[algo] = {"forward": cells / (ms * 1e-3), "forward_ms": ms,
+                         "max_rel_vs_oracle": float(np.max(np.abs(K / ref - 1.0)))}
+        if scheme == "approx":
+            Xg, Yg = Xt.clone().requires_grad_(True), Yt.clone().requires_grad_(True)
+
+            def fb():
+                Xg.grad = None
+                Yg.grad = None
+                sk.sig_gram(Xg, Yg, scheme, order, algo="batched").sum().backward()
+            ms = best_of(torch, fb)
+            row["batched"]["fwd_bwd"] = cells / (ms * 1e-3)
+            row["batched"]["fwd_bwd_ms"] = ms
+        row["plain_vs_batched_forward"] = row["batched"]["forward"] / row["plain"]["forward"]
+        out[f"{scheme}_{order}"] = row
+    out["value"] = out["approx_4"]["plain"]["forward"]
+    return out
+
+
+def large_block_leg(sk, torch, dev, rows: int = 16) -> dict:
+    """`rows` x 1024 block of the 1024 x 1024 R^32 Gram (approximation N = 8),
+    forward + backward through log K (seed gK = 1/K by the exponents), FP32
+    sweep with the bf16 3-way split Gram and FP32 points swept in FP64."""
+    import workloads as W
+    from oracle import c_oracle as C
+    X, Y = W.large_gram(0)
+    Xt = torch.tensor(X[:rows], device=dev)
+    Yt = torch.tensor(Y, device=dev)
+    cells = float(rows * Y.shape[0] * (X.shape[1] - 1) * (Y.shape[1] - 1))
+    rng = np.random.default_rng(16)
+    ia = rng.choice(rows, 8)
+    ib = rng.choice(Y.shape[0], 8)
+    m, e = C.pairs([X[a].astype(np.float64) for a in ia], [Y[b].astype(np.float64) for b in ib],
+                   C.APPROX, 8)
+    out = {"workload": f"{rows} x 1024 block of the 1024x1024 Gram, R^32, 1024 steps, "
+                       "unit-variance cell constants, approximation N=8, FP32 points, "
+                       "fwd+bwd through log K", "cells": cells, "unit": "cell-updates/s"}
+    for mode, kw in (("fp32_sweep_bf16x3_gram", dict(gram_mode="bf16x3")),
+                     ("fp64_sweep", dict(sweep="f64"))):
+        res = {}
+
+        def fb():
+            K, Ke = sk.gram(Xt, Yt, "approx", 8, return_exp=True, **kw)
+            gK = 1.0 / K
+            sk.gram_backward(Xt, Yt, gK, "approx", 8, gK_exp=-Ke, **kw)
+            res["K"], res["Ke"] = K, Ke
+        ms = best_of(torch, fb, reps=2)
+        K, Ke = res["K"].cpu().numpy(), res["Ke"].cpu().numpy()
+        sh = Ke[ia, ib].astype(np.int64) - e
+        err = np.abs(np.ldexp(K[ia, ib].astype(np.float64), sh) - m) / np.abs(m)
+        out[mode] = {"fwd_bwd_ms": ms, "fwd_bwd": cells / (ms * 1e-3),
+                     "gram_entries_per_s": rows * Y.shape[0] / (ms * 1e-3),
+                     "mape_8_pairs": float(err.mean()), "max_ape_8_pairs": float(err.max())}
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -556,8 +650,10 @@ def main(argv=None) -> int:
            "data": "synthetic",
            "config": {"workload": "128x128 Gram, paths in R^8, 256 Brownian steps "
                                   "(std 0.5/16), polynomial interpolation N=6, FP32 sweep, "
-                                  "FP32 MFMA increment Gram, fwd+bwd (loss sum K)",
-                      "pairs": N_PATHS * N_PATHS, "cells_per_pair": STEPS * STEPS},
+                                  "FP32 increment Gram by an 8-term FMA chain per cell "
+                                  "(k_gram_direct), fwd+bwd (loss sum K)",
+                      "pairs": N_PATHS * N_PATHS, "cells_per_pair": STEPS * STEPS,
+                      "gram_kernel": "k_gram_direct"},
            "gram_entries_per_s": entries, "roofline": roofline}
 
     # accuracy on the 16 x 16 block (and the larger CPU sample), CPU oracle
@@ -595,21 +691,16 @@ def main(argv=None) -> int:
             "sample": f"{sx}x{sy} block X[0:{sx}] x Y[0:{sy}], one thread", "seconds": s1 - s0}
         out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count(), "model": cpu_model(),
                                        "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+    # the same Gram's constants by MFMA tiles (the label above names the
+    # kernel the step runs)
+    _lib.profile_enable(True)
+    sk.gram(Xt.detach(), Yt.detach(), SCHEME, ORDER, gram_mode="mfma")
+    torch.cuda.synchronize()
+    out["gram_mfma_ms"] = _lib.profile_read("gram")[0]
+    _lib.profile_enable(False)
     if not args.no_plain:
-        npl = 16
-        Xd = Xt.detach()[:1].double()
-        Yd = Yt.detach()[:npl].double()
-        sk.gram(Xd, Yd, SCHEME, ORDER, algo="plain")
-        torch.cuda.synchronize()
-        p0 = time.perf_counter()
-        Kp = sk.gram(Xd, Yd, SCHEME, ORDER, algo="plain")
-        torch.cuda.synchronize()
-        p1 = time.perf_counter()
-        out["plain_fp64"] = {"value": npl * STEPS * STEPS / (p1 - p0), "unit": "cell-updates/s",
-                             "sample": f"{npl} pairs X[0] x Y[0:{npl}], forward only, one launch "
-                                       "per pair",
-                             "max_rel_vs_oracle": float(np.max(np.abs(
-                                 Kp.cpu().numpy()[0] / ref[0, :npl] - 1.0)))}
+        out["plain_fp64"] = plain_leg(sk, torch, dev)
+        out["large_gram_block"] = large_block_leg(sk, torch, dev)
     out["kernel_source_hash"] = kernel_source_hash()
     print(json.dumps(out), flush=True)
     return 0

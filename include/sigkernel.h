@@ -143,14 +143,16 @@ extern "C" {
 
 /* compiled limits */
 #define SK_MIN_POLY_ORDER 2
-#define SK_MAX_POLY_ORDER 8
+#define SK_MAX_POLY_ORDER 12     /* FP64 sweeps (SK_F64, or SK_F32 with SK_SWEEP_F64) */
+#define SK_MAX_POLY_ORDER_F32 8  /* FP32 sweeps                                       */
 #define SK_MAX_DYADIC_ORDER 8
 #define SK_MAX_BACKWARD_DIM 64
 
 typedef struct sk_params {
     int32_t scheme; /* SK_FD, SK_POLY_APPROX, SK_POLY_INTERP or SK_FD2              */
     int32_t order;  /* N in [SK_MIN_POLY_ORDER, SK_MAX_POLY_ORDER] for the polynomial
-                       schemes; lambda in [0, SK_MAX_DYADIC_ORDER] for SK_FD, SK_FD2  */
+                       schemes (SK_MAX_POLY_ORDER_F32 for FP32 sweeps); lambda in
+                       [0, SK_MAX_DYADIC_ORDER] for SK_FD, SK_FD2                    */
     int32_t dtype;  /* SK_F32 or SK_F64                                              */
     int32_t algo;   /* SK_ALGO_BATCHED, SK_ALGO_PLAIN or SK_ALGO_PIPELINE            */
     int32_t gram;   /* SK_GRAM_NATIVE, SK_GRAM_BF16X3 or SK_GRAM_MFMA (batched algorithm) */

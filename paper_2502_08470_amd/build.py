@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsigkernel.so")
-SOURCES = ["sk_inst_f32.hip", "sk_inst_f64.hip", "sk_api.cpp"]
+SOURCES = ["sk_inst_f32.hip", "sk_inst_f64.hip", "sk_inst_f64_hi.hip", "sk_api.cpp"]
 ARCH = os.environ.get("SK_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

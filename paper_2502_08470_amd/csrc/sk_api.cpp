@@ -224,6 +224,9 @@ int check_params(const sk_params* p, bool backward) {
             return fail(SK_EINVAL, "polynomial order %d < %d", p->order, SK_MIN_POLY_ORDER);
         if (p->order > SK_MAX_POLY_ORDER)
             return fail(SK_EUNSUPPORTED, "polynomial order %d > %d", p->order, SK_MAX_POLY_ORDER);
+        if (p->dtype == SK_F32 && !(p->flags & SK_SWEEP_F64) && p->order > SK_MAX_POLY_ORDER_F32)
+            return fail(SK_EUNSUPPORTED, "FP32 sweeps are compiled for orders up to %d (FP64 sweeps to %d)",
+                        SK_MAX_POLY_ORDER_F32, SK_MAX_POLY_ORDER);
     } else {
         return fail(SK_EINVAL, "scheme %d", p->scheme);
     }
@@ -1790,9 +1793,10 @@ int sigkernel_status(hipStream_t stream, int32_t clear, uint32_t* flags) {
     g_last_error.clear();
     if (!flags) return fail(SK_EINVAL, "flags is NULL");
     SK_TRY_HIP(hipStreamSynchronize(stream), "stream synchronize");
-    unsigned* w[2] = {nullptr, nullptr};
+    unsigned* w[3] = {nullptr, nullptr, nullptr};
     SK_TRY_HIP(SkLaunch<float>::status_word(&w[0]), "status word (FP32 kernels)");
     SK_TRY_HIP(SkLaunch<double>::status_word(&w[1]), "status word (FP64 kernels)");
+    SK_TRY_HIP(sk_hi_status_word(&w[2]), "status word (FP64 kernels, orders 9-12)");
     uint32_t f = 0;
     for (unsigned* p : w) {
         unsigned v = 0;

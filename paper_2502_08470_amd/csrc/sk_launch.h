@@ -5,9 +5,11 @@
 
 #include "sk_kernels.h"
 
-// orders with compiled polynomial kernels
+// orders with compiled polynomial kernels (FP64 also N = 9..12, compiled in
+// their own translation unit, sk_inst_f64_hi.hip)
 #define SK_MIN_ORDER 2
 #define SK_MAX_ORDER 8
+#define SK_MAX_ORDER_F64 12
 #define SK_MAX_DYADIC 8
 #define SK_MAX_DIM 64
 // checkpoint stride of the adjoint's forward recompute
@@ -94,3 +96,13 @@ struct SkLaunch {
 
 extern template struct SkLaunch<float>;
 extern template struct SkLaunch<double>;
+
+// FP64 orders SK_MAX_ORDER < N <= SK_MAX_ORDER_F64 (sk_inst_f64_hi.hip)
+hipError_t sk_hi_sweep(const SweepArgs<double>& a, int N, bool interp, bool ckpt, int64_t npairs,
+                       int ring, bool gx, hipStream_t st);
+hipError_t sk_hi_sweep_pipe(const PipeArgs<double>& a, int N, bool interp, bool ckpt, hipStream_t st);
+hipError_t sk_hi_adjoint(const AdjArgs<double>& a, int N, bool interp, int64_t npairs, int ring,
+                         bool gx, hipStream_t st);
+hipError_t sk_hi_adjoint_pipe(const AdjPipeArgs<double>& a, int N, bool interp, hipStream_t st);
+hipError_t sk_hi_plain_poly(const PlainArgs<double>& a, int N, bool interp, hipStream_t st);
+hipError_t sk_hi_status_word(unsigned** p);

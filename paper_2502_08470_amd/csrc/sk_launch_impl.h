@@ -186,7 +186,11 @@ hipError_t SkLaunch<R>::sweep(const SweepArgs<R>& a, int N, bool interp, bool ck
         case 6: return sk_sweep_t<R, 6>(a, interp, ckpt, npairs, ring, gx, st);
         case 7: return sk_sweep_t<R, 7>(a, interp, ckpt, npairs, ring, gx, st);
         case 8: return sk_sweep_t<R, 8>(a, interp, ckpt, npairs, ring, gx, st);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (sizeof(R) == 8)
+                if (N > SK_MAX_ORDER && N <= SK_MAX_ORDER_F64)
+                    return sk_hi_sweep(a, N, interp, ckpt, npairs, ring, gx, st);
+            return hipErrorInvalidValue;
     }
 }
 
@@ -228,7 +232,10 @@ hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, boo
         case 6: return interp ? sk_pipe_n<R, 6, T>(a, ckpt, st) : sk_pipe_n<R, 6, 0>(a, ckpt, st);
         case 7: return interp ? sk_pipe_n<R, 7, T>(a, ckpt, st) : sk_pipe_n<R, 7, 0>(a, ckpt, st);
         case 8: return interp ? sk_pipe_n<R, 8, T>(a, ckpt, st) : sk_pipe_n<R, 8, 0>(a, ckpt, st);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (sizeof(R) == 8)
+                if (N > SK_MAX_ORDER && N <= SK_MAX_ORDER_F64) return sk_hi_sweep_pipe(a, N, interp, ckpt, st);
+            return hipErrorInvalidValue;
     }
 }
 
@@ -251,7 +258,10 @@ hipError_t SkLaunch<R>::adjoint_pipe(const AdjPipeArgs<R>& a, int N, bool interp
         case 6: return interp ? sk_adj_pipe_n<R, 6, T>(a, st) : sk_adj_pipe_n<R, 6, 0>(a, st);
         case 7: return interp ? sk_adj_pipe_n<R, 7, T>(a, st) : sk_adj_pipe_n<R, 7, 0>(a, st);
         case 8: return interp ? sk_adj_pipe_n<R, 8, T>(a, st) : sk_adj_pipe_n<R, 8, 0>(a, st);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (sizeof(R) == 8)
+                if (N > SK_MAX_ORDER && N <= SK_MAX_ORDER_F64) return sk_hi_adjoint_pipe(a, N, interp, st);
+            return hipErrorInvalidValue;
     }
 }
 
@@ -295,7 +305,11 @@ hipError_t SkLaunch<R>::adjoint(const AdjArgs<R>& a, int N, bool interp, int64_t
         case 6: return sk_adj_t<R, 6>(a, interp, npairs, ring, gx, st);
         case 7: return sk_adj_t<R, 7>(a, interp, npairs, ring, gx, st);
         case 8: return sk_adj_t<R, 8>(a, interp, npairs, ring, gx, st);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (sizeof(R) == 8)
+                if (N > SK_MAX_ORDER && N <= SK_MAX_ORDER_F64)
+                    return sk_hi_adjoint(a, N, interp, npairs, ring, gx, st);
+            return hipErrorInvalidValue;
     }
 }
 
@@ -382,7 +396,10 @@ hipError_t SkLaunch<R>::plain_poly(const PlainArgs<R>& a, int N, bool interp, hi
         case 6: return sk_plain_n<R, 6>(a, interp, st);
         case 7: return sk_plain_n<R, 7>(a, interp, st);
         case 8: return sk_plain_n<R, 8>(a, interp, st);
-        default: return hipErrorInvalidValue;
+        default:
+            if constexpr (sizeof(R) == 8)
+                if (N > SK_MAX_ORDER && N <= SK_MAX_ORDER_F64) return sk_hi_plain_poly(a, N, interp, st);
+            return hipErrorInvalidValue;
     }
 }
 

@@ -347,3 +347,13 @@ def test_sweep_f64_workspace_adds_the_fp64_copies():
             head += (3 * 100 * 4 * 8 + 255) // 256 * 256 + (5 * 70 * 4 * 8 + 255) // 256 * 256
         assert wf == w64 + head, (bwd, wf, w64, head)
         assert lib.sigkernel_gram_workspace(3, 100, 5, 70, 4, p32, bwd) < wf
+
+
+def test_order_limits_per_sweep_precision():
+    lib = L.lib()
+    # FP64 sweeps to 12, FP32 sweeps to 8; FP32 points swept in FP64 to 12
+    assert lib.sigkernel_gram_workspace(2, 10, 2, 10, 3, P(order=12, dtype=0), 1) > 0
+    assert lib.sigkernel_gram_workspace(2, 10, 2, 10, 3, P(order=13, dtype=0), 0) == 0
+    assert lib.sigkernel_gram_workspace(2, 10, 2, 10, 3, P(order=9, dtype=1), 0) == 0
+    assert "up to 8" in L.last_error()
+    assert lib.sigkernel_gram_workspace(2, 10, 2, 10, 3, P(order=12, dtype=1, flags=L.SK_SWEEP_F64), 1) > 0
