@@ -278,9 +278,10 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
     }
 #pragma unroll
     for (int r = 2; r <= N; ++r) {
-        R tp = (R)0, tq = (R)0;
+        // Toeplitz row r, from its k = r term (w_0 = 1)
+        R tp = P[r], tq = Q[r];
 #pragma unroll
-        for (int k = r; k >= 0; --k) {
+        for (int k = r - 1; k >= 0; --k) {
             tp = fma(w[r - k], P[k], tp);
             tq = fma(w[r - k], Q[k], tq);
         }
@@ -541,9 +542,9 @@ __device__ __forceinline__ void sk_cell_adj_in(R c, int T, const SkTab<R>& tab, 
 #pragma unroll
     for (int r = 1; r <= N; ++r) {
         const R ea = a[r], eb = b[r];
-        R tp = (R)0, tq = (R)0;
+        R tp = P[r - 1], tq = Q[r - 1];  // Toeplitz row r - 1, from its w_0 = 1 term
 #pragma unroll
-        for (int k = r - 1; k >= 0; --k) {
+        for (int k = r - 2; k >= 0; --k) {
             tp = fma(w[r - 1 - k], P[k], tp);
             tq = fma(w[r - 1 - k], Q[k], tq);
         }

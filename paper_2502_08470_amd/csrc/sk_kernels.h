@@ -1358,15 +1358,25 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 El_recv = ltag[jj];
             }
         }
-        // outputs nobody consumes have zero adjoint
+        // outputs nobody consumes have zero adjoint (a wave-uniform test
+        // skips the selects on steps where every lane consumes both)
         const bool ta = live && !last_col, tb = live && !last_row;
         R ap[N + 1], aq[N + 1];
 #pragma unroll
         for (int n = 0; n <= N; ++n) {
-            ap[n] = ta ? lp[n] : (R)0;
-            aq[n] = tb ? lq_recv[n] : (R)0;
+            ap[n] = lp[n];
+            aq[n] = lq_recv[n];
         }
-        int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+        int ea = El, eb = El_recv;
+        if (sk_wave_any(!(ta && tb))) {
+#pragma unroll
+            for (int n = 0; n <= N; ++n) {
+                ap[n] = ta ? ap[n] : (R)0;
+                aq[n] = tb ? aq[n] : (R)0;
+            }
+            ea = ta ? ea : SK_ZERO_EXP;
+            eb = tb ? eb : SK_ZERO_EXP;
+        }
         // endpoint seed (once per pair): L = gK * 1/2 sum_n (Po'_n + Qo'_n)/n!
         const bool seed = live && last_col && last_row;
         if (sk_wave_any(seed) && seed) {
@@ -1764,10 +1774,19 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             R ap[N + 1], aq[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
-                ap[n] = ta ? lp[n] : (R)0;
-                aq[n] = tb ? lq_recv[n] : (R)0;
+                ap[n] = lp[n];
+                aq[n] = lq_recv[n];
             }
-            int ea = ta ? El : SK_ZERO_EXP, eb = tb ? El_recv : SK_ZERO_EXP;
+            int ea = El, eb = El_recv;
+            if (sk_wave_any(!(ta && tb))) {  // selects only on steps that need them
+#pragma unroll
+                for (int n = 0; n <= N; ++n) {
+                    ap[n] = ta ? ap[n] : (R)0;
+                    aq[n] = tb ? aq[n] : (R)0;
+                }
+                ea = ta ? ea : SK_ZERO_EXP;
+                eb = tb ? eb : SK_ZERO_EXP;
+            }
             const bool seed = live && last_col && last_row;
             if (sk_wave_any(seed) && seed) {
 #pragma unroll
