@@ -66,7 +66,34 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_interp_gra
 CALIBRATE_MIB = 1024
 # bench kernel label -> prefix of the kernel symbol
 KERNEL_SYMBOL = {"gram": "k_gram_direct<", "sweep": "k_sweep<", "sweep_ckpt": "k_sweep<",
-                 "adjoint": "k_adjoint", "contract": "k_contract<", "reduce": "k_reduce"}
+                 "adjoint": "k_adjoint<", "sweep_pipe": "k_sweep_pipe<",
+                 "sweep_ckpt_pipe": "k_sweep_pipe<", "adjoint_pipe": "k_adjoint_pipe<",
+                 "contract": "k_contract<", "reduce": "k_reduce"}
+
+
+def template_args(symbol: str):
+    """Template arguments of a kernel symbol 'void k_x<a, b, ...>(...)'."""
+    if "<" not in symbol:
+        return []
+    inner = symbol.split("<", 1)[1].split(">(", 1)[0]
+    return [a.strip() for a in inner.split(",")]
+
+
+def symbol_matches(label: str, symbol: str, stride: int) -> bool:
+    """Whether `symbol` is the kernel behind the bench label `label` when the
+    backward runs with checkpoint stride `stride` (k_sweep<R, N, TMAX, CKPT,
+    S, GX>, k_sweep_pipe<R, N, TMAX, CKPT, S>, k_adjoint<R, N, TMAX, S, GX>,
+    k_adjoint_pipe<R, N, TMAX, S>)."""
+    if not symbol.startswith("void " + KERNEL_SYMBOL[label]):
+        return False
+    a = template_args(symbol)
+    if label in ("sweep", "sweep_pipe"):
+        return len(a) > 3 and a[3] == "false"
+    if label in ("sweep_ckpt", "sweep_ckpt_pipe"):
+        return len(a) > 4 and a[3] == "true" and a[4] == str(stride)
+    if label in ("adjoint", "adjoint_pipe"):
+        return len(a) > 3 and a[3] == str(stride)
+    return True
 
 
 def kernel_source_hash() -> str:
@@ -140,9 +167,10 @@ def cpu_model() -> str | None:
     return None
 
 
-def traffic_for(label: str, kernel_name_hint: str | None = None):
-    """HBM bytes per launch of the kernel `label` from the committed counter
-    summary, or None when absent or taken from other kernel sources."""
+def traffic_for(label: str, stride: int = 4):
+    """HBM bytes per launch of the kernel `label` (backward with checkpoint
+    stride `stride`) from the committed counter summary, or None when absent
+    or taken from other kernel sources."""
     try:
         with open(TRAFFIC_SUMMARY) as fh:
             summ = json.load(fh)
@@ -150,10 +178,7 @@ def traffic_for(label: str, kernel_name_hint: str | None = None):
         return None
     if summ.get("source_hash") != kernel_source_hash():
         return None
-    pre = KERNEL_SYMBOL[label]
-    hits = [v for k, v in summ["kernels"].items()
-            if k.startswith("void " + pre) and (label != "sweep_ckpt" or ", true," in k)
-            and (label != "sweep" or ", false," in k)]
+    hits = [v for k, v in summ["kernels"].items() if symbol_matches(label, k, stride)]
     if len(hits) != 1:
         return None
     return hits[0]
@@ -198,7 +223,7 @@ def accuracy_study() -> int:
         def mape(scheme, order):
             K = sk.gram(Xt, Yt, scheme, order).cpu().numpy()
             return float(np.mean(np.abs(K / ref - 1.0)))
-        for N in range(2, 9):  # compiled orders
+        for N in range(2, 13):  # compiled FP64 orders
             rows.append({"steps": steps, "scheme": "approx", "order": N, "mape": mape("approx", N)})
             rows.append({"steps": steps, "scheme": "interp", "order": N, "mape": mape("interp", N)})
         for lam in range(0, 5):
@@ -359,8 +384,14 @@ def workload_study(large_rows: int = 256) -> int:
     Xc, Yc = torch.cat(xl), torch.cat(yl)
     cells = float(sum((len(a) - 1) * (len(b) - 1) for a, b in zip(xs, ys)))
     plan = sk.PairsPlan(xl, yl, "approx", 8, backward=True)
-    plan.tune(Xc, Yc)
     k = torch.empty(len(xs), device=dev)
+    gk = torch.ones(len(xs), device=dev)
+    gX, gY = torch.empty_like(Xc), torch.empty_like(Yc)
+    default_cfg = plan.config()
+    fb_default = best_ms(lambda: (plan.forward(Xc, Yc, k), plan.backward(Xc, Yc, gk, gX, gY)), 2)
+    tt0 = time.perf_counter()
+    plan.tune(Xc, Yc)
+    tune_s = time.perf_counter() - tt0
     fwd = best_ms(lambda: plan.forward(Xc, Yc, k))
     g = torch.cuda.CUDAGraph()
     side = torch.cuda.Stream()
@@ -372,10 +403,9 @@ def workload_study(large_rows: int = 256) -> int:
     with torch.cuda.graph(g):
         plan.forward(Xc, Yc, k)
     graph = best_ms(lambda: g.replay())
-    gk = torch.ones(len(xs), device=dev)
-    gX, gY = torch.empty_like(Xc), torch.empty_like(Yc)
     fb = best_ms(lambda: (plan.forward(Xc, Yc, k), plan.backward(Xc, Yc, gk, gX, gY)), 2)
-    out["uneven_pairs"] = {"cells": cells, "plan": plan.config(),
+    out["uneven_pairs"] = {"cells": cells, "plan": plan.config(), "plan_default": default_cfg,
+                           "fwd_bwd_ms_default_plan": fb_default, "tuning_s": tune_s,
                            "forward_ms": fwd, "forward_graph_ms": graph, "fwd_bwd_ms": fb,
                            "forward_cells_per_s": cells / fwd * 1e3,
                            "fwd_bwd_cells_per_s": cells / fb * 1e3}
@@ -544,6 +574,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the Gram tuner (algorithm and checkpoint stride) before the warm-up")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after timing, copy MIB MiB device to device once (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -591,11 +623,20 @@ def main(argv=None) -> int:
         K.sum().backward()
         return K.detach(), Xt.grad, Yt.grad
 
+    tuned = None
+    if not args.no_tune:
+        # the tuner times each algorithm and checkpoint stride on this
+        # workload (outside the timed region); autograd then takes its choice
+        tt0 = time.perf_counter()
+        tuned = sk.tune_gram(Xt.detach(), Yt.detach(), SCHEME, ORDER, backward=True)
+        tuned["tuning_s"] = time.perf_counter() - tt0
+        print(f"[bench] tuned {tuned}", file=sys.stderr, flush=True)
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         K, gX, gY = step()
     torch.cuda.synchronize()
-    kernels = ["gram", "sweep", "sweep_ckpt", "adjoint", "contract", "reduce"]
+    kernels = ["gram", "sweep", "sweep_ckpt", "adjoint", "sweep_pipe", "sweep_ckpt_pipe",
+               "adjoint_pipe", "contract", "reduce"]
     _lib.profile_enable(True)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -625,8 +666,9 @@ def main(argv=None) -> int:
     # applies the transposed map: 2 forwards without the deciding row (the
     # dL/dc terms are not counted)
     fl_fwd = fwd_cell_flops(ORDER, 0, deciding=True)
-    flops_per_cell = {"sweep": fl_fwd, "sweep_ckpt": fl_fwd,
-                      "adjoint": 2.0 * fwd_cell_flops(ORDER, 0),
+    fl_adj = 2.0 * fwd_cell_flops(ORDER, 0)
+    flops_per_cell = {"sweep": fl_fwd, "sweep_ckpt": fl_fwd, "adjoint": fl_adj,
+                      "sweep_pipe": fl_fwd, "sweep_ckpt_pipe": fl_fwd, "adjoint_pipe": fl_adj,
                       "gram": 2.0 * DIM, "contract": 4.0 * DIM}
     dom = max((k for k in flops_per_cell if ktimes[k][1] > 0), key=lambda k: ktimes[k][0])
     dom_ms, dom_n = ktimes[dom]
@@ -634,8 +676,9 @@ def main(argv=None) -> int:
     # launches of part of the pairs): FLOPs per launch = cells * steps / launches
     cells_per_launch = cells * args.steps / dom_n
     achieved = flops_per_cell[dom] * cells_per_launch / (dom_ms / dom_n * 1e-3)
-    tr = traffic_for(dom)
-    roofline = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12,
+    stride = tuned["ckpt"] if tuned is not None else 4
+    tr = traffic_for(dom, stride)
+    roofline = {"kernel": dom, "ckpt_stride": stride, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VALU,
                 "traffic": None if tr is None else tr["bytes"],
@@ -653,7 +696,9 @@ def main(argv=None) -> int:
                                   "FP32 increment Gram by an 8-term FMA chain per cell "
                                   "(k_gram_direct), fwd+bwd (loss sum K)",
                       "pairs": N_PATHS * N_PATHS, "cells_per_pair": STEPS * STEPS,
-                      "gram_kernel": "k_gram_direct"},
+                      "gram_kernel": "k_gram_direct",
+                      "schedule": tuned if tuned is not None else
+                      {"algo": sk.gram_algo(Xt, Yt, SCHEME), "ckpt": 4, "tuned": False}},
            "gram_entries_per_s": entries, "roofline": roofline}
 
     # accuracy on the 16 x 16 block (and the larger CPU sample), CPU oracle

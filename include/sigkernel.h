@@ -163,6 +163,15 @@ typedef struct sk_params {
                        its backward sweeps the refined grid and sums dL/dc over
                        each cell's 4^lambda sub-cells, times 4^-lambda, before the
                        contraction; must be 0 for SK_FD, SK_FD2                     */
+    int32_t ckpt;   /* checkpoint stride S of the backward (steps per segment of the
+                       checkpointing sweep and the adjoint's replay): 0 picks the
+                       precision's default (4 for FP32 sweeps, 2 for FP64 sweeps);
+                       FP32 sweeps accept 2 or 4, FP64 sweeps (SK_F64 or
+                       SK_SWEEP_F64) 2; other values give SK_EUNSUPPORTED, and any
+                       nonzero value for SK_FD, SK_FD2 SK_EINVAL.  Every stride
+                       computes the same kernel values and gradients up to rounding
+                       order; the choice trades adjoint register pressure against
+                       checkpoint traffic (see sigkernel_gram_tune)              */
 } sk_params;
 
 /*
@@ -273,14 +282,25 @@ int sigkernel_backward(int32_t op, const void* X, const int64_t* x_off, int64_t 
  *   ws_bytes: size of the workspace the plan will run with (chunks are sized
  *   to it); 0 lets sigkernel_plan_workspace report the size for one chunk
  *   per LDS class (capped at 160 GiB).
- * sigkernel_plan_tune times every configuration of the forward on the given
- * inputs (three runs each, device time), keeps the fastest in the plan,
- * uploads it, and remembers it for plans and one-shot sigkernel_pairs /
- * sigkernel_backward calls of the same shape in this process (shape = params,
- * d and the sequence of path lengths).  best_ms (nullable) receives its time.
+ * sigkernel_plan_tune times configurations of the schedule on the given
+ * inputs (a warm-up and two timed runs each, device time on `stream`): the
+ * forward for forward plans, forward + backward (dL/dk = 1, buffers the tuner
+ * allocates and frees) for backward plans.  It searches in three stages, each
+ * from the best so far: pair order x transposition x LDS classes; the
+ * strip-pipeline threshold (every threshold that moves a different set of
+ * pairs to the pipeline); the checkpoint strides of the precision (backward
+ * plans).  Configurations needing more than ws_bytes are skipped
+ * (sigkernel_plan_tune_workspace gives the largest any of them needs).  The
+ * fastest is kept in the plan, uploaded, and stored in the process's tune
+ * cache for plans and one-shot sigkernel_pairs / sigkernel_backward calls of
+ * the same shape class (see sigkernel_tune_cache_save).  best_ms (nullable)
+ * receives its time.  Every configuration computes the same values up to
+ * rounding order.
  * sigkernel_plan_config reports the configuration in use and the number of
  * launches (chunks) of one forward; sigkernel_plan_configure sets it by hand
- * (each flag 0 or 1; the plan must be uploaded again).  The caller owns the plan and destroys
+ * (each flag 0 or 1; pipeline 1 = pairs of two or more strips; the plan must
+ * be uploaded again).  sigkernel_plan_get_cfg / sigkernel_plan_set_cfg do
+ * the same with the whole configuration (sk_plan_cfg).  The caller owns the plan and destroys
  * it with sigkernel_plan_destroy; a plan may be used from one thread at a
  * time.  Errors: as for sigkernel_pairs; SK_EINVAL for a plan that was not
  * uploaded to this workspace, or a backward on a forward-only plan.
@@ -319,7 +339,55 @@ int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, in
                           int32_t* pipeline, int64_t* launches);
 int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t buckets,
                              int32_t pipeline, size_t ws_bytes);
+typedef struct sk_plan_cfg {
+    int32_t longest_first;       /* 1: pairs in decreasing wavefront steps          */
+    int32_t transpose;           /* 1: pairs whose second path is longer transposed */
+    int32_t lds_classes;         /* 1: a forward launch per LDS class               */
+    int32_t pipeline_min_strips; /* k >= 2: pairs of k or more 64-row strips run on
+                                    the strip pipeline; 0: none (1 is SK_EINVAL)    */
+    int32_t ckpt;                /* checkpoint stride (0: the plan's sk_params.ckpt;
+                                    get_cfg reports the stride in use)            */
+    int64_t launches;            /* get_cfg only: forward chunks                   */
+} sk_plan_cfg;
+int sigkernel_plan_get_cfg(const sk_plan* plan, sk_plan_cfg* cfg);
+int sigkernel_plan_set_cfg(sk_plan* plan, const sk_plan_cfg* cfg, size_t ws_bytes);
+size_t sigkernel_plan_tune_workspace(const sk_plan* plan);
 void sigkernel_plan_destroy(sk_plan* plan);
+
+/*
+ * Gram tuner (the autotuned batching of uneven and few-pair workloads).
+ * sigkernel_gram_tune times, on the given inputs, the forward (backward != 0:
+ * forward + backward through the saved state, dL/dK = 1) of every algorithm
+ * (SK_ALGO_BATCHED, and SK_ALGO_PIPELINE for polynomial schemes on paths of
+ * several strips) and checkpoint stride the precision offers, with the
+ * caller's other parameters; writes the fastest parameters to *best and their
+ * time to *best_ms (nullable), and stores the choice in the tune cache under
+ * the call's key.  It allocates and frees its own device memory and
+ * synchronises `stream`.  sigkernel_gram_tuned looks a call's key up without
+ * touching the device beyond naming its architecture: *found = 1 and *out =
+ * the caller's parameters with the tuned algo and ckpt, or *found = 0 and
+ * *out = *p.  Every candidate computes the same values up to rounding order.
+ * Errors: as for sigkernel_gram; SK_EUNSUPPORTED for SK_ALGO_PLAIN.
+ *
+ * Tune cache.  Keys: GPU architecture, call kind (Gram or pairs), scheme,
+ * order, dtype, Gram mode, refinement, flags, direction, d, and the shape
+ * class (ceil(log2) of the pair counts and of the mean and largest segment
+ * counts of each side).  sigkernel_tune_cache_save writes the cache as text
+ * (a header line, then one entry a line), through a temporary file renamed
+ * over `path`.  sigkernel_tune_cache_load merges a saved cache into the
+ * process's: a missing file loads nothing and is not an error; a file whose
+ * first line is not the header loads nothing (*skipped = 1); malformed
+ * entries are skipped and counted.  *loaded / *skipped (nullable) receive
+ * the counts.  sigkernel_tune_cache_clear empties the process's cache.
+ */
+int sigkernel_gram_tune(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                        int64_t ly_pts, int64_t d, const sk_params* p, int32_t backward,
+                        hipStream_t stream, sk_params* best, double* best_ms);
+int sigkernel_gram_tuned(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                         const sk_params* p, int32_t backward, sk_params* out, int32_t* found);
+int sigkernel_tune_cache_save(const char* path);
+int sigkernel_tune_cache_load(const char* path, int32_t* loaded, int32_t* skipped);
+void sigkernel_tune_cache_clear(void);
 
 /*
  * Permutation two-sample test on the unbiased MMD^2 (the statistical testing

@@ -53,6 +53,14 @@ EXPORTS = (
     "sigkernel_set_spin_limit",
     "sigkernel_interp_table",
     "sigkernel_gram_static",
+    "sigkernel_plan_get_cfg",
+    "sigkernel_plan_set_cfg",
+    "sigkernel_plan_tune_workspace",
+    "sigkernel_gram_tune",
+    "sigkernel_gram_tuned",
+    "sigkernel_tune_cache_save",
+    "sigkernel_tune_cache_load",
+    "sigkernel_tune_cache_clear",
 )
 
 
@@ -60,7 +68,13 @@ class SkParams(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("algo", ctypes.c_int32),
                 ("gram", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("dyadic", ctypes.c_int32)]
+                ("dyadic", ctypes.c_int32), ("ckpt", ctypes.c_int32)]
+
+
+class SkPlanCfg(ctypes.Structure):
+    _fields_ = [("longest_first", ctypes.c_int32), ("transpose", ctypes.c_int32),
+                ("lds_classes", ctypes.c_int32), ("pipeline_min_strips", ctypes.c_int32),
+                ("ckpt", ctypes.c_int32), ("launches", ctypes.c_int64)]
 
 
 class SigKernelError(RuntimeError):
@@ -128,6 +142,24 @@ def lib():
     L.sigkernel_plan_config.restype = ctypes.c_int
     L.sigkernel_plan_configure.argtypes = [vp, i32, i32, i32, i32, sz]
     L.sigkernel_plan_configure.restype = ctypes.c_int
+    cp = ctypes.POINTER(SkPlanCfg)
+    L.sigkernel_plan_get_cfg.argtypes = [vp, cp]
+    L.sigkernel_plan_get_cfg.restype = ctypes.c_int
+    L.sigkernel_plan_set_cfg.argtypes = [vp, cp, sz]
+    L.sigkernel_plan_set_cfg.restype = ctypes.c_int
+    L.sigkernel_plan_tune_workspace.argtypes = [vp]
+    L.sigkernel_plan_tune_workspace.restype = sz
+    L.sigkernel_gram_tune.argtypes = [vp, i64, i64, vp, i64, i64, i64, pp, i32, vp, pp,
+                                      ctypes.POINTER(ctypes.c_double)]
+    L.sigkernel_gram_tune.restype = ctypes.c_int
+    L.sigkernel_gram_tuned.argtypes = [i64, i64, i64, i64, i64, pp, i32, pp, ctypes.POINTER(i32)]
+    L.sigkernel_gram_tuned.restype = ctypes.c_int
+    L.sigkernel_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.sigkernel_tune_cache_save.restype = ctypes.c_int
+    L.sigkernel_tune_cache_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.sigkernel_tune_cache_load.restype = ctypes.c_int
+    L.sigkernel_tune_cache_clear.argtypes = []
+    L.sigkernel_tune_cache_clear.restype = None
     L.sigkernel_plan_destroy.argtypes = [vp]
     L.sigkernel_plan_destroy.restype = None
     L.sigkernel_mmd_permutation.argtypes = [vp, i64, i64, vp, i64, i32, vp, vp, vp]
@@ -199,3 +231,19 @@ def interp_table(order: int, dtype: int):
                                        rmax.ctypes.data_as(dp), cmax.ctypes.data_as(dp),
                                        ctypes.byref(cap)))
     return rs.reshape(order + 1, SK_TAIL_TABLE), rmax, cmax, cap.value
+
+
+def tune_cache_save(path: str) -> None:
+    """Write the process's tune cache to ``path`` (text, replaced atomically)."""
+    check(lib().sigkernel_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str):
+    """Merge a saved tune cache; returns (entries loaded, entries skipped)."""
+    n, k = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().sigkernel_tune_cache_load(os.fsencode(path), ctypes.byref(n), ctypes.byref(k)))
+    return n.value, k.value
+
+
+def tune_cache_clear() -> None:
+    lib().sigkernel_tune_cache_clear()

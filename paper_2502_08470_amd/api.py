@@ -16,11 +16,12 @@ from . import _lib as L
 _SCHEMES = {"fd": L.SK_FD, "fd2": L.SK_FD2, "approx": L.SK_POLY_APPROX,
             "interp": L.SK_POLY_INTERP}
 _ALGOS = {"batched": L.SK_ALGO_BATCHED, "plain": L.SK_ALGO_PLAIN, "pipeline": L.SK_ALGO_PIPELINE}
+_ALGO_NAMES = {v: k for k, v in _ALGOS.items()}
 _GRAMS = {"native": L.SK_GRAM_NATIVE, "bf16x3": L.SK_GRAM_BF16X3, "mfma": L.SK_GRAM_MFMA}
 
 
 def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: str = "native",
-            flags: int = 0, dyadic: int = 0, sweep: str = "native") -> L.SkParams:
+            flags: int = 0, dyadic: int = 0, sweep: str = "native", ckpt: int = 0) -> L.SkParams:
     if dtype == torch.float32:
         dt = L.SK_F32
     elif dtype == torch.float64:
@@ -38,7 +39,7 @@ def _params(dtype: torch.dtype, scheme: str, order: int, algo: str, gram_mode: s
     if sweep == "f64":
         flags |= L.SK_SWEEP_F64
     return L.SkParams(_SCHEMES[scheme], int(order), dt, _ALGOS[algo], _GRAMS[gram_mode], int(flags),
-                      int(dyadic))
+                      int(dyadic), int(ckpt))
 
 
 def _dev(t: torch.Tensor) -> torch.Tensor:
@@ -152,9 +153,10 @@ def pairs(xs, ys, scheme: str = "approx", order: int = 4, algo: str = "batched",
 def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: str = "approx",
                   order: int = 4, gK_exp: Optional[torch.Tensor] = None,
                   gram_mode: str = "native", symmetric: bool = False, algo: str = "batched",
-                  dyadic: int = 0, sweep: str = "native"):
+                  dyadic: int = 0, sweep: str = "native", ckpt: int = 0):
     """(dL/dX, dL/dY) for L = sum(gK * K) with K = gram(X, Y, scheme, order,
-    dyadic=dyadic, sweep=sweep).
+    dyadic=dyadic, sweep=sweep).  ``ckpt`` is the checkpoint stride (0: the
+    precision's default; see tune_gram).
     ``symmetric`` (Y is X): returns (dL/dX with both contributions, None).
     ``algo`` "pipeline" runs pairs of several strips on the pipelined
     checkpoint sweep and adjoint (for few, long paths; the call synchronises
@@ -166,7 +168,7 @@ def gram_backward(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor, scheme: st
         raise ValueError("gram_backward runs the batched algorithm or the strip pipeline")
     gK = _dev(gK.to(X.dtype))
     p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0,
-                dyadic=dyadic, sweep=sweep)
+                dyadic=dyadic, sweep=sweep, ckpt=ckpt)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     if gK.shape != (nx, ny):
@@ -232,9 +234,9 @@ def cell_constants(X: torch.Tensor, Y: torch.Tensor, gram_mode: str = "native") 
 
 def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
                     order: int = 4, gram_mode: str = "native", algo: str = "batched",
-                    dyadic: int = 0) -> int:
+                    dyadic: int = 0, ckpt: int = 0) -> int:
     """Bytes of the backward state kept by gram_save for these shapes."""
-    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic, ckpt=ckpt)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     nb = L.lib().sigkernel_gram_state_size(nx, lxp, ny, lyp, d, ctypes.byref(p))
@@ -245,18 +247,18 @@ def gram_state_size(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",
 
 def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
               return_exp: bool = False, gram_mode: str = "native", algo: str = "batched",
-              dyadic: int = 0):
+              dyadic: int = 0, ckpt: int = 0):
     """Gram matrix plus the state its backward needs: returns (K, state) or
     (K, K_exp, state).  Pass the state to gram_backward_saved with the same
     ``algo`` ("pipeline": the strip pipeline's checkpoint sweep; the call
     synchronises the stream once to upload its job lists)."""
     X, Y = _dev(X), _dev(Y)
-    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic)
+    p = _params(X.dtype, scheme, order, algo, gram_mode, dyadic=dyadic, ckpt=ckpt)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     K = torch.empty((nx, ny), dtype=X.dtype, device=X.device)
     Ke = torch.empty((nx, ny), dtype=torch.int32, device=X.device) if return_exp else None
-    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode, algo, dyadic), X.device)
+    state = _workspace(gram_state_size(X, Y, scheme, order, gram_mode, algo, dyadic, ckpt), X.device)
     L.check(L.lib().sigkernel_gram_save(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
                                         _ptr(K), _ptr(Ke), _ptr(state), state.numel(),
                                         _stream(X)))
@@ -266,15 +268,16 @@ def gram_save(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: i
 def gram_backward_saved(X: torch.Tensor, Y: torch.Tensor, gK: torch.Tensor,
                         state: torch.Tensor, scheme: str = "approx", order: int = 4,
                         gK_exp: Optional[torch.Tensor] = None, gram_mode: str = "native",
-                        symmetric: bool = False, algo: str = "batched", dyadic: int = 0):
+                        symmetric: bool = False, algo: str = "batched", dyadic: int = 0,
+                        ckpt: int = 0):
     """Same result as gram_backward, from the state left by gram_save(X, Y)
-    with the same ``algo`` and ``dyadic``."""
+    with the same ``algo``, ``dyadic`` and ``ckpt``."""
     X, Y = _dev(X), _dev(Y)
     if symmetric:
         Y = X
     gK = _dev(gK.to(X.dtype))
     p = _params(X.dtype, scheme, order, algo, gram_mode, L.SK_SYMMETRIC if symmetric else 0,
-                dyadic=dyadic)
+                dyadic=dyadic, ckpt=ckpt)
     nx, lxp, d = X.shape
     ny, lyp, _ = Y.shape
     gX = torch.empty_like(X)
@@ -311,6 +314,7 @@ class PairsPlan:
         self._p = _params(Xc.dtype, scheme, order, "batched", gram_mode, dyadic=dyadic)
         self._lib = L.lib()
         h = ctypes.c_void_p(0)
+        _load_tune_cache()
         L.check(self._lib.sigkernel_plan_create(_i64arr(xo), _i64arr(yo), self.npairs, self.d,
                                                 ctypes.byref(self._p), 1 if backward else 0, 0,
                                                 ctypes.byref(h)))
@@ -324,34 +328,51 @@ class PairsPlan:
                                                 _stream(self.ws)))
 
     def tune(self, Xcat: torch.Tensor, Ycat: torch.Tensor) -> float:
-        """Time every configuration on these inputs and keep the fastest;
-        returns its forward time in ms."""
+        """Time the tuner's configurations on these inputs (forward, and for
+        a backward plan forward + backward), keep the fastest, store it in the
+        tune cache (and the SK_TUNE_CACHE file); returns its time in ms.  The
+        workspace grows to what the largest configuration needs while tuning
+        and is then fitted to the choice."""
+        _load_tune_cache()
+        need = self._lib.sigkernel_plan_tune_workspace(self._h)
+        if need > self.ws.numel():
+            self.ws = _workspace(need, self.device)
         ms = ctypes.c_double(0.0)
         L.check(self._lib.sigkernel_plan_tune(self._h, _ptr(_dev(Xcat)), _ptr(_dev(Ycat)),
                                               _ptr(self.ws), self.ws.numel(), _stream(self.ws),
                                               ctypes.byref(ms)))
+        self._fit_workspace()
+        _save_tune_cache()
         return ms.value
 
-    def config(self) -> dict:
-        o, w, b, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        n = ctypes.c_int64()
-        L.check(self._lib.sigkernel_plan_config(self._h, ctypes.byref(o), ctypes.byref(w),
-                                                ctypes.byref(b), ctypes.byref(p), ctypes.byref(n)))
-        return {"longest_first": bool(o.value), "transpose": bool(w.value),
-                "lds_classes": bool(b.value), "pipeline": bool(p.value), "launches": int(n.value)}
-
-    def configure(self, longest_first: bool, transpose: bool, lds_classes: bool,
-                  pipeline: bool = False):
-        """Set the configuration by hand (rebuilds the plan, grows the
-        workspace if this configuration needs more, and uploads).  ``pipeline``
-        runs pairs with several strips on the strip pipeline: their forward,
-        and for a backward plan their checkpoint sweep and adjoint."""
-        L.check(self._lib.sigkernel_plan_configure(self._h, int(longest_first), int(transpose),
-                                                   int(lds_classes), int(pipeline), 0))
+    def _fit_workspace(self):
         nb = self._lib.sigkernel_plan_workspace(self._h)
-        if nb > self.ws.numel():
+        if nb > self.ws.numel() or nb < 0.75 * self.ws.numel():
             self.ws = _workspace(nb, self.device)
         self._upload()
+
+    def config(self) -> dict:
+        c = L.SkPlanCfg()
+        L.check(self._lib.sigkernel_plan_get_cfg(self._h, ctypes.byref(c)))
+        return {"longest_first": bool(c.longest_first), "transpose": bool(c.transpose),
+                "lds_classes": bool(c.lds_classes), "pipeline": c.pipeline_min_strips >= 2,
+                "pipeline_min_strips": int(c.pipeline_min_strips), "ckpt": int(c.ckpt),
+                "launches": int(c.launches)}
+
+    def configure(self, longest_first: bool, transpose: bool, lds_classes: bool,
+                  pipeline: Union[bool, int] = False, ckpt: int = 0):
+        """Set the configuration by hand (rebuilds the plan, grows the
+        workspace if this configuration needs more, and uploads).  ``pipeline``
+        runs pairs with several strips (True or 1: two or more; an int k >= 2:
+        k or more) on the strip pipeline: their forward, and for a backward plan
+        their checkpoint sweep and adjoint.  ``ckpt``: checkpoint stride of
+        the backward (0: the precision's default)."""
+        k = int(pipeline)
+        if k in (0, 1):  # False / True: no pipeline / pairs of two or more strips
+            k = 2 * k
+        c = L.SkPlanCfg(int(longest_first), int(transpose), int(lds_classes), k, int(ckpt), 0)
+        L.check(self._lib.sigkernel_plan_set_cfg(self._h, ctypes.byref(c), 0))
+        self._fit_workspace()
 
     def forward(self, Xcat: torch.Tensor, Ycat: torch.Tensor, k: torch.Tensor,
                 k_exp: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -422,20 +443,101 @@ def gram_algo(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx") -> str:
     return "pipeline" if strips >= 2 and Y.shape[1] > 1 and few else "batched"
 
 
+# ---------------------------------------------------------------------------
+# tuning: the library's tune cache, persisted in the file SK_TUNE_CACHE names
+# ---------------------------------------------------------------------------
+_cache_loaded = False
+
+
+def _tune_cache_path() -> Optional[str]:
+    import os
+    return os.environ.get("SK_TUNE_CACHE") or None
+
+
+def _load_tune_cache() -> None:
+    """Merge the SK_TUNE_CACHE file into the library's cache, once."""
+    global _cache_loaded
+    if _cache_loaded:
+        return
+    _cache_loaded = True
+    path = _tune_cache_path()
+    if path:
+        L.tune_cache_load(path)
+
+
+def _save_tune_cache() -> None:
+    path = _tune_cache_path()
+    if path:
+        L.tune_cache_save(path)
+
+
+def gram_tuned(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
+               gram_mode: str = "native", dyadic: int = 0, sweep: str = "native",
+               backward: bool = True, symmetric: bool = False) -> Optional[dict]:
+    """The tune cache's choice for a Gram call of this shape class:
+    {"algo", "ckpt"}, or None when the class has not been tuned."""
+    _load_tune_cache()
+    p = _params(X.dtype, scheme, order, "batched", gram_mode,
+                L.SK_SYMMETRIC if symmetric else 0, dyadic=dyadic, sweep=sweep)
+    out, found = L.SkParams(), ctypes.c_int32(0)
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    L.check(L.lib().sigkernel_gram_tuned(nx, lxp, ny, lyp, d, ctypes.byref(p), int(backward),
+                                         ctypes.byref(out), ctypes.byref(found)))
+    if not found.value:
+        return None
+    return {"algo": _ALGO_NAMES[out.algo], "ckpt": int(out.ckpt)}
+
+
+def tune_gram(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
+              gram_mode: str = "native", dyadic: int = 0, sweep: str = "native",
+              backward: bool = True, symmetric: bool = False) -> dict:
+    """Time every algorithm (batched, strip pipeline) and checkpoint stride
+    on these inputs (forward, or forward + backward through the saved state),
+    store the fastest in the tune cache (and the SK_TUNE_CACHE file), and
+    return {"algo", "ckpt", "ms"}.  Synchronises the current stream."""
+    _load_tune_cache()
+    X, Y = _dev(X), _dev(Y)
+    if symmetric:
+        Y = X
+    p = _params(X.dtype, scheme, order, "batched", gram_mode,
+                L.SK_SYMMETRIC if symmetric else 0, dyadic=dyadic, sweep=sweep)
+    best, ms = L.SkParams(), ctypes.c_double(0.0)
+    nx, lxp, d = X.shape
+    ny, lyp, _ = Y.shape
+    L.check(L.lib().sigkernel_gram_tune(_ptr(X), nx, lxp, _ptr(Y), ny, lyp, d, ctypes.byref(p),
+                                        int(backward), _stream(X), ctypes.byref(best),
+                                        ctypes.byref(ms)))
+    _save_tune_cache()
+    return {"algo": _ALGO_NAMES[best.algo], "ckpt": int(best.ckpt), "ms": ms.value}
+
+
 class SigKernelGram(torch.autograd.Function):
     """Differentiable Gram matrix; the backward runs the library's adjoint
     sweep (exact gradient of the computed scheme).  Batched: when the
     backward state fits the memory budget the forward keeps it (gram_save)
     and the backward starts from it; otherwise the backward recomputes it in
-    chunks.  ``algo`` (by default gram_algo's choice) selects the batched
-    algorithm or the strip pipeline for both."""
+    chunks.  ``algo`` selects the batched algorithm or the strip pipeline for
+    both; None takes the tune cache's choice for this shape class (algorithm
+    and checkpoint stride, see tune_gram) and else gram_algo's.  ``tune``
+    tunes the shape class on these inputs first when the cache has no entry."""
 
     @staticmethod
     def forward(ctx, X, Y, scheme="approx", order=4, gram_mode="native", algo=None, dyadic=0,
-                sweep="native"):
+                sweep="native", tune=False):
         ctx.save_for_backward(X, Y)
         ctx.scheme, ctx.order, ctx.gram_mode, ctx.dyadic = scheme, order, gram_mode, dyadic
         ctx.sweep = sweep
+        ctx.ckpt = 0
+        if algo is None:
+            bwd = scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad)
+            t = gram_tuned(X, Y, scheme, order, gram_mode, dyadic, sweep, backward=bwd,
+                           symmetric=X is Y)
+            if t is None and tune and X.shape[0] * Y.shape[0] > 0:
+                t = tune_gram(X.detach(), Y.detach(), scheme, order, gram_mode, dyadic, sweep,
+                              backward=bwd, symmetric=X is Y)
+            if t is not None:
+                algo, ctx.ckpt = t["algo"], t["ckpt"]
         ctx.algo = algo or gram_algo(X, Y, scheme)
         # the same tensor on both sides: one gradient with both contributions
         ctx.symmetric = X is Y
@@ -444,10 +546,10 @@ class SigKernelGram(torch.autograd.Function):
             return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode, dyadic=dyadic,
                         sweep=sweep)
         if scheme not in ("fd", "fd2") and (X.requires_grad or Y.requires_grad):
-            size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo, dyadic)
+            size = gram_state_size(X, Y, scheme, order, gram_mode, ctx.algo, dyadic, ctx.ckpt)
             if size <= _state_budget(X.device):
                 K, ctx.state = gram_save(X, Y, scheme, order, gram_mode=gram_mode, algo=ctx.algo,
-                                         dyadic=dyadic)
+                                         dyadic=dyadic, ckpt=ctx.ckpt)
                 return K
         return gram(X, Y, scheme, order, algo=ctx.algo, gram_mode=gram_mode, dyadic=dyadic)
 
@@ -455,21 +557,22 @@ class SigKernelGram(torch.autograd.Function):
     def backward(ctx, gK):
         X, Y = ctx.saved_tensors
         kw = dict(gram_mode=ctx.gram_mode, symmetric=ctx.symmetric, algo=ctx.algo,
-                  dyadic=ctx.dyadic)
+                  dyadic=ctx.dyadic, ckpt=ctx.ckpt)
         if ctx.state is not None:
             gX, gY = gram_backward_saved(X, Y, gK, ctx.state, ctx.scheme, ctx.order, **kw)
             ctx.state = None
         else:
             gX, gY = gram_backward(X, Y, gK, ctx.scheme, ctx.order, sweep=ctx.sweep, **kw)
-        return gX, gY, None, None, None, None, None, None
+        return gX, gY, None, None, None, None, None, None, None
 
 
 def sig_gram(X, Y, scheme: str = "approx", order: int = 4, gram_mode: str = "native",
-             algo: Optional[str] = None, dyadic: int = 0, sweep: str = "native") -> torch.Tensor:
+             algo: Optional[str] = None, dyadic: int = 0, sweep: str = "native",
+             tune: bool = False) -> torch.Tensor:
     """Differentiable Gram matrix (SigKernelGram); ``dyadic`` > 0 runs the
     hybrid scheme on the dyadically refined grid; ``sweep`` "f64" sweeps
-    float32 paths in FP64."""
-    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo, dyadic, sweep)
+    float32 paths in FP64; ``algo`` None and ``tune`` as for SigKernelGram."""
+    return SigKernelGram.apply(X, Y, scheme, order, gram_mode, algo, dyadic, sweep, tune)
 
 
 class SigKernelPairs(torch.autograd.Function):

@@ -243,6 +243,14 @@ int check_params(const sk_params* p, bool backward) {
     if (p->gram == SK_GRAM_BF16X3 && p->algo == SK_ALGO_PLAIN)
         return fail(SK_EUNSUPPORTED, "the bf16 split Gram is not a plain-algorithm mode");
     if (p->flags & ~(SK_SYMMETRIC | SK_SWEEP_F64)) return fail(SK_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->ckpt != 0) {
+        const bool f64sweep = p->dtype == SK_F64 || (p->flags & SK_SWEEP_F64);
+        if (p->ckpt < 0) return fail(SK_EINVAL, "checkpoint stride %d < 0", p->ckpt);
+        if (is_fd(*p)) return fail(SK_EINVAL, "the finite-difference schemes have no checkpoint stride");
+        if (f64sweep ? p->ckpt != 2 : (p->ckpt != 2 && p->ckpt != 4))
+            return fail(SK_EUNSUPPORTED, "checkpoint stride %d (compiled: %s)", p->ckpt,
+                        f64sweep ? "2 for FP64 sweeps" : "2 or 4 for FP32 sweeps");
+    }
     if (p->flags & SK_SWEEP_F64) {
         if (p->dtype != SK_F32) return fail(SK_EINVAL, "SK_SWEEP_F64 applies to SK_F32 paths");
         if (p->gram == SK_GRAM_BF16X3)
@@ -363,7 +371,11 @@ int ring_adj_of(const sk_params& p, int ly) {
     const int c = grid_cols(p, ly);
     return c > gx_cols_adj(p) ? 0 : c;
 }
+// Checkpoint stride S of the backward: p.ckpt when set (validated), else the
+// precision's default.  Shorter segments shorten the adjoint's replay state
+// (fewer registers, more waves per SIMD) at the cost of more checkpoints.
 int ckpt_stride(const sk_params& p) {
+    if (p.ckpt > 0) return p.ckpt;
     return p.dtype == SK_F32 ? SkCkptStride<float>::value : SkCkptStride<double>::value;
 }
 
@@ -497,7 +509,7 @@ int run_chunk_forward(const sk_params& p, const R* X, const R* Y, int64_t d, con
         sa.K = K; sa.Kexp = Kexp;
         sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
         sa.gx_cols = gx_cols_fwd(p);
-        sa.lam = lam;
+        sa.lam = lam; sa.S = ckpt_stride(p);
         SK_LAUNCH("sweep", st, SkLaunch<R>::sweep(sa, p.order, interp, false, P, ring,
                                                   grid_cols(p, max_ly) > sa.gx_cols, st), "sweep");
     }
@@ -529,6 +541,7 @@ int run_chunk_forward_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
     pa.spin_limit = g_spin_limit.load();
     pa.desc = src.desc; pa.jobs = jobs; pa.njobs = njobs; pa.lam = lam_of(p);
+    pa.S = ckpt_stride(p);
     SK_LAUNCH("sweep_pipe", st, SkLaunch<R>::sweep_pipe(pa, p.order, p.scheme == SK_POLY_INTERP, false, st),
               "pipelined strip sweep");
     return SK_OK;
@@ -564,6 +577,7 @@ int run_chunk_prepare_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     pa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     pa.progress = prog; pa.abort = abrt; pa.spin_limit = g_spin_limit.load();
     pa.desc = src.desc; pa.jobs = jobs_fwd; pa.njobs = njobs; pa.lam = lam_of(p);
+    pa.S = ckpt_stride(p);
     pa.ck = reinterpret_cast<R*>(ws + L.ck);
     pa.ce = reinterpret_cast<int32_t*>(ws + L.ce);
     pa.qb = reinterpret_cast<R*>(ws + L.qb);
@@ -599,6 +613,7 @@ int run_chunk_adjoint_pipe(const sk_params& p, const R* X, const R* Y, int64_t d
     aa.progress = prog; aa.abort = reinterpret_cast<int*>(ws + L.total) - 1;
     aa.spin_limit = g_spin_limit.load();
     aa.desc = src.desc; aa.jobs = jobs_adj; aa.njobs = njobs; aa.lam = lam_of(p);
+    aa.S = ckpt_stride(p);
     SK_LAUNCH("adjoint_pipe", st, SkLaunch<R>::adjoint_pipe(aa, p.order, interp, st),
               "pipelined adjoint sweep");
     if (aa.lam == 0) return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
@@ -713,7 +728,7 @@ int run_chunk_prepare(const sk_params& p, const R* X, const R* Y, int64_t d,
     sa.qe = reinterpret_cast<int32_t*>(ws + L.qe);
     sa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     sa.gx_cols = gx_cols_fwd(p);
-    sa.lam = lam_of(p);
+    sa.lam = lam_of(p); sa.S = ckpt_stride(p);
     SK_LAUNCH("sweep_ckpt", st, SkLaunch<R>::sweep(sa, p.order, interp, true, P, ring,
                                                        grid_cols(p, max_ly) > sa.gx_cols, st), "checkpoint sweep");
     return SK_OK;
@@ -752,7 +767,7 @@ int run_chunk_adjoint(const sk_params& p, const R* X, const R* Y, int64_t d,
     aa.gskew = reinterpret_cast<R*>(ws + L.gskew);
     aa.xb = reinterpret_cast<unsigned*>(ws + L.xb);
     aa.gx_cols = gx_cols_adj(p);
-    aa.lam = lam_of(p);
+    aa.lam = lam_of(p); aa.S = ckpt_stride(p);
     SK_LAUNCH("adjoint", st, SkLaunch<R>::adjoint(aa, p.order, interp, P, ring,
                                                   grid_cols(p, max_ly) > aa.gx_cols, st), "adjoint sweep");
     if (aa.lam == 0) return run_contract<R>(X, Y, d, src, P, max_strips, ws, L, st);
@@ -1163,8 +1178,11 @@ struct PlanCfg {
     int32_t order;    // 1: longest pairs first (by wavefront steps); 0: given order
     int32_t swap;     // 1: transpose pairs whose second path is longer
     int32_t buckets;  // 1: separate launches per LDS class of the forward sweep
-    int32_t pipe;     // 1: pairs with several strips on the strip pipeline (forward and backward)
+    int32_t pipe;     // k >= 2: pairs of k or more strips on the strip pipeline (forward and
+                      // backward); 0: none
+    int32_t ckpt;     // checkpoint stride of the backward (0: the caller's sk_params.ckpt)
 };
+constexpr PlanCfg kDefaultPlanCfg = {1, 1, 1, 2, 0};
 
 struct PlanChunk {
     int64_t first = 0, count = 0;  // range of the plan's descriptor array
@@ -1178,11 +1196,12 @@ struct PlanChunk {
 };
 
 struct PlanImpl {
-    sk_params p;
+    sk_params p;       // the parameters in use (ckpt: the configuration's stride)
+    sk_params p_user;  // as the caller gave them
     int64_t npairs = 0, d = 0;
     bool backward = false;
     std::vector<int64_t> xo, yo;
-    PlanCfg cfg = {1, 1, 1, 1};
+    PlanCfg cfg = kDefaultPlanCfg;
     // forward and backward chunkings (the backward keeps more state per pair,
     // so its chunks are smaller); descriptors hold chunk-relative offsets
     std::vector<SkPairDesc> fdesc, bdesc;
@@ -1225,6 +1244,13 @@ int plan_build(PlanImpl& P0, const PlanCfg& cfg, size_t ws_bytes) {
 }
 
 int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
+    if (cfg.pipe < 0 || cfg.pipe == 1) return fail(SK_EINVAL, "pipeline threshold %d strips", cfg.pipe);
+    P.p = P.p_user;
+    if (cfg.ckpt != 0) {
+        P.p.ckpt = cfg.ckpt;
+        const int rc = check_params(&P.p, P.backward);
+        if (rc) return rc;
+    }
     const sk_params& p = P.p;
     const int lam = lam_of(p);
     const size_t es = esize(p);
@@ -1245,7 +1271,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
         const int32_t cls_fwd = cfg.buckets ? lds_class(p, ey[i]) : 0;
         // pairs of several strips go to the strip pipeline (class 6), which
         // balances the load strip by strip instead of pair by pair
-        pipe[i] = (cfg.pipe && !is_fd(p) && g.nstrips >= 2) ? 1 : 0;
+        pipe[i] = (cfg.pipe >= 2 && !is_fd(p) && g.nstrips >= cfg.pipe) ? 1 : 0;
         clsf[i] = pipe[i] ? 6 : cls_fwd;
         // the backward runs its other pairs in one launch per chunk: a launch
         // per LDS class pays the longest pairs' sequential tail once per
@@ -1409,7 +1435,7 @@ int plan_build_into(PlanImpl& P, const PlanCfg& cfg, size_t ws_bytes) {
 
 int plan_init(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
               const sk_params& p, bool backward) {
-    P.p = p;
+    P.p = P.p_user = p;
     P.npairs = npairs;
     P.d = d;
     P.backward = backward;
@@ -1418,58 +1444,124 @@ int plan_init(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs,
     return SK_OK;
 }
 
-// Tuned configurations, keyed by everything that shapes the plan.
-struct TuneKey {
-    sk_params p;
-    int64_t npairs, d;
-    uint64_t lens;  // hash of the (lx, ly) sequence
-    bool operator==(const TuneKey& o) const {
-        return std::memcmp(&p, &o.p, sizeof(p)) == 0 && npairs == o.npairs && d == o.d &&
-               lens == o.lens;
-    }
+// ---------------------------------------------------------------------------
+// tune cache: tuned configurations keyed by (GPU architecture, scheme, order,
+// precision, Gram mode, refinement, direction, d, shape class), where the
+// shape class is the ceil(log2) of the pair count and of the mean and
+// largest segment counts of each side.  Kept per process; saved to and
+// loaded from a text file by sigkernel_tune_cache_save / _load.
+// ---------------------------------------------------------------------------
+struct TuneVal {
+    PlanCfg cfg;     // plans (and one-shot pairs calls)
+    int32_t algo;    // Gram calls: SK_ALGO_BATCHED or SK_ALGO_PIPELINE
+    double ms;       // timed forward (+ backward) of the winner
 };
 std::mutex g_tune_mu;
-std::vector<std::pair<TuneKey, PlanCfg>> g_tune_cache;
+std::vector<std::pair<std::string, TuneVal>> g_tune_cache;
 
-TuneKey tune_key(const PlanImpl& P) {
-    TuneKey k;
-    std::memset(&k, 0, sizeof(k));
-    k.p = P.p;
-    k.p.flags = 0;
-    k.npairs = P.npairs;
-    k.d = P.d;
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the segment counts
-    for (int64_t i = 0; i < P.npairs; ++i) {
-        uint64_t v = (uint64_t)(P.xo[i + 1] - P.xo[i]) * 1000003ull + (uint64_t)(P.yo[i + 1] - P.yo[i]);
-        for (int b = 0; b < 8; ++b) {
-            h ^= (v >> (8 * b)) & 0xff;
-            h *= 1099511628211ull;
-        }
-    }
-    k.lens = h;
-    return k;
+int clog2(int64_t v) {
+    int r = 0;
+    while (r < 62 && ((int64_t)1 << r) < v) ++r;
+    return r;
 }
 
-bool tuned_cfg(const PlanImpl& P, PlanCfg* cfg) {
-    const TuneKey k = tune_key(P);
+// gfx name of the current device ("none" without one), looked up once per device.
+std::string device_arch() {
+    static std::mutex mu;
+    static std::vector<std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return "none";
+    std::lock_guard<std::mutex> g(mu);
+    if ((size_t)dev >= names.size()) names.resize(dev + 1);
+    if (names[dev].empty()) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "none";
+        std::string n = prop.gcnArchName;
+        const size_t colon = n.find(':');
+        names[dev] = n.substr(0, colon);
+        if (names[dev].empty()) names[dev] = "unknown";
+    }
+    return names[dev];
+}
+
+std::string params_key(const char* kind, const sk_params& p, bool backward, int64_t d) {
+    char b[160];
+    std::snprintf(b, sizeof(b), "%s|%s|s%d|n%d|t%d|g%d|y%d|f%d|b%d|d%lld", kind,
+                  device_arch().c_str(), p.scheme, p.order, p.dtype, p.gram, p.dyadic,
+                  p.flags, backward ? 1 : 0, (long long)d);
+    return b;
+}
+
+std::string plan_key(const PlanImpl& P) {
+    int64_t sx = 0, sy = 0, mx = 0, my = 0;
+    for (int64_t i = 0; i < P.npairs; ++i) {
+        const int64_t lx = P.xo[i + 1] - P.xo[i] - 1, ly = P.yo[i + 1] - P.yo[i] - 1;
+        sx += lx; sy += ly;
+        mx = std::max(mx, lx); my = std::max(my, ly);
+    }
+    const int64_t n = std::max<int64_t>(P.npairs, 1);
+    char b[96];
+    std::snprintf(b, sizeof(b), "|P%d|x%d,%d|y%d,%d", clog2(P.npairs), clog2((sx + n - 1) / n),
+                  clog2(mx), clog2((sy + n - 1) / n), clog2(my));
+    return params_key("pairs", P.p_user, P.backward, P.d) + b;
+}
+
+std::string gram_key(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                     const sk_params& p, bool backward) {
+    sk_params q = p;
+    q.algo = SK_ALGO_BATCHED;  // tuned
+    q.ckpt = 0;                // tuned
+    char b[96];
+    std::snprintf(b, sizeof(b), "|P%d,%d|x%d|y%d", clog2(nx), clog2(ny), clog2(lx_pts - 1),
+                  clog2(ly_pts - 1));
+    return params_key("gram", q, backward, d) + b;
+}
+
+bool tune_lookup(const std::string& k, TuneVal* v) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     for (const auto& e : g_tune_cache)
         if (e.first == k) {
-            *cfg = e.second;
+            *v = e.second;
             return true;
         }
     return false;
 }
 
-void remember_cfg(const PlanImpl& P, const PlanCfg& cfg) {
-    const TuneKey k = tune_key(P);
+void tune_store(const std::string& k, const TuneVal& v) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     for (auto& e : g_tune_cache)
         if (e.first == k) {
-            e.second = cfg;
+            e.second = v;
             return;
         }
-    g_tune_cache.push_back({k, cfg});
+    g_tune_cache.push_back({k, v});
+}
+
+bool tuned_cfg(const PlanImpl& P, PlanCfg* cfg) {
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        if (g_tune_cache.empty()) return false;  // no device query for an empty cache
+    }
+    TuneVal v;
+    if (!tune_lookup(plan_key(P), &v)) return false;
+    // the cached stride must still be valid for these parameters
+    sk_params q = P.p_user;
+    if (v.cfg.ckpt) q.ckpt = v.cfg.ckpt;
+    const std::string saved = g_last_error;
+    if (check_params(&q, P.backward)) {
+        g_last_error = saved;
+        return false;
+    }
+    *cfg = v.cfg;
+    return true;
+}
+
+void remember_cfg(const PlanImpl& P, const PlanCfg& cfg, double ms) {
+    TuneVal v;
+    v.cfg = cfg;
+    v.algo = SK_ALGO_BATCHED;
+    v.ms = ms;
+    tune_store(plan_key(P), v);
 }
 
 int plan_check_device(const PlanImpl& P) {
@@ -1618,52 +1710,153 @@ int plan_backward_saved(const PlanImpl& P, const R* Xc, const R* Yc, const R* gK
     return plan_chunk_adjoint<R>(P, P.bchunks[0], Xc, Yc, gK, gKexp, gX, gY, ws, st);
 }
 
-// Time every configuration's forward (best of two runs after a warm-up),
-// keep the fastest, remember it for plans of the same shape.
+// Device buffers of a tuning run's backward: dL/dk = 1 and the gradients.
+template <typename R>
+struct TuneBufs {
+    R* gk = nullptr;
+    R* gx = nullptr;
+    R* gy = nullptr;
+    ~TuneBufs() {
+        if (gk) (void)hipFree(gk);
+        if (gx) (void)hipFree(gx);
+        if (gy) (void)hipFree(gy);
+    }
+    int alloc(int64_t nk, int64_t nxv, int64_t nyv, hipStream_t st) {
+        SK_TRY_HIP(hipMalloc((void**)&gk, std::max<int64_t>(nk, 1) * sizeof(R)), "tuning buffers");
+        SK_TRY_HIP(hipMalloc((void**)&gx, std::max<int64_t>(nxv, 1) * sizeof(R)), "tuning buffers");
+        SK_TRY_HIP(hipMalloc((void**)&gy, std::max<int64_t>(nyv, 1) * sizeof(R)), "tuning buffers");
+        SK_TRY_HIP(SkLaunch<R>::fill(gk, std::max<int64_t>(nk, 1), (R)1, st), "fill");
+        return SK_OK;
+    }
+};
+
+// Device time (ms) of `run` on `st`: a warm-up, then the best of two runs.
+template <typename F>
+int time_best(F&& run, hipStream_t st, double* ms_out) {
+    hipEvent_t e0, e1;
+    SK_TRY_HIP(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SK_EHIP, "event");
+    }
+    int rc = SK_OK;
+    double t = 1e30;
+    for (int rep = 0; rep < 3 && !rc; ++rep) {
+        hipError_t he = hipEventRecord(e0, st);
+        if (he == hipSuccess) rc = run();
+        if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
+        if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (!rc && he != hipSuccess) rc = hip_fail(he, "tuning run");
+        if (!rc && rep > 0) t = std::min(t, (double)ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) *ms_out = t;
+    return rc;
+}
+
+// Configurations the plan tuner visits, in three stages, each starting from
+// the best so far: (1) pair order, transposition and LDS classes, (2) the
+// strip-pipeline threshold (every threshold that moves a different set of
+// pairs to the pipeline), (3) for backward plans the checkpoint strides the
+// precision offers.  Workspace need of a configuration: plan total.
+std::vector<int32_t> pipe_thresholds(const PlanImpl& P, const PlanCfg& cfg) {
+    std::vector<int32_t> out = {0};
+    if (is_fd(P.p_user)) return out;
+    const int lam = lam_of(P.p_user);
+    std::vector<int32_t> ns(P.npairs);
+    for (int64_t i = 0; i < P.npairs; ++i) {
+        int lx = (int)(P.xo[i + 1] - P.xo[i] - 1), ly = (int)(P.yo[i + 1] - P.yo[i] - 1);
+        if (cfg.swap && ly > lx) std::swap(lx, ly);
+        ns[i] = sk_make_geom(lx << lam, ly << lam).nstrips;
+    }
+    int64_t prev = -1;
+    for (int32_t k : {2, 3, 4, 6, 8, 12, 16, 24, 32, 64}) {
+        int64_t cnt = 0;
+        for (int32_t v : ns) cnt += v >= k;
+        if (cnt == 0) break;
+        if (cnt != prev) out.push_back(k);
+        prev = cnt;
+    }
+    return out;
+}
+std::vector<int32_t> ckpt_choices(const sk_params& p, bool backward) {
+    if (!backward || is_fd(p)) return {0};
+    const bool f64 = p.dtype == SK_F64 || (p.flags & SK_SWEEP_F64);
+    return f64 ? std::vector<int32_t>{2} : std::vector<int32_t>{4, 2};
+}
+
+// Largest workspace any configuration the tuner visits can need (host only).
+int64_t plan_tune_workspace(const PlanImpl& P0) {
+    PlanImpl P = P0;
+    int64_t need = P0.total;
+    for (int o = 0; o < 2; ++o)
+        for (int w = 0; w < 2; ++w)
+            for (int b = 0; b < 2; ++b)
+                for (int32_t k : pipe_thresholds(P0, PlanCfg{o, w, b, 0, 0}))
+                    for (int32_t s : ckpt_choices(P0.p_user, P0.backward)) {
+                        const PlanCfg cfg = {o, w, b, k, s};
+                        if (plan_build_into(P, cfg, SIZE_MAX) == SK_OK) need = std::max(need, P.total);
+                    }
+    g_last_error.clear();
+    return need;
+}
+
+// Time the tuner's configurations on these inputs (forward, and for backward
+// plans forward + backward with dL/dk = 1), keep the fastest in the plan,
+// upload it and remember it for plans and one-shot calls of the same shape
+// class.  Configurations whose workspace exceeds wsb are skipped.
 template <typename R>
 int plan_tune(PlanImpl& P, const R* Xc, const R* Yc, void* ws, size_t wsb, hipStream_t st,
               double* best_ms) {
-    hipEvent_t e0, e1;
-    SK_TRY_HIP(hipEventCreate(&e0), "event");
-    SK_TRY_HIP(hipEventCreate(&e1), "event");
+    TuneBufs<R> tb;
+    int rc = SK_OK;
+    if (P.backward && (rc = tb.alloc(P.npairs, P.xo[P.npairs] * P.d, P.yo[P.npairs] * P.d, st)))
+        return rc;
     PlanCfg best = P.cfg;
     double best_t = -1.0;
-    int rc = SK_OK;
+    auto visit = [&](const PlanCfg& cfg) -> int {
+        int r = plan_build(P, cfg, wsb);
+        if (r == SK_EWORKSPACE) {  // this configuration does not fit: skip it
+            g_last_error.clear();
+            return SK_OK;
+        }
+        if (r || (r = plan_upload(P, ws, wsb, st))) return r;
+        R* K = reinterpret_cast<R*>((char*)ws + P.kbuf_off);
+        double t = 0.0;
+        r = time_best([&]() -> int {
+            if (!P.backward) return plan_forward<R>(P, Xc, Yc, K, nullptr, ws, st);
+            int q = plan_forward<R>(P, Xc, Yc, K, nullptr, ws, st);
+            return q ? q : plan_backward<R>(P, Xc, Yc, tb.gk, nullptr, tb.gx, tb.gy, ws, st);
+        }, st, &t);
+        if (r) return r;
+        if (best_t < 0 || t < best_t) {
+            best_t = t;
+            best = cfg;
+        }
+        return SK_OK;
+    };
+    const PlanCfg base = kDefaultPlanCfg;
     for (int o = 0; o < 2 && !rc; ++o)
         for (int w = 0; w < 2 && !rc; ++w)
-            for (int b = 0; b < 2 && !rc; ++b)
-            for (int pp = 0; pp < 2 && !rc; ++pp) {
-                const PlanCfg cfg = {o, w, b, pp};
-                rc = plan_build(P, cfg, wsb);
-                if (rc == SK_EWORKSPACE) {  // this configuration does not fit: skip it
-                    rc = SK_OK;
-                    g_last_error.clear();
-                    continue;
-                }
-                if (rc || (rc = plan_upload(P, ws, wsb, st))) break;
-                R* K = reinterpret_cast<R*>((char*)ws + P.kbuf_off);
-                double t = 1e30;
-                for (int rep = 0; rep < 3 && !rc; ++rep) {
-                    hipError_t he = hipEventRecord(e0, st);
-                    if (he == hipSuccess) rc = plan_forward<R>(P, Xc, Yc, K, nullptr, ws, st);
-                    if (!rc && he == hipSuccess) he = hipEventRecord(e1, st);
-                    if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-                    if (he != hipSuccess) rc = hip_fail(he, "tuning run");
-                    if (!rc && rep > 0) t = std::min(t, (double)ms);
-                }
-                if (!rc && (best_t < 0 || t < best_t)) {
-                    best_t = t;
-                    best = cfg;
-                }
-            }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+            for (int b = 0; b < 2 && !rc; ++b) rc = visit(PlanCfg{o, w, b, base.pipe, base.ckpt});
+    if (!rc) {
+        const PlanCfg s1 = best;
+        for (int32_t k : pipe_thresholds(P, s1))
+            if (!rc && k != s1.pipe) rc = visit(PlanCfg{s1.order, s1.swap, s1.buckets, k, s1.ckpt});
+    }
+    if (!rc) {
+        const PlanCfg s2 = best;
+        for (int32_t c : ckpt_choices(P.p_user, P.backward))
+            if (!rc && c != 0 && c != ckpt_stride(P.p_user))
+                rc = visit(PlanCfg{s2.order, s2.swap, s2.buckets, s2.pipe, c});
+    }
     if (rc) return rc;
     if (best_t < 0) return fail(SK_EWORKSPACE, "no configuration fits a workspace of %zu bytes", wsb);
     if ((rc = plan_build(P, best, wsb)) || (rc = plan_upload(P, ws, wsb, st))) return rc;
-    remember_cfg(P, best);
+    remember_cfg(P, best, best_t);
     if (best_ms) *best_ms = best_t;
     return SK_OK;
 }
@@ -1705,9 +1898,9 @@ int pairs_plain(const R* Xc, const int64_t* xo, const R* Yc, const int64_t* yo, 
 int oneshot_plan(PlanImpl& P, const int64_t* xo, const int64_t* yo, int64_t npairs, int64_t d,
                  const sk_params& p, bool backward, size_t wsb) {
     plan_init(P, xo, yo, npairs, d, p, backward);
-    PlanCfg cfg = {1, 1, 1, 1};
+    PlanCfg cfg = kDefaultPlanCfg;
     tuned_cfg(P, &cfg);
-    if (p.algo == SK_ALGO_PIPELINE) cfg.pipe = 1;  // the pipeline wherever a pair has several strips
+    if (p.algo == SK_ALGO_PIPELINE) cfg.pipe = 2;  // the pipeline wherever a pair has several strips
     return plan_build(P, cfg, wsb);
 }
 
@@ -2147,7 +2340,7 @@ int sigkernel_plan_create(const int64_t* x_off, const int64_t* y_off, int64_t np
     try {
         sk_plan* P = new sk_plan();
         plan_init(P->impl, x_off, y_off, npairs, d, *p, backward != 0);
-        PlanCfg cfg = {1, 1, 1, 1};
+        PlanCfg cfg = kDefaultPlanCfg;
         tuned_cfg(P->impl, &cfg);
         rc = plan_build(P->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
         if (rc) {
@@ -2292,7 +2485,7 @@ int sigkernel_plan_config(const sk_plan* plan, int32_t* order, int32_t* swap, in
     if (order) *order = plan->impl.cfg.order;
     if (swap) *swap = plan->impl.cfg.swap;
     if (buckets) *buckets = plan->impl.cfg.buckets;
-    if (pipeline) *pipeline = plan->impl.cfg.pipe;
+    if (pipeline) *pipeline = plan->impl.cfg.pipe >= 2 ? 1 : 0;
     if (launches) *launches = (int64_t)plan->impl.fchunks.size();
     return SK_OK;
 }
@@ -2303,7 +2496,8 @@ int sigkernel_plan_configure(sk_plan* plan, int32_t order, int32_t swap, int32_t
     if (!plan) return fail(SK_EINVAL, "plan is NULL");
     if ((order | swap | buckets | pipeline) & ~1) return fail(SK_EINVAL, "configuration flags are 0 or 1");
     try {
-        const PlanCfg cfg = {order, swap, buckets, pipeline};
+        PlanCfg cfg = plan->impl.cfg;
+        cfg.order = order; cfg.swap = swap; cfg.buckets = buckets; cfg.pipe = pipeline ? 2 : 0;
         return plan_build(plan->impl, cfg, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
     } catch (...) {
         return fail(SK_EINVAL, "internal exception");
@@ -2471,6 +2665,285 @@ int sigkernel_cell_constants(const void* X, int64_t nx, int64_t lx_pts, const vo
         }
     }
     return SK_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Gram tuner and the tune cache's file
+// ---------------------------------------------------------------------------
+namespace {
+// Device memory of one Gram tuning run, freed on every return path.
+struct DevMem {
+    void* p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t n) {
+        SK_TRY_HIP(hipMalloc(&p, std::max<size_t>(n, 256)), "tuning buffers");
+        return SK_OK;
+    }
+};
+
+template <typename R>
+int gram_tune_impl(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                   int64_t ly_pts, int64_t d, const sk_params& p, bool backward, hipStream_t st,
+                   sk_params* best_p, double* best_ms) {
+    const bool sym = (p.flags & SK_SYMMETRIC) != 0;
+    const bool saved = backward && !(p.flags & SK_SWEEP_F64);
+    std::vector<sk_params> cands;
+    std::vector<int32_t> algos = {SK_ALGO_BATCHED};
+    const int64_t segs = std::max(lx_pts, ly_pts) - 1;
+    if (!is_fd(p) && (segs << lam_of(p)) > 64) algos.push_back(SK_ALGO_PIPELINE);
+    for (int32_t a : algos)
+        for (int32_t c : ckpt_choices(p, backward)) {
+            sk_params q = p;
+            q.algo = a;
+            q.ckpt = c;
+            cands.push_back(q);
+        }
+    // workspace: the largest any candidate needs
+    size_t wsb = 0;
+    for (const sk_params& q : cands) {
+        const size_t w = saved ? sigkernel_gram_state_size(nx, lx_pts, ny, ly_pts, d, &q)
+                               : std::max(sigkernel_gram_workspace(nx, lx_pts, ny, ly_pts, d, &q, 0),
+                                          backward ? sigkernel_gram_workspace(nx, lx_pts, ny, ly_pts, d, &q, 1)
+                                                   : (size_t)0);
+        wsb = std::max(wsb, w);
+    }
+    g_last_error.clear();
+    if (wsb == 0) return fail(SK_EINVAL, "no configuration applies to this Gram call");
+    DevMem ws, K, gk, gx, gy;
+    const int64_t nk = nx * ny, nxv = nx * lx_pts * d, nyv = ny * ly_pts * d;
+    int rc = ws.alloc(wsb);
+    if (!rc) rc = K.alloc(nk * sizeof(R));
+    if (!rc && backward) {
+        if (!(rc = gk.alloc(nk * sizeof(R))) && !(rc = gx.alloc(nxv * sizeof(R))) &&
+            !(rc = gy.alloc(nyv * sizeof(R))))
+            rc = SkLaunch<R>::fill((R*)gk.p, nk, (R)1, st) == hipSuccess ? SK_OK : fail(SK_EHIP, "fill");
+    }
+    if (rc) return rc;
+    double bt = -1.0;
+    for (const sk_params& q : cands) {
+        double t = 0.0;
+        int r = time_best([&]() -> int {
+            int z;
+            if (saved) {
+                z = sigkernel_gram_save(X, nx, lx_pts, Y, ny, ly_pts, d, &q, K.p, nullptr, ws.p, wsb, st);
+                if (!z)
+                    z = sigkernel_gram_backward_saved(X, nx, lx_pts, Y, ny, ly_pts, d, &q, gk.p, nullptr,
+                                                      gx.p, sym ? nullptr : gy.p, ws.p, wsb, st);
+                return z;
+            }
+            z = sigkernel_gram(X, nx, lx_pts, Y, ny, ly_pts, d, &q, K.p, nullptr, ws.p, wsb, st);
+            if (!z && backward)
+                z = sigkernel_backward(SK_OP_GRAM, X, nullptr, nx, lx_pts, Y, nullptr, ny, ly_pts, d, &q,
+                                       gk.p, nullptr, gx.p, sym ? nullptr : gy.p, ws.p, wsb, st);
+            return z;
+        }, st, &t);
+        if (r == SK_EUNSUPPORTED || r == SK_EWORKSPACE) {  // not offered for this call: skip
+            g_last_error.clear();
+            continue;
+        }
+        if (r) return r;
+        if (bt < 0 || t < bt) {
+            bt = t;
+            *best_p = q;
+        }
+    }
+    if (bt < 0) return fail(SK_EUNSUPPORTED, "no configuration runs this Gram call");
+    TuneVal v;
+    v.cfg = kDefaultPlanCfg;
+    v.cfg.ckpt = best_p->ckpt;
+    v.algo = best_p->algo;
+    v.ms = bt;
+    tune_store(gram_key(nx, lx_pts, ny, ly_pts, d, p, backward), v);
+    if (best_ms) *best_ms = bt;
+    return SK_OK;
+}
+
+constexpr const char* kTuneHeader = "# sigkernel tune cache 1";
+}  // namespace
+
+extern "C" {
+
+int sigkernel_gram_tune(const void* X, int64_t nx, int64_t lx_pts, const void* Y, int64_t ny,
+                        int64_t ly_pts, int64_t d, const sk_params* p, int32_t backward,
+                        hipStream_t stream, sk_params* best, double* best_ms) {
+    g_last_error.clear();
+    if (!X || !Y || !best) return fail(SK_EINVAL, "NULL pointer");
+    int rc = check_params(p, backward != 0);
+    if (!rc) rc = check_dims(d, backward != 0);
+    if (!rc) rc = check_gram_geom(lx_pts, ly_pts, lam_of(*p));
+    if (rc) return rc;
+    if (p->algo == SK_ALGO_PLAIN) return fail(SK_EUNSUPPORTED, "the plain algorithm has nothing to tune");
+    if (nx <= 0 || ny <= 0) return fail(SK_EINVAL, "empty Gram");
+    try {
+        if (p->dtype == SK_F32)
+            return gram_tune_impl<float>(X, nx, lx_pts, Y, ny, ly_pts, d, *p, backward != 0, stream, best,
+                                         best_ms);
+        return gram_tune_impl<double>(X, nx, lx_pts, Y, ny, ly_pts, d, *p, backward != 0, stream, best,
+                                      best_ms);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_gram_tuned(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
+                         const sk_params* p, int32_t backward, sk_params* out, int32_t* found) {
+    g_last_error.clear();
+    if (!p || !out || !found) return fail(SK_EINVAL, "NULL pointer");
+    *found = 0;
+    *out = *p;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        if (g_tune_cache.empty()) return SK_OK;
+    }
+    try {
+        TuneVal v;
+        if (!tune_lookup(gram_key(nx, lx_pts, ny, ly_pts, d, *p, backward != 0), &v)) return SK_OK;
+        sk_params q = *p;
+        q.algo = v.algo;
+        q.ckpt = v.cfg.ckpt;
+        if (check_params(&q, backward != 0)) {  // a stale entry: keep the caller's parameters
+            g_last_error.clear();
+            return SK_OK;
+        }
+        *out = q;
+        *found = 1;
+        return SK_OK;
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_tune_cache_save(const char* path) {
+    g_last_error.clear();
+    if (!path) return fail(SK_EINVAL, "NULL path");
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(SK_EINVAL, "cannot write %s", tmp.c_str());
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        std::fprintf(f, "%s\n", kTuneHeader);
+        for (const auto& e : g_tune_cache)
+            std::fprintf(f, "%s %d %d %d %d %d %d %.6g\n", e.first.c_str(), e.second.cfg.order,
+                         e.second.cfg.swap, e.second.cfg.buckets, e.second.cfg.pipe, e.second.cfg.ckpt,
+                         e.second.algo, e.second.ms);
+    }
+    const bool ok = std::fflush(f) == 0 && !std::ferror(f);
+    if (std::fclose(f) != 0 || !ok) {
+        std::remove(tmp.c_str());
+        return fail(SK_EINVAL, "writing %s failed", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(SK_EINVAL, "cannot replace %s", path);
+    }
+    return SK_OK;
+}
+
+int sigkernel_tune_cache_load(const char* path, int32_t* loaded, int32_t* skipped) {
+    g_last_error.clear();
+    if (loaded) *loaded = 0;
+    if (skipped) *skipped = 0;
+    if (!path) return fail(SK_EINVAL, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return SK_OK;  // no cache yet: defaults
+    char line[1024];
+    bool header = false;
+    int32_t nl = 0, ns = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        const size_t len = std::strlen(line);
+        if (len == 0 || line[len - 1] != '\n') {  // over-long or unterminated line
+            ++ns;
+            if (len == sizeof(line) - 1) {
+                int ch;
+                while ((ch = std::fgetc(f)) != EOF && ch != '\n') {}
+            }
+            continue;
+        }
+        line[len - 1] = 0;
+        if (!header) {
+            header = std::strcmp(line, kTuneHeader) == 0;
+            if (!header) break;  // not a tune cache: take nothing from it
+            continue;
+        }
+        char key[512];
+        int o, w, b, pp, ck, al, used = 0;
+        double ms;
+        const int got = std::sscanf(line, "%511s %d %d %d %d %d %d %lf%n", key, &o, &w, &b, &pp, &ck, &al,
+                                    &ms, &used);
+        const bool ok = got == 8 && line[used] == 0 && (o == 0 || o == 1) && (w == 0 || w == 1) &&
+                        (b == 0 || b == 1) && (pp == 0 || (pp >= 2 && pp <= 1 << 20)) &&
+                        (ck == 0 || ck == 2 || ck == 4) &&
+                        (al == SK_ALGO_BATCHED || al == SK_ALGO_PIPELINE) && std::isfinite(ms) &&
+                        (std::strncmp(key, "pairs|", 6) == 0 || std::strncmp(key, "gram|", 5) == 0);
+        if (!ok) {
+            ++ns;
+            continue;
+        }
+        TuneVal v;
+        v.cfg = PlanCfg{o, w, b, pp, ck};
+        v.algo = al;
+        v.ms = ms;
+        tune_store(key, v);
+        ++nl;
+    }
+    std::fclose(f);
+    if (!header && (nl | ns) == 0) {
+        if (skipped) *skipped = 1;
+        return SK_OK;
+    }
+    if (loaded) *loaded = nl;
+    if (skipped) *skipped = ns;
+    return SK_OK;
+}
+
+void sigkernel_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache.clear();
+}
+
+int sigkernel_plan_get_cfg(const sk_plan* plan, sk_plan_cfg* out) {
+    g_last_error.clear();
+    if (!plan || !out) return fail(SK_EINVAL, "NULL pointer");
+    const PlanCfg& c = plan->impl.cfg;
+    out->longest_first = c.order;
+    out->transpose = c.swap;
+    out->lds_classes = c.buckets;
+    out->pipeline_min_strips = c.pipe;
+    out->ckpt = ckpt_stride(plan->impl.p);
+    out->launches = (int64_t)plan->impl.fchunks.size();
+    return SK_OK;
+}
+
+int sigkernel_plan_set_cfg(sk_plan* plan, const sk_plan_cfg* cfg, size_t ws_bytes) {
+    g_last_error.clear();
+    if (!plan || !cfg) return fail(SK_EINVAL, "NULL pointer");
+    if ((cfg->longest_first | cfg->transpose | cfg->lds_classes) & ~1)
+        return fail(SK_EINVAL, "configuration flags are 0 or 1");
+    try {
+        const PlanCfg c = {cfg->longest_first, cfg->transpose, cfg->lds_classes, cfg->pipeline_min_strips,
+                           cfg->ckpt};
+        return plan_build(plan->impl, c, ws_bytes == 0 ? SIZE_MAX : ws_bytes);
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+size_t sigkernel_plan_tune_workspace(const sk_plan* plan) {
+    g_last_error.clear();
+    if (!plan) {
+        fail(SK_EINVAL, "plan is NULL");
+        return 0;
+    }
+    try {
+        return (size_t)plan_tune_workspace(plan->impl);
+    } catch (...) {
+        fail(SK_EINVAL, "internal exception");
+        return 0;
+    }
 }
 
 }  // extern "C"

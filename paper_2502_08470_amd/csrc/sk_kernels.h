@@ -639,6 +639,7 @@ struct SweepArgs {
     unsigned* xb;          // global strip-boundary exchange records (long pairs)
     int32_t gx_cols;       // pairs with more columns use the global exchange
     int32_t lam;           // dyadic refinement of the grid (hybrid method), forward only
+    int32_t S;             // checkpoint stride of the checkpointing sweep
 };
 
 // Global strip-boundary exchange, consumer side: at the start of every
@@ -952,6 +953,7 @@ struct PipeArgs {
     int32_t* ce;             // CKPT: per strip, [sk_pipe_steps / S][64 + 1]
     R* qb;                   // CKPT: strip-boundary edges [nstrips][ly][N + 1]
     int32_t* qe;             // CKPT: their exponents [nstrips][ly]
+    int32_t S;               // CKPT: checkpoint stride
 };
 
 // Hand-over without cache-wide fences: the producer stores its records and
@@ -1236,6 +1238,7 @@ struct AdjArgs {
     unsigned* xb;          // global strip-boundary exchange records (long pairs)
     int32_t gx_cols;       // pairs with more columns use the global exchange
     int32_t lam;           // dyadic refinement of the pairs' grids (hybrid scheme)
+    int32_t S;             // checkpoint stride (as the checkpointing sweep's)
 };
 
 // Exponent of an adjoint vector that is zero by construction: below any
@@ -1626,6 +1629,7 @@ struct AdjPipeArgs {
     const int2* jobs;       // (pair, strip), every pair's strips in decreasing order
     int64_t njobs;
     int32_t lam;            // dyadic refinement of the pairs' grids (hybrid scheme)
+    int32_t S;              // checkpoint stride (as the checkpointing sweep's)
 };
 
 // LDS of the pipelined adjoint: the exchange staging slot, then the

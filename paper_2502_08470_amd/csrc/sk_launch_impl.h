@@ -149,10 +149,13 @@ hipError_t SkLaunch<R>::gram_strip(const GramArgs<R>& a0, int max_strips, int ma
     return hipSuccess;
 }
 
-template <typename R, int N, int TMAX>
-static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
+// Checkpoint strides compiled per precision (the stride the host chose is
+// a.S; FP32 2 or 4, FP64 2).  Only checkpointing kernels depend on it.
+template <typename R> constexpr bool sk_alt_stride() { return sizeof(R) == 4; }
+
+template <typename R, int N, int TMAX, int S>
+static hipError_t sk_sweep_s(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
                              hipStream_t st) {
-    constexpr int S = SkCkptStride<R>::value;
     size_t lds = SkLaunch<R>::sweep_lds(N, ring);
     dim3 grid((unsigned)npairs), blk(64);
     if (ckpt && gx)
@@ -165,6 +168,16 @@ static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, i
         hipLaunchKernelGGL((k_sweep<R, N, TMAX, false, S, false>), grid, blk, lds, st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+template <typename R, int N, int TMAX>
+static hipError_t sk_sweep_n(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
+                             hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    if constexpr (sk_alt_stride<R>())
+        if (ckpt && a.S == 2) return sk_sweep_s<R, N, TMAX, 2>(a, ckpt, npairs, ring, gx, st);
+    if (ckpt && a.S != S) return hipErrorInvalidValue;
+    return sk_sweep_s<R, N, TMAX, S>(a, ckpt, npairs, ring, gx, st);
 }
 
 template <typename R, int N>
@@ -217,6 +230,9 @@ static hipError_t sk_pipe_n(const PipeArgs<R>& a, bool ckpt, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
     const void* kern = ckpt ? reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, true, S>)
                             : reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, false, S>);
+    if constexpr (sk_alt_stride<R>())
+        if (ckpt && a.S == 2) kern = reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, true, 2>);
+    if (ckpt && a.S != S && !(sk_alt_stride<R>() && a.S == 2)) return hipErrorInvalidValue;
     return sk_coop_launch(kern, a, a.njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
 }
 
@@ -242,6 +258,11 @@ hipError_t SkLaunch<R>::sweep_pipe(const PipeArgs<R>& a, int N, bool interp, boo
 template <typename R, int N, int TMAX>
 static hipError_t sk_adj_pipe_n(const AdjPipeArgs<R>& a, hipStream_t st) {
     constexpr int S = SkCkptStride<R>::value;
+    if constexpr (sk_alt_stride<R>())
+        if (a.S == 2)
+            return sk_coop_launch(reinterpret_cast<const void*>(&k_adjoint_pipe<R, N, TMAX, 2>), a,
+                                  a.njobs, (size_t)sk_adj_pipe_lds<R>(N, TMAX, 2), st);
+    if (a.S != S) return hipErrorInvalidValue;
     const void* kern = reinterpret_cast<const void*>(&k_adjoint_pipe<R, N, TMAX, S>);
     return sk_coop_launch(kern, a, a.njobs, (size_t)sk_adj_pipe_lds<R>(N, TMAX, S), st);
 }
@@ -265,9 +286,8 @@ hipError_t SkLaunch<R>::adjoint_pipe(const AdjPipeArgs<R>& a, int N, bool interp
     }
 }
 
-template <typename R, int N, int TMAX, bool GX>
-static hipError_t sk_adj_g(const AdjArgs<R>& a, int64_t npairs, int ring, hipStream_t st) {
-    constexpr int S = SkCkptStride<R>::value;
+template <typename R, int N, int TMAX, bool GX, int S>
+static hipError_t sk_adj_gs(const AdjArgs<R>& a, int64_t npairs, int ring, hipStream_t st) {
     size_t lds = SkLaunch<R>::adjoint_lds(N, ring);
     if constexpr (sk_adj_two_waves<R, N, TMAX, GX>())
         hipLaunchKernelGGL((k_adjoint_w2<R, N, TMAX, S, GX>), dim3((unsigned)npairs), dim3(64), lds,
@@ -277,6 +297,15 @@ static hipError_t sk_adj_g(const AdjArgs<R>& a, int64_t npairs, int ring, hipStr
                            st, a);
     SK_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+template <typename R, int N, int TMAX, bool GX>
+static hipError_t sk_adj_g(const AdjArgs<R>& a, int64_t npairs, int ring, hipStream_t st) {
+    constexpr int S = SkCkptStride<R>::value;
+    if constexpr (sk_alt_stride<R>())
+        if (a.S == 2) return sk_adj_gs<R, N, TMAX, GX, 2>(a, npairs, ring, st);
+    if (a.S != S) return hipErrorInvalidValue;
+    return sk_adj_gs<R, N, TMAX, GX, S>(a, npairs, ring, st);
 }
 
 template <typename R, int N, int TMAX>
