@@ -74,6 +74,15 @@ __host__ __device__ constexpr int sk_gx_words(int N, int es) {
                                                              : (N + 1) * es / 4 + 1) + 3) / 4 * 4;
 }
 __host__ __device__ constexpr int sk_gx_stage_bytes(int N, int es) { return SK_GX_BLOCK * sk_gx_words(N, es) * 4; }
+// The batched adjoint stages, one checkpoint segment ahead, the strip-boundary
+// edges its lane 0 replays at steps 1..S-1 of a segment, for strides S <= 4:
+// per step the coefficients 0..N, then the exponent in the last word (N + 2
+// words in FP32; 2N + 4 in FP64, an even count that keeps every step's
+// coefficients 8-byte aligned); rounded up to 16 bytes.
+__host__ __device__ constexpr int sk_adj_qst_words(int N, int es) { return (N + 1) * es / 4 + (es == 8 ? 2 : 1); }
+__host__ __device__ constexpr int sk_adj_qst_bytes(int N, int es) {
+    return (3 * sk_adj_qst_words(N, es) * 4 + 15) / 16 * 16;
+}
 
 // Local steps of one strip on the strip pipeline: lane r processes column
 // t - r at local step t, so lane 63 finishes the last column at step

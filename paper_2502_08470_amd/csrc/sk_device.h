@@ -57,6 +57,18 @@ template <> struct SkTailReg<double> { static constexpr int value = 6; };
 static __device__ unsigned sk_status_word;
 __device__ __forceinline__ void sk_raise_status(unsigned bit) { atomicOr(&sk_status_word, bit); }
 
+// Streaming accesses: data written once and read once by a later kernel
+// (checkpoints, skewed dL/dc), far larger than the caches, bypass their
+// retention with non-temporal loads and stores.
+template <typename T>
+__device__ __forceinline__ void sk_st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
+template <typename T>
+__device__ __forceinline__ T sk_ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
+
+// A pointer into LDS (address space 3): its arithmetic is 32-bit, where a
+// generic pointer's would be 64-bit with an unused high half.
+template <typename T> using SkLds = __attribute__((address_space(3))) T*;
+
 // Kernel-argument tables of the interpolation scheme.
 template <typename R>
 struct SkTab {

@@ -815,10 +815,10 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                 R* ck = a.ck + pd.ck_off + kk * 2 * (N + 1) * 64;
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
-                    ck[n * 64 + r] = P[n];
-                    ck[(N + 1 + n) * 64 + r] = Qin[n];
+                    sk_st_nt(ck + n * 64 + r, P[n]);
+                    sk_st_nt(ck + (N + 1 + n) * 64 + r, Qin[n]);
                 }
-                a.ce[pd.ce_off + kk * (SK_LANES + 1) + r] = E;
+                sk_st_nt(a.ce + pd.ce_off + kk * (SK_LANES + 1) + r, E);
             }
             R Po[N + 1], Qo[N + 1];
             double Po0, Po1, Qo0, Qo1;
@@ -1258,8 +1258,11 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     const bool gx = GX && g.ly > a.gx_cols;  // wave-uniform
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
-    R* llds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES));
-    int* ltag = reinterpret_cast<int*>(llds + (size_t)g.ly * (N + 1));
+    // boundary edges lane 0 replays at steps 1..S-1 of the current segment
+    // (LDS-typed pointers: 32-bit address arithmetic)
+    SkLds<unsigned> qst = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES));
+    SkLds<R> llds = (SkLds<R>)(sk_smem + sk_gx_stage_bytes(N, ES) + sk_adj_qst_bytes(N, ES));
+    SkLds<int> ltag = (SkLds<int>)(llds + g.ly * (N + 1));
     unsigned* xg = a.xb + pd.xb_off;
     unsigned xr[(8 * GXW + 63) / 64];
 #pragma unroll
@@ -1288,6 +1291,48 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
     // tail rows whose derivatives a replayed step keeps; segments with a
     // longer tail take the slow path below
     constexpr int TR = TMAX > 0 ? SkTailReg<R>::value : 0;
+    // Inputs of a checkpoint segment are loaded one segment ahead (PF: the
+    // stride-4 kernels, whose registers allow two waves per SIMD only, so
+    // memory latency is not hidden by other waves): the segment's cell
+    // constants at the top of the previous segment, the lane state, its
+    // exponent and one word per lane of the boundary edges lane 0 reads at
+    // steps 1..S-1 (plus, in lane TWL, the tail-length word) once the
+    // previous segment's replay no longer needs its own.  The boundary edges
+    // go through LDS, so no load is waited for inside a segment.
+    constexpr bool PF = S >= 4;
+    constexpr int QW = sk_adj_qst_words(N, ES), TWL = (S - 1) * QW;
+    static_assert(!PF || (S <= 4 && TWL < 64), "staged boundary edges exceed one word per lane");
+    R pfP[N + 1], pfQ[N + 1], pfc[S];
+    int pfE = 0;
+    unsigned pfq = 0u;
+    auto prefetch_c = [&](int kk) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) pfc[u] = cs[(int64_t)(kk * S + u) * 64 + r];
+    };
+    auto prefetch_state = [&](int kk) {
+        const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
+#pragma unroll
+        for (int n = 0; n <= N; ++n) {
+            pfP[n] = sk_ld_nt(ck + n * 64 + r);
+            pfQ[n] = sk_ld_nt(ck + (N + 1 + n) * 64 + r);
+        }
+        pfE = sk_ld_nt(a.ce + pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r);
+        // word w of the edge lane 0 takes at step u (live, strips >= 1)
+        pfq = 0u;
+        if (r < TWL) {
+            const int u = 1 + r / QW, w = r - (u - 1) * QW;
+            const int L0 = kk * S + u, s0 = L0 / g.Tp, j0 = L0 - s0 * g.Tp;
+            if (s0 >= 1 && s0 < g.nstrips && j0 < g.ly && s0 * 64 < g.lx) {
+                const int64_t o = (int64_t)s0 * g.ly + j0;
+                if (w < (N + 1) * (ES / 4))
+                    pfq = reinterpret_cast<const unsigned*>(a.qb + pd.qb_off + o * (N + 1))[w];
+                else if (w == QW - 1)
+                    pfq = (unsigned)a.qe[pd.qe_off + o];
+            }
+        } else if (TMAX > 0 && r == TWL) {
+            pfq = (unsigned)a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + SK_LANES];
+        }
+    };
     // Inputs of replayed step u of a segment: the bottom edge P (this lane's
     // state) and the left edge Qin (from lane r-1, or the strip boundary /
     // the initial edge for lane 0), aligned to a common exponent E.  Step 0
@@ -1315,6 +1360,11 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
 #pragma unroll
                     for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
                     Ein = 0;
+                } else if (PF) {
+                    const SkLds<unsigned> q = qst + (u - 1) * QW;
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) Qin[n] = ((SkLds<R>)q)[n];
+                    Ein = (int)q[QW - 1];
                 } else {
                     const int64_t o = (int64_t)s * g.ly + j;
 #pragma unroll
@@ -1357,7 +1407,7 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 El_recv = (int)rec[(N + 1) * (ES / 4)];
             } else {
 #pragma unroll
-                for (int n = 0; n <= N; ++n) lq_recv[n] = llds[jj * (N + 1) + n];
+                for (int n = 0; n <= N; ++n) lq_recv[n] = llds[__mul24(jj, N + 1) + n];
                 El_recv = ltag[jj];
             }
         }
@@ -1414,11 +1464,11 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 rec[(N + 1) * (ES / 4)] = (unsigned)Ec;
             } else {
 #pragma unroll
-                for (int n = 0; n <= N; ++n) llds[jj * (N + 1) + n] = lqs[n];
+                for (int n = 0; n <= N; ++n) llds[__mul24(jj, N + 1) + n] = lqs[n];
                 ltag[jj] = Ec;
             }
         }
-        gs[(int64_t)tau * 64 + r] = live ? sk_ldexp(gv, Ec + Eu) : (R)0;
+        sk_st_nt(gs + (int64_t)tau * 64 + r, live ? sk_ldexp(gv, Ec + Eu) : (R)0);
         if ((tau & 7) == 0 && live) {
             R m = (R)0;
 #pragma unroll
@@ -1439,6 +1489,10 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             }
         }
     };
+    if (PF) {
+        prefetch_c(nck - 1);
+        prefetch_state(nck - 1);
+    }
     for (int kk = nck - 1; kk >= 0; --kk) {
         const int tau0 = kk * S;
         // blocks of 8 steps, processed from the top; a segment never
@@ -1446,12 +1500,24 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
         if (gx && (kk == nck - 1 || ((tau0 + S) & 7) == 0))
             sk_gx_stage<GXW>(xr, stage, xg, (tau0 & ~7) - 8, r, lane63_col);
         const R* ck = a.ck + pd.ck_off + (int64_t)kk * 2 * (N + 1) * 64;
-        const int E0 = a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r];
-        // tail lengths the forward folded at the segment's steps
-        const unsigned tword =
-            TMAX > 0 ? (unsigned)__builtin_amdgcn_readfirstlane(
-                           a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + SK_LANES])
-                     : 0u;
+        R cseg[S];
+        int E0;
+        unsigned tword = 0u;  // tail lengths the forward folded at the segment's steps
+        if (PF) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) cseg[u] = pfc[u];
+            E0 = pfE;
+            if (TMAX > 0) tword = (unsigned)__builtin_amdgcn_readlane((int)pfq, TWL);
+            // this segment's boundary edges into LDS (the wave's own earlier
+            // LDS reads of the previous segment's are ordered before)
+            if (r < TWL) qst[r] = pfq;
+            if (kk > 0) prefetch_c(kk - 1);
+        } else {
+            E0 = sk_ld_nt(a.ce + pd.ce_off + (int64_t)kk * (SK_LANES + 1) + r);
+            if (TMAX > 0)
+                tword = (unsigned)__builtin_amdgcn_readfirstlane(
+                    a.ce[pd.ce_off + (int64_t)kk * (SK_LANES + 1) + SK_LANES]);
+        }
         unsigned tseg = 0u;  // longest tail of the segment (wave-uniform)
 #pragma unroll
         for (int u = 0; u < S; ++u) {
@@ -1459,9 +1525,6 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             tseg = tu > tseg ? tu : tseg;
         }
         if (TMAX == 0 || tseg <= (unsigned)TR) {
-            R cseg[S];
-#pragma unroll
-            for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
             // ---- replay the segment's forward from the checkpoint, recording
             // each cell's row derivatives, kept tail length and exponent
             constexpr int M = N + TR;
@@ -1469,12 +1532,16 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             int Tst[S], Est[S];
             bool lv[S];
             int sst[S], jst[S];
+            if (!PF) {
+#pragma unroll
+                for (int u = 0; u < S; ++u) cseg[u] = cs[(int64_t)(tau0 + u) * 64 + r];
+            }
             int E = E0;
             R P[N + 1], Qs[N + 1];
 #pragma unroll
             for (int n = 0; n <= N; ++n) {
-                P[n] = ck[n * 64 + r];
-                Qs[n] = ck[(N + 1 + n) * 64 + r];
+                P[n] = PF ? pfP[n] : sk_ld_nt(ck + n * 64 + r);
+                Qs[n] = PF ? pfQ[n] : sk_ld_nt(ck + (N + 1 + n) * 64 + r);
             }
             int Es = E;
             int L = tau0 - r, s = 0, j = 0;
@@ -1510,6 +1577,8 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 }
                 ++L;
             }
+            // the next segment's state loads while this one's adjoint runs
+            if (PF && kk > 0) prefetch_state(kk - 1);
             // ---- adjoint steps in reverse
 #pragma unroll
             for (int u = S - 1; u >= 0; --u)
@@ -1567,6 +1636,7 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                     sk_cell_adj_in<R, N, TMAX>(cu, Tu, a.tab, ap, aq, P, Qin, lp, lqs, gv);
                 });
             }
+            if (PF && kk > 0) prefetch_state(kk - 1);
         }
     }
 }

@@ -81,6 +81,7 @@ struct SkLaunch {
     }
     static size_t adjoint_lds(int N, int ring) {
         return (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)) +
+               (size_t)sk_adj_qst_bytes(N, (int)sizeof(R)) +
                (size_t)ring * sk_ring_col_bytes_adj(N, (int)sizeof(R));
     }
     static size_t gram_lds(int dpad) { return (size_t)(192 * (dpad + 1) + 64 * 66) * sizeof(R); }
