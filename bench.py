@@ -109,7 +109,7 @@ def kernel_source_hash() -> str:
 
 def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
     """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs of
-    `bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain --calibrate-copy 1024`.
+    `bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain --no-tune --calibrate-copy 1024`.
     Each counter is scaled by bytes / counter-KiB of the largest device copy
     dispatch (the 1 GiB calibration copy: 1 GiB read, 1 GiB written)."""
     import csv
@@ -143,10 +143,10 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_json: str) -> int:
                            "fetch_bytes_per_unit": fscale, "write_bytes_per_unit": wscale},
            # the commands, with the output folders of the two runs as given
            "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {rel(os.path.dirname(fetch_csv))} -o fetch -f csv -- "
-                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
+                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain --no-tune "
                         f"--calibrate-copy {CALIBRATE_MIB}",
                         f"rocprofv3 --pmc WRITE_SIZE -d {rel(os.path.dirname(write_csv))} -o write -f csv -- "
-                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain "
+                        "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-plain --no-tune "
                         f"--calibrate-copy {CALIBRATE_MIB}",
                         f"python3 bench.py --pmc-summary {rel(fetch_csv)} {rel(write_csv)} {rel(out_json)}"],
            "kernels": kernels}
