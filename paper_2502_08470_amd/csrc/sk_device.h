@@ -207,6 +207,7 @@ __device__ __forceinline__ bool sk_wave_any(bool v) { return __any(v ? 1 : 0) !=
 // a replay repeats the decisions of the forward it replays.
 // DS: element stride of DP and DQ (1 for registers; 64 for an LDS array with
 // one slot per lane).
+// Wout (nullable): receives w_m = c^m/m!, m = 1..N (as the rows used them).
 template <typename R, int N, int TMAX, bool WD = false, bool HI = true, bool FIXT = false,
           int DS = 1>
 __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N + 1], double P0,
@@ -214,7 +215,8 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
                                             const SkTab<R>& tab, R (&Po)[N + 1], R (&Qo)[N + 1],
                                             double& Po0, double& Po1, double& Qo0, double& Qo1,
                                             R* DP = nullptr, R* DQ = nullptr,
-                                            int* Tkept = nullptr, int Tfix = 0) {
+                                            int* Tkept = nullptr, int Tfix = 0,
+                                            R* Wout = nullptr) {
     // tail rows unrolled with constant indices (the rest in a loop)
     constexpr int TU = TMAX < SkTailReg<R>::value ? TMAX : SkTailReg<R>::value;
     // rows up to N + TU in the unrolled part (+1 that only decides, when
@@ -228,13 +230,25 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
     cp[0] = (R)1;
     // the sweep's state takes c^m/m! by its own recurrence (independent
     // rounding of the Toeplitz and Hankel parts measured about twice as
-    // accurate); where FP32 accuracy is enough one multiply does
+    // accurate).  Where FP32 accuracy is enough (!HI) the rows up to N need no
+    // c^m: their Hankel sums are taken against r!/(r+k)!, so that
+    // c^r sum_k Q'_k/(r+k)! = w_r sum_k Q'_k r!/(r+k)!, and the tail rows
+    // start c^m from w_N N!.
     auto power = [&](int m) {
+        if (!HI && m <= N) {
+            w[m] = m == 1 ? c : w[m - 1] * (c * (R)(1.0 / m));
+            return;
+        }
+        if (!HI && m == N + 1) cp[N] = w[N] * (R)(1.0 / sk_inv_fact(N));
         cp[m] = cp[m - 1] * c;
         w[m] = HI ? w[m - 1] * (c * (R)(1.0 / m)) : cp[m] * ifact<R>(m);
     };
 #pragma unroll
     for (int m = 1; m <= MU; ++m) power(m);
+    if (Wout) {  // c^m/m!, m = 1..N, for the adjoint of the same cell
+#pragma unroll
+        for (int m = 1; m <= N; ++m) Wout[m - 1] = w[m];
+    }
     if (WD && !FIXT) {
         // rows 0..N-1 are always written; tail rows only when kept (a replay
         // with the tail length given reads exactly the rows it folds)
@@ -300,13 +314,18 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
         R hq = (R)0, hp = (R)0;
 #pragma unroll
         for (int k = N; k >= 1; --k) {
-            hq = fma(Q[k], ifact<R>(r + k), hq);
-            hp = fma(P[k], ifact<R>(r + k), hp);
+            // HI: 1/(r+k)!;  !HI: r!/(r+k)! (see power)
+            const R f = HI ? ifact<R>(r + k) : (R)(sk_inv_fact(r + k) / sk_inv_fact(r));
+            hq = fma(Q[k], f, hq);
+            hp = fma(P[k], f, hp);
         }
-        Po[r] = fma(cp[r], hq, tp);
-        Qo[r] = fma(cp[r], hp, tq);
+        // Hankel weight of row r, c^r (HI) or w_r; of its c-derivative,
+        // r c^(r-1) (HI) or w_(r-1) (since r c^(r-1) / r! = w_(r-1))
+        const R hw = HI ? cp[r] : w[r];
+        Po[r] = fma(hw, hq, tp);
+        Qo[r] = fma(hw, hp, tq);
         if (WD) {
-            const R rc = (R)r * cp[r - 1];
+            const R rc = HI ? (R)r * cp[r - 1] : w[r - 1];
             DP[(r - 1) * DS] = fma(rc, hq, tpp);
             DQ[(r - 1) * DS] = fma(rc, hp, tqp);
             tpp = tp;
@@ -463,20 +482,27 @@ __device__ __forceinline__ void sk_cell_fwd(const R (&P)[N + 1], const R (&Q)[N 
 // order, so no per-row arrays stay live:
 //   aP_k += w_{r-k} ea_r (k <= min(r, N)),  aP_k += c^r eb_r / (r+k)! (k >= 1),
 // with ea_r = a_r for r <= N and ea_r = sum_n Rs[n][r] a_n for tail rows.
+// The rows up to N take their Hankel part as w_r eb_r against r!/(r+k)!
+// (c^r/(r+k)! = w_r r!/(r+k)!), so they need only w_m = c^m/m!, which the
+// forward replay of the same cell can hand over (Wpre, nullable: m = 1..N);
+// tail rows continue c^m from w_N N!.
 template <typename R, int N, int TMAX, int DS = 1>
 __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, const R (&a)[N + 1],
                                             const R (&b)[N + 1], const R* DP, const R* DQ,
-                                            R (&aP)[N + 1], R (&aQ)[N + 1], R& g) {
+                                            R (&aP)[N + 1], R (&aQ)[N + 1], R& g,
+                                            const R* Wpre = nullptr) {
     constexpr int M = N + TMAX;
     R w[M + 1], cp[M + 1];
     w[0] = (R)1;
     cp[0] = (R)1;
     auto power = [&](int m) {
+        if (m == N + 1) cp[N] = w[N] * (R)(1.0 / sk_inv_fact(N));
         cp[m] = cp[m - 1] * c;
         w[m] = cp[m] * ifact<R>(m);  // gradients need FP32 accuracy only
     };
 #pragma unroll
-    for (int m = 1; m <= N; ++m) power(m);  // tail rows compute theirs as they go
+    for (int m = 1; m <= N; ++m)  // tail rows compute theirs as they go
+        w[m] = Wpre ? Wpre[m - 1] : (m == 1 ? c : w[m - 1] * (c * (R)(1.0 / m)));
     // row 0 initialises the outputs (w_0 = c^0 = 1)
     aP[0] = a[0];
     aQ[0] = b[0];
@@ -513,11 +539,13 @@ __device__ __forceinline__ void sk_cell_adj(R c, int T, const SkTab<R>& tab, con
             aP[k] = fma(w[r - k], ea, aP[k]);
             aQ[k] = fma(w[r - k], eb, aQ[k]);
         }
-        const R cb = cp[r] * eb, ca = cp[r] * ea;
+        const R hw = r <= N ? w[r] : cp[r];
+        const R cb = hw * eb, ca = hw * ea;
 #pragma unroll
         for (int k = 1; k <= N; ++k) {
-            aP[k] = fma(cb, ifact<R>(r + k), aP[k]);
-            aQ[k] = fma(ca, ifact<R>(r + k), aQ[k]);
+            const R f = r <= N ? (R)(sk_inv_fact(r + k) / sk_inv_fact(r)) : ifact<R>(r + k);
+            aP[k] = fma(cb, f, aP[k]);
+            aQ[k] = fma(ca, f, aQ[k]);
         }
     }
     g = gacc;

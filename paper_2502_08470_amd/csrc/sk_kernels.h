@@ -1529,6 +1529,7 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
             // each cell's row derivatives, kept tail length and exponent
             constexpr int M = N + TR;
             R Dp[S][M], Dq[S][M];
+            R Wst[S][N];  // c^m/m! of each step, kept for its adjoint (PF only)
             int Tst[S], Est[S];
             bool lv[S];
             int sst[S], jst[S];
@@ -1562,7 +1563,8 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
                 Tst[u] = (int)((tword >> (8 * u)) & 0xffu);
                 sk_cell_fwd<R, N, TR, true, false, true>(P, Qin, 0.0, 0.0, 0.0, 0.0, cseg[u], live,
                                                          a.tab, Po, Qo, Po0, Po1, Qo0, Qo1, Dp[u],
-                                                         Dq[u], nullptr, Tst[u]);
+                                                         Dq[u], nullptr, Tst[u],
+                                                         PF ? Wst[u] : nullptr);
 #pragma unroll
                 for (int n = 0; n <= N; ++n) {
                     P[n] = Po[n];
@@ -1583,7 +1585,8 @@ __device__ __forceinline__ void sk_adjoint_body(const AdjArgs<R>& a) {
 #pragma unroll
             for (int u = S - 1; u >= 0; --u)
                 adj_step(u, tau0, lv[u], sst[u], jst[u], Est[u], [&](R (&ap)[N + 1], R (&aq)[N + 1], R& gv) {
-                    sk_cell_adj<R, N, TR>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv);
+                    sk_cell_adj<R, N, TR>(cseg[u], Tst[u], a.tab, ap, aq, Dp[u], Dq[u], lp, lqs, gv,
+                                          PF ? Wst[u] : nullptr);
                 });
         } else {
             // ---- slow path (a tail longer than TR rows in this segment):
