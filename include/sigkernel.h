@@ -412,6 +412,27 @@ int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32
                               hipStream_t stream);
 
 /*
+ * Unbiased (U-statistic) MMD^2 between path sets X (nx paths) and Y (ny
+ * paths) from the kernel values of one pair list, as sigkernel_pairs
+ * computes it: k holds first the nx(nx-1)/2 pairs a < b of X, then the
+ * ny(ny-1)/2 pairs a < b of Y, then the nx*ny pairs of X with Y (each group
+ * in any order).  Since k is symmetric and the within-set diagonals are left
+ * out, MMD^2 = 2/(nx(nx-1)) sum_XX k + 2/(ny(ny-1)) sum_YY k
+ * - 2/(nx ny) sum_XY k; the sums are accumulated in FP64 (the statistic of
+ * sigkernel_mmd_permutation, for the observed split, from a pair list).
+ *   k: device, dtype SK_F32 or SK_F64; out: device, one element of dtype.
+ * sigkernel_mmd2_pairs_backward writes gk[i] = dMMD^2/dk_i * gout[0] over the
+ * same pair list (gout: device, one element of dtype; gk: device, as k).
+ * Both only queue one kernel on `stream`; the caller owns every buffer.
+ * Errors: SK_EINVAL for nx < 2, ny < 2, a NULL pointer or a bad dtype;
+ * SK_EUNSUPPORTED above 2^24 paths in a set.
+ */
+int sigkernel_mmd2_pairs(const void* k, int64_t nx, int64_t ny, int32_t dtype, void* out,
+                         hipStream_t stream);
+int sigkernel_mmd2_pairs_backward(const void* gout, int64_t nx, int64_t ny, int32_t dtype, void* gk,
+                                  hipStream_t stream);
+
+/*
  * Forward and backward of a Gram call with the backward's state kept in
  * between (trading memory for the recomputation sigkernel_backward does).
  * sigkernel_gram_save computes K (and K_exp) like sigkernel_gram with the

@@ -49,6 +49,8 @@ EXPORTS = (
     "sigkernel_plan_configure",
     "sigkernel_plan_destroy",
     "sigkernel_mmd_permutation",
+    "sigkernel_mmd2_pairs",
+    "sigkernel_mmd2_pairs_backward",
     "sigkernel_status",
     "sigkernel_set_spin_limit",
     "sigkernel_interp_table",
@@ -164,6 +166,9 @@ def lib():
     L.sigkernel_plan_destroy.restype = None
     L.sigkernel_mmd_permutation.argtypes = [vp, i64, i64, vp, i64, i32, vp, vp, vp]
     L.sigkernel_mmd_permutation.restype = ctypes.c_int
+    for name in ("sigkernel_mmd2_pairs", "sigkernel_mmd2_pairs_backward"):
+        getattr(L, name).argtypes = [vp, i64, i64, i32, vp, vp]
+        getattr(L, name).restype = ctypes.c_int
     L.sigkernel_status.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32)]
     L.sigkernel_status.restype = ctypes.c_int
     L.sigkernel_set_spin_limit.argtypes = [i32]

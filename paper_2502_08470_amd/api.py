@@ -52,6 +52,14 @@ def _stream(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.SK_F32
+    if t.dtype == torch.float64:
+        return L.SK_F64
+    raise L.SigKernelError(L.SK_EINVAL, f"dtype {t.dtype}: float32 or float64 expected")
+
+
 def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
@@ -636,32 +644,52 @@ def sig_pairs(A, B, scheme: str = "approx", order: int = 4, pipeline: bool = Fal
     return SigKernelPairs.apply(A, B, scheme, order, pipeline, dyadic, sweep)
 
 
+class MMD2Pairs(torch.autograd.Function):
+    """Unbiased MMD^2 from the kernel values of a [XX pairs a < b | YY pairs
+    a < b | XY pairs] list (sigkernel_mmd2_pairs; FP64 accumulation), and its
+    derivative with respect to those values (sigkernel_mmd2_pairs_backward)."""
+
+    @staticmethod
+    def forward(ctx, k, nx, ny):
+        k = k.contiguous()
+        out = torch.empty(1, dtype=k.dtype, device=k.device)
+        L.check(L.lib().sigkernel_mmd2_pairs(_ptr(k), nx, ny, _dt(k), _ptr(out), _stream(k)))
+        ctx.nx, ctx.ny, ctx.shape = nx, ny, k.shape
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.reshape(1).contiguous()
+        gk = torch.empty(ctx.shape, dtype=g.dtype, device=g.device)
+        L.check(L.lib().sigkernel_mmd2_pairs_backward(_ptr(g), ctx.nx, ctx.ny, _dt(g), _ptr(gk),
+                                                      _stream(g)))
+        return gk, None, None
+
+
 def mmd2(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx", order: int = 4,
          gram_mode: str = "native", sweep: str = "native") -> torch.Tensor:
     """Unbiased (U-statistic) squared MMD between path sets X and Y, with the
-    within-sample diagonals excluded; differentiable in X and Y.  Native Gram
-    arithmetic with equal path lengths: the pairs a < b of each set and all
-    cross pairs, in one pair list (k is symmetric, and the diagonal pairs do
-    not enter), otherwise three Gram matrices.  ``sweep`` "f64" sweeps
-    float32 paths in FP64 (the statistic is a difference of nearly equal
-    means, so its gradient loses digits the FP32 state cannot spare)."""
+    within-sample diagonals excluded; differentiable in X and Y.  The kernel
+    values of the pairs a < b of each set and of all cross pairs (k is
+    symmetric, and the diagonal pairs do not enter) go to the library's
+    MMD^2 kernel.  Native Gram arithmetic with equal path lengths computes
+    them as one pair list, otherwise they are taken from three Gram
+    matrices.  ``sweep`` "f64" sweeps float32 paths in FP64 (the statistic
+    is a difference of nearly equal means, so its gradient loses digits the
+    FP32 state cannot spare)."""
     n, m = X.shape[0], Y.shape[0]
+    ia, ib = torch.triu_indices(n, n, 1, device=X.device)
+    ja, jb = torch.triu_indices(m, m, 1, device=Y.device)
     if gram_mode == "native" and X.shape[1] == Y.shape[1] and scheme not in ("fd", "fd2"):
-        ia, ib = torch.triu_indices(n, n, 1, device=X.device)
-        ja, jb = torch.triu_indices(m, m, 1, device=Y.device)
         A = torch.cat([X[ia], Y[ja], X.repeat_interleave(m, 0)], 0)
         B = torch.cat([X[ib], Y[jb], Y.repeat(n, 1, 1)], 0)
         k = sig_pairs(A, B, scheme, order, sweep=sweep)
-        nxx, nyy = ia.numel(), ja.numel()
-        sxx = 2.0 * k[:nxx].sum() / (n * (n - 1))
-        syy = 2.0 * k[nxx:nxx + nyy].sum() / (m * (m - 1))
-        return sxx + syy - 2.0 * k[nxx + nyy:].mean()
-    Kxx = sig_gram(X, X, scheme, order, gram_mode, sweep=sweep)
-    Kyy = sig_gram(Y, Y, scheme, order, gram_mode, sweep=sweep)
-    Kxy = sig_gram(X, Y, scheme, order, gram_mode, sweep=sweep)
-    sxx = (Kxx.sum() - torch.diagonal(Kxx).sum()) / (n * (n - 1))
-    syy = (Kyy.sum() - torch.diagonal(Kyy).sum()) / (m * (m - 1))
-    return sxx + syy - 2.0 * Kxy.mean()
+    else:
+        Kxx = sig_gram(X, X, scheme, order, gram_mode, sweep=sweep)
+        Kyy = sig_gram(Y, Y, scheme, order, gram_mode, sweep=sweep)
+        Kxy = sig_gram(X, Y, scheme, order, gram_mode, sweep=sweep)
+        k = torch.cat([Kxx[ia, ib], Kyy[ja, jb], Kxy.reshape(-1)])
+    return MMD2Pairs.apply(k, n, m)
 
 
 def mmd_permutation_test(X: torch.Tensor, Y: torch.Tensor, scheme: str = "approx",

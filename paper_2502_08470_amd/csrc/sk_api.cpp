@@ -2533,6 +2533,56 @@ int sigkernel_mmd_permutation(const void* Kzz, int64_t m, int64_t n, const int32
     }
 }
 
+static int check_mmd2(int64_t nx, int64_t ny, int32_t dtype, const void* a, const void* b) {
+    if (dtype != SK_F32 && dtype != SK_F64) return fail(SK_EINVAL, "dtype %d", dtype);
+    if (nx < 2 || ny < 2)
+        return fail(SK_EINVAL, "each set needs at least 2 paths (nx=%lld, ny=%lld)", (long long)nx,
+                    (long long)ny);
+    if (nx > (1 << 24) || ny > (1 << 24)) return fail(SK_EUNSUPPORTED, "set above 2^24 paths");
+    if (!a || !b) return fail(SK_EINVAL, "NULL pointer");
+    return SK_OK;
+}
+
+int sigkernel_mmd2_pairs(const void* k, int64_t nx, int64_t ny, int32_t dtype, void* out,
+                         hipStream_t stream) {
+    g_last_error.clear();
+    if (int rc = check_mmd2(nx, ny, dtype, k, out)) return rc;
+    try {
+        if (dtype == SK_F32)
+            SK_LAUNCH("mmd2", stream,
+                      SkLaunch<float>::mmd2_pairs((const float*)k, nx, ny, (float*)out, stream),
+                      "MMD^2 of a pair list");
+        else
+            SK_LAUNCH("mmd2", stream,
+                      SkLaunch<double>::mmd2_pairs((const double*)k, nx, ny, (double*)out, stream),
+                      "MMD^2 of a pair list");
+        return SK_OK;
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
+int sigkernel_mmd2_pairs_backward(const void* gout, int64_t nx, int64_t ny, int32_t dtype, void* gk,
+                                  hipStream_t stream) {
+    g_last_error.clear();
+    if (int rc = check_mmd2(nx, ny, dtype, gout, gk)) return rc;
+    try {
+        if (dtype == SK_F32)
+            SK_LAUNCH("mmd2", stream,
+                      SkLaunch<float>::mmd2_pairs_seed((const float*)gout, nx, ny, (float*)gk,
+                                                       stream),
+                      "MMD^2 seeds");
+        else
+            SK_LAUNCH("mmd2", stream,
+                      SkLaunch<double>::mmd2_pairs_seed((const double*)gout, nx, ny, (double*)gk,
+                                                        stream),
+                      "MMD^2 seeds");
+        return SK_OK;
+    } catch (...) {
+        return fail(SK_EINVAL, "internal exception");
+    }
+}
+
 size_t sigkernel_gram_state_size(int64_t nx, int64_t lx_pts, int64_t ny, int64_t ly_pts, int64_t d,
                                  const sk_params* p) {
     g_last_error.clear();

@@ -2561,6 +2561,54 @@ __global__ __launch_bounds__(256) void k_mmd_perm(const R* K, int64_t m, int64_t
     if (threadIdx.x == 0) stats[p] = (R)red[0];
 }
 
+// Unbiased MMD^2 of two path sets X (nx paths) and Y (ny paths) from the
+// kernel values of one pair list: [pairs a < b of X][pairs a < b of Y][all
+// X x Y pairs].  The within-set diagonals do not enter and k is symmetric, so
+// each within-set pair stands for two entries of its Gram matrix:
+//   MMD^2 = 2/(nx(nx-1)) sum_xx k + 2/(ny(ny-1)) sum_yy k - 2/(nx ny) sum_xy k.
+// One workgroup, FP64 accumulation.
+__host__ __device__ inline void sk_mmd2_weights(int64_t nx, int64_t ny, double* wxx, double* wyy,
+                                                double* wxy) {
+    *wxx = 2.0 / ((double)nx * (double)(nx - 1));
+    *wyy = 2.0 / ((double)ny * (double)(ny - 1));
+    *wxy = -2.0 / ((double)nx * (double)ny);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_mmd2_pairs(const R* k, int64_t nx, int64_t ny, R* out) {
+    __shared__ double red[256];
+    double wxx, wyy, wxy;
+    sk_mmd2_weights(nx, ny, &wxx, &wyy, &wxy);
+    const int64_t nxx = nx * (nx - 1) / 2, nyy = ny * (ny - 1) / 2, tot = nxx + nyy + nx * ny;
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) {
+        const double v = (double)k[i];
+        if (i < nxx) sxx += v;
+        else if (i < nxx + nyy) syy += v;
+        else sxy += v;
+    }
+    red[threadIdx.x] = wxx * sxx + wyy * syy + wxy * sxy;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (R)red[0];
+}
+
+// Its derivative: gk[i] = dMMD^2/dk_i * gout[0] over the same pair list.
+template <typename R>
+__global__ __launch_bounds__(256) void k_mmd2_pairs_seed(const R* gout, int64_t nx, int64_t ny,
+                                                         R* gk) {
+    double wxx, wyy, wxy;
+    sk_mmd2_weights(nx, ny, &wxx, &wyy, &wxy);
+    const int64_t nxx = nx * (nx - 1) / 2, nyy = ny * (ny - 1) / 2, tot = nxx + nyy + nx * ny;
+    const double g = (double)gout[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (int64_t)gridDim.x * blockDim.x)
+        gk[i] = (R)(g * (i < nxx ? wxx : i < nxx + nyy ? wyy : wxy));
+}
+
 // p-value of stats[0] (the observed split) against stats[1..]:
 // (1 + #{stats[q] >= stats[0], q >= 1}) / nperm, one workgroup.
 template <typename R>

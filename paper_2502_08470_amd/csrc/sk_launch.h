@@ -67,6 +67,9 @@ struct SkLaunch {
     static hipError_t plain_fd(const PlainArgs<R>& a, hipStream_t st);
     static hipError_t mmd_perm(const R* K, int64_t m, int64_t n, const int32_t* perms,
                                int64_t nperm, R* stats, double* pvalue, hipStream_t st);
+    // unbiased MMD^2 from a [xx | yy | xy] pair list, and its seeds
+    static hipError_t mmd2_pairs(const R* k, int64_t nx, int64_t ny, R* out, hipStream_t st);
+    static hipError_t mmd2_pairs_seed(const R* gout, int64_t nx, int64_t ny, R* gk, hipStream_t st);
     static hipError_t unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                              int64_t npairs, int64_t cells, hipStream_t st);
     // device address of the status word the kernels of this instantiation

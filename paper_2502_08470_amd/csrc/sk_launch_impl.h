@@ -455,6 +455,23 @@ hipError_t SkLaunch<R>::mmd_perm(const R* K, int64_t m, int64_t n, const int32_t
 }
 
 template <typename R>
+hipError_t SkLaunch<R>::mmd2_pairs(const R* k, int64_t nx, int64_t ny, R* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_mmd2_pairs<R>, dim3(1), dim3(256), 0, st, k, nx, ny, out);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t SkLaunch<R>::mmd2_pairs_seed(const R* gout, int64_t nx, int64_t ny, R* gk,
+                                        hipStream_t st) {
+    const int64_t tot = nx * (nx - 1) / 2 + ny * (ny - 1) / 2 + nx * ny;
+    const unsigned blocks = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_mmd2_pairs_seed<R>, dim3(blocks), dim3(256), 0, st, gout, nx, ny, gk);
+    SK_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename R>
 hipError_t SkLaunch<R>::unskew(const SkPairSrc& src, const R* cskew, R* C, int64_t first,
                                int64_t npairs, int64_t cells, hipStream_t st) {
     if (npairs <= 0 || cells <= 0) return hipSuccess;

@@ -212,6 +212,20 @@ def test_mmd_permutation_argument_errors():
     assert call(m=1 << 20, n=8) == L.SK_EUNSUPPORTED
 
 
+def test_mmd2_pairs_argument_errors():
+    lib = L.lib()
+    vp = ctypes.c_void_p
+    for fn in (lib.sigkernel_mmd2_pairs, lib.sigkernel_mmd2_pairs_backward):
+        def call(nx=4, ny=5, dtype=1, a=1, b=1):
+            return fn(vp(a), nx, ny, dtype, vp(b), None)
+        assert call(nx=1) == L.SK_EINVAL
+        assert call(ny=1) == L.SK_EINVAL
+        assert call(dtype=7) == L.SK_EINVAL
+        assert call(a=0) == L.SK_EINVAL
+        assert call(b=0) == L.SK_EINVAL
+        assert call(nx=(1 << 24) + 1) == L.SK_EUNSUPPORTED
+
+
 def test_pipeline_plan_grouping_and_workspace():
     # host-side plan build: pairs of several 64-row strips form one launch
     # group on the strip pipeline, the rest run batched; a backward plan keeps
