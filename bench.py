@@ -64,11 +64,14 @@ N_PATHS, STEPS, DIM = 128, 256, 8
 CPU_BLOCK = (48, 64)
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_batched_interp_gram_128x128.json")
 CALIBRATE_MIB = 1024
-# bench kernel label -> prefix of the kernel symbol
-KERNEL_SYMBOL = {"gram": "k_gram_direct<", "sweep": "k_sweep<", "sweep_ckpt": "k_sweep<",
-                 "adjoint": "k_adjoint<", "sweep_pipe": "k_sweep_pipe<",
-                 "sweep_ckpt_pipe": "k_sweep_pipe<", "adjoint_pipe": "k_adjoint_pipe<",
-                 "contract": "k_contract<", "reduce": "k_reduce"}
+# bench kernel label -> names of the kernels behind it (the adjoint has an
+# entry point that asks for two waves per SIMD, k_adjoint_w2)
+KERNEL_SYMBOL = {"gram": ("k_gram_direct",), "sweep": ("k_sweep",), "sweep_ckpt": ("k_sweep",),
+                 "adjoint": ("k_adjoint", "k_adjoint_w2"), "sweep_pipe": ("k_sweep_pipe",),
+                 "sweep_ckpt_pipe": ("k_sweep_pipe",),
+                 "adjoint_pipe": ("k_adjoint_pipe",),
+                 "contract": ("k_contract",),
+                 "reduce": ("k_reduce_gram_x", "k_reduce_gram_y", "k_reduce_pairs")}
 
 
 def template_args(symbol: str):
@@ -84,7 +87,7 @@ def symbol_matches(label: str, symbol: str, stride: int) -> bool:
     backward runs with checkpoint stride `stride` (k_sweep<R, N, TMAX, CKPT,
     S, GX>, k_sweep_pipe<R, N, TMAX, CKPT, S>, k_adjoint<R, N, TMAX, S, GX>,
     k_adjoint_pipe<R, N, TMAX, S>)."""
-    if not symbol.startswith("void " + KERNEL_SYMBOL[label]):
+    if not symbol.startswith("void ") or symbol[5:].split("<", 1)[0] not in KERNEL_SYMBOL[label]:
         return False
     a = template_args(symbol)
     if label in ("sweep", "sweep_pipe"):

@@ -114,4 +114,9 @@ def test_long_pairs_exponents_fp32(sk):
     m, e = oracle_gram(X.astype(np.float64), Y.astype(np.float64), "approx", 8)
     assert (e + np.log2(np.abs(m))).max() > 150  # 2^203: beyond FP32
     got = np.ldexp(K.cpu().double().numpy(), Ke.cpu().numpy() - e)
-    assert np.abs(got / m - 1).max() < 1e-3
+    # at the pair's FP32 conditioning floor (oracle vs its FP32 model,
+    # 6.9e-7 here): measured 10.7 times it
+    from oracle import c_oracle as C
+    mf, ef = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX_F32MODEL, 8)
+    floor = np.maximum(np.abs(np.ldexp(mf, ef - e) / m - 1), 1e-7)
+    assert (np.abs(got / m - 1) / floor).max() <= 30

@@ -11,6 +11,7 @@ Tolerances:
 import numpy as np
 import pytest
 
+from oracle import c_oracle as C
 from tests.gpu_common import bm_paths, log_banner, oracle_gram, rel_err, rel_err_exp
 
 torch = pytest.importorskip("torch")
@@ -74,9 +75,16 @@ def test_bf16x3_gram_matches_oracle_and_fp32(sk):
     m, e = oracle_gram(X.astype(np.float64), Y.astype(np.float64), "approx", 8)
     err3 = rel_err_exp(K3.cpu().numpy(), E3.cpu().numpy(), m, e)
     err1 = rel_err_exp(K1.cpu().numpy(), E1.cpu().numpy(), m, e)
-    # both within the FP32 conditioning floor of these pairs, and of the same size
-    assert err3.max() < 1e-3 and err1.max() < 1e-3, (err3.max(), err1.max())
-    assert err3.mean() < 3 * err1.mean() + 1e-6, (err3.mean(), err1.mean())
+    # each pair's FP32 conditioning floor: the oracle against its FP32 model
+    # (increments, cell constants and edge rows >= 2 rounded to FP32)
+    mf, ef = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX_F32MODEL, 8)
+    floor = np.maximum(rel_err_exp(mf, ef, m, e), 1e-7)
+    # both at the floor (measured: ratio median 2.1 / 1.0, max 72 / 61 for
+    # the split / FP32 Gram; floors up to 5e-5), and of the same size
+    for err in (err3, err1):
+        ratio = err / floor
+        assert np.median(ratio) <= 5 and ratio.max() <= 150, (np.median(ratio), ratio.max())
+    assert err3.mean() < 4 * err1.mean() + 1e-6, (err3.mean(), err1.mean())
 
 
 # ---------------------------------------------------------------------------
@@ -150,7 +158,11 @@ def test_fp32_exponent_tracking(sk):
     m, e = oracle_gram(X.astype(np.float64), Y.astype(np.float64), "approx", 8)
     assert (e + np.log2(np.abs(m))).max() > 200  # beyond FP32
     err = rel_err_exp(K.cpu().numpy(), Ke.cpu().numpy(), m, e)
-    assert err.max() < 1e-3, err.max()
+    # at the pairs' FP32 conditioning floor (oracle vs its FP32 model; here
+    # up to 6e-4): measured ratio median 2.1, max 9.9
+    mf, ef = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX_F32MODEL, 8)
+    ratio = err / np.maximum(rel_err_exp(mf, ef, m, e), 1e-7)
+    assert ratio.max() <= 30, ratio
 
 
 # ---------------------------------------------------------------------------

@@ -84,10 +84,13 @@ def test_pipeline_exponent_tracking_fp32(sk):
     assert int(Ep.cpu().numpy()[0, 0]) > 128
     assert np.array_equal(Kp.cpu().numpy(), Kb.cpu().numpy())
     assert np.array_equal(Ep.cpu().numpy(), Eb.cpu().numpy())
-    # the value (about -0.11 * 2^178) comes out of heavy cancellation, so the
-    # FP32 result is only a sanity check against the oracle
+    # the value (about -0.11 * 2^178) comes out of heavy cancellation: the
+    # FP32 result is held to the pair's FP32 conditioning floor (the oracle
+    # against its FP32 model, 1.6e-6 here; measured 0.5 times it)
     m, e = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX, 8)
-    assert rel_err_exp(Kp.cpu().numpy(), Ep.cpu().numpy(), m, e).max() < 1e-2
+    mf, ef = C.gram(X.astype(np.float64), Y.astype(np.float64), C.APPROX_F32MODEL, 8)
+    floor = np.maximum(rel_err_exp(mf, ef, m, e), 1e-7)
+    assert (rel_err_exp(Kp.cpu().numpy(), Ep.cpu().numpy(), m, e) / floor).max() <= 5
 
 
 def test_pipeline_hybrid_fp64(sk):
