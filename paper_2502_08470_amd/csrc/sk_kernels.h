@@ -2175,6 +2175,158 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
     }
 }
 
+// The same contraction on 16x16x4 MFMA tiles (FP32), for d up to 16 DB: it
+// is two matrix products per (pair, strip), dL/d(dx) (64 x d) += G (64 x ly)
+// dY (ly x d) and the strip's partial dL/d(dy) (ly x d) = G^T dX, with K = ly
+// and 64 respectively.  One workgroup (4 waves) per (pair, strip) walks the
+// columns in tiles of 64: the skewed rows of dL/dc are un-skewed into an LDS
+// ring G[64][128] by column (each skewed row is read once, coalesced; a tile
+// needs rows up to 63 past its last column, so the ring holds the tile and the
+// next one's leading part), the tile's y increments into LDS, and the next
+// tile's rows and increments are loaded into registers while the current
+// tile's MFMAs run.  Wave w owns rows 16w..16w+15 of dL/d(dx) (accumulated in
+// registers over the tiles) and columns 16w..16w+15 of each tile's dL/d(dy).
+#define SK_CMFMA_GS 132  // LDS row stride of the ring (2-way conflicts at most)
+template <int DB>
+__host__ __device__ constexpr int sk_cmfma_ds() { return 16 * DB + 4; }  // stride of dX / dY rows
+template <int DB>
+__host__ __device__ constexpr int sk_cmfma_lds() {
+    return (64 * SK_CMFMA_GS + 2 * 64 * sk_cmfma_ds<DB>()) * 4;
+}
+
+template <int DB>
+__global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float> a) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s = blockIdx.y;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    if (g.nsteps == 0 || s >= g.nstrips) return;
+    constexpr int DS = sk_cmfma_ds<DB>();
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    SkLds<float> G = (SkLds<float>)sk_smem;                 // [64][GS], column c at c & 127
+    SkLds<float> Yt = G + 64 * SK_CMFMA_GS;                 // [64][DS]: y increments of the tile
+    SkLds<float> Xs = Yt + 64 * DS;                         // [64][DS]: x increments of the strip
+    const int64_t ld = a.d;
+    const int d = (int)a.d, ly = g.ly;
+    const float* X = (pd.swap ? a.Y : a.X) + pd.x_off * ld;
+    const float* Y = (pd.swap ? a.X : a.Y) + pd.y_off * ld;
+    const int64_t tau0 = (int64_t)s * g.Tp;                  // skewed row of the strip's (0, 0)
+    const float* gsk = a.gskew + pd.c_off + tau0 * 64;
+    const int64_t rows_left = (int64_t)g.nsteps_pad - tau0;  // skewed rows of the pair from tau0
+    const int nrow = g.lx - s * 64 < 64 ? g.lx - s * 64 : 64;
+    // x increments of the strip's rows (zero past the last row and past d)
+    for (int e = tid; e < 64 * 16 * DB; e += 256) {
+        const int rr = e / (16 * DB), k = e - rr * (16 * DB);
+        float v = 0.0f;
+        if (rr < nrow && k < d) {
+            const int64_t i = (int64_t)s * 64 + rr;
+            v = X[(i + 1) * ld + k] - X[i * ld + k];
+        }
+        Xs[rr * DS + k] = v;
+    }
+    // registers of the next tile: skewed rows t0n + w + 4u (u < 16) at this
+    // lane, and y increments of its columns (value e = tid + 256 h of the
+    // tile's 64 x 16 DB block)
+    constexpr int YH = (64 * 16 * DB + 255) / 256;
+    float gr[16], yr[YH];
+    auto load_rows = [&](int t0n, int count) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = t0n + w + 4 * u;
+            gr[u] = (4 * u + w < count && t < rows_left) ? sk_ld_nt(gsk + (int64_t)t * 64 + lane) : 0.0f;
+        }
+    };
+    auto store_rows = [&](int t0n, int count) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = t0n + w + 4 * u, j = t - lane;
+            // only the strip's cells: the skewed rows also hold other strips'
+            // cells and, past the pair's last step, unwritten slots
+            if (4 * u + w < count && lane < nrow && j >= 0 && j < ly)
+                G[lane * SK_CMFMA_GS + (j & 127)] = gr[u];
+        }
+    };
+    auto load_y = [&](int j0) {
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int e = tid + 256 * h, jj = e / (16 * DB), k = e - jj * (16 * DB), j = j0 + jj;
+            yr[h] = (e < 64 * 16 * DB && k < d && j < ly)
+                        ? Y[(int64_t)(j + 1) * ld + k] - Y[(int64_t)j * ld + k] : 0.0f;
+        }
+    };
+    auto store_y = [&]() {
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int e = tid + 256 * h, jj = e / (16 * DB), k = e - jj * (16 * DB);
+            if (e < 64 * 16 * DB) Yt[jj * DS + k] = yr[h];
+        }
+    };
+    // clear the ring once: rows past the strip's last row stay zero, and
+    // columns j >= ly of the last tile keep earlier tiles' values, which meet
+    // zero y increments
+    for (int e = tid; e < 64 * SK_CMFMA_GS; e += 256) G[e] = 0.0f;
+    __syncthreads();
+    // prologue: skewed rows 0..62 (columns of tile 0 that rows < 63 hold)
+    load_rows(0, 63);
+    store_rows(0, 63);
+    load_rows(63, 64);
+    load_y(0);
+    sk_f4 accx[DB];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) accx[b] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int ntiles = (ly + 63) / 64;
+    for (int jt = 0; jt < ntiles; ++jt) {
+        const int j0 = 64 * jt;
+        // tile jt needs skewed rows up to j0 + 126 (held in registers)
+        store_rows(j0 + 63, 64);
+        store_y();
+        __syncthreads();
+        if (jt + 1 < ntiles) {  // the next tile's rows and increments load under the MFMAs
+            load_rows(j0 + 127, 64);
+            load_y(j0 + 64);
+        }
+        // dL/d(dx)[16w + m][n] += sum_k G[16w + m][j0 + k] dY[k][n]
+#pragma unroll
+        for (int kk = 0; kk < 64; kk += 4) {
+            const float av = G[(16 * w + (lane & 15)) * SK_CMFMA_GS + ((j0 + kk + (lane >> 4)) & 127)];
+#pragma unroll
+            for (int b = 0; b < DB; ++b) {
+                const float bv = Yt[(kk + (lane >> 4)) * DS + 16 * b + (lane & 15)];
+                accx[b] = SkMfma<float>::mma(av, bv, accx[b]);
+            }
+        }
+        // the strip's dL/d(dy)[j0 + 16w + m][n] = sum_k G[k][j0 + 16w + m] dX[k][n]
+        sk_f4 accy[DB];
+#pragma unroll
+        for (int b = 0; b < DB; ++b) accy[b] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < 64; kk += 4) {
+            const float av = G[(kk + (lane >> 4)) * SK_CMFMA_GS + ((j0 + 16 * w + (lane & 15)) & 127)];
+#pragma unroll
+            for (int b = 0; b < DB; ++b) {
+                const float bv = Xs[(kk + (lane >> 4)) * DS + 16 * b + (lane & 15)];
+                accy[b] = SkMfma<float>::mma(av, bv, accy[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < DB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + 16 * w + SkMfma<float>::row(lane, v), k = 16 * b + (lane & 15);
+                if (j < ly && k < d) a.dyp[pd.dy_off + ((int64_t)s * ly + j) * ld + k] = accy[b][v];
+            }
+        __syncthreads();  // the ring's and the tile's next contents are stored after this
+    }
+#pragma unroll
+    for (int b = 0; b < DB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 16 * w + SkMfma<float>::row(lane, v), k = 16 * b + (lane & 15);
+            if (rr < nrow && k < d) a.dxp[pd.dx_off + ((int64_t)s * 64 + rr) * ld + k] = accx[b][v];
+        }
+}
+
 // Hybrid scheme backward: every sub-cell of cell (i, j) on the lam-order
 // refinement has the constant c_ij / 4^lam, so dL/dc_ij is 4^-lam times the
 // sum of dL/dc' over its 4^lam sub-cells.  One thread per element (tau, r)
