@@ -2182,20 +2182,27 @@ __global__ __launch_bounds__(64) void k_contract(const ContractArgs<R> a) {
 // columns in tiles of 64: the skewed rows of dL/dc are un-skewed into an LDS
 // ring G[64][128] by column (each skewed row is read once, coalesced; a tile
 // needs rows up to 63 past its last column, so the ring holds the tile and the
-// next one's leading part), the tile's y increments into LDS, and the next
-// tile's rows and increments are loaded into registers while the current
-// tile's MFMAs run.  Wave w owns rows 16w..16w+15 of dL/d(dx) (accumulated in
-// registers over the tiles) and columns 16w..16w+15 of each tile's dL/d(dy).
+// next one's leading part), and the tile's y increments into LDS; the next
+// tile's rows and increments load into registers during the current tile's
+// MFMAs.  The x increments, the B operand of every tile's G^T dX, stay in
+// registers, which keeps the LDS of a workgroup under 40 KiB: four
+// workgroups per CU at d <= 16 (1.97 -> 1.64 ms on 128 x 128 Gram pairs of
+// 256 steps in R^8; two chunks of rows in flight per wave, at two waves per
+// SIMD, took 2.42 ms).  Wave w owns rows 16w..16w+15 of dL/d(dx)
+// (accumulated in registers over the tiles) and columns 16w..16w+15 of each
+// tile's dL/d(dy).
 #define SK_CMFMA_GS 132  // LDS row stride of the ring (2-way conflicts at most)
 template <int DB>
-__host__ __device__ constexpr int sk_cmfma_ds() { return 16 * DB + 4; }  // stride of dX / dY rows
+__host__ __device__ constexpr int sk_cmfma_ds() { return 16 * DB + 4; }  // stride of dY rows
 template <int DB>
 __host__ __device__ constexpr int sk_cmfma_lds() {
-    return (64 * SK_CMFMA_GS + 2 * 64 * sk_cmfma_ds<DB>()) * 4;
+    return (64 * SK_CMFMA_GS + 64 * sk_cmfma_ds<DB>()) * 4;
 }
 
 template <int DB>
 __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float> a) {
+    // (a scalar wave index, which makes the row loads' conditions scalar
+    // branches, is slower: 2.05 against 1.64 ms on 128 x 128 Gram pairs)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int s = blockIdx.y;
     const int64_t local = blockIdx.x;
@@ -2206,7 +2213,6 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
     extern __shared__ __align__(16) unsigned char sk_smem[];
     SkLds<float> G = (SkLds<float>)sk_smem;                 // [64][GS], column c at c & 127
     SkLds<float> Yt = G + 64 * SK_CMFMA_GS;                 // [64][DS]: y increments of the tile
-    SkLds<float> Xs = Yt + 64 * DS;                         // [64][DS]: x increments of the strip
     const int64_t ld = a.d;
     const int d = (int)a.d, ly = g.ly;
     const float* X = (pd.swap ? a.Y : a.X) + pd.x_off * ld;
@@ -2215,38 +2221,32 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
     const float* gsk = a.gskew + pd.c_off + tau0 * 64;
     const int64_t rows_left = (int64_t)g.nsteps_pad - tau0;  // skewed rows of the pair from tau0
     const int nrow = g.lx - s * 64 < 64 ? g.lx - s * 64 : 64;
-    // x increments of the strip's rows (zero past the last row and past d)
-    for (int e = tid; e < 64 * 16 * DB; e += 256) {
-        const int rr = e / (16 * DB), k = e - rr * (16 * DB);
-        float v = 0.0f;
-        if (rr < nrow && k < d) {
-            const int64_t i = (int64_t)s * 64 + rr;
-            v = X[(i + 1) * ld + k] - X[i * ld + k];
-        }
-        Xs[rr * DS + k] = v;
-    }
-    // registers of the next tile: skewed rows t0n + w + 4u (u < 16) at this
-    // lane, and y increments of its columns (value e = tid + 256 h of the
-    // tile's 64 x 16 DB block)
-    constexpr int YH = (64 * 16 * DB + 255) / 256;
-    float gr[16], yr[YH];
-    auto load_rows = [&](int t0n, int count) {
+    const int ntiles = (ly + 63) / 64;
+    // chunk c of skewed rows: rows 0..62 for c = -1 (the columns of tile 0
+    // that rows below 63 hold), rows 64c + 63 .. 64c + 126 for c >= 0 (the
+    // rest of tile c and the leading part of tile c + 1).  Lane `lane` of
+    // wave w holds rows t0 + w + 4u, u < 16.
+    auto load_rows = [&](float (&rows)[16], int c) {
+        const int t0n = c < 0 ? 0 : 64 * c + 63, count = c < 0 ? 63 : (c < ntiles ? 64 : 0);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int t = t0n + w + 4 * u;
-            gr[u] = (4 * u + w < count && t < rows_left) ? sk_ld_nt(gsk + (int64_t)t * 64 + lane) : 0.0f;
+            rows[u] = (4 * u + w < count && t < rows_left) ? sk_ld_nt(gsk + (int64_t)t * 64 + lane) : 0.0f;
         }
     };
-    auto store_rows = [&](int t0n, int count) {
+    auto store_rows = [&](const float (&rows)[16], int c) {
+        const int t0n = c < 0 ? 0 : 64 * c + 63, count = c < 0 ? 63 : 64;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int t = t0n + w + 4 * u, j = t - lane;
-            // only the strip's cells: the skewed rows also hold other strips'
-            // cells and, past the pair's last step, unwritten slots
+            // only the strip's cells: past the strip's rows and the pair's
+            // last step the skewed slots are not this strip's
             if (4 * u + w < count && lane < nrow && j >= 0 && j < ly)
-                G[lane * SK_CMFMA_GS + (j & 127)] = gr[u];
+                G[lane * SK_CMFMA_GS + (j & 127)] = rows[u];
         }
     };
+    constexpr int YH = (64 * 16 * DB + 255) / 256;
+    float yr[YH];
     auto load_y = [&](int j0) {
 #pragma unroll
         for (int h = 0; h < YH; ++h) {
@@ -2264,32 +2264,50 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
     };
     // clear the ring once: rows past the strip's last row stay zero, and
     // columns j >= ly of the last tile keep earlier tiles' values, which meet
-    // zero y increments
+    // zero y increments.  The x increments of the strip's rows (zero past its
+    // last row and past d) pass through the tile's y area into registers:
+    // xb[b][q] is B[4q + lane / 16][lane % 16] of the q-th k-step of column
+    // block b.
     for (int e = tid; e < 64 * SK_CMFMA_GS; e += 256) G[e] = 0.0f;
+    for (int e = tid; e < 64 * 16 * DB; e += 256) {
+        const int rr = e / (16 * DB), k = e - rr * (16 * DB);
+        float v = 0.0f;
+        if (rr < nrow && k < d) {
+            const int64_t i = (int64_t)s * 64 + rr;
+            v = X[(i + 1) * ld + k] - X[i * ld + k];
+        }
+        Yt[rr * DS + k] = v;
+    }
+    float gr[16];
+    load_rows(gr, -1);
     __syncthreads();
-    // prologue: skewed rows 0..62 (columns of tile 0 that rows < 63 hold)
-    load_rows(0, 63);
-    store_rows(0, 63);
-    load_rows(63, 64);
+    float xb[DB][16];
+#pragma unroll
+    for (int b = 0; b < DB; ++b)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xb[b][q] = Yt[(4 * q + (lane >> 4)) * DS + 16 * b + (lane & 15)];
+    store_rows(gr, -1);
+    load_rows(gr, 0);
     load_y(0);
+    __syncthreads();  // the x increments are read before tile 0's y increments replace them
     sk_f4 accx[DB];
 #pragma unroll
     for (int b = 0; b < DB; ++b) accx[b] = {0.0f, 0.0f, 0.0f, 0.0f};
-    const int ntiles = (ly + 63) / 64;
-    for (int jt = 0; jt < ntiles; ++jt) {
-        const int j0 = 64 * jt;
-        // tile jt needs skewed rows up to j0 + 126 (held in registers)
-        store_rows(j0 + 63, 64);
+    // tile jt: its chunk is in cur, which is then refilled with chunk jt + 1
+    auto tile = [&](int jt, float (&cur)[16]) {
+        // the tile's columns sit at cb .. cb + 63 of the ring, without wrapping
+        const int j0 = 64 * jt, cb = j0 & 127;
+        store_rows(cur, jt);
         store_y();
         __syncthreads();
-        if (jt + 1 < ntiles) {  // the next tile's rows and increments load under the MFMAs
-            load_rows(j0 + 127, 64);
+        if (jt + 1 < ntiles) {
             load_y(j0 + 64);
+            load_rows(cur, jt + 1);
         }
         // dL/d(dx)[16w + m][n] += sum_k G[16w + m][j0 + k] dY[k][n]
 #pragma unroll
         for (int kk = 0; kk < 64; kk += 4) {
-            const float av = G[(16 * w + (lane & 15)) * SK_CMFMA_GS + ((j0 + kk + (lane >> 4)) & 127)];
+            const float av = G[(16 * w + (lane & 15)) * SK_CMFMA_GS + cb + kk + (lane >> 4)];
 #pragma unroll
             for (int b = 0; b < DB; ++b) {
                 const float bv = Yt[(kk + (lane >> 4)) * DS + 16 * b + (lane & 15)];
@@ -2301,13 +2319,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
 #pragma unroll
         for (int b = 0; b < DB; ++b) accy[b] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kk = 0; kk < 64; kk += 4) {
-            const float av = G[(kk + (lane >> 4)) * SK_CMFMA_GS + ((j0 + 16 * w + (lane & 15)) & 127)];
+        for (int q = 0; q < 16; ++q) {
+            const float av = G[(4 * q + (lane >> 4)) * SK_CMFMA_GS + cb + 16 * w + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < DB; ++b) {
-                const float bv = Xs[(kk + (lane >> 4)) * DS + 16 * b + (lane & 15)];
-                accy[b] = SkMfma<float>::mma(av, bv, accy[b]);
-            }
+            for (int b = 0; b < DB; ++b) accy[b] = SkMfma<float>::mma(av, xb[b][q], accy[b]);
         }
 #pragma unroll
         for (int b = 0; b < DB; ++b)
@@ -2317,7 +2332,8 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
                 if (j < ly && k < d) a.dyp[pd.dy_off + ((int64_t)s * ly + j) * ld + k] = accy[b][v];
             }
         __syncthreads();  // the ring's and the tile's next contents are stored after this
-    }
+    };
+    for (int jt = 0; jt < ntiles; ++jt) tile(jt, gr);
 #pragma unroll
     for (int b = 0; b < DB; ++b)
 #pragma unroll

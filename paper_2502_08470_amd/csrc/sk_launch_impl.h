@@ -362,7 +362,7 @@ template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    // FP32, d <= 32: the MFMA tiles (d = 8: 2.05 -> 1.97 ms on the 128 x 128
+    // FP32, d <= 32: the MFMA tiles (d = 8: 2.05 -> 1.64 ms on the 128 x 128
     // Gram of 256-step paths; d = 32: 2.3x faster); FP64 and d > 32: the VALU
     // wavefront kernel
     if constexpr (sizeof(R) == 4) {
