@@ -64,7 +64,7 @@ __host__ __device__ inline SkGeom sk_make_geom(int32_t lx, int32_t ly) {
 // gx_cols below SK_GX_MIN_COLS.
 #define SK_GX_BLOCK 8
 #define SK_GX_MIN_COLS 96
-__host__ __device__ constexpr int sk_ring_col_bytes_fwd(int N, int es) { return 16 + (N - 1) * es + 4; }
+__host__ __device__ constexpr int sk_ring_col_bytes_fwd(int N, int es) { return (16 + (N - 1) * es + 4 + 7) / 8 * 8; }
 __host__ __device__ constexpr int sk_ring_col_bytes_adj(int N, int es) { return (N + 1) * es + 4; }
 // 32-bit words of one global exchange record, rounded up to 16 bytes:
 // forward: FP64 coefficients 0 and 1, coefficients 2..N, exponent;

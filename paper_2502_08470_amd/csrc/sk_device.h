@@ -120,6 +120,24 @@ __device__ __forceinline__ double lane_from_next(double v) {
 __device__ __forceinline__ int lane_from_prev(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
 }
+// lane r receives the value of lane r-1 and lane 0 receives `lane0` (its own
+// value of that argument): the same lane move with the first lane's input
+// merged in, for inputs every lane reads alike (a broadcast LDS read)
+__device__ __forceinline__ float lane_from_prev_or(float v, float lane0) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(lane0), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_prev_or(double v, double lane0) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    int2 z = *reinterpret_cast<int2*>(&lane0);
+    int2 o;
+    o.x = __builtin_amdgcn_update_dpp(z.x, b.x, 0x138, 0xf, 0xf, false);
+    o.y = __builtin_amdgcn_update_dpp(z.y, b.y, 0x138, 0xf, 0xf, false);
+    return *reinterpret_cast<double*>(&o);
+}
+__device__ __forceinline__ int lane_from_prev_or(int v, int lane0) {
+    return __builtin_amdgcn_update_dpp(lane0, v, 0x138, 0xf, 0xf, false);
+}
 __device__ __forceinline__ int lane_from_next(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
 }

@@ -687,6 +687,56 @@ __device__ __forceinline__ void sk_write_k(R* K, int32_t* Kexp, int64_t idx, dou
     }
 }
 
+// A strip-boundary edge of the forward sweep in LDS (a ring entry or a
+// staged exchange record, 8-byte aligned): FP64 coefficients 0 and 1 in
+// words 0..3, coefficients 2..N from word 4, then the exponent.
+template <typename R, int N>
+__device__ __forceinline__ void sk_edge_read(SkLds<unsigned> rec, double& q0, double& q1,
+                                             R (&q)[N + 1], int& e) {
+    constexpr int ES = (int)sizeof(R), NW = 4 + (N - 1) * ES / 4 + 1, NW2 = (NW + 1) / 2;
+    unsigned wv[2 * NW2];
+#pragma unroll
+    for (int k = 0; k < NW2; ++k) {
+        const unsigned long long v = ((SkLds<unsigned long long>)rec)[k];
+        wv[2 * k] = (unsigned)v;
+        wv[2 * k + 1] = (unsigned)(v >> 32);
+    }
+    q0 = __hiloint2double((int)wv[1], (int)wv[0]);
+    q1 = __hiloint2double((int)wv[3], (int)wv[2]);
+#pragma unroll
+    for (int n = 2; n <= N; ++n) {
+        if constexpr (ES == 4)
+            q[n] = __uint_as_float(wv[4 + n - 2]);
+        else
+            q[n] = __hiloint2double((int)wv[4 + 2 * (n - 2) + 1], (int)wv[4 + 2 * (n - 2)]);
+    }
+    e = (int)wv[NW - 1];
+}
+template <typename R, int N>
+__device__ __forceinline__ void sk_edge_write(SkLds<unsigned> rec, double q0, double q1,
+                                              const R (&q)[N + 1], int e) {
+    constexpr int ES = (int)sizeof(R), NW = 4 + (N - 1) * ES / 4 + 1, NW2 = (NW + 1) / 2;
+    unsigned wv[2 * NW2];
+    wv[0] = (unsigned)__double2loint(q0);
+    wv[1] = (unsigned)__double2hiint(q0);
+    wv[2] = (unsigned)__double2loint(q1);
+    wv[3] = (unsigned)__double2hiint(q1);
+#pragma unroll
+    for (int n = 2; n <= N; ++n) {
+        if constexpr (ES == 4) {
+            wv[4 + n - 2] = __float_as_uint(q[n]);
+        } else {
+            wv[4 + 2 * (n - 2)] = (unsigned)__double2loint(q[n]);
+            wv[4 + 2 * (n - 2) + 1] = (unsigned)__double2hiint(q[n]);
+        }
+    }
+    wv[NW - 1] = (unsigned)e;
+    if (NW < 2 * NW2) wv[2 * NW2 - 1] = 0u;
+#pragma unroll
+    for (int k = 0; k < NW2; ++k)
+        ((SkLds<unsigned long long>)rec)[k] = (unsigned long long)wv[2 * k] | ((unsigned long long)wv[2 * k + 1] << 32);
+}
+
 // Magnitude bookkeeping: every lane carries its own power-of-two exponent E
 // (the edges it holds are mantissa * 2^E).  Lanes of one wave sit at very
 // different places of the grid, whose kernel values can differ by far more
@@ -715,9 +765,10 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     const bool gx = GX && g.ly > a.gx_cols;  // wave-uniform
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);                // [8][GXW]
-    double* qlds0 = reinterpret_cast<double*>(sk_smem + sk_gx_stage_bytes(N, ES));  // [ly][2]
-    R* qlds = reinterpret_cast<R*>(qlds0 + 2 * (size_t)g.ly);     // [ly][N-1]
-    int* qtag = reinterpret_cast<int*>(qlds + (size_t)g.ly * (N - 1));
+    // ring entry of a column: FP64 coefficients 0 and 1, coefficients 2..N,
+    // exponent (the layout of a global exchange record), 8-byte aligned
+    constexpr int RW = sk_ring_col_bytes_fwd(N, ES) / 4;
+    const SkLds<unsigned> ring = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES));  // [ly][RW]
     unsigned* xg = a.xb + pd.xb_off;  // [ly][GXW] (exchange pairs only)
     unsigned xr[(8 * GXW + 63) / 64];
 #pragma unroll
@@ -739,6 +790,17 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     int E = 0, Es = 0;
     int L = -r, s = 0, j = 0;
     bool live = false;
+    // The ring starts with the initial left edge (1, 0, ..., 0; exponent 0),
+    // which lane 0 of strip 0 reads: the entry of column j is first written by
+    // lane 63 of strip 0, 63 steps after that read.  (Exchange pairs take the
+    // initial edge by a wave-uniform test instead.)
+    if (!gx) {
+        for (int col = r; col < g.ly; col += 64) {
+            SkLds<unsigned> e = ring + __mul24(col, RW);
+#pragma unroll
+            for (int w = 0; w < RW; ++w) e[w] = (w == 1) ? 0x3ff00000u : 0u;  // words 0-1: 1.0
+        }
+    }
     const int nst8 = (g.nsteps + 7) & ~7;
     R cb[8], cn[8];
 #pragma unroll
@@ -753,11 +815,28 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int tau = t0 + u;
+            // lane 0's left edge: the strip-boundary entry of its column (the
+            // ring, or the staged exchange record of this step), read alike by
+            // every lane and merged into the lane move that feeds lanes 1..63
+            const int j0 = __builtin_amdgcn_readfirstlane(j), s0 = __builtin_amdgcn_readfirstlane(s);
+            double B0, B1;
+            R Bq[N + 1];
+            int Be;
+            sk_edge_read<R, N>(gx ? (SkLds<unsigned>)stage + u * GXW
+                                  : ring + __mul24(j0 < g.ly ? j0 : g.ly - 1, RW),
+                               B0, B1, Bq, Be);
+            if (gx && s0 == 0) {
+                B0 = 1.0;
+                B1 = 0.0;
+#pragma unroll
+                for (int n = 2; n <= N; ++n) Bq[n] = (R)0;
+                Be = 0;
+            }
             R Qin[N + 1];
 #pragma unroll
-            for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev(Qs[n]);
-            double Qin0 = lane_from_prev(Qs0), Qin1 = lane_from_prev(Qs1);
-            int Ein = lane_from_prev(Es);
+            for (int n = 2; n <= N; ++n) Qin[n] = lane_from_prev_or(Qs[n], Bq[n]);
+            double Qin0 = lane_from_prev_or(Qs0, B0), Qin1 = lane_from_prev_or(Qs1, B1);
+            int Ein = lane_from_prev_or(Es, Be);
             const int i = s * 64 + r;
             live = (L >= 0) && (s < g.nstrips) && (j < g.ly) && (i < g.lx);
             if (live) {
@@ -767,29 +846,6 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
 #pragma unroll
                     for (int n = 2; n <= N; ++n) P[n] = (R)0;
                     E = 0;
-                }
-                if (r == 0) {
-                    if (s == 0) {
-                        Qin0 = 1.0;
-                        Qin1 = 0.0;
-#pragma unroll
-                        for (int n = 2; n <= N; ++n) Qin[n] = (R)0;
-                        Ein = 0;
-                    } else if (gx) {
-                        const unsigned* rec = stage + u * GXW;
-                        Qin0 = *reinterpret_cast<const double*>(rec);
-                        Qin1 = *reinterpret_cast<const double*>(rec + 2);
-#pragma unroll
-                        for (int n = 2; n <= N; ++n)
-                            Qin[n] = *reinterpret_cast<const R*>(rec + 4 + (n - 2) * (ES / 4));
-                        Ein = (int)rec[4 + (N - 1) * (ES / 4)];
-                    } else {
-                        Qin0 = qlds0[2 * j];
-                        Qin1 = qlds0[2 * j + 1];
-#pragma unroll
-                        for (int n = 2; n <= N; ++n) Qin[n] = qlds[j * (N - 1) + n - 2];
-                        Ein = qtag[j];
-                    }
                 }
                 const int Ec = E > Ein ? E : Ein;
                 const int dp = E - Ec, dq = Ein - Ec;
@@ -855,18 +911,15 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                         for (int n = 2; n <= N; ++n)
                             *reinterpret_cast<R*>(rec + 4 + (n - 2) * (ES / 4)) = Qo[n];
                         rec[4 + (N - 1) * (ES / 4)] = (unsigned)E;
+                        if (CKPT) {
+                            const int64_t o = (int64_t)(s + 1) * g.ly + j;
+#pragma unroll
+                            for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
+                            a.qe[pd.qe_off + o] = E;
+                        }
                     } else {
-                        qlds0[2 * j] = Qo0;
-                        qlds0[2 * j + 1] = Qo1;
-#pragma unroll
-                        for (int n = 2; n <= N; ++n) qlds[j * (N - 1) + n - 2] = Qo[n];
-                        qtag[j] = E;
-                    }
-                    if (CKPT) {
-                        const int64_t o = (int64_t)(s + 1) * g.ly + j;
-#pragma unroll
-                        for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
-                        a.qe[pd.qe_off + o] = E;
+                        // (the checkpoint copy of ring entries leaves once per block)
+                        sk_edge_write<R, N>(ring + __mul24(j, RW), Qo0, Qo1, Qo, E);
                     }
                 }
                 if (i == g.lx - 1 && j == g.ly - 1) {
@@ -884,6 +937,40 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                 }
             }
             ++L;
+        }
+        // the strip-boundary edges lane 63 handed over in this block, from
+        // the ring to the adjoint's global copy (one coalesced pass; an entry
+        // is rewritten only Tp >= 64 steps after it was written)
+        if (CKPT && !gx) {
+            // lane 63's place after the block: the place of step t0 + u is
+            // 8 - u columns back (while L >= 0 it advanced every step)
+            const int Le = __builtin_amdgcn_readlane(L, 63), se = __builtin_amdgcn_readlane(s, 63),
+                      je = __builtin_amdgcn_readlane(j, 63);
+            constexpr int QR = N + 2;  // N + 1 coefficients and the exponent
+#pragma unroll
+            for (int e0 = 0; e0 < 8 * QR; e0 += 64) {
+                const int e = e0 + r, u = e / QR, w = e - u * QR;
+                const int back = 8 - u;
+                int jc = je - back, sc = se;
+                if (jc < 0) {
+                    jc += g.Tp;
+                    --sc;
+                }
+                if (e < 8 * QR && Le - back >= 0 && sc + 1 < g.nstrips && jc < g.ly) {
+                    const SkLds<unsigned> rec = ring + __mul24(jc, RW);
+                    const int64_t o = (int64_t)(sc + 1) * g.ly + jc;
+                    if (w <= N) {
+                        R v;
+                        if (w < 2)
+                            v = (R)(*(SkLds<double>)(rec + 2 * w));
+                        else
+                            v = *(SkLds<R>)(rec + 4 + (w - 2) * (ES / 4));
+                        a.qb[pd.qb_off + o * (N + 1) + w] = v;
+                    } else {
+                        a.qe[pd.qe_off + o] = (int)rec[4 + (N - 1) * (ES / 4)];
+                    }
+                }
+            }
         }
         // per-lane rescale of the live state
         if (live) {
