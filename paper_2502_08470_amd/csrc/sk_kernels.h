@@ -1083,6 +1083,10 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
     constexpr int XR = (8 * GXW + 63) / 64;
     extern __shared__ __align__(16) unsigned char sk_smem[];
     unsigned* stage = reinterpret_cast<unsigned*>(sk_smem);  // [8][GXW]
+    // lane 63's records of the current 8-step block, stored to the global
+    // slot by all lanes at the block's end (before it is published)
+    const SkLds<unsigned> ost = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES));  // [8][GXW]
+    constexpr int NW = 4 + (N - 1) * (ES / 4) + 1;  // words of a record
     for (int64_t q = blockIdx.x; q < a.njobs; q += gridDim.x) {
         // the job: strip s of a pair with geometry g and arrays at these bases
         const int2 jb = a.jobs[q];
@@ -1240,21 +1244,19 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                 Es = E;
                 if (live) {
                     if (r == 63 && has_next) {
-                        unsigned* rec = rout + (int64_t)j * GXW;
-                        unsigned wd[4 + (N - 1) * (ES / 4) + 1];
-                        *reinterpret_cast<double*>(wd) = Qo0;
-                        *reinterpret_cast<double*>(wd + 2) = Qo1;
-#pragma unroll
-                        for (int n = 2; n <= N; ++n)
-                            *reinterpret_cast<R*>(wd + 4 + (n - 2) * (ES / 4)) = Qo[n];
-                        wd[4 + (N - 1) * (ES / 4)] = (unsigned)E;
-#pragma unroll
-                        for (int k = 0; k < 4 + (N - 1) * (ES / 4) + 1; ++k) sk_store_coherent(rec + k, wd[k]);
                         if (CKPT) {
-                            const int64_t o = (int64_t)(s + 1) * ly + j;
+                            sk_edge_write<R, N>(ost + u * GXW, Qo0, Qo1, Qo, E);
+                        } else {
+                            unsigned* rec = rout + (int64_t)j * GXW;
+                            unsigned wd[NW];
+                            *reinterpret_cast<double*>(wd) = Qo0;
+                            *reinterpret_cast<double*>(wd + 2) = Qo1;
 #pragma unroll
-                            for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
-                            a.qe[pd.qe_off + o] = E;
+                            for (int n = 2; n <= N; ++n)
+                                *reinterpret_cast<R*>(wd + 4 + (n - 2) * (ES / 4)) = Qo[n];
+                            wd[NW - 1] = (unsigned)E;
+#pragma unroll
+                            for (int k = 0; k < NW; ++k) sk_store_coherent(rec + k, wd[k]);
                         }
                     }
                     if (i == g.lx - 1 && j == ly - 1) {
@@ -1263,6 +1265,40 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                         for (int n = N; n >= 2; --n) kr = fma(Po[n] + Qo[n], ifact<R>(n), kr);
                         const double kv = 0.5 * (Po0 + Qo0 + Po1 + Qo1 + (double)kr);
                         sk_write_k(a.K, a.Kexp, k_idx, kv, E);
+                    }
+                }
+            }
+            // CKPT: lane 63's records of this block (columns t0 + m - 63
+            // that exist) to strip s+1's slot and to the adjoint's copy of
+            // the boundary edges, in one pass of all lanes (without CKPT lane
+            // 63 stores its records as it goes: the pass's registers would
+            // cost that kernel a wave per SIMD)
+            if (CKPT && has_next) {
+#pragma unroll
+                for (int h = 0; h < XR; ++h) {
+                    const int w = r + 64 * h, m = w / GXW, qw = w - m * GXW, jc = t0 + m - 63;
+                    if (w < 8 * GXW && qw < NW && jc >= 0 && jc < ly)
+                        sk_store_coherent(rout + (int64_t)jc * GXW + qw, ost[w]);
+                }
+                {
+                    constexpr int QR = N + 2;  // N + 1 coefficients and the exponent
+#pragma unroll
+                    for (int e0 = 0; e0 < 8 * QR; e0 += 64) {
+                        const int e = e0 + r, m = e / QR, w = e - m * QR, jc = t0 + m - 63;
+                        if (e < 8 * QR && jc >= 0 && jc < ly) {
+                            const SkLds<unsigned> rec = ost + m * GXW;
+                            const int64_t o = (int64_t)(s + 1) * ly + jc;
+                            if (w <= N) {
+                                R v;
+                                if (w < 2)
+                                    v = (R)(*(SkLds<double>)(rec + 2 * w));
+                                else
+                                    v = *(SkLds<R>)(rec + 4 + (w - 2) * (ES / 4));
+                                a.qb[pd.qb_off + o * (N + 1) + w] = v;
+                            } else {
+                                a.qe[pd.qe_off + o] = (int)rec[NW - 1];
+                            }
+                        }
                     }
                 }
             }

@@ -233,7 +233,7 @@ static hipError_t sk_pipe_n(const PipeArgs<R>& a, bool ckpt, hipStream_t st) {
     if constexpr (sk_alt_stride<R>())
         if (ckpt && a.S == 2) kern = reinterpret_cast<const void*>(&k_sweep_pipe<R, N, TMAX, true, 2>);
     if (ckpt && a.S != S && !(sk_alt_stride<R>() && a.S == 2)) return hipErrorInvalidValue;
-    return sk_coop_launch(kern, a, a.njobs, (size_t)sk_gx_stage_bytes(N, (int)sizeof(R)), st);
+    return sk_coop_launch(kern, a, a.njobs, (size_t)2 * sk_gx_stage_bytes(N, (int)sizeof(R)), st);
 }
 
 template <typename R>
