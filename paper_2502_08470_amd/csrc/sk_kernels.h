@@ -1832,11 +1832,14 @@ struct AdjPipeArgs {
 // segment's row derivatives [P/Q][S][N + TR][64 lanes] (in LDS rather than
 // registers, which leaves room for two waves per SIMD without spilling), TR
 // the tail rows kept per step (SkTailReg; 0 for the approximation scheme,
-// TMAX = 0).
+// TMAX = 0), the boundary edges lane 0 replays at steps 1..S-1 of a segment
+// (staged one segment ahead, as in the batched adjoint), and lane 0's
+// outgoing records of the current 8-step block.
 template <typename R>
 __host__ __device__ constexpr int sk_adj_pipe_lds(int N, int TMAX, int S) {
     return sk_gx_stage_bytes(N, (int)sizeof(R)) +
-           2 * S * (N + (TMAX > 0 ? SkTailReg<R>::value : 0)) * 64 * (int)sizeof(R);
+           2 * S * (N + (TMAX > 0 ? SkTailReg<R>::value : 0)) * 64 * (int)sizeof(R) +
+           sk_adj_qst_bytes(N, (int)sizeof(R)) + sk_gx_stage_bytes(N, (int)sizeof(R));
 }
 
 template <typename R, int N, int TMAX, int S>
@@ -1850,6 +1853,11 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     R* dlds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES)) + r;  // [2][S][M][64], this lane's slot
     auto DPu = [&](int u) { return dlds + (0 * S + u) * M * 64; };
     auto DQu = [&](int u) { return dlds + (1 * S + u) * M * 64; };
+    constexpr int QW = sk_adj_qst_words(N, ES);
+    static_assert((S - 1) * QW <= 64, "staged boundary edges exceed one word per lane");
+    const SkLds<unsigned> qst =
+        (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES) + 2 * S * M * 64 * ES);  // [S-1][QW]
+    const SkLds<unsigned> ost = qst + sk_adj_qst_bytes(N, ES) / 4;                      // [8][GXW]
     for (int64_t q = blockIdx.x; q < a.njobs; q += gridDim.x) {
         const int2 jb = a.jobs[q];
         const SkPairDesc pd = a.desc[jb.x];
@@ -1938,10 +1946,10 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                         for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
                         Ein = 0;
                     } else {
-                        const int64_t o = (int64_t)s * ly + j;
+                        const SkLds<unsigned> qq = qst + (u - 1) * QW;
 #pragma unroll
-                        for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
-                        Ein = a.qe[pd.qe_off + o];
+                        for (int n = 0; n <= N; ++n) Qin[n] = ((SkLds<R>)qq)[n];
+                        Ein = (int)qq[QW - 1];
                     }
                 }
                 const int Ec = E > Ein ? E : Ein;
@@ -2010,14 +2018,11 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             cell(ap, aq, gv);
             El = Ec;
             Els = Ec;
-            if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
-                unsigned wd[RW];
+            if (live && r == 0 && s > 0) {  // to strip s-1's lane 63 (leaves with the block)
+                const SkLds<unsigned> rec = ost + (t & 7) * GXW;
 #pragma unroll
-                for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(wd + n * (ES / 4)) = lqs[n];
-                wd[RW - 1] = (unsigned)Ec;
-                unsigned* rec = rout + (int64_t)jj * GXW;
-#pragma unroll
-                for (int k = 0; k < RW; ++k) sk_store_coherent(rec + k, wd[k]);
+                for (int n = 0; n <= N; ++n) *(SkLds<R>)(rec + n * (ES / 4)) = lqs[n];
+                rec[RW - 1] = (unsigned)Ec;
             }
             if (live) gs[(int64_t)t * 64 + r] = sk_ldexp(gv, Ec + Eu);
             if ((t & 7) == 0 && live) {
@@ -2040,6 +2045,23 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                 }
             }
         };
+        // word r of the boundary edges lane 0 replays at steps 1..S-1 of
+        // segment kk (strips >= 1), loaded one segment ahead of its use
+        auto load_q = [&](int kk) -> unsigned {
+            unsigned v = 0u;
+            if (s > 0 && r < (S - 1) * QW) {
+                const int u = 1 + r / QW, w = r - (u - 1) * QW, j = kk * S + u;
+                if (j < ly) {
+                    const int64_t o = (int64_t)s * ly + j;
+                    if (w < (N + 1) * (ES / 4))
+                        v = reinterpret_cast<const unsigned*>(a.qb + pd.qb_off + o * (N + 1))[w];
+                    else if (w == QW - 1)
+                        v = (unsigned)a.qe[pd.qe_off + o];
+                }
+            }
+            return v;
+        };
+        unsigned pq = load_q(nckl - 1);
         int published = 0;
         for (int kk = nckl - 1; ok && kk >= 0; --kk) {
             const int t0 = kk * S;
@@ -2052,6 +2074,10 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                 }
                 sk_gx_stage<GXW, true>(xr, stage, rin, b - 8, r, col63);
             }
+            // this segment's staged edges (the wave's own reads of the previous
+            // segment's are ordered before), then the next segment's loads
+            if (r < (S - 1) * QW) qst[r] = pq;
+            if (kk > 0) pq = load_q(kk - 1);
             const R* ck = ckb + (int64_t)kk * 2 * (N + 1) * 64;
             const int E0 = ceb[(int64_t)kk * (SK_LANES + 1) + r];
             const unsigned tword =
@@ -2147,9 +2173,17 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
                     });
                 }
             }
-            // lane 0 has handed over the columns j >= t0: publish them once
-            // its record stores have completed
+            // lane 0 has handed over the columns j >= t0: its records of the
+            // block's steps t0..t0+7 (column t at step t) go to strip s-1's
+            // slot in one pass of all lanes, then the count is published once
+            // the stores have completed
             if (s > 0 && (t0 & 7) == 0) {
+#pragma unroll
+                for (int h = 0; h < XR; ++h) {
+                    const int w = r + 64 * h, m = w / GXW, qw = w - m * GXW, jc = t0 + m;
+                    if (w < 8 * GXW && qw < RW && jc < ly)
+                        sk_store_coherent(rout + (int64_t)jc * GXW + qw, ost[w]);
+                }
                 int done = ly - t0;
                 done = done < 0 ? 0 : (done > ly ? ly : done);
                 if (done > published) {
