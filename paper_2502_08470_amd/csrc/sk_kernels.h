@@ -1853,8 +1853,14 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     R* dlds = reinterpret_cast<R*>(sk_smem + sk_gx_stage_bytes(N, ES)) + r;  // [2][S][M][64], this lane's slot
     auto DPu = [&](int u) { return dlds + (0 * S + u) * M * 64; };
     auto DQu = [&](int u) { return dlds + (1 * S + u) * M * 64; };
+    // FP32: lane 0's replayed boundary edges are loaded one segment ahead,
+    // and lane 0's outgoing records leave once per block (FP64 has no
+    // registers to spare for either).  (Loading the segment's lane state one
+    // segment ahead as well costs this kernel a wave per SIMD: 85.8 -> 92.0 ms
+    // on 4096 uneven pairs.)
+    constexpr bool PF = ES == 4;
     constexpr int QW = sk_adj_qst_words(N, ES);
-    static_assert((S - 1) * QW <= 64, "staged boundary edges exceed one word per lane");
+    static_assert(!PF || (S - 1) * QW <= 64, "staged boundary edges exceed one word per lane");
     const SkLds<unsigned> qst =
         (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES) + 2 * S * M * 64 * ES);  // [S-1][QW]
     const SkLds<unsigned> ost = qst + sk_adj_qst_bytes(N, ES) / 4;                      // [8][GXW]
@@ -1945,11 +1951,16 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
 #pragma unroll
                         for (int n = 0; n <= N; ++n) Qin[n] = n == 0 ? (R)1 : (R)0;
                         Ein = 0;
-                    } else {
+                    } else if (PF) {
                         const SkLds<unsigned> qq = qst + (u - 1) * QW;
 #pragma unroll
                         for (int n = 0; n <= N; ++n) Qin[n] = ((SkLds<R>)qq)[n];
                         Ein = (int)qq[QW - 1];
+                    } else {
+                        const int64_t o = (int64_t)s * ly + j;
+#pragma unroll
+                        for (int n = 0; n <= N; ++n) Qin[n] = a.qb[pd.qb_off + o * (N + 1) + n];
+                        Ein = a.qe[pd.qe_off + o];
                     }
                 }
                 const int Ec = E > Ein ? E : Ein;
@@ -2018,11 +2029,21 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             cell(ap, aq, gv);
             El = Ec;
             Els = Ec;
-            if (live && r == 0 && s > 0) {  // to strip s-1's lane 63 (leaves with the block)
-                const SkLds<unsigned> rec = ost + (t & 7) * GXW;
+            if (live && r == 0 && s > 0) {  // to strip s-1's lane 63
+                if (PF) {  // (leaves with the block)
+                    const SkLds<unsigned> rec = ost + (t & 7) * GXW;
 #pragma unroll
-                for (int n = 0; n <= N; ++n) *(SkLds<R>)(rec + n * (ES / 4)) = lqs[n];
-                rec[RW - 1] = (unsigned)Ec;
+                    for (int n = 0; n <= N; ++n) *(SkLds<R>)(rec + n * (ES / 4)) = lqs[n];
+                    rec[RW - 1] = (unsigned)Ec;
+                } else {
+                    unsigned wd[RW];
+#pragma unroll
+                    for (int n = 0; n <= N; ++n) *reinterpret_cast<R*>(wd + n * (ES / 4)) = lqs[n];
+                    wd[RW - 1] = (unsigned)Ec;
+                    unsigned* rec = rout + (int64_t)jj * GXW;
+#pragma unroll
+                    for (int k = 0; k < RW; ++k) sk_store_coherent(rec + k, wd[k]);
+                }
             }
             if (live) gs[(int64_t)t * 64 + r] = sk_ldexp(gv, Ec + Eu);
             if ((t & 7) == 0 && live) {
@@ -2049,7 +2070,7 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
         // segment kk (strips >= 1), loaded one segment ahead of its use
         auto load_q = [&](int kk) -> unsigned {
             unsigned v = 0u;
-            if (s > 0 && r < (S - 1) * QW) {
+            if (PF && s > 0 && r < (S - 1) * QW) {
                 const int u = 1 + r / QW, w = r - (u - 1) * QW, j = kk * S + u;
                 if (j < ly) {
                     const int64_t o = (int64_t)s * ly + j;
@@ -2076,8 +2097,8 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             }
             // this segment's staged edges (the wave's own reads of the previous
             // segment's are ordered before), then the next segment's loads
-            if (r < (S - 1) * QW) qst[r] = pq;
-            if (kk > 0) pq = load_q(kk - 1);
+            if (PF && r < (S - 1) * QW) qst[r] = pq;
+            if (PF && kk > 0) pq = load_q(kk - 1);
             const R* ck = ckb + (int64_t)kk * 2 * (N + 1) * 64;
             const int E0 = ceb[(int64_t)kk * (SK_LANES + 1) + r];
             const unsigned tword =
@@ -2179,7 +2200,7 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
             // the stores have completed
             if (s > 0 && (t0 & 7) == 0) {
 #pragma unroll
-                for (int h = 0; h < XR; ++h) {
+                for (int h = 0; h < (PF ? XR : 0); ++h) {
                     const int w = r + 64 * h, m = w / GXW, qw = w - m * GXW, jc = t0 + m;
                     if (w < 8 * GXW && qw < RW && jc < ly)
                         sk_store_coherent(rout + (int64_t)jc * GXW + qw, ost[w]);
@@ -2199,9 +2220,9 @@ __device__ __forceinline__ void sk_adjoint_pipe_body(const AdjPipeArgs<R>& a) {
     }
 }
 
-// With the row derivatives in LDS every order fits two waves per SIMD
-// without spilling (at most 245 registers, FP64 N = 8 interpolation), and
-// the derivatives' LDS allows no more.
+// With the row derivatives in LDS every order fits two waves per SIMD (the
+// derivatives' LDS allows no more); FP64 interpolation at N = 8 spills 120
+// bytes per lane there.
 template <typename R, int N, int TMAX, int S>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 8)))
 void k_adjoint_pipe(const AdjPipeArgs<R> a) {
