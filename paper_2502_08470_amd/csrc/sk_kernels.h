@@ -2521,6 +2521,160 @@ __global__ __launch_bounds__(256) void k_contract_mfma(const ContractArgs<float>
         }
 }
 
+// FP64 version of the MFMA contraction (16x16x4 FP64 tiles), for d up to
+// 16 DB.  FP64 doubles the bytes of every LDS operand, so the column tiles
+// are 32 wide and the ring holds 96 columns (a tile and the 63 columns past
+// it that its rows also hold), which keeps a workgroup under 64 KiB; the x
+// increments, the B operand of G^T dX, stay in registers.  Wave w owns rows
+// 16w..16w+15 of dL/d(dx) and, of each tile's 32 x 16 DB block of dL/d(dy),
+// the 16 columns (w & 1) and the dimension block w >> 1 (waves whose block is
+// past DB take no part in that product).
+#define SK_CMFMA64_RC 96   // ring columns
+#define SK_CMFMA64_GS 100  // LDS row stride of the ring, in doubles
+template <int DB>
+__host__ __device__ constexpr int sk_cmfma64_ds() { return 16 * DB + 2; }  // stride of dY rows
+template <int DB>
+__host__ __device__ constexpr int sk_cmfma64_lds() {
+    return (64 * SK_CMFMA64_GS + 32 * sk_cmfma64_ds<DB>()) * 8;
+}
+
+template <int DB>
+__global__ __launch_bounds__(256) void k_contract_mfma_f64(const ContractArgs<double> a) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s = blockIdx.y;
+    const int64_t local = blockIdx.x;
+    const SkPairDesc pd = sk_pair(a.src, local);
+    const SkGeom g = sk_make_geom(pd.lx, pd.ly);
+    if (g.nsteps == 0 || s >= g.nstrips) return;
+    constexpr int TW = 32, RC = SK_CMFMA64_RC, GS = SK_CMFMA64_GS, DS = sk_cmfma64_ds<DB>();
+    extern __shared__ __align__(16) unsigned char sk_smem[];
+    SkLds<double> G = (SkLds<double>)sk_smem;  // [64][GS], column c at c % RC
+    SkLds<double> Yt = G + 64 * GS;            // [TW][DS]: y increments of the tile
+    const int64_t ld = a.d;
+    const int d = (int)a.d, ly = g.ly;
+    const double* X = (pd.swap ? a.Y : a.X) + pd.x_off * ld;
+    const double* Y = (pd.swap ? a.X : a.Y) + pd.y_off * ld;
+    const int64_t tau0 = (int64_t)s * g.Tp;                  // skewed row of the strip's (0, 0)
+    const double* gsk = a.gskew + pd.c_off + tau0 * 64;
+    const int64_t rows_left = (int64_t)g.nsteps_pad - tau0;  // skewed rows of the pair from tau0
+    const int nrow = g.lx - s * 64 < 64 ? g.lx - s * 64 : 64;
+    const int ntiles = (ly + TW - 1) / TW;
+    const int bb = w >> 1;  // this wave's dimension block of dL/d(dy)
+    // x increments of the strip's rows (zero past the last row and past d),
+    // staged through the ring's space: xb[q] = B[4q + lane / 16][lane % 16]
+    // of the q-th k-step of dimension block bb
+    for (int e = tid; e < 64 * 16 * DB; e += 256) {
+        const int rr = e / (16 * DB), k = e - rr * (16 * DB);
+        double v = 0.0;
+        if (rr < nrow && k < d) {
+            const int64_t i = (int64_t)s * 64 + rr;
+            v = X[(i + 1) * ld + k] - X[i * ld + k];
+        }
+        G[rr * DS + k] = v;
+    }
+    __syncthreads();
+    double xb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        xb[q] = bb < DB ? G[(4 * q + (lane >> 4)) * DS + 16 * bb + (lane & 15)] : 0.0;
+    __syncthreads();
+    // clear the ring once: rows past the strip's last row stay zero, and
+    // columns j >= ly of the last tile keep earlier tiles' values, which meet
+    // zero y increments
+    for (int e = tid; e < 64 * GS; e += 256) G[e] = 0.0;
+    // skewed rows t0n + w + 4u (u < 8) at this lane
+    double gr[8];
+    auto load_rows = [&](int t0n, int count) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0n + w + 4 * u;
+            gr[u] = (4 * u + w < count && t < rows_left) ? sk_ld_nt(gsk + (int64_t)t * 64 + lane) : 0.0;
+        }
+    };
+    auto store_rows = [&](int t0n, int count) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0n + w + 4 * u, j = t - lane;
+            // only the strip's cells: past the strip's rows and the pair's
+            // last step the skewed slots are not this strip's
+            if (4 * u + w < count && lane < nrow && j >= 0 && j < ly) G[lane * GS + j % RC] = gr[u];
+        }
+    };
+    constexpr int YH = (TW * 16 * DB + 255) / 256;
+    double yr[YH];
+    auto load_y = [&](int j0) {
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int e = tid + 256 * h, jj = e / (16 * DB), k = e - jj * (16 * DB), j = j0 + jj;
+            yr[h] = (e < TW * 16 * DB && k < d && j < ly)
+                        ? Y[(int64_t)(j + 1) * ld + k] - Y[(int64_t)j * ld + k] : 0.0;
+        }
+    };
+    auto store_y = [&]() {
+#pragma unroll
+        for (int h = 0; h < YH; ++h) {
+            const int e = tid + 256 * h, jj = e / (16 * DB), k = e - jj * (16 * DB);
+            if (e < TW * 16 * DB) Yt[jj * DS + k] = yr[h];
+        }
+    };
+    __syncthreads();
+    // prologue: skewed rows 0..62 (the columns of tile 0 that rows below 63 hold)
+    load_rows(0, 32);
+    store_rows(0, 32);
+    load_rows(32, 31);
+    store_rows(32, 31);
+    // chunk of tile jt: skewed rows TW jt + 63 .. TW jt + 62 + TW (the rest of
+    // tile jt and the leading part of the next tiles)
+    load_rows(63, TW);
+    load_y(0);
+    sk_d4 accx[DB];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) accx[b] = {0.0, 0.0, 0.0, 0.0};
+    for (int jt = 0; jt < ntiles; ++jt) {
+        // the tile's columns sit at cb .. cb + TW - 1 of the ring, without wrapping
+        const int j0 = TW * jt, cb = j0 % RC;
+        store_rows(j0 + 63, TW);
+        store_y();
+        __syncthreads();
+        if (jt + 1 < ntiles) {  // the next tile's rows and increments load under the MFMAs
+            load_y(j0 + TW);
+            load_rows(j0 + TW + 63, TW);
+        }
+        // dL/d(dx)[16w + m][n] += sum_k G[16w + m][j0 + k] dY[k][n]
+#pragma unroll
+        for (int kk = 0; kk < TW; kk += 4) {
+            const double av = G[(16 * w + (lane & 15)) * GS + cb + kk + (lane >> 4)];
+#pragma unroll
+            for (int b = 0; b < DB; ++b) {
+                const double bv = Yt[(kk + (lane >> 4)) * DS + 16 * b + (lane & 15)];
+                accx[b] = SkMfma<double>::mma(av, bv, accx[b]);
+            }
+        }
+        // the strip's dL/d(dy)[j0 + 16 (w & 1) + m][16 bb + n] = sum_k G[k][j0 + 16 (w & 1) + m] dX[k][16 bb + n]
+        if (bb < DB) {
+            sk_d4 accy = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double av = G[(4 * q + (lane >> 4)) * GS + cb + 16 * (w & 1) + (lane & 15)];
+                accy = SkMfma<double>::mma(av, xb[q], accy);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = j0 + 16 * (w & 1) + SkMfma<double>::row(lane, v), k = 16 * bb + (lane & 15);
+                if (j < ly && k < d) a.dyp[pd.dy_off + ((int64_t)s * ly + j) * ld + k] = accy[v];
+            }
+        }
+        __syncthreads();  // the ring's and the tile's next contents are stored after this
+    }
+#pragma unroll
+    for (int b = 0; b < DB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 16 * w + SkMfma<double>::row(lane, v), k = 16 * b + (lane & 15);
+            if (rr < nrow && k < d) a.dxp[pd.dx_off + ((int64_t)s * 64 + rr) * ld + k] = accx[b][v];
+        }
+}
+
 // Hybrid scheme backward: every sub-cell of cell (i, j) on the lam-order
 // refinement has the constant c_ij / 4^lam, so dL/dc_ij is 4^-lam times the
 // sum of dL/dc' over its 4^lam sub-cells.  One thread per element (tau, r)

@@ -362,9 +362,20 @@ template <typename R>
 hipError_t SkLaunch<R>::contract(const ContractArgs<R>& a, int max_strips, int64_t npairs,
                                  hipStream_t st) {
     if (npairs <= 0 || max_strips <= 0) return hipSuccess;
-    // FP32, d <= 32: the MFMA tiles (d = 8: 2.05 -> 1.64 ms on the 128 x 128
-    // Gram of 256-step paths; d = 32: 2.3x faster); FP64 and d > 32: the VALU
+    // d <= 32: the MFMA tiles (FP32, d = 8: 2.05 -> 1.64 ms on the 128 x 128
+    // Gram of 256-step paths; d = 32: 2.3x faster); d > 32: the VALU
     // wavefront kernel
+    if constexpr (sizeof(R) == 8) {
+        if (a.d <= 32) {
+            dim3 g2((unsigned)npairs, max_strips);
+            if (a.d <= 16)
+                hipLaunchKernelGGL(k_contract_mfma_f64<1>, g2, dim3(256), sk_cmfma64_lds<1>(), st, a);
+            else
+                hipLaunchKernelGGL(k_contract_mfma_f64<2>, g2, dim3(256), sk_cmfma64_lds<2>(), st, a);
+            SK_CHECK_LAUNCH();
+            return hipSuccess;
+        }
+    }
     if constexpr (sizeof(R) == 4) {
         if (a.d <= 32) {
             dim3 g2((unsigned)npairs, max_strips);
