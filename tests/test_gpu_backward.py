@@ -103,6 +103,28 @@ def test_wide_dimension_gradient_matches_finite_differences(sk):
         assert abs(got - fd) <= 1e-6 * scale, (which, idx, got, fd)
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-6), (torch.float32, 1e-5)])
+def test_mfma_contraction_two_dimension_blocks(sk, dtype, tol):
+    # d = 20: the MFMA contraction's two 16-dimension blocks (the second
+    # partial), on ragged two-strip pairs whose columns end inside a tile
+    log_banner(f"two-block MFMA contraction gradient {dtype}")
+    rng = np.random.default_rng(23)
+    X = bm_paths(rng, 2, 100, 20, 0.2 / np.sqrt(100))
+    Y = bm_paths(rng, 2, 77, 20, 0.2 / np.sqrt(77))
+    if dtype == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+        Y = Y.astype(np.float32).astype(np.float64)
+    gK = rng.normal(size=(2, 2))
+    gX, gY = sk.gram_backward(dev(X, dtype), dev(Y, dtype), dev(gK, dtype), "approx", 5)
+    gX, gY = gX.cpu().double().numpy(), gY.cpu().double().numpy()
+    scale = max(np.abs(gX).max(), np.abs(gY).max())
+    for which, idx in [("x", (0, 0, 0)), ("x", (1, 63, 15)), ("x", (0, 64, 16)), ("x", (1, 100, 19)),
+                       ("y", (0, 0, 3)), ("y", (1, 31, 17)), ("y", (0, 32, 16)), ("y", (1, 77, 19))]:
+        fd = fd_gram_grad(X, Y, gK, "approx", 5, idx, which)
+        got = gX[idx] if which == "x" else gY[idx]
+        assert abs(got - fd) <= tol * scale, (which, idx, got, fd)
+
+
 def test_gradient_seed_exponent(sk):
     rng = np.random.default_rng(4)
     X = dev(bm_paths(rng, 2, 70, 3, 0.05), torch.float64)
