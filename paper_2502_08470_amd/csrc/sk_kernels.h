@@ -1052,6 +1052,18 @@ struct PipeArgs {
 __device__ __forceinline__ void sk_store_coherent(unsigned* p, unsigned v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// a record of `nw` words (8-byte aligned; word nw is writable padding when
+// nw is odd) in 8-byte device-coherent stores
+template <int NW>
+__device__ __forceinline__ void sk_store_record_coherent(unsigned* rec, const unsigned (&wd)[NW]) {
+#pragma unroll
+    for (int k = 0; k < NW; k += 2) {
+        const unsigned long long v =
+            (unsigned long long)wd[k] | ((unsigned long long)(k + 1 < NW ? wd[k + 1] : 0u) << 32);
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(rec + k), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 __device__ __forceinline__ void sk_stores_complete() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);  // every counter of this wave at zero
@@ -1255,8 +1267,7 @@ __global__ __launch_bounds__(64) void k_sweep_pipe(const PipeArgs<R> a) {
                             for (int n = 2; n <= N; ++n)
                                 *reinterpret_cast<R*>(wd + 4 + (n - 2) * (ES / 4)) = Qo[n];
                             wd[NW - 1] = (unsigned)E;
-#pragma unroll
-                            for (int k = 0; k < NW; ++k) sk_store_coherent(rec + k, wd[k]);
+                            sk_store_record_coherent<NW>(rec, wd);
                         }
                     }
                     if (i == g.lx - 1 && j == ly - 1) {
