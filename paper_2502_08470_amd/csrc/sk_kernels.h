@@ -768,7 +768,12 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
     // ring entry of a column: FP64 coefficients 0 and 1, coefficients 2..N,
     // exponent (the layout of a global exchange record), 8-byte aligned
     constexpr int RW = sk_ring_col_bytes_fwd(N, ES) / 4;
-    const SkLds<unsigned> ring = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES));  // [ly][RW]
+    // exchange launches that checkpoint also keep lane 63's records of the
+    // current 8-step block in LDS ([8][GXW], before the ring), for the
+    // adjoint's copy of the boundary edges
+    constexpr int OST = (GX && CKPT) ? sk_gx_stage_bytes(N, ES) : 0;
+    const SkLds<unsigned> ost = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES));
+    const SkLds<unsigned> ring = (SkLds<unsigned>)(sk_smem + sk_gx_stage_bytes(N, ES) + OST);  // [ly][RW]
     unsigned* xg = a.xb + pd.xb_off;  // [ly][GXW] (exchange pairs only)
     unsigned xr[(8 * GXW + 63) / 64];
 #pragma unroll
@@ -904,19 +909,32 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             if (live) {
                 if (r == 63 && s + 1 < g.nstrips) {
                     if (gx) {
-                        unsigned* rec = xg + (int64_t)j * GXW;
-                        *reinterpret_cast<double*>(rec) = Qo0;
-                        *reinterpret_cast<double*>(rec + 2) = Qo1;
+                        // the record in 16-byte stores (records are 16-byte
+                        // aligned, GXW words each)
+                        constexpr int NW = 4 + (N - 1) * (ES / 4) + 1, NQ = (NW + 3) / 4;
+                        unsigned wd[4 * NQ];
+                        wd[0] = (unsigned)__double2loint(Qo0);
+                        wd[1] = (unsigned)__double2hiint(Qo0);
+                        wd[2] = (unsigned)__double2loint(Qo1);
+                        wd[3] = (unsigned)__double2hiint(Qo1);
 #pragma unroll
-                        for (int n = 2; n <= N; ++n)
-                            *reinterpret_cast<R*>(rec + 4 + (n - 2) * (ES / 4)) = Qo[n];
-                        rec[4 + (N - 1) * (ES / 4)] = (unsigned)E;
-                        if (CKPT) {
-                            const int64_t o = (int64_t)(s + 1) * g.ly + j;
-#pragma unroll
-                            for (int n = 0; n <= N; ++n) a.qb[pd.qb_off + o * (N + 1) + n] = Qo[n];
-                            a.qe[pd.qe_off + o] = E;
+                        for (int n = 2; n <= N; ++n) {
+                            if constexpr (ES == 4) {
+                                wd[4 + n - 2] = __float_as_uint(Qo[n]);
+                            } else {
+                                wd[4 + 2 * (n - 2)] = (unsigned)__double2loint(Qo[n]);
+                                wd[4 + 2 * (n - 2) + 1] = (unsigned)__double2hiint(Qo[n]);
+                            }
                         }
+                        wd[NW - 1] = (unsigned)E;
+#pragma unroll
+                        for (int k = NW; k < 4 * NQ; ++k) wd[k] = 0u;
+                        uint4* rec = reinterpret_cast<uint4*>(xg + (int64_t)j * GXW);
+#pragma unroll
+                        for (int k = 0; k < NQ; ++k)
+                            rec[k] = make_uint4(wd[4 * k], wd[4 * k + 1], wd[4 * k + 2], wd[4 * k + 3]);
+                        // (the checkpoint copy leaves once per block, from LDS)
+                        if (CKPT) sk_edge_write<R, N>(ost + u * GXW, Qo0, Qo1, Qo, E);
                     } else {
                         // (the checkpoint copy of ring entries leaves once per block)
                         sk_edge_write<R, N>(ring + __mul24(j, RW), Qo0, Qo1, Qo, E);
@@ -939,9 +957,10 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
             ++L;
         }
         // the strip-boundary edges lane 63 handed over in this block, from
-        // the ring to the adjoint's global copy (one coalesced pass; an entry
-        // is rewritten only Tp >= 64 steps after it was written)
-        if (CKPT && !gx) {
+        // the ring (an entry is rewritten only Tp >= 64 steps after it was
+        // written) or, for exchange pairs, the block's LDS staging, to the
+        // adjoint's global copy in one coalesced pass
+        if (CKPT) {
             // lane 63's place after the block: the place of step t0 + u is
             // 8 - u columns back (while L >= 0 it advanced every step)
             const int Le = __builtin_amdgcn_readlane(L, 63), se = __builtin_amdgcn_readlane(s, 63),
@@ -957,7 +976,7 @@ __global__ __launch_bounds__(64) void k_sweep(const SweepArgs<R> a) {
                     --sc;
                 }
                 if (e < 8 * QR && Le - back >= 0 && sc + 1 < g.nstrips && jc < g.ly) {
-                    const SkLds<unsigned> rec = ring + __mul24(jc, RW);
+                    const SkLds<unsigned> rec = gx ? ost + u * GXW : ring + __mul24(jc, RW);
                     const int64_t o = (int64_t)(sc + 1) * g.ly + jc;
                     if (w <= N) {
                         R v;

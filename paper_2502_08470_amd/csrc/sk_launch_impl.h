@@ -156,7 +156,8 @@ template <typename R> constexpr bool sk_alt_stride() { return sizeof(R) == 4; }
 template <typename R, int N, int TMAX, int S>
 static hipError_t sk_sweep_s(const SweepArgs<R>& a, bool ckpt, int64_t npairs, int ring, bool gx,
                              hipStream_t st) {
-    size_t lds = SkLaunch<R>::sweep_lds(N, ring);
+    // exchange launches that checkpoint stage lane 63's records of a block
+    size_t lds = SkLaunch<R>::sweep_lds(N, ring) + (ckpt && gx ? sk_gx_stage_bytes(N, (int)sizeof(R)) : 0);
     dim3 grid((unsigned)npairs), blk(64);
     if (ckpt && gx)
         hipLaunchKernelGGL((k_sweep<R, N, TMAX, true, S, true>), grid, blk, lds, st, a);
