@@ -104,6 +104,37 @@ def test_long_gram_gradients(sk, dtype, tol):
         assert abs(got - fd) <= tol * scale, (which, idx, got, fd)
 
 
+def test_long_gram_interp_gradients_fp64(sk):
+    # the interpolation scheme's backward on exchange pairs (1500 columns):
+    # the checkpoint sweep's boundary-edge copy and the replayed tail lengths
+    # against central differences of the oracle
+    from oracle import c_oracle as C
+    log_banner("global exchange interpolation gradients fp64")
+    rng = np.random.default_rng(64)
+    X = bm_paths(rng, 2, 130, 3, 0.5 / np.sqrt(130))
+    Y = bm_paths(rng, 1, 1500, 3, 0.5 / np.sqrt(1500))
+    gK = rng.normal(size=(2, 1))
+    gX, gY = sk.gram_backward(dev(X, torch.float64), dev(Y, torch.float64), dev(gK, torch.float64),
+                              "interp", 6, algo="batched")
+    gX, gY = gX.cpu().numpy(), gY.cpu().numpy()
+    scale = max(np.abs(gX).max(), np.abs(gY).max())
+
+    def loss(Xv, Yv):
+        m, e = C.gram(Xv, Yv, C.INTERP, 6)
+        return float(np.sum(gK * np.ldexp(m, e)))
+    h = 1e-4
+    for which, idx in [("x", (0, 63, 0)), ("x", (1, 130, 2)), ("y", (0, 1, 1)), ("y", (0, 999, 0)),
+                       ("y", (0, 1500, 2))]:
+        P = (X if which == "x" else Y).copy()
+        P[idx] += h
+        lp = loss(P, Y) if which == "x" else loss(X, P)
+        P[idx] -= 2 * h
+        lm = loss(P, Y) if which == "x" else loss(X, P)
+        fd = (lp - lm) / (2 * h)
+        got = gX[idx] if which == "x" else gY[idx]
+        assert abs(got - fd) <= 1e-6 * scale, (which, idx, got, fd)
+
+
 def test_long_pairs_exponents_fp32(sk):
     # values far beyond FP32 range through the global exchange records
     log_banner("global exchange exponents")
