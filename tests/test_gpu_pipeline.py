@@ -219,6 +219,26 @@ def test_pipeline_backward_fp32_interp_matches_batched(sk):
             assert np.abs(a[off[i]:off[i + 1]] - b[off[i]:off[i + 1]]).max() <= 2e-5 * s, i
 
 
+@pytest.mark.parametrize("ckpt", [2, 4])
+def test_pipeline_gram_backward_fp32_strides(sk, ckpt):
+    # approximation N = 8, d = 16 (the uneven pairs' scheme) at both FP32
+    # checkpoint strides: the pipelined adjoint's staged boundary edges and
+    # per-block records against the batched backward at the same stride
+    log_banner(f"pipeline gram backward fp32 stride {ckpt}")
+    rng = np.random.default_rng(88)
+    X = bm_paths(rng, 3, 300, 16, 0.5 / np.sqrt(300)).astype(np.float32)
+    Y = bm_paths(rng, 2, 213, 16, 0.5 / np.sqrt(213)).astype(np.float32)
+    gK = dev(rng.normal(size=(3, 2)), torch.float32)
+    Xt, Yt = dev(X, torch.float32), dev(Y, torch.float32)
+    gXb, gYb = sk.gram_backward(Xt, Yt, gK, "approx", 8, algo="batched", ckpt=ckpt)
+    gXp, gYp = sk.gram_backward(Xt, Yt, gK, "approx", 8, algo="pipeline", ckpt=ckpt)
+    assert torch.isfinite(gXp).all() and torch.isfinite(gYp).all()
+    for g1, g0 in ((gXp, gXb), (gYp, gYb)):
+        a, b = g1.cpu().double().numpy(), g0.cpu().double().numpy()
+        for i in range(a.shape[0]):
+            assert np.abs(a[i] - b[i]).max() <= 2e-5 * np.abs(b[i]).max(), i
+
+
 def test_pipeline_backward_graph_replays_match_eager(sk):
     # the pipelined backward (Gram, two cooperative launches, counter fills,
     # contraction, reduction) captured into a HIP graph: every replay equals
